@@ -1,0 +1,159 @@
+"""FP64 CPU oracle for residual-specific partial-jet propagation (Sec. 2.2, Eq. 1-3).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+benchmark's CPU-baseline leg, never by the GPU library or its Python binding.
+It shares no code with the GPU path.  Its arithmetic lives in pinn_oracle.cpp;
+this module only marshals numpy arrays through ctypes.
+
+Parameters are given as a list of (W, b) pairs, W shaped (out, in), and are
+widened to float64.  A channel set is a list of (direction, order) pairs whose
+first entry is the value (order 0).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liborc.so")
+
+ACT = {"tanh": 0, "identity": 1, "square": 2, "cube": 3, "sin": 4}
+PDE = {"none": 0, "burgers": 1, "ns": 2, "ks": 3, "heat": 4}
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        lib.orc_n_res.argtypes = [ctypes.c_int]
+        lib.orc_n_res.restype = ctypes.c_int
+        lib.orc_eval.argtypes = [ctypes.c_int, ip, dp, ctypes.c_int, ctypes.c_int, dp,
+                                 ctypes.c_int, ip, ip, ctypes.c_int64, dp,
+                                 dp, dp, dp, dp, dp, ctypes.c_int]
+        lib.orc_eval.restype = ctypes.c_int
+        lib.orc_eval_cs.argtypes = [ctypes.c_int, ip, dp, dp, ctypes.c_double, ctypes.c_int,
+                                    ctypes.c_int, dp, ctypes.c_int, ip, ip, ctypes.c_int64, dp,
+                                    dp, dp, dp, ctypes.c_int]
+        lib.orc_eval_cs.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _dp(a: Optional[np.ndarray]):
+    if a is None:
+        return ctypes.POINTER(ctypes.c_double)()
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def dims_of(params) -> list:
+    dims = [int(params[0][0].shape[1])]
+    for W, _ in params:
+        dims.append(int(W.shape[0]))
+    return dims
+
+
+def pack_theta(params) -> np.ndarray:
+    """Flatten [(W1, b1), ..., (WL, bL)] into one float64 vector (W then b per layer)."""
+    parts = []
+    for W, b in params:
+        parts.append(np.asarray(W, dtype=np.float64).reshape(-1))
+        parts.append(np.asarray(b, dtype=np.float64).reshape(-1))
+    return np.ascontiguousarray(np.concatenate(parts))
+
+
+def unpack_theta(theta: np.ndarray, dims: Sequence[int]) -> list:
+    out, off = [], 0
+    for l in range(len(dims) - 1):
+        n_out, n_in = dims[l + 1], dims[l]
+        W = theta[off:off + n_out * n_in].reshape(n_out, n_in)
+        off += n_out * n_in
+        b = theta[off:off + n_out]
+        off += n_out
+        out.append((W, b))
+    return out
+
+
+def n_res(pde: str) -> int:
+    return int(_load().orc_n_res(PDE[pde]))
+
+
+@dataclass
+class OracleResult:
+    jets: Optional[np.ndarray]   # (d_out, C, N)
+    r: Optional[np.ndarray]      # (n_res, N)
+    loss: Optional[float]
+    grad: Optional[np.ndarray]   # packed like pack_theta
+
+
+def _common(params, channels, coef):
+    dims = np.ascontiguousarray(dims_of(params), dtype=np.int32)
+    ch = list(channels)
+    ch_dir = np.ascontiguousarray([max(c[0], 0) if c[1] > 0 else 0 for c in ch], dtype=np.int32)
+    ch_ord = np.ascontiguousarray([c[1] for c in ch], dtype=np.int32)
+    cf = np.zeros(4, dtype=np.float64)
+    cf[:len(coef)] = np.asarray(coef, dtype=np.float64)
+    return dims, ch_dir, ch_ord, cf
+
+
+def evaluate(params, x, channels, pde: str = "none", coef: Sequence[float] = (), act: str = "tanh",
+             want_jets: bool = True, want_residual: bool = True, want_grad: bool = True,
+             r_bar: Optional[np.ndarray] = None, threads: int = 0) -> OracleResult:
+    """Jets, residuals, loss and parameter gradient at the points x (N x d), in FP64."""
+    lib = _load()
+    dims, ch_dir, ch_ord, cf = _common(params, channels, coef)
+    theta = pack_theta(params)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    N = xx.shape[0]
+    C = len(ch_dir)
+    nr = n_res(pde)
+    jets = np.zeros((dims[-1], C, N)) if want_jets else None
+    has_res = want_residual and nr > 0
+    r = np.zeros((nr, N)) if has_res else None
+    loss = np.zeros(1) if has_res else None
+    grad = np.zeros(theta.size) if (want_grad and nr > 0) else None
+    rb = None if r_bar is None else np.ascontiguousarray(r_bar, dtype=np.float64).reshape(nr, N)
+    st = lib.orc_eval(len(dims) - 1, _ip(dims), _dp(theta), ACT[act], PDE[pde], _dp(cf),
+                      C, _ip(ch_dir), _ip(ch_ord), N, _dp(xx),
+                      _dp(jets), _dp(r), _dp(loss), _dp(rb), _dp(grad), int(threads))
+    if st != 0:
+        raise ValueError(f"orc_eval failed with status {st}")
+    return OracleResult(jets, r, None if loss is None else float(loss[0]), grad)
+
+
+def complex_step(params, delta: np.ndarray, x, channels, pde: str = "none",
+                 coef: Sequence[float] = (), act: str = "tanh", h: float = 1e-30,
+                 threads: int = 0):
+    """Directional derivatives along delta (packed like theta) of (jets, r, loss)."""
+    lib = _load()
+    dims, ch_dir, ch_ord, cf = _common(params, channels, coef)
+    theta = pack_theta(params)
+    dl = np.ascontiguousarray(delta, dtype=np.float64)
+    assert dl.size == theta.size
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    N = xx.shape[0]
+    C = len(ch_dir)
+    nr = n_res(pde)
+    djets = np.zeros((dims[-1], C, N))
+    dr = np.zeros((nr, N)) if nr > 0 else None
+    dloss = np.zeros(1) if nr > 0 else None
+    st = lib.orc_eval_cs(len(dims) - 1, _ip(dims), _dp(theta), _dp(dl), float(h), ACT[act],
+                         PDE[pde], _dp(cf), C, _ip(ch_dir), _ip(ch_ord), N, _dp(xx),
+                         _dp(djets), _dp(dr), _dp(dloss), int(threads))
+    if st != 0:
+        raise ValueError(f"orc_eval_cs failed with status {st}")
+    return djets, dr, None if dloss is None else float(dloss[0])

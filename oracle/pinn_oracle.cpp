@@ -1,0 +1,557 @@
+/*
+ * FP64 CPU oracle: plain per-point partial-jet forward pass, residual, loss and
+ * reverse sweep for the parameter gradient.
+ *
+ * TEST INFRASTRUCTURE ONLY (see pinn_oracle.h).  Deliberately slow and direct:
+ * one collocation point at a time, one dot product per (channel, neuron), no
+ * blocking or fusion, so that each step can be read against the paper:
+ *   - layer affine map and activation:             Eq. 1
+ *   - first-order derivative states:                Eq. 2
+ *   - second-order (pure) derivative states:        Eq. 3
+ *   - higher orders by the same recursion:          Sec. 2.2 (text after Eq. 3);
+ *     written here as the univariate Faa di Bruno formula along one direction
+ *   - only the states the residual needs:           Sec. 2.2 ("on-demand partial jet")
+ *   - residuals: Burgers and KS as in Sec. 3.1.1, Navier-Stokes Eq. 16,
+ *     heat u_t - kappa Lap u - f (a workload of this library, not of the paper)
+ *   - parameter gradient by reverse-mode differentiation of the scalar loss,
+ *     which the paper keeps for training (Sec. 2.2, Sec. 3.1.1).
+ */
+#include "pinn_oracle.h"
+
+#include <cmath>
+#include <complex>
+#include <vector>
+#include <omp.h>
+
+namespace {
+
+constexpr int kMaxCh = 16;
+constexpr int kMaxDir = 8;
+constexpr int kMaxOrder = 4;
+constexpr int64_t kChunk = 64; /* points per deterministic partial sum */
+
+using cplx = std::complex<double>;
+
+struct ChannelSet {
+  int C = 0;
+  int dir[kMaxCh];
+  int ord[kMaxCh];
+  /* at[i][k]: channel index of d^k/dx_i^k, or -1.  at[i][0] = 0 (the value). */
+  int at[kMaxDir][kMaxOrder + 1];
+  int top[kMaxDir]; /* highest order present along direction i */
+};
+
+int build_channels(int n_ch, const int *ch_dir, const int *ch_ord, int d_in, ChannelSet *cs) {
+  if (n_ch < 1 || n_ch > kMaxCh || d_in < 1 || d_in > kMaxDir) return -1;
+  cs->C = n_ch;
+  for (int i = 0; i < kMaxDir; ++i) {
+    cs->top[i] = 0;
+    cs->at[i][0] = 0;
+    for (int k = 1; k <= kMaxOrder; ++k) cs->at[i][k] = -1;
+  }
+  if (ch_ord[0] != 0) return -1;
+  cs->dir[0] = -1;
+  cs->ord[0] = 0;
+  for (int c = 1; c < n_ch; ++c) {
+    int i = ch_dir[c], k = ch_ord[c];
+    if (i < 0 || i >= d_in || k < 1 || k > kMaxOrder) return -1;
+    if (cs->at[i][k] != -1) return -1; /* duplicate */
+    cs->dir[c] = i;
+    cs->ord[c] = k;
+    cs->at[i][k] = c;
+  }
+  for (int i = 0; i < d_in; ++i) {
+    int k = 0;
+    while (k + 1 <= kMaxOrder && cs->at[i][k + 1] >= 0) ++k;
+    cs->top[i] = k;
+    for (int kk = k + 1; kk <= kMaxOrder; ++kk)
+      if (cs->at[i][kk] >= 0) return -1; /* order chain must be a prefix 1..k */
+  }
+  return 0;
+}
+
+/* Derivatives phi^(0..5)(z) of the activation. */
+template <class T>
+void act_derivs(int act, T z, T *p) {
+  switch (act) {
+    case ORC_ACT_TANH: {
+      /* tanh' = 1 - tanh^2; each further derivative follows by differentiating
+         a polynomial in s = tanh z and using ds/dz = 1 - s^2. */
+      T s = std::tanh(z);
+      T s1 = 1.0 - s * s;
+      p[0] = s;
+      p[1] = s1;
+      p[2] = -2.0 * s * s1;
+      p[3] = s1 * (6.0 * s * s - 2.0);
+      p[4] = s * s1 * (16.0 - 24.0 * s * s);
+      p[5] = s1 * (16.0 - 120.0 * s * s + 120.0 * s * s * s * s);
+      break;
+    }
+    case ORC_ACT_IDENTITY:
+      p[0] = z; p[1] = 1.0; p[2] = 0.0; p[3] = 0.0; p[4] = 0.0; p[5] = 0.0;
+      break;
+    case ORC_ACT_SQUARE:
+      p[0] = z * z; p[1] = 2.0 * z; p[2] = 2.0; p[3] = 0.0; p[4] = 0.0; p[5] = 0.0;
+      break;
+    case ORC_ACT_CUBE:
+      p[0] = z * z * z; p[1] = 3.0 * z * z; p[2] = 6.0 * z; p[3] = 6.0; p[4] = 0.0; p[5] = 0.0;
+      break;
+    default: { /* ORC_ACT_SIN */
+      T sn = std::sin(z), cs = std::cos(z);
+      p[0] = sn; p[1] = cs; p[2] = -sn; p[3] = -cs; p[4] = sn; p[5] = cs;
+      break;
+    }
+  }
+}
+
+/* Order-k derivative of phi(z(x)) along one direction, from z_1..z_k (the
+ * derivatives of the pre-activation along that direction) and phi^(j)(z_0).
+ * q points at phi^(0): the formulas read q[1] = phi', q[2] = phi'', ...
+ * Called with q shifted by one it gives the partial derivative of a_k with
+ * respect to z_0, since d phi^(j)(z_0)/d z_0 = phi^(j+1)(z_0). */
+template <class T>
+T faa_di_bruno(int k, const T *q, const T *zz) {
+  const T z1 = zz[1];
+  switch (k) {
+    case 1: return q[1] * z1;
+    case 2: return q[2] * z1 * z1 + q[1] * zz[2];
+    case 3: return q[3] * z1 * z1 * z1 + 3.0 * q[2] * z1 * zz[2] + q[1] * zz[3];
+    default:
+      return q[4] * z1 * z1 * z1 * z1 + 6.0 * q[3] * z1 * z1 * zz[2] +
+             q[2] * (3.0 * zz[2] * zz[2] + 4.0 * z1 * zz[3]) + q[1] * zz[4];
+  }
+}
+
+/* Partial derivative of a_k (formula above) with respect to z_m, 1 <= m <= k. */
+template <class T>
+T faa_di_bruno_dz(int k, int m, const T *q, const T *zz) {
+  const T z1 = zz[1];
+  if (m == k) return q[1];
+  switch (k) {
+    case 2: /* m = 1 */
+      return 2.0 * q[2] * z1;
+    case 3:
+      if (m == 1) return 3.0 * q[3] * z1 * z1 + 3.0 * q[2] * zz[2];
+      return 3.0 * q[2] * z1; /* m = 2 */
+    default: /* k = 4 */
+      if (m == 1) return 4.0 * q[4] * z1 * z1 * z1 + 12.0 * q[3] * z1 * zz[2] + 4.0 * q[2] * zz[3];
+      if (m == 2) return 6.0 * q[3] * z1 * z1 + 6.0 * q[2] * zz[2];
+      return 4.0 * q[2] * z1; /* m = 3 */
+  }
+}
+
+struct NetView {
+  int L;
+  const int *dims;
+  std::vector<int64_t> w_off, b_off;
+  int64_t n_theta;
+};
+
+NetView make_view(int L, const int *dims) {
+  NetView v;
+  v.L = L;
+  v.dims = dims;
+  int64_t off = 0;
+  for (int l = 0; l < L; ++l) {
+    v.w_off.push_back(off);
+    off += (int64_t)dims[l + 1] * dims[l];
+    v.b_off.push_back(off);
+    off += dims[l + 1];
+  }
+  v.n_theta = off;
+  return v;
+}
+
+/* Per-point state for the reverse sweep: a[l] = input of layer l (C x dims[l]),
+ * z[l] = output of layer l before activation (C x dims[l+1]). */
+template <class T>
+struct PointWork {
+  std::vector<std::vector<T>> a, z;
+  void init(const NetView &nv, int C) {
+    a.resize(nv.L);
+    z.resize(nv.L);
+    for (int l = 0; l < nv.L; ++l) {
+      a[l].assign((size_t)C * nv.dims[l], T(0));
+      z[l].assign((size_t)C * nv.dims[l + 1], T(0));
+    }
+  }
+};
+
+/* Forward partial-jet pass for one point (Eq. 1-3 and the recursion). */
+template <class T>
+void forward_point(const NetView &nv, const T *theta, const ChannelSet &cs, int act,
+                   const double *xp, PointWork<T> &pw) {
+  const int C = cs.C;
+  const int d = nv.dims[0];
+  /* Seeds: a^0 = x, d a^0 / d x_i = e_i, higher derivatives of the input vanish. */
+  std::vector<T> &a0 = pw.a[0];
+  for (size_t q = 0; q < a0.size(); ++q) a0[q] = T(0);
+  for (int j = 0; j < d; ++j) a0[j] = T(xp[j]);
+  for (int c = 1; c < C; ++c)
+    if (cs.ord[c] == 1) a0[(size_t)c * d + cs.dir[c]] = T(1);
+
+  for (int l = 0; l < nv.L; ++l) {
+    const int n_in = nv.dims[l], n_out = nv.dims[l + 1];
+    const T *W = theta + nv.w_off[l];
+    const T *b = theta + nv.b_off[l];
+    const std::vector<T> &a = pw.a[l];
+    std::vector<T> &z = pw.z[l];
+    /* The same W acts on every channel; the bias enters the value only. */
+    for (int c = 0; c < C; ++c)
+      for (int i = 0; i < n_out; ++i) {
+        T s = (c == 0) ? b[i] : T(0);
+        for (int j = 0; j < n_in; ++j) s += W[(size_t)i * n_in + j] * a[(size_t)c * n_in + j];
+        z[(size_t)c * n_out + i] = s;
+      }
+    if (l == nv.L - 1) break; /* linear output layer */
+    std::vector<T> &an = pw.a[l + 1];
+    for (int i = 0; i < n_out; ++i) {
+      T phi[6];
+      act_derivs(act, z[i], phi);
+      an[i] = phi[0];
+      for (int dir = 0; dir < d; ++dir) {
+        T zz[kMaxOrder + 1];
+        zz[0] = z[i];
+        for (int k = 1; k <= cs.top[dir]; ++k) zz[k] = z[(size_t)cs.at[dir][k] * n_out + i];
+        for (int k = 1; k <= cs.top[dir]; ++k)
+          an[(size_t)cs.at[dir][k] * n_out + i] = faa_di_bruno(k, phi, zz);
+      }
+    }
+  }
+}
+
+/* Residual channel lookups.  Returns -2 when a needed channel is missing. */
+struct PdeChannels {
+  int u, ut, ux, uxx, uxxxx, uy, uyy, uz, uzz;
+};
+
+int pde_channels(int kind, int d_in, int d_out, const ChannelSet &cs, PdeChannels *pc) {
+  auto need = [&](int dir, int k) { return (dir < d_in) ? cs.at[dir][k] : -1; };
+  *pc = PdeChannels{0, -1, -1, -1, -1, -1, -1, -1, -1};
+  switch (kind) {
+    case ORC_PDE_NONE: return 0;
+    case ORC_PDE_BURGERS:
+      if (d_in != 2 || d_out != 1) return -1;
+      pc->ux = need(0, 1); pc->uxx = need(0, 2); pc->ut = need(1, 1);
+      return (pc->ux < 0 || pc->uxx < 0 || pc->ut < 0) ? -2 : 0;
+    case ORC_PDE_NS:
+      if (d_in != 2 || d_out != 3) return -1;
+      pc->ux = need(0, 1); pc->uxx = need(0, 2); pc->uy = need(1, 1); pc->uyy = need(1, 2);
+      return (pc->ux < 0 || pc->uxx < 0 || pc->uy < 0 || pc->uyy < 0) ? -2 : 0;
+    case ORC_PDE_KS:
+      if (d_in != 2 || d_out != 1) return -1;
+      pc->ux = need(0, 1); pc->uxx = need(0, 2); pc->uxxxx = need(0, 4); pc->ut = need(1, 1);
+      return (pc->ux < 0 || pc->uxx < 0 || pc->uxxxx < 0 || pc->ut < 0) ? -2 : 0;
+    case ORC_PDE_HEAT:
+      if (d_in != 4 || d_out != 1) return -1;
+      pc->uxx = need(0, 2); pc->uyy = need(1, 2); pc->uzz = need(2, 2); pc->ut = need(3, 1);
+      return (pc->uxx < 0 || pc->uyy < 0 || pc->uzz < 0 || pc->ut < 0) ? -2 : 0;
+    default: return -1;
+  }
+}
+
+/* Heat source f = sin(pi x) sin(pi y) sin(pi z) exp(-t). */
+double heat_source(const double *xp) {
+  const double pi = 3.14159265358979323846;
+  return std::sin(pi * xp[0]) * std::sin(pi * xp[1]) * std::sin(pi * xp[2]) * std::exp(-xp[3]);
+}
+
+/* u(o, c) = output o, channel c, taken from the last layer's pre-activation. */
+template <class T>
+void residual_point(int kind, const double *coef, const PdeChannels &pc, const double *xp,
+                    const std::vector<T> &u, int C, T *r) {
+  auto U = [&](int o, int c) { return u[(size_t)c * (u.size() / C) + o]; };
+  switch (kind) {
+    case ORC_PDE_BURGERS: {
+      const double nu = coef[0];
+      r[0] = U(0, pc.ut) + U(0, 0) * U(0, pc.ux) - nu * U(0, pc.uxx);
+      break;
+    }
+    case ORC_PDE_NS: { /* Eq. 16, outputs (u, v, p) = (0, 1, 2) */
+      const double Re = coef[0];
+      T u0 = U(0, 0), v0 = U(1, 0);
+      r[0] = U(0, pc.ux) + U(1, pc.uy);
+      r[1] = u0 * U(0, pc.ux) + v0 * U(0, pc.uy) + U(2, pc.ux) - (U(0, pc.uxx) + U(0, pc.uyy)) / Re;
+      r[2] = u0 * U(1, pc.ux) + v0 * U(1, pc.uy) + U(2, pc.uy) - (U(1, pc.uxx) + U(1, pc.uyy)) / Re;
+      break;
+    }
+    case ORC_PDE_KS: {
+      const double al = coef[0], be = coef[1], ga = coef[2];
+      r[0] = U(0, pc.ut) + al * U(0, 0) * U(0, pc.ux) + be * U(0, pc.uxx) + ga * U(0, pc.uxxxx);
+      break;
+    }
+    case ORC_PDE_HEAT: {
+      const double ka = coef[0];
+      r[0] = U(0, pc.ut) - ka * (U(0, pc.uxx) + U(0, pc.uyy) + U(0, pc.uzz)) - heat_source(xp);
+      break;
+    }
+    default: break;
+  }
+}
+
+/* Cotangent of the residual with respect to the output jets: ubar(o, c) =
+ * sum_k rbar_k d r_k / d u(o, c), by the chain rule on the formulas above. */
+void residual_adjoint_point(int kind, const double *coef, const PdeChannels &pc,
+                            const std::vector<double> &u, int C, const double *rbar,
+                            std::vector<double> &ubar) {
+  const size_t d_out = u.size() / C;
+  auto U = [&](int o, int c) { return u[(size_t)c * d_out + o]; };
+  auto UB = [&](int o, int c) -> double & { return ubar[(size_t)c * d_out + o]; };
+  for (double &v : ubar) v = 0.0;
+  switch (kind) {
+    case ORC_PDE_BURGERS: {
+      const double nu = coef[0];
+      UB(0, pc.ut) += rbar[0];
+      UB(0, 0) += rbar[0] * U(0, pc.ux);
+      UB(0, pc.ux) += rbar[0] * U(0, 0);
+      UB(0, pc.uxx) += -nu * rbar[0];
+      break;
+    }
+    case ORC_PDE_NS: {
+      const double Re = coef[0];
+      const double rc = rbar[0], ru = rbar[1], rv = rbar[2];
+      /* r_c = u_x + v_y */
+      UB(0, pc.ux) += rc;
+      UB(1, pc.uy) += rc;
+      /* r_u = u u_x + v u_y + p_x - (u_xx + u_yy)/Re */
+      UB(0, 0) += ru * U(0, pc.ux);
+      UB(0, pc.ux) += ru * U(0, 0);
+      UB(1, 0) += ru * U(0, pc.uy);
+      UB(0, pc.uy) += ru * U(1, 0);
+      UB(2, pc.ux) += ru;
+      UB(0, pc.uxx) += -ru / Re;
+      UB(0, pc.uyy) += -ru / Re;
+      /* r_v = u v_x + v v_y + p_y - (v_xx + v_yy)/Re */
+      UB(0, 0) += rv * U(1, pc.ux);
+      UB(1, pc.ux) += rv * U(0, 0);
+      UB(1, 0) += rv * U(1, pc.uy);
+      UB(1, pc.uy) += rv * U(1, 0);
+      UB(2, pc.uy) += rv;
+      UB(1, pc.uxx) += -rv / Re;
+      UB(1, pc.uyy) += -rv / Re;
+      break;
+    }
+    case ORC_PDE_KS: {
+      const double al = coef[0], be = coef[1], ga = coef[2];
+      UB(0, pc.ut) += rbar[0];
+      UB(0, 0) += al * rbar[0] * U(0, pc.ux);
+      UB(0, pc.ux) += al * rbar[0] * U(0, 0);
+      UB(0, pc.uxx) += be * rbar[0];
+      UB(0, pc.uxxxx) += ga * rbar[0];
+      break;
+    }
+    case ORC_PDE_HEAT: {
+      const double ka = coef[0];
+      UB(0, pc.ut) += rbar[0];
+      UB(0, pc.uxx) += -ka * rbar[0];
+      UB(0, pc.uyy) += -ka * rbar[0];
+      UB(0, pc.uzz) += -ka * rbar[0];
+      break;
+    }
+    default: break;
+  }
+}
+
+/* Reverse sweep for one point: given zbar of the last layer (the output jets'
+ * cotangent), accumulate d/dtheta into g. */
+void backward_point(const NetView &nv, const double *theta, const ChannelSet &cs, int act,
+                    PointWork<double> &pw, std::vector<double> &zbar, double *g) {
+  const int C = cs.C;
+  const int d = nv.dims[0];
+  std::vector<double> abar;
+  for (int l = nv.L - 1; l >= 0; --l) {
+    const int n_in = nv.dims[l], n_out = nv.dims[l + 1];
+    const double *W = theta + nv.w_off[l];
+    const std::vector<double> &a = pw.a[l];
+    double *gW = g + nv.w_off[l];
+    double *gb = g + nv.b_off[l];
+    /* z_c = W a_c (+ b for c = 0):  dW += zbar_c a_c^T,  db += zbar_0 */
+    for (int c = 0; c < C; ++c)
+      for (int i = 0; i < n_out; ++i) {
+        const double zb = zbar[(size_t)c * n_out + i];
+        if (zb == 0.0) continue;
+        for (int j = 0; j < n_in; ++j) gW[(size_t)i * n_in + j] += zb * a[(size_t)c * n_in + j];
+      }
+    for (int i = 0; i < n_out; ++i) gb[i] += zbar[i];
+    if (l == 0) break; /* the input seeds do not depend on theta */
+    /* abar_c = W^T zbar_c */
+    abar.assign((size_t)C * n_in, 0.0);
+    for (int c = 0; c < C; ++c)
+      for (int i = 0; i < n_out; ++i) {
+        const double zb = zbar[(size_t)c * n_out + i];
+        for (int j = 0; j < n_in; ++j) abar[(size_t)c * n_in + j] += W[(size_t)i * n_in + j] * zb;
+      }
+    /* Adjoint of the activation jet of layer l-1 (whose output is a[l]). */
+    const std::vector<double> &zp = pw.z[l - 1];
+    std::vector<double> zbp((size_t)C * n_in, 0.0);
+    for (int j = 0; j < n_in; ++j) {
+      double phi[6];
+      act_derivs(act, zp[j], phi);
+      double z0bar = phi[1] * abar[j]; /* a_0 = phi(z_0) */
+      for (int dir = 0; dir < d; ++dir) {
+        const int K = cs.top[dir];
+        if (K == 0) continue;
+        double zz[kMaxOrder + 1];
+        zz[0] = zp[j];
+        for (int k = 1; k <= K; ++k) zz[k] = zp[(size_t)cs.at[dir][k] * n_in + j];
+        for (int k = 1; k <= K; ++k) {
+          const double ab = abar[(size_t)cs.at[dir][k] * n_in + j];
+          z0bar += faa_di_bruno(k, phi + 1, zz) * ab; /* a_k depends on z_0 through phi^(.) */
+          for (int m = 1; m <= k; ++m)
+            zbp[(size_t)cs.at[dir][m] * n_in + j] += faa_di_bruno_dz(k, m, phi, zz) * ab;
+        }
+      }
+      zbp[j] = z0bar;
+    }
+    zbar.swap(zbp);
+  }
+}
+
+struct Problem {
+  NetView nv;
+  ChannelSet cs;
+  PdeChannels pc;
+  int n_res;
+};
+
+int setup(int n_layers, const int *dims, int act, int pde_kind, int n_ch, const int *ch_dir,
+          const int *ch_ord, int64_t N, Problem *P) {
+  if (n_layers < 1 || !dims || N < 0 || act < 0 || act > ORC_ACT_SIN) return -1;
+  for (int l = 0; l <= n_layers; ++l)
+    if (dims[l] < 1) return -1;
+  P->nv = make_view(n_layers, dims);
+  if (build_channels(n_ch, ch_dir, ch_ord, dims[0], &P->cs)) return -1;
+  int st = pde_channels(pde_kind, dims[0], dims[n_layers], P->cs, &P->pc);
+  if (st) return st;
+  P->n_res = orc_n_res(pde_kind);
+  return 0;
+}
+
+int n_threads_or_default(int n) { return n > 0 ? n : omp_get_max_threads(); }
+
+} /* namespace */
+
+extern "C" int orc_n_res(int pde_kind) {
+  switch (pde_kind) {
+    case ORC_PDE_BURGERS: return 1;
+    case ORC_PDE_NS: return 3;
+    case ORC_PDE_KS: return 1;
+    case ORC_PDE_HEAT: return 1;
+    default: return 0;
+  }
+}
+
+extern "C" int orc_eval(int n_layers, const int *dims, const double *theta, int act, int pde_kind,
+                        const double *coef, int n_ch, const int *ch_dir, const int *ch_ord,
+                        int64_t N, const double *x, double *jets, double *r, double *loss,
+                        const double *r_bar, double *grad, int n_threads) {
+  Problem P;
+  int st = setup(n_layers, dims, act, pde_kind, n_ch, ch_dir, ch_ord, N, &P);
+  if (st) return st;
+  if (!theta || (N > 0 && !x)) return -1;
+  if ((r || loss || grad) && P.n_res == 0) return -1; /* residual quantities need a PDE */
+  const NetView &nv = P.nv;
+  const int C = P.cs.C, d = dims[0], d_out = dims[n_layers], n_res = P.n_res;
+  const int64_t n_chunks = (N + kChunk - 1) / kChunk;
+  std::vector<double> chunk_loss(n_chunks > 0 ? n_chunks : 1, 0.0);
+  std::vector<std::vector<double>> chunk_grad;
+  if (grad) chunk_grad.assign(n_chunks, std::vector<double>());
+
+#pragma omp parallel num_threads(n_threads_or_default(n_threads))
+  {
+    PointWork<double> pw;
+    pw.init(nv, C);
+    std::vector<double> rr(n_res > 0 ? n_res : 1), rb(n_res > 0 ? n_res : 1);
+    std::vector<double> ubar((size_t)C * d_out), zbar;
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t ch = 0; ch < n_chunks; ++ch) {
+      double lsum = 0.0;
+      if (grad) chunk_grad[ch].assign(nv.n_theta, 0.0);
+      const int64_t n_end = std::min<int64_t>(N, (ch + 1) * kChunk);
+      for (int64_t n = ch * kChunk; n < n_end; ++n) {
+        const double *xp = x + n * d;
+        forward_point(nv, theta, P.cs, act, xp, pw);
+        const std::vector<double> &u = pw.z[nv.L - 1];
+        if (jets)
+          for (int o = 0; o < d_out; ++o)
+            for (int c = 0; c < C; ++c) jets[((size_t)o * C + c) * N + n] = u[(size_t)c * d_out + o];
+        if (n_res == 0) continue;
+        residual_point(pde_kind, coef, P.pc, xp, u, C, rr.data());
+        for (int k = 0; k < n_res; ++k) {
+          if (r) r[(size_t)k * N + n] = rr[k];
+          lsum += rr[k] * rr[k];
+        }
+        if (grad) {
+          for (int k = 0; k < n_res; ++k)
+            rb[k] = r_bar ? r_bar[(size_t)k * N + n] : 2.0 * rr[k] / (double)N;
+          residual_adjoint_point(pde_kind, coef, P.pc, u, C, rb.data(), ubar);
+          zbar = ubar;
+          backward_point(nv, theta, P.cs, act, pw, zbar, chunk_grad[ch].data());
+        }
+      }
+      chunk_loss[ch] = lsum;
+    }
+  }
+  if (loss) {
+    double s = 0.0;
+    for (int64_t ch = 0; ch < n_chunks; ++ch) s += chunk_loss[ch];
+    *loss = N > 0 ? s / (double)N : 0.0;
+  }
+  if (grad) {
+    for (int64_t q = 0; q < nv.n_theta; ++q) grad[q] = 0.0;
+    for (int64_t ch = 0; ch < n_chunks; ++ch)
+      for (int64_t q = 0; q < nv.n_theta; ++q) grad[q] += chunk_grad[ch][q];
+  }
+  return 0;
+}
+
+extern "C" int orc_eval_cs(int n_layers, const int *dims, const double *theta, const double *delta,
+                           double h, int act, int pde_kind, const double *coef, int n_ch,
+                           const int *ch_dir, const int *ch_ord, int64_t N, const double *x,
+                           double *djets, double *dr, double *dloss, int n_threads) {
+  Problem P;
+  int st = setup(n_layers, dims, act, pde_kind, n_ch, ch_dir, ch_ord, N, &P);
+  if (st) return st;
+  if (!theta || !delta || !(h > 0.0) || (N > 0 && !x)) return -1;
+  if ((dr || dloss) && P.n_res == 0) return -1;
+  const NetView &nv = P.nv;
+  const int C = P.cs.C, d = dims[0], d_out = dims[n_layers], n_res = P.n_res;
+  std::vector<cplx> th(nv.n_theta);
+  for (int64_t q = 0; q < nv.n_theta; ++q) th[q] = cplx(theta[q], h * delta[q]);
+  const int64_t n_chunks = (N + kChunk - 1) / kChunk;
+  std::vector<cplx> chunk_loss(n_chunks > 0 ? n_chunks : 1, cplx(0.0, 0.0));
+
+#pragma omp parallel num_threads(n_threads_or_default(n_threads))
+  {
+    PointWork<cplx> pw;
+    pw.init(nv, C);
+    std::vector<cplx> rr(n_res > 0 ? n_res : 1);
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t ch = 0; ch < n_chunks; ++ch) {
+      cplx lsum(0.0, 0.0);
+      const int64_t n_end = std::min<int64_t>(N, (ch + 1) * kChunk);
+      for (int64_t n = ch * kChunk; n < n_end; ++n) {
+        const double *xp = x + n * d;
+        forward_point(nv, th.data(), P.cs, act, xp, pw);
+        const std::vector<cplx> &u = pw.z[nv.L - 1];
+        if (djets)
+          for (int o = 0; o < d_out; ++o)
+            for (int c = 0; c < C; ++c)
+              djets[((size_t)o * C + c) * N + n] = u[(size_t)c * d_out + o].imag() / h;
+        if (n_res == 0) continue;
+        residual_point(pde_kind, coef, P.pc, xp, u, C, rr.data());
+        for (int k = 0; k < n_res; ++k) {
+          if (dr) dr[(size_t)k * N + n] = rr[k].imag() / h;
+          lsum += rr[k] * rr[k]; /* analytic square, not |r|^2 */
+        }
+      }
+      chunk_loss[ch] = lsum;
+    }
+  }
+  if (dloss) {
+    cplx s(0.0, 0.0);
+    for (int64_t ch = 0; ch < n_chunks; ++ch) s += chunk_loss[ch];
+    *dloss = N > 0 ? (s / (double)N).imag() / h : 0.0;
+  }
+  return 0;
+}

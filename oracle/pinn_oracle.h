@@ -1,0 +1,77 @@
+/*
+ * FP64 CPU oracle for residual-specific partial-jet propagation through an MLP
+ * (Cao, Lu & Zhang, "Verified residual-specific explicit derivative kernels ...",
+ * Sec. 2.2, Eq. 1-3; residuals of Sec. 3.1.1 and Eq. 16).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or helper with the GPU library under paper_2606_29702_amd/.
+ *
+ * Conventions (all arrays row-major, all buffers owned by the caller):
+ *   Network: L = n_layers affine maps, dims[0..L]; layer l (0-based) maps
+ *     dims[l] -> dims[l+1].  theta packs, for l = 0..L-1, W_l (dims[l+1] x dims[l])
+ *     followed by b_l (dims[l+1]).  The activation acts after layers 0..L-2;
+ *     the last layer is linear.
+ *   Channel set: C channels, channel 0 is the value.  Channel c > 0 is the pure
+ *     derivative of order ch_ord[c] (1..4) along input direction ch_dir[c].
+ *     For every (dir, k>1) channel the (dir, k-1) channel must also be present.
+ *   Jets: d_out x C x N.   Residuals: n_res x N.
+ *   Loss: sum over residual components of (1/N) sum_n r^2.
+ *   Gradient: d(loss)/d(theta) packed like theta, or, when r_bar is given,
+ *     the cotangent product J_theta^T r_bar (r_bar is n_res x N).
+ */
+#ifndef PINN_ORACLE_H
+#define PINN_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ORC_ACT_TANH = 0,     /* the paper's activation */
+  ORC_ACT_IDENTITY = 1, /* pins: the network is affine */
+  ORC_ACT_SQUARE = 2,   /* pins: the network is a polynomial */
+  ORC_ACT_CUBE = 3,
+  ORC_ACT_SIN = 4       /* pins: derivatives cycle in closed form */
+};
+
+enum {
+  ORC_PDE_NONE = 0,    /* jets only */
+  ORC_PDE_BURGERS = 1, /* coef = {nu}; inputs (x, t); r = u_t + u u_x - nu u_xx */
+  ORC_PDE_NS = 2,      /* coef = {Re}; inputs (x, y); outputs (u, v, p); Eq. 16 */
+  ORC_PDE_KS = 3,      /* coef = {alpha, beta, gamma}; r = u_t + a u u_x + b u_xx + g u_xxxx */
+  ORC_PDE_HEAT = 4     /* coef = {kappa}; inputs (x, y, z, t);
+                          r = u_t - kappa (u_xx + u_yy + u_zz) - sin(pi x) sin(pi y) sin(pi z) e^-t */
+};
+
+/* Status: 0 ok, -1 bad argument, -2 channel set does not cover the PDE. */
+
+/* Number of residual components of a PDE kind (0 for ORC_PDE_NONE). */
+int orc_n_res(int pde_kind);
+
+/* Full evaluation.  Any of jets, r, loss, grad may be NULL (not computed).
+ * r_bar NULL means the cotangent of the loss (2 r / N).  n_threads <= 0 uses
+ * the OpenMP default.  The result does not depend on the thread count: points
+ * are processed in fixed chunks whose partial sums are added in chunk order. */
+int orc_eval(int n_layers, const int *dims, const double *theta, int act,
+             int pde_kind, const double *coef,
+             int n_ch, const int *ch_dir, const int *ch_ord,
+             int64_t N, const double *x,
+             double *jets, double *r, double *loss,
+             const double *r_bar, double *grad, int n_threads);
+
+/* Complex-step directional derivative along delta in parameter space:
+ * evaluates the forward pass at theta + i h delta in complex arithmetic and
+ * returns Im(.)/h for the jets, the residuals and the loss (each may be NULL). */
+int orc_eval_cs(int n_layers, const int *dims, const double *theta,
+                const double *delta, double h, int act,
+                int pde_kind, const double *coef,
+                int n_ch, const int *ch_dir, const int *ch_ord,
+                int64_t N, const double *x,
+                double *djets, double *dr, double *dloss, int n_threads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

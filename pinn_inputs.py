@@ -1,0 +1,156 @@
+"""Seeded synthetic inputs for the partial-jet PINN workloads.
+
+This module only draws random numbers: network parameters, collocation points
+and ensemble members.  It contains none of the method's arithmetic, and both
+the GPU library's tests and the FP64 oracle take their inputs from here.
+
+Recipe (all float64 draws from numpy PCG64, rounded once to float32):
+  * weights: Xavier-normal, std = sqrt(2 / (fan_in + fan_out)), W shaped
+    (out, in), drawn layer by layer; biases zero unless bias_std > 0 (tests use
+    nonzero biases so the bias path is exercised);
+  * points: N x d, each coordinate uniform on its interval, drawn after the
+    weights from the same generator;
+  * ensemble: a master SeedSequence spawns one child per network; each child
+    draws width, depth, viscosity and point count, then weights, then points.
+
+The workload shapes follow the library's five benchmark problems (viscous
+Burgers, steady Navier-Stokes at Re = 100, Kuramoto-Sivashinsky, 3-D heat and
+a 64-network Burgers ensemble).  Channel orders are the library's ABI orders.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+# Channel sets in ABI order: (direction, order); direction indexes the input
+# coordinates of the workload, order 0 is the value.
+CHANNELS = {
+    # inputs (x, t): u, u_t, u_x, u_xx
+    "burgers": [(0, 0), (1, 1), (0, 1), (0, 2)],
+    # inputs (x, y): value, d/dx, d/dy, d2/dx2, d2/dy2
+    "ns": [(0, 0), (0, 1), (1, 1), (0, 2), (1, 2)],
+    # inputs (x, t): u, u_t, u_x, u_xx, u_xxx, u_xxxx
+    "ks": [(0, 0), (1, 1), (0, 1), (0, 2), (0, 3), (0, 4)],
+    # inputs (x, y, z, t): u, u_t, u_x, u_y, u_z, u_xx, u_yy, u_zz
+    "heat": [(0, 0), (3, 1), (0, 1), (1, 1), (2, 1), (0, 2), (1, 2), (2, 2)],
+}
+
+N_RES = {"burgers": 1, "ns": 3, "ks": 1, "heat": 1}
+
+
+@dataclass
+class Workload:
+    name: str
+    pde: str
+    dims: List[int]
+    coef: Tuple[float, ...]
+    domain: List[Tuple[float, float]]
+    N: int
+    note: str = ""
+
+    @property
+    def width(self) -> int:
+        return self.dims[1]
+
+    @property
+    def hidden(self) -> int:
+        return len(self.dims) - 2
+
+
+def _mlp(d_in: int, width: int, hidden: int, d_out: int) -> List[int]:
+    return [d_in] + [width] * hidden + [d_out]
+
+
+WORKLOADS = {
+    "burgers": Workload("burgers", "burgers", _mlp(2, 32, 3, 1), (0.01 / math.pi,),
+                        [(-1.0, 1.0), (0.0, 1.0)], 1024,
+                        "viscous Burgers u_t + u u_x - (0.01/pi) u_xx, 2-32x3-1 tanh"),
+    "ns": Workload("ns", "ns", _mlp(2, 128, 6, 3), (100.0,), [(0.0, 1.0), (0.0, 1.0)], 65536,
+                   "steady incompressible Navier-Stokes, Re = 100, 2-128x6-3 tanh"),
+    "ks": Workload("ks", "ks", _mlp(2, 256, 8, 1), (1.0, 1.0, 1.0),
+                   [(0.0, 32.0 * math.pi), (0.0, 1.0)], 131072,
+                   "Kuramoto-Sivashinsky u_t + u u_x + u_xx + u_xxxx, 2-256x8-1 tanh"),
+    "heat": Workload("heat", "heat", _mlp(4, 512, 8, 1), (0.1,), [(0.0, 1.0)] * 4, 262144,
+                     "3-D heat u_t - 0.1 Lap u - f, 4-512x8-1 tanh"),
+}
+
+
+def xavier_params(dims: Sequence[int], rng: np.random.Generator, bias_std: float = 0.0):
+    params = []
+    for l in range(len(dims) - 1):
+        fan_in, fan_out = dims[l], dims[l + 1]
+        std = math.sqrt(2.0 / (fan_in + fan_out))
+        W = rng.normal(0.0, std, size=(fan_out, fan_in)).astype(np.float32)
+        if bias_std > 0.0:
+            b = rng.normal(0.0, bias_std, size=(fan_out,)).astype(np.float32)
+        else:
+            b = np.zeros((fan_out,), dtype=np.float32)
+        params.append((W, b))
+    return params
+
+
+def uniform_points(N: int, domain: Sequence[Tuple[float, float]], rng: np.random.Generator):
+    d = len(domain)
+    u = rng.random((N, d))
+    lo = np.array([a for a, _ in domain])
+    hi = np.array([b for _, b in domain])
+    return (lo + (hi - lo) * u).astype(np.float32)
+
+
+@dataclass
+class Problem:
+    workload: Workload
+    params: list                    # [(W float32 (out, in), b float32 (out,)), ...]
+    x: np.ndarray                   # (N, d) float32
+    coef: Tuple[float, ...]
+    channels: list = field(default_factory=list)
+
+
+def make_problem(name: str, N: Optional[int] = None, seed: int = 0, bias_std: float = 0.0,
+                 dims: Optional[Sequence[int]] = None) -> Problem:
+    """Workload `name` with its default shape; N and dims may be overridden for tests."""
+    wl = WORKLOADS[name]
+    if dims is not None or N is not None:
+        wl = Workload(wl.name, wl.pde, list(dims) if dims is not None else list(wl.dims), wl.coef,
+                      wl.domain, int(N) if N is not None else wl.N, wl.note)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    params = xavier_params(wl.dims, rng, bias_std)
+    x = uniform_points(wl.N, wl.domain, rng)
+    return Problem(wl, params, x, wl.coef, CHANNELS[wl.pde])
+
+
+@dataclass
+class EnsembleMember:
+    width: int
+    hidden: int
+    nu: float
+    N: int
+    params: list
+    x: np.ndarray
+
+    @property
+    def dims(self) -> List[int]:
+        return _mlp(2, self.width, self.hidden, 1)
+
+
+def make_ensemble(n_nets: int = 64, seed: int = 0, widths=(32, 64, 128, 256), depth=(3, 8),
+                  nu_range=(1e-3, 1e-1), n_range=(2048, 65536), bias_std: float = 0.0,
+                  with_points: bool = True) -> List[EnsembleMember]:
+    """Burgers ensemble: width categorical, hidden depth uniform integer, nu log-uniform,
+    N uniform integer (inclusive bounds), on x in [-1, 1], t in [0, 1]."""
+    children = np.random.SeedSequence(seed).spawn(n_nets)
+    out = []
+    dom = WORKLOADS["burgers"].domain
+    for ss in children:
+        rng = np.random.Generator(np.random.PCG64(ss))
+        w = int(rng.choice(np.asarray(widths)))
+        H = int(rng.integers(depth[0], depth[1] + 1))
+        nu = float(math.exp(rng.uniform(math.log(nu_range[0]), math.log(nu_range[1]))))
+        N = int(rng.integers(n_range[0], n_range[1] + 1))
+        params = xavier_params(_mlp(2, w, H, 1), rng, bias_std)
+        x = uniform_points(N, dom, rng) if with_points else None
+        out.append(EnsembleMember(w, H, nu, N, params, x))
+    return out

@@ -1,0 +1,92 @@
+"""Nested torch.autograd reference, the paper's AD baseline (Sec. 3.1.1): the
+network is evaluated as a plain tanh MLP and every coordinate derivative the
+residual needs is obtained by repeated autograd.grad calls.  FP64 on the CPU.
+Used only to pin the oracle; it is a library route independent of both the
+oracle's jet recursion and the GPU kernels."""
+import math
+
+import numpy as np
+import torch
+
+
+def mlp(params64, X, act=torch.tanh):
+    h = X
+    L = len(params64)
+    for l, (W, b) in enumerate(params64):
+        h = h @ W.T + b
+        if l < L - 1:
+            h = act(h)
+    return h
+
+
+def torch_params(params, requires_grad=True):
+    out = []
+    for W, b in params:
+        Wt = torch.tensor(np.asarray(W, dtype=np.float64), requires_grad=requires_grad)
+        bt = torch.tensor(np.asarray(b, dtype=np.float64), requires_grad=requires_grad)
+        out.append((Wt, bt))
+    return out
+
+
+def nested_jets(params64, x, channels, act=torch.tanh):
+    """Returns (jets dict {(o, c): tensor (N,)}, X) with a graph kept for backward."""
+    X = torch.tensor(np.asarray(x, dtype=np.float64), requires_grad=True)
+    U = mlp(params64, X, act)
+    jets = {}
+    for o in range(U.shape[1]):
+        u = U[:, o]
+        for c, (dr, k) in enumerate(channels):
+            if k == 0:
+                jets[(o, c)] = u
+                continue
+            g = u
+            for _ in range(k):
+                g = torch.autograd.grad(g.sum(), X, create_graph=True)[0][:, dr]
+            jets[(o, c)] = g
+    return jets, X
+
+
+def residuals(pde, jets, channels, X, coef):
+    idx = {ch: c for c, ch in enumerate(channels)}
+
+    def J(o, dr, k):
+        return jets[(o, idx[(0, 0)] if k == 0 else idx[(dr, k)])]
+
+    if pde == "burgers":  # inputs (x, t)
+        nu = coef[0]
+        return [J(0, 1, 1) + J(0, 0, 0) * J(0, 0, 1) - nu * J(0, 0, 2)]
+    if pde == "ns":  # Eq. 16, inputs (x, y), outputs (u, v, p)
+        Re = coef[0]
+        u, v = J(0, 0, 0), J(1, 0, 0)
+        rc = J(0, 0, 1) + J(1, 1, 1)
+        ru = u * J(0, 0, 1) + v * J(0, 1, 1) + J(2, 0, 1) - (J(0, 0, 2) + J(0, 1, 2)) / Re
+        rv = u * J(1, 0, 1) + v * J(1, 1, 1) + J(2, 1, 1) - (J(1, 0, 2) + J(1, 1, 2)) / Re
+        return [rc, ru, rv]
+    if pde == "ks":  # inputs (x, t)
+        a, b, g = coef
+        return [J(0, 1, 1) + a * J(0, 0, 0) * J(0, 0, 1) + b * J(0, 0, 2) + g * J(0, 0, 4)]
+    if pde == "heat":  # inputs (x, y, z, t)
+        ka = coef[0]
+        Xd = X.detach()
+        f = (torch.sin(math.pi * Xd[:, 0]) * torch.sin(math.pi * Xd[:, 1]) *
+             torch.sin(math.pi * Xd[:, 2]) * torch.exp(-Xd[:, 3]))
+        return [J(0, 3, 1) - ka * (J(0, 0, 2) + J(0, 1, 2) + J(0, 2, 2)) - f]
+    raise ValueError(pde)
+
+
+def evaluate(params, x, channels, pde, coef, act=torch.tanh):
+    """(jets (d_out, C, N), r (n_res, N), loss, grad packed W,b per layer) in FP64."""
+    p64 = torch_params(params)
+    jets, X = nested_jets(p64, x, channels, act)
+    rs = residuals(pde, jets, channels, X, coef)
+    N = X.shape[0]
+    loss = sum((r * r).sum() / N for r in rs)
+    leaves = [t for pair in p64 for t in pair]
+    grads = torch.autograd.grad(loss, leaves, allow_unused=True)
+    grads = [torch.zeros_like(t) if g is None else g for g, t in zip(grads, leaves)]
+    d_out = params[-1][0].shape[0]
+    C = len(channels)
+    J = np.stack([np.stack([jets[(o, c)].detach().numpy() for c in range(C)]) for o in range(d_out)])
+    R = np.stack([r.detach().numpy() for r in rs])
+    G = np.concatenate([g.detach().numpy().reshape(-1) for g in grads])
+    return J, R, float(loss.detach()), G
