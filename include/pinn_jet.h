@@ -1,0 +1,164 @@
+/*
+ * pinn_jet.h - C ABI of the MI355X (gfx950) partial-jet PINN library.
+ *
+ * The library evaluates, for a tanh MLP u_theta(x) and a PDE residual r, the
+ * derivative states the residual needs (the "partial jet"), the residual, the
+ * mean-squared residual loss and its parameter gradient, following
+ * Cao, Lu & Zhang, "Verified residual-specific explicit derivative kernels for
+ * physics-informed learning and discretized PDE adjoints":
+ *   - layer map z = W a + b, a = tanh(z)                          (Eq. 1)
+ *   - derivative states: d_i z = W d_i a, d_i a = tanh'(z) d_i z   (Eq. 2)
+ *     d_ii z = W d_ii a, d_ii a = tanh'' (d_i z)^2 + tanh' d_ii z  (Eq. 3)
+ *     and the same recursion to order 4 for pure derivatives        (Sec. 2.2)
+ *   - only the channels the residual needs are propagated, and all channels of
+ *     a layer go through one stacked GEMM with the bias on the value only
+ *                                                                    (Sec. 2.2)
+ *   - residuals: viscous Burgers and Kuramoto-Sivashinsky (Sec. 3.1.1),
+ *     steady incompressible Navier-Stokes (Eq. 16), and a 3-D heat equation;
+ *   - the parameter gradient is reverse-mode differentiation of the scalar
+ *     loss (Sec. 2.2, Sec. 3.1.1), here a hand-written adjoint.
+ *
+ * General conventions
+ *   - All array arguments are DEVICE pointers unless marked "host".  Arrays are
+ *     row-major.  The caller owns every buffer it passes; the library owns only
+ *     the plan's workspace (allocated in pinn_plan_create, freed in
+ *     pinn_plan_destroy).  The step calls (forward / residual / backward) do not
+ *     allocate and may be captured into a HIP graph.
+ *   - Calls are asynchronous and ordered on `stream` (a hipStream_t passed as
+ *     void*, NULL = the default stream).  Nothing is synchronised.  A device
+ *     fault surfaces at the caller's next synchronisation.
+ *   - Every function returns a pinn_status; it never throws or aborts.  On a
+ *     non-OK status pinn_last_error() holds a message (per host thread).  All
+ *     argument checks happen on the host before any device work is enqueued,
+ *     so a call that fails a check has no effect.
+ *   - A plan is not safe to use from two host threads at once.
+ */
+#ifndef PINN_JET_H
+#define PINN_JET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pinn_status;
+enum {
+  PINN_OK = 0,
+  PINN_ERR_ARG = -1,         /* a NULL pointer, a size out of range, a shape mismatch */
+  PINN_ERR_UNSUPPORTED = -2, /* valid request this build does not implement */
+  PINN_ERR_NOMEM = -3,       /* device allocation failed */
+  PINN_ERR_DEVICE = -4,      /* a HIP call failed */
+  PINN_ERR_STATE = -5,       /* backward without the matching residual call */
+  PINN_ERR_CAP = -6          /* save_cap_bytes below the minimum saved state */
+};
+
+/* PDE kinds.  Input ordering and channel order (the order of the jet channels
+ * in every jets array) are fixed per kind:
+ *   PINN_BURGERS_1D  inputs (x, t), output u, coef = {nu}
+ *                    r = u_t + u u_x - nu u_xx            channels: u, u_t, u_x, u_xx
+ *   PINN_NS2D_STEADY inputs (x, y), outputs (u, v, p), coef = {Re}
+ *                    r_c = u_x + v_y
+ *                    r_u = u u_x + v u_y + p_x - (u_xx + u_yy)/Re
+ *                    r_v = u v_x + v v_y + p_y - (v_xx + v_yy)/Re      (Eq. 16)
+ *                    residual rows in the order (r_c, r_u, r_v)
+ *                    channels: value, d/dx, d/dy, d2/dx2, d2/dy2 (for every output)
+ *   PINN_KS_1D       inputs (x, t), output u, coef = {alpha, beta, gamma}
+ *                    r = u_t + alpha u u_x + beta u_xx + gamma u_xxxx
+ *                    channels: u, u_t, u_x, u_xx, u_xxx, u_xxxx
+ *   PINN_HEAT_3D     inputs (x, y, z, t), output u, coef = {kappa}
+ *                    r = u_t - kappa (u_xx + u_yy + u_zz) - sin(pi x) sin(pi y) sin(pi z) e^-t
+ *                    channels: u, u_t, u_x, u_y, u_z, u_xx, u_yy, u_zz          */
+enum { PINN_BURGERS_1D = 1, PINN_NS2D_STEADY = 2, PINN_KS_1D = 3, PINN_HEAT_3D = 4 };
+
+/* Operand type of the hidden-layer GEMMs.  Accumulation, the activation jet,
+ * its adjoint, the residual and the loss are always FP32. */
+enum { PINN_FP32 = 0, PINN_BF16 = 1, PINN_FP16 = 2 };
+
+/* Plan flags. */
+enum {
+  PINN_VERIFY_F64 = 1u /* also produce FP64 loss and gradient reductions */
+};
+
+/* Network: L = n_layers affine maps; dims[0] = number of inputs, dims[L] =
+ * number of outputs, dims[1..L-1] = hidden width w (all equal; a multiple of 32,
+ * 32 <= w <= 512).  W[l] is a device array of dims[l+1] x dims[l] floats, b[l]
+ * of dims[l+1] floats.  tanh follows layers 0..L-2; layer L-1 is linear.
+ * Requires L >= 2.  The parameter values may change between calls; the shapes
+ * must match the plan's. */
+typedef struct {
+  int32_t n_layers;
+  const int32_t *dims;     /* host, n_layers + 1 entries */
+  const float *const *W;   /* host array of n_layers device pointers */
+  const float *const *b;   /* host array of n_layers device pointers */
+} pinn_net;
+
+typedef struct {
+  int32_t kind;    /* PINN_BURGERS_1D ... */
+  double coef[4];  /* see the PDE kinds above; unused entries ignored */
+} pinn_pde;
+
+typedef struct pinn_plan_s *pinn_plan;
+
+/* Creates a plan for one network shape, PDE kind and maximum point count.
+ *   prec            PINN_FP32 / PINN_BF16 / PINN_FP16
+ *   flags           0 or PINN_VERIFY_F64
+ *   save_cap_bytes  upper bound on the device bytes kept between
+ *                   pinn_jet_residual and pinn_jet_backward (the saved layer
+ *                   states); 0 = no bound (store every layer).  Under a bound
+ *                   the plan stores a subset of layers and recomputes the rest
+ *                   during backward (results are bitwise identical).
+ *                   PINN_ERR_CAP if even the smallest checkpoint set exceeds it.
+ * Allocates all device workspace on the current HIP device. */
+pinn_status pinn_plan_create(const pinn_net *net, const pinn_pde *pde, int64_t max_points,
+                             int32_t prec, uint32_t flags, size_t save_cap_bytes,
+                             pinn_plan *out);
+pinn_status pinn_plan_destroy(pinn_plan plan);
+
+/* Bytes of saved layer state the plan keeps at max_points, and its total
+ * device workspace (host outputs; either may be NULL). */
+pinn_status pinn_plan_memory(pinn_plan plan, size_t *saved_bytes, size_t *workspace_bytes);
+
+/* Forward partial-jet pass (Eq. 1-3 and the recursion of Sec. 2.2).
+ *   x     N x d_in floats (point-major)
+ *   jets  d_out x C x N floats: jets[(o*C + c)*N + n] is channel c of output o
+ *         at point n, channels in the PDE kind's order.
+ * 1 <= N <= max_points.  Invalidates the state saved by pinn_jet_residual. */
+pinn_status pinn_jet_forward(pinn_plan plan, const pinn_net *net, const float *x, int64_t N,
+                             float *jets, void *stream);
+
+/* Forward pass, residual and loss.  Saves the state pinn_jet_backward needs.
+ *   r         n_res x N floats (may be NULL)
+ *   loss      1 float: sum over residual rows of (1/N) sum_n r^2 (may be NULL)
+ *   loss_f64  1 double, the same reduction in FP64; requires PINN_VERIFY_F64
+ *             (may be NULL)
+ *   jets      optional d_out x C x N output as in pinn_jet_forward (may be NULL) */
+pinn_status pinn_jet_residual(pinn_plan plan, const pinn_net *net, const pinn_pde *pde,
+                              const float *x, int64_t N, float *r, float *loss,
+                              double *loss_f64, float *jets, void *stream);
+
+/* Parameter gradient by the hand-written adjoint of the jet recursion.
+ * Must follow pinn_jet_residual on the same plan with the same net
+ * parameter pointers, x and N (PINN_ERR_STATE otherwise).
+ *   r_bar    n_res x N cotangent of r, or NULL for the loss gradient (2 r / N)
+ *   dW, db   host arrays of n_layers device pointers shaped like W and b;
+ *            overwritten with J^T r_bar (or dL/dtheta)
+ *   dW_f64, db_f64  optional host arrays of device pointers receiving the same
+ *            gradient reduced in FP64 (requires PINN_VERIFY_F64), or NULL. */
+pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pde *pde,
+                              const float *x, int64_t N, const float *r_bar,
+                              float *const *dW, float *const *db,
+                              double *const *dW_f64, double *const *db_f64, void *stream);
+
+/* Message for the last non-OK status on this host thread ("" if none). */
+const char *pinn_last_error(void);
+
+/* Channel count for a PDE kind, and the number of residual rows (host). */
+int32_t pinn_pde_channels(int32_t kind);
+int32_t pinn_pde_residuals(int32_t kind);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PINN_JET_H */

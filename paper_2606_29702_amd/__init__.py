@@ -1,0 +1,7 @@
+"""MI355X (gfx950) residual-specific partial-jet PINN library.
+
+The arithmetic lives in the HIP library libpinnjet.so (C ABI in
+include/pinn_jet.h); this package only marshals torch tensors into it.
+"""
+from ._lib import PinnError, KINDS, PRECISIONS  # noqa: F401  (raises if the library is missing)
+from .jet import CHANNELS, RESIDUALS, DEFAULT_COEF, PinnPlan, JetResidual, jet_residual  # noqa: F401

@@ -1,0 +1,80 @@
+"""ctypes loader for libpinnjet.so (the gfx950 HIP library) and its C ABI.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind include/pinn_jet.h.  If the library is missing this module
+raises at import time; there is no fallback implementation.
+"""
+import ctypes
+import os
+
+# torch brings its own HIP runtime (soname libamdhip64.so.7).  Loading torch
+# first makes the library bind to that same runtime, so that torch's streams
+# and device memory are valid handles inside the library.  Loading the library
+# first would map a second runtime into the process.
+import torch  # noqa: F401
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpinnjet.so")
+
+PINN_OK = 0
+STATUS_NAMES = {0: "PINN_OK", -1: "PINN_ERR_ARG", -2: "PINN_ERR_UNSUPPORTED", -3: "PINN_ERR_NOMEM",
+                -4: "PINN_ERR_DEVICE", -5: "PINN_ERR_STATE", -6: "PINN_ERR_CAP"}
+KINDS = {"burgers": 1, "ns": 2, "ks": 3, "heat": 4}
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
+PINN_VERIFY_F64 = 1
+
+# Every symbol the public header declares.
+EXPORTS = ["pinn_plan_create", "pinn_plan_destroy", "pinn_plan_memory", "pinn_jet_forward",
+           "pinn_jet_residual", "pinn_jet_backward", "pinn_last_error", "pinn_pde_channels",
+           "pinn_pde_residuals"]
+
+
+class PinnError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class Net(ctypes.Structure):
+    _fields_ = [("n_layers", ctypes.c_int32), ("dims", ctypes.POINTER(ctypes.c_int32)),
+                ("W", ctypes.POINTER(ctypes.c_void_p)), ("b", ctypes.POINTER(ctypes.c_void_p))]
+
+
+class Pde(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("coef", ctypes.c_double * 4)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc for gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    NetP, PdeP = ctypes.POINTER(Net), ctypes.POINTER(Pde)
+    lib.pinn_plan_create.argtypes = [NetP, PdeP, i64, i32, ctypes.c_uint32, ctypes.c_size_t, pp]
+    lib.pinn_plan_destroy.argtypes = [vp]
+    lib.pinn_plan_memory.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
+    lib.pinn_jet_forward.argtypes = [vp, NetP, vp, i64, vp, vp]
+    lib.pinn_jet_residual.argtypes = [vp, NetP, PdeP, vp, i64, vp, vp, vp, vp, vp]
+    lib.pinn_jet_backward.argtypes = [vp, NetP, PdeP, vp, i64, vp, pp, pp, pp, pp, vp]
+    lib.pinn_last_error.restype = ctypes.c_char_p
+    lib.pinn_last_error.argtypes = []
+    lib.pinn_pde_channels.argtypes = [i32]
+    lib.pinn_pde_residuals.argtypes = [i32]
+    for name in ("pinn_plan_create", "pinn_plan_destroy", "pinn_plan_memory", "pinn_jet_forward",
+                 "pinn_jet_residual", "pinn_jet_backward", "pinn_pde_channels", "pinn_pde_residuals"):
+        getattr(lib, name).restype = ctypes.c_int32
+    return lib
+
+
+lib = _load()
+
+
+def check(status: int) -> None:
+    if status != PINN_OK:
+        raise PinnError(status, lib.pinn_last_error().decode())
+
+
+def ptr_array(ptrs):
+    arr = (ctypes.c_void_p * len(ptrs))(*[ctypes.c_void_p(p) if p else None for p in ptrs])
+    return ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p)), arr

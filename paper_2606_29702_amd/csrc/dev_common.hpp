@@ -1,0 +1,104 @@
+// Device-side building blocks for gfx950: operand types, MFMA fragments and
+// wave reductions.  Written for CDNA4 only (64-lane wavefronts).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pj {
+
+typedef __bf16 bf16_t;
+typedef _Float16 f16_t;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWave = 64;
+
+// One MFMA step of the 16x16 output tile with K = 32 along the contraction.
+// Lane l supplies 8 consecutive contraction elements starting at 8*(l/16) of
+// row (l%16) of the A tile and of column (l%16) of the B tile; the output tile
+// holds, in lane l, column (l%16) and rows 4*(l/16) + 0..3.
+template <class T>
+struct Mma;
+
+template <>
+struct Mma<bf16_t> {
+  using frag = bf16x8;
+  static __device__ __forceinline__ frag load(const bf16_t *p) {
+    return *reinterpret_cast<const bf16x8 *>(p);
+  }
+  static __device__ __forceinline__ void mma(f32x4 &acc, const frag &a, const frag &b) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+  }
+};
+
+template <>
+struct Mma<f16_t> {
+  using frag = f16x8;
+  static __device__ __forceinline__ frag load(const f16_t *p) {
+    return *reinterpret_cast<const f16x8 *>(p);
+  }
+  static __device__ __forceinline__ void mma(f32x4 &acc, const frag &a, const frag &b) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc, 0, 0, 0);
+  }
+};
+
+// FP32 operands: eight 16x16x4 MFMAs cover the same 32-long contraction.  MFMA
+// e pairs element e of every lane's A and B fragments, so lane group g covers
+// contraction indices 8g + e on both sides, the same set as the 16-bit forms.
+template <>
+struct Mma<float> {
+  struct frag {
+    f32x4 lo, hi;
+  };
+  static __device__ __forceinline__ frag load(const float *p) {
+    frag f;
+    f.lo = reinterpret_cast<const f32x4 *>(p)[0];
+    f.hi = reinterpret_cast<const f32x4 *>(p)[1];
+    return f;
+  }
+  static __device__ __forceinline__ void mma(f32x4 &acc, const frag &a, const frag &b) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.lo[e], b.lo[e], acc, 0, 0, 0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.hi[e], b.hi[e], acc, 0, 0, 0);
+  }
+};
+
+template <class T>
+__device__ __forceinline__ T to_op(float v) {
+  return static_cast<T>(v);
+}
+
+// Store 4 consecutive values.
+__device__ __forceinline__ void store4(float *p, float a, float b, float c, float d) {
+  *reinterpret_cast<f32x4 *>(p) = f32x4{a, b, c, d};
+}
+__device__ __forceinline__ void store4(bf16_t *p, float a, float b, float c, float d) {
+  *reinterpret_cast<bf16x4 *>(p) = bf16x4{(bf16_t)a, (bf16_t)b, (bf16_t)c, (bf16_t)d};
+}
+__device__ __forceinline__ void store4(f16_t *p, float a, float b, float c, float d) {
+  *reinterpret_cast<f16x4 *>(p) = f16x4{(f16_t)a, (f16_t)b, (f16_t)c, (f16_t)d};
+}
+
+__device__ __forceinline__ float to_f32(float v) { return v; }
+__device__ __forceinline__ float to_f32(bf16_t v) { return static_cast<float>(v); }
+__device__ __forceinline__ float to_f32(f16_t v) { return static_cast<float>(v); }
+
+// Sum over the lanes of a group of `G` consecutive lanes (G a power of two <= 64).
+template <int G>
+__device__ __forceinline__ float group_sum(float v) {
+#pragma unroll
+  for (int m = G / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, G);
+  return v;
+}
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int m = G / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, G);
+  return v;
+}
+
+}  // namespace pj

@@ -1,0 +1,87 @@
+// Host-visible launchers of the gfx950 kernels.  All buffers are device
+// pointers; every launcher enqueues on `st` and returns the launch status.
+//
+// Data layout in HBM (one network, N_pad = points rounded up to the point tile):
+//   stack  [N_pad][C][w]  channel-major within a point, neuron index fastest;
+//          the layer GEMM contracts over the neuron index, so every lane reads
+//          8 consecutive elements (16 bytes in BF16/FP16) per MFMA operand.
+//   S      [N_pad][C][w]  FP32 saved state of an activation layer:
+//          S[n][0][j] = tanh(z_0), S[n][c][j] = z_c for the derivative channels.
+//   W, WT  [w][w] operand-type copies of a hidden weight and of its transpose.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "jet_math.hpp"
+
+namespace pj {
+
+enum Prec { P_FP32 = 0, P_BF16 = 1, P_FP16 = 2 };
+enum Kind { K_BURGERS = 1, K_NS = 2, K_KS = 3, K_HEAT = 4 };
+
+constexpr int kPointTile = 128;  // N_pad granularity shared by all kernels
+
+int op_size(int prec);
+
+// W (fp32, rows x cols) -> Wop (operand type, same layout) and, if WTop is not
+// null, its transpose (cols x rows).
+hipError_t launch_cast(int prec, const float *W, int rows, int cols, void *Wop, void *WTop,
+                       hipStream_t st);
+
+// Layer 1: z = W1 x + b1 with the seeds d x / d x_i = e_i, then the activation jet.
+hipError_t launch_seed_fwd(int kind, int prec, const float *x, int64_t N, int64_t N_pad,
+                           const float *W1, const float *b1, int w, void *A1, float *S1,
+                           hipStream_t st);
+
+// Hidden layer: Z = W A_in (+ b on the value channel), A_out = jet(Z), S_out saved.
+hipError_t launch_layer_fwd(int kind, int prec, const void *A_in, const void *Wop, const float *b,
+                            void *A_out, float *S_out, int64_t N_pad, int w, hipStream_t st);
+
+// Hidden layer adjoint: Abar = W^T Zbar_in, then Zbar_out = jet_adjoint(Abar, S_prev).
+hipError_t launch_layer_bwd(int kind, int prec, const void *Zb_in, const void *WTop,
+                            const float *S_prev, void *Zb_out, int64_t N_pad, int w, hipStream_t st);
+
+// Output layer, residual and per-block loss partial sums (16 points per block).
+hipError_t launch_out_fwd(int kind, int prec, const void *A_H, const float *WL, const float *bL,
+                          const float *x, int64_t N, int64_t N_pad, int w, Coef k, float *jets,
+                          float *r, float *u_save, float *r_save, float *loss_part,
+                          double *loss_part64, hipStream_t st);
+
+// Deterministic sum of the loss partials; writes loss / N (fp32) and its FP64 twin.
+hipError_t launch_loss_reduce(const float *part, const double *part64, int n_part, double inv_n,
+                              float *loss, double *loss64, hipStream_t st);
+
+// Output-layer adjoint: ubar from rbar (or 2 r / N), then Zbar of the last
+// hidden layer.  ubar is written as [N_pad][d_out][C].
+hipError_t launch_out_bwd(int kind, int prec, const float *u_save, const float *r_save,
+                          const float *r_bar, int64_t N, int64_t N_pad, float rbar_scale,
+                          const float *WL, const float *S_H, int w, Coef k, float *ubar,
+                          void *Zb_H, hipStream_t st);
+
+// Partial sums of the output layer's dW, db over chunks of points:
+// part[chunk][d_out*w + d_out].
+hipError_t launch_dw_out(int kind, int prec, const float *ubar, const void *A_H, int64_t N_pad,
+                         int w, float *part, int n_chunks, hipStream_t st);
+
+// Partial sums of the first layer's dW, db: part[chunk][w*d_in + w].
+hipError_t launch_dw_seed(int kind, int prec, const void *Zb_1, const float *x, int64_t N,
+                          int64_t N_pad, int w, float *part, int n_chunks, hipStream_t st);
+
+// Split-K partials of a hidden layer's dW = sum_rows Zbar^T A (rows = points x
+// channels) and of db = sum over value rows of Zbar.
+//   part    [splits][w][w]     part_db [splits][w]
+hipError_t launch_dw_hidden(int prec, int C, const void *Zb, const void *A_prev, int64_t N_pad, int w,
+                            float *part, float *part_db, int splits, hipStream_t st);
+
+// out[q] = sum_s part[s * stride + q] for q < M, summed in s order; FP32
+// result into out32 (may be null), FP64 into out64 (may be null).
+hipError_t launch_reduce_parts(const float *part, int splits, int64_t stride, int64_t M,
+                               float *out32, double *out64, hipStream_t st);
+
+// Same, where the M values are scattered into two destinations: q < M1 goes
+// to a[q], q >= M1 to b[q - M1] (used for packed dW/db partials).
+hipError_t launch_reduce_parts2(const float *part, int splits, int64_t stride, int64_t M1,
+                                int64_t M2, float *a32, float *b32, double *a64, double *b64,
+                                hipStream_t st);
+
+}  // namespace pj

@@ -1,0 +1,190 @@
+"""Python binding of the partial-jet C ABI: a plan object and the
+torch.autograd.Function whose backward is the library's hand-written adjoint.
+
+Tensors are torch device tensors (float32, contiguous); torch supplies device
+memory and the current stream, the library does all the arithmetic.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib
+from ._lib import KINDS, PRECISIONS, Net, Pde, check, lib, ptr_array
+
+CHANNELS = {k: lib.pinn_pde_channels(v) for k, v in KINDS.items()}
+RESIDUALS = {k: lib.pinn_pde_residuals(v) for k, v in KINDS.items()}
+
+DEFAULT_COEF = {"burgers": (0.01 / 3.141592653589793,), "ns": (100.0,), "ks": (1.0, 1.0, 1.0),
+                "heat": (0.1,)}
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check_tensor(t: torch.Tensor, name: str) -> None:
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float32 device tensor")
+
+
+class _NetView:
+    """Holds the ctypes pinn_net and the arrays it points to."""
+
+    def __init__(self, params: Sequence[Tuple[torch.Tensor, torch.Tensor]]):
+        dims = [int(params[0][0].shape[1])] + [int(W.shape[0]) for W, _ in params]
+        for l, (W, b) in enumerate(params):
+            _check_tensor(W, f"W[{l}]")
+            _check_tensor(b, f"b[{l}]")
+        self.dims = (ctypes.c_int32 * len(dims))(*dims)
+        self.Wp, self._wa = ptr_array([W.data_ptr() for W, _ in params])
+        self.bp, self._ba = ptr_array([b.data_ptr() for _, b in params])
+        self.net = Net(len(params), ctypes.cast(self.dims, ctypes.POINTER(ctypes.c_int32)), self.Wp, self.bp)
+
+
+def _pde(kind: str, coef: Sequence[float]) -> Pde:
+    p = Pde()
+    p.kind = KINDS[kind]
+    for i, c in enumerate(coef):
+        p.coef[i] = float(c)
+    return p
+
+
+class PinnPlan:
+    """One network shape + PDE kind + maximum point count on the current device."""
+
+    def __init__(self, dims: Sequence[int], pde: str, max_points: int, precision: str = "fp32",
+                 verify_f64: bool = False, save_cap_bytes: int = 0,
+                 coef: Optional[Sequence[float]] = None):
+        self.dims = list(dims)
+        self.pde = pde
+        self.coef = tuple(coef) if coef is not None else DEFAULT_COEF[pde]
+        self.precision = precision
+        self.verify_f64 = verify_f64
+        self.C = CHANNELS[pde]
+        self.n_res = RESIDUALS[pde]
+        self.max_points = int(max_points)
+        # Shape-only net for plan creation: non-null placeholders are never read.
+        ptrs = [1] * (len(dims) - 1)
+        d = (ctypes.c_int32 * len(dims))(*dims)
+        Wp, wa = ptr_array(ptrs)
+        bp, ba = ptr_array(ptrs)
+        net = Net(len(dims) - 1, ctypes.cast(d, ctypes.POINTER(ctypes.c_int32)), Wp, bp)
+        handle = ctypes.c_void_p()
+        flags = _lib.PINN_VERIFY_F64 if verify_f64 else 0
+        check(lib.pinn_plan_create(ctypes.byref(net), ctypes.byref(_pde(pde, self.coef)), self.max_points,
+                                   PRECISIONS[precision], flags, int(save_cap_bytes), ctypes.byref(handle)))
+        self.handle = handle
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            check(lib.pinn_plan_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def memory(self) -> Tuple[int, int]:
+        s, w = ctypes.c_size_t(), ctypes.c_size_t()
+        check(lib.pinn_plan_memory(self.handle, ctypes.byref(s), ctypes.byref(w)))
+        return s.value, w.value
+
+    # ---------------------------------------------------------------- calls
+    def forward(self, params, x: torch.Tensor) -> torch.Tensor:
+        """Jets (d_out, C, N) at the points x (N, d_in)."""
+        _check_tensor(x, "x")
+        nv = _NetView(params)
+        N = x.shape[0]
+        jets = torch.empty((self.dims[-1], self.C, N), device=x.device, dtype=torch.float32)
+        check(lib.pinn_jet_forward(self.handle, ctypes.byref(nv.net), ctypes.c_void_p(x.data_ptr()), N,
+                                   ctypes.c_void_p(jets.data_ptr()), _stream()))
+        return jets
+
+    def residual(self, params, x: torch.Tensor, want_jets: bool = False):
+        """Returns (r (n_res, N), loss (1,), loss_f64 (1,) or None, jets or None)."""
+        _check_tensor(x, "x")
+        nv = _NetView(params)
+        N = x.shape[0]
+        dev = x.device
+        r = torch.empty((self.n_res, N), device=dev, dtype=torch.float32)
+        loss = torch.empty((), device=dev, dtype=torch.float32)
+        loss64 = torch.empty((), device=dev, dtype=torch.float64) if self.verify_f64 else None
+        jets = torch.empty((self.dims[-1], self.C, N), device=dev, dtype=torch.float32) if want_jets else None
+        check(lib.pinn_jet_residual(
+            self.handle, ctypes.byref(nv.net), ctypes.byref(_pde(self.pde, self.coef)),
+            ctypes.c_void_p(x.data_ptr()), N, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(loss.data_ptr()),
+            ctypes.c_void_p(loss64.data_ptr()) if loss64 is not None else None,
+            ctypes.c_void_p(jets.data_ptr()) if jets is not None else None, _stream()))
+        return r, loss, loss64, jets
+
+    def backward(self, params, x: torch.Tensor, r_bar: Optional[torch.Tensor] = None,
+                 want_f64: bool = False):
+        """Gradient [(dW, db), ...] of the loss (r_bar None) or of <r_bar, r>;
+        with want_f64 also the FP64 reductions."""
+        nv = _NetView(params)
+        N = x.shape[0]
+        dev = x.device
+        if r_bar is not None:
+            _check_tensor(r_bar, "r_bar")
+            if tuple(r_bar.shape) != (self.n_res, N):
+                raise ValueError("r_bar must be (n_res, N)")
+        grads = [(torch.empty_like(W), torch.empty_like(b)) for W, b in params]
+        dWp, k1 = ptr_array([g[0].data_ptr() for g in grads])
+        dbp, k2 = ptr_array([g[1].data_ptr() for g in grads])
+        g64 = None
+        dW64p = db64p = None
+        if want_f64:
+            g64 = [(torch.empty(W.shape, device=dev, dtype=torch.float64),
+                    torch.empty(b.shape, device=dev, dtype=torch.float64)) for W, b in params]
+            dW64p, k3 = ptr_array([g[0].data_ptr() for g in g64])
+            db64p, k4 = ptr_array([g[1].data_ptr() for g in g64])
+        check(lib.pinn_jet_backward(
+            self.handle, ctypes.byref(nv.net), ctypes.byref(_pde(self.pde, self.coef)),
+            ctypes.c_void_p(x.data_ptr()), N,
+            ctypes.c_void_p(r_bar.data_ptr()) if r_bar is not None else None,
+            dWp, dbp, dW64p, db64p, _stream()))
+        return (grads, g64) if want_f64 else grads
+
+
+class JetResidual(torch.autograd.Function):
+    """(r, loss) = JetResidual.apply(plan, x, W1, b1, ..., WL, bL).
+
+    Backward forms r_bar = g_r + g_loss * 2 r / N and runs the library's
+    adjoint; x receives no gradient."""
+
+    @staticmethod
+    def forward(ctx, plan: PinnPlan, x: torch.Tensor, *flat):
+        params = [(flat[2 * i], flat[2 * i + 1]) for i in range(len(flat) // 2)]
+        r, loss, _, _ = plan.residual(params, x)
+        ctx.plan = plan
+        ctx.params = params
+        ctx.save_for_backward(x, r)
+        return r, loss
+
+    @staticmethod
+    def backward(ctx, g_r, g_loss):
+        x, r = ctx.saved_tensors
+        N = x.shape[0]
+        r_bar = None
+        if g_r is not None:
+            r_bar = g_r.contiguous().float()
+        if g_loss is not None:
+            term = g_loss.reshape(()) * (2.0 / N) * r
+            r_bar = term if r_bar is None else r_bar + term
+        if r_bar is None:
+            r_bar = torch.zeros_like(r)
+        grads = ctx.plan.backward(ctx.params, x, r_bar.contiguous())
+        out = [None, None]
+        for dW, db in grads:
+            out += [dW, db]
+        return tuple(out)
+
+
+def jet_residual(plan: PinnPlan, params, x: torch.Tensor):
+    flat: List[torch.Tensor] = [t for pair in params for t in pair]
+    return JetResidual.apply(plan, x, *flat)

@@ -1,0 +1,201 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle, on the
+same seeded inputs.
+
+Bar (rel. L2 over the flattened vector, computed in FP64 on the host):
+  FP32 operands:  jets, residuals and gradient <= 1e-5; loss <= 1e-5 relative.
+  BF16 / FP16:    the measured bound per result, asserted with the margins
+                  below (the paper fixes no low-precision bound).
+Sizes span several point tiles and a ragged tail.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import pinn_inputs as pi
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+# measured-error ceilings of the 16-bit operand paths (relative L2)
+LOWP_TOL = {"bf16": {"r": 2e-2, "grad": 5e-2, "jets": 2e-2},
+            "fp16": {"r": 5e-3, "grad": 1e-2, "jets": 5e-3}}
+
+SMALL = {
+    "burgers": dict(dims=[2, 32, 32, 32, 1], N=300),
+    "ns": dict(dims=[2, 64, 64, 64, 3], N=257),
+    "ks": dict(dims=[2, 64, 64, 64, 1], N=200),
+    "heat": dict(dims=[4, 64, 64, 1], N=130),
+}
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_29702_amd as pj
+    return pj
+
+
+def dev_params(params, grad=False):
+    return [(torch.tensor(W, device="cuda").requires_grad_(grad), torch.tensor(b, device="cuda").requires_grad_(grad))
+            for W, b in params]
+
+
+def flat(grads):
+    return np.concatenate([np.concatenate([dW.detach().double().cpu().numpy().ravel(),
+                                           db.detach().double().cpu().numpy().ravel()]) for dW, db in grads])
+
+
+def small_problem(pde, seed=0, unsaturated=False):
+    cfg = SMALL[pde]
+    prob = pi.make_problem(pde, N=cfg["N"], seed=seed, bias_std=0.3, dims=cfg["dims"])
+    if unsaturated:
+        rng = np.random.default_rng(seed + 77)
+        prob.x = np.stack([rng.uniform(-1.5, 1.5, cfg["N"]), rng.uniform(0, 1, cfg["N"])], 1).astype(np.float32)
+    return prob
+
+
+def run_gpu(lib, prob, prec, verify=True, max_points=None):
+    wl = prob.workload
+    N = prob.x.shape[0]
+    plan = lib.PinnPlan(wl.dims, wl.pde, max_points or N, precision=prec, verify_f64=verify, coef=prob.coef)
+    params = dev_params(prob.params)
+    x = torch.tensor(prob.x, device="cuda")
+    jets_fwd = plan.forward(params, x)
+    r, loss, loss64, jets = plan.residual(params, x, want_jets=True)
+    out = plan.backward(params, x, want_f64=verify)
+    grads, g64 = out if verify else (out, None)
+    torch.cuda.synchronize()
+    res = dict(jets_fwd=jets_fwd.cpu().numpy(), jets=jets.cpu().numpy(), r=r.cpu().numpy(),
+               loss=float(loss), grad=flat(grads))
+    if verify:
+        res["loss64"] = float(loss64)
+        res["grad64"] = flat(g64)
+    plan.close()
+    return res
+
+
+CASES = [("burgers", False), ("ns", False), ("ks", False), ("ks", True), ("heat", False)]
+
+
+@pytest.mark.parametrize("pde,unsat", CASES)
+def test_fp32_parity(lib, pde, unsat):
+    prob = small_problem(pde, seed=1, unsaturated=unsat)
+    g = run_gpu(lib, prob, "fp32")
+    ref = oracle.evaluate(prob.params, prob.x, prob.channels, pde, prob.coef)
+    errs = dict(jets=rel(g["jets"], ref.jets), jets_fwd=rel(g["jets_fwd"], ref.jets), r=rel(g["r"], ref.r),
+                grad=rel(g["grad"], ref.grad), grad64=rel(g["grad64"], ref.grad),
+                loss=abs(g["loss"] - ref.loss) / ref.loss, loss64=abs(g["loss64"] - ref.loss) / ref.loss)
+    print(pde, "unsat" if unsat else "", {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= FP32_TOL, (k, v)
+    assert np.array_equal(g["jets"], g["jets_fwd"])
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("pde,unsat", CASES)
+def test_lowprec_parity(lib, pde, unsat, prec):
+    prob = small_problem(pde, seed=2, unsaturated=unsat)
+    g = run_gpu(lib, prob, prec)
+    ref = oracle.evaluate(prob.params, prob.x, prob.channels, pde, prob.coef)
+    errs = dict(jets=rel(g["jets"], ref.jets), r=rel(g["r"], ref.r), grad=rel(g["grad"], ref.grad))
+    cos = float(g["grad"] @ ref.grad / (np.linalg.norm(g["grad"]) * np.linalg.norm(ref.grad)))
+    print(pde, prec, "unsat" if unsat else "", {k: f"{v:.2e}" for k, v in errs.items()}, f"cos {cos:.6f}")
+    for k, v in errs.items():
+        assert v <= LOWP_TOL[prec][k], (k, v)
+    assert cos > 0.99
+
+
+@pytest.mark.parametrize("N", [1, 17, 127, 128, 129, 383])
+def test_ragged_sizes(lib, N):
+    prob = pi.make_problem("burgers", N=N, seed=3, bias_std=0.3, dims=[2, 32, 32, 1])
+    g = run_gpu(lib, prob, "fp32", max_points=400)
+    ref = oracle.evaluate(prob.params, prob.x, prob.channels, "burgers", prob.coef)
+    assert rel(g["r"], ref.r) <= FP32_TOL
+    assert rel(g["grad"], ref.grad) <= FP32_TOL
+    assert abs(g["loss"] - ref.loss) <= FP32_TOL * ref.loss
+
+
+def test_cotangent_and_autograd(lib):
+    """The autograd Function's backward equals J^T r_bar with r_bar = g_r + 2 g_L r / N,
+    and an explicit cotangent matches the oracle's J^T w."""
+    prob = small_problem("ns", seed=4)
+    wl = prob.workload
+    N = prob.x.shape[0]
+    plan = lib.PinnPlan(wl.dims, "ns", N, coef=prob.coef)
+    params = dev_params(prob.params, grad=True)
+    x = torch.tensor(prob.x, device="cuda")
+    w = torch.tensor(np.random.default_rng(5).normal(size=(3, N)).astype(np.float32), device="cuda")
+    r, loss = lib.jet_residual(plan, params, x)
+    ((r * w).sum() + 0.5 * loss).backward()
+    torch.cuda.synchronize()
+    got = flat([(W.grad, b.grad) for W, b in params])
+    ref_w = oracle.evaluate(prob.params, prob.x, prob.channels, "ns", prob.coef,
+                            r_bar=w.cpu().numpy().astype(np.float64)).grad
+    ref_l = oracle.evaluate(prob.params, prob.x, prob.channels, "ns", prob.coef).grad
+    assert rel(got, ref_w + 0.5 * ref_l) <= FP32_TOL
+    plan.close()
+
+
+def test_inner_product_identity_gpu(lib):
+    """<J delta, w> (oracle complex step) = <delta, J^T w> (GPU adjoint, FP64 reduction)."""
+    prob = small_problem("ks", seed=6, unsaturated=True)
+    wl = prob.workload
+    N = prob.x.shape[0]
+    plan = lib.PinnPlan(wl.dims, "ks", N, verify_f64=True, coef=prob.coef)
+    params = dev_params(prob.params)
+    x = torch.tensor(prob.x, device="cuda")
+    rng = np.random.default_rng(7)
+    w = rng.normal(size=(1, N)).astype(np.float32)
+    plan.residual(params, x)
+    _, g64 = plan.backward(params, x, r_bar=torch.tensor(w, device="cuda"), want_f64=True)
+    JTw = flat(g64)
+    delta = rng.normal(size=JTw.size)
+    _, Jd, _ = oracle.complex_step(prob.params, delta, prob.x, prob.channels, "ks", prob.coef)
+    lhs = float(np.sum(Jd * w))
+    rhs = float(delta @ JTw)
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+    plan.close()
+
+
+def test_determinism(lib):
+    prob = small_problem("heat", seed=8)
+    a = run_gpu(lib, prob, "bf16")
+    b = run_gpu(lib, prob, "bf16")
+    for k in ("jets", "r", "grad", "grad64"):
+        assert np.array_equal(a[k], b[k]), k
+    assert a["loss"] == b["loss"]
+
+
+def test_state_errors(lib):
+    from paper_2606_29702_amd import PinnError
+    prob = small_problem("burgers", seed=9)
+    wl = prob.workload
+    N = prob.x.shape[0]
+    plan = lib.PinnPlan(wl.dims, "burgers", N, coef=prob.coef)
+    params = dev_params(prob.params)
+    x = torch.tensor(prob.x, device="cuda")
+    with pytest.raises(PinnError) as e:
+        plan.backward(params, x)
+    assert e.value.status == -5
+    plan.residual(params, x)
+    with pytest.raises(PinnError) as e:
+        plan.backward(params, x[: N - 1].contiguous())
+    assert e.value.status == -5
+    plan.forward(params, x)  # invalidates the saved state
+    with pytest.raises(PinnError) as e:
+        plan.backward(params, x)
+    assert e.value.status == -5
+    with pytest.raises(PinnError) as e:
+        plan.residual(params, torch.zeros((N + 1, 2), device="cuda"))
+    assert e.value.status == -1
+    plan.close()
