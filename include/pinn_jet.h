@@ -151,6 +151,24 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
                               float *const *dW, float *const *db,
                               double *const *dW_f64, double *const *db_f64, void *stream);
 
+/* Launch timing, a measurement aid for benchmarks.  pinn_plan_profile selects
+ * one kernel class (0 = off) and clears the accumulator; from then on every
+ * launch of that class made through this plan is bracketed by a pair of
+ * hipEvents recorded on the call's stream.  pinn_plan_profile_read waits for
+ * the recorded events and returns the summed kernel time (ms) and the number
+ * of launches.  Do not enable it while capturing a HIP graph. */
+enum {
+  PINN_K_LAYER_FWD = 1,  /* hidden-layer GEMM + activation jet                  */
+  PINN_K_LAYER_BWD = 2,  /* hidden-layer transposed GEMM + jet adjoint          */
+  PINN_K_DW_HIDDEN = 3,  /* hidden-layer weight gradient (split-K partials)     */
+  PINN_K_OUT_FWD = 4,    /* output layer + residual + loss partials             */
+  PINN_K_OUT_BWD = 5,    /* residual adjoint + output layer adjoint             */
+  PINN_K_SEED_FWD = 6,   /* first layer + activation jet                        */
+  PINN_K_OTHER = 7       /* casts, reductions, first/last layer gradients       */
+};
+pinn_status pinn_plan_profile(pinn_plan plan, int32_t kernel_class);
+pinn_status pinn_plan_profile_read(pinn_plan plan, double *total_ms, int64_t *launches);
+
 /* Message for the last non-OK status on this host thread ("" if none). */
 const char *pinn_last_error(void);
 

@@ -26,7 +26,9 @@ PINN_VERIFY_F64 = 1
 # Every symbol the public header declares.
 EXPORTS = ["pinn_plan_create", "pinn_plan_destroy", "pinn_plan_memory", "pinn_jet_forward",
            "pinn_jet_residual", "pinn_jet_backward", "pinn_last_error", "pinn_pde_channels",
-           "pinn_pde_residuals"]
+           "pinn_pde_residuals", "pinn_plan_profile", "pinn_plan_profile_read"]
+KERNEL_CLASSES = {"layer_fwd": 1, "layer_bwd": 2, "dw_hidden": 3, "out_fwd": 4, "out_bwd": 5,
+                  "seed_fwd": 6, "other": 7}
 
 
 class PinnError(RuntimeError):
@@ -57,12 +59,15 @@ def _load():
     lib.pinn_jet_forward.argtypes = [vp, NetP, vp, i64, vp, vp]
     lib.pinn_jet_residual.argtypes = [vp, NetP, PdeP, vp, i64, vp, vp, vp, vp, vp]
     lib.pinn_jet_backward.argtypes = [vp, NetP, PdeP, vp, i64, vp, pp, pp, pp, pp, vp]
+    lib.pinn_plan_profile.argtypes = [vp, i32]
+    lib.pinn_plan_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.pinn_last_error.restype = ctypes.c_char_p
     lib.pinn_last_error.argtypes = []
     lib.pinn_pde_channels.argtypes = [i32]
     lib.pinn_pde_residuals.argtypes = [i32]
     for name in ("pinn_plan_create", "pinn_plan_destroy", "pinn_plan_memory", "pinn_jet_forward",
-                 "pinn_jet_residual", "pinn_jet_backward", "pinn_pde_channels", "pinn_pde_residuals"):
+                 "pinn_jet_residual", "pinn_jet_backward", "pinn_pde_channels", "pinn_pde_residuals",
+                 "pinn_plan_profile", "pinn_plan_profile_read"):
         getattr(lib, name).restype = ctypes.c_int32
     return lib
 

@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void k_dw_hidden(const T *__restrict__ Zb, con
     __syncthreads();
   }
 
-  float *pp = part + (int64_t)blockIdx.z * w * w;
+  float *pp = part + (int64_t)blockIdx.z * ((int64_t)w * w + w);
 #pragma unroll
   for (int jt = 0; jt < NT; ++jt)
 #pragma unroll
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(256) void k_dw_hidden(const T *__restrict__ Zb, con
         const int k = k0 + H * wk + 16 * kt + r16;
         pp[(int64_t)j * w + k] = acc[jt][kt][i];
       }
-  if (do_db && t < TILE) part_db[(int64_t)blockIdx.z * w + j0 + t] = db;
+  if (do_db && t < TILE) part_db[(int64_t)blockIdx.z * ((int64_t)w * w + w) + j0 + t] = db;
 }
 
 namespace {

@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void k_seed_fwd(const float *__restrict__ x, i
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     A1[base + (int64_t)c * w] = static_cast<T>(a[c]);
-    S1[base + (int64_t)c * w] = c == 0 ? s : z[c];
+    if (S1) S1[base + (int64_t)c * w] = c == 0 ? s : z[c];
   }
 }
 
@@ -192,20 +192,17 @@ __global__ __launch_bounds__(256) void k_loss_reduce(const float *__restrict__ p
 }
 
 // ------------------------------------------------------ output adjoint
-// ubar = d<rbar, r>/du (residual adjoint), abar_c = W_L^T ubar_c, then the
-// jet adjoint of the last hidden layer.  16 lanes per point.
-template <class PDE, class T>
-__global__ __launch_bounds__(256) void k_out_bwd(const float *__restrict__ u_save,
+// ubar = d<rbar, r>/du by the residual adjoint; one thread per point.
+template <class PDE>
+__global__ __launch_bounds__(256) void k_out_adj(const float *__restrict__ u_save,
                                                  const float *__restrict__ r_save,
                                                  const float *__restrict__ r_bar, int64_t N,
-                                                 int64_t N_pad, float rbar_scale,
-                                                 const float *__restrict__ WL,
-                                                 const float *__restrict__ SH, int w, Coef k,
-                                                 float *__restrict__ ubar, T *__restrict__ ZbH) {
+                                                 int64_t N_pad, float rbar_scale, Coef k,
+                                                 float *__restrict__ ubar) {
   using CH = typename PDE::CH;
   constexpr int C = CH::C, DOUT = PDE::DOUT, NRES = PDE::NRES;
-  const int q = threadIdx.x & 15, grp = threadIdx.x >> 4;
-  const int64_t n = (int64_t)blockIdx.x * 16 + grp;
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (n >= N_pad) return;
   const bool valid = n < N;
   float u[DOUT][C], ub[DOUT][C], rb[NRES];
 #pragma unroll
@@ -216,46 +213,35 @@ __global__ __launch_bounds__(256) void k_out_bwd(const float *__restrict__ u_sav
   for (int e = 0; e < NRES; ++e)
     rb[e] = !valid ? 0.f : (r_bar ? r_bar[e * N + n] : rbar_scale * r_save[e * N_pad + n]);
   PDE::adjoint(u, rb, k, ub);
-  if (q == 0)
 #pragma unroll
-    for (int o = 0; o < DOUT; ++o)
+  for (int o = 0; o < DOUT; ++o)
 #pragma unroll
-      for (int c = 0; c < C; ++c) ubar[(n * DOUT + o) * C + c] = ub[o][c];
-  const float *sp = SH + n * C * w;
-  T *zp = ZbH + n * C * w;
-  for (int kk = q; kk < w; kk += 16) {
-    float ab[C], zs[C], zb[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      float s = 0.f;
-#pragma unroll
-      for (int o = 0; o < DOUT; ++o) s += WL[o * w + kk] * ub[o][c];
-      ab[c] = s;
-      zs[c] = sp[c * w + kk];
-    }
-    jet_adjoint<CH>(ab, zs[0], zs, zb);
-#pragma unroll
-    for (int c = 0; c < C; ++c) zp[c * w + kk] = static_cast<T>(zb[c]);
-  }
+    for (int c = 0; c < C; ++c) ubar[(n * DOUT + o) * C + c] = ub[o][c];
 }
 
 // ------------------------------------------------ thin gradient reductions
 // Output layer: dW_L[o][k] = sum_n sum_c ubar[n][o][c] a_H[n][c][k],
-// db_L[o] = sum_n ubar[n][o][0].  Workgroup = (chunk of points, 256 neurons).
+// db_L[o] = sum_n ubar[n][o][0].  Workgroup = one chunk of points; thread
+// (sub, k) handles neuron k for the points sub, sub + NSUB, ... of the chunk
+// (NSUB = 256 / w sub-groups when w < 256); the sub-group sums are added in
+// sub order through LDS.
 template <class PDE, class T>
 __global__ __launch_bounds__(256) void k_dw_out(const float *__restrict__ ubar, const T *__restrict__ AH,
                                                 int64_t N_pad, int w, float *__restrict__ part,
                                                 int64_t pts_per_chunk) {
   constexpr int C = PDE::CH::C, DOUT = PDE::DOUT;
-  const int kk = blockIdx.y * 256 + threadIdx.x;
+  __shared__ float red[256 * DOUT];
+  const int nsub = w >= 256 ? 1 : 256 / w;
+  const int sub = threadIdx.x / (w >= 256 ? 256 : w);
+  const int kk = blockIdx.y * 256 + threadIdx.x % (w >= 256 ? 256 : w);
   const int64_t nb = (int64_t)blockIdx.x * pts_per_chunk;
   const int64_t ne = nb + pts_per_chunk < N_pad ? nb + pts_per_chunk : N_pad;
-  float acc[DOUT], accb[DOUT];
+  float acc[DOUT];
 #pragma unroll
-  for (int o = 0; o < DOUT; ++o) acc[o] = accb[o] = 0.f;
-  for (int64_t n = nb; n < ne; ++n) {
-    const float *ub = ubar + n * DOUT * C;
-    if (kk < w) {
+  for (int o = 0; o < DOUT; ++o) acc[o] = 0.f;
+  if (sub < nsub && kk < w) {
+    for (int64_t n = nb + sub; n < ne; n += nsub) {
+      const float *ub = ubar + n * DOUT * C;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         const float a = to_f32(AH[(n * C + c) * w + kk]);
@@ -263,70 +249,116 @@ __global__ __launch_bounds__(256) void k_dw_out(const float *__restrict__ ubar, 
         for (int o = 0; o < DOUT; ++o) acc[o] += ub[o * C + c] * a;
       }
     }
-#pragma unroll
-    for (int o = 0; o < DOUT; ++o) accb[o] += ub[o * C];
   }
+#pragma unroll
+  for (int o = 0; o < DOUT; ++o) red[o * 256 + threadIdx.x] = acc[o];
+  __syncthreads();
   const int64_t stride = (int64_t)DOUT * w + DOUT;
   float *pp = part + blockIdx.x * stride;
-  if (kk < w)
+  if (threadIdx.x < (w >= 256 ? 256 : w) && kk < w) {
 #pragma unroll
-    for (int o = 0; o < DOUT; ++o) pp[o * w + kk] = acc[o];
-  if (blockIdx.y == 0 && threadIdx.x == 0)
-#pragma unroll
-    for (int o = 0; o < DOUT; ++o) pp[DOUT * w + o] = accb[o];
+    for (int o = 0; o < DOUT; ++o) {
+      float s = 0.f;
+      for (int q = 0; q < nsub; ++q) s += red[o * 256 + q * w + threadIdx.x];
+      pp[o * w + kk] = s;
+    }
+  }
+  if (blockIdx.y == 0 && threadIdx.x < DOUT) {
+    float s = 0.f;
+    for (int64_t n = nb; n < ne; ++n) s += ubar[(n * DOUT + threadIdx.x) * C];
+    pp[DOUT * w + threadIdx.x] = s;
+  }
 }
 
 // First layer: dW_1[j][i] = sum_n (zbar_0[n][j] x[n][i] + zbar_{e_i}[n][j]),
 // where zbar_{e_i} is the first-order channel along input i (its seed is the
-// unit vector e_i); db_1[j] = sum_n zbar_0[n][j].
+// unit vector e_i); db_1[j] = sum_n zbar_0[n][j].  Same thread layout as above.
 template <class CH, class T>
 __global__ __launch_bounds__(256) void k_dw_seed(const T *__restrict__ Zb1, const float *__restrict__ x,
                                                  int64_t N, int w, float *__restrict__ part,
                                                  int64_t pts_per_chunk) {
   constexpr int C = CH::C, D = CH::DIN;
-  const int j = blockIdx.y * 256 + threadIdx.x;
-  if (j >= w) return;
+  __shared__ float red[256 * (D + 1)];
+  const int span = w >= 256 ? 256 : w;
+  const int nsub = 256 / span;
+  const int sub = threadIdx.x / span;
+  const int j = blockIdx.y * 256 + threadIdx.x % span;
   const int64_t nb = (int64_t)blockIdx.x * pts_per_chunk;
   const int64_t ne = nb + pts_per_chunk < N ? nb + pts_per_chunk : N;
-  float acc[D], accb = 0.f;
+  float acc[D + 1];
 #pragma unroll
-  for (int i = 0; i < D; ++i) acc[i] = 0.f;
-  for (int64_t n = nb; n < ne; ++n) {
-    const T *zp = Zb1 + n * C * w + j;
-    const float z0 = to_f32(zp[0]);
+  for (int i = 0; i <= D; ++i) acc[i] = 0.f;
+  if (sub < nsub && j < w) {
+    for (int64_t n = nb + sub; n < ne; n += nsub) {
+      const T *zp = Zb1 + n * C * w + j;
+      const float z0 = to_f32(zp[0]);
 #pragma unroll
-    for (int i = 0; i < D; ++i) acc[i] += z0 * x[n * D + i];
+      for (int i = 0; i < D; ++i) acc[i] += z0 * x[n * D + i];
 #pragma unroll
-    for (int d = 0; d < CH::NDIR; ++d) acc[CH::in(d)] += to_f32(zp[(int64_t)CH::at(d, 1) * w]);
-    accb += z0;
+      for (int d = 0; d < CH::NDIR; ++d) acc[CH::in(d)] += to_f32(zp[(int64_t)CH::at(d, 1) * w]);
+      acc[D] += z0;
+    }
   }
-  const int64_t stride = (int64_t)w * D + w;
-  float *pp = part + blockIdx.x * stride;
 #pragma unroll
-  for (int i = 0; i < D; ++i) pp[j * D + i] = acc[i];
-  pp[(int64_t)w * D + j] = accb;
+  for (int i = 0; i <= D; ++i) red[i * 256 + threadIdx.x] = acc[i];
+  __syncthreads();
+  if (threadIdx.x < span && j < w) {
+    const int64_t stride = (int64_t)w * D + w;
+    float *pp = part + blockIdx.x * stride;
+#pragma unroll
+    for (int i = 0; i <= D; ++i) {
+      float s = 0.f;
+      for (int q = 0; q < nsub; ++q) s += red[i * 256 + q * span + threadIdx.x];
+      if (i < D)
+        pp[j * D + i] = s;
+      else
+        pp[(int64_t)w * D + j] = s;
+    }
+  }
 }
 
-__global__ __launch_bounds__(256) void k_reduce_parts(const float *__restrict__ part, int splits,
-                                                      int64_t stride, int64_t M1, int64_t M2,
-                                                      float *__restrict__ a32, float *__restrict__ b32,
-                                                      double *__restrict__ a64, double *__restrict__ b64) {
-  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (q >= M1 + M2) return;
-  const bool want64 = q < M1 ? (a64 != nullptr) : (b64 != nullptr);
+// Deterministic sum over `splits` partial arrays.  A workgroup owns 256 / G
+// outputs; thread (o, g) sums the splits g, g + G, g + 2G, ... of output o in
+// order, and the G group sums are then added in g order.
+template <int G>
+__global__ __launch_bounds__(256) void k_reduce_parts_g(const float *__restrict__ part, int splits,
+                                                        int64_t stride, int64_t M1, int64_t M2,
+                                                        float *__restrict__ a32, float *__restrict__ b32,
+                                                        double *__restrict__ a64, double *__restrict__ b64) {
+  constexpr int OUTS = 256 / G;
+  __shared__ float s32[256];
+  __shared__ double s64[256];
+  const int o = threadIdx.x % OUTS, g = threadIdx.x / OUTS;
+  const int64_t q = (int64_t)blockIdx.x * OUTS + o;
+  const bool live = q < M1 + M2;
+  const bool want64 = live && (q < M1 ? (a64 != nullptr) : (b64 != nullptr));
   float s = 0.f;
   double sd = 0.0;
-  for (int sp = 0; sp < splits; ++sp) {
-    const float v = part[sp * stride + q];
-    s += v;
-    if (want64) sd += (double)v;
+  if (live) {
+#pragma unroll 4
+    for (int sp = g; sp < splits; sp += G) {
+      const float v = part[sp * stride + q];
+      s += v;
+      if (want64) sd += (double)v;
+    }
   }
-  if (q < M1) {
-    if (a32) a32[q] = s;
-    if (a64) a64[q] = sd;
-  } else {
-    if (b32) b32[q - M1] = s;
-    if (b64) b64[q - M1] = sd;
+  s32[threadIdx.x] = s;
+  s64[threadIdx.x] = sd;
+  __syncthreads();
+  if (g == 0 && live) {
+    float t = 0.f;
+    double td = 0.0;
+    for (int k = 0; k < G; ++k) {
+      t += s32[k * OUTS + o];
+      td += s64[k * OUTS + o];
+    }
+    if (q < M1) {
+      if (a32) a32[q] = t;
+      if (a64) a64[q] = td;
+    } else {
+      if (b32) b32[q - M1] = t;
+      if (b64) b64[q - M1] = td;
+    }
   }
 }
 
@@ -394,25 +426,20 @@ hipError_t launch_loss_reduce(const float *part, const double *part64, int n_par
   return hipGetLastError();
 }
 
-hipError_t launch_out_bwd(int kind, int prec, const float *u_save, const float *r_save,
-                          const float *r_bar, int64_t N, int64_t N_pad, float rbar_scale,
-                          const float *WL, const float *S_H, int w, Coef k, float *ubar,
-                          void *Zb_H, hipStream_t st) {
-  dim3 grid((unsigned)(N_pad / 16));
+hipError_t launch_out_adj(int kind, const float *u_save, const float *r_save, const float *r_bar,
+                          int64_t N, int64_t N_pad, float rbar_scale, Coef k, float *ubar, hipStream_t st) {
+  dim3 grid((unsigned)((N_pad + 255) / 256));
   return by_kind(kind, [&](auto pde) {
     using PDE = decltype(pde);
-    return by_prec(prec, [&](auto tv) {
-      using T = decltype(tv);
-      hipLaunchKernelGGL((k_out_bwd<PDE, T>), grid, dim3(256), 0, st, u_save, r_save, r_bar, N, N_pad,
-                         rbar_scale, WL, S_H, w, k, ubar, static_cast<T *>(Zb_H));
-      return hipGetLastError();
-    });
+    hipLaunchKernelGGL((k_out_adj<PDE>), grid, dim3(256), 0, st, u_save, r_save, r_bar, N, N_pad, rbar_scale,
+                       k, ubar);
+    return hipGetLastError();
   });
 }
 
 hipError_t launch_dw_out(int kind, int prec, const float *ubar, const void *A_H, int64_t N_pad,
                          int w, float *part, int n_chunks, hipStream_t st) {
-  const int64_t ppc = (N_pad + n_chunks - 1) / n_chunks;
+  const int64_t ppc = (N_pad + n_chunks - 1) / n_chunks;  // chunks beyond N_pad write zeros
   dim3 grid((unsigned)n_chunks, (unsigned)((w + 255) / 256));
   return by_kind(kind, [&](auto pde) {
     using PDE = decltype(pde);
@@ -449,9 +476,16 @@ hipError_t launch_reduce_parts2(const float *part, int splits, int64_t stride, i
                                 int64_t M2, float *a32, float *b32, double *a64, double *b64,
                                 hipStream_t st) {
   const int64_t M = M1 + M2;
-  dim3 grid((unsigned)((M + 255) / 256));
-  hipLaunchKernelGGL(k_reduce_parts, grid, dim3(256), 0, st, part, splits, stride, M1, M2, a32, b32,
-                     a64, b64);
+  // few outputs with many splits: more threads per output
+  if (M * 4 < 256LL * 256 && splits >= 64) {
+    dim3 grid((unsigned)((M + 7) / 8));
+    hipLaunchKernelGGL(k_reduce_parts_g<32>, grid, dim3(256), 0, st, part, splits, stride, M1, M2, a32, b32,
+                       a64, b64);
+  } else {
+    dim3 grid((unsigned)((M + 63) / 64));
+    hipLaunchKernelGGL(k_reduce_parts_g<4>, grid, dim3(256), 0, st, part, splits, stride, M1, M2, a32, b32,
+                       a64, b64);
+  }
   return hipGetLastError();
 }
 

@@ -1,161 +1,301 @@
-// Hidden-layer stacked-channel GEMM on MFMA with the activation jet (forward)
+// Hidden-layer stacked-channel GEMMs on MFMA with the activation jet (forward)
 // or its adjoint (backward) fused into the epilogue.
 //
 // All channels of a layer share one weight matrix (Sec. 2.2: the states are
-// stacked along the batch dimension and go through one GEMM).  Here the stack
-// of a point block is [points][C][w]; a workgroup computes, for 32*WN points
-// and 32*WJ output neurons, all C channels at once, so that every lane ends
-// the contraction holding z_0 ... z_{C-1} of the same (neuron, point) pairs in
-// registers and can apply the jet rules of Eq. 2-3 (and their adjoint)
-// without another pass over memory.
+// stacked along the batch dimension and go through one GEMM).  A stack is
+// stored [points][C][w]; a wave computes, for 32 output neurons and 16*NTN
+// points, all C channels at once, so that every lane ends the contraction
+// holding z_0 ... z_{C-1} of the same (neuron, point) pairs in registers and
+// can apply the jet rules of Eq. 2-3 (and their adjoint) without another pass
+// over memory.
 //
-// Tile: 4 waves; wave (wj, wn) owns neurons [32 wj, 32 wj + 32) x points
-// [32 wn, 32 wn + 32) of the workgroup tile, i.e. 2 x 2 MFMA 16x16 output
-// tiles per channel.  The contraction runs over the neuron index of the
-// previous layer, 32 at a time.
+// Workgroup: 4 waves, WJ of them side by side along the neurons and 4/WJ
+// along the points.  Output tile per wave: 2 x NTN MFMA 16x16 tiles per
+// channel; the contraction runs over the neuron index of the previous layer,
+// 32 at a time, with operands read straight from global memory (L2-resident
+// weights; each stack element is read by the WJ waves that share its points).
 #include "dev_common.hpp"
 #include "kernels.hpp"
 
 namespace pj {
 
-template <class CH, class T, int WJ, bool BWD>
-__global__ __launch_bounds__(256) void k_layer(const T *__restrict__ Bsrc, const T *__restrict__ Wop,
-                                               const float *__restrict__ bias,
-                                               const float *__restrict__ S_in, T *__restrict__ Out,
-                                               float *__restrict__ S_out, int w) {
+// Accumulates acc[jt][nt][c] += sum_k Wop[m0 + 16 jt + r][k] * B[n0 + 16 nt + r][c][k]
+// over k in [0, w): the stacked-channel GEMM of one wave tile.
+template <class T, int C, int NTN>
+__device__ __forceinline__ void stacked_gemm(f32x4 (&acc)[2][NTN][C], const T *__restrict__ Wop,
+                                             const T *__restrict__ B, int m0, int64_t n0, int w, int lane) {
   using M = Mma<T>;
-  constexpr int C = CH::C;
-  constexpr int WN = 4 / WJ;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int wj = wave % WJ, wn = wave / WJ;
-  const int m0 = (blockIdx.y * WJ + wj) * 32;  // first output neuron of this wave
-  const int64_t n0 = ((int64_t)blockIdx.x * WN + wn) * 32;  // first point of this wave
   const int r = lane & 15, g = lane >> 4;
-  const int64_t ps = (int64_t)C * w;  // elements per point in a stack
-
-  f32x4 acc[2][2][C];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int c = 0; c < C; ++c) acc[a][b][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-
+  const int64_t ps = (int64_t)C * w;
   const T *wp0 = Wop + (int64_t)(m0 + r) * w + 8 * g;
   const T *wp1 = wp0 + (int64_t)16 * w;
-  const T *bp0 = Bsrc + (n0 + r) * ps + 8 * g;
-  const T *bp1 = bp0 + 16 * ps;
-
+  const T *bp = B + (n0 + r) * ps + 8 * g;
   for (int k = 0; k < w; k += 32) {
     const typename M::frag a0 = M::load(wp0 + k);
     const typename M::frag a1 = M::load(wp1 + k);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      const typename M::frag b0 = M::load(bp0 + c * w + k);
-      const typename M::frag b1 = M::load(bp1 + c * w + k);
-      M::mma(acc[0][0][c], a0, b0);
-      M::mma(acc[0][1][c], a0, b1);
-      M::mma(acc[1][0][c], a1, b0);
-      M::mma(acc[1][1][c], a1, b1);
+#pragma unroll
+      for (int nt = 0; nt < NTN; ++nt) {
+        const typename M::frag b = M::load(bp + nt * 16 * ps + c * w + k);
+        M::mma(acc[0][nt][c], a0, b);
+        M::mma(acc[1][nt][c], a1, b);
+      }
     }
   }
+}
 
-  // Epilogue: lane holds neurons mb..mb+3 of point n for every channel.
+template <int C, int NTN>
+__device__ __forceinline__ void zero_acc(f32x4 (&acc)[2][NTN][C]) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < NTN; ++b)
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[a][b][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+}
+
+// Forward hidden layer: Z = W A_in (+ b on the value channel), A_out = jet(Z);
+// with STORE_S also the FP32 state S (tanh z_0 and the derivative channels).
+template <class CH, class T, int WJ, bool STORE_S>
+__global__ __launch_bounds__(256) void k_layer_fwd(const T *__restrict__ A_in, const T *__restrict__ Wop,
+                                                   const float *__restrict__ bias, T *__restrict__ A_out,
+                                                   float *__restrict__ S_out, int w) {
+  constexpr int C = CH::C;
+  constexpr int WN = 4 / WJ;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wj = wave % WJ, wn = wave / WJ;
+  const int m0 = (blockIdx.y * WJ + wj) * 32;
+  const int64_t n0 = ((int64_t)blockIdx.x * WN + wn) * 32;
+  const int r = lane & 15, g = lane >> 4;
+  const int64_t ps = (int64_t)C * w;
+
+  f32x4 acc[2][2][C];
+  zero_acc<C, 2>(acc);
+  stacked_gemm<T, C, 2>(acc, Wop, A_in, m0, n0, w, lane);
+
 #pragma unroll
   for (int jt = 0; jt < 2; ++jt) {
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
       const int64_t n = n0 + 16 * nt + r;
       const int mb = m0 + 16 * jt + 4 * g;
-      float out[4][C];
-      if constexpr (!BWD) {
-        float sv[4][C];
+      float out[4][C], sv[4][C];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          float z[C], a[C];
+      for (int i = 0; i < 4; ++i) {
+        float z[C], a[C], s;
 #pragma unroll
-          for (int c = 0; c < C; ++c) z[c] = acc[jt][nt][c][i];
-          z[0] += bias[mb + i];
-          float s;
-          jet_forward<CH>(z, a, s);
-          sv[i][0] = s;
-#pragma unroll
-          for (int c = 0; c < C; ++c) {
-            out[i][c] = a[c];
-            if (c > 0) sv[i][c] = z[c];
-          }
-        }
+        for (int c = 0; c < C; ++c) z[c] = acc[jt][nt][c][i];
+        z[0] += bias[mb + i];
+        jet_forward<CH>(z, a, s);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          store4(Out + n * ps + c * w + mb, out[0][c], out[1][c], out[2][c], out[3][c]);
-          store4(S_out + n * ps + c * w + mb, sv[0][c], sv[1][c], sv[2][c], sv[3][c]);
+          out[i][c] = a[c];
+          sv[i][c] = c == 0 ? s : z[c];
         }
-      } else {
-        f32x4 sv[C];
+      }
 #pragma unroll
-        for (int c = 0; c < C; ++c) sv[c] = *reinterpret_cast<const f32x4 *>(S_in + n * ps + c * w + mb);
+      for (int c = 0; c < C; ++c) {
+        store4(A_out + n * ps + c * w + mb, out[0][c], out[1][c], out[2][c], out[3][c]);
+        if constexpr (STORE_S) store4(S_out + n * ps + c * w + mb, sv[0][c], sv[1][c], sv[2][c], sv[3][c]);
+      }
+    }
+  }
+}
+
+// Backward hidden layer.  Produces Zbar of layer l-1 for one tile:
+//   abar  = W_l^T Zbar_l (MFMA)                      when !TOP
+//         = W_L^T ubar   (output layer, d_out rows)  when TOP
+//   z     = saved S                                  ZSRC == Z_FROM_S
+//         = W_{l-1} A_{l-2} + b_{l-1} (MFMA recompute) ZSRC == Z_FROM_GEMM
+//         = W_1 x + b_1 with the input seeds         ZSRC == Z_FROM_X
+//   Zbar_{l-1} = jet_adjoint(abar, z).
+enum { Z_FROM_S = 0, Z_FROM_GEMM = 1, Z_FROM_X = 2 };
+
+struct BwdArgs {
+  const void *Zb_in;   // [N_pad][C][w] operand type (!TOP)
+  const void *WT;      // [w][w] transpose of W_l, operand type (!TOP)
+  const float *ubar;   // [N_pad][DOUT][C] (TOP)
+  const float *WL;     // [DOUT][w] (TOP)
+  const float *S_in;   // [N_pad][C][w] (Z_FROM_S)
+  const void *A_prev;  // [N_pad][C][w] operand type (Z_FROM_GEMM)
+  const void *Wz;      // [w][w] operand type (Z_FROM_GEMM)
+  const float *bz;     // [w] (Z_FROM_GEMM, Z_FROM_X)
+  const float *x;      // [N][DIN] (Z_FROM_X)
+  const float *W1;     // [w][DIN] (Z_FROM_X)
+  int64_t N;
+  void *Zb_out;        // [N_pad][C][w] operand type
+  int w;
+};
+
+template <class CH, class T, int WJ, int NTN, bool TOP, int DOUT, int ZSRC>
+__global__ __launch_bounds__(256) void k_layer_bwd(BwdArgs args) {
+  constexpr int C = CH::C, D = CH::DIN;
+  constexpr int WN = 4 / WJ;
+  const int w = args.w;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wj = wave % WJ, wn = wave / WJ;
+  const int m0 = (blockIdx.y * WJ + wj) * 32;
+  const int64_t n0 = ((int64_t)blockIdx.x * WN + wn) * (16 * NTN);
+  const int r = lane & 15, g = lane >> 4;
+  const int64_t ps = (int64_t)C * w;
+  T *Zb_out = static_cast<T *>(args.Zb_out);
+
+  f32x4 acc_a[2][NTN][C];
+  zero_acc<C, NTN>(acc_a);
+  if constexpr (!TOP)
+    stacked_gemm<T, C, NTN>(acc_a, static_cast<const T *>(args.WT), static_cast<const T *>(args.Zb_in), m0, n0,
+                            w, lane);
+  f32x4 acc_z[2][NTN][C];
+  if constexpr (ZSRC == Z_FROM_GEMM) {
+    zero_acc<C, NTN>(acc_z);
+    stacked_gemm<T, C, NTN>(acc_z, static_cast<const T *>(args.Wz), static_cast<const T *>(args.A_prev), m0, n0,
+                            w, lane);
+  }
+
+#pragma unroll
+  for (int jt = 0; jt < 2; ++jt) {
+#pragma unroll
+    for (int nt = 0; nt < NTN; ++nt) {
+      const int64_t n = n0 + 16 * nt + r;
+      const int mb = m0 + 16 * jt + 4 * g;
+      // z (pre-activation channels of layer l-1) for the 4 neurons of this lane
+      float zz[4][C];
+      if constexpr (ZSRC == Z_FROM_S) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const f32x4 v = *reinterpret_cast<const f32x4 *>(args.S_in + n * ps + c * w + mb);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) zz[i][c] = v[i];
+        }
+      } else if constexpr (ZSRC == Z_FROM_GEMM) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          float ab[C], zs[C], zb[C];
+#pragma unroll
+          for (int c = 0; c < C; ++c) zz[i][c] = acc_z[jt][nt][c][i];
+          zz[i][0] = tanhf(zz[i][0] + args.bz[mb + i]);
+        }
+      } else {
+        float xin[D];
+#pragma unroll
+        for (int q = 0; q < D; ++q) xin[q] = n < args.N ? args.x[n * D + q] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int j = mb + i;
+#pragma unroll
+          for (int c = 0; c < C; ++c) zz[i][c] = 0.f;
+          float z0 = args.bz[j];
+#pragma unroll
+          for (int q = 0; q < D; ++q) z0 += args.W1[j * D + q] * xin[q];
+          zz[i][0] = tanhf(z0);
+#pragma unroll
+          for (int d = 0; d < CH::NDIR; ++d) zz[i][CH::at(d, 1)] = args.W1[j * D + CH::in(d)];
+        }
+      }
+      // abar for the same neurons
+      float ab[4][C];
+      if constexpr (TOP) {
+        float ub[DOUT][C];
+#pragma unroll
+        for (int o = 0; o < DOUT; ++o)
+#pragma unroll
+          for (int c = 0; c < C; ++c) ub[o][c] = args.ubar[(n * DOUT + o) * C + c];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int c = 0; c < C; ++c) {
-            ab[c] = acc[jt][nt][c][i];
-            zs[c] = sv[c][i];
+            float s = 0.f;
+#pragma unroll
+            for (int o = 0; o < DOUT; ++o) s += args.WL[o * w + mb + i] * ub[o][c];
+            ab[i][c] = s;
           }
-          jet_adjoint<CH>(ab, zs[0], zs, zb);
+      } else {
 #pragma unroll
-          for (int c = 0; c < C; ++c) out[i][c] = zb[c];
-        }
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int c = 0; c < C; ++c)
-          store4(Out + n * ps + c * w + mb, out[0][c], out[1][c], out[2][c], out[3][c]);
+          for (int c = 0; c < C; ++c) ab[i][c] = acc_a[jt][nt][c][i];
       }
+      float out[4][C];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float zb[C];
+        jet_adjoint<CH>(ab[i], zz[i][0], zz[i], zb);
+#pragma unroll
+        for (int c = 0; c < C; ++c) out[i][c] = zb[c];
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+        store4(Zb_out + n * ps + c * w + mb, out[0][c], out[1][c], out[2][c], out[3][c]);
     }
   }
 }
 
 namespace {
 
-template <class CH, class T, bool BWD>
-hipError_t launch_layer_t(const void *Bsrc, const void *Wop, const float *bias, const float *S_in,
-                          void *Out, float *S_out, int64_t N_pad, int w, hipStream_t st) {
+template <class CH, class T>
+hipError_t launch_fwd_t(const void *A_in, const void *Wop, const float *b, void *A_out, float *S_out,
+                        int64_t N_pad, int w, hipStream_t st) {
   const int WJ = (w % 128 == 0) ? 4 : ((w % 64 == 0) ? 2 : 1);
   const int WN = 4 / WJ;
   dim3 grid((unsigned)(N_pad / (32 * WN)), (unsigned)(w / (32 * WJ)));
-  const T *B = static_cast<const T *>(Bsrc);
+  const T *Ai = static_cast<const T *>(A_in);
   const T *Wp = static_cast<const T *>(Wop);
-  T *O = static_cast<T *>(Out);
-  if (WJ == 4)
-    hipLaunchKernelGGL((k_layer<CH, T, 4, BWD>), grid, dim3(256), 0, st, B, Wp, bias, S_in, O, S_out, w);
-  else if (WJ == 2)
-    hipLaunchKernelGGL((k_layer<CH, T, 2, BWD>), grid, dim3(256), 0, st, B, Wp, bias, S_in, O, S_out, w);
-  else
-    hipLaunchKernelGGL((k_layer<CH, T, 1, BWD>), grid, dim3(256), 0, st, B, Wp, bias, S_in, O, S_out, w);
+  T *Ao = static_cast<T *>(A_out);
+#define PJ_FWD(WJV, SV) \
+  hipLaunchKernelGGL((k_layer_fwd<CH, T, WJV, SV>), grid, dim3(256), 0, st, Ai, Wp, b, Ao, S_out, w)
+  if (S_out) {
+    if (WJ == 4) PJ_FWD(4, true); else if (WJ == 2) PJ_FWD(2, true); else PJ_FWD(1, true);
+  } else {
+    if (WJ == 4) PJ_FWD(4, false); else if (WJ == 2) PJ_FWD(2, false); else PJ_FWD(1, false);
+  }
+#undef PJ_FWD
   return hipGetLastError();
 }
 
-template <class T, bool BWD>
-hipError_t launch_layer_kind(int kind, const void *Bsrc, const void *Wop, const float *bias,
-                             const float *S_in, void *Out, float *S_out, int64_t N_pad, int w,
-                             hipStream_t st) {
-  switch (kind) {
-    case K_BURGERS: return launch_layer_t<ChBurgers, T, BWD>(Bsrc, Wop, bias, S_in, Out, S_out, N_pad, w, st);
-    case K_NS: return launch_layer_t<ChNS, T, BWD>(Bsrc, Wop, bias, S_in, Out, S_out, N_pad, w, st);
-    case K_KS: return launch_layer_t<ChKS, T, BWD>(Bsrc, Wop, bias, S_in, Out, S_out, N_pad, w, st);
-    case K_HEAT: return launch_layer_t<ChHeat, T, BWD>(Bsrc, Wop, bias, S_in, Out, S_out, N_pad, w, st);
-    default: return hipErrorInvalidValue;
-  }
+template <class CH, class T, bool TOP, int DOUT, int ZSRC>
+hipError_t launch_bwd_t(const BwdArgs &a, int64_t N_pad, hipStream_t st) {
+  const int w = a.w;
+  const int WJ = (w % 128 == 0) ? 4 : ((w % 64 == 0) ? 2 : 1);
+  const int WN = 4 / WJ;
+  // two accumulator sets (abar and the recomputed z) at C = 8 would not fit
+  // with two 16-point tiles per wave
+  constexpr int NTN = (ZSRC == Z_FROM_GEMM && CH::C >= 8) ? 1 : 2;
+  dim3 grid((unsigned)(N_pad / (16 * NTN * WN)), (unsigned)(w / (32 * WJ)));
+#define PJ_BWD(WJV) hipLaunchKernelGGL((k_layer_bwd<CH, T, WJV, NTN, TOP, DOUT, ZSRC>), grid, dim3(256), 0, st, a)
+  if (WJ == 4) PJ_BWD(4); else if (WJ == 2) PJ_BWD(2); else PJ_BWD(1);
+#undef PJ_BWD
+  return hipGetLastError();
 }
 
-template <bool BWD>
-hipError_t launch_layer_prec(int kind, int prec, const void *Bsrc, const void *Wop, const float *bias,
-                             const float *S_in, void *Out, float *S_out, int64_t N_pad, int w,
-                             hipStream_t st) {
-  switch (prec) {
-    case P_FP32: return launch_layer_kind<float, BWD>(kind, Bsrc, Wop, bias, S_in, Out, S_out, N_pad, w, st);
-    case P_BF16: return launch_layer_kind<bf16_t, BWD>(kind, Bsrc, Wop, bias, S_in, Out, S_out, N_pad, w, st);
-    case P_FP16: return launch_layer_kind<f16_t, BWD>(kind, Bsrc, Wop, bias, S_in, Out, S_out, N_pad, w, st);
+template <class PDE, class T>
+hipError_t launch_bwd_kind(const BwdArgs &a, bool top, int zsrc, int64_t N_pad, hipStream_t st) {
+  using CH = typename PDE::CH;
+  constexpr int DO = PDE::DOUT;
+  if (top) {
+    if (zsrc == Z_FROM_S) return launch_bwd_t<CH, T, true, DO, Z_FROM_S>(a, N_pad, st);
+    if (zsrc == Z_FROM_GEMM) return launch_bwd_t<CH, T, true, DO, Z_FROM_GEMM>(a, N_pad, st);
+    return launch_bwd_t<CH, T, true, DO, Z_FROM_X>(a, N_pad, st);
+  }
+  if (zsrc == Z_FROM_S) return launch_bwd_t<CH, T, false, DO, Z_FROM_S>(a, N_pad, st);
+  if (zsrc == Z_FROM_GEMM) return launch_bwd_t<CH, T, false, DO, Z_FROM_GEMM>(a, N_pad, st);
+  return launch_bwd_t<CH, T, false, DO, Z_FROM_X>(a, N_pad, st);
+}
+
+template <class F>
+hipError_t dispatch(int kind, int prec, F &&f) {
+  auto by_prec = [&](auto pde) -> hipError_t {
+    switch (prec) {
+      case P_FP32: return f(pde, float{});
+      case P_BF16: return f(pde, bf16_t{});
+      case P_FP16: return f(pde, f16_t{});
+      default: return hipErrorInvalidValue;
+    }
+  };
+  switch (kind) {
+    case K_BURGERS: return by_prec(PdeBurgers{});
+    case K_NS: return by_prec(PdeNS{});
+    case K_KS: return by_prec(PdeKS{});
+    case K_HEAT: return by_prec(PdeHeat{});
     default: return hipErrorInvalidValue;
   }
 }
@@ -164,12 +304,18 @@ hipError_t launch_layer_prec(int kind, int prec, const void *Bsrc, const void *W
 
 hipError_t launch_layer_fwd(int kind, int prec, const void *A_in, const void *Wop, const float *b,
                             void *A_out, float *S_out, int64_t N_pad, int w, hipStream_t st) {
-  return launch_layer_prec<false>(kind, prec, A_in, Wop, b, nullptr, A_out, S_out, N_pad, w, st);
+  return dispatch(kind, prec, [&](auto pde, auto tv) {
+    using CH = typename decltype(pde)::CH;
+    return launch_fwd_t<CH, decltype(tv)>(A_in, Wop, b, A_out, S_out, N_pad, w, st);
+  });
 }
 
-hipError_t launch_layer_bwd(int kind, int prec, const void *Zb_in, const void *WTop,
-                            const float *S_prev, void *Zb_out, int64_t N_pad, int w, hipStream_t st) {
-  return launch_layer_prec<true>(kind, prec, Zb_in, WTop, nullptr, S_prev, Zb_out, nullptr, N_pad, w, st);
+hipError_t launch_layer_bwd(int kind, int prec, const LayerBwd &L, int64_t N_pad, hipStream_t st) {
+  BwdArgs a{L.Zb_in, L.WT, L.ubar, L.WL, L.S_in, L.A_prev, L.Wz, L.bz, L.x, L.W1, L.N, L.Zb_out, L.w};
+  const int zsrc = L.S_in ? Z_FROM_S : (L.A_prev ? Z_FROM_GEMM : Z_FROM_X);
+  return dispatch(kind, prec, [&](auto pde, auto tv) {
+    return launch_bwd_kind<decltype(pde), decltype(tv)>(a, L.top, zsrc, N_pad, st);
+  });
 }
 
 }  // namespace pj

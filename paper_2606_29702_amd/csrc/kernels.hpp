@@ -28,18 +28,35 @@ int op_size(int prec);
 hipError_t launch_cast(int prec, const float *W, int rows, int cols, void *Wop, void *WTop,
                        hipStream_t st);
 
-// Layer 1: z = W1 x + b1 with the seeds d x / d x_i = e_i, then the activation jet.
+// Layer 1: z = W1 x + b1 with the seeds d x / d x_i = e_i, then the activation
+// jet.  S1 may be null (state not stored).
 hipError_t launch_seed_fwd(int kind, int prec, const float *x, int64_t N, int64_t N_pad,
                            const float *W1, const float *b1, int w, void *A1, float *S1,
                            hipStream_t st);
 
-// Hidden layer: Z = W A_in (+ b on the value channel), A_out = jet(Z), S_out saved.
+// Hidden layer: Z = W A_in (+ b on the value channel), A_out = jet(Z); S_out
+// (may be null) receives the FP32 state tanh(z_0), z_1 .. z_{C-1}.
 hipError_t launch_layer_fwd(int kind, int prec, const void *A_in, const void *Wop, const float *b,
                             void *A_out, float *S_out, int64_t N_pad, int w, hipStream_t st);
 
-// Hidden layer adjoint: Abar = W^T Zbar_in, then Zbar_out = jet_adjoint(Abar, S_prev).
-hipError_t launch_layer_bwd(int kind, int prec, const void *Zb_in, const void *WTop,
-                            const float *S_prev, void *Zb_out, int64_t N_pad, int w, hipStream_t st);
+// Hidden layer adjoint, producing Zbar of layer l-1 (see k_layer.hip):
+//   abar = W_l^T Zbar_l (top = false) or W_L^T ubar (top = true, output layer);
+//   z_{l-1} from S_in if given, else recomputed from A_prev with Wz, bz if
+//   A_prev is given, else recomputed from x with W1, bz (first layer);
+//   Zbar_{l-1} = jet_adjoint(abar, z_{l-1}).
+struct LayerBwd {
+  bool top;
+  const void *Zb_in, *WT;       // !top
+  const float *ubar, *WL;       // top
+  const float *S_in;            // saved state, or null
+  const void *A_prev, *Wz;      // recompute from the previous stack
+  const float *bz;              // bias of layer l-1
+  const float *x, *W1;          // recompute of the first layer
+  int64_t N;
+  void *Zb_out;
+  int w;
+};
+hipError_t launch_layer_bwd(int kind, int prec, const LayerBwd &L, int64_t N_pad, hipStream_t st);
 
 // Output layer, residual and per-block loss partial sums (16 points per block).
 hipError_t launch_out_fwd(int kind, int prec, const void *A_H, const float *WL, const float *bL,
@@ -51,12 +68,10 @@ hipError_t launch_out_fwd(int kind, int prec, const void *A_H, const float *WL, 
 hipError_t launch_loss_reduce(const float *part, const double *part64, int n_part, double inv_n,
                               float *loss, double *loss64, hipStream_t st);
 
-// Output-layer adjoint: ubar from rbar (or 2 r / N), then Zbar of the last
-// hidden layer.  ubar is written as [N_pad][d_out][C].
-hipError_t launch_out_bwd(int kind, int prec, const float *u_save, const float *r_save,
-                          const float *r_bar, int64_t N, int64_t N_pad, float rbar_scale,
-                          const float *WL, const float *S_H, int w, Coef k, float *ubar,
-                          void *Zb_H, hipStream_t st);
+// Residual adjoint at the outputs: ubar[n][o][c] = d<rbar, r>/d u_c[o] at
+// point n, rbar = r_bar or rbar_scale * r (zero on padded points).
+hipError_t launch_out_adj(int kind, const float *u_save, const float *r_save, const float *r_bar,
+                          int64_t N, int64_t N_pad, float rbar_scale, Coef k, float *ubar, hipStream_t st);
 
 // Partial sums of the output layer's dW, db over chunks of points:
 // part[chunk][d_out*w + d_out].
@@ -68,8 +83,8 @@ hipError_t launch_dw_seed(int kind, int prec, const void *Zb_1, const float *x, 
                           int64_t N_pad, int w, float *part, int n_chunks, hipStream_t st);
 
 // Split-K partials of a hidden layer's dW = sum_rows Zbar^T A (rows = points x
-// channels) and of db = sum over value rows of Zbar.
-//   part    [splits][w][w]     part_db [splits][w]
+// channels) and of db = sum over value rows of Zbar, packed per split as
+// part[split][w*w + w] (dW row-major, then db).  part_db must equal part + w*w.
 hipError_t launch_dw_hidden(int prec, int C, const void *Zb, const void *A_prev, int64_t N_pad, int w,
                             float *part, float *part_db, int splits, hipStream_t st);
 

@@ -100,6 +100,10 @@ struct pinn_plan_s {
   int64_t max_points = 0, npad_max = 0;
   size_t save_cap = 0;
   int device = 0;
+  // FP32 operands keep the FP32 layer state for the adjoint; 16-bit operands
+  // recompute it in the backward kernels (a second MFMA GEMM is cheaper than
+  // writing and reading the state).
+  bool store_S = false;
 
   // device workspace (indices are 1-based layer numbers; entry 0 unused)
   std::vector<void *> Wop, WTop;  // hidden layers 2..H, operand-type copies
@@ -109,7 +113,7 @@ struct pinn_plan_s {
   float *u_save = nullptr, *r_save = nullptr, *ubar = nullptr;
   float *loss_part = nullptr;
   double *loss_part64 = nullptr;
-  float *part = nullptr, *part_db = nullptr;
+  float *part = nullptr;
   int dw_splits = 1, thin_chunks = 1;
   std::vector<void *> allocs;
   size_t saved_bytes = 0, ws_bytes = 0;
@@ -119,6 +123,13 @@ struct pinn_plan_s {
   int64_t st_N = 0;
   const float *st_x = nullptr;
   std::vector<const float *> st_W, st_b;
+
+  // launch timing of one kernel class (pinn_plan_profile)
+  int prof_class = 0;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  double prof_ms = 0.0;
+  int64_t prof_launches = 0;
 
   bool verify() const { return (flags & PINN_VERIFY_F64) != 0; }
 
@@ -130,7 +141,23 @@ struct pinn_plan_s {
     }
     return e;
   }
+  // Adds the elapsed times of all recorded event pairs and empties the pool.
+  hipError_t harvest() {
+    if (ev_used == 0) return hipSuccess;
+    hipError_t e = hipEventSynchronize(ev_pool[ev_used - 1]);
+    if (e) return e;
+    for (size_t i = 0; i + 1 < ev_used; i += 2) {
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, ev_pool[i], ev_pool[i + 1]);
+      if (e) return e;
+      prof_ms += ms;
+      ++prof_launches;
+    }
+    ev_used = 0;
+    return hipSuccess;
+  }
   ~pinn_plan_s() {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (void *p : allocs) (void)hipFree(p);
   }
 };
@@ -141,9 +168,37 @@ int dw_splits_for(int64_t npad, int C, int w) {
   const int tile = (w % 64 == 0) ? 64 : 32;
   const int64_t tiles = (int64_t)(w / tile) * (w / tile);
   const int64_t rows = npad * C;
-  int64_t s = (2048 + tiles - 1) / tiles;
-  s = std::min<int64_t>(s, std::max<int64_t>(1, rows / 256));
+  // about two workgroups per CU, at least 1024 rows per split
+  int64_t s = (512 + tiles - 1) / tiles;
+  s = std::min<int64_t>(s, std::max<int64_t>(1, rows / 1024));
   return (int)std::max<int64_t>(1, s);
+}
+
+// Runs one launch; when its kernel class is the one being profiled, brackets
+// it with a pair of events on the same stream.
+template <class F>
+hipError_t timed(pinn_plan p, int cls, hipStream_t st, F &&launch) {
+  if (p->prof_class != cls) return launch();
+  if (p->ev_used + 2 > p->ev_pool.size()) {
+    if (p->ev_pool.size() < 2048) {
+      for (int i = 0; i < 64; ++i) {
+        hipEvent_t ev;
+        hipError_t e = hipEventCreate(&ev);
+        if (e) return e;
+        p->ev_pool.push_back(ev);
+      }
+    } else {
+      hipError_t e = p->harvest();
+      if (e) return e;
+    }
+  }
+  hipError_t e = hipEventRecord(p->ev_pool[p->ev_used], st);
+  if (e) return e;
+  e = launch();
+  if (e) return e;
+  e = hipEventRecord(p->ev_pool[p->ev_used + 1], st);
+  p->ev_used += 2;
+  return e;
 }
 
 pinn_status check_call(pinn_plan plan, const pinn_net *net, const float *x, int64_t N) {
@@ -174,14 +229,14 @@ pinn_status run_forward(pinn_plan p, const pinn_net *net, const pinn_pde *pde, c
   const int w = p->w, H = p->H, L = p->L;
   hipError_t e;
   for (int l = 2; l <= H; ++l) {
-    e = pj::launch_cast(p->prec, net->W[l - 1], w, w, p->Wop[l], nullptr, st);
+    e = timed(p, PINN_K_OTHER, st, [&] { return pj::launch_cast(p->prec, net->W[l - 1], w, w, p->Wop[l], nullptr, st); });
     if (e) return hip_fail(e, "cast");
   }
-  e = pj::launch_seed_fwd(p->kind, p->prec, x, N, npad, net->W[0], net->b[0], w, p->A[1], p->S[1], st);
+  e = timed(p, PINN_K_SEED_FWD, st, [&] { return pj::launch_seed_fwd(p->kind, p->prec, x, N, npad, net->W[0], net->b[0], w, p->A[1], p->S[1], st); });
   if (e) return hip_fail(e, "seed layer");
   for (int l = 2; l <= H; ++l) {
-    e = pj::launch_layer_fwd(p->kind, p->prec, p->A[l - 1], p->Wop[l], net->b[l - 1], p->A[l], p->S[l],
-                             npad, w, st);
+    e = timed(p, PINN_K_LAYER_FWD, st, [&] { return pj::launch_layer_fwd(p->kind, p->prec, p->A[l - 1], p->Wop[l], net->b[l - 1], p->A[l], p->S[l],
+                             npad, w, st); });
     if (e) return hip_fail(e, "hidden layer");
   }
   pinn_pde dflt{};
@@ -191,11 +246,11 @@ pinn_status run_forward(pinn_plan p, const pinn_net *net, const pinn_pde *pde, c
     pde = &dflt;
   }
   double *lp64 = p->verify() ? p->loss_part64 : nullptr;
-  e = pj::launch_out_fwd(p->kind, p->prec, p->A[H], net->W[L - 1], net->b[L - 1], x, N, npad, w,
-                         coef_of(pde), jets, r, p->u_save, p->r_save, p->loss_part, lp64, st);
+  e = timed(p, PINN_K_OUT_FWD, st, [&] { return pj::launch_out_fwd(p->kind, p->prec, p->A[H], net->W[L - 1], net->b[L - 1], x, N, npad, w,
+                         coef_of(pde), jets, r, p->u_save, p->r_save, p->loss_part, lp64, st); });
   if (e) return hip_fail(e, "output layer");
   if (loss || loss_f64) {
-    e = pj::launch_loss_reduce(p->loss_part, lp64, (int)(npad / 16), 1.0 / (double)N, loss, loss_f64, st);
+    e = timed(p, PINN_K_OTHER, st, [&] { return pj::launch_loss_reduce(p->loss_part, lp64, (int)(npad / 16), 1.0 / (double)N, loss, loss_f64, st); });
     if (e) return hip_fail(e, "loss reduction");
   }
   return PINN_OK;
@@ -240,7 +295,8 @@ pinn_status pinn_plan_create(const pinn_net *net, const pinn_pde *pde, int64_t m
   const int64_t npad = round_up(max_points, pj::kPointTile);
   const size_t osz = (size_t)pj::op_size(prec);
   const size_t stack_elems = (size_t)npad * ki.C * w;
-  const size_t saved = (size_t)H * stack_elems * (osz + sizeof(float));
+  const bool store_S = prec == PINN_FP32;
+  const size_t saved = (size_t)H * stack_elems * (osz + (store_S ? sizeof(float) : 0));
   if (save_cap_bytes != 0 && save_cap_bytes < saved)
     return fail(PINN_ERR_CAP, "save_cap_bytes = %zu below the %zu bytes of saved layer state", save_cap_bytes,
                 saved);
@@ -258,6 +314,7 @@ pinn_status pinn_plan_create(const pinn_net *net, const pinn_pde *pde, int64_t m
   p->npad_max = npad;
   p->save_cap = save_cap_bytes;
   p->saved_bytes = saved;
+  p->store_S = store_S;
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
     return fail(PINN_ERR_DEVICE, "no HIP device");
@@ -276,7 +333,7 @@ pinn_status pinn_plan_create(const pinn_net *net, const pinn_pde *pde, int64_t m
   }
   for (int l = 1; l <= H; ++l) {
     A(&p->A[l], stack_elems * osz);
-    A(reinterpret_cast<void **>(&p->S[l]), stack_elems * sizeof(float));
+    if (store_S) A(reinterpret_cast<void **>(&p->S[l]), stack_elems * sizeof(float));
   }
   A(&p->Zb[0], stack_elems * osz);
   A(&p->Zb[1], stack_elems * osz);
@@ -286,12 +343,11 @@ pinn_status pinn_plan_create(const pinn_net *net, const pinn_pde *pde, int64_t m
   A(reinterpret_cast<void **>(&p->loss_part), (size_t)(npad / 16) * sizeof(float));
   A(reinterpret_cast<void **>(&p->loss_part64), (size_t)(npad / 16) * sizeof(double));
   p->dw_splits = dw_splits_for(npad, ki.C, w);
-  p->thin_chunks = (int)std::max<int64_t>(1, std::min<int64_t>(256, npad / 64));
+  p->thin_chunks = (int)std::max<int64_t>(1, npad / 64);
   const size_t part_elems =
-      std::max<size_t>((size_t)p->dw_splits * w * w,
+      std::max<size_t>((size_t)p->dw_splits * ((size_t)w * w + w),
                        (size_t)p->thin_chunks * std::max(ki.dout * w + ki.dout, w * ki.din + w));
   A(reinterpret_cast<void **>(&p->part), part_elems * sizeof(float));
-  A(reinterpret_cast<void **>(&p->part_db), (size_t)p->dw_splits * w * sizeof(float));
   if (e != hipSuccess) {
     delete p;
     return fail(e == hipErrorOutOfMemory ? PINN_ERR_NOMEM : PINN_ERR_DEVICE, "workspace allocation: %s",
@@ -313,6 +369,28 @@ pinn_status pinn_plan_memory(pinn_plan plan, size_t *saved_bytes, size_t *worksp
   if (!plan) return fail(PINN_ERR_ARG, "plan is NULL");
   if (saved_bytes) *saved_bytes = plan->saved_bytes;
   if (workspace_bytes) *workspace_bytes = plan->ws_bytes;
+  return PINN_OK;
+}
+
+pinn_status pinn_plan_profile(pinn_plan plan, int32_t kernel_class) {
+  g_err.clear();
+  if (!plan) return fail(PINN_ERR_ARG, "plan is NULL");
+  if (kernel_class < 0 || kernel_class > PINN_K_OTHER)
+    return fail(PINN_ERR_ARG, "unknown kernel class %d", kernel_class);
+  plan->prof_class = kernel_class;
+  plan->ev_used = 0;
+  plan->prof_ms = 0.0;
+  plan->prof_launches = 0;
+  return PINN_OK;
+}
+
+pinn_status pinn_plan_profile_read(pinn_plan plan, double *total_ms, int64_t *launches) {
+  g_err.clear();
+  if (!plan) return fail(PINN_ERR_ARG, "plan is NULL");
+  hipError_t e = plan->harvest();
+  if (e) return hip_fail(e, "event timing");
+  if (total_ms) *total_ms = plan->prof_ms;
+  if (launches) *launches = plan->prof_launches;
   return PINN_OK;
 }
 
@@ -378,37 +456,68 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
   auto f64 = [&](double *const *arr, int l) -> double * { return arr ? arr[l] : nullptr; };
   hipError_t e;
   for (int l = 2; l <= H; ++l) {
-    e = pj::launch_cast(p->prec, net->W[l - 1], w, w, p->Wop[l], p->WTop[l], s);
+    e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_cast(p->prec, net->W[l - 1], w, w, p->Wop[l], p->WTop[l], s); });
     if (e) return hip_fail(e, "cast");
   }
-  // Output layer: ubar, zbar of layer H, then dW_L, db_L.
-  e = pj::launch_out_bwd(p->kind, p->prec, p->u_save, p->r_save, r_bar, N, npad, (float)(2.0 / (double)N),
-                         net->W[L - 1], p->S[H], w, coef_of(pde), p->ubar, p->Zb[H % 2], s);
+  // Source of z for the adjoint of activation layer m: the saved state, or a
+  // recompute from the previous stack (m >= 2) or from x (m = 1).
+  auto zsrc = [&](pj::LayerBwd &B, int m) {
+    if (p->store_S) {
+      B.S_in = p->S[m];
+    } else if (m >= 2) {
+      B.A_prev = p->A[m - 1];
+      B.Wz = p->Wop[m];
+      B.bz = net->b[m - 1];
+    } else {
+      B.x = x;
+      B.W1 = net->W[0];
+      B.bz = net->b[0];
+    }
+  };
+  // Output layer: ubar, then zbar of layer H, then dW_L, db_L.
+  e = timed(p, PINN_K_OUT_BWD, s, [&] { return pj::launch_out_adj(p->kind, p->u_save, p->r_save, r_bar, N, npad, (float)(2.0 / (double)N), coef_of(pde), p->ubar, s); });
   if (e) return hip_fail(e, "output adjoint");
-  e = pj::launch_dw_out(p->kind, p->prec, p->ubar, p->A[H], npad, w, p->part, p->thin_chunks, s);
+  {
+    pj::LayerBwd B{};
+    B.top = true;
+    B.ubar = p->ubar;
+    B.WL = net->W[L - 1];
+    B.N = N;
+    B.w = w;
+    B.Zb_out = p->Zb[H % 2];
+    zsrc(B, H);
+    e = timed(p, PINN_K_OUT_BWD, s, [&] { return pj::launch_layer_bwd(p->kind, p->prec, B, npad, s); });
+    if (e) return hip_fail(e, "last hidden adjoint");
+  }
+  e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_dw_out(p->kind, p->prec, p->ubar, p->A[H], npad, w, p->part, p->thin_chunks, s); });
   if (e) return hip_fail(e, "output-layer gradient");
-  e = pj::launch_reduce_parts2(p->part, p->thin_chunks, (int64_t)ki.dout * w + ki.dout,
+  e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, p->thin_chunks, (int64_t)ki.dout * w + ki.dout,
                                (int64_t)ki.dout * w, ki.dout, dW[L - 1], db[L - 1], f64(dW_f64, L - 1),
-                               f64(db_f64, L - 1), s);
+                               f64(db_f64, L - 1), s); });
   if (e) return hip_fail(e, "reduction");
   // Hidden layers H..2.
   for (int l = H; l >= 2; --l) {
     void *cur = p->Zb[l % 2], *prev = p->Zb[(l - 1) % 2];
-    e = pj::launch_dw_hidden(p->prec, ki.C, cur, p->A[l - 1], npad, w, p->part, p->part_db, p->dw_splits, s);
+    e = timed(p, PINN_K_DW_HIDDEN, s, [&] { return pj::launch_dw_hidden(p->prec, ki.C, cur, p->A[l - 1], npad, w, p->part, p->part + (size_t)w * w, p->dw_splits, s); });
     if (e) return hip_fail(e, "hidden-layer gradient");
-    e = pj::launch_reduce_parts(p->part, p->dw_splits, (int64_t)w * w, (int64_t)w * w, dW[l - 1],
-                                f64(dW_f64, l - 1), s);
+    e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, p->dw_splits, (int64_t)w * w + w, (int64_t)w * w, w, dW[l - 1], db[l - 1], f64(dW_f64, l - 1), f64(db_f64, l - 1), s); });
     if (e) return hip_fail(e, "reduction");
-    e = pj::launch_reduce_parts(p->part_db, p->dw_splits, w, w, db[l - 1], f64(db_f64, l - 1), s);
-    if (e) return hip_fail(e, "reduction");
-    e = pj::launch_layer_bwd(p->kind, p->prec, cur, p->WTop[l], p->S[l - 1], prev, npad, w, s);
+    pj::LayerBwd B{};
+    B.top = false;
+    B.Zb_in = cur;
+    B.WT = p->WTop[l];
+    B.N = N;
+    B.w = w;
+    B.Zb_out = prev;
+    zsrc(B, l - 1);
+    e = timed(p, PINN_K_LAYER_BWD, s, [&] { return pj::launch_layer_bwd(p->kind, p->prec, B, npad, s); });
     if (e) return hip_fail(e, "hidden adjoint");
   }
   // First layer.
-  e = pj::launch_dw_seed(p->kind, p->prec, p->Zb[1], x, N, npad, w, p->part, p->thin_chunks, s);
+  e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_dw_seed(p->kind, p->prec, p->Zb[1], x, N, npad, w, p->part, p->thin_chunks, s); });
   if (e) return hip_fail(e, "first-layer gradient");
-  e = pj::launch_reduce_parts2(p->part, p->thin_chunks, (int64_t)w * ki.din + w, (int64_t)w * ki.din, w,
-                               dW[0], db[0], f64(dW_f64, 0), f64(db_f64, 0), s);
+  e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, p->thin_chunks, (int64_t)w * ki.din + w, (int64_t)w * ki.din, w,
+                               dW[0], db[0], f64(dW_f64, 0), f64(db_f64, 0), s); });
   if (e) return hip_fail(e, "reduction");
   return PINN_OK;
 }

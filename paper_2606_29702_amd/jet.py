@@ -94,6 +94,17 @@ class PinnPlan:
         check(lib.pinn_plan_memory(self.handle, ctypes.byref(s), ctypes.byref(w)))
         return s.value, w.value
 
+    def profile(self, kernel_class: str) -> None:
+        """Start timing launches of one kernel class ('off' to stop)."""
+        cls = 0 if kernel_class == "off" else _lib.KERNEL_CLASSES[kernel_class]
+        check(lib.pinn_plan_profile(self.handle, cls))
+
+    def profile_read(self) -> Tuple[float, int]:
+        """(summed kernel milliseconds, launches) since profile(); waits for the events."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        check(lib.pinn_plan_profile_read(self.handle, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
     # ---------------------------------------------------------------- calls
     def forward(self, params, x: torch.Tensor) -> torch.Tensor:
         """Jets (d_out, C, N) at the points x (N, d_in)."""
