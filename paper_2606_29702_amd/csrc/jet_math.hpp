@@ -53,29 +53,54 @@ struct ChHeat {
 };
 
 // tanh and its derivatives as polynomials in s = tanh(z), from ds/dz = 1 - s^2.
-// 1 - s^2 is formed as (1 - s)(1 + s) to keep its relative accuracy when |s|
-// approaches 1 (saturated neurons).
 struct TanhDerivs {
   float s, s1, s2, s3, s4, s5;
 };
 
+// s = tanh(z) and s1 = 1 - s^2.
+//  FAST (16-bit operand paths): from the identity tanh z = 1 - 2 / (e + 1),
+//    e = exp(2z), with the hardware base-2 exponential and reciprocal; then
+//    1 - s = 2 / (e + 1) and 1 + s = 2e / (e + 1), so 1 - s^2 = 4 e / (e + 1)^2
+//    carries no cancellation for saturated neurons.  Absolute error a few
+//    1e-7, far below the BF16/FP16 operand rounding.
+//  otherwise (FP32 path): the device library tanhf, and (1 - s)(1 + s).
+struct TanhS {
+  float s, s1;
+};
+template <bool FAST>
+__device__ __forceinline__ TanhS tanh_eval(float z) {
+  TanhS t;
+  if constexpr (FAST) {
+    const float e = __builtin_amdgcn_exp2f(z * 2.8853900817779268f);  // exp(2z) = 2^(2 z log2 e)
+    const float q = __builtin_amdgcn_rcpf(e + 1.f);
+    t.s = 1.f - 2.f * q;
+    t.s1 = e < 3.0e38f ? 4.f * (e * q) * q : 0.f;
+  } else {
+    t.s = tanhf(z);
+    t.s1 = (1.f - t.s) * (1.f + t.s);
+  }
+  return t;
+}
+
+// Higher derivatives from s and s1 = 1 - s^2.
 template <int MAXD>
-__device__ __forceinline__ TanhDerivs tanh_derivs_from_s(float s) {
+__device__ __forceinline__ TanhDerivs tanh_derivs(float s, float s1) {
   TanhDerivs t;
   const float ss = s * s;
   t.s = s;
-  t.s1 = (1.f - s) * (1.f + s);
-  t.s2 = -2.f * s * t.s1;
-  t.s3 = MAXD >= 3 ? t.s1 * (6.f * ss - 2.f) : 0.f;
-  t.s4 = MAXD >= 4 ? s * t.s1 * (16.f - 24.f * ss) : 0.f;
-  t.s5 = MAXD >= 5 ? t.s1 * (16.f + ss * (120.f * ss - 120.f)) : 0.f;
+  t.s1 = s1;
+  t.s2 = -2.f * s * s1;
+  t.s3 = MAXD >= 3 ? s1 * (6.f * ss - 2.f) : 0.f;
+  t.s4 = MAXD >= 4 ? s * s1 * (16.f - 24.f * ss) : 0.f;
+  t.s5 = MAXD >= 5 ? s1 * (16.f + ss * (120.f * ss - 120.f)) : 0.f;
   return t;
 }
 
 // Activation jet: z (pre-activation channels, bias already in z[0]) -> a.
-template <class CH>
+template <class CH, bool FAST = false>
 __device__ __forceinline__ void jet_forward(const float (&z)[CH::C], float (&a)[CH::C], float &s_out) {
-  const TanhDerivs t = tanh_derivs_from_s<CH::MAXK>(tanhf(z[0]));
+  const TanhS ts = tanh_eval<FAST>(z[0]);
+  const TanhDerivs t = tanh_derivs<CH::MAXK>(ts.s, ts.s1);
   s_out = t.s;
   a[0] = t.s;
 #pragma unroll
@@ -100,14 +125,14 @@ __device__ __forceinline__ void jet_forward(const float (&z)[CH::C], float (&a)[
 }
 
 // Adjoint of jet_forward.  Inputs: the cotangent ab of the activation jet,
-// s = tanh(z_0) and the derivative channels zs[c] = z_c (c >= 1) saved by the
-// forward pass.  Output: zb, the cotangent of the pre-activation channels.
+// s = tanh(z_0), s1 = 1 - s^2 and the derivative channels zs[c] = z_c (c >= 1)
+// of the forward pass.  Output: zb, the cotangent of the pre-activation channels.
 // Each a_k of a chain depends on z_1..z_k directly and on z_0 through the
 // tanh derivatives (d s_j / d z_0 = s_{j+1}).
 template <class CH>
-__device__ __forceinline__ void jet_adjoint(const float (&ab)[CH::C], float s, const float (&zs)[CH::C],
+__device__ __forceinline__ void jet_adjoint(const float (&ab)[CH::C], float s, float s1, const float (&zs)[CH::C],
                                             float (&zb)[CH::C]) {
-  const TanhDerivs t = tanh_derivs_from_s<CH::MAXK + 1>(s);
+  const TanhDerivs t = tanh_derivs<CH::MAXK + 1>(s, s1);
   float zb0 = t.s1 * ab[0];
 #pragma unroll
   for (int d = 0; d < CH::NDIR; ++d) {

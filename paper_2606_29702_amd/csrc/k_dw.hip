@@ -5,19 +5,25 @@
 // is deterministic.  db = sum over the value rows of zbar.
 //
 // The stacks are stored [rows][w] with the neuron index contiguous, so the
-// contraction index is strided in memory.  A workgroup stages 32 rows x 64
-// columns of each operand through LDS and every lane then gathers its 8
-// contraction elements down a column of the staged tile.
+// contraction index is strided in memory.  A workgroup stages 32 rows x TILE
+// columns of each operand through LDS (double-buffered: the next chunk's
+// global loads are in flight while the current chunk is multiplied) and every
+// lane gathers its 8 contraction elements down a column of the staged tile.
 #include "dev_common.hpp"
 #include "kernels.hpp"
 
 namespace pj {
 
-template <class T>
-struct LdsPitch {
-  // row pitch in elements: 8-byte aligned rows, padded to spread the column
-  // gathers of the four lane groups over different banks
-  static constexpr int value = 64 + 8 / (int)sizeof(T) * 2;
+template <class T, int TILE>
+struct DwLayout {
+  // Row pitch in elements: rows stay 8-byte aligned and rows 8 apart fall
+  // 16 banks apart, so the four lane groups of a column gather do not collide.
+  static constexpr int pitch = TILE + 8 / (int)sizeof(T);
+  static constexpr int tile_elems = 32 * pitch;
+  static constexpr int per_row = TILE / 8;              // 8-element copies per row
+  static constexpr int copies = 32 * per_row;           // per operand per chunk
+  static constexpr int per_thread = (copies + 255) / 256;
+  static constexpr int words = (int)sizeof(T);          // 8-byte words per copy
 };
 
 template <class T>
@@ -48,20 +54,6 @@ __device__ __forceinline__ Mma<float>::frag gather_col<float>(const float *p, in
   return f;
 }
 
-// Copy 8 consecutive elements (16 B for 16-bit types, 32 B for FP32) from
-// global memory into an 8-byte aligned LDS row segment.
-template <class T>
-__device__ __forceinline__ void copy8(T *dst, const T *src) {
-  constexpr int n64 = (int)sizeof(T);  // number of 8-byte words in 8 elements
-  const uint2 *s = reinterpret_cast<const uint2 *>(src);
-  uint2 *d = reinterpret_cast<uint2 *>(dst);
-  uint2 tmp[n64];
-#pragma unroll
-  for (int i = 0; i < n64; ++i) tmp[i] = s[i];
-#pragma unroll
-  for (int i = 0; i < n64; ++i) d[i] = tmp[i];
-}
-
 template <class T, int TILE>
 __global__ __launch_bounds__(256) void k_dw_hidden(const T *__restrict__ Zb, const T *__restrict__ A,
                                                    int64_t rows_total, int64_t rows_per_split, int w,
@@ -70,11 +62,11 @@ __global__ __launch_bounds__(256) void k_dw_hidden(const T *__restrict__ Zb, con
   // Workgroup tile: TILE x TILE of dW; wave (wj, wk) owns a (TILE/2)^2 quarter,
   // i.e. NT x NT MFMA 16x16 tiles.
   using M = Mma<T>;
-  constexpr int P = LdsPitch<T>::value;
+  using LY = DwLayout<T, TILE>;
+  constexpr int P = LY::pitch;
   constexpr int NT = TILE / 32;
   constexpr int H = TILE / 2;
-  __shared__ __align__(16) T Zs[32 * P];
-  __shared__ __align__(16) T As[32 * P];
+  __shared__ __align__(16) T lds[2][2][LY::tile_elems];  // [buffer][Zbar, A][rows x pitch]
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wj = wave & 1, wk = wave >> 1;
@@ -91,16 +83,50 @@ __global__ __launch_bounds__(256) void k_dw_hidden(const T *__restrict__ Zb, con
     for (int b = 0; b < NT; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
   float db = 0.f;
 
-  // loader: 32 rows x TILE columns, 8 elements per thread
-  constexpr int per_row = TILE / 8;
-  const bool loader = t < 32 * per_row;
-  const int lrow = t / per_row, lcol = (t % per_row) * 8;
-  for (int64_t r0 = rb; r0 < re; r0 += 32) {
-    if (loader) {
-      copy8(Zs + lrow * P + lcol, Zb + (r0 + lrow) * w + j0 + lcol);
-      copy8(As + lrow * P + lcol, A + (r0 + lrow) * w + k0 + lcol);
+  uint2 stage[2][LY::per_thread][LY::words];
+  auto fetch = [&](int64_t r0) {
+#pragma unroll
+    for (int u = 0; u < LY::per_thread; ++u) {
+      const int q = t + 256 * u;
+      if (q < LY::copies) {
+        const int row = q / LY::per_row, col = (q % LY::per_row) * 8;
+        const uint2 *sz = reinterpret_cast<const uint2 *>(Zb + (r0 + row) * w + j0 + col);
+        const uint2 *sa = reinterpret_cast<const uint2 *>(A + (r0 + row) * w + k0 + col);
+#pragma unroll
+        for (int v = 0; v < LY::words; ++v) {
+          stage[0][u][v] = sz[v];
+          stage[1][u][v] = sa[v];
+        }
+      }
     }
-    __syncthreads();
+  };
+  auto commit = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < LY::per_thread; ++u) {
+      const int q = t + 256 * u;
+      if (q < LY::copies) {
+        const int row = q / LY::per_row, col = (q % LY::per_row) * 8;
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          uint2 *d = reinterpret_cast<uint2 *>(&lds[buf][m][row * P + col]);
+#pragma unroll
+          for (int v = 0; v < LY::words; ++v) d[v] = stage[m][u][v];
+        }
+      }
+    }
+  };
+
+  if (rb < re) {
+    fetch(rb);
+    commit(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int64_t r0 = rb; r0 < re; r0 += 32) {
+    const bool more = r0 + 32 < re;
+    if (more) fetch(r0 + 32);
+    const T *Zs = lds[buf][0];
+    const T *As = lds[buf][1];
     if (do_db && t < TILE) {
       // rows r with r % C == 0 are value rows
       const int first = (int)((C - (r0 % C)) % C);
@@ -115,7 +141,9 @@ __global__ __launch_bounds__(256) void k_dw_hidden(const T *__restrict__ Zb, con
     for (int jt = 0; jt < NT; ++jt)
 #pragma unroll
       for (int kt = 0; kt < NT; ++kt) M::mma(acc[jt][kt], fa[jt], fb[kt]);
+    if (more) commit(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
 
   float *pp = part + (int64_t)blockIdx.z * ((int64_t)w * w + w);
@@ -132,17 +160,20 @@ __global__ __launch_bounds__(256) void k_dw_hidden(const T *__restrict__ Zb, con
   if (do_db && t < TILE) part_db[(int64_t)blockIdx.z * ((int64_t)w * w + w) + j0 + t] = db;
 }
 
+int dw_tile(int w) { return (w % 128 == 0) ? 128 : ((w % 64 == 0) ? 64 : 32); }
+
 namespace {
 template <class T>
 void launch_dw_t(const T *Zb, const T *A, int64_t rows, int64_t rps, int w, int C, float *part,
                  float *part_db, int splits, hipStream_t st) {
-  if (w % 64 == 0) {
-    dim3 grid((unsigned)(w / 64), (unsigned)(w / 64), (unsigned)splits);
+  const int tile = dw_tile(w);
+  dim3 grid((unsigned)(w / tile), (unsigned)(w / tile), (unsigned)splits);
+  if (tile == 128)
+    hipLaunchKernelGGL((k_dw_hidden<T, 128>), grid, dim3(256), 0, st, Zb, A, rows, rps, w, C, part, part_db);
+  else if (tile == 64)
     hipLaunchKernelGGL((k_dw_hidden<T, 64>), grid, dim3(256), 0, st, Zb, A, rows, rps, w, C, part, part_db);
-  } else {
-    dim3 grid((unsigned)(w / 32), (unsigned)(w / 32), (unsigned)splits);
+  else
     hipLaunchKernelGGL((k_dw_hidden<T, 32>), grid, dim3(256), 0, st, Zb, A, rows, rps, w, C, part, part_db);
-  }
 }
 }  // namespace
 

@@ -41,6 +41,30 @@ hipError_t launch_cast(int prec, const float *W, int rows, int cols, void *Wop, 
   return hipGetLastError();
 }
 
+// All hidden w x w weights in one launch: blockIdx.y selects the layer.
+template <class T>
+__global__ __launch_bounds__(256) void k_cast_all(CastPack pk, int w) {
+  const int l = blockIdx.y;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)w * w) return;
+  const int i = (int)(idx / w), j = (int)(idx % w);
+  const float v = pk.W[l][idx];
+  static_cast<T *>(pk.Wop[l])[idx] = static_cast<T>(v);
+  if (pk.WTop[l]) static_cast<T *>(pk.WTop[l])[(int64_t)j * w + i] = static_cast<T>(v);
+}
+
+hipError_t launch_cast_all(int prec, const CastPack &pk, int n, int w, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  dim3 grid((unsigned)(((int64_t)w * w + 255) / 256), (unsigned)n);
+  switch (prec) {
+    case P_FP32: hipLaunchKernelGGL(k_cast_all<float>, grid, dim3(256), 0, st, pk, w); break;
+    case P_BF16: hipLaunchKernelGGL(k_cast_all<bf16_t>, grid, dim3(256), 0, st, pk, w); break;
+    case P_FP16: hipLaunchKernelGGL(k_cast_all<f16_t>, grid, dim3(256), 0, st, pk, w); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------- seed layer
 // Layer 1 takes the raw coordinates: its value pre-activation is W1 x + b1,
 // its first-order derivative along input i is the column W1[:, i] (the seed
@@ -65,7 +89,7 @@ __global__ __launch_bounds__(256) void k_seed_fwd(const float *__restrict__ x, i
 #pragma unroll
   for (int d = 0; d < CH::NDIR; ++d) z[CH::at(d, 1)] = W1[j * D + CH::in(d)];
   float a[C], s;
-  jet_forward<CH>(z, a, s);
+  jet_forward<CH, sizeof(T) == 2>(z, a, s);
   const int64_t base = n * C * w + j;
 #pragma unroll
   for (int c = 0; c < C; ++c) {

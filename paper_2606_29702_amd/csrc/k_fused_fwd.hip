@@ -1,0 +1,293 @@
+// Whole-network forward pass for one block of P collocation points per
+// workgroup: seed layer, every hidden layer (stacked-channel GEMM on MFMA with
+// the activation jet in its epilogue), linear output layer, residual and the
+// block's loss partial sum, in one launch.
+//
+// The block's stack [P][C][w] lives in LDS for the whole pass (one row of
+// C*w + 8 elements per point; the 8-element pad puts consecutive points on
+// different LDS banks for the 16-byte operand reads).  Layer l reads its
+// weights from global memory (L2-resident, shared by all workgroups), the
+// stack from LDS, and writes the new stack back into the same LDS buffer
+// after a barrier.  Global memory sees only x, the stacks saved for the
+// backward pass (written once, coalesced), the optional FP32 states, and the
+// per-point outputs.
+//
+// Wave layout: the P/16 x w/16 MFMA output tiles of a layer are split over NW
+// waves, TPW consecutive neuron tiles of one 16-point tile per wave, so that
+// every B operand read from LDS feeds TPW MFMAs.
+#include "dev_common.hpp"
+#include "kernels.hpp"
+
+namespace pj {
+
+template <class PDE, class T, int NW, int TPW, int P>
+__global__ __launch_bounds__(NW * 64) void k_fwd_fused(FusedFwdArgs a) {
+  using CH = typename PDE::CH;
+  using M = Mma<T>;
+  constexpr int C = CH::C, D = CH::DIN, DOUT = PDE::DOUT, NRES = PDE::NRES;
+  constexpr int NT = NW * 64;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *stk = reinterpret_cast<T *>(smem_raw);
+  __shared__ float red32[P];
+  __shared__ double red64[P];
+
+  const int w = a.w;
+  const int pitch = C * w + 8;  // elements per point row in LDS
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int64_t nb = (int64_t)blockIdx.x * P;
+  const int64_t gps = (int64_t)C * w;  // elements per point in a global stack
+
+  // ---- layer 1: z = W1 x + b1, d z / d x_i = W1[:, i], then the jet
+  for (int idx = tid; idx < P * w; idx += NT) {
+    const int p = idx / w, j = idx % w;
+    const int64_t n = nb + p;
+    float z[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) z[c] = 0.f;
+    float z0 = a.b1[j];
+#pragma unroll
+    for (int i = 0; i < D; ++i) z0 += a.W1[j * D + i] * (n < a.N ? a.x[n * D + i] : 0.f);
+    z[0] = z0;
+#pragma unroll
+    for (int d = 0; d < CH::NDIR; ++d) z[CH::at(d, 1)] = a.W1[j * D + CH::in(d)];
+    float act[C], s;
+    jet_forward<CH, sizeof(T) == 2>(z, act, s);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      stk[p * pitch + c * w + j] = static_cast<T>(act[c]);
+      if (a.A[1]) static_cast<T *>(a.A[1])[(n * C + c) * w + j] = static_cast<T>(act[c]);
+      if (a.S[1]) a.S[1][(n * C + c) * w + j] = c == 0 ? s : z[c];
+    }
+  }
+  __syncthreads();
+
+  // ---- hidden layers 2..H
+  const int NJ = w / 16;
+  const int tile0 = wave * TPW;          // first (point tile, neuron tile) of this wave
+  const int nt = tile0 / NJ;             // its 16-point tile
+  const int jt0 = tile0 % NJ;            // first of its TPW neuron tiles
+  for (int l = 2; l <= a.H; ++l) {
+    const T *Wl = static_cast<const T *>(a.Wop[l]);
+    f32x4 acc[TPW][C];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t)
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const T *wrow = Wl + (int64_t)(jt0 * 16 + r) * w + 8 * g;
+    const T *brow = stk + (nt * 16 + r) * pitch + 8 * g;
+    typename M::frag fa[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) fa[t] = M::load(wrow + (int64_t)t * 16 * w);
+    for (int k = 0; k < w; k += 32) {
+      typename M::frag fb[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) fb[c] = M::load(brow + c * w + k);
+      typename M::frag fn[TPW];
+      const int kn = k + 32 < w ? k + 32 : k;  // prefetch the next weight fragments
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) fn[t] = M::load(wrow + (int64_t)t * 16 * w + kn);
+#pragma unroll
+      for (int t = 0; t < TPW; ++t)
+#pragma unroll
+        for (int c = 0; c < C; ++c) M::mma(acc[t][c], fa[t], fb[c]);
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) fa[t] = fn[t];
+    }
+    __syncthreads();  // every wave has finished reading layer l-1's stack
+
+    const float *bl = a.b[l];
+    float *Sl = a.S[l];
+    const int p = nt * 16 + r;
+    const int64_t n = nb + p;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int mb = (jt0 + t) * 16 + 4 * g;
+      float out[4][C], sv[4][C];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float z[C], act[C], s;
+#pragma unroll
+        for (int c = 0; c < C; ++c) z[c] = acc[t][c][i];
+        z[0] += bl[mb + i];
+        jet_forward<CH, sizeof(T) == 2>(z, act, s);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          out[i][c] = act[c];
+          sv[i][c] = c == 0 ? s : z[c];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        store4(stk + p * pitch + c * w + mb, out[0][c], out[1][c], out[2][c], out[3][c]);
+        if (Sl) store4(Sl + n * gps + c * w + mb, sv[0][c], sv[1][c], sv[2][c], sv[3][c]);
+      }
+    }
+    __syncthreads();  // layer l's stack complete in LDS
+
+    if (a.A[l]) {
+      // coalesced copy of the block's stack to global memory, 8 elements per thread
+      T *Ag = static_cast<T *>(a.A[l]) + nb * gps;
+      const int per_pt = C * w / 8;
+      for (int q = tid; q < P * per_pt; q += NT) {
+        const int pp = q / per_pt, off = (q % per_pt) * 8;
+        const uint4 *src = reinterpret_cast<const uint4 *>(stk + pp * pitch + off);
+        uint4 *dst = reinterpret_cast<uint4 *>(Ag + pp * gps + off);
+        if constexpr (sizeof(T) == 2) {
+          *dst = *src;
+        } else {
+          dst[0] = src[0];
+          dst[1] = src[1];
+        }
+      }
+    }
+  }
+
+  // ---- output layer, residual, loss partial: TPP threads per point
+  constexpr int TPP = NT / P;
+  {
+    const int p = tid / TPP, q = tid % TPP;
+    const int64_t n = nb + p;
+    float u[DOUT][C];
+#pragma unroll
+    for (int o = 0; o < DOUT; ++o)
+#pragma unroll
+      for (int c = 0; c < C; ++c) u[o][c] = 0.f;
+    for (int k = q; k < w; k += TPP) {
+      float wv[DOUT];
+#pragma unroll
+      for (int o = 0; o < DOUT; ++o) wv[o] = a.WL[o * w + k];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const float av = to_f32(stk[p * pitch + c * w + k]);
+#pragma unroll
+        for (int o = 0; o < DOUT; ++o) u[o][c] += wv[o] * av;
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < DOUT; ++o) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) u[o][c] = group_sum<TPP>(u[o][c]);
+      u[o][0] += a.bL[o];
+    }
+    const bool valid = n < a.N;
+    float xin[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) xin[i] = valid ? a.x[n * D + i] : 0.f;
+    float rr[NRES];
+    PDE::residual(u, xin, a.k, rr);
+    if (q == 0) {
+      float l32 = 0.f;
+      double l64 = 0.0;
+      if (valid) {
+#pragma unroll
+        for (int e = 0; e < NRES; ++e) {
+          l32 += rr[e] * rr[e];
+          if (a.loss_part64) l64 += (double)rr[e] * (double)rr[e];
+        }
+      }
+      red32[p] = l32;
+      red64[p] = l64;
+      if (a.u_save)
+#pragma unroll
+        for (int o = 0; o < DOUT; ++o)
+#pragma unroll
+          for (int c = 0; c < C; ++c) a.u_save[(n * DOUT + o) * C + c] = u[o][c];
+      if (a.r_save)
+#pragma unroll
+        for (int e = 0; e < NRES; ++e) a.r_save[e * a.N_pad + n] = valid ? rr[e] : 0.f;
+      if (valid) {
+        if (a.r)
+#pragma unroll
+          for (int e = 0; e < NRES; ++e) a.r[e * a.N + n] = rr[e];
+        if (a.jets)
+#pragma unroll
+          for (int o = 0; o < DOUT; ++o)
+#pragma unroll
+            for (int c = 0; c < C; ++c) a.jets[(int64_t)(o * C + c) * a.N + n] = u[o][c];
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0 && a.loss_part) {
+    float s = 0.f;
+    double sd = 0.0;
+    for (int p = 0; p < P; ++p) {
+      s += red32[p];
+      sd += red64[p];
+    }
+    a.loss_part[blockIdx.x] = s;
+    if (a.loss_part64) a.loss_part64[blockIdx.x] = sd;
+  }
+}
+
+namespace {
+
+// LDS bytes of one block's stack.
+size_t stack_lds(int P, int C, int w, int osz) { return (size_t)P * (C * w + 8) * osz; }
+
+template <class PDE, class T>
+hipError_t launch_fused_t(const FusedFwdArgs &a, int P, hipStream_t st) {
+  constexpr int C = PDE::CH::C;
+  const int w = a.w;
+  const size_t lds = stack_lds(P, C, w, sizeof(T));
+  const unsigned grid = (unsigned)(a.N_pad / P);
+  // tiles per layer = (P/16) * (w/16); 4 per wave where possible
+  const int tiles = (P / 16) * (w / 16);
+#define PJ_FUSED(NWV, TPWV, PV)                                                                       \
+  do {                                                                                                \
+    auto kfn = k_fwd_fused<PDE, T, NWV, TPWV, PV>;                                                    \
+    hipError_t e_ = hipFuncSetAttribute((const void *)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                        (int)lds);                                                    \
+    if (e_ != hipSuccess) return e_;                                                                  \
+    hipLaunchKernelGGL(kfn, dim3(grid), dim3(NWV * 64), lds, st, a);                                  \
+  } while (0)
+  if (P == 32) {
+    if (tiles == 4) PJ_FUSED(4, 1, 32);          // w = 32
+    else if (tiles == 8) PJ_FUSED(4, 2, 32);     // w = 64
+    else if (tiles == 16) PJ_FUSED(4, 4, 32);    // w = 128
+    else if (tiles == 32) PJ_FUSED(8, 4, 32);    // w = 256
+    else return hipErrorInvalidValue;
+  } else {
+    if (tiles == 16) PJ_FUSED(4, 4, 16);         // w = 256
+    else if (tiles == 32) PJ_FUSED(8, 4, 16);    // w = 512
+    else if (tiles == 8) PJ_FUSED(4, 2, 16);     // w = 128
+    else return hipErrorInvalidValue;
+  }
+#undef PJ_FUSED
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int fused_fwd_points(int C, int w, int prec) {
+  const int osz = op_size(prec);
+  const size_t cap = 144 * 1024;
+  const int tiles32 = 2 * (w / 16), tiles16 = w / 16;
+  if ((tiles32 == 4 || tiles32 == 8 || tiles32 == 16 || tiles32 == 32) &&
+      stack_lds(32, C, w, osz) <= cap)
+    return 32;
+  if ((tiles16 == 8 || tiles16 == 16 || tiles16 == 32) && stack_lds(16, C, w, osz) <= cap) return 16;
+  return 0;
+}
+
+hipError_t launch_fwd_fused(int kind, int prec, const FusedFwdArgs &a, int P, hipStream_t st) {
+  auto by_prec = [&](auto pde) -> hipError_t {
+    using PDE = decltype(pde);
+    switch (prec) {
+      case P_FP32: return launch_fused_t<PDE, float>(a, P, st);
+      case P_BF16: return launch_fused_t<PDE, bf16_t>(a, P, st);
+      case P_FP16: return launch_fused_t<PDE, f16_t>(a, P, st);
+      default: return hipErrorInvalidValue;
+    }
+  };
+  switch (kind) {
+    case K_BURGERS: return by_prec(PdeBurgers{});
+    case K_NS: return by_prec(PdeNS{});
+    case K_KS: return by_prec(PdeKS{});
+    case K_HEAT: return by_prec(PdeHeat{});
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace pj

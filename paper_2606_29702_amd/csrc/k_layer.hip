@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void k_layer_fwd(const T *__restrict__ A_in, c
 #pragma unroll
         for (int c = 0; c < C; ++c) z[c] = acc[jt][nt][c][i];
         z[0] += bias[mb + i];
-        jet_forward<CH>(z, a, s);
+        jet_forward<CH, sizeof(T) == 2>(z, a, s);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           out[i][c] = a[c];
@@ -159,8 +159,10 @@ __global__ __launch_bounds__(256) void k_layer_bwd(BwdArgs args) {
     for (int nt = 0; nt < NTN; ++nt) {
       const int64_t n = n0 + 16 * nt + r;
       const int mb = m0 + 16 * jt + 4 * g;
-      // z (pre-activation channels of layer l-1) for the 4 neurons of this lane
-      float zz[4][C];
+      // z (pre-activation channels of layer l-1) for the 4 neurons of this lane,
+      // with zz[i][0] replaced by s = tanh(z_0) and s1[i] = 1 - s^2
+      constexpr bool FAST = sizeof(T) == 2;
+      float zz[4][C], s1[4];
       if constexpr (ZSRC == Z_FROM_S) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -168,12 +170,16 @@ __global__ __launch_bounds__(256) void k_layer_bwd(BwdArgs args) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) zz[i][c] = v[i];
         }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s1[i] = (1.f - zz[i][0]) * (1.f + zz[i][0]);
       } else if constexpr (ZSRC == Z_FROM_GEMM) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
 #pragma unroll
           for (int c = 0; c < C; ++c) zz[i][c] = acc_z[jt][nt][c][i];
-          zz[i][0] = tanhf(zz[i][0] + args.bz[mb + i]);
+          const TanhS ts = tanh_eval<FAST>(zz[i][0] + args.bz[mb + i]);
+          zz[i][0] = ts.s;
+          s1[i] = ts.s1;
         }
       } else {
         float xin[D];
@@ -187,7 +193,9 @@ __global__ __launch_bounds__(256) void k_layer_bwd(BwdArgs args) {
           float z0 = args.bz[j];
 #pragma unroll
           for (int q = 0; q < D; ++q) z0 += args.W1[j * D + q] * xin[q];
-          zz[i][0] = tanhf(z0);
+          const TanhS ts = tanh_eval<FAST>(z0);
+          zz[i][0] = ts.s;
+          s1[i] = ts.s1;
 #pragma unroll
           for (int d = 0; d < CH::NDIR; ++d) zz[i][CH::at(d, 1)] = args.W1[j * D + CH::in(d)];
         }
@@ -219,7 +227,7 @@ __global__ __launch_bounds__(256) void k_layer_bwd(BwdArgs args) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         float zb[C];
-        jet_adjoint<CH>(ab[i], zz[i][0], zz[i], zb);
+        jet_adjoint<CH>(ab[i], zz[i][0], s1[i], zz[i], zb);
 #pragma unroll
         for (int c = 0; c < C; ++c) out[i][c] = zb[c];
       }
@@ -227,6 +235,164 @@ __global__ __launch_bounds__(256) void k_layer_bwd(BwdArgs args) {
       for (int c = 0; c < C; ++c)
         store4(Zb_out + n * ps + c * w + mb, out[0][c], out[1][c], out[2][c], out[3][c]);
     }
+  }
+}
+
+// LDS-staged variant of k_layer_bwd for workgroups that cover every neuron
+// of P points: the Zbar tile of layer l and, for the recompute, the stack tile
+// of layer l-2 are copied into LDS with coalesced 16-byte loads (all issued
+// before the first MFMA), then both GEMMs read their B operands from LDS.
+// The tile split over waves is the one of the fused forward pass.
+template <class T>
+__device__ __forceinline__ void stage_tile(T *dst, const T *src, int P, int C, int w, int pitch, int tid,
+                                           int nthreads) {
+  const int per_pt = C * w / 8;
+  for (int q = tid; q < P * per_pt; q += nthreads) {
+    const int pp = q / per_pt, off = (q % per_pt) * 8;
+    const uint4 *s = reinterpret_cast<const uint4 *>(src + (int64_t)pp * C * w + off);
+    uint4 *d = reinterpret_cast<uint4 *>(dst + pp * pitch + off);
+    if constexpr (sizeof(T) == 2) {
+      *d = *s;
+    } else {
+      d[0] = s[0];
+      d[1] = s[1];
+    }
+  }
+}
+
+template <class T, int C, int TPW>
+__device__ __forceinline__ void lds_gemm(f32x4 (&acc)[TPW][C], const T *__restrict__ Wop, const T *stk,
+                                         int pitch, int jt0, int nt, int w, int lane) {
+  using M = Mma<T>;
+  const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int t = 0; t < TPW; ++t)
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const T *wrow = Wop + (int64_t)(jt0 * 16 + r) * w + 8 * g;
+  const T *brow = stk + (nt * 16 + r) * pitch + 8 * g;
+  typename M::frag fa[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) fa[t] = M::load(wrow + (int64_t)t * 16 * w);
+  for (int k = 0; k < w; k += 32) {
+    typename M::frag fb[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) fb[c] = M::load(brow + c * w + k);
+    typename M::frag fn[TPW];
+    const int kn = k + 32 < w ? k + 32 : k;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) fn[t] = M::load(wrow + (int64_t)t * 16 * w + kn);
+#pragma unroll
+    for (int t = 0; t < TPW; ++t)
+#pragma unroll
+      for (int c = 0; c < C; ++c) M::mma(acc[t][c], fa[t], fb[c]);
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) fa[t] = fn[t];
+  }
+}
+
+template <class CH, class T, int NW, int TPW, int P, bool TOP, int DOUT, int ZSRC>
+__global__ __launch_bounds__(NW * 64) void k_layer_bwd_lds(BwdArgs args) {
+  constexpr int C = CH::C, D = CH::DIN;
+  constexpr bool FAST = sizeof(T) == 2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int w = args.w;
+  const int pitch = C * w + 8;
+  T *lds_b = reinterpret_cast<T *>(smem_raw);                         // Zbar_l tile
+  T *lds_a = lds_b + (TOP ? 0 : P * pitch);                           // stack tile of layer l-2
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int64_t nb = (int64_t)blockIdx.x * P;
+  const int64_t ps = (int64_t)C * w;
+  if constexpr (!TOP) stage_tile<T>(lds_b, static_cast<const T *>(args.Zb_in) + nb * ps, P, C, w, pitch, tid, NW * 64);
+  if constexpr (ZSRC == Z_FROM_GEMM)
+    stage_tile<T>(lds_a, static_cast<const T *>(args.A_prev) + nb * ps, P, C, w, pitch, tid, NW * 64);
+  __syncthreads();
+
+  const int NJ = w / 16;
+  const int tile0 = wave * TPW;
+  const int nt = tile0 / NJ, jt0 = tile0 % NJ;
+  f32x4 acc_a[TPW][C];
+  if constexpr (!TOP) lds_gemm<T, C, TPW>(acc_a, static_cast<const T *>(args.WT), lds_b, pitch, jt0, nt, w, lane);
+  f32x4 acc_z[TPW][C];
+  if constexpr (ZSRC == Z_FROM_GEMM)
+    lds_gemm<T, C, TPW>(acc_z, static_cast<const T *>(args.Wz), lds_a, pitch, jt0, nt, w, lane);
+
+  T *Zb_out = static_cast<T *>(args.Zb_out);
+  const int64_t n = nb + nt * 16 + r;
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int mb = (jt0 + t) * 16 + 4 * g;
+    float zz[4][C], s1[4];
+    if constexpr (ZSRC == Z_FROM_S) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const f32x4 v = *reinterpret_cast<const f32x4 *>(args.S_in + n * ps + c * w + mb);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) zz[i][c] = v[i];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) s1[i] = (1.f - zz[i][0]) * (1.f + zz[i][0]);
+    } else if constexpr (ZSRC == Z_FROM_GEMM) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) zz[i][c] = acc_z[t][c][i];
+        const TanhS ts = tanh_eval<FAST>(zz[i][0] + args.bz[mb + i]);
+        zz[i][0] = ts.s;
+        s1[i] = ts.s1;
+      }
+    } else {
+      float xin[D];
+#pragma unroll
+      for (int q = 0; q < D; ++q) xin[q] = n < args.N ? args.x[n * D + q] : 0.f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int j = mb + i;
+#pragma unroll
+        for (int c = 0; c < C; ++c) zz[i][c] = 0.f;
+        float z0 = args.bz[j];
+#pragma unroll
+        for (int q = 0; q < D; ++q) z0 += args.W1[j * D + q] * xin[q];
+        const TanhS ts = tanh_eval<FAST>(z0);
+        zz[i][0] = ts.s;
+        s1[i] = ts.s1;
+#pragma unroll
+        for (int d = 0; d < CH::NDIR; ++d) zz[i][CH::at(d, 1)] = args.W1[j * D + CH::in(d)];
+      }
+    }
+    float ab[4][C];
+    if constexpr (TOP) {
+      float ub[DOUT][C];
+#pragma unroll
+      for (int o = 0; o < DOUT; ++o)
+#pragma unroll
+        for (int c = 0; c < C; ++c) ub[o][c] = args.ubar[(n * DOUT + o) * C + c];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          float sacc = 0.f;
+#pragma unroll
+          for (int o = 0; o < DOUT; ++o) sacc += args.WL[o * w + mb + i] * ub[o][c];
+          ab[i][c] = sacc;
+        }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < C; ++c) ab[i][c] = acc_a[t][c][i];
+    }
+    float out[4][C];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float zb[C];
+      jet_adjoint<CH>(ab[i], zz[i][0], s1[i], zz[i], zb);
+#pragma unroll
+      for (int c = 0; c < C; ++c) out[i][c] = zb[c];
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) store4(Zb_out + n * ps + c * w + mb, out[0][c], out[1][c], out[2][c], out[3][c]);
   }
 }
 
@@ -252,9 +418,48 @@ hipError_t launch_fwd_t(const void *A_in, const void *Wop, const float *b, void 
   return hipGetLastError();
 }
 
+// LDS-staged configuration (points per workgroup, waves, neuron tiles per
+// wave) for the backward layer kernel, or P = 0 when the staged tiles would
+// not fit the LDS and register budget.
+struct BwdLdsCfg {
+  int P, NW, TPW;
+};
+inline BwdLdsCfg bwd_lds_cfg(int C, int w, int osz, bool two_tiles) {
+  const size_t tile = (size_t)16 * (C * w + 8) * osz;
+  const size_t lds = tile * (two_tiles ? 2 : 1);
+  if (lds > 100 * 1024) return {0, 0, 0};
+  switch (w) {
+    case 32: return {16, 2, 1};
+    case 64: return {16, 4, 1};
+    case 128: return {16, 4, 2};
+    case 256: return {16, 8, 2};
+    default: return {0, 0, 0};
+  }
+}
+
 template <class CH, class T, bool TOP, int DOUT, int ZSRC>
 hipError_t launch_bwd_t(const BwdArgs &a, int64_t N_pad, hipStream_t st) {
   const int w = a.w;
+  const BwdLdsCfg cfg = bwd_lds_cfg(CH::C, w, (int)sizeof(T), !TOP && ZSRC == Z_FROM_GEMM);
+  if (cfg.P > 0 && CH::C * w * (int)sizeof(T) % 16 == 0) {
+    const int tiles = (TOP ? 0 : 1) + (ZSRC == Z_FROM_GEMM ? 1 : 0);
+    const size_t lds = (size_t)tiles * cfg.P * (CH::C * w + 8) * sizeof(T);
+    const dim3 grid((unsigned)(N_pad / cfg.P));
+#define PJ_BWDL(NWV, TPWV)                                                                             \
+  do {                                                                                                 \
+    auto kfn = k_layer_bwd_lds<CH, T, NWV, TPWV, 16, TOP, DOUT, ZSRC>;                                 \
+    hipError_t e_ = hipFuncSetAttribute((const void *)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                        (int)(lds > 0 ? lds : 16));                                    \
+    if (e_ != hipSuccess) return e_;                                                                   \
+    hipLaunchKernelGGL(kfn, grid, dim3(NWV * 64), lds, st, a);                                         \
+  } while (0)
+    if (cfg.NW == 2) PJ_BWDL(2, 1);
+    else if (cfg.NW == 4 && cfg.TPW == 1) PJ_BWDL(4, 1);
+    else if (cfg.NW == 4) PJ_BWDL(4, 2);
+    else PJ_BWDL(8, 2);
+#undef PJ_BWDL
+    return hipGetLastError();
+  }
   const int WJ = (w % 128 == 0) ? 4 : ((w % 64 == 0) ? 2 : 1);
   const int WN = 4 / WJ;
   // two accumulator sets (abar and the recomputed z) at C = 8 would not fit

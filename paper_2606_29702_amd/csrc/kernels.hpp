@@ -28,6 +28,14 @@ int op_size(int prec);
 hipError_t launch_cast(int prec, const float *W, int rows, int cols, void *Wop, void *WTop,
                        hipStream_t st);
 
+// Casts of n hidden w x w weights in one launch (WTop entries may be null).
+struct CastPack {
+  const float *W[16];
+  void *Wop[16];
+  void *WTop[16];
+};
+hipError_t launch_cast_all(int prec, const CastPack &pk, int n, int w, hipStream_t st);
+
 // Layer 1: z = W1 x + b1 with the seeds d x / d x_i = e_i, then the activation
 // jet.  S1 may be null (state not stored).
 hipError_t launch_seed_fwd(int kind, int prec, const float *x, int64_t N, int64_t N_pad,
@@ -58,6 +66,30 @@ struct LayerBwd {
 };
 hipError_t launch_layer_bwd(int kind, int prec, const LayerBwd &L, int64_t N_pad, hipStream_t st);
 
+// Whole-network forward pass for blocks of P points (k_fused_fwd.hip): seed
+// layer, hidden layers, output layer, residual and one loss partial per block.
+// Arrays are indexed by the 1-based layer number.  A[l], S[l], u_save,
+// r_save, r, jets, loss_part may be null (not written).
+constexpr int kMaxHidden = 16;
+struct FusedFwdArgs {
+  const float *x;
+  int64_t N, N_pad;
+  int w, H;
+  const float *W1, *b1;                 // layer 1 (fp32)
+  const void *Wop[kMaxHidden + 1];      // layers 2..H, operand type
+  const float *b[kMaxHidden + 1];       // layers 2..H
+  const float *WL, *bL;                 // output layer (fp32)
+  void *A[kMaxHidden + 1];              // saved stacks, layers 1..H
+  float *S[kMaxHidden + 1];             // saved FP32 states, layers 1..H
+  Coef k;
+  float *jets, *r, *u_save, *r_save, *loss_part;
+  double *loss_part64;
+};
+// Points per workgroup for the fused forward pass (32 or 16), or 0 when the
+// block's stack does not fit in LDS (the layer-by-layer kernels are used).
+int fused_fwd_points(int C, int w, int prec);
+hipError_t launch_fwd_fused(int kind, int prec, const FusedFwdArgs &a, int P, hipStream_t st);
+
 // Output layer, residual and per-block loss partial sums (16 points per block).
 hipError_t launch_out_fwd(int kind, int prec, const void *A_H, const float *WL, const float *bL,
                           const float *x, int64_t N, int64_t N_pad, int w, Coef k, float *jets,
@@ -85,6 +117,7 @@ hipError_t launch_dw_seed(int kind, int prec, const void *Zb_1, const float *x, 
 // Split-K partials of a hidden layer's dW = sum_rows Zbar^T A (rows = points x
 // channels) and of db = sum over value rows of Zbar, packed per split as
 // part[split][w*w + w] (dW row-major, then db).  part_db must equal part + w*w.
+int dw_tile(int w);  // dW workgroup tile edge (128, 64 or 32)
 hipError_t launch_dw_hidden(int prec, int C, const void *Zb, const void *A_prev, int64_t N_pad, int w,
                             float *part, float *part_db, int splits, hipStream_t st);
 

@@ -165,7 +165,7 @@ struct pinn_plan_s {
 namespace {
 
 int dw_splits_for(int64_t npad, int C, int w) {
-  const int tile = (w % 64 == 0) ? 64 : 32;
+  const int tile = pj::dw_tile(w);
   const int64_t tiles = (int64_t)(w / tile) * (w / tile);
   const int64_t rows = npad * C;
   // about two workgroups per CU, at least 1024 rows per split
@@ -224,13 +224,61 @@ pj::Coef coef_of(const pinn_pde *pde) {
 // Forward pass through all layers; optionally the residual and the loss.
 pinn_status run_forward(pinn_plan p, const pinn_net *net, const pinn_pde *pde, const float *x,
                         int64_t N, float *jets, float *r, float *loss, double *loss_f64,
-                        hipStream_t st) {
+                        bool save_state, hipStream_t st) {
   const int64_t npad = round_up(N, pj::kPointTile);
   const int w = p->w, H = p->H, L = p->L;
   hipError_t e;
-  for (int l = 2; l <= H; ++l) {
-    e = timed(p, PINN_K_OTHER, st, [&] { return pj::launch_cast(p->prec, net->W[l - 1], w, w, p->Wop[l], nullptr, st); });
+  {
+    pj::CastPack pk{};
+    for (int l = 2; l <= H; ++l) {
+      pk.W[l - 2] = net->W[l - 1];
+      pk.Wop[l - 2] = p->Wop[l];
+    }
+    e = timed(p, PINN_K_OTHER, st, [&] { return pj::launch_cast_all(p->prec, pk, H - 1, w, st); });
     if (e) return hip_fail(e, "cast");
+  }
+  pinn_pde dflt0{};
+  const pinn_pde *pd = pde;
+  if (!pd) {
+    dflt0.kind = p->kind;
+    dflt0.coef[0] = 1.0;
+    pd = &dflt0;
+  }
+  double *lp64 = p->verify() ? p->loss_part64 : nullptr;
+  const int P = pj::fused_fwd_points(p->ki.C, w, p->prec);
+  if (P > 0) {
+    pj::FusedFwdArgs a{};
+    a.x = x;
+    a.N = N;
+    a.N_pad = npad;
+    a.w = w;
+    a.H = H;
+    a.W1 = net->W[0];
+    a.b1 = net->b[0];
+    for (int l = 2; l <= H; ++l) {
+      a.Wop[l] = p->Wop[l];
+      a.b[l] = net->b[l - 1];
+    }
+    a.WL = net->W[L - 1];
+    a.bL = net->b[L - 1];
+    for (int l = 1; l <= H; ++l) {
+      a.A[l] = save_state ? p->A[l] : nullptr;
+      a.S[l] = save_state ? p->S[l] : nullptr;
+    }
+    a.k = coef_of(pd);
+    a.jets = jets;
+    a.r = r;
+    a.u_save = p->u_save;
+    a.r_save = p->r_save;
+    a.loss_part = p->loss_part;
+    a.loss_part64 = lp64;
+    e = timed(p, PINN_K_LAYER_FWD, st, [&] { return pj::launch_fwd_fused(p->kind, p->prec, a, P, st); });
+    if (e) return hip_fail(e, "fused forward");
+    if (loss || loss_f64) {
+      e = timed(p, PINN_K_OTHER, st, [&] { return pj::launch_loss_reduce(p->loss_part, lp64, (int)(npad / P), 1.0 / (double)N, loss, loss_f64, st); });
+      if (e) return hip_fail(e, "loss reduction");
+    }
+    return PINN_OK;
   }
   e = timed(p, PINN_K_SEED_FWD, st, [&] { return pj::launch_seed_fwd(p->kind, p->prec, x, N, npad, net->W[0], net->b[0], w, p->A[1], p->S[1], st); });
   if (e) return hip_fail(e, "seed layer");
@@ -239,15 +287,8 @@ pinn_status run_forward(pinn_plan p, const pinn_net *net, const pinn_pde *pde, c
                              npad, w, st); });
     if (e) return hip_fail(e, "hidden layer");
   }
-  pinn_pde dflt{};
-  if (!pde) {
-    dflt.kind = p->kind;
-    dflt.coef[0] = 1.0;
-    pde = &dflt;
-  }
-  double *lp64 = p->verify() ? p->loss_part64 : nullptr;
   e = timed(p, PINN_K_OUT_FWD, st, [&] { return pj::launch_out_fwd(p->kind, p->prec, p->A[H], net->W[L - 1], net->b[L - 1], x, N, npad, w,
-                         coef_of(pde), jets, r, p->u_save, p->r_save, p->loss_part, lp64, st); });
+                         coef_of(pd), jets, r, p->u_save, p->r_save, p->loss_part, lp64, st); });
   if (e) return hip_fail(e, "output layer");
   if (loss || loss_f64) {
     e = timed(p, PINN_K_OTHER, st, [&] { return pj::launch_loss_reduce(p->loss_part, lp64, (int)(npad / 16), 1.0 / (double)N, loss, loss_f64, st); });
@@ -401,7 +442,7 @@ pinn_status pinn_jet_forward(pinn_plan plan, const pinn_net *net, const float *x
   if (st) return st;
   if (!jets) return fail(PINN_ERR_ARG, "jets is NULL");
   plan->have_state = false;
-  return run_forward(plan, net, nullptr, x, N, jets, nullptr, nullptr, nullptr, (hipStream_t)stream);
+  return run_forward(plan, net, nullptr, x, N, jets, nullptr, nullptr, nullptr, false, (hipStream_t)stream);
 }
 
 pinn_status pinn_jet_residual(pinn_plan plan, const pinn_net *net, const pinn_pde *pde,
@@ -414,7 +455,7 @@ pinn_status pinn_jet_residual(pinn_plan plan, const pinn_net *net, const pinn_pd
   if (st) return st;
   if (loss_f64 && !plan->verify()) return fail(PINN_ERR_ARG, "loss_f64 needs a PINN_VERIFY_F64 plan");
   plan->have_state = false;
-  st = run_forward(plan, net, pde, x, N, jets, r, loss, loss_f64, (hipStream_t)stream);
+  st = run_forward(plan, net, pde, x, N, jets, r, loss, loss_f64, true, (hipStream_t)stream);
   if (st) return st;
   plan->have_state = true;
   plan->st_N = N;
@@ -455,8 +496,14 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
   const KindInfo &ki = p->ki;
   auto f64 = [&](double *const *arr, int l) -> double * { return arr ? arr[l] : nullptr; };
   hipError_t e;
-  for (int l = 2; l <= H; ++l) {
-    e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_cast(p->prec, net->W[l - 1], w, w, p->Wop[l], p->WTop[l], s); });
+  {
+    pj::CastPack pk{};
+    for (int l = 2; l <= H; ++l) {
+      pk.W[l - 2] = net->W[l - 1];
+      pk.Wop[l - 2] = p->Wop[l];
+      pk.WTop[l - 2] = p->WTop[l];
+    }
+    e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_cast_all(p->prec, pk, H - 1, w, s); });
     if (e) return hip_fail(e, "cast");
   }
   // Source of z for the adjoint of activation layer m: the saved state, or a

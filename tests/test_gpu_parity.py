@@ -115,6 +115,21 @@ def test_lowprec_parity(lib, pde, unsat, prec):
     assert cos > 0.99
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("pde", ["ns", "heat"])
+def test_layerwise_forward_path(lib, pde, prec):
+    """w = 96 has no whole-network forward tiling, so the layer-by-layer
+    forward kernels run; they must agree with the oracle too."""
+    dims = [2, 96, 96, 96, 3] if pde == "ns" else [4, 96, 96, 1]
+    prob = pi.make_problem(pde, N=150, seed=12, bias_std=0.3, dims=dims)
+    g = run_gpu(lib, prob, prec)
+    ref = oracle.evaluate(prob.params, prob.x, prob.channels, pde, prob.coef)
+    tol = FP32_TOL if prec == "fp32" else LOWP_TOL[prec]["grad"]
+    assert rel(g["jets"], ref.jets) <= tol
+    assert rel(g["r"], ref.r) <= (FP32_TOL if prec == "fp32" else LOWP_TOL[prec]["r"])
+    assert rel(g["grad"], ref.grad) <= tol
+
+
 @pytest.mark.parametrize("N", [1, 17, 127, 128, 129, 383])
 def test_ragged_sizes(lib, N):
     prob = pi.make_problem("burgers", N=N, seed=3, bias_std=0.3, dims=[2, 32, 32, 1])
