@@ -100,6 +100,7 @@ typedef struct {
 } pinn_pde;
 
 typedef struct pinn_plan_s *pinn_plan;
+typedef struct pinn_batch_s *pinn_batch;
 
 /* Creates a plan for one network shape, PDE kind and maximum point count.
  *   prec            PINN_FP32 / PINN_BF16 / PINN_FP16
@@ -150,6 +151,55 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
                               const float *x, int64_t N, const float *r_bar,
                               float *const *dW, float *const *db,
                               double *const *dW_f64, double *const *db_f64, void *stream);
+
+/* Tunable launch parameters of a plan.  They change reduction order and
+ * workgroup shapes, never the arithmetic: every setting is deterministic and
+ * agrees with the others to rounding.
+ *   dw_splits   number of split-K partials of each hidden-layer weight gradient
+ *               (1 .. twice the plan's default)
+ *   fwd_points  points per workgroup of the whole-network forward kernel
+ *               (0 = the largest tiling whose stack fits in LDS, else 16 or 32) */
+typedef struct {
+  int32_t dw_splits;
+  int32_t fwd_points;
+} pinn_tuning;
+pinn_status pinn_plan_get_tuning(pinn_plan plan, pinn_tuning *tuning);
+pinn_status pinn_plan_set_tuning(pinn_plan plan, const pinn_tuning *tuning);
+
+/* Autotuner: times `reps` residual + backward steps (after one warm-up step)
+ * for each candidate tuning on the caller's data, keeps the fastest and
+ * returns it with its milliseconds per step.  Synchronises the stream and
+ * allocates temporary gradient buffers; invalidates the saved state. */
+pinn_status pinn_plan_autotune(pinn_plan plan, const pinn_net *net, const pinn_pde *pde, const float *x,
+                               int64_t N, int32_t reps, pinn_tuning *best, double *best_ms, void *stream);
+
+/* Ensembles (many independent networks, each with its own shape, PDE
+ * coefficients and point count, stepped together).
+ *   pinn_batch_create   one plan per network (arguments as pinn_plan_create,
+ *                       no save cap); nets[i], pdes[i], max_points[i] host arrays.
+ *   pinn_batch_step     for every network i: residual, loss[i] (device array of
+ *                       n floats) and the loss gradient into dW[i][l], db[i][l]
+ *                       (host arrays of host arrays of device pointers).  The
+ *                       networks run concurrently on a pool of side streams
+ *                       forked from and joined back into `stream`.  With graphs
+ *                       enabled (the default) the first call captures the whole
+ *                       step into a HIP graph and later calls with the same
+ *                       pointers, sizes and coefficients replay it; any change
+ *                       triggers a new capture.
+ *   pinn_batch_configure  side-stream count (1..16) and graph on/off.
+ *   pinn_batch_autotune   times `reps` steps for each side-stream count
+ *                       (1, 2, 4, 8, 16 up to n) and keeps the fastest. */
+pinn_status pinn_batch_create(int32_t n, const pinn_net *nets, const pinn_pde *pdes, const int64_t *max_points,
+                              int32_t prec, uint32_t flags, pinn_batch *out);
+pinn_status pinn_batch_destroy(pinn_batch batch);
+pinn_status pinn_batch_configure(pinn_batch batch, int32_t n_streams, int32_t use_graph);
+pinn_status pinn_batch_step(pinn_batch batch, const pinn_net *nets, const pinn_pde *pdes, const float *const *x,
+                            const int64_t *N, float *loss, float *const *const *dW, float *const *const *db,
+                            void *stream);
+pinn_status pinn_batch_autotune(pinn_batch batch, const pinn_net *nets, const pinn_pde *pdes,
+                                const float *const *x, const int64_t *N, float *loss, float *const *const *dW,
+                                float *const *const *db, int32_t reps, int32_t *best_streams, double *best_ms,
+                                void *stream);
 
 /* Launch timing, a measurement aid for benchmarks.  pinn_plan_profile selects
  * one kernel class (0 = off) and clears the accumulator; from then on every

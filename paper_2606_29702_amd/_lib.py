@@ -26,7 +26,9 @@ PINN_VERIFY_F64 = 1
 # Every symbol the public header declares.
 EXPORTS = ["pinn_plan_create", "pinn_plan_destroy", "pinn_plan_memory", "pinn_jet_forward",
            "pinn_jet_residual", "pinn_jet_backward", "pinn_last_error", "pinn_pde_channels",
-           "pinn_pde_residuals", "pinn_plan_profile", "pinn_plan_profile_read"]
+           "pinn_pde_residuals", "pinn_plan_profile", "pinn_plan_profile_read", "pinn_plan_get_tuning",
+           "pinn_plan_set_tuning", "pinn_plan_autotune", "pinn_batch_create", "pinn_batch_destroy",
+           "pinn_batch_configure", "pinn_batch_step", "pinn_batch_autotune"]
 KERNEL_CLASSES = {"layer_fwd": 1, "layer_bwd": 2, "dw_hidden": 3, "out_fwd": 4, "out_bwd": 5,
                   "seed_fwd": 6, "other": 7}
 
@@ -46,6 +48,10 @@ class Pde(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("coef", ctypes.c_double * 4)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("dw_splits", ctypes.c_int32), ("fwd_points", ctypes.c_int32)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc for gfx950)")
@@ -61,13 +67,27 @@ def _load():
     lib.pinn_jet_backward.argtypes = [vp, NetP, PdeP, vp, i64, vp, pp, pp, pp, pp, vp]
     lib.pinn_plan_profile.argtypes = [vp, i32]
     lib.pinn_plan_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    TuneP = ctypes.POINTER(Tuning)
+    dptr = ctypes.POINTER(ctypes.c_double)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    lib.pinn_plan_get_tuning.argtypes = [vp, TuneP]
+    lib.pinn_plan_set_tuning.argtypes = [vp, TuneP]
+    lib.pinn_plan_autotune.argtypes = [vp, NetP, PdeP, vp, i64, i32, TuneP, dptr, vp]
+    lib.pinn_batch_create.argtypes = [i32, NetP, PdeP, i64p, i32, ctypes.c_uint32, pp]
+    lib.pinn_batch_destroy.argtypes = [vp]
+    lib.pinn_batch_configure.argtypes = [vp, i32, i32]
+    lib.pinn_batch_step.argtypes = [vp, NetP, PdeP, pp, i64p, vp, pp, pp, vp]
+    lib.pinn_batch_autotune.argtypes = [vp, NetP, PdeP, pp, i64p, vp, pp, pp, i32,
+                                        ctypes.POINTER(ctypes.c_int32), dptr, vp]
     lib.pinn_last_error.restype = ctypes.c_char_p
     lib.pinn_last_error.argtypes = []
     lib.pinn_pde_channels.argtypes = [i32]
     lib.pinn_pde_residuals.argtypes = [i32]
     for name in ("pinn_plan_create", "pinn_plan_destroy", "pinn_plan_memory", "pinn_jet_forward",
                  "pinn_jet_residual", "pinn_jet_backward", "pinn_pde_channels", "pinn_pde_residuals",
-                 "pinn_plan_profile", "pinn_plan_profile_read"):
+                 "pinn_plan_profile", "pinn_plan_profile_read", "pinn_plan_get_tuning", "pinn_plan_set_tuning",
+                 "pinn_plan_autotune", "pinn_batch_create", "pinn_batch_destroy", "pinn_batch_configure",
+                 "pinn_batch_step", "pinn_batch_autotune"):
         getattr(lib, name).restype = ctypes.c_int32
     return lib
 

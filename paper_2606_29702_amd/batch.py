@@ -1,0 +1,118 @@
+"""Ensembles of independent partial-jet PINNs stepped together (C ABI
+pinn_batch_*): one plan per network, the networks run concurrently on side
+streams, and the whole step is captured once into a HIP graph and replayed.
+
+Gradient and loss buffers are owned by the batch object and reused across
+steps, so that repeated steps with the same parameter and point tensors
+replay the captured graph.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence, Tuple
+
+import torch
+
+from ._lib import KINDS, PRECISIONS, Net, Pde, check, lib, ptr_array
+from .jet import DEFAULT_COEF, _check_tensor, _stream
+
+
+class PinnBatch:
+    def __init__(self, dims: Sequence[Sequence[int]], pde: str, coefs: Sequence[Sequence[float]],
+                 max_points: Sequence[int], precision: str = "bf16", device: str = "cuda"):
+        self.n = len(dims)
+        assert len(coefs) == self.n and len(max_points) == self.n
+        self.dims = [list(d) for d in dims]
+        self.pde = pde
+        self.coefs = [tuple(c) for c in coefs]
+        self.device = device
+        keep = []
+        nets = (Net * self.n)()
+        for i, d in enumerate(self.dims):
+            da = (ctypes.c_int32 * len(d))(*d)
+            Wp, wa = ptr_array([1] * (len(d) - 1))
+            bp, ba = ptr_array([1] * (len(d) - 1))
+            keep += [da, wa, ba]
+            nets[i] = Net(len(d) - 1, ctypes.cast(da, ctypes.POINTER(ctypes.c_int32)), Wp, bp)
+        self._pdes = self._make_pdes()
+        mp = (ctypes.c_int64 * self.n)(*[int(m) for m in max_points])
+        h = ctypes.c_void_p()
+        check(lib.pinn_batch_create(self.n, nets, self._pdes, mp, PRECISIONS[precision], 0, ctypes.byref(h)))
+        self.handle = h
+        self.loss = torch.zeros(self.n, device=device, dtype=torch.float32)
+        self.grads: Optional[List[List[Tuple[torch.Tensor, torch.Tensor]]]] = None
+        self._args = None
+        self._args_key = None
+
+    def _make_pdes(self):
+        pdes = (Pde * self.n)()
+        for i, c in enumerate(self.coefs):
+            pdes[i].kind = KINDS[self.pde]
+            for q, v in enumerate(c):
+                pdes[i].coef[q] = float(v)
+        return pdes
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            check(lib.pinn_batch_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def configure(self, n_streams: int, use_graph: bool = True) -> None:
+        check(lib.pinn_batch_configure(self.handle, int(n_streams), 1 if use_graph else 0))
+
+    def _marshal(self, params_list, xs):
+        key = tuple(t.data_ptr() for ps in params_list for pair in ps for t in pair) + \
+            tuple(x.data_ptr() for x in xs) + tuple(x.shape[0] for x in xs)
+        if self._args_key == key:
+            return self._args
+        if self.grads is None:
+            self.grads = [[(torch.empty_like(W), torch.empty_like(b)) for W, b in ps] for ps in params_list]
+        keep = []
+        nets = (Net * self.n)()
+        dWs = (ctypes.c_void_p * self.n)()
+        dbs = (ctypes.c_void_p * self.n)()
+        for i, (ps, x) in enumerate(zip(params_list, xs)):
+            _check_tensor(x, f"x[{i}]")
+            for l, (W, b) in enumerate(ps):
+                _check_tensor(W, f"W[{i}][{l}]")
+                _check_tensor(b, f"b[{i}][{l}]")
+            d = [int(ps[0][0].shape[1])] + [int(W.shape[0]) for W, _ in ps]
+            da = (ctypes.c_int32 * len(d))(*d)
+            Wp, wa = ptr_array([W.data_ptr() for W, _ in ps])
+            bp, ba = ptr_array([b.data_ptr() for _, b in ps])
+            gWp, gwa = ptr_array([g[0].data_ptr() for g in self.grads[i]])
+            gbp, gba = ptr_array([g[1].data_ptr() for g in self.grads[i]])
+            keep += [da, wa, ba, gwa, gba]
+            nets[i] = Net(len(d) - 1, ctypes.cast(da, ctypes.POINTER(ctypes.c_int32)), Wp, bp)
+            dWs[i] = ctypes.cast(gWp, ctypes.c_void_p)
+            dbs[i] = ctypes.cast(gbp, ctypes.c_void_p)
+        xp = (ctypes.c_void_p * self.n)(*[x.data_ptr() for x in xs])
+        Ns = (ctypes.c_int64 * self.n)(*[int(x.shape[0]) for x in xs])
+        self._args = (nets, xp, Ns, dWs, dbs, keep)
+        self._args_key = key
+        return self._args
+
+    def step(self, params_list, xs) -> Tuple[torch.Tensor, List[List[Tuple[torch.Tensor, torch.Tensor]]]]:
+        """One residual + gradient step of every network; returns (loss (n,), grads)."""
+        nets, xp, Ns, dWs, dbs, _ = self._marshal(params_list, xs)
+        pp = ctypes.POINTER(ctypes.c_void_p)
+        check(lib.pinn_batch_step(self.handle, nets, self._pdes, ctypes.cast(xp, pp), Ns,
+                                  ctypes.c_void_p(self.loss.data_ptr()), ctypes.cast(dWs, pp),
+                                  ctypes.cast(dbs, pp), _stream()))
+        return self.loss, self.grads
+
+    def autotune(self, params_list, xs, reps: int = 3) -> Tuple[int, float]:
+        nets, xp, Ns, dWs, dbs, _ = self._marshal(params_list, xs)
+        pp = ctypes.POINTER(ctypes.c_void_p)
+        bs, ms = ctypes.c_int32(), ctypes.c_double()
+        check(lib.pinn_batch_autotune(self.handle, nets, self._pdes, ctypes.cast(xp, pp), Ns,
+                                      ctypes.c_void_p(self.loss.data_ptr()), ctypes.cast(dWs, pp),
+                                      ctypes.cast(dbs, pp), int(reps), ctypes.byref(bs), ctypes.byref(ms),
+                                      _stream()))
+        return bs.value, ms.value

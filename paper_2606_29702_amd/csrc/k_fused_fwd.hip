@@ -1,7 +1,9 @@
 // Whole-network forward pass for one block of P collocation points per
 // workgroup: seed layer, every hidden layer (stacked-channel GEMM on MFMA with
 // the activation jet in its epilogue), linear output layer, residual and the
-// block's loss partial sum, in one launch.
+// block's loss partial sum, in one launch.  The same kernel also recomputes a
+// segment of layers l_first..l_last from a saved stack (checkpointed
+// backward), so recomputed stacks are bit-for-bit the ones of the forward pass.
 //
 // The block's stack [P][C][w] lives in LDS for the whole pass (one row of
 // C*w + 8 elements per point; the 8-element pad puts consecutive points on
@@ -38,36 +40,54 @@ __global__ __launch_bounds__(NW * 64) void k_fwd_fused(FusedFwdArgs a) {
   const int64_t nb = (int64_t)blockIdx.x * P;
   const int64_t gps = (int64_t)C * w;  // elements per point in a global stack
 
-  // ---- layer 1: z = W1 x + b1, d z / d x_i = W1[:, i], then the jet
-  for (int idx = tid; idx < P * w; idx += NT) {
-    const int p = idx / w, j = idx % w;
-    const int64_t n = nb + p;
-    float z[C];
+  // ---- input of layer l_first: the seed layer from x, or a saved stack
+  if (a.l_first == 1) {
+    // layer 1: z = W1 x + b1, d z / d x_i = W1[:, i], then the jet
+    for (int idx = tid; idx < P * w; idx += NT) {
+      const int p = idx / w, j = idx % w;
+      const int64_t n = nb + p;
+      float z[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) z[c] = 0.f;
-    float z0 = a.b1[j];
+      for (int c = 0; c < C; ++c) z[c] = 0.f;
+      float z0 = a.b1[j];
 #pragma unroll
-    for (int i = 0; i < D; ++i) z0 += a.W1[j * D + i] * (n < a.N ? a.x[n * D + i] : 0.f);
-    z[0] = z0;
+      for (int i = 0; i < D; ++i) z0 += a.W1[j * D + i] * (n < a.N ? a.x[n * D + i] : 0.f);
+      z[0] = z0;
 #pragma unroll
-    for (int d = 0; d < CH::NDIR; ++d) z[CH::at(d, 1)] = a.W1[j * D + CH::in(d)];
-    float act[C], s;
-    jet_forward<CH, sizeof(T) == 2>(z, act, s);
+      for (int d = 0; d < CH::NDIR; ++d) z[CH::at(d, 1)] = a.W1[j * D + CH::in(d)];
+      float act[C], s;
+      jet_forward<CH, sizeof(T) == 2>(z, act, s);
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-      stk[p * pitch + c * w + j] = static_cast<T>(act[c]);
-      if (a.A[1]) static_cast<T *>(a.A[1])[(n * C + c) * w + j] = static_cast<T>(act[c]);
-      if (a.S[1]) a.S[1][(n * C + c) * w + j] = c == 0 ? s : z[c];
+      for (int c = 0; c < C; ++c) {
+        stk[p * pitch + c * w + j] = static_cast<T>(act[c]);
+        if (a.A[1]) static_cast<T *>(a.A[1])[(n * C + c) * w + j] = static_cast<T>(act[c]);
+        if (a.S[1]) a.S[1][(n * C + c) * w + j] = c == 0 ? s : z[c];
+      }
+    }
+  } else {
+    // the saved stack of layer l_first - 1, coalesced, 8 elements per thread
+    const T *Ag = static_cast<const T *>(a.A_in) + nb * gps;
+    const int per_pt = C * w / 8;
+    for (int q = tid; q < P * per_pt; q += NT) {
+      const int pp = q / per_pt, off = (q % per_pt) * 8;
+      const uint4 *src = reinterpret_cast<const uint4 *>(Ag + pp * gps + off);
+      uint4 *dst = reinterpret_cast<uint4 *>(stk + pp * pitch + off);
+      if constexpr (sizeof(T) == 2) {
+        *dst = *src;
+      } else {
+        dst[0] = src[0];
+        dst[1] = src[1];
+      }
     }
   }
   __syncthreads();
 
-  // ---- hidden layers 2..H
+  // ---- hidden layers max(2, l_first) .. l_last
   const int NJ = w / 16;
   const int tile0 = wave * TPW;          // first (point tile, neuron tile) of this wave
   const int nt = tile0 / NJ;             // its 16-point tile
   const int jt0 = tile0 % NJ;            // first of its TPW neuron tiles
-  for (int l = 2; l <= a.H; ++l) {
+  for (int l = a.l_first > 2 ? a.l_first : 2; l <= a.l_last; ++l) {
     const T *Wl = static_cast<const T *>(a.Wop[l]);
     f32x4 acc[TPW][C];
 #pragma unroll
@@ -144,6 +164,7 @@ __global__ __launch_bounds__(NW * 64) void k_fwd_fused(FusedFwdArgs a) {
   }
 
   // ---- output layer, residual, loss partial: TPP threads per point
+  if (!a.do_output) return;
   constexpr int TPP = NT / P;
   {
     const int p = tid / TPP, q = tid % TPP;
@@ -259,6 +280,15 @@ hipError_t launch_fused_t(const FusedFwdArgs &a, int P, hipStream_t st) {
 }
 
 }  // namespace
+
+bool fused_fwd_fits(int P, int C, int w, int prec) {
+  const size_t cap = 144 * 1024;
+  const int tiles = (P / 16) * (w / 16);
+  if (stack_lds(P, C, w, op_size(prec)) > cap) return false;
+  if (P == 32) return tiles == 4 || tiles == 8 || tiles == 16 || tiles == 32;
+  if (P == 16) return tiles == 8 || tiles == 16 || tiles == 32;
+  return false;
+}
 
 int fused_fwd_points(int C, int w, int prec) {
   const int osz = op_size(prec);

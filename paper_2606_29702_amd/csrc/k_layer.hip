@@ -462,9 +462,10 @@ hipError_t launch_bwd_t(const BwdArgs &a, int64_t N_pad, hipStream_t st) {
   }
   const int WJ = (w % 128 == 0) ? 4 : ((w % 64 == 0) ? 2 : 1);
   const int WN = 4 / WJ;
-  // two accumulator sets (abar and the recomputed z) at C = 8 would not fit
-  // with two 16-point tiles per wave
-  constexpr int NTN = (ZSRC == Z_FROM_GEMM && CH::C >= 8) ? 1 : 2;
+  // Two accumulator sets (abar and the recomputed z) at C = 8 do not fit with
+  // two 16-point tiles per wave.  The tile does not depend on the source of z,
+  // so the saved-state and recompute variants run the same GEMM tiling.
+  constexpr int NTN = CH::C >= 8 ? 1 : 2;
   dim3 grid((unsigned)(N_pad / (16 * NTN * WN)), (unsigned)(w / (32 * WJ)));
 #define PJ_BWD(WJV) hipLaunchKernelGGL((k_layer_bwd<CH, T, WJV, NTN, TOP, DOUT, ZSRC>), grid, dim3(256), 0, st, a)
   if (WJ == 4) PJ_BWD(4); else if (WJ == 2) PJ_BWD(2); else PJ_BWD(1);

@@ -75,6 +75,9 @@ struct FusedFwdArgs {
   const float *x;
   int64_t N, N_pad;
   int w, H;
+  int l_first, l_last;                  // hidden layers computed (1 <= l_first <= l_last <= H)
+  const void *A_in;                     // stack of layer l_first - 1 (when l_first > 1)
+  bool do_output;                       // output layer + residual (requires l_last == H)
   const float *W1, *b1;                 // layer 1 (fp32)
   const void *Wop[kMaxHidden + 1];      // layers 2..H, operand type
   const float *b[kMaxHidden + 1];       // layers 2..H
@@ -88,6 +91,7 @@ struct FusedFwdArgs {
 // Points per workgroup for the fused forward pass (32 or 16), or 0 when the
 // block's stack does not fit in LDS (the layer-by-layer kernels are used).
 int fused_fwd_points(int C, int w, int prec);
+bool fused_fwd_fits(int P, int C, int w, int prec);
 hipError_t launch_fwd_fused(int kind, int prec, const FusedFwdArgs &a, int P, hipStream_t st);
 
 // Output layer, residual and per-block loss partial sums (16 points per block).

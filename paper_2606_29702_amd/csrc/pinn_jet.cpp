@@ -107,14 +107,23 @@ struct pinn_plan_s {
 
   // device workspace (indices are 1-based layer numbers; entry 0 unused)
   std::vector<void *> Wop, WTop;  // hidden layers 2..H, operand-type copies
-  std::vector<void *> A;          // activation stacks, layers 1..H
-  std::vector<float *> S;         // saved FP32 states, layers 1..H
+  std::vector<void *> A;          // activation stacks, layers 1..H (null: not materialized)
+  std::vector<float *> S;         // saved FP32 states, layers 1..H (store_S only)
+  // Checkpoint schedule: ckpt[l] means layer l's stack is kept from the
+  // forward pass to the backward pass.  The other layers are recomputed
+  // during backward, one segment (the layers between two checkpoints) at a
+  // time, into the scratch slots.
+  std::vector<char> ckpt;
+  std::vector<void *> slot;
+  std::vector<void *> ckpt_buf;   // owned buffers of the checkpoint layers
   void *Zb[2] = {nullptr, nullptr};
   float *u_save = nullptr, *r_save = nullptr, *ubar = nullptr;
   float *loss_part = nullptr;
   double *loss_part64 = nullptr;
   float *part = nullptr;
   int dw_splits = 1, thin_chunks = 1;
+  int dw_splits_max = 1;   // partial buffer capacity (autotune candidates stay below it)
+  int fwd_points = 0;      // fused forward points per workgroup; 0 = largest that fits
   std::vector<void *> allocs;
   size_t saved_bytes = 0, ws_bytes = 0;
 
@@ -221,31 +230,32 @@ pj::Coef coef_of(const pinn_pde *pde) {
   return k;
 }
 
-// Forward pass through all layers; optionally the residual and the loss.
-pinn_status run_forward(pinn_plan p, const pinn_net *net, const pinn_pde *pde, const float *x,
-                        int64_t N, float *jets, float *r, float *loss, double *loss_f64,
-                        bool save_state, hipStream_t st) {
-  const int64_t npad = round_up(N, pj::kPointTile);
+// Hidden layers l_first..l_last starting from x (l_first = 1) or from A_in,
+// the stack of layer l_first - 1; dest[l] / Sdest[l] (may be null) receive
+// layer l's stack / FP32 state.  With `output`, also the output layer, the
+// residual and the loss partials (l_last must be H).  Returns the number of
+// loss partials in *n_part.
+struct FwdOutputs {
+  bool output = false;
+  const pinn_pde *pde = nullptr;
+  float *jets = nullptr, *r = nullptr;
+};
+
+pinn_status fwd_range(pinn_plan p, const pinn_net *net, const float *x, int64_t N, int64_t npad, int l_first,
+                      int l_last, const void *A_in, void *const *dest, float *const *Sdest,
+                      const FwdOutputs &o, int *n_part, hipStream_t st) {
   const int w = p->w, H = p->H, L = p->L;
   hipError_t e;
-  {
-    pj::CastPack pk{};
-    for (int l = 2; l <= H; ++l) {
-      pk.W[l - 2] = net->W[l - 1];
-      pk.Wop[l - 2] = p->Wop[l];
-    }
-    e = timed(p, PINN_K_OTHER, st, [&] { return pj::launch_cast_all(p->prec, pk, H - 1, w, st); });
-    if (e) return hip_fail(e, "cast");
-  }
-  pinn_pde dflt0{};
-  const pinn_pde *pd = pde;
+  pinn_pde dflt{};
+  const pinn_pde *pd = o.pde;
   if (!pd) {
-    dflt0.kind = p->kind;
-    dflt0.coef[0] = 1.0;
-    pd = &dflt0;
+    dflt.kind = p->kind;
+    dflt.coef[0] = 1.0;
+    pd = &dflt;
   }
   double *lp64 = p->verify() ? p->loss_part64 : nullptr;
-  const int P = pj::fused_fwd_points(p->ki.C, w, p->prec);
+  int P = pj::fused_fwd_points(p->ki.C, w, p->prec);
+  if (P > 0 && p->fwd_points > 0 && pj::fused_fwd_fits(p->fwd_points, p->ki.C, w, p->prec)) P = p->fwd_points;
   if (P > 0) {
     pj::FusedFwdArgs a{};
     a.x = x;
@@ -253,6 +263,10 @@ pinn_status run_forward(pinn_plan p, const pinn_net *net, const pinn_pde *pde, c
     a.N_pad = npad;
     a.w = w;
     a.H = H;
+    a.l_first = l_first;
+    a.l_last = l_last;
+    a.A_in = A_in;
+    a.do_output = o.output;
     a.W1 = net->W[0];
     a.b1 = net->b[0];
     for (int l = 2; l <= H; ++l) {
@@ -261,39 +275,116 @@ pinn_status run_forward(pinn_plan p, const pinn_net *net, const pinn_pde *pde, c
     }
     a.WL = net->W[L - 1];
     a.bL = net->b[L - 1];
-    for (int l = 1; l <= H; ++l) {
-      a.A[l] = save_state ? p->A[l] : nullptr;
-      a.S[l] = save_state ? p->S[l] : nullptr;
+    for (int l = l_first; l <= l_last; ++l) {
+      a.A[l] = dest ? dest[l] : nullptr;
+      a.S[l] = Sdest ? Sdest[l] : nullptr;
     }
     a.k = coef_of(pd);
-    a.jets = jets;
-    a.r = r;
-    a.u_save = p->u_save;
-    a.r_save = p->r_save;
-    a.loss_part = p->loss_part;
-    a.loss_part64 = lp64;
+    if (o.output) {
+      a.jets = o.jets;
+      a.r = o.r;
+      a.u_save = p->u_save;
+      a.r_save = p->r_save;
+      a.loss_part = p->loss_part;
+      a.loss_part64 = lp64;
+    }
     e = timed(p, PINN_K_LAYER_FWD, st, [&] { return pj::launch_fwd_fused(p->kind, p->prec, a, P, st); });
     if (e) return hip_fail(e, "fused forward");
-    if (loss || loss_f64) {
-      e = timed(p, PINN_K_OTHER, st, [&] { return pj::launch_loss_reduce(p->loss_part, lp64, (int)(npad / P), 1.0 / (double)N, loss, loss_f64, st); });
-      if (e) return hip_fail(e, "loss reduction");
-    }
+    if (n_part) *n_part = (int)(npad / P);
     return PINN_OK;
   }
-  e = timed(p, PINN_K_SEED_FWD, st, [&] { return pj::launch_seed_fwd(p->kind, p->prec, x, N, npad, net->W[0], net->b[0], w, p->A[1], p->S[1], st); });
-  if (e) return hip_fail(e, "seed layer");
-  for (int l = 2; l <= H; ++l) {
-    e = timed(p, PINN_K_LAYER_FWD, st, [&] { return pj::launch_layer_fwd(p->kind, p->prec, p->A[l - 1], p->Wop[l], net->b[l - 1], p->A[l], p->S[l],
-                             npad, w, st); });
+  // layer by layer; layers without a destination go through two temporaries
+  // (the adjoint ping-pong buffers, unused during a forward pass)
+  const void *prev = A_in;
+  for (int l = l_first; l <= l_last; ++l) {
+    void *out = (dest && dest[l]) ? dest[l] : p->Zb[l % 2];
+    float *S = Sdest ? Sdest[l] : nullptr;
+    if (l == 1) {
+      e = timed(p, PINN_K_SEED_FWD, st, [&] { return pj::launch_seed_fwd(p->kind, p->prec, x, N, npad, net->W[0], net->b[0], w, out, S, st); });
+    } else {
+      e = timed(p, PINN_K_LAYER_FWD, st, [&] { return pj::launch_layer_fwd(p->kind, p->prec, prev, p->Wop[l], net->b[l - 1], out, S, npad, w, st); });
+    }
     if (e) return hip_fail(e, "hidden layer");
+    prev = out;
   }
-  e = timed(p, PINN_K_OUT_FWD, st, [&] { return pj::launch_out_fwd(p->kind, p->prec, p->A[H], net->W[L - 1], net->b[L - 1], x, N, npad, w,
-                         coef_of(pd), jets, r, p->u_save, p->r_save, p->loss_part, lp64, st); });
-  if (e) return hip_fail(e, "output layer");
+  if (o.output) {
+    e = timed(p, PINN_K_OUT_FWD, st, [&] { return pj::launch_out_fwd(p->kind, p->prec, prev, net->W[L - 1], net->b[L - 1], x, N, npad, w, coef_of(pd), o.jets, o.r, p->u_save, p->r_save, p->loss_part, lp64, st); });
+    if (e) return hip_fail(e, "output layer");
+    if (n_part) *n_part = (int)(npad / 16);
+  }
+  return PINN_OK;
+}
+
+pinn_status cast_weights(pinn_plan p, const pinn_net *net, bool transposed, hipStream_t st) {
+  pj::CastPack pk{};
+  for (int l = 2; l <= p->H; ++l) {
+    pk.W[l - 2] = net->W[l - 1];
+    pk.Wop[l - 2] = p->Wop[l];
+    pk.WTop[l - 2] = transposed ? p->WTop[l] : nullptr;
+  }
+  hipError_t e = timed(p, PINN_K_OTHER, st, [&] { return pj::launch_cast_all(p->prec, pk, p->H - 1, p->w, st); });
+  return e ? hip_fail(e, "cast") : PINN_OK;
+}
+
+// Forward pass through all layers, the residual and the loss.  With
+// save_state the checkpoint layers' stacks (and FP32 states) are kept.
+pinn_status run_forward(pinn_plan p, const pinn_net *net, const pinn_pde *pde, const float *x,
+                        int64_t N, float *jets, float *r, float *loss, double *loss_f64,
+                        bool save_state, hipStream_t st) {
+  const int64_t npad = round_up(N, pj::kPointTile);
+  const int H = p->H;
+  pinn_status rs = cast_weights(p, net, false, st);
+  if (rs) return rs;
+  // stacks of non-checkpoint layers from an earlier backward are stale now
+  for (int l = 1; l <= H; ++l)
+    if (!p->ckpt[l]) p->A[l] = nullptr;
+  std::vector<void *> dest(H + 1, nullptr);
+  std::vector<float *> Sdest(H + 1, nullptr);
+  if (save_state)
+    for (int l = 1; l <= H; ++l) {
+      dest[l] = p->ckpt[l] ? p->ckpt_buf[l] : nullptr;
+      Sdest[l] = p->S[l];
+    }
+  FwdOutputs o;
+  o.output = true;
+  o.pde = pde;
+  o.jets = jets;
+  o.r = r;
+  int n_part = 0;
+  rs = fwd_range(p, net, x, N, npad, 1, H, nullptr, dest.data(), Sdest.data(), o, &n_part, st);
+  if (rs) return rs;
   if (loss || loss_f64) {
-    e = timed(p, PINN_K_OTHER, st, [&] { return pj::launch_loss_reduce(p->loss_part, lp64, (int)(npad / 16), 1.0 / (double)N, loss, loss_f64, st); });
+    double *lp64 = p->verify() ? p->loss_part64 : nullptr;
+    hipError_t e = timed(p, PINN_K_OTHER, st, [&] { return pj::launch_loss_reduce(p->loss_part, lp64, n_part, 1.0 / (double)N, loss, loss_f64, st); });
     if (e) return hip_fail(e, "loss reduction");
   }
+  return PINN_OK;
+}
+
+// Stack of layer j (1 <= j <= H) for the backward pass: a checkpoint, or the
+// segment of non-checkpoint layers around j recomputed into the scratch slots
+// from the checkpoint below it (or from x).
+pinn_status backward_stack(pinn_plan p, const pinn_net *net, const float *x, int64_t N, int64_t npad, int j,
+                           const void **out, hipStream_t st) {
+  if (p->A[j]) {
+    *out = p->A[j];
+    return PINN_OK;
+  }
+  const int H = p->H;
+  int c = j - 1;
+  while (c > 0 && !p->ckpt[c]) --c;
+  int top = j;
+  while (top + 1 <= H && !p->ckpt[top + 1]) ++top;
+  for (int l = 1; l <= H; ++l)
+    if (!p->ckpt[l]) p->A[l] = nullptr;  // the slots now hold this segment
+  std::vector<void *> dest(H + 1, nullptr);
+  for (int l = c + 1; l <= top; ++l) dest[l] = p->slot[l - c - 1];
+  FwdOutputs o;
+  pinn_status rs = fwd_range(p, net, x, N, npad, c + 1, top, c > 0 ? p->A[c] : nullptr, dest.data(), nullptr, o,
+                             nullptr, st);
+  if (rs) return rs;
+  for (int l = c + 1; l <= top; ++l) p->A[l] = dest[l];
+  *out = p->A[j];
   return PINN_OK;
 }
 
@@ -336,11 +427,33 @@ pinn_status pinn_plan_create(const pinn_net *net, const pinn_pde *pde, int64_t m
   const int64_t npad = round_up(max_points, pj::kPointTile);
   const size_t osz = (size_t)pj::op_size(prec);
   const size_t stack_elems = (size_t)npad * ki.C * w;
-  const bool store_S = prec == PINN_FP32;
-  const size_t saved = (size_t)H * stack_elems * (osz + (store_S ? sizeof(float) : 0));
-  if (save_cap_bytes != 0 && save_cap_bytes < saved)
-    return fail(PINN_ERR_CAP, "save_cap_bytes = %zu below the %zu bytes of saved layer state", save_cap_bytes,
-                saved);
+  // Checkpoint schedule.  No bound: every stack is kept (and, for FP32
+  // operands, the FP32 layer states).  Under a bound: k = cap / stack stacks
+  // are kept, at every s-th layer with s = ceil(H / (k + 1)); the FP32 states
+  // are recomputed.
+  const size_t stack_bytes = stack_elems * osz;
+  const bool store_S = save_cap_bytes == 0 && prec == PINN_FP32;
+  std::vector<char> ckpt(H + 1, 1);
+  ckpt[0] = 0;
+  if (save_cap_bytes != 0) {
+    const size_t kmax = save_cap_bytes / stack_bytes;
+    if (kmax < 1)
+      return fail(PINN_ERR_CAP, "save_cap_bytes = %zu below one saved layer stack (%zu bytes)", save_cap_bytes,
+                  stack_bytes);
+    if (kmax < (size_t)H) {
+      const int sgap = (H + (int)kmax) / ((int)kmax + 1);  // ceil(H / (k + 1))
+      for (int l = 1; l <= H; ++l) ckpt[l] = (l % sgap == 0 && l < H) ? 1 : 0;
+    }
+  }
+  int n_ckpt = 0, max_gap = 0;
+  for (int l = 1, c = 0; l <= H + 1; ++l) {
+    if (l == H + 1 || ckpt[l]) {
+      max_gap = std::max(max_gap, l - c - 1);
+      c = l;
+    }
+    if (l <= H && ckpt[l]) ++n_ckpt;
+  }
+  const size_t saved = (size_t)n_ckpt * stack_bytes + (store_S ? (size_t)H * stack_elems * sizeof(float) : 0);
 
   pinn_plan p = new (std::nothrow) pinn_plan_s;
   if (!p) return fail(PINN_ERR_NOMEM, "host allocation failed");
@@ -356,6 +469,7 @@ pinn_status pinn_plan_create(const pinn_net *net, const pinn_pde *pde, int64_t m
   p->save_cap = save_cap_bytes;
   p->saved_bytes = saved;
   p->store_S = store_S;
+  p->ckpt = ckpt;
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
     return fail(PINN_ERR_DEVICE, "no HIP device");
@@ -372,10 +486,16 @@ pinn_status pinn_plan_create(const pinn_net *net, const pinn_pde *pde, int64_t m
     A(&p->Wop[l], (size_t)w * w * osz);
     A(&p->WTop[l], (size_t)w * w * osz);
   }
+  p->ckpt_buf.assign(H + 1, nullptr);
   for (int l = 1; l <= H; ++l) {
-    A(&p->A[l], stack_elems * osz);
+    if (ckpt[l]) {
+      A(&p->ckpt_buf[l], stack_bytes);
+      p->A[l] = p->ckpt_buf[l];
+    }
     if (store_S) A(reinterpret_cast<void **>(&p->S[l]), stack_elems * sizeof(float));
   }
+  p->slot.assign(max_gap, nullptr);
+  for (int q = 0; q < max_gap; ++q) A(&p->slot[q], stack_bytes);
   A(&p->Zb[0], stack_elems * osz);
   A(&p->Zb[1], stack_elems * osz);
   A(reinterpret_cast<void **>(&p->u_save), (size_t)npad * ki.dout * ki.C * sizeof(float));
@@ -384,9 +504,10 @@ pinn_status pinn_plan_create(const pinn_net *net, const pinn_pde *pde, int64_t m
   A(reinterpret_cast<void **>(&p->loss_part), (size_t)(npad / 16) * sizeof(float));
   A(reinterpret_cast<void **>(&p->loss_part64), (size_t)(npad / 16) * sizeof(double));
   p->dw_splits = dw_splits_for(npad, ki.C, w);
+  p->dw_splits_max = 2 * p->dw_splits;
   p->thin_chunks = (int)std::max<int64_t>(1, npad / 64);
   const size_t part_elems =
-      std::max<size_t>((size_t)p->dw_splits * ((size_t)w * w + w),
+      std::max<size_t>((size_t)p->dw_splits_max * ((size_t)w * w + w),
                        (size_t)p->thin_chunks * std::max(ki.dout * w + ki.dout, w * ki.din + w));
   A(reinterpret_cast<void **>(&p->part), part_elems * sizeof(float));
   if (e != hipSuccess) {
@@ -496,23 +617,18 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
   const KindInfo &ki = p->ki;
   auto f64 = [&](double *const *arr, int l) -> double * { return arr ? arr[l] : nullptr; };
   hipError_t e;
-  {
-    pj::CastPack pk{};
-    for (int l = 2; l <= H; ++l) {
-      pk.W[l - 2] = net->W[l - 1];
-      pk.Wop[l - 2] = p->Wop[l];
-      pk.WTop[l - 2] = p->WTop[l];
-    }
-    e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_cast_all(p->prec, pk, H - 1, w, s); });
-    if (e) return hip_fail(e, "cast");
-  }
+  pinn_status rs = cast_weights(p, net, true, s);
+  if (rs) return rs;
   // Source of z for the adjoint of activation layer m: the saved state, or a
-  // recompute from the previous stack (m >= 2) or from x (m = 1).
-  auto zsrc = [&](pj::LayerBwd &B, int m) {
+  // recompute from the stack of layer m - 1 (m >= 2) or from x (m = 1).
+  auto zsrc = [&](pj::LayerBwd &B, int m) -> pinn_status {
     if (p->store_S) {
       B.S_in = p->S[m];
     } else if (m >= 2) {
-      B.A_prev = p->A[m - 1];
+      const void *Am1 = nullptr;
+      pinn_status r2 = backward_stack(p, net, x, N, npad, m - 1, &Am1, s);
+      if (r2) return r2;
+      B.A_prev = Am1;
       B.Wz = p->Wop[m];
       B.bz = net->b[m - 1];
     } else {
@@ -520,6 +636,7 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
       B.W1 = net->W[0];
       B.bz = net->b[0];
     }
+    return PINN_OK;
   };
   // Output layer: ubar, then zbar of layer H, then dW_L, db_L.
   e = timed(p, PINN_K_OUT_BWD, s, [&] { return pj::launch_out_adj(p->kind, p->u_save, p->r_save, r_bar, N, npad, (float)(2.0 / (double)N), coef_of(pde), p->ubar, s); });
@@ -532,20 +649,28 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
     B.N = N;
     B.w = w;
     B.Zb_out = p->Zb[H % 2];
-    zsrc(B, H);
+    rs = zsrc(B, H);
+    if (rs) return rs;
     e = timed(p, PINN_K_OUT_BWD, s, [&] { return pj::launch_layer_bwd(p->kind, p->prec, B, npad, s); });
     if (e) return hip_fail(e, "last hidden adjoint");
   }
-  e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_dw_out(p->kind, p->prec, p->ubar, p->A[H], npad, w, p->part, p->thin_chunks, s); });
+  const void *AH = nullptr;
+  rs = backward_stack(p, net, x, N, npad, H, &AH, s);
+  if (rs) return rs;
+  e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_dw_out(p->kind, p->prec, p->ubar, AH, npad, w, p->part, p->thin_chunks, s); });
   if (e) return hip_fail(e, "output-layer gradient");
   e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, p->thin_chunks, (int64_t)ki.dout * w + ki.dout,
                                (int64_t)ki.dout * w, ki.dout, dW[L - 1], db[L - 1], f64(dW_f64, L - 1),
                                f64(db_f64, L - 1), s); });
   if (e) return hip_fail(e, "reduction");
-  // Hidden layers H..2.
+  // Hidden layers H..2: dW_l, db_l from zbar_l and the stack of layer l - 1,
+  // then zbar of layer l - 1.
   for (int l = H; l >= 2; --l) {
     void *cur = p->Zb[l % 2], *prev = p->Zb[(l - 1) % 2];
-    e = timed(p, PINN_K_DW_HIDDEN, s, [&] { return pj::launch_dw_hidden(p->prec, ki.C, cur, p->A[l - 1], npad, w, p->part, p->part + (size_t)w * w, p->dw_splits, s); });
+    const void *Al1 = nullptr;
+    rs = backward_stack(p, net, x, N, npad, l - 1, &Al1, s);
+    if (rs) return rs;
+    e = timed(p, PINN_K_DW_HIDDEN, s, [&] { return pj::launch_dw_hidden(p->prec, ki.C, cur, Al1, npad, w, p->part, p->part + (size_t)w * w, p->dw_splits, s); });
     if (e) return hip_fail(e, "hidden-layer gradient");
     e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, p->dw_splits, (int64_t)w * w + w, (int64_t)w * w, w, dW[l - 1], db[l - 1], f64(dW_f64, l - 1), f64(db_f64, l - 1), s); });
     if (e) return hip_fail(e, "reduction");
@@ -556,7 +681,8 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
     B.N = N;
     B.w = w;
     B.Zb_out = prev;
-    zsrc(B, l - 1);
+    rs = zsrc(B, l - 1);
+    if (rs) return rs;
     e = timed(p, PINN_K_LAYER_BWD, s, [&] { return pj::launch_layer_bwd(p->kind, p->prec, B, npad, s); });
     if (e) return hip_fail(e, "hidden adjoint");
   }
@@ -566,6 +692,360 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
   e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, p->thin_chunks, (int64_t)w * ki.din + w, (int64_t)w * ki.din, w,
                                dW[0], db[0], f64(dW_f64, 0), f64(db_f64, 0), s); });
   if (e) return hip_fail(e, "reduction");
+  return PINN_OK;
+}
+
+
+pinn_status pinn_plan_get_tuning(pinn_plan plan, pinn_tuning *t) {
+  g_err.clear();
+  if (!plan || !t) return fail(PINN_ERR_ARG, "plan or tuning is NULL");
+  t->dw_splits = plan->dw_splits;
+  t->fwd_points = plan->fwd_points;
+  return PINN_OK;
+}
+
+pinn_status pinn_plan_set_tuning(pinn_plan plan, const pinn_tuning *t) {
+  g_err.clear();
+  if (!plan || !t) return fail(PINN_ERR_ARG, "plan or tuning is NULL");
+  if (t->dw_splits < 1 || t->dw_splits > plan->dw_splits_max)
+    return fail(PINN_ERR_ARG, "dw_splits = %d outside [1, %d]", t->dw_splits, plan->dw_splits_max);
+  if (t->fwd_points != 0 && !pj::fused_fwd_fits(t->fwd_points, plan->ki.C, plan->w, plan->prec))
+    return fail(PINN_ERR_ARG, "fwd_points = %d has no fused forward tiling at this width", t->fwd_points);
+  plan->dw_splits = t->dw_splits;
+  plan->fwd_points = t->fwd_points;
+  plan->have_state = false;
+  return PINN_OK;
+}
+
+pinn_status pinn_plan_autotune(pinn_plan plan, const pinn_net *net, const pinn_pde *pde, const float *x,
+                               int64_t N, int32_t reps, pinn_tuning *best, double *best_ms, void *stream) {
+  g_err.clear();
+  pinn_status st = check_call(plan, net, x, N);
+  if (st) return st;
+  st = check_pde(pde, plan->kind);
+  if (st) return st;
+  if (reps < 1 || reps > 1000) return fail(PINN_ERR_ARG, "reps = %d outside [1, 1000]", reps);
+  hipStream_t s = (hipStream_t)stream;
+  pinn_plan p = plan;
+  // gradient outputs for the trial steps
+  std::vector<void *> bufs;
+  std::vector<float *> dW(p->L), db(p->L);
+  hipError_t e = hipSuccess;
+  for (int l = 0; l < p->L && e == hipSuccess; ++l) {
+    void *a = nullptr, *b = nullptr;
+    e = hipMalloc(&a, (size_t)net->dims[l] * net->dims[l + 1] * sizeof(float));
+    if (e == hipSuccess) bufs.push_back(a), e = hipMalloc(&b, (size_t)net->dims[l + 1] * sizeof(float));
+    if (e == hipSuccess) bufs.push_back(b);
+    dW[l] = (float *)a;
+    db[l] = (float *)b;
+  }
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  auto cleanup = [&]() {
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    for (void *q : bufs) (void)hipFree(q);
+  };
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "autotune setup");
+  }
+  const pinn_tuning orig{p->dw_splits, p->fwd_points};
+  const int s0 = dw_splits_for(round_up(N, pj::kPointTile), p->ki.C, p->w);
+  std::vector<pinn_tuning> cand;
+  for (int sp : {std::max(1, s0 / 2), s0, std::min(p->dw_splits_max, 2 * s0)})
+    for (int fp : {0, 16}) {
+      if (fp == 16 && (!pj::fused_fwd_fits(16, p->ki.C, p->w, p->prec) ||
+                       pj::fused_fwd_points(p->ki.C, p->w, p->prec) == 16))
+        continue;
+      pinn_tuning t{sp, fp};
+      bool dup = false;
+      for (auto &c : cand) dup = dup || (c.dw_splits == t.dw_splits && c.fwd_points == t.fwd_points);
+      if (!dup) cand.push_back(t);
+    }
+  double bms = 1e300;
+  pinn_tuning bt = orig;
+  for (const pinn_tuning &c : cand) {
+    p->dw_splits = c.dw_splits;
+    p->fwd_points = c.fwd_points;
+    for (int it = -1; it < reps && st == PINN_OK; ++it) {
+      if (it == 0) e = hipEventRecord(t0, s);
+      st = pinn_jet_residual(p, net, pde, x, N, nullptr, nullptr, nullptr, nullptr, stream);
+      if (st == PINN_OK)
+        st = pinn_jet_backward(p, net, pde, x, N, nullptr, dW.data(), db.data(), nullptr, nullptr, stream);
+    }
+    if (st != PINN_OK) break;
+    e = hipEventRecord(t1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(t1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+    if (e != hipSuccess) break;
+    if (ms / reps < bms) {
+      bms = ms / reps;
+      bt = c;
+    }
+  }
+  cleanup();
+  if (st != PINN_OK) return st;
+  if (e != hipSuccess) return hip_fail(e, "autotune timing");
+  p->dw_splits = bt.dw_splits;
+  p->fwd_points = bt.fwd_points;
+  p->have_state = false;
+  if (best) *best = bt;
+  if (best_ms) *best_ms = bms;
+  return PINN_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Ensembles: many independent networks stepped together.
+// ---------------------------------------------------------------------------
+struct pinn_batch_s {
+  int n = 0;
+  std::vector<pinn_plan> plans;
+  std::vector<int> L;
+  int n_streams = 8;
+  std::vector<hipStream_t> streams;   // side streams (default priority)
+  std::vector<hipEvent_t> ev_join;    // one per side stream
+  hipEvent_t ev_fork = nullptr, ev_in = nullptr, ev_out = nullptr;
+  hipStream_t origin = nullptr;       // capture origin
+  bool use_graph = true;
+  hipGraphExec_t exec = nullptr;
+  std::vector<const void *> key;      // every pointer baked into the captured graph
+  ~pinn_batch_s() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    for (hipEvent_t e : ev_join) (void)hipEventDestroy(e);
+    for (hipEvent_t e : {ev_fork, ev_in, ev_out})
+      if (e) (void)hipEventDestroy(e);
+    for (hipStream_t s : streams) (void)hipStreamDestroy(s);
+    if (origin) (void)hipStreamDestroy(origin);
+    for (pinn_plan p : plans) delete p;
+  }
+};
+
+namespace {
+
+constexpr int kMaxBatchStreams = 16;
+
+hipError_t batch_streams(pinn_batch b, int n) {
+  while ((int)b->streams.size() < n) {
+    hipStream_t s;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e) return e;
+    b->streams.push_back(s);
+    hipEvent_t ev;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e) return e;
+    b->ev_join.push_back(ev);
+  }
+  b->n_streams = n;
+  return hipSuccess;
+}
+
+// Enqueues one step of every network: fork from `origin` to the side streams,
+// network i on side stream i mod S (networks in the order given), join back.
+pinn_status batch_enqueue(pinn_batch b, const pinn_net *nets, const pinn_pde *pdes, const float *const *x,
+                          const int64_t *N, float *loss, float *const *const *dW, float *const *const *db,
+                          hipStream_t origin) {
+  hipError_t e = hipEventRecord(b->ev_fork, origin);
+  if (e) return hip_fail(e, "fork");
+  for (int s = 0; s < b->n_streams; ++s) {
+    e = hipStreamWaitEvent(b->streams[s], b->ev_fork, 0);
+    if (e) return hip_fail(e, "fork");
+  }
+  for (int i = 0; i < b->n; ++i) {
+    hipStream_t s = b->streams[i % b->n_streams];
+    pinn_status st = pinn_jet_residual(b->plans[i], &nets[i], &pdes[i], x[i], N[i], nullptr, loss + i, nullptr,
+                                       nullptr, s);
+    if (st) return st;
+    st = pinn_jet_backward(b->plans[i], &nets[i], &pdes[i], x[i], N[i], nullptr, dW[i], db[i], nullptr, nullptr, s);
+    if (st) return st;
+  }
+  for (int s = 0; s < b->n_streams; ++s) {
+    e = hipEventRecord(b->ev_join[s], b->streams[s]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(origin, b->ev_join[s], 0);
+    if (e) return hip_fail(e, "join");
+  }
+  return PINN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pinn_status pinn_batch_create(int32_t n, const pinn_net *nets, const pinn_pde *pdes, const int64_t *max_points,
+                              int32_t prec, uint32_t flags, pinn_batch *out) {
+  g_err.clear();
+  if (!out) return fail(PINN_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || n > 4096) return fail(PINN_ERR_ARG, "n = %d outside [1, 4096]", n);
+  if (!nets || !pdes || !max_points) return fail(PINN_ERR_ARG, "nets, pdes or max_points is NULL");
+  pinn_batch b = new (std::nothrow) pinn_batch_s;
+  if (!b) return fail(PINN_ERR_NOMEM, "host allocation failed");
+  for (int i = 0; i < n; ++i) {
+    pinn_plan p = nullptr;
+    pinn_status st = pinn_plan_create(&nets[i], &pdes[i], max_points[i], prec, flags, 0, &p);
+    if (st) {
+      std::string msg = g_err;
+      delete b;
+      return fail(st, "network %d: %s", i, msg.c_str());
+    }
+    b->plans.push_back(p);
+    b->L.push_back(nets[i].n_layers);
+  }
+  b->n = n;
+  hipError_t e = batch_streams(b, std::min(8, n));
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_fail(e, "batch streams");
+  }
+  *out = b;
+  return PINN_OK;
+}
+
+pinn_status pinn_batch_destroy(pinn_batch b) {
+  g_err.clear();
+  if (!b) return fail(PINN_ERR_ARG, "batch is NULL");
+  delete b;
+  return PINN_OK;
+}
+
+pinn_status pinn_batch_configure(pinn_batch b, int32_t n_streams, int32_t use_graph) {
+  g_err.clear();
+  if (!b) return fail(PINN_ERR_ARG, "batch is NULL");
+  if (n_streams < 1 || n_streams > kMaxBatchStreams)
+    return fail(PINN_ERR_ARG, "n_streams = %d outside [1, %d]", n_streams, kMaxBatchStreams);
+  hipError_t e = batch_streams(b, n_streams);
+  if (e) return hip_fail(e, "batch streams");
+  b->use_graph = use_graph != 0;
+  if (b->exec) {
+    (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  b->key.clear();
+  return PINN_OK;
+}
+
+pinn_status pinn_batch_step(pinn_batch b, const pinn_net *nets, const pinn_pde *pdes, const float *const *x,
+                            const int64_t *N, float *loss, float *const *const *dW, float *const *const *db,
+                            void *stream) {
+  g_err.clear();
+  if (!b) return fail(PINN_ERR_ARG, "batch is NULL");
+  if (!nets || !pdes || !x || !N || !loss || !dW || !db) return fail(PINN_ERR_ARG, "a batch argument is NULL");
+  // validate everything on the host before enqueueing anything
+  std::vector<const void *> key;
+  key.push_back(loss);
+  for (int i = 0; i < b->n; ++i) {
+    pinn_status st = check_call(b->plans[i], &nets[i], x[i], N[i]);
+    if (st == PINN_OK) st = check_pde(&pdes[i], b->plans[i]->kind);
+    if (st) {
+      std::string msg = g_err;
+      return fail(st, "network %d: %s", i, msg.c_str());
+    }
+    if (!dW[i] || !db[i]) return fail(PINN_ERR_ARG, "network %d: dW or db is NULL", i);
+    for (int l = 0; l < b->L[i]; ++l)
+      if (!dW[i][l] || !db[i][l]) return fail(PINN_ERR_ARG, "network %d: dW[%d] or db[%d] is NULL", i, l, l);
+    key.push_back(x[i]);
+    key.push_back(reinterpret_cast<const void *>((intptr_t)N[i]));
+    for (int q = 0; q < 4; ++q) {
+      double c = pdes[i].coef[q];
+      intptr_t bits;
+      std::memcpy(&bits, &c, sizeof bits);
+      key.push_back(reinterpret_cast<const void *>(bits));
+    }
+    for (int l = 0; l < b->L[i]; ++l) {
+      key.push_back(nets[i].W[l]);
+      key.push_back(nets[i].b[l]);
+      key.push_back(dW[i][l]);
+      key.push_back(db[i][l]);
+    }
+  }
+  hipStream_t caller = (hipStream_t)stream;
+  if (!b->use_graph) return batch_enqueue(b, nets, pdes, x, N, loss, dW, db, caller);
+
+  hipError_t e;
+  if (!b->exec || key != b->key) {
+    // capture one step on the private origin stream, then instantiate it
+    if (b->exec) {
+      (void)hipGraphExecDestroy(b->exec);
+      b->exec = nullptr;
+    }
+    for (pinn_plan p : b->plans) p->prof_class = 0;  // no event timing inside a graph
+    e = hipStreamBeginCapture(b->origin, hipStreamCaptureModeRelaxed);
+    if (e) return hip_fail(e, "graph capture");
+    pinn_status st = batch_enqueue(b, nets, pdes, x, N, loss, dW, db, b->origin);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->origin, &g);
+    if (st) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e) return hip_fail(e, "graph capture");
+    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e) return hip_fail(e, "graph instantiate");
+    b->key = key;
+  }
+  e = hipEventRecord(b->ev_in, caller);
+  if (e == hipSuccess) e = hipStreamWaitEvent(b->origin, b->ev_in, 0);
+  if (e == hipSuccess) e = hipGraphLaunch(b->exec, b->origin);
+  if (e == hipSuccess) e = hipEventRecord(b->ev_out, b->origin);
+  if (e == hipSuccess) e = hipStreamWaitEvent(caller, b->ev_out, 0);
+  if (e) return hip_fail(e, "graph launch");
+  return PINN_OK;
+}
+
+pinn_status pinn_batch_autotune(pinn_batch b, const pinn_net *nets, const pinn_pde *pdes, const float *const *x,
+                                const int64_t *N, float *loss, float *const *const *dW, float *const *const *db,
+                                int32_t reps, int32_t *best_streams, double *best_ms, void *stream) {
+  g_err.clear();
+  if (!b) return fail(PINN_ERR_ARG, "batch is NULL");
+  if (reps < 1 || reps > 1000) return fail(PINN_ERR_ARG, "reps = %d outside [1, 1000]", reps);
+  hipStream_t caller = (hipStream_t)stream;
+  hipEvent_t t0, t1;
+  hipError_t e = hipEventCreate(&t0);
+  if (e) return hip_fail(e, "autotune events");
+  e = hipEventCreate(&t1);
+  if (e) {
+    (void)hipEventDestroy(t0);
+    return hip_fail(e, "autotune events");
+  }
+  const bool graph = b->use_graph;
+  double bms = 1e300;
+  int bs = b->n_streams;
+  pinn_status st = PINN_OK;
+  for (int ns : {1, 2, 4, 8, 16}) {
+    if (ns > b->n) break;
+    st = pinn_batch_configure(b, ns, graph);
+    for (int it = -1; it < reps && st == PINN_OK; ++it) {
+      if (it == 0) e = hipEventRecord(t0, caller);
+      st = pinn_batch_step(b, nets, pdes, x, N, loss, dW, db, stream);
+    }
+    if (st) break;
+    e = hipEventRecord(t1, caller);
+    if (e == hipSuccess) e = hipEventSynchronize(t1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+    if (e) break;
+    if (ms / reps < bms) {
+      bms = ms / reps;
+      bs = ns;
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (st) return st;
+  if (e) return hip_fail(e, "autotune timing");
+  st = pinn_batch_configure(b, bs, graph);
+  if (st) return st;
+  if (best_streams) *best_streams = bs;
+  if (best_ms) *best_ms = bms;
   return PINN_OK;
 }
 

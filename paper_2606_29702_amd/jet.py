@@ -12,7 +12,7 @@ from typing import List, Optional, Sequence, Tuple
 import torch
 
 from . import _lib
-from ._lib import KINDS, PRECISIONS, Net, Pde, check, lib, ptr_array
+from ._lib import KINDS, PRECISIONS, Net, Pde, Tuning, check, lib, ptr_array
 
 CHANNELS = {k: lib.pinn_pde_channels(v) for k, v in KINDS.items()}
 RESIDUALS = {k: lib.pinn_pde_residuals(v) for k, v in KINDS.items()}
@@ -93,6 +93,25 @@ class PinnPlan:
         s, w = ctypes.c_size_t(), ctypes.c_size_t()
         check(lib.pinn_plan_memory(self.handle, ctypes.byref(s), ctypes.byref(w)))
         return s.value, w.value
+
+    def tuning(self) -> dict:
+        t = Tuning()
+        check(lib.pinn_plan_get_tuning(self.handle, ctypes.byref(t)))
+        return {"dw_splits": t.dw_splits, "fwd_points": t.fwd_points}
+
+    def set_tuning(self, dw_splits: int, fwd_points: int = 0) -> None:
+        t = Tuning(int(dw_splits), int(fwd_points))
+        check(lib.pinn_plan_set_tuning(self.handle, ctypes.byref(t)))
+
+    def autotune(self, params, x: torch.Tensor, reps: int = 3) -> Tuple[dict, float]:
+        """Times the candidate tunings on (params, x), keeps the fastest; returns it and ms/step."""
+        _check_tensor(x, "x")
+        nv = _NetView(params)
+        t, ms = Tuning(), ctypes.c_double()
+        check(lib.pinn_plan_autotune(self.handle, ctypes.byref(nv.net), ctypes.byref(_pde(self.pde, self.coef)),
+                                     ctypes.c_void_p(x.data_ptr()), x.shape[0], int(reps), ctypes.byref(t),
+                                     ctypes.byref(ms), _stream()))
+        return {"dw_splits": t.dw_splits, "fwd_points": t.fwd_points}, ms.value
 
     def profile(self, kernel_class: str) -> None:
         """Start timing launches of one kernel class ('off' to stop)."""
