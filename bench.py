@@ -143,6 +143,51 @@ def nested_autograd_fp32(prob, steps):
     return (time.perf_counter() - t0) * 1e3 / steps
 
 
+def ensemble(steps, seed=0):
+    """The 64-network Burgers ensemble: one BF16 step of all networks (side
+    streams, HIP graph replay, autotuned stream count) against 64 sequential
+    plain-FP32 calls on one stream, same GPU."""
+    import torch
+    import pinn_inputs as pi
+    from paper_2606_29702_amd import PinnBatch, PinnPlan
+    ens = pi.make_ensemble(seed=seed)
+    total = sum(m.N for m in ens)
+    params = [[(torch.tensor(W, device="cuda"), torch.tensor(b, device="cuda")) for W, b in m.params] for m in ens]
+    xs = [torch.tensor(m.x, device="cuda") for m in ens]
+    batch = PinnBatch([m.dims for m in ens], "burgers", [(m.nu,) for m in ens], [m.N for m in ens],
+                      precision="bf16")
+    n_streams, _ = batch.autotune(params, xs, reps=2)
+    for _ in range(2):
+        batch.step(params, xs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batch.step(params, xs)
+    torch.cuda.synchronize()
+    t_b = (time.perf_counter() - t0) / steps
+    batch.close()
+    plans = [PinnPlan(m.dims, "burgers", m.N, precision="fp32", coef=(m.nu,)) for m in ens]
+
+    def seq():
+        for pl, p, x in zip(plans, params, xs):
+            pl.residual(p, x)
+            pl.backward(p, x)
+
+    seq()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        seq()
+    torch.cuda.synchronize()
+    t_s = (time.perf_counter() - t0) / steps
+    for pl in plans:
+        pl.close()
+    return {"nets": len(ens), "points": total, "value": round(total / t_b, 1), "unit": "pts/s",
+            "ms_per_step": round(t_b * 1e3, 3), "side_streams": n_streams,
+            "fp32_sequential": {"value": round(total / t_s, 1), "ms_per_step": round(t_s * 1e3, 3)},
+            "speedup_vs_fp32_sequential": round(t_s / t_b, 3)}
+
+
 def cpu_baseline(prob, target_s=15.0):
     """The FP64 oracle on the host cores over a bounded sample of the same points."""
     import numpy as np
@@ -201,7 +246,7 @@ def main():
     ap.add_argument("--workload", default="ns", choices=["burgers", "ns", "ks", "heat"])
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-context", action="store_true", help="skip the FP32 and nested-autograd context runs")
+    ap.add_argument("--no-context", action="store_true", help="skip the FP32, nested-autograd and ensemble context runs")
     ap.add_argument("--copy-probe-mib", type=int, default=0, help="only run a plain device copy of this size")
     args = ap.parse_args()
 
@@ -267,6 +312,10 @@ def main():
         except RuntimeError as e:  # out of memory at large N is reported, not fatal
             out["nested_autograd_fp32"] = {"error": str(e)[:200]}
             torch.cuda.empty_cache()
+
+    if not args.no_context:
+        out["ensemble_burgers_64"] = ensemble(steps=5)
+        log(f"ensemble: {out['ensemble_burgers_64']}")
 
     if not args.no_cpu_baseline:
         cb, n_s, ref = cpu_baseline(prob)

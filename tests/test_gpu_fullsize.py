@@ -1,0 +1,113 @@
+"""Parity at the workloads' full shapes and point counts, in the launch
+configuration the benchmark uses.
+
+  Burgers  2-32x3-1,   N = 1024:    every output against the oracle.
+  NS       2-128x6-3,  N = 65536:   every residual, the loss and the full gradient.
+  KS       2-256x8-1,  N = 131072:  residuals at 2048 sampled points (the oracle
+                                    evaluates points independently), gradient on
+                                    the first 8192 points.
+  Heat     4-512x8-1,  N = 262144,  BF16 under an 8 GiB cap on saved state:
+                                    residuals at 1024 sampled points, loss checked
+                                    against the mean of r^2, gradient of the
+                                    same capped plan on the first 2048 points.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import pinn_inputs as pi
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+BF16 = {"r": 2e-2, "grad": 5e-2}
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_29702_amd as pj
+    return pj
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def flat(grads):
+    return np.concatenate([np.concatenate([dW.double().cpu().numpy().ravel(), db.double().cpu().numpy().ravel()])
+                           for dW, db in grads])
+
+
+def run(lib, prob, prec, n=None, cap=0):
+    wl = prob.workload
+    x_np = prob.x if n is None else prob.x[:n]
+    N = x_np.shape[0]
+    plan = lib.PinnPlan(wl.dims, wl.pde, N, precision=prec, coef=prob.coef, save_cap_bytes=cap)
+    params = [(torch.tensor(W, device="cuda"), torch.tensor(b, device="cuda")) for W, b in prob.params]
+    x = torch.tensor(x_np, device="cuda")
+    r, loss, _, _ = plan.residual(params, x)
+    g = plan.backward(params, x)
+    torch.cuda.synchronize()
+    saved, _ = plan.memory()
+    out = r.cpu().numpy(), float(loss), flat(g), saved
+    plan.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_burgers_full(lib, prec):
+    prob = pi.make_problem("burgers")
+    r, loss, g, _ = run(lib, prob, prec)
+    ref = oracle.evaluate(prob.params, prob.x, prob.channels, "burgers", prob.coef)
+    tol_r, tol_g = (FP32_TOL, FP32_TOL) if prec == "fp32" else (BF16["r"], BF16["grad"])
+    print(prec, "burgers", rel(r, ref.r), rel(g, ref.grad))
+    assert rel(r, ref.r) <= tol_r and rel(g, ref.grad) <= tol_g
+    assert abs(loss - ref.loss) <= max(tol_r, 1e-6) * ref.loss * 4
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_ns_full(lib, prec):
+    prob = pi.make_problem("ns")
+    r, loss, g, _ = run(lib, prob, prec)
+    ref = oracle.evaluate(prob.params, prob.x, prob.channels, "ns", prob.coef)
+    tol_r, tol_g = (FP32_TOL, FP32_TOL) if prec == "fp32" else (BF16["r"], BF16["grad"])
+    print(prec, "ns", rel(r, ref.r), rel(g, ref.grad), abs(loss - ref.loss) / ref.loss)
+    assert rel(r, ref.r) <= tol_r and rel(g, ref.grad) <= tol_g
+    assert abs(loss - ref.loss) <= 2 * tol_r * ref.loss
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_ks_full(lib, prec):
+    prob = pi.make_problem("ks")
+    r, loss, _, _ = run(lib, prob, prec)
+    idx = np.sort(np.random.default_rng(1).choice(prob.x.shape[0], 2048, replace=False))
+    ref = oracle.evaluate(prob.params, prob.x[idx], prob.channels, "ks", prob.coef, want_grad=False)
+    tol_r, tol_g = (FP32_TOL, FP32_TOL) if prec == "fp32" else (BF16["r"], BF16["grad"])
+    assert rel(r[:, idx], ref.r) <= tol_r
+    # loss over all points from the GPU residuals
+    assert abs(loss - float(np.mean(r.astype(np.float64) ** 2))) <= 1e-5 * loss
+    _, _, g, _ = run(lib, prob, prec, n=8192)
+    refg = oracle.evaluate(prob.params, prob.x[:8192], prob.channels, "ks", prob.coef)
+    print(prec, "ks", rel(r[:, idx], ref.r), rel(g, refg.grad))
+    assert rel(g, refg.grad) <= tol_g
+
+
+def test_heat_full_under_cap(lib):
+    prob = pi.make_problem("heat")
+    cap = 8 << 30
+    r, loss, _, saved = run(lib, prob, "bf16", cap=cap)
+    assert saved <= cap
+    idx = np.sort(np.random.default_rng(2).choice(prob.x.shape[0], 1024, replace=False))
+    ref = oracle.evaluate(prob.params, prob.x[idx], prob.channels, "heat", prob.coef, want_grad=False)
+    assert rel(r[:, idx], ref.r) <= BF16["r"]
+    assert abs(loss - float(np.mean(r.astype(np.float64) ** 2))) <= 1e-5 * loss
+    # the capped plan's gradient on a sub-batch (cap scaled with the point count
+    # so that the same checkpoint schedule is used)
+    n = 2048
+    _, _, g, _ = run(lib, prob, "bf16", n=n, cap=cap * n // prob.x.shape[0])
+    refg = oracle.evaluate(prob.params, prob.x[:n], prob.channels, "heat", prob.coef)
+    print("heat", rel(r[:, idx], ref.r), rel(g, refg.grad))
+    assert rel(g, refg.grad) <= BF16["grad"]
