@@ -36,6 +36,37 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def source_hash():
+    """Hash of the HIP library sources, to tie counter figures to the kernels they measured."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2606_29702_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(workload, prec, kernel_class):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when
+    there is none for this workload or the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_{prec}_hbm_bytes.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if " = " in line:
+                k, v = line.strip().split(" = ", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != source_hash() or kernel_class not in vals:
+        return None
+    return float(vals[kernel_class])
+
+
 def copy_probe(mib):
     """A plain device copy of known size (calibration of the HBM byte counters)."""
     import torch
@@ -279,8 +310,13 @@ def main():
     if dom in GEMM_CLASSES:
         flops = 2.0 * w * w * C * N  # one stacked-channel w x w GEMM over N points
         achieved = flops / (main_run["dominant_avg_ms"] * 1e-3) / 1e12
+        traffic = profiled_traffic(args.workload, args.precision, dom)
         roof = dict(bound="mfma", achieved=round(achieved, 3), peak=PEAK[args.precision], unit="TFLOP/s",
-                    frac=round(achieved / PEAK[args.precision], 5), traffic=None, kernel=dom,
+                    frac=round(achieved / PEAK[args.precision], 5),
+                    traffic=None if traffic is None else round(traffic),
+                    traffic_unit="bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+                    achieved_hbm_GBps=None if traffic is None else
+                    round(traffic / (main_run["dominant_avg_ms"] * 1e-3) / 1e9, 1), kernel=dom,
                     avg_launch_us=round(main_run["dominant_avg_ms"] * 1e3, 2),
                     launches=main_run["dominant_launches"])
     else:
