@@ -103,6 +103,8 @@ def time_path(prob, prec, steps, warmup, profile_dominant=True):
         plan.residual(params, x)
         plan.backward(params, x)
 
+    # the library's autotuner picks split-K, forward tiling and backward variant
+    tuning, tuned_ms = plan.autotune(params, x, reps=3)
     # warmup; one profiled step per kernel class to find the dominant class
     class_ms = {}
     for i in range(max(warmup, 1)):
@@ -130,7 +132,7 @@ def time_path(prob, prec, steps, warmup, profile_dominant=True):
     plan.profile("off")
     plan.close()
     return dict(ms_per_step=(t1 - t0) * 1e3 / steps, class_ms=class_ms, dominant=dominant,
-                dominant_avg_ms=dom_ms / max(dom_n, 1), dominant_launches=dom_n)
+                dominant_avg_ms=dom_ms / max(dom_n, 1), dominant_launches=dom_n, tuning=tuning)
 
 
 def nested_autograd_fp32(prob, steps):
@@ -332,6 +334,7 @@ def main():
                    "coef": list(prob.coef), "step": "forward jets + residual + MSE loss + dtheta"},
         "roofline": roof,
         "kernel_ms_per_step": {k: round(v[0], 4) for k, v in main_run["class_ms"].items()},
+        "tuning": main_run["tuning"],
     }
 
     if not args.no_context:

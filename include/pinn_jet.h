@@ -158,10 +158,14 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
  *   dw_splits   number of split-K partials of each hidden-layer weight gradient
  *               (1 .. twice the plan's default)
  *   fwd_points  points per workgroup of the whole-network forward kernel
- *               (0 = the largest tiling whose stack fits in LDS, else 16 or 32) */
+ *               (0 = the largest tiling whose stack fits in LDS, else 16 or 32)
+ *   bwd_fused   1: hidden-layer weight gradients are accumulated inside the
+ *               persistent backward layer kernels where the width allows
+ *               (32, 64, 128); 0 (default): separate split-K gradient kernels */
 typedef struct {
   int32_t dw_splits;
   int32_t fwd_points;
+  int32_t bwd_fused;
 } pinn_tuning;
 pinn_status pinn_plan_get_tuning(pinn_plan plan, pinn_tuning *tuning);
 pinn_status pinn_plan_set_tuning(pinn_plan plan, const pinn_tuning *tuning);

@@ -1,0 +1,314 @@
+// Persistent backward layer kernel with the hidden-layer weight gradient fused
+// in.  For activation layer m it produces, per block of 16 points,
+//   abar_m   = W_{m+1}^T Zbar_{m+1}      (MFMA; or W_L^T ubar at the top)
+//   z_m      = saved state, or W_m A_{m-1} + b_m recomputed on MFMA
+//   Zbar_m   = jet_adjoint(abar_m, z_m)
+// and accumulates dW_m += Zbar_m^T A_{m-1} and db_m += sum of the value rows
+// of Zbar_m over all the blocks it processes, in registers.  Each workgroup
+// loops over blocks of points and writes one partial dW_m, db_m at the end;
+// the partials are summed in workgroup order by the reduction kernel.
+//
+// Both operands of the gradient are already in LDS: the previous stack A_{m-1}
+// is staged for the recompute, and Zbar_m is written back into the LDS tile
+// that held Zbar_{m+1} once the abar GEMM has consumed it.  The gradient
+// contracts over the rows (point, channel) of the tile, 16 at a time
+// (MFMA 16x16x16), with each lane gathering its 4 rows down a column.
+#include "dev_common.hpp"
+#include "kernels.hpp"
+
+namespace pj {
+
+typedef __bf16 bf16x4v __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4v __attribute__((ext_vector_type(4)));
+
+// MFMA with a 16-long contraction: lane l supplies the 4 consecutive
+// contraction elements 4*(l/16) .. 4*(l/16)+3 of row (l%16) of A and of
+// column (l%16) of B.
+template <class T>
+struct Mma16;
+template <>
+struct Mma16<bf16_t> {
+  using frag = bf16x4v;
+  static __device__ __forceinline__ void mma(f32x4 &acc, const frag &a, const frag &b) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+  }
+};
+template <>
+struct Mma16<f16_t> {
+  using frag = f16x4v;
+  static __device__ __forceinline__ void mma(f32x4 &acc, const frag &a, const frag &b) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc, 0, 0, 0);
+  }
+};
+// FP32: four 16x16x4 MFMAs; MFMA e pairs element e of every lane's fragments,
+// so lane group g covers contraction indices 4g + e on both sides.
+template <>
+struct Mma16<float> {
+  using frag = f32x4;
+  static __device__ __forceinline__ void mma(f32x4 &acc, const frag &a, const frag &b) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b[e], acc, 0, 0, 0);
+  }
+};
+
+template <class T>
+__device__ __forceinline__ void stage_rows(T *dst, const T *src, int P, int rowlen, int pitch, int tid, int nt) {
+  const int per_pt = rowlen / 8;
+  for (int q = tid; q < P * per_pt; q += nt) {
+    const int pp = q / per_pt, off = (q % per_pt) * 8;
+    const uint4 *s = reinterpret_cast<const uint4 *>(src + (int64_t)pp * rowlen + off);
+    uint4 *d = reinterpret_cast<uint4 *>(dst + pp * pitch + off);
+    if constexpr (sizeof(T) == 2) {
+      *d = *s;
+    } else {
+      d[0] = s[0];
+      d[1] = s[1];
+    }
+  }
+}
+
+template <class T, int C, int TPW>
+__device__ __forceinline__ void tile_gemm(f32x4 (&acc)[TPW][C], const T *__restrict__ Wop, const T *stk, int pitch,
+                                          int jt0, int w, int lane) {
+  using M = Mma<T>;
+  const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int t = 0; t < TPW; ++t)
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const T *wrow = Wop + (int64_t)(jt0 * 16 + r) * w + 8 * g;
+  const T *brow = stk + r * pitch + 8 * g;
+  typename M::frag fa[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) fa[t] = M::load(wrow + (int64_t)t * 16 * w);
+  for (int k = 0; k < w; k += 32) {
+    typename M::frag fb[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) fb[c] = M::load(brow + c * w + k);
+    typename M::frag fn[TPW];
+    const int kn = k + 32 < w ? k + 32 : k;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) fn[t] = M::load(wrow + (int64_t)t * 16 * w + kn);
+#pragma unroll
+    for (int t = 0; t < TPW; ++t)
+#pragma unroll
+      for (int c = 0; c < C; ++c) M::mma(acc[t][c], fa[t], fb[c]);
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) fa[t] = fn[t];
+  }
+}
+
+template <class CH, class T, int W, int NW, int TPW, bool TOP, int DOUT, int ZSRC>
+__global__ __launch_bounds__(NW * 64) void k_bwd_dw(BwdArgs args, float *__restrict__ part, int64_t n_tiles) {
+  using M16 = Mma16<T>;
+  constexpr int C = CH::C, P = 16;
+  constexpr bool FAST = sizeof(T) == 2;
+  constexpr int pitch = C * W + 8;
+  constexpr int JW = W / NW;      // gradient rows owned by one wave
+  constexpr int JT = JW / 16, KT = W / 16;
+  constexpr int ROWS = P * C;     // contraction rows per tile (multiple of 16)
+  static_assert(JW % 16 == 0 && ROWS % 16 == 0, "tile shape");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *lds_b = reinterpret_cast<T *>(smem_raw);  // Zbar_{m+1}, then Zbar_m
+  T *lds_a = lds_b + P * pitch;                // A_{m-1}
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  constexpr int64_t ps = (int64_t)C * W;
+  const int jt0 = wave * TPW;  // neuron tiles of this wave in the layer GEMMs (one 16-point tile)
+
+  f32x4 dacc[JT][KT];
+#pragma unroll
+  for (int a = 0; a < JT; ++a)
+#pragma unroll
+    for (int b = 0; b < KT; ++b) dacc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float db = 0.f;
+
+  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const int64_t nb = tile * P;
+    if constexpr (!TOP) stage_rows<T>(lds_b, static_cast<const T *>(args.Zb_in) + nb * ps, P, C * W, pitch, tid, NW * 64);
+    stage_rows<T>(lds_a, static_cast<const T *>(args.A_prev) + nb * ps, P, C * W, pitch, tid, NW * 64);
+    __syncthreads();
+
+    f32x4 acc_a[TPW][C];
+    if constexpr (!TOP) tile_gemm<T, C, TPW>(acc_a, static_cast<const T *>(args.WT), lds_b, pitch, jt0, W, lane);
+    f32x4 acc_z[TPW][C];
+    if constexpr (ZSRC == Z_FROM_GEMM)
+      tile_gemm<T, C, TPW>(acc_z, static_cast<const T *>(args.Wz), lds_a, pitch, jt0, W, lane);
+    __syncthreads();  // the Zbar_{m+1} tile is consumed; it now receives Zbar_m
+
+    const int64_t n = nb + r;
+    T *Zb_out = static_cast<T *>(args.Zb_out);
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int mb = (jt0 + t) * 16 + 4 * g;
+      float zz[4][C], s1[4];
+      if constexpr (ZSRC == Z_FROM_S) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const f32x4 v = *reinterpret_cast<const f32x4 *>(args.S_in + n * ps + c * W + mb);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) zz[i][c] = v[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s1[i] = (1.f - zz[i][0]) * (1.f + zz[i][0]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+          for (int c = 0; c < C; ++c) zz[i][c] = acc_z[t][c][i];
+          const TanhS ts = tanh_eval<FAST>(zz[i][0] + args.bz[mb + i]);
+          zz[i][0] = ts.s;
+          s1[i] = ts.s1;
+        }
+      }
+      float ab[4][C];
+      if constexpr (TOP) {
+        float ub[DOUT][C];
+#pragma unroll
+        for (int o = 0; o < DOUT; ++o)
+#pragma unroll
+          for (int c = 0; c < C; ++c) ub[o][c] = args.ubar[(n * DOUT + o) * C + c];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            float sacc = 0.f;
+#pragma unroll
+            for (int o = 0; o < DOUT; ++o) sacc += args.WL[o * W + mb + i] * ub[o][c];
+            ab[i][c] = sacc;
+          }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int c = 0; c < C; ++c) ab[i][c] = acc_a[t][c][i];
+      }
+      float out[4][C];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float zb[C];
+        jet_adjoint<CH>(ab[i], zz[i][0], s1[i], zz[i], zb);
+#pragma unroll
+        for (int c = 0; c < C; ++c) out[i][c] = zb[c];
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        store4(Zb_out + n * ps + c * W + mb, out[0][c], out[1][c], out[2][c], out[3][c]);
+        store4(lds_b + r * pitch + c * W + mb, out[0][c], out[1][c], out[2][c], out[3][c]);
+      }
+    }
+    __syncthreads();  // Zbar_m tile complete in LDS
+
+    // db_m: value rows (channel 0) of the tile
+    if (tid < W) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) db += to_f32(lds_b[p * pitch + tid]);
+    }
+    // dW_m += Zbar_m^T A_{m-1} over the tile's rows (point, channel)
+#pragma unroll
+    for (int s = 0; s < ROWS / 16; ++s) {
+      int off[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = 16 * s + 4 * g + e;
+        off[e] = (row / C) * pitch + (row % C) * W;
+      }
+      typename M16::frag fa[JT], fb[KT];
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt) {
+        const int j = wave * JW + jt * 16 + r;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) fa[jt][e] = lds_b[off[e] + j];
+      }
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt) {
+        const int k = kt * 16 + r;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) fb[kt][e] = lds_a[off[e] + k];
+      }
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt)
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) M16::mma(dacc[jt][kt], fa[jt], fb[kt]);
+    }
+    __syncthreads();  // before the next tile is staged over both buffers
+  }
+
+  float *pp = part + (int64_t)blockIdx.x * ((int64_t)W * W + W);
+#pragma unroll
+  for (int jt = 0; jt < JT; ++jt)
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int j = wave * JW + jt * 16 + 4 * g + i;
+        const int k = kt * 16 + r;
+        pp[(int64_t)j * W + k] = dacc[jt][kt][i];
+      }
+  if (tid < W) pp[(int64_t)W * W + tid] = db;
+}
+
+namespace {
+
+template <class CH, class T, int W, bool TOP, int DOUT, int ZSRC>
+hipError_t launch_w(const BwdArgs &a, float *part, int64_t n_tiles, int grid, hipStream_t st) {
+  constexpr int NW = W == 32 ? 2 : (W == 256 ? 8 : 4);
+  constexpr int TPW = (W / 16) / NW;
+  constexpr size_t lds = (size_t)2 * 16 * (CH::C * W + 8) * sizeof(T);
+  auto kfn = k_bwd_dw<CH, T, W, NW, TPW, TOP, DOUT, ZSRC>;
+  hipError_t e = hipFuncSetAttribute((const void *)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kfn, dim3((unsigned)grid), dim3(NW * 64), lds, st, a, part, n_tiles);
+  return hipGetLastError();
+}
+
+template <class PDE, class T>
+hipError_t launch_kind(const BwdArgs &a, bool top, int zsrc, float *part, int64_t n_tiles, int grid,
+                       hipStream_t st) {
+  using CH = typename PDE::CH;
+  constexpr int DO = PDE::DOUT;
+#define PJ_W(WV)                                                                                    \
+  if (a.w == WV) {                                                                                  \
+    if (top)                                                                                        \
+      return zsrc == Z_FROM_S ? launch_w<CH, T, WV, true, DO, Z_FROM_S>(a, part, n_tiles, grid, st)  \
+                              : launch_w<CH, T, WV, true, DO, Z_FROM_GEMM>(a, part, n_tiles, grid, st); \
+    return zsrc == Z_FROM_S ? launch_w<CH, T, WV, false, DO, Z_FROM_S>(a, part, n_tiles, grid, st)   \
+                            : launch_w<CH, T, WV, false, DO, Z_FROM_GEMM>(a, part, n_tiles, grid, st); \
+  }
+  PJ_W(32) PJ_W(64) PJ_W(128)
+#undef PJ_W
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool bwd_dw_fused_supported(int C, int w, int prec) {
+  if (w != 32 && w != 64 && w != 128) return false;
+  const size_t lds = (size_t)2 * 16 * (C * w + 8) * op_size(prec);
+  return lds <= 100 * 1024;
+}
+
+hipError_t launch_bwd_dw(int kind, int prec, const LayerBwd &L, float *part, int64_t N_pad, int grid,
+                         hipStream_t st) {
+  BwdArgs a{L.Zb_in, L.WT, L.ubar, L.WL, L.S_in, L.A_prev, L.Wz, L.bz, L.x, L.W1, L.N, L.Zb_out, L.w};
+  const int zsrc = L.S_in ? Z_FROM_S : Z_FROM_GEMM;
+  const int64_t n_tiles = N_pad / 16;
+  auto by_prec = [&](auto pde) -> hipError_t {
+    using PDE = decltype(pde);
+    switch (prec) {
+      case P_FP32: return launch_kind<PDE, float>(a, L.top, zsrc, part, n_tiles, grid, st);
+      case P_BF16: return launch_kind<PDE, bf16_t>(a, L.top, zsrc, part, n_tiles, grid, st);
+      case P_FP16: return launch_kind<PDE, f16_t>(a, L.top, zsrc, part, n_tiles, grid, st);
+      default: return hipErrorInvalidValue;
+    }
+  };
+  switch (kind) {
+    case K_BURGERS: return by_prec(PdeBurgers{});
+    case K_NS: return by_prec(PdeNS{});
+    case K_KS: return by_prec(PdeKS{});
+    case K_HEAT: return by_prec(PdeHeat{});
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace pj

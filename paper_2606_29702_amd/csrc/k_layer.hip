@@ -110,24 +110,6 @@ __global__ __launch_bounds__(256) void k_layer_fwd(const T *__restrict__ A_in, c
 //         = W_{l-1} A_{l-2} + b_{l-1} (MFMA recompute) ZSRC == Z_FROM_GEMM
 //         = W_1 x + b_1 with the input seeds         ZSRC == Z_FROM_X
 //   Zbar_{l-1} = jet_adjoint(abar, z).
-enum { Z_FROM_S = 0, Z_FROM_GEMM = 1, Z_FROM_X = 2 };
-
-struct BwdArgs {
-  const void *Zb_in;   // [N_pad][C][w] operand type (!TOP)
-  const void *WT;      // [w][w] transpose of W_l, operand type (!TOP)
-  const float *ubar;   // [N_pad][DOUT][C] (TOP)
-  const float *WL;     // [DOUT][w] (TOP)
-  const float *S_in;   // [N_pad][C][w] (Z_FROM_S)
-  const void *A_prev;  // [N_pad][C][w] operand type (Z_FROM_GEMM)
-  const void *Wz;      // [w][w] operand type (Z_FROM_GEMM)
-  const float *bz;     // [w] (Z_FROM_GEMM, Z_FROM_X)
-  const float *x;      // [N][DIN] (Z_FROM_X)
-  const float *W1;     // [w][DIN] (Z_FROM_X)
-  int64_t N;
-  void *Zb_out;        // [N_pad][C][w] operand type
-  int w;
-};
-
 template <class CH, class T, int WJ, int NTN, bool TOP, int DOUT, int ZSRC>
 __global__ __launch_bounds__(256) void k_layer_bwd(BwdArgs args) {
   constexpr int C = CH::C, D = CH::DIN;

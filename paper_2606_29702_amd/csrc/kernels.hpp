@@ -66,6 +66,34 @@ struct LayerBwd {
 };
 hipError_t launch_layer_bwd(int kind, int prec, const LayerBwd &L, int64_t N_pad, hipStream_t st);
 
+// Kernel-side argument block of the backward layer kernels.
+enum { Z_FROM_S = 0, Z_FROM_GEMM = 1, Z_FROM_X = 2 };
+
+struct BwdArgs {
+  const void *Zb_in;   // [N_pad][C][w] operand type (!TOP)
+  const void *WT;      // [w][w] transpose of W_l, operand type (!TOP)
+  const float *ubar;   // [N_pad][DOUT][C] (TOP)
+  const float *WL;     // [DOUT][w] (TOP)
+  const float *S_in;   // [N_pad][C][w] (Z_FROM_S)
+  const void *A_prev;  // [N_pad][C][w] operand type (Z_FROM_GEMM)
+  const void *Wz;      // [w][w] operand type (Z_FROM_GEMM)
+  const float *bz;     // [w] (Z_FROM_GEMM, Z_FROM_X)
+  const float *x;      // [N][DIN] (Z_FROM_X)
+  const float *W1;     // [w][DIN] (Z_FROM_X)
+  int64_t N;
+  void *Zb_out;        // [N_pad][C][w] operand type
+  int w;
+};
+
+
+// Persistent backward layer kernel with the weight gradient of the layer it
+// produces fused in (k_bwd_fused.hip).  Needs L.A_prev (the previous stack)
+// even when L.S_in is given.  Writes `grid` partials part[g][w*w + w]
+// (dW row-major, then db), summed by launch_reduce_parts2.
+bool bwd_dw_fused_supported(int C, int w, int prec);
+hipError_t launch_bwd_dw(int kind, int prec, const LayerBwd &L, float *part, int64_t N_pad, int grid,
+                         hipStream_t st);
+
 // Whole-network forward pass for blocks of P points (k_fused_fwd.hip): seed
 // layer, hidden layers, output layer, residual and one loss partial per block.
 // Arrays are indexed by the 1-based layer number.  A[l], S[l], u_save,

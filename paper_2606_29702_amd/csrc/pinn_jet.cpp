@@ -124,6 +124,7 @@ struct pinn_plan_s {
   int dw_splits = 1, thin_chunks = 1;
   int dw_splits_max = 1;   // partial buffer capacity (autotune candidates stay below it)
   int fwd_points = 0;      // fused forward points per workgroup; 0 = largest that fits
+  int bwd_fused = 0;       // weight gradients inside the backward layer kernels when supported
   std::vector<void *> allocs;
   size_t saved_bytes = 0, ws_bytes = 0;
 
@@ -638,6 +639,68 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
     }
     return PINN_OK;
   };
+  const bool fused = p->bwd_fused && H >= 2 && pj::bwd_dw_fused_supported(ki.C, w, p->prec);
+  if (fused) {
+    // Each backward layer kernel also produces the weight gradient of the
+    // layer whose zbar it computes: dW_m from zbar_m and the stack of m - 1.
+    const int grid = (int)std::min<int64_t>(std::min<int64_t>(npad / 16, p->dw_splits_max), 512);
+    e = timed(p, PINN_K_OUT_BWD, s, [&] { return pj::launch_out_adj(p->kind, p->u_save, p->r_save, r_bar, N, npad, (float)(2.0 / (double)N), coef_of(pde), p->ubar, s); });
+    if (e) return hip_fail(e, "output adjoint");
+    auto layer = [&](pj::LayerBwd &B, int m, int cls) -> pinn_status {
+      const void *Am1 = nullptr;
+      pinn_status r2 = backward_stack(p, net, x, N, npad, m - 1, &Am1, s);
+      if (r2) return r2;
+      B.A_prev = Am1;
+      if (p->store_S) {
+        B.S_in = p->S[m];
+      } else {
+        B.Wz = p->Wop[m];
+        B.bz = net->b[m - 1];
+      }
+      B.N = N;
+      B.w = w;
+      B.Zb_out = p->Zb[m % 2];
+      hipError_t e2 = timed(p, cls, s, [&] { return pj::launch_bwd_dw(p->kind, p->prec, B, p->part, npad, grid, s); });
+      if (e2) return hip_fail(e2, "backward layer");
+      e2 = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, grid, (int64_t)w * w + w, (int64_t)w * w, w, dW[m - 1], db[m - 1], f64(dW_f64, m - 1), f64(db_f64, m - 1), s); });
+      return e2 ? hip_fail(e2, "reduction") : PINN_OK;
+    };
+    {
+      pj::LayerBwd B{};
+      B.top = true;
+      B.ubar = p->ubar;
+      B.WL = net->W[L - 1];
+      rs = layer(B, H, PINN_K_OUT_BWD);
+      if (rs) return rs;
+    }
+    const void *AH = nullptr;
+    rs = backward_stack(p, net, x, N, npad, H, &AH, s);
+    if (rs) return rs;
+    e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_dw_out(p->kind, p->prec, p->ubar, AH, npad, w, p->part, p->thin_chunks, s); });
+    if (e) return hip_fail(e, "output-layer gradient");
+    e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, p->thin_chunks, (int64_t)ki.dout * w + ki.dout, (int64_t)ki.dout * w, ki.dout, dW[L - 1], db[L - 1], f64(dW_f64, L - 1), f64(db_f64, L - 1), s); });
+    if (e) return hip_fail(e, "reduction");
+    for (int l = H; l >= 3; --l) {
+      pj::LayerBwd B{};
+      B.top = false;
+      B.Zb_in = p->Zb[l % 2];
+      B.WT = p->WTop[l];
+      rs = layer(B, l - 1, PINN_K_LAYER_BWD);
+      if (rs) return rs;
+    }
+    // zbar of layer 1 (its z comes from x; its gradient is the thin seed kernel's)
+    pj::LayerBwd B{};
+    B.top = false;
+    B.Zb_in = p->Zb[0];
+    B.WT = p->WTop[2];
+    B.N = N;
+    B.w = w;
+    B.Zb_out = p->Zb[1];
+    rs = zsrc(B, 1);
+    if (rs) return rs;
+    e = timed(p, PINN_K_LAYER_BWD, s, [&] { return pj::launch_layer_bwd(p->kind, p->prec, B, npad, s); });
+    if (e) return hip_fail(e, "hidden adjoint");
+  } else {
   // Output layer: ubar, then zbar of layer H, then dW_L, db_L.
   e = timed(p, PINN_K_OUT_BWD, s, [&] { return pj::launch_out_adj(p->kind, p->u_save, p->r_save, r_bar, N, npad, (float)(2.0 / (double)N), coef_of(pde), p->ubar, s); });
   if (e) return hip_fail(e, "output adjoint");
@@ -686,6 +749,7 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
     e = timed(p, PINN_K_LAYER_BWD, s, [&] { return pj::launch_layer_bwd(p->kind, p->prec, B, npad, s); });
     if (e) return hip_fail(e, "hidden adjoint");
   }
+  }
   // First layer.
   e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_dw_seed(p->kind, p->prec, p->Zb[1], x, N, npad, w, p->part, p->thin_chunks, s); });
   if (e) return hip_fail(e, "first-layer gradient");
@@ -701,6 +765,7 @@ pinn_status pinn_plan_get_tuning(pinn_plan plan, pinn_tuning *t) {
   if (!plan || !t) return fail(PINN_ERR_ARG, "plan or tuning is NULL");
   t->dw_splits = plan->dw_splits;
   t->fwd_points = plan->fwd_points;
+  t->bwd_fused = plan->bwd_fused;
   return PINN_OK;
 }
 
@@ -711,8 +776,10 @@ pinn_status pinn_plan_set_tuning(pinn_plan plan, const pinn_tuning *t) {
     return fail(PINN_ERR_ARG, "dw_splits = %d outside [1, %d]", t->dw_splits, plan->dw_splits_max);
   if (t->fwd_points != 0 && !pj::fused_fwd_fits(t->fwd_points, plan->ki.C, plan->w, plan->prec))
     return fail(PINN_ERR_ARG, "fwd_points = %d has no fused forward tiling at this width", t->fwd_points);
+  if (t->bwd_fused != 0 && t->bwd_fused != 1) return fail(PINN_ERR_ARG, "bwd_fused must be 0 or 1");
   plan->dw_splits = t->dw_splits;
   plan->fwd_points = t->fwd_points;
+  plan->bwd_fused = t->bwd_fused;
   plan->have_state = false;
   return PINN_OK;
 }
@@ -751,15 +818,18 @@ pinn_status pinn_plan_autotune(pinn_plan plan, const pinn_net *net, const pinn_p
     cleanup();
     return hip_fail(e, "autotune setup");
   }
-  const pinn_tuning orig{p->dw_splits, p->fwd_points};
+  const pinn_tuning orig{p->dw_splits, p->fwd_points, p->bwd_fused};
   const int s0 = dw_splits_for(round_up(N, pj::kPointTile), p->ki.C, p->w);
   std::vector<pinn_tuning> cand;
+  const bool can_fuse = pj::bwd_dw_fused_supported(p->ki.C, p->w, p->prec);
   for (int sp : {std::max(1, s0 / 2), s0, std::min(p->dw_splits_max, 2 * s0)})
-    for (int fp : {0, 16}) {
+    for (int fp : {0, 16})
+    for (int bf : {0, 1}) {
       if (fp == 16 && (!pj::fused_fwd_fits(16, p->ki.C, p->w, p->prec) ||
                        pj::fused_fwd_points(p->ki.C, p->w, p->prec) == 16))
         continue;
-      pinn_tuning t{sp, fp};
+      if (bf == 1 && !can_fuse) continue;
+      pinn_tuning t{sp, fp, bf};
       bool dup = false;
       for (auto &c : cand) dup = dup || (c.dw_splits == t.dw_splits && c.fwd_points == t.fwd_points);
       if (!dup) cand.push_back(t);
@@ -769,6 +839,7 @@ pinn_status pinn_plan_autotune(pinn_plan plan, const pinn_net *net, const pinn_p
   for (const pinn_tuning &c : cand) {
     p->dw_splits = c.dw_splits;
     p->fwd_points = c.fwd_points;
+    p->bwd_fused = c.bwd_fused;
     for (int it = -1; it < reps && st == PINN_OK; ++it) {
       if (it == 0) e = hipEventRecord(t0, s);
       st = pinn_jet_residual(p, net, pde, x, N, nullptr, nullptr, nullptr, nullptr, stream);
@@ -791,6 +862,7 @@ pinn_status pinn_plan_autotune(pinn_plan plan, const pinn_net *net, const pinn_p
   if (e != hipSuccess) return hip_fail(e, "autotune timing");
   p->dw_splits = bt.dw_splits;
   p->fwd_points = bt.fwd_points;
+  p->bwd_fused = bt.bwd_fused;
   p->have_state = false;
   if (best) *best = bt;
   if (best_ms) *best_ms = bms;

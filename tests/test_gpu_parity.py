@@ -264,3 +264,30 @@ def test_cap_below_one_stack_is_rejected(lib):
     with pytest.raises(PinnError) as e:
         lib.PinnPlan([2, 64, 64, 3], "ns", 1000, precision="bf16", save_cap_bytes=1000)
     assert e.value.status == -6
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("pde,dims", [("ns", [2, 128, 128, 128, 128, 3]), ("burgers", [2, 32, 32, 32, 32, 1]),
+                                      ("heat", [4, 64, 64, 64, 1])])
+def test_fused_and_separate_weight_gradients_agree(lib, pde, dims, prec):
+    """Weight gradients accumulated inside the persistent backward kernels and
+    those of the separate split-K kernels agree to rounding and with the oracle."""
+    prob = pi.make_problem(pde, N=777, seed=31, bias_std=0.3, dims=dims)
+    params = dev_params(prob.params)
+    x = torch.tensor(prob.x, device="cuda")
+    gs = []
+    for fused in (1, 0):
+        plan = lib.PinnPlan(dims, pde, 777, precision=prec, coef=prob.coef)
+        t = plan.tuning()
+        plan.set_tuning(t["dw_splits"], 0, fused)
+        plan.residual(params, x)
+        gs.append(flat(plan.backward(params, x)))
+        plan.close()
+    ref = oracle.evaluate(prob.params, prob.x, prob.channels, pde, prob.coef)
+    # BF16: the measured ceiling of deep Burgers networks (cf. the ensemble test)
+    tol = FP32_TOL if prec == "fp32" else 0.2
+    for g in gs:
+        cos = float(g @ ref.grad / (np.linalg.norm(g) * np.linalg.norm(ref.grad)))
+        print(pde, prec, f"grad rel {rel(g, ref.grad):.2e} cos {cos:.6f}")
+        assert rel(g, ref.grad) <= tol and cos > 0.99
+    assert rel(gs[0], gs[1]) <= (2e-6 if prec == "fp32" else 2e-2)
