@@ -14,14 +14,14 @@
 
 namespace pj {
 
-template <class T, int TILE>
+template <class T, int TILE, int RC>
 struct DwLayout {
   // Row pitch in elements: rows stay 8-byte aligned and rows 8 apart fall
   // 16 banks apart, so the four lane groups of a column gather do not collide.
   static constexpr int pitch = TILE + 8 / (int)sizeof(T);
-  static constexpr int tile_elems = 32 * pitch;
+  static constexpr int tile_elems = RC * pitch;         // RC rows staged per chunk
   static constexpr int per_row = TILE / 8;              // 8-element copies per row
-  static constexpr int copies = 32 * per_row;           // per operand per chunk
+  static constexpr int copies = RC * per_row;           // per operand per chunk
   static constexpr int per_thread = (copies + 255) / 256;
   static constexpr int words = (int)sizeof(T);          // 8-byte words per copy
 };
@@ -54,15 +54,15 @@ __device__ __forceinline__ Mma<float>::frag gather_col<float>(const float *p, in
   return f;
 }
 
-template <class T, int TILE>
+template <class T, int TILE, int RC>
 __global__ __launch_bounds__(256) void k_dw_hidden(const T *__restrict__ Zb, const T *__restrict__ A,
                                                    int64_t rows_total, int64_t rows_per_split, int w,
                                                    int C, float *__restrict__ part,
                                                    float *__restrict__ part_db) {
   // Workgroup tile: TILE x TILE of dW; wave (wj, wk) owns a (TILE/2)^2 quarter,
-  // i.e. NT x NT MFMA 16x16 tiles.
+  // i.e. NT x NT MFMA 16x16 tiles.  RC rows (a multiple of 32) are staged per chunk.
   using M = Mma<T>;
-  using LY = DwLayout<T, TILE>;
+  using LY = DwLayout<T, TILE, RC>;
   constexpr int P = LY::pitch;
   constexpr int NT = TILE / 32;
   constexpr int H = TILE / 2;
@@ -122,25 +122,30 @@ __global__ __launch_bounds__(256) void k_dw_hidden(const T *__restrict__ Zb, con
   }
   __syncthreads();
   int buf = 0;
-  for (int64_t r0 = rb; r0 < re; r0 += 32) {
-    const bool more = r0 + 32 < re;
-    if (more) fetch(r0 + 32);
+  for (int64_t r0 = rb; r0 < re; r0 += RC) {
+    const bool more = r0 + RC < re;
+    if (more) fetch(r0 + RC);
     const T *Zs = lds[buf][0];
     const T *As = lds[buf][1];
     if (do_db && t < TILE) {
       // rows r with r % C == 0 are value rows
       const int first = (int)((C - (r0 % C)) % C);
-      for (int rr = first; rr < 32; rr += C) db += to_f32(Zs[rr * P + t]);
+      for (int rr = first; rr < RC; rr += C) db += to_f32(Zs[rr * P + t]);
     }
-    typename M::frag fa[NT], fb[NT];
 #pragma unroll
-    for (int jt = 0; jt < NT; ++jt) fa[jt] = gather_col<T>(Zs + (8 * g) * P + H * wj + 16 * jt + r16, P);
+    for (int ks = 0; ks < RC / 32; ++ks) {
+      typename M::frag fa[NT], fb[NT];
 #pragma unroll
-    for (int kt = 0; kt < NT; ++kt) fb[kt] = gather_col<T>(As + (8 * g) * P + H * wk + 16 * kt + r16, P);
+      for (int jt = 0; jt < NT; ++jt)
+        fa[jt] = gather_col<T>(Zs + (32 * ks + 8 * g) * P + H * wj + 16 * jt + r16, P);
 #pragma unroll
-    for (int jt = 0; jt < NT; ++jt)
+      for (int kt = 0; kt < NT; ++kt)
+        fb[kt] = gather_col<T>(As + (32 * ks + 8 * g) * P + H * wk + 16 * kt + r16, P);
 #pragma unroll
-      for (int kt = 0; kt < NT; ++kt) M::mma(acc[jt][kt], fa[jt], fb[kt]);
+      for (int jt = 0; jt < NT; ++jt)
+#pragma unroll
+        for (int kt = 0; kt < NT; ++kt) M::mma(acc[jt][kt], fa[jt], fb[kt]);
+    }
     if (more) commit(buf ^ 1);
     __syncthreads();
     buf ^= 1;
@@ -168,12 +173,15 @@ void launch_dw_t(const T *Zb, const T *A, int64_t rows, int64_t rps, int w, int 
                  float *part_db, int splits, hipStream_t st) {
   const int tile = dw_tile(w);
   dim3 grid((unsigned)(w / tile), (unsigned)(w / tile), (unsigned)splits);
-  if (tile == 128)
-    hipLaunchKernelGGL((k_dw_hidden<T, 128>), grid, dim3(256), 0, st, Zb, A, rows, rps, w, C, part, part_db);
+  // 128-wide tiles stage 64 rows per chunk (more bytes in flight per workgroup)
+  if (tile == 128 && rps % 64 == 0)
+    hipLaunchKernelGGL((k_dw_hidden<T, 128, 64>), grid, dim3(256), 0, st, Zb, A, rows, rps, w, C, part, part_db);
+  else if (tile == 128)
+    hipLaunchKernelGGL((k_dw_hidden<T, 128, 32>), grid, dim3(256), 0, st, Zb, A, rows, rps, w, C, part, part_db);
   else if (tile == 64)
-    hipLaunchKernelGGL((k_dw_hidden<T, 64>), grid, dim3(256), 0, st, Zb, A, rows, rps, w, C, part, part_db);
+    hipLaunchKernelGGL((k_dw_hidden<T, 64, 32>), grid, dim3(256), 0, st, Zb, A, rows, rps, w, C, part, part_db);
   else
-    hipLaunchKernelGGL((k_dw_hidden<T, 32>), grid, dim3(256), 0, st, Zb, A, rows, rps, w, C, part, part_db);
+    hipLaunchKernelGGL((k_dw_hidden<T, 32, 32>), grid, dim3(256), 0, st, Zb, A, rows, rps, w, C, part, part_db);
 }
 }  // namespace
 

@@ -245,52 +245,73 @@ __global__ __launch_bounds__(256) void k_out_adj(const float *__restrict__ u_sav
 
 // ------------------------------------------------ thin gradient reductions
 // Output layer: dW_L[o][k] = sum_n sum_c ubar[n][o][c] a_H[n][c][k],
-// db_L[o] = sum_n ubar[n][o][0].  Workgroup = one chunk of points; thread
-// (sub, k) handles neuron k for the points sub, sub + NSUB, ... of the chunk
-// (NSUB = 256 / w sub-groups when w < 256); the sub-group sums are added in
-// sub order through LDS.
+// db_L[o] = sum_n ubar[n][o][0].  Workgroup = one chunk of points.  A row
+// (point, channel) of the stack is read by w/8 lanes, 8 neurons (16 bytes in
+// BF16/FP16) each; the 256 / (w/8) row groups stride over the chunk's rows and
+// their sums are added in group order through LDS.
+template <class T>
+__device__ __forceinline__ void load8f(const T *p, float (&v)[8]) {
+  if constexpr (sizeof(T) == 2) {
+    typedef T T8 __attribute__((ext_vector_type(8)));
+    const T8 q = *reinterpret_cast<const T8 *>(p);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = static_cast<float>(q[e]);
+  } else {
+    const f32x4 lo = reinterpret_cast<const f32x4 *>(p)[0], hi = reinterpret_cast<const f32x4 *>(p)[1];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      v[e] = lo[e];
+      v[e + 4] = hi[e];
+    }
+  }
+}
+
 template <class PDE, class T>
 __global__ __launch_bounds__(256) void k_dw_out(const float *__restrict__ ubar, const T *__restrict__ AH,
                                                 int64_t N_pad, int w, float *__restrict__ part,
                                                 int64_t pts_per_chunk) {
   constexpr int C = PDE::CH::C, DOUT = PDE::DOUT;
-  __shared__ float red[256 * DOUT];
-  const int nsub = w >= 256 ? 1 : 256 / w;
-  const int sub = threadIdx.x / (w >= 256 ? 256 : w);
-  const int kk = blockIdx.y * 256 + threadIdx.x % (w >= 256 ? 256 : w);
+  __shared__ float red[2048 * DOUT];  // (256 / (w/8)) groups x DOUT x w = 2048 * DOUT
+  const int lpr = w / 8, rgs = 256 / lpr;
+  const int q = threadIdx.x % lpr, rg = threadIdx.x / lpr;
   const int64_t nb = (int64_t)blockIdx.x * pts_per_chunk;
   const int64_t ne = nb + pts_per_chunk < N_pad ? nb + pts_per_chunk : N_pad;
-  float acc[DOUT];
+  const int rows = (int)(ne > nb ? (ne - nb) * C : 0);
+  float acc[DOUT][8];
 #pragma unroll
-  for (int o = 0; o < DOUT; ++o) acc[o] = 0.f;
-  if (sub < nsub && kk < w) {
-    for (int64_t n = nb + sub; n < ne; n += nsub) {
-      const float *ub = ubar + n * DOUT * C;
+  for (int o = 0; o < DOUT; ++o)
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const float a = to_f32(AH[(n * C + c) * w + kk]);
+    for (int e = 0; e < 8; ++e) acc[o][e] = 0.f;
+  if (rg < rgs) {
+    for (int rr = rg; rr < rows; rr += rgs) {
+      const int64_t n = nb + rr / C;
+      const int c = rr % C;
+      float a[8];
+      load8f<T>(AH + (n * C + c) * w + 8 * q, a);
 #pragma unroll
-        for (int o = 0; o < DOUT; ++o) acc[o] += ub[o * C + c] * a;
+      for (int o = 0; o < DOUT; ++o) {
+        const float u = ubar[(n * DOUT + o) * C + c];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc[o][e] += u * a[e];
       }
     }
-  }
 #pragma unroll
-  for (int o = 0; o < DOUT; ++o) red[o * 256 + threadIdx.x] = acc[o];
+    for (int o = 0; o < DOUT; ++o)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) red[(rg * DOUT + o) * w + 8 * q + e] = acc[o][e];
+  }
   __syncthreads();
   const int64_t stride = (int64_t)DOUT * w + DOUT;
   float *pp = part + blockIdx.x * stride;
-  if (threadIdx.x < (w >= 256 ? 256 : w) && kk < w) {
-#pragma unroll
-    for (int o = 0; o < DOUT; ++o) {
-      float s = 0.f;
-      for (int q = 0; q < nsub; ++q) s += red[o * 256 + q * w + threadIdx.x];
-      pp[o * w + kk] = s;
-    }
+  for (int idx = threadIdx.x; idx < DOUT * w; idx += 256) {
+    float sum = 0.f;
+    for (int g2 = 0; g2 < rgs; ++g2) sum += red[g2 * DOUT * w + idx];
+    pp[idx] = sum;
   }
-  if (blockIdx.y == 0 && threadIdx.x < DOUT) {
-    float s = 0.f;
-    for (int64_t n = nb; n < ne; ++n) s += ubar[(n * DOUT + threadIdx.x) * C];
-    pp[DOUT * w + threadIdx.x] = s;
+  if (threadIdx.x < DOUT) {
+    float sum = 0.f;
+    for (int64_t n = nb; n < ne; ++n) sum += ubar[(n * DOUT + threadIdx.x) * C];
+    pp[DOUT * w + threadIdx.x] = sum;
   }
 }
 
@@ -464,7 +485,7 @@ hipError_t launch_out_adj(int kind, const float *u_save, const float *r_save, co
 hipError_t launch_dw_out(int kind, int prec, const float *ubar, const void *A_H, int64_t N_pad,
                          int w, float *part, int n_chunks, hipStream_t st) {
   const int64_t ppc = (N_pad + n_chunks - 1) / n_chunks;  // chunks beyond N_pad write zeros
-  dim3 grid((unsigned)n_chunks, (unsigned)((w + 255) / 256));
+  dim3 grid((unsigned)n_chunks);
   return by_kind(kind, [&](auto pde) {
     using PDE = decltype(pde);
     return by_prec(prec, [&](auto tv) {

@@ -823,11 +823,11 @@ pinn_status pinn_plan_autotune(pinn_plan plan, const pinn_net *net, const pinn_p
   std::vector<pinn_tuning> cand;
   const bool can_fuse = pj::bwd_dw_fused_supported(p->ki.C, p->w, p->prec);
   for (int sp : {std::max(1, s0 / 2), s0, std::min(p->dw_splits_max, 2 * s0)})
-    for (int fp : {0, 16})
+    for (int fp : {0, 16, 32})
     for (int bf : {0, 1}) {
-      if (fp == 16 && (!pj::fused_fwd_fits(16, p->ki.C, p->w, p->prec) ||
-                       pj::fused_fwd_points(p->ki.C, p->w, p->prec) == 16))
-        continue;
+      // 0 (layer-by-layer forward) only when no whole-network tiling exists
+      const bool any_fused = pj::fused_fwd_points(p->ki.C, p->w, p->prec) > 0;
+      if (fp == 0 ? any_fused : !pj::fused_fwd_fits(fp, p->ki.C, p->w, p->prec)) continue;
       if (bf == 1 && !can_fuse) continue;
       pinn_tuning t{sp, fp, bf};
       bool dup = false;
