@@ -89,7 +89,7 @@ def gpu_params(prob):
     return [(torch.tensor(W, device="cuda"), torch.tensor(b, device="cuda")) for W, b in prob.params]
 
 
-def time_path(prob, prec, steps, warmup, profile_dominant=True):
+def time_path(prob, prec, steps, warmup, profile_dominant=True, tuning=None):
     """Times `steps` residual+backward steps; returns ms/step and per-class kernel times."""
     import torch
     from paper_2606_29702_amd import PinnPlan
@@ -103,8 +103,13 @@ def time_path(prob, prec, steps, warmup, profile_dominant=True):
         plan.residual(params, x)
         plan.backward(params, x)
 
-    # the library's autotuner picks split-K, forward tiling and backward variant
-    tuning, tuned_ms = plan.autotune(params, x, reps=3)
+    # the library's autotuner picks split-K, forward tiling and backward variant,
+    # unless a tuning is given
+    if tuning is None:
+        tuning, _ = plan.autotune(params, x, reps=3)
+    else:
+        plan.set_tuning(*tuning)
+        tuning = plan.tuning()
     # warmup; one profiled step per kernel class to find the dominant class
     class_ms = {}
     for i in range(max(warmup, 1)):
@@ -281,6 +286,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-context", action="store_true", help="skip the FP32, nested-autograd and ensemble context runs")
     ap.add_argument("--copy-probe-mib", type=int, default=0, help="only run a plain device copy of this size")
+    ap.add_argument("--tuning", default=None,
+                    help="dw_splits,fwd_points,bwd_fused instead of running the autotuner (e.g. for profiling)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -302,7 +309,8 @@ def main():
     w, H = wl.width, wl.hidden
 
     log(f"workload {args.workload}: dims {wl.dims}, N {N}, C {C}, precision {args.precision}")
-    main_run = time_path(prob, args.precision, args.steps, args.warmup)
+    tuning = tuple(int(v) for v in args.tuning.split(",")) if args.tuning else None
+    main_run = time_path(prob, args.precision, args.steps, args.warmup, tuning=tuning)
     ms = main_run["ms_per_step"]
     value = N / (ms * 1e-3)
     log(f"{args.precision}: {ms:.3f} ms/step, {value/1e6:.2f} Mpts/s, dominant {main_run['dominant']} "
