@@ -521,10 +521,15 @@ hipError_t launch_reduce_parts2(const float *part, int splits, int64_t stride, i
                                 int64_t M2, float *a32, float *b32, double *a64, double *b64,
                                 hipStream_t st) {
   const int64_t M = M1 + M2;
-  // few outputs with many splits: more threads per output
+  // enough workgroups to keep many loads in flight: more threads per output
+  // when there are few outputs or many splits
   if (M * 4 < 256LL * 256 && splits >= 64) {
     dim3 grid((unsigned)((M + 7) / 8));
     hipLaunchKernelGGL(k_reduce_parts_g<32>, grid, dim3(256), 0, st, part, splits, stride, M1, M2, a32, b32,
+                       a64, b64);
+  } else if (splits >= 64) {
+    dim3 grid((unsigned)((M + 15) / 16));
+    hipLaunchKernelGGL(k_reduce_parts_g<16>, grid, dim3(256), 0, st, part, splits, stride, M1, M2, a32, b32,
                        a64, b64);
   } else {
     dim3 grid((unsigned)((M + 63) / 64));

@@ -228,17 +228,32 @@ __global__ __launch_bounds__(256) void k_layer_bwd(BwdArgs args) {
 template <class T>
 __device__ __forceinline__ void stage_tile(T *dst, const T *src, int P, int C, int w, int pitch, int tid,
                                            int nthreads) {
-  const int per_pt = C * w / 8;
-  for (int q = tid; q < P * per_pt; q += nthreads) {
-    const int pp = q / per_pt, off = (q % per_pt) * 8;
-    const uint4 *s = reinterpret_cast<const uint4 *>(src + (int64_t)pp * C * w + off);
-    uint4 *d = reinterpret_cast<uint4 *>(dst + pp * pitch + off);
-    if constexpr (sizeof(T) == 2) {
-      *d = *s;
-    } else {
-      d[0] = s[0];
-      d[1] = s[1];
+  // A thread issues four 16-byte loads before its LDS stores, so that several
+  // loads are in flight per thread (named values, not an array, keep them in
+  // registers).
+  const int per_pt = C * w * (int)sizeof(T) / 16;  // 16-byte pieces per point row
+  const int total = P * per_pt;
+  constexpr int per16 = 16 / (int)sizeof(T);
+  auto ld = [&](int q) {
+    uint4 v = {0u, 0u, 0u, 0u};
+    if (q < total) {
+      const int pp = q / per_pt, off = (q % per_pt) * per16;
+      v = *reinterpret_cast<const uint4 *>(src + (int64_t)pp * C * w + off);
     }
+    return v;
+  };
+  auto st = [&](int q, uint4 v) {
+    if (q < total) {
+      const int pp = q / per_pt, off = (q % per_pt) * per16;
+      *reinterpret_cast<uint4 *>(dst + pp * pitch + off) = v;
+    }
+  };
+  for (int q0 = tid; q0 < total; q0 += 4 * nthreads) {
+    const uint4 v0 = ld(q0), v1 = ld(q0 + nthreads), v2 = ld(q0 + 2 * nthreads), v3 = ld(q0 + 3 * nthreads);
+    st(q0, v0);
+    st(q0 + nthreads, v1);
+    st(q0 + 2 * nthreads, v2);
+    st(q0 + 3 * nthreads, v3);
   }
 }
 
