@@ -2,7 +2,10 @@
 
 Every source under csrc/ is compiled by hipcc for gfx950 only, in parallel,
 then linked into one shared library next to this file.  Packed FP32 VALU
-instructions are disabled for all device code.
+instructions are disabled for all device code.  Except in k_layer.hip (where
+it measured slower), MFMA instructions are selected in their VGPR form
+(accumulators in ordinary VGPRs), which keeps the compiler from shuffling
+loop-carried accumulators through AGPRs.
 """
 import concurrent.futures as cf
 import os
@@ -21,9 +24,14 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
+MFMA_VGPR = ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]
+NO_MFMA_VGPR = {"k_layer.hip"}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+    extra = [] if os.path.basename(src) in NO_MFMA_VGPR else MFMA_VGPR
+    cmd = [HIPCC] + FLAGS + extra + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

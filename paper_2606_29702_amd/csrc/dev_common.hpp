@@ -101,4 +101,88 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
+// Row blocks moved between global memory, where the rows of a block are
+// contiguous, and LDS, where row p starts at element p * pitch.  The unit is a
+// 16-byte piece: piece q of a block sits at element q * (16 / sizeof(T)) in
+// global memory and row(q) * (pitch - row_elems) further on in LDS.  A thread
+// takes the pieces tid, tid + nthreads, ...; their rows are advanced by
+// increments (one division per thread, none per piece).  Each thread issues
+// NB reads before its NB writes, so that up to NB accesses are in flight.
+// row_elems * sizeof(T) must be a multiple of 16 and every base address
+// 16-byte aligned.
+struct PieceWalk {
+  int q, row, col;
+  int per_row, step, drow, dcol;
+  __device__ __forceinline__ PieceWalk(int q0, int step_, int per_row_)
+      : q(q0), per_row(per_row_), step(step_) {
+    row = q0 / per_row;
+    col = q0 - row * per_row;
+    drow = step / per_row;
+    dcol = step - drow * per_row;
+  }
+  __device__ __forceinline__ void next() {
+    q += step;
+    row += drow;
+    col += dcol;
+    if (col >= per_row) {
+      col -= per_row;
+      ++row;
+    }
+  }
+};
+
+// Global -> LDS.  Block 0 (rows 0 .. rows-1 in LDS) comes from g0; with TWO,
+// block 1 (LDS rows rows .. 2 rows - 1) comes from g1.
+template <class T, int NB, bool TWO>
+__device__ __forceinline__ void stage_rows(T *lds, const T *g0, const T *g1, int rows, int row_elems, int pitch,
+                                           int tid, int nthreads) {
+  constexpr int per16 = 16 / (int)sizeof(T);
+  const int per_row = row_elems / per16;
+  const int total0 = rows * per_row;
+  const int total = TWO ? 2 * total0 : total0;
+  const int pad = pitch - row_elems;
+  PieceWalk it(tid, nthreads, per_row);
+  while (it.q < total) {
+    uint4 v[NB];
+    int dst[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const bool live = it.q < total;
+      const T *src = g0 + it.q * per16;
+      if (TWO && it.q >= total0) src = g1 + (it.q - total0) * per16;
+      v[u] = live ? *reinterpret_cast<const uint4 *>(src) : uint4{0u, 0u, 0u, 0u};
+      dst[u] = live ? it.q * per16 + it.row * pad : -1;
+      it.next();
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+      if (dst[u] >= 0) *reinterpret_cast<uint4 *>(lds + dst[u]) = v[u];
+  }
+}
+
+// LDS -> global, one block.
+template <class T, int NB>
+__device__ __forceinline__ void unstage_rows(T *g, const T *lds, int rows, int row_elems, int pitch, int tid,
+                                             int nthreads) {
+  constexpr int per16 = 16 / (int)sizeof(T);
+  const int per_row = row_elems / per16;
+  const int total = rows * per_row;
+  const int pad = pitch - row_elems;
+  PieceWalk it(tid, nthreads, per_row);
+  while (it.q < total) {
+    uint4 v[NB];
+    int dst[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const bool live = it.q < total;
+      v[u] = live ? *reinterpret_cast<const uint4 *>(lds + it.q * per16 + it.row * pad) : uint4{0u, 0u, 0u, 0u};
+      dst[u] = live ? it.q * per16 : -1;
+      it.next();
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+      if (dst[u] >= 0) *reinterpret_cast<uint4 *>(g + dst[u]) = v[u];
+  }
+}
+
 }  // namespace pj

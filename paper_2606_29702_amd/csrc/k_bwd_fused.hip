@@ -51,22 +51,6 @@ struct Mma16<float> {
   }
 };
 
-template <class T>
-__device__ __forceinline__ void stage_rows(T *dst, const T *src, int P, int rowlen, int pitch, int tid, int nt) {
-  const int per_pt = rowlen / 8;
-  for (int q = tid; q < P * per_pt; q += nt) {
-    const int pp = q / per_pt, off = (q % per_pt) * 8;
-    const uint4 *s = reinterpret_cast<const uint4 *>(src + (int64_t)pp * rowlen + off);
-    uint4 *d = reinterpret_cast<uint4 *>(dst + pp * pitch + off);
-    if constexpr (sizeof(T) == 2) {
-      *d = *s;
-    } else {
-      d[0] = s[0];
-      d[1] = s[1];
-    }
-  }
-}
-
 template <class T, int C, int TPW>
 __device__ __forceinline__ void tile_gemm(f32x4 (&acc)[TPW][C], const T *__restrict__ Wop, const T *stk, int pitch,
                                           int jt0, int w, int lane) {
@@ -125,8 +109,12 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_dw(BwdArgs args, float *__restr
 
   for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int64_t nb = tile * P;
-    if constexpr (!TOP) stage_rows<T>(lds_b, static_cast<const T *>(args.Zb_in) + nb * ps, P, C * W, pitch, tid, NW * 64);
-    stage_rows<T>(lds_a, static_cast<const T *>(args.A_prev) + nb * ps, P, C * W, pitch, tid, NW * 64);
+    if constexpr (!TOP)
+      stage_rows<T, 12, true>(lds_b, static_cast<const T *>(args.Zb_in) + nb * ps,
+                              static_cast<const T *>(args.A_prev) + nb * ps, P, C * W, pitch, tid, NW * 64);
+    else
+      stage_rows<T, 12, false>(lds_a, static_cast<const T *>(args.A_prev) + nb * ps, nullptr, P, C * W, pitch, tid,
+                               NW * 64);
     __syncthreads();
 
     f32x4 acc_a[TPW][C];

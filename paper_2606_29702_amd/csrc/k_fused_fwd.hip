@@ -65,20 +65,8 @@ __global__ __launch_bounds__(NW * 64) void k_fwd_fused(FusedFwdArgs a) {
       }
     }
   } else {
-    // the saved stack of layer l_first - 1, coalesced, 8 elements per thread
-    const T *Ag = static_cast<const T *>(a.A_in) + nb * gps;
-    const int per_pt = C * w / 8;
-    for (int q = tid; q < P * per_pt; q += NT) {
-      const int pp = q / per_pt, off = (q % per_pt) * 8;
-      const uint4 *src = reinterpret_cast<const uint4 *>(Ag + pp * gps + off);
-      uint4 *dst = reinterpret_cast<uint4 *>(stk + pp * pitch + off);
-      if constexpr (sizeof(T) == 2) {
-        *dst = *src;
-      } else {
-        dst[0] = src[0];
-        dst[1] = src[1];
-      }
-    }
+    // the saved stack of layer l_first - 1, coalesced 16-byte pieces
+    stage_rows<T, 8, false>(stk, static_cast<const T *>(a.A_in) + nb * gps, nullptr, P, C * w, pitch, tid, NT);
   }
   __syncthreads();
 
@@ -145,22 +133,8 @@ __global__ __launch_bounds__(NW * 64) void k_fwd_fused(FusedFwdArgs a) {
     }
     __syncthreads();  // layer l's stack complete in LDS
 
-    if (a.A[l]) {
-      // coalesced copy of the block's stack to global memory, 8 elements per thread
-      T *Ag = static_cast<T *>(a.A[l]) + nb * gps;
-      const int per_pt = C * w / 8;
-      for (int q = tid; q < P * per_pt; q += NT) {
-        const int pp = q / per_pt, off = (q % per_pt) * 8;
-        const uint4 *src = reinterpret_cast<const uint4 *>(stk + pp * pitch + off);
-        uint4 *dst = reinterpret_cast<uint4 *>(Ag + pp * gps + off);
-        if constexpr (sizeof(T) == 2) {
-          *dst = *src;
-        } else {
-          dst[0] = src[0];
-          dst[1] = src[1];
-        }
-      }
-    }
+    if (a.A[l])  // coalesced copy of the block's stack to global memory
+      unstage_rows<T, 8>(static_cast<T *>(a.A[l]) + nb * gps, stk, P, C * w, pitch, tid, NT);
   }
 
   // ---- output layer, residual, loss partial: TPP threads per point

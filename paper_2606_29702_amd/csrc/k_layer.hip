@@ -225,38 +225,6 @@ __global__ __launch_bounds__(256) void k_layer_bwd(BwdArgs args) {
 // of layer l-2 are copied into LDS with coalesced 16-byte loads (all issued
 // before the first MFMA), then both GEMMs read their B operands from LDS.
 // The tile split over waves is the one of the fused forward pass.
-template <class T>
-__device__ __forceinline__ void stage_tile(T *dst, const T *src, int P, int C, int w, int pitch, int tid,
-                                           int nthreads) {
-  // A thread issues four 16-byte loads before its LDS stores, so that several
-  // loads are in flight per thread (named values, not an array, keep them in
-  // registers).
-  const int per_pt = C * w * (int)sizeof(T) / 16;  // 16-byte pieces per point row
-  const int total = P * per_pt;
-  constexpr int per16 = 16 / (int)sizeof(T);
-  auto ld = [&](int q) {
-    uint4 v = {0u, 0u, 0u, 0u};
-    if (q < total) {
-      const int pp = q / per_pt, off = (q % per_pt) * per16;
-      v = *reinterpret_cast<const uint4 *>(src + (int64_t)pp * C * w + off);
-    }
-    return v;
-  };
-  auto st = [&](int q, uint4 v) {
-    if (q < total) {
-      const int pp = q / per_pt, off = (q % per_pt) * per16;
-      *reinterpret_cast<uint4 *>(dst + pp * pitch + off) = v;
-    }
-  };
-  for (int q0 = tid; q0 < total; q0 += 4 * nthreads) {
-    const uint4 v0 = ld(q0), v1 = ld(q0 + nthreads), v2 = ld(q0 + 2 * nthreads), v3 = ld(q0 + 3 * nthreads);
-    st(q0, v0);
-    st(q0 + nthreads, v1);
-    st(q0 + 2 * nthreads, v2);
-    st(q0 + 3 * nthreads, v3);
-  }
-}
-
 template <class T, int C, int TPW>
 __device__ __forceinline__ void lds_gemm(f32x4 (&acc)[TPW][C], const T *__restrict__ Wop, const T *stk,
                                          int pitch, int jt0, int nt, int w, int lane) {
@@ -301,9 +269,18 @@ __global__ __launch_bounds__(NW * 64) void k_layer_bwd_lds(BwdArgs args) {
   const int r = lane & 15, g = lane >> 4;
   const int64_t nb = (int64_t)blockIdx.x * P;
   const int64_t ps = (int64_t)C * w;
-  if constexpr (!TOP) stage_tile<T>(lds_b, static_cast<const T *>(args.Zb_in) + nb * ps, P, C, w, pitch, tid, NW * 64);
-  if constexpr (ZSRC == Z_FROM_GEMM)
-    stage_tile<T>(lds_a, static_cast<const T *>(args.A_prev) + nb * ps, P, C, w, pitch, tid, NW * 64);
+  // both tiles in one pass (Zbar_l first, then the stack of layer l-2), so that
+  // a thread's loads of the two are in flight together
+  {
+    const T *zb_in = static_cast<const T *>(args.Zb_in) + nb * ps;
+    const T *a_prev = static_cast<const T *>(args.A_prev) + nb * ps;
+    if constexpr (!TOP && ZSRC == Z_FROM_GEMM)
+      stage_rows<T, 12, true>(lds_b, zb_in, a_prev, P, C * w, pitch, tid, NW * 64);
+    else if constexpr (!TOP)
+      stage_rows<T, 12, false>(lds_b, zb_in, nullptr, P, C * w, pitch, tid, NW * 64);
+    else if constexpr (ZSRC == Z_FROM_GEMM)
+      stage_rows<T, 12, false>(lds_a, a_prev, nullptr, P, C * w, pitch, tid, NW * 64);
+  }
   __syncthreads();
 
   const int NJ = w / 16;
