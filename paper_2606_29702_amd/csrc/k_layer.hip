@@ -225,34 +225,73 @@ __global__ __launch_bounds__(256) void k_layer_bwd(BwdArgs args) {
 // of layer l-2 are copied into LDS with coalesced 16-byte loads (all issued
 // before the first MFMA), then both GEMMs read their B operands from LDS.
 // The tile split over waves is the one of the fused forward pass.
-template <class T, int C, int TPW>
-__device__ __forceinline__ void lds_gemm(f32x4 (&acc)[TPW][C], const T *__restrict__ Wop, const T *stk,
-                                         int pitch, int jt0, int nt, int w, int lane) {
+// Weight fragments of the first KP contraction steps (32 each) of a wave's TPW
+// neuron tiles, loaded before the stack tiles are staged so that their L2
+// latency is hidden behind the staging.
+template <class T, int TPW, int KP>
+struct WFrags {
+  typename Mma<T>::frag f[TPW][KP];
+};
+
+template <class T, int TPW, int KP>
+__device__ __forceinline__ void load_wfrags(WFrags<T, TPW, KP> &wf, const T *__restrict__ Wop, int jt0, int w,
+                                            int lane) {
+  const int r = lane & 15, g = lane >> 4;
+  const T *wrow = Wop + (int64_t)(jt0 * 16 + r) * w + 8 * g;
+#pragma unroll
+  for (int kk = 0; kk < KP; ++kk)
+#pragma unroll
+    for (int t = 0; t < TPW; ++t)
+      if (kk * 32 < w) wf.f[t][kk] = Mma<T>::load(wrow + (int64_t)t * 16 * w + kk * 32);
+}
+
+// acc[t][c] = rows (jt0 + t) * 16 .. + 15 of Wop (w x w) times the channel-c
+// columns of the 16-point tile nt of the LDS stack.  The first KP steps use
+// the preloaded fragments; further steps stream the weights from global
+// memory one step ahead.
+template <class T, int C, int TPW, int KP>
+__device__ __forceinline__ void lds_gemm(f32x4 (&acc)[TPW][C], const WFrags<T, TPW, KP> &wf,
+                                         const T *__restrict__ Wop, const T *stk, int pitch, int jt0, int nt, int w,
+                                         int lane) {
   using M = Mma<T>;
   const int r = lane & 15, g = lane >> 4;
 #pragma unroll
   for (int t = 0; t < TPW; ++t)
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const T *wrow = Wop + (int64_t)(jt0 * 16 + r) * w + 8 * g;
   const T *brow = stk + (nt * 16 + r) * pitch + 8 * g;
-  typename M::frag fa[TPW];
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) fa[t] = M::load(wrow + (int64_t)t * 16 * w);
-  for (int k = 0; k < w; k += 32) {
-    typename M::frag fb[C];
+  for (int kk = 0; kk < KP; ++kk) {
+    if (kk * 32 < w) {
+      typename M::frag fb[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) fb[c] = M::load(brow + c * w + k);
-    typename M::frag fn[TPW];
-    const int kn = k + 32 < w ? k + 32 : k;
+      for (int c = 0; c < C; ++c) fb[c] = M::load(brow + c * w + kk * 32);
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) fn[t] = M::load(wrow + (int64_t)t * 16 * w + kn);
+      for (int t = 0; t < TPW; ++t)
 #pragma unroll
-    for (int t = 0; t < TPW; ++t)
+        for (int c = 0; c < C; ++c) M::mma(acc[t][c], wf.f[t][kk], fb[c]);
+    }
+  }
+  if (KP * 32 < w) {
+    const T *wrow = Wop + (int64_t)(jt0 * 16 + r) * w + 8 * g;
+    typename M::frag fa[TPW];
 #pragma unroll
-      for (int c = 0; c < C; ++c) M::mma(acc[t][c], fa[t], fb[c]);
+    for (int t = 0; t < TPW; ++t) fa[t] = M::load(wrow + (int64_t)t * 16 * w + KP * 32);
+    for (int k = KP * 32; k < w; k += 32) {
+      typename M::frag fb[C];
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) fa[t] = fn[t];
+      for (int c = 0; c < C; ++c) fb[c] = M::load(brow + c * w + k);
+      typename M::frag fn[TPW];
+      const int kn = k + 32 < w ? k + 32 : k;
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) fn[t] = M::load(wrow + (int64_t)t * 16 * w + kn);
+#pragma unroll
+      for (int t = 0; t < TPW; ++t)
+#pragma unroll
+        for (int c = 0; c < C; ++c) M::mma(acc[t][c], fa[t], fb[c]);
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) fa[t] = fn[t];
+    }
   }
 }
 
@@ -269,6 +308,15 @@ __global__ __launch_bounds__(NW * 64) void k_layer_bwd_lds(BwdArgs args) {
   const int r = lane & 15, g = lane >> 4;
   const int64_t nb = (int64_t)blockIdx.x * P;
   const int64_t ps = (int64_t)C * w;
+  const int NJ = w / 16;
+  const int tile0 = wave * TPW;
+  const int nt = tile0 / NJ, jt0 = tile0 % NJ;
+  // weight fragments of the first contraction steps, loaded first (16
+  // registers per GEMM)
+  constexpr int KP = (sizeof(T) == 2 ? 4 : 2) / TPW > 0 ? (sizeof(T) == 2 ? 4 : 2) / TPW : 1;
+  WFrags<T, TPW, KP> wf_a, wf_z;
+  if constexpr (!TOP) load_wfrags(wf_a, static_cast<const T *>(args.WT), jt0, w, lane);
+  if constexpr (ZSRC == Z_FROM_GEMM) load_wfrags(wf_z, static_cast<const T *>(args.Wz), jt0, w, lane);
   // both tiles in one pass (Zbar_l first, then the stack of layer l-2), so that
   // a thread's loads of the two are in flight together
   {
@@ -283,14 +331,12 @@ __global__ __launch_bounds__(NW * 64) void k_layer_bwd_lds(BwdArgs args) {
   }
   __syncthreads();
 
-  const int NJ = w / 16;
-  const int tile0 = wave * TPW;
-  const int nt = tile0 / NJ, jt0 = tile0 % NJ;
   f32x4 acc_a[TPW][C];
-  if constexpr (!TOP) lds_gemm<T, C, TPW>(acc_a, static_cast<const T *>(args.WT), lds_b, pitch, jt0, nt, w, lane);
+  if constexpr (!TOP)
+    lds_gemm<T, C, TPW, KP>(acc_a, wf_a, static_cast<const T *>(args.WT), lds_b, pitch, jt0, nt, w, lane);
   f32x4 acc_z[TPW][C];
   if constexpr (ZSRC == Z_FROM_GEMM)
-    lds_gemm<T, C, TPW>(acc_z, static_cast<const T *>(args.Wz), lds_a, pitch, jt0, nt, w, lane);
+    lds_gemm<T, C, TPW, KP>(acc_z, wf_z, static_cast<const T *>(args.Wz), lds_a, pitch, jt0, nt, w, lane);
 
   T *Zb_out = static_cast<T *>(args.Zb_out);
   const int64_t n = nb + nt * 16 + r;
