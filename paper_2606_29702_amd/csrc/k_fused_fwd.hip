@@ -40,53 +40,73 @@ __global__ __launch_bounds__(NW * 64) void k_fwd_fused(FusedFwdArgs a) {
   const int64_t nb = (int64_t)blockIdx.x * P;
   const int64_t gps = (int64_t)C * w;  // elements per point in a global stack
 
+  // Wave layout of every layer: this wave owns the TPW neuron tiles jt0 ..
+  // jt0 + TPW - 1 of the 16-point tile nt; lane (r, g) holds point nt * 16 + r
+  // and, in tile t, neurons (jt0 + t) * 16 + 4 g + 0..3.
+  const int NJ = w / 16;
+  const int tile0 = wave * TPW;
+  const int nt = tile0 / NJ;
+  const int jt0 = tile0 % NJ;
+  const int p_l = nt * 16 + r;  // this lane's point within the block
+  const int64_t n_l = nb + p_l;
+
   // ---- input of layer l_first: the seed layer from x, or a saved stack
   if (a.l_first == 1) {
     // layer 1: z = W1 x + b1, d z / d x_i = W1[:, i], then the jet
-    for (int idx = tid; idx < P * w; idx += NT) {
-      const int p = idx / w, j = idx % w;
-      const int64_t n = nb + p;
-      float z[C];
+    float xin[D];
 #pragma unroll
-      for (int c = 0; c < C; ++c) z[c] = 0.f;
-      float z0 = a.b1[j];
+    for (int i = 0; i < D; ++i) xin[i] = n_l < a.N ? a.x[n_l * D + i] : 0.f;
 #pragma unroll
-      for (int i = 0; i < D; ++i) z0 += a.W1[j * D + i] * (n < a.N ? a.x[n * D + i] : 0.f);
-      z[0] = z0;
+    for (int t = 0; t < TPW; ++t) {
+      const int mb = (jt0 + t) * 16 + 4 * g;
+      float out[4][C], sv[4][C];
 #pragma unroll
-      for (int d = 0; d < CH::NDIR; ++d) z[CH::at(d, 1)] = a.W1[j * D + CH::in(d)];
-      float act[C], s;
-      jet_forward<CH, sizeof(T) == 2>(z, act, s);
+      for (int i = 0; i < 4; ++i) {
+        const int j = mb + i;
+        float z[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) z[c] = 0.f;
+        float z0 = a.b1[j];
+#pragma unroll
+        for (int q = 0; q < D; ++q) z0 += a.W1[j * D + q] * xin[q];
+        z[0] = z0;
+#pragma unroll
+        for (int d = 0; d < CH::NDIR; ++d) z[CH::at(d, 1)] = a.W1[j * D + CH::in(d)];
+        float act[C], sg;
+        jet_forward<CH, sizeof(T) == 2>(z, act, sg);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          out[i][c] = act[c];
+          sv[i][c] = c == 0 ? sg : z[c];
+        }
+      }
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        stk[p * pitch + c * w + j] = static_cast<T>(act[c]);
-        if (a.A[1]) static_cast<T *>(a.A[1])[(n * C + c) * w + j] = static_cast<T>(act[c]);
-        if (a.S[1]) a.S[1][(n * C + c) * w + j] = c == 0 ? s : z[c];
+        store4(stk + p_l * pitch + c * w + mb, out[0][c], out[1][c], out[2][c], out[3][c]);
+        if (a.S[1]) store4(a.S[1] + n_l * gps + c * w + mb, sv[0][c], sv[1][c], sv[2][c], sv[3][c]);
       }
     }
+    __syncthreads();
+    if (a.A[1]) unstage_rows<T, 8>(static_cast<T *>(a.A[1]) + nb * gps, stk, P, C * w, pitch, tid, NT);
   } else {
     // the saved stack of layer l_first - 1, coalesced 16-byte pieces
     stage_rows<T, 8, false>(stk, static_cast<const T *>(a.A_in) + nb * gps, nullptr, P, C * w, pitch, tid, NT);
+    __syncthreads();
   }
-  __syncthreads();
 
   // ---- hidden layers max(2, l_first) .. l_last
-  const int NJ = w / 16;
-  const int tile0 = wave * TPW;          // first (point tile, neuron tile) of this wave
-  const int nt = tile0 / NJ;             // its 16-point tile
-  const int jt0 = tile0 % NJ;            // first of its TPW neuron tiles
   for (int l = a.l_first > 2 ? a.l_first : 2; l <= a.l_last; ++l) {
     const T *Wl = static_cast<const T *>(a.Wop[l]);
-    f32x4 acc[TPW][C];
-#pragma unroll
-    for (int t = 0; t < TPW; ++t)
-#pragma unroll
-      for (int c = 0; c < C; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
     const T *wrow = Wl + (int64_t)(jt0 * 16 + r) * w + 8 * g;
     const T *brow = stk + (nt * 16 + r) * pitch + 8 * g;
     typename M::frag fa[TPW];
 #pragma unroll
     for (int t = 0; t < TPW; ++t) fa[t] = M::load(wrow + (int64_t)t * 16 * w);
+    f32x4 acc[TPW][C];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t)
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int k = 0; k < w; k += 32) {
       typename M::frag fb[C];
 #pragma unroll
@@ -106,8 +126,8 @@ __global__ __launch_bounds__(NW * 64) void k_fwd_fused(FusedFwdArgs a) {
 
     const float *bl = a.b[l];
     float *Sl = a.S[l];
-    const int p = nt * 16 + r;
-    const int64_t n = nb + p;
+    const int p = p_l;
+    const int64_t n = n_l;
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
       const int mb = (jt0 + t) * 16 + 4 * g;
