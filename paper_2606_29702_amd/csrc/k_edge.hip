@@ -407,6 +407,71 @@ __global__ __launch_bounds__(256) void k_reduce_parts_g(const float *__restrict_
   }
 }
 
+// The same sum with 16-byte loads.  A workgroup of NT threads owns COLS float4
+// columns (4 * COLS consecutive outputs); thread (col, grp), col = tid % COLS,
+// sums the splits grp, grp + G, ... (G = NT / COLS) of its column in order,
+// and the G group sums are then added in group order.  Consecutive lanes read
+// consecutive 16-byte pieces of one partial row.  Requires stride, M1 and
+// M1 + M2 to be multiples of 4 and part 16-byte aligned.
+template <int COLS, int NT>
+__global__ __launch_bounds__(NT) void k_reduce_parts_v4(const float *__restrict__ part, int splits, int64_t stride,
+                                                        int64_t M1, int64_t M2, float *__restrict__ a32,
+                                                        float *__restrict__ b32, double *__restrict__ a64,
+                                                        double *__restrict__ b64) {
+  constexpr int G = NT / COLS;
+  __shared__ f32x4 s32[NT];
+  __shared__ double s64[NT][4];
+  const int col = threadIdx.x % COLS, grp = threadIdx.x / COLS;
+  const int64_t c4 = (int64_t)blockIdx.x * COLS + col;
+  const bool live = 4 * c4 < M1 + M2;
+  const bool want64 = a64 != nullptr || b64 != nullptr;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+  if (live) {
+    const f32x4 *src = reinterpret_cast<const f32x4 *>(part) + c4;
+    const int64_t st4 = stride / 4;
+    if (want64) {
+      for (int sp = grp; sp < splits; sp += G) {
+        const f32x4 v = src[sp * st4];
+        acc += v;
+        d0 += (double)v[0];
+        d1 += (double)v[1];
+        d2 += (double)v[2];
+        d3 += (double)v[3];
+      }
+    } else {
+#pragma unroll 4
+      for (int sp = grp; sp < splits; sp += G) acc += src[sp * st4];
+    }
+  }
+  s32[threadIdx.x] = acc;
+  s64[threadIdx.x][0] = d0;
+  s64[threadIdx.x][1] = d1;
+  s64[threadIdx.x][2] = d2;
+  s64[threadIdx.x][3] = d3;
+  __syncthreads();
+  if (grp == 0 && live) {
+    f32x4 t = s32[col];
+    double td[4] = {s64[col][0], s64[col][1], s64[col][2], s64[col][3]};
+    for (int k = 1; k < G; ++k) {
+      t += s32[k * COLS + col];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) td[e] += s64[k * COLS + col][e];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t q = 4 * c4 + e;
+      if (q < M1) {
+        if (a32) a32[q] = t[e];
+        if (a64) a64[q] = td[e];
+      } else {
+        if (b32) b32[q - M1] = t[e];
+        if (b64) b64[q - M1] = td[e];
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 namespace {
 
@@ -523,7 +588,12 @@ hipError_t launch_reduce_parts2(const float *part, int splits, int64_t stride, i
   const int64_t M = M1 + M2;
   // enough workgroups to keep many loads in flight: more threads per output
   // when there are few outputs or many splits
-  if (M * 4 < 256LL * 256 && splits >= 64) {
+  if (splits >= 64 && M >= 4096 && stride % 4 == 0 && M1 % 4 == 0 && M % 4 == 0 &&
+      reinterpret_cast<uintptr_t>(part) % 16 == 0) {
+    dim3 grid((unsigned)((M / 4 + 15) / 16));
+    hipLaunchKernelGGL((k_reduce_parts_v4<16, 256>), grid, dim3(256), 0, st, part, splits, stride, M1, M2, a32,
+                       b32, a64, b64);
+  } else if (M * 4 < 256LL * 256 && splits >= 64) {
     dim3 grid((unsigned)((M + 7) / 8));
     hipLaunchKernelGGL(k_reduce_parts_g<32>, grid, dim3(256), 0, st, part, splits, stride, M1, M2, a32, b32,
                        a64, b64);
