@@ -106,7 +106,7 @@ def time_path(prob, prec, steps, warmup, profile_dominant=True, tuning=None):
     # the library's autotuner picks split-K, forward tiling and backward variant,
     # unless a tuning is given
     if tuning is None:
-        tuning, _ = plan.autotune(params, x, reps=3)
+        tuning, _ = plan.autotune(params, x, reps=10)
     else:
         plan.set_tuning(*tuning)
         tuning = plan.tuning()

@@ -171,8 +171,9 @@ pinn_status pinn_plan_get_tuning(pinn_plan plan, pinn_tuning *tuning);
 pinn_status pinn_plan_set_tuning(pinn_plan plan, const pinn_tuning *tuning);
 
 /* Autotuner: times `reps` residual + backward steps (after one warm-up step)
- * for each candidate tuning on the caller's data, keeps the fastest and
- * returns it with its milliseconds per step.  Synchronises the stream and
+ * for each candidate tuning on the caller's data, in two interleaved rounds,
+ * keeps the candidate with the fastest round and returns it with its
+ * milliseconds per step.  Synchronises the stream and
  * allocates temporary gradient buffers; invalidates the saved state. */
 pinn_status pinn_plan_autotune(pinn_plan plan, const pinn_net *net, const pinn_pde *pde, const float *x,
                                int64_t N, int32_t reps, pinn_tuning *best, double *best_ms, void *stream);

@@ -92,6 +92,8 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_dw(BwdArgs args, float *__restr
   constexpr int JT = JW / 16, KT = W / 16;
   constexpr int ROWS = P * C;     // contraction rows per tile (multiple of 16)
   static_assert(JW % 16 == 0 && ROWS % 16 == 0, "tile shape");
+  // 16-byte pieces per thread when staging both tiles: all in flight at once
+  constexpr int SNB = (2 * P * C * W * (int)sizeof(T) / 16 + NW * 64 - 1) / (NW * 64);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *lds_b = reinterpret_cast<T *>(smem_raw);  // Zbar_{m+1}, then Zbar_m
   T *lds_a = lds_b + P * pitch;                // A_{m-1}
@@ -110,10 +112,10 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_dw(BwdArgs args, float *__restr
   for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int64_t nb = tile * P;
     if constexpr (!TOP)
-      stage_rows<T, 12, true>(lds_b, static_cast<const T *>(args.Zb_in) + nb * ps,
+      stage_rows<T, SNB, true>(lds_b, static_cast<const T *>(args.Zb_in) + nb * ps,
                               static_cast<const T *>(args.A_prev) + nb * ps, P, C * W, pitch, tid, NW * 64);
     else
-      stage_rows<T, 12, false>(lds_a, static_cast<const T *>(args.A_prev) + nb * ps, nullptr, P, C * W, pitch, tid,
+      stage_rows<T, SNB, false>(lds_a, static_cast<const T *>(args.A_prev) + nb * ps, nullptr, P, C * W, pitch, tid,
                                NW * 64);
     __syncthreads();
 
@@ -192,9 +194,12 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_dw(BwdArgs args, float *__restr
 #pragma unroll
       for (int p = 0; p < P; ++p) db += to_f32(lds_b[p * pitch + tid]);
     }
-    // dW_m += Zbar_m^T A_{m-1} over the tile's rows (point, channel)
-#pragma unroll
-    for (int s = 0; s < ROWS / 16; ++s) {
+    // dW_m += Zbar_m^T A_{m-1} over the tile's rows (point, channel), 16 rows
+    // per step.  Below the top layer the steps stay rolled, which keeps the
+    // gathered operands of a single step in registers (two waves per SIMD
+    // instead of one); the top-layer variant keeps fewer accumulators live and
+    // unrolls.
+    auto dw_step = [&](int s) {
       int off[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
@@ -218,6 +223,13 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_dw(BwdArgs args, float *__restr
       for (int jt = 0; jt < JT; ++jt)
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt) M16::mma(dacc[jt][kt], fa[jt], fb[kt]);
+    };
+    if constexpr (TOP) {
+#pragma unroll
+      for (int s = 0; s < ROWS / 16; ++s) dw_step(s);
+    } else {
+#pragma unroll 1
+      for (int s = 0; s < ROWS / 16; ++s) dw_step(s);
     }
     __syncthreads();  // before the next tile is staged over both buffers
   }
