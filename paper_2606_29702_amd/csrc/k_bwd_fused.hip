@@ -20,6 +20,19 @@ namespace pj {
 
 typedef __bf16 bf16x4v __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x4v __attribute__((ext_vector_type(4)));
+typedef short i16x4v __attribute__((ext_vector_type(4)));
+
+// 8-byte LDS transpose read of 16-bit elements (gfx950), as the 4-element
+// MFMA operand of type T.
+template <class T>
+__device__ __forceinline__ auto lds_tr16(const T *p) {
+  const i16x4v v = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+      (__attribute__((address_space(3))) i16x4v *)(const_cast<T *>(p)));
+  if constexpr (sizeof(T) == 2 && __is_same(T, bf16_t))
+    return __builtin_bit_cast(bf16x4v, v);
+  else
+    return __builtin_bit_cast(f16x4v, v);
+}
 
 // MFMA with a 16-long contraction: lane l supplies the 4 consecutive
 // contraction elements 4*(l/16) .. 4*(l/16)+3 of row (l%16) of A and of
@@ -207,17 +220,31 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_dw(BwdArgs args, float *__restr
         off[e] = (row / C) * pitch + (row % C) * W;
       }
       typename M16::frag fa[JT], fb[KT];
+      if constexpr (sizeof(T) == 2) {
+        // LDS transpose read: within each group of 16 lanes, output lane
+        // 4a + e receives element e of the 8-byte reads of lanes a, a + 4,
+        // a + 8, a + 12.  Lane r of group g therefore reads row
+        // 16 s + 4 g + r / 4 at columns 4 (r % 4) .. + 3 of the 16-column
+        // tile, and receives column r of rows 16 s + 4 g .. + 3: its operand.
+        const int row = 16 * s + 4 * g + (r >> 2);
+        const int roff = (row / C) * pitch + (row % C) * W + 4 * (r & 3);
 #pragma unroll
-      for (int jt = 0; jt < JT; ++jt) {
-        const int j = wave * JW + jt * 16 + r;
+        for (int jt = 0; jt < JT; ++jt) fa[jt] = lds_tr16<T>(lds_b + roff + wave * JW + jt * 16);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) fa[jt][e] = lds_b[off[e] + j];
-      }
+        for (int kt = 0; kt < KT; ++kt) fb[kt] = lds_tr16<T>(lds_a + roff + kt * 16);
+      } else {
 #pragma unroll
-      for (int kt = 0; kt < KT; ++kt) {
-        const int k = kt * 16 + r;
+        for (int jt = 0; jt < JT; ++jt) {
+          const int j = wave * JW + jt * 16 + r;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) fb[kt][e] = lds_a[off[e] + k];
+          for (int e = 0; e < 4; ++e) fa[jt][e] = lds_b[off[e] + j];
+        }
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) {
+          const int k = kt * 16 + r;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) fb[kt][e] = lds_a[off[e] + k];
+        }
       }
 #pragma unroll
       for (int jt = 0; jt < JT; ++jt)
