@@ -219,7 +219,8 @@ enum {
   PINN_K_OUT_FWD = 4,    /* output layer + residual + loss partials             */
   PINN_K_OUT_BWD = 5,    /* residual adjoint + output layer adjoint             */
   PINN_K_SEED_FWD = 6,   /* first layer + activation jet                        */
-  PINN_K_OTHER = 7       /* casts, reductions, first/last layer gradients       */
+  PINN_K_OTHER = 7,      /* casts, reductions, first/last layer gradients       */
+  PINN_K_BWD_DW = 8      /* hidden-layer adjoint with its weight gradient fused */
 };
 pinn_status pinn_plan_profile(pinn_plan plan, int32_t kernel_class);
 pinn_status pinn_plan_profile_read(pinn_plan plan, double *total_ms, int64_t *launches);

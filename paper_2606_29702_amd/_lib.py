@@ -30,7 +30,7 @@ EXPORTS = ["pinn_plan_create", "pinn_plan_destroy", "pinn_plan_memory", "pinn_je
            "pinn_plan_set_tuning", "pinn_plan_autotune", "pinn_batch_create", "pinn_batch_destroy",
            "pinn_batch_configure", "pinn_batch_step", "pinn_batch_autotune"]
 KERNEL_CLASSES = {"layer_fwd": 1, "layer_bwd": 2, "dw_hidden": 3, "out_fwd": 4, "out_bwd": 5,
-                  "seed_fwd": 6, "other": 7}
+                  "seed_fwd": 6, "other": 7, "bwd_dw": 8}
 
 
 class PinnError(RuntimeError):

@@ -538,7 +538,7 @@ pinn_status pinn_plan_memory(pinn_plan plan, size_t *saved_bytes, size_t *worksp
 pinn_status pinn_plan_profile(pinn_plan plan, int32_t kernel_class) {
   g_err.clear();
   if (!plan) return fail(PINN_ERR_ARG, "plan is NULL");
-  if (kernel_class < 0 || kernel_class > PINN_K_OTHER)
+  if (kernel_class < 0 || kernel_class > PINN_K_BWD_DW)
     return fail(PINN_ERR_ARG, "unknown kernel class %d", kernel_class);
   plan->prof_class = kernel_class;
   plan->ev_used = 0;
@@ -685,7 +685,7 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
       B.top = false;
       B.Zb_in = p->Zb[l % 2];
       B.WT = p->WTop[l];
-      rs = layer(B, l - 1, PINN_K_LAYER_BWD);
+      rs = layer(B, l - 1, PINN_K_BWD_DW);
       if (rs) return rs;
     }
     // zbar of layer 1 (its z comes from x; its gradient is the thin seed kernel's)
