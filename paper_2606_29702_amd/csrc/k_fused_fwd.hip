@@ -22,6 +22,24 @@
 
 namespace pj {
 
+// Copy of the block's stack (P rows of C w elements, LDS pitch `pitch`) to
+// global memory, where the rows are contiguous, in 16-byte pieces.  With
+// per_row pieces per row and R = max(1, NT / per_row) rows per sweep, thread
+// t owns piece columns t % per_row (+ NT, ...) of rows t / per_row (+ R, ...),
+// so its addresses advance by constant strides.  Threads with t / per_row >= R
+// idle.
+template <class T, int NT, int P>
+__device__ __forceinline__ void copy_out_rows(T *g, const T *lds, int row_elems, int pitch, int row0, int col) {
+  constexpr int per16 = 16 / (int)sizeof(T);
+  const int per_row = row_elems / per16;
+  const int R = per_row <= NT ? NT / per_row : 1;
+  if (row0 >= R) return;
+  for (int row = row0; row < P; row += R)
+    for (int c = col; c < per_row; c += NT)
+      *reinterpret_cast<uint4 *>(g + row * row_elems + c * per16) =
+          *reinterpret_cast<const uint4 *>(lds + row * pitch + c * per16);
+}
+
 template <class PDE, class T, int NW, int TPW, int P>
 __global__ __launch_bounds__(NW * 64) void k_fwd_fused(FusedFwdArgs a) {
   using CH = typename PDE::CH;
@@ -49,6 +67,9 @@ __global__ __launch_bounds__(NW * 64) void k_fwd_fused(FusedFwdArgs a) {
   const int jt0 = tile0 % NJ;
   const int p_l = nt * 16 + r;  // this lane's point within the block
   const int64_t n_l = nb + p_l;
+  // this thread's place in the stack copy-out (row and 16-byte column)
+  const int per_row16 = C * w * (int)sizeof(T) / 16;
+  const int out_row0 = tid / per_row16, out_col = tid - out_row0 * per_row16;
 
   // ---- input of layer l_first: the seed layer from x, or a saved stack
   if (a.l_first == 1) {
@@ -87,7 +108,7 @@ __global__ __launch_bounds__(NW * 64) void k_fwd_fused(FusedFwdArgs a) {
       }
     }
     __syncthreads();
-    if (a.A[1]) unstage_rows<T, 8>(static_cast<T *>(a.A[1]) + nb * gps, stk, P, C * w, pitch, tid, NT);
+    if (a.A[1]) copy_out_rows<T, NT, P>(static_cast<T *>(a.A[1]) + nb * gps, stk, C * w, pitch, out_row0, out_col);
   } else {
     // the saved stack of layer l_first - 1, coalesced 16-byte pieces
     stage_rows<T, 8, false>(stk, static_cast<const T *>(a.A_in) + nb * gps, nullptr, P, C * w, pitch, tid, NT);
@@ -154,7 +175,7 @@ __global__ __launch_bounds__(NW * 64) void k_fwd_fused(FusedFwdArgs a) {
     __syncthreads();  // layer l's stack complete in LDS
 
     if (a.A[l])  // coalesced copy of the block's stack to global memory
-      unstage_rows<T, 8>(static_cast<T *>(a.A[l]) + nb * gps, stk, P, C * w, pitch, tid, NT);
+      copy_out_rows<T, NT, P>(static_cast<T *>(a.A[l]) + nb * gps, stk, C * w, pitch, out_row0, out_col);
   }
 
   // ---- output layer, residual, loss partial: TPP threads per point
