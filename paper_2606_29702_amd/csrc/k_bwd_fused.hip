@@ -275,12 +275,248 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_dw(BwdArgs args, float *__restr
   if (tid < W) pp[(int64_t)W * W + tid] = db;
 }
 
+// Double-buffered form of k_bwd_dw for 16-bit operands below the top layer,
+// with z recomputed from A_{m-1}.  The tiles are stored in LDS without row
+// padding: 16-byte piece c of row p sits at piece position c ^ p of that row
+// (rows of a multiple of 16 pieces), which keeps the 16 points of an MFMA
+// operand read on different banks.  While a tile's jet adjoint and dW run,
+// the next tile's Zbar_{m+1} and A_{m-1} stream into the other buffer pair
+// with direct-to-LDS loads, so their HBM latency is hidden.  Every global load
+// a tile waits on (weight fragments, biases) is issued before that prefetch,
+// since the load counter completes in order.
+// The double-buffered kernel applies to 16-bit operands when a row is a
+// multiple of 16 pieces and the four tile buffers fit in 80 KB (two
+// workgroups per CU).
+template <class T>
+constexpr bool bwd_db_ok(int C, int W) {
+  return sizeof(T) == 2 && (C * W / 8) % 16 == 0 && 4 * 16 * C * W * 2 <= 80 * 1024;
+}
+
+template <class T, int C, int W>
+struct SwzTile {
+  static constexpr int RE = C * W;         // elements per row (one point)
+  static constexpr int PER_ROW = RE / 8;   // 16-byte pieces per row
+  static constexpr int ELEMS = 16 * RE;    // one 16-point tile
+  static_assert(sizeof(T) == 2 && PER_ROW % 16 == 0, "swizzled tile shape");
+  // element e of row p
+  static __device__ __forceinline__ int at(int p, int e) { return p * RE + ((((e >> 3) ^ p)) << 3) + (e & 7); }
+};
+
+template <class T, int C, int W, int NW>
+__device__ __forceinline__ void prefetch_tile(T *dst, const T *src, int wave, int lane) {
+  using L = SwzTile<T, C, W>;
+  constexpr int TOTAL = 16 * L::PER_ROW;  // pieces, a multiple of 256
+#pragma unroll 1
+  for (int q0 = 0; q0 < TOTAL; q0 += NW * 64) {
+    const int qw = __builtin_amdgcn_readfirstlane(q0 + wave * 64);  // this wave's 64 pieces
+    const int q = qw + lane;
+    const int p = q / L::PER_ROW, cs = q - p * L::PER_ROW;
+    // LDS piece q (row p, position cs) holds source piece cs ^ p of row p
+    __builtin_amdgcn_global_load_lds((const void *)(src + p * L::RE + ((cs ^ p) << 3)),
+                                     (__attribute__((address_space(3))) void *)(dst + qw * 8), 16, 0, 0);
+  }
+}
+
+template <class T, int C, int TPW, int W>
+__device__ __forceinline__ void swz_gemm(f32x4 (&acc)[TPW][C], const T *__restrict__ Wop, const T *stk, int jt0,
+                                         int lane) {
+  using M = Mma<T>;
+  using L = SwzTile<T, C, W>;
+  const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int t = 0; t < TPW; ++t)
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const T *wrow = Wop + (int64_t)(jt0 * 16 + r) * W + 8 * g;
+  const T *row = stk + r * L::RE;
+  typename M::frag fa[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) fa[t] = M::load(wrow + (int64_t)t * 16 * W);
+  // unrolled by two only: a full unroll hoists every operand read and costs
+  // the second wave per SIMD
+#pragma unroll 2
+  for (int kk = 0; kk < W / 32; ++kk) {
+    typename M::frag fb[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) fb[c] = M::load(row + ((((c * W + kk * 32) >> 3) + g) ^ r) * 8);
+    typename M::frag fn[TPW];
+    const int kn = kk + 1 < W / 32 ? kk + 1 : kk;  // the next weight fragments
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) fn[t] = M::load(wrow + (int64_t)t * 16 * W + kn * 32);
+#pragma unroll
+    for (int t = 0; t < TPW; ++t)
+#pragma unroll
+      for (int c = 0; c < C; ++c) M::mma(acc[t][c], fa[t], fb[c]);
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) fa[t] = fn[t];
+  }
+}
+
+template <class CH, class T, int W, int NW, int TPW, int DOUT>
+__global__ __launch_bounds__(NW * 64) void k_bwd_dw_db(BwdArgs args, float *__restrict__ part, int64_t n_tiles) {
+  using M = Mma<T>;
+  using M16 = Mma16<T>;
+  using L = SwzTile<T, CH::C, W>;
+  constexpr int C = CH::C, P = 16;
+  constexpr int JW = W / NW;
+  constexpr int JT = JW / 16, KT = W / 16, KS = W / 32;
+  constexpr int ROWS = P * C;
+  static_assert(JW % 16 == 0 && ROWS % 16 == 0, "tile shape");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *buf = reinterpret_cast<T *>(smem_raw);  // [Zbar 0][A 0][Zbar 1][A 1]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  constexpr int64_t ps = (int64_t)C * W;
+  const int jt0 = wave * TPW;
+  const T *Zb_in = static_cast<const T *>(args.Zb_in);
+  const T *A_prev = static_cast<const T *>(args.A_prev);
+  const T *WT = static_cast<const T *>(args.WT);
+  const T *Wz = static_cast<const T *>(args.Wz);
+  T *Zb_out = static_cast<T *>(args.Zb_out);
+
+  f32x4 dacc[JT][KT];
+#pragma unroll
+  for (int a = 0; a < JT; ++a)
+#pragma unroll
+    for (int b = 0; b < KT; ++b) dacc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float db = 0.f;
+
+  if (blockIdx.x < n_tiles) {
+    const int64_t nb = (int64_t)blockIdx.x * P;
+    prefetch_tile<T, C, W, NW>(buf, Zb_in + nb * ps, wave, lane);
+    prefetch_tile<T, C, W, NW>(buf + L::ELEMS, A_prev + nb * ps, wave, lane);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+
+  int cur = 0;
+  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const int64_t nb = tile * P;
+    T *zb_t = buf + (2 * cur) * L::ELEMS;
+    T *a_t = buf + (2 * cur + 1) * L::ELEMS;
+
+    // the GEMMs (their weight fragments stream from L2 ahead of use)
+    f32x4 acc_a[TPW][C], acc_z[TPW][C];
+    swz_gemm<T, C, TPW, W>(acc_a, WT, zb_t, jt0, lane);
+    swz_gemm<T, C, TPW, W>(acc_z, Wz, a_t, jt0, lane);
+    // tanh of the recomputed z_0 (with the bias, a global load) before the
+    // prefetch below is issued: the load counter completes in order, so any
+    // load waited on after the prefetch would wait for the prefetch too
+    float sv[TPW][4], s1v[TPW][4];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const TanhS ts = tanh_eval<true>(acc_z[t][0][i] + args.bz[(jt0 + t) * 16 + 4 * g + i]);
+        sv[t][i] = ts.s;
+        s1v[t][i] = ts.s1;
+      }
+    __syncthreads();  // the Zbar_{m+1} tile is consumed; it now receives Zbar_m
+
+    // the next tile streams into the other buffer pair during the adjoint and
+    // dW; every load issued so far completes first, so that no later wait on
+    // them also waits for the prefetch
+    __builtin_amdgcn_s_waitcnt(0);
+    const int64_t next = tile + gridDim.x;
+    if (next < n_tiles) {
+      T *zb_n = buf + (2 * (cur ^ 1)) * L::ELEMS;
+      prefetch_tile<T, C, W, NW>(zb_n, Zb_in + next * P * ps, wave, lane);
+      prefetch_tile<T, C, W, NW>(zb_n + L::ELEMS, A_prev + next * P * ps, wave, lane);
+    }
+
+    const int64_t n = nb + r;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int mb = (jt0 + t) * 16 + 4 * g;
+      float zz[4][C], s1[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int c = 1; c < C; ++c) zz[i][c] = acc_z[t][c][i];
+        zz[i][0] = sv[t][i];
+        s1[i] = s1v[t][i];
+      }
+      float out[4][C];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float ab[C], zb[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) ab[c] = acc_a[t][c][i];
+        jet_adjoint<CH>(ab, zz[i][0], s1[i], zz[i], zb);
+#pragma unroll
+        for (int c = 0; c < C; ++c) out[i][c] = zb[c];
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        store4(Zb_out + n * ps + c * W + mb, out[0][c], out[1][c], out[2][c], out[3][c]);
+        store4(zb_t + L::at(r, c * W + mb), out[0][c], out[1][c], out[2][c], out[3][c]);
+      }
+    }
+    // Zbar_m tile complete in LDS.  A plain barrier after the LDS stores have
+    // completed: a full __syncthreads() would also wait for the prefetch.
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+
+    if (tid < W) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) db += to_f32(zb_t[L::at(p, tid)]);
+    }
+    // dW_m += Zbar_m^T A_{m-1}: 16 rows (point, channel) per step; LDS
+    // transpose reads give each lane column r of rows 16 s + 4 g .. + 3
+#pragma unroll 1
+    for (int s = 0; s < ROWS / 16; ++s) {
+      const int row = 16 * s + 4 * g + (r >> 2);
+      const int p = row / C, ch = row - p * C;
+      const int half = 4 * (r & 1);
+      typename M16::frag fa[JT], fb[KT];
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt) {
+        const int piece = ((ch * W + wave * JW + jt * 16) >> 3) + ((r & 3) >> 1);
+        fa[jt] = lds_tr16<T>(zb_t + p * L::RE + ((piece ^ p) << 3) + half);
+      }
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt) {
+        const int piece = ((ch * W + kt * 16) >> 3) + ((r & 3) >> 1);
+        fb[kt] = lds_tr16<T>(a_t + p * L::RE + ((piece ^ p) << 3) + half);
+      }
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt)
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) M16::mma(dacc[jt][kt], fa[jt], fb[kt]);
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // the next tile has landed
+    __syncthreads();                // and this tile's buffers are free
+    cur ^= 1;
+  }
+
+  float *pp = part + (int64_t)blockIdx.x * ((int64_t)W * W + W);
+#pragma unroll
+  for (int jt = 0; jt < JT; ++jt)
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int j = wave * JW + jt * 16 + 4 * g + i;
+        const int k = kt * 16 + r;
+        pp[(int64_t)j * W + k] = dacc[jt][kt][i];
+      }
+  if (tid < W) pp[(int64_t)W * W + tid] = db;
+}
+
 namespace {
 
 template <class CH, class T, int W, bool TOP, int DOUT, int ZSRC>
 hipError_t launch_w(const BwdArgs &a, float *part, int64_t n_tiles, int grid, hipStream_t st) {
   constexpr int NW = W == 32 ? 2 : (W == 256 ? 8 : 4);
   constexpr int TPW = (W / 16) / NW;
+  if constexpr (!TOP && ZSRC == Z_FROM_GEMM && bwd_db_ok<T>(CH::C, W)) {
+    constexpr size_t lds = (size_t)4 * SwzTile<T, CH::C, W>::ELEMS * sizeof(T);
+    auto kfn = k_bwd_dw_db<CH, T, W, NW, TPW, DOUT>;
+    hipError_t e = hipFuncSetAttribute((const void *)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kfn, dim3((unsigned)grid), dim3(NW * 64), lds, st, a, part, n_tiles);
+    return hipGetLastError();
+  }
   constexpr size_t lds = (size_t)2 * 16 * (CH::C * W + 8) * sizeof(T);
   auto kfn = k_bwd_dw<CH, T, W, NW, TPW, TOP, DOUT, ZSRC>;
   hipError_t e = hipFuncSetAttribute((const void *)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

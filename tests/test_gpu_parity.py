@@ -291,3 +291,55 @@ def test_fused_and_separate_weight_gradients_agree(lib, pde, dims, prec):
         print(pde, prec, f"grad rel {rel(g, ref.grad):.2e} cos {cos:.6f}")
         assert rel(g, ref.grad) <= tol and cos > 0.99
     assert rel(gs[0], gs[1]) <= (2e-6 if prec == "fp32" else 2e-2)
+
+
+@pytest.mark.parametrize("pde,dims", [("ns", [2, 128, 128, 128, 128, 3]), ("burgers", [2, 32, 32, 32, 32, 1]),
+                                      ("heat", [4, 64, 64, 64, 1])])
+def test_fused_backward_many_tiles(lib, pde, dims):
+    """BF16 fused backward with several 16-point tiles per persistent
+    workgroup (the next tile streams in while the current one is processed):
+    against the separate kernels, the oracle, and itself run to run."""
+    N = 20000
+    prob = pi.make_problem(pde, N=N, seed=41, bias_std=0.3, dims=dims)
+    params = dev_params(prob.params)
+    x = torch.tensor(prob.x, device="cuda")
+    gs = []
+    for fused in (1, 1, 0):
+        plan = lib.PinnPlan(dims, pde, N, precision="bf16", coef=prob.coef)
+        t = plan.tuning()
+        plan.set_tuning(t["dw_splits"], t["fwd_points"], fused)
+        plan.residual(params, x)
+        gs.append(flat(plan.backward(params, x)))
+        plan.close()
+    assert np.array_equal(gs[0], gs[1])
+    ref = oracle.evaluate(prob.params, prob.x, prob.channels, pde, prob.coef)
+    for g in gs:
+        cos = float(g @ ref.grad / (np.linalg.norm(g) * np.linalg.norm(ref.grad)))
+        print(pde, f"grad rel {rel(g, ref.grad):.2e} cos {cos:.6f}")
+        assert rel(g, ref.grad) <= 0.2 and cos > 0.99
+    assert rel(gs[0], gs[2]) <= 2e-2
+
+
+@pytest.mark.parametrize("pde,dims", [("ns", [2, 128, 128, 128, 128, 128, 3]), ("heat", [4, 64, 64, 64, 64, 1])])
+def test_fused_backward_checkpointed_bitwise(lib, pde, dims):
+    """The fused backward reading recomputed stacks (checkpointed plan) equals
+    the store-all plan bit for bit."""
+    N = 5000
+    prob = pi.make_problem(pde, N=N, seed=43, bias_std=0.3, dims=dims)
+    C = len(prob.channels)
+    npad = (N + 127) // 128 * 128
+    stack = npad * C * dims[1] * 2
+    params = dev_params(prob.params)
+    x = torch.tensor(prob.x, device="cuda")
+    outs = []
+    for cap in (0, stack + stack // 2):
+        plan = lib.PinnPlan(dims, pde, N, precision="bf16", save_cap_bytes=cap, coef=prob.coef)
+        t = plan.tuning()
+        plan.set_tuning(t["dw_splits"], t["fwd_points"], 1)
+        r, loss, _, _ = plan.residual(params, x)
+        grads = plan.backward(params, x)
+        torch.cuda.synchronize()
+        outs.append((r.cpu().numpy(), flat(grads)))
+        plan.close()
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
