@@ -362,8 +362,10 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_dw_db(BwdArgs args, float *__re
   constexpr int JT = JW / 16, KT = W / 16, KS = W / 32;
   constexpr int ROWS = P * C;
   static_assert(JW % 16 == 0 && ROWS % 16 == 0, "tile shape");
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *buf = reinterpret_cast<T *>(smem_raw);  // [Zbar 0][A 0][Zbar 1][A 1]
+  // two buffer pairs [Zbar][A] as separate objects, so that the compiler can
+  // tell the pair being prefetched from the pair being read
+  __shared__ __align__(16) T pair0[2 * L::ELEMS];
+  __shared__ __align__(16) T pair1[2 * L::ELEMS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r = lane & 15, g = lane >> 4;
   constexpr int64_t ps = (int64_t)C * W;
@@ -383,17 +385,17 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_dw_db(BwdArgs args, float *__re
 
   if (blockIdx.x < n_tiles) {
     const int64_t nb = (int64_t)blockIdx.x * P;
-    prefetch_tile<T, C, W, NW>(buf, Zb_in + nb * ps, wave, lane);
-    prefetch_tile<T, C, W, NW>(buf + L::ELEMS, A_prev + nb * ps, wave, lane);
+    prefetch_tile<T, C, W, NW>(pair0, Zb_in + nb * ps, wave, lane);
+    prefetch_tile<T, C, W, NW>(pair0 + L::ELEMS, A_prev + nb * ps, wave, lane);
   }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 
-  int cur = 0;
-  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+  // one tile in buffer pair `cur`; the next one streams into pair `nxt`
+  auto step = [&](int64_t tile, T *cur, T *nxt) __attribute__((always_inline)) {
     const int64_t nb = tile * P;
-    T *zb_t = buf + (2 * cur) * L::ELEMS;
-    T *a_t = buf + (2 * cur + 1) * L::ELEMS;
+    T *zb_t = cur;
+    T *a_t = cur + L::ELEMS;
 
     // the GEMMs (their weight fragments stream from L2 ahead of use)
     f32x4 acc_a[TPW][C], acc_z[TPW][C];
@@ -419,9 +421,8 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_dw_db(BwdArgs args, float *__re
     __builtin_amdgcn_s_waitcnt(0);
     const int64_t next = tile + gridDim.x;
     if (next < n_tiles) {
-      T *zb_n = buf + (2 * (cur ^ 1)) * L::ELEMS;
-      prefetch_tile<T, C, W, NW>(zb_n, Zb_in + next * P * ps, wave, lane);
-      prefetch_tile<T, C, W, NW>(zb_n + L::ELEMS, A_prev + next * P * ps, wave, lane);
+      prefetch_tile<T, C, W, NW>(nxt, Zb_in + next * P * ps, wave, lane);
+      prefetch_tile<T, C, W, NW>(nxt + L::ELEMS, A_prev + next * P * ps, wave, lane);
     }
 
     const int64_t n = nb + r;
@@ -486,7 +487,13 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_dw_db(BwdArgs args, float *__re
     }
     __builtin_amdgcn_s_waitcnt(0);  // the next tile has landed
     __syncthreads();                // and this tile's buffers are free
-    cur ^= 1;
+  };
+  for (int64_t tile = blockIdx.x; tile < n_tiles;) {
+    step(tile, pair0, pair1);
+    tile += gridDim.x;
+    if (tile >= n_tiles) break;
+    step(tile, pair1, pair0);
+    tile += gridDim.x;
   }
 
   float *pp = part + (int64_t)blockIdx.x * ((int64_t)W * W + W);
@@ -510,11 +517,8 @@ hipError_t launch_w(const BwdArgs &a, float *part, int64_t n_tiles, int grid, hi
   constexpr int NW = W == 32 ? 2 : (W == 256 ? 8 : 4);
   constexpr int TPW = (W / 16) / NW;
   if constexpr (!TOP && ZSRC == Z_FROM_GEMM && bwd_db_ok<T>(CH::C, W)) {
-    constexpr size_t lds = (size_t)4 * SwzTile<T, CH::C, W>::ELEMS * sizeof(T);
-    auto kfn = k_bwd_dw_db<CH, T, W, NW, TPW, DOUT>;
-    hipError_t e = hipFuncSetAttribute((const void *)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kfn, dim3((unsigned)grid), dim3(NW * 64), lds, st, a, part, n_tiles);
+    hipLaunchKernelGGL((k_bwd_dw_db<CH, T, W, NW, TPW, DOUT>), dim3((unsigned)grid), dim3(NW * 64), 0, st, a, part,
+                       n_tiles);
     return hipGetLastError();
   }
   constexpr size_t lds = (size_t)2 * 16 * (CH::C * W + 8) * sizeof(T);
