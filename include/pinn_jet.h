@@ -141,7 +141,8 @@ pinn_status pinn_jet_residual(pinn_plan plan, const pinn_net *net, const pinn_pd
 
 /* Parameter gradient by the hand-written adjoint of the jet recursion.
  * Must follow pinn_jet_residual on the same plan with the same net
- * parameter pointers, x and N (PINN_ERR_STATE otherwise).
+ * parameter pointers, x and N (PINN_ERR_STATE otherwise), and the parameter
+ * values of that call (the operand-type weight copies it made are reused).
  *   r_bar    n_res x N cotangent of r, or NULL for the loss gradient (2 r / N)
  *   dW, db   host arrays of n_layers device pointers shaped like W and b;
  *            overwritten with J^T r_bar (or dL/dtheta)
@@ -161,7 +162,8 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
  *               (0 = the largest tiling whose stack fits in LDS, else 16 or 32)
  *   bwd_fused   1: hidden-layer weight gradients are accumulated inside the
  *               persistent backward layer kernels where the width allows
- *               (32, 64, 128); 0 (default): separate split-K gradient kernels */
+ *               (32, 64, 128); 0: separate split-K gradient kernels.  Default:
+ *               1 for 16-bit operands where supported, else 0. */
 typedef struct {
   int32_t dw_splits;
   int32_t fwd_points;

@@ -334,7 +334,9 @@ pinn_status run_forward(pinn_plan p, const pinn_net *net, const pinn_pde *pde, c
                         bool save_state, hipStream_t st) {
   const int64_t npad = round_up(N, pj::kPointTile);
   const int H = p->H;
-  pinn_status rs = cast_weights(p, net, false, st);
+  // operand-type weights; a residual call (save_state) also makes the
+  // transposed copies its backward pass uses
+  pinn_status rs = cast_weights(p, net, save_state, st);
   if (rs) return rs;
   // stacks of non-checkpoint layers from an earlier backward are stale now
   for (int l = 1; l <= H; ++l)
@@ -506,6 +508,9 @@ pinn_status pinn_plan_create(const pinn_net *net, const pinn_pde *pde, int64_t m
   A(reinterpret_cast<void **>(&p->loss_part64), (size_t)(npad / 16) * sizeof(double));
   p->dw_splits = dw_splits_for(npad, ki.C, w);
   p->dw_splits_max = 2 * p->dw_splits;
+  // 16-bit operands: weight gradients fused into the backward layer kernels
+  // where the width allows (the faster variant measured on the NS workload)
+  p->bwd_fused = (prec != PINN_FP32 && pj::bwd_dw_fused_supported(ki.C, w, prec)) ? 1 : 0;
   p->thin_chunks = (int)std::max<int64_t>(1, npad / 64);
   const size_t part_elems =
       std::max<size_t>((size_t)p->dw_splits_max * ((size_t)w * w + w),
@@ -618,8 +623,8 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
   const KindInfo &ki = p->ki;
   auto f64 = [&](double *const *arr, int l) -> double * { return arr ? arr[l] : nullptr; };
   hipError_t e;
-  pinn_status rs = cast_weights(p, net, true, s);
-  if (rs) return rs;
+  // the operand-type weights W and W^T were made by the residual call
+  pinn_status rs = PINN_OK;
   // Source of z for the adjoint of activation layer m: the saved state, or a
   // recompute from the stack of layer m - 1 (m >= 2) or from x (m = 1).
   auto zsrc = [&](pj::LayerBwd &B, int m) -> pinn_status {
