@@ -272,33 +272,55 @@ __global__ __launch_bounds__(256) void k_dw_out(const float *__restrict__ ubar, 
                                                 int64_t pts_per_chunk) {
   constexpr int C = PDE::CH::C, DOUT = PDE::DOUT;
   __shared__ float red[2048 * DOUT];  // (256 / (w/8)) groups x DOUT x w = 2048 * DOUT
+  __shared__ float red_b[256 * DOUT];  // per row group: sum of ubar over value rows
   const int lpr = w / 8, rgs = 256 / lpr;
   const int q = threadIdx.x % lpr, rg = threadIdx.x / lpr;
   const int64_t nb = (int64_t)blockIdx.x * pts_per_chunk;
   const int64_t ne = nb + pts_per_chunk < N_pad ? nb + pts_per_chunk : N_pad;
   const int rows = (int)(ne > nb ? (ne - nb) * C : 0);
-  float acc[DOUT][8];
+  float acc[DOUT][8], accb[DOUT];
 #pragma unroll
-  for (int o = 0; o < DOUT; ++o)
+  for (int o = 0; o < DOUT; ++o) {
+    accb[o] = 0.f;
 #pragma unroll
     for (int e = 0; e < 8; ++e) acc[o][e] = 0.f;
+  }
   if (rg < rgs) {
-    for (int rr = rg; rr < rows; rr += rgs) {
-      const int64_t n = nb + rr / C;
-      const int c = rr % C;
-      float a[8];
-      load8f<T>(AH + (n * C + c) * w + 8 * q, a);
+    // four rows per round, all loads issued before the arithmetic; rows past
+    // the end re-read the round's first row (in bounds) and are not added
+    constexpr int B = 4;
+    for (int rr0 = rg; rr0 < rows; rr0 += B * rgs) {
+      float a[B][8], u[B][DOUT];
+      bool val[B];
 #pragma unroll
-      for (int o = 0; o < DOUT; ++o) {
-        const float u = ubar[(n * DOUT + o) * C + c];
+      for (int b = 0; b < B; ++b) {
+        const int rr = rr0 + b * rgs < rows ? rr0 + b * rgs : rr0;
+        const int64_t n = nb + rr / C;
+        const int c = rr % C;
+        val[b] = c == 0;
+        load8f<T>(AH + (n * C + c) * w + 8 * q, a[b]);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) acc[o][e] += u * a[e];
+        for (int o = 0; o < DOUT; ++o) u[b][o] = ubar[(n * DOUT + o) * C + c];
+      }
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        if (rr0 + b * rgs < rows) {
+#pragma unroll
+          for (int o = 0; o < DOUT; ++o) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) acc[o][e] += u[b][o] * a[b][e];
+            if (val[b]) accb[o] += u[b][o];  // db_L: value rows
+          }
+        }
       }
     }
 #pragma unroll
     for (int o = 0; o < DOUT; ++o)
 #pragma unroll
       for (int e = 0; e < 8; ++e) red[(rg * DOUT + o) * w + 8 * q + e] = acc[o][e];
+    if (q == 0)
+#pragma unroll
+      for (int o = 0; o < DOUT; ++o) red_b[rg * DOUT + o] = accb[o];
   }
   __syncthreads();
   const int64_t stride = (int64_t)DOUT * w + DOUT;
@@ -310,7 +332,7 @@ __global__ __launch_bounds__(256) void k_dw_out(const float *__restrict__ ubar, 
   }
   if (threadIdx.x < DOUT) {
     float sum = 0.f;
-    for (int64_t n = nb; n < ne; ++n) sum += ubar[(n * DOUT + threadIdx.x) * C];
+    for (int g2 = 0; g2 < rgs; ++g2) sum += red_b[g2 * DOUT + threadIdx.x];
     pp[DOUT * w + threadIdx.x] = sum;
   }
 }
