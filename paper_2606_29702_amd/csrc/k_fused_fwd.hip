@@ -178,41 +178,65 @@ __global__ __launch_bounds__(NW * 64) void k_fwd_fused(FusedFwdArgs a) {
       copy_out_rows<T, NT, P>(static_cast<T *>(a.A[l]) + nb * gps, stk, C * w, pitch, out_row0, out_col);
   }
 
-  // ---- output layer, residual, loss partial: TPP threads per point
+  // ---- output layer on MFMA, residual, loss partial.  Wave v < P / 16 takes
+  // the point tile v: U_c = W_L A_c for every channel c, with W_L as the A
+  // operand (rows = outputs, padded to 16 with zeros) and the stack as the B
+  // operand.  For 16-bit stacks W_L enters as a pair of 16-bit parts (value
+  // and remainder), which keeps the product at FP32-level accuracy.  Lane l
+  // of the output tile holds point l % 16 and outputs 4 (l / 16) + 0..3, so
+  // lanes 0..15 hold every output of their point.
   if (!a.do_output) return;
-  constexpr int TPP = NT / P;
-  {
-    const int p = tid / TPP, q = tid % TPP;
-    const int64_t n = nb + p;
-    float u[DOUT][C];
+  static_assert(DOUT <= 4, "outputs per point");
+  if (wave < P / 16) {
+    const int pt = wave;
+    f32x4 uacc[C];
 #pragma unroll
-    for (int o = 0; o < DOUT; ++o)
+    for (int c = 0; c < C; ++c) uacc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const T *brow = stk + (pt * 16 + r) * pitch + 8 * g;
+    for (int k = 0; k < w; k += 32) {
+      float wv[8];
 #pragma unroll
-      for (int c = 0; c < C; ++c) u[o][c] = 0.f;
-    for (int k = q; k < w; k += TPP) {
-      float wv[DOUT];
+      for (int e = 0; e < 8; ++e) wv[e] = r < DOUT ? a.WL[r * w + k + 8 * g + e] : 0.f;
+      typename M::frag fb[C];
 #pragma unroll
-      for (int o = 0; o < DOUT; ++o) wv[o] = a.WL[o * w + k];
+      for (int c = 0; c < C; ++c) fb[c] = M::load(brow + c * w + k);
+      if constexpr (sizeof(T) == 2) {
+        typename M::frag whi, wlo;
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const float av = to_f32(stk[p * pitch + c * w + k]);
+        for (int e = 0; e < 8; ++e) {
+          const T h = static_cast<T>(wv[e]);
+          whi[e] = h;
+          wlo[e] = static_cast<T>(wv[e] - static_cast<float>(h));
+        }
 #pragma unroll
-        for (int o = 0; o < DOUT; ++o) u[o][c] += wv[o] * av;
+        for (int c = 0; c < C; ++c) {
+          M::mma(uacc[c], whi, fb[c]);
+          M::mma(uacc[c], wlo, fb[c]);
+        }
+      } else {
+        typename M::frag wf;
+        wf.lo = f32x4{wv[0], wv[1], wv[2], wv[3]};
+        wf.hi = f32x4{wv[4], wv[5], wv[6], wv[7]};
+#pragma unroll
+        for (int c = 0; c < C; ++c) M::mma(uacc[c], wf, fb[c]);
       }
     }
+    if (g == 0) {
+      const int p = pt * 16 + r;
+      const int64_t n = nb + p;
+      float u[DOUT][C];
 #pragma unroll
-    for (int o = 0; o < DOUT; ++o) {
+      for (int o = 0; o < DOUT; ++o)
 #pragma unroll
-      for (int c = 0; c < C; ++c) u[o][c] = group_sum<TPP>(u[o][c]);
-      u[o][0] += a.bL[o];
-    }
-    const bool valid = n < a.N;
-    float xin[D];
+        for (int c = 0; c < C; ++c) u[o][c] = uacc[c][o];
 #pragma unroll
-    for (int i = 0; i < D; ++i) xin[i] = valid ? a.x[n * D + i] : 0.f;
-    float rr[NRES];
-    PDE::residual(u, xin, a.k, rr);
-    if (q == 0) {
+      for (int o = 0; o < DOUT; ++o) u[o][0] += a.bL[o];
+      const bool valid = n < a.N;
+      float xin[D];
+#pragma unroll
+      for (int i = 0; i < D; ++i) xin[i] = valid ? a.x[n * D + i] : 0.f;
+      float rr[NRES];
+      PDE::residual(u, xin, a.k, rr);
       float l32 = 0.f;
       double l64 = 0.0;
       if (valid) {
