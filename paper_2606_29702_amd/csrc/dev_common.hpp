@@ -160,29 +160,4 @@ __device__ __forceinline__ void stage_rows(T *lds, const T *g0, const T *g1, int
   }
 }
 
-// LDS -> global, one block.
-template <class T, int NB>
-__device__ __forceinline__ void unstage_rows(T *g, const T *lds, int rows, int row_elems, int pitch, int tid,
-                                             int nthreads) {
-  constexpr int per16 = 16 / (int)sizeof(T);
-  const int per_row = row_elems / per16;
-  const int total = rows * per_row;
-  const int pad = pitch - row_elems;
-  PieceWalk it(tid, nthreads, per_row);
-  while (it.q < total) {
-    uint4 v[NB];
-    int dst[NB];
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      const bool live = it.q < total;
-      v[u] = live ? *reinterpret_cast<const uint4 *>(lds + it.q * per16 + it.row * pad) : uint4{0u, 0u, 0u, 0u};
-      dst[u] = live ? it.q * per16 : -1;
-      it.next();
-    }
-#pragma unroll
-    for (int u = 0; u < NB; ++u)
-      if (dst[u] >= 0) *reinterpret_cast<uint4 *>(g + dst[u]) = v[u];
-  }
-}
-
 }  // namespace pj

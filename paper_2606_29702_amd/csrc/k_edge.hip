@@ -599,11 +599,6 @@ hipError_t launch_dw_seed(int kind, int prec, const void *Zb_1, const float *x, 
   });
 }
 
-hipError_t launch_reduce_parts(const float *part, int splits, int64_t stride, int64_t M,
-                               float *out32, double *out64, hipStream_t st) {
-  return launch_reduce_parts2(part, splits, stride, M, 0, out32, nullptr, out64, nullptr, st);
-}
-
 hipError_t launch_reduce_parts2(const float *part, int splits, int64_t stride, int64_t M1,
                                 int64_t M2, float *a32, float *b32, double *a64, double *b64,
                                 hipStream_t st) {

@@ -153,13 +153,10 @@ int dw_tile(int w);  // dW workgroup tile edge (128, 64 or 32)
 hipError_t launch_dw_hidden(int prec, int C, const void *Zb, const void *A_prev, int64_t N_pad, int w,
                             float *part, float *part_db, int splits, hipStream_t st);
 
-// out[q] = sum_s part[s * stride + q] for q < M, summed in s order; FP32
-// result into out32 (may be null), FP64 into out64 (may be null).
-hipError_t launch_reduce_parts(const float *part, int splits, int64_t stride, int64_t M,
-                               float *out32, double *out64, hipStream_t st);
-
-// Same, where the M values are scattered into two destinations: q < M1 goes
-// to a[q], q >= M1 to b[q - M1] (used for packed dW/db partials).
+// out[q] = sum_s part[s * stride + q] for q < M1 + M2, summed in a fixed
+// order (deterministic), scattered into two destinations: q < M1 goes to
+// a[q], q >= M1 to b[q - M1] (packed dW/db partials).  FP32 results into
+// a32/b32, FP64 sums of the same partials into a64/b64; each may be null.
 hipError_t launch_reduce_parts2(const float *part, int splits, int64_t stride, int64_t M1,
                                 int64_t M2, float *a32, float *b32, double *a64, double *b64,
                                 hipStream_t st);
