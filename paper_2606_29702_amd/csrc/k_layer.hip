@@ -340,6 +340,12 @@ __global__ __launch_bounds__(NW * 64) void k_layer_bwd_lds(BwdArgs args) {
 
   T *Zb_out = static_cast<T *>(args.Zb_out);
   const int64_t n = nb + nt * 16 + r;
+  // the point's inputs: for the first layer's z, or for its gradient
+  float xin[D];
+  if (ZSRC == Z_FROM_X || (ZSRC == Z_FROM_S && !TOP && args.seed_part)) {
+#pragma unroll
+    for (int q = 0; q < D; ++q) xin[q] = n < args.N ? args.x[n * D + q] : 0.f;
+  }
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
     const int mb = (jt0 + t) * 16 + 4 * g;
@@ -363,9 +369,6 @@ __global__ __launch_bounds__(NW * 64) void k_layer_bwd_lds(BwdArgs args) {
         s1[i] = ts.s1;
       }
     } else {
-      float xin[D];
-#pragma unroll
-      for (int q = 0; q < D; ++q) xin[q] = n < args.N ? args.x[n * D + q] : 0.f;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int j = mb + i;
@@ -410,6 +413,33 @@ __global__ __launch_bounds__(NW * 64) void k_layer_bwd_lds(BwdArgs args) {
       jet_adjoint<CH>(ab[i], zz[i][0], s1[i], zz[i], zb);
 #pragma unroll
       for (int c = 0; c < C; ++c) out[i][c] = zb[c];
+    }
+    if constexpr (ZSRC != Z_FROM_GEMM && !TOP) {
+      if (args.seed_part) {
+        // first-layer gradient of this tile instead of Zbar_1 (the seeds of
+        // the input layer, reversed): dW_1[j][q] = sum over points of
+        // zbar_0 x_q plus the first-order channel of direction q; db_1[j] =
+        // sum of zbar_0.  The 16 points of the tile are the 16 lanes r of
+        // each lane group, summed by a butterfly.
+        float *sp = args.seed_part + (int64_t)blockIdx.x * ((int64_t)w * D + w);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          float v[D + 1];
+#pragma unroll
+          for (int q = 0; q < D; ++q) v[q] = out[i][0] * xin[q];
+#pragma unroll
+          for (int d = 0; d < CH::NDIR; ++d) v[CH::in(d)] += out[i][CH::at(d, 1)];
+          v[D] = out[i][0];
+#pragma unroll
+          for (int e = 0; e <= D; ++e) v[e] = group_sum<16>(v[e]);
+          if (r == 0) {
+#pragma unroll
+            for (int q = 0; q < D; ++q) sp[(mb + i) * D + q] = v[q];
+            sp[(int64_t)w * D + mb + i] = v[D];
+          }
+        }
+        continue;
+      }
     }
 #pragma unroll
     for (int c = 0; c < C; ++c) store4(Zb_out + n * ps + c * w + mb, out[0][c], out[1][c], out[2][c], out[3][c]);
@@ -461,6 +491,8 @@ template <class CH, class T, bool TOP, int DOUT, int ZSRC>
 hipError_t launch_bwd_t(const BwdArgs &a, int64_t N_pad, hipStream_t st) {
   const int w = a.w;
   const BwdLdsCfg cfg = bwd_lds_cfg(CH::C, w, (int)sizeof(T), !TOP && ZSRC == Z_FROM_GEMM);
+  // the first-layer gradient partials are produced by the LDS-staged kernel only
+  if (a.seed_part && !(cfg.P > 0 && CH::C * w * (int)sizeof(T) % 16 == 0)) return hipErrorInvalidValue;
   if (cfg.P > 0 && CH::C * w * (int)sizeof(T) % 16 == 0) {
     const int tiles = (TOP ? 0 : 1) + (ZSRC == Z_FROM_GEMM ? 1 : 0);
     const size_t lds = (size_t)tiles * cfg.P * (CH::C * w + 8) * sizeof(T);
@@ -536,8 +568,15 @@ hipError_t launch_layer_fwd(int kind, int prec, const void *A_in, const void *Wo
   });
 }
 
+bool seed_grad_fused_supported(int C, int w, int prec) {
+  const int osz = prec == P_FP32 ? 4 : 2;
+  return bwd_lds_cfg(C, w, osz, false).P > 0 && C * w * osz % 16 == 0;
+}
+
 hipError_t launch_layer_bwd(int kind, int prec, const LayerBwd &L, int64_t N_pad, hipStream_t st) {
-  BwdArgs a{L.Zb_in, L.WT, L.ubar, L.WL, L.S_in, L.A_prev, L.Wz, L.bz, L.x, L.W1, L.N, L.Zb_out, L.w};
+  if (L.seed_part && (L.top || L.A_prev || !L.x)) return hipErrorInvalidValue;
+  BwdArgs a{L.Zb_in, L.WT, L.ubar, L.WL, L.S_in, L.A_prev, L.Wz, L.bz, L.x, L.W1, L.N, L.Zb_out, L.w,
+            L.seed_part};
   const int zsrc = L.S_in ? Z_FROM_S : (L.A_prev ? Z_FROM_GEMM : Z_FROM_X);
   return dispatch(kind, prec, [&](auto pde, auto tv) {
     return launch_bwd_kind<decltype(pde), decltype(tv)>(a, L.top, zsrc, N_pad, st);

@@ -63,8 +63,14 @@ struct LayerBwd {
   int64_t N;
   void *Zb_out;
   int w;
+  // first layer only (z from x): when non-null, the kernel writes the first
+  // layer's weight-gradient partials seed_part[tile][w*DIN + w] (dW_1
+  // row-major, then db_1; one partial per 16-point tile) instead of Zb_out
+  float *seed_part = nullptr;
 };
 hipError_t launch_layer_bwd(int kind, int prec, const LayerBwd &L, int64_t N_pad, hipStream_t st);
+// Whether launch_layer_bwd can produce seed_part for this shape.
+bool seed_grad_fused_supported(int C, int w, int prec);
 
 // Kernel-side argument block of the backward layer kernels.
 enum { Z_FROM_S = 0, Z_FROM_GEMM = 1, Z_FROM_X = 2 };
@@ -83,6 +89,7 @@ struct BwdArgs {
   int64_t N;
   void *Zb_out;        // [N_pad][C][w] operand type
   int w;
+  float *seed_part;    // Z_FROM_X: first-layer gradient partials instead of Zb_out
 };
 
 

@@ -512,9 +512,10 @@ pinn_status pinn_plan_create(const pinn_net *net, const pinn_pde *pde, int64_t m
   // where the width allows (the faster variant measured on the NS workload)
   p->bwd_fused = (prec != PINN_FP32 && pj::bwd_dw_fused_supported(ki.C, w, prec)) ? 1 : 0;
   p->thin_chunks = (int)std::max<int64_t>(1, npad / 64);
-  const size_t part_elems =
+  const size_t part_elems = std::max<size_t>(
       std::max<size_t>((size_t)p->dw_splits_max * ((size_t)w * w + w),
-                       (size_t)p->thin_chunks * std::max(ki.dout * w + ki.dout, w * ki.din + w));
+                       (size_t)p->thin_chunks * std::max(ki.dout * w + ki.dout, w * ki.din + w)),
+      (size_t)(npad / 16) * ((size_t)w * ki.din + w));  // first-layer partials, one per 16-point tile
   A(reinterpret_cast<void **>(&p->part), part_elems * sizeof(float));
   if (e != hipSuccess) {
     delete p;
@@ -628,6 +629,7 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
   // Source of z for the adjoint of activation layer m: the saved state, or a
   // recompute from the stack of layer m - 1 (m >= 2) or from x (m = 1).
   auto zsrc = [&](pj::LayerBwd &B, int m) -> pinn_status {
+    if (m == 1) B.x = x;  // also the inputs of the first layer's gradient
     if (p->store_S) {
       B.S_in = p->S[m];
     } else if (m >= 2) {
@@ -645,6 +647,9 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
     return PINN_OK;
   };
   const bool fused = p->bwd_fused && H >= 2 && pj::bwd_dw_fused_supported(ki.C, w, p->prec);
+  // layer 1's adjoint kernel also yields the first layer's gradient (H >= 2:
+  // layer 1 is then a hidden-layer adjoint from zbar_2, not the top layer)
+  const bool seed_fused = H >= 2 && pj::seed_grad_fused_supported(ki.C, w, p->prec);
   if (fused) {
     // Each backward layer kernel also produces the weight gradient of the
     // layer whose zbar it computes: dW_m from zbar_m and the stack of m - 1.
@@ -701,6 +706,7 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
     B.N = N;
     B.w = w;
     B.Zb_out = p->Zb[1];
+    B.seed_part = seed_fused ? p->part : nullptr;
     rs = zsrc(B, 1);
     if (rs) return rs;
     e = timed(p, PINN_K_LAYER_BWD, s, [&] { return pj::launch_layer_bwd(p->kind, p->prec, B, npad, s); });
@@ -749,13 +755,21 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
     B.N = N;
     B.w = w;
     B.Zb_out = prev;
+    B.seed_part = (l == 2 && seed_fused) ? p->part : nullptr;
     rs = zsrc(B, l - 1);
     if (rs) return rs;
     e = timed(p, PINN_K_LAYER_BWD, s, [&] { return pj::launch_layer_bwd(p->kind, p->prec, B, npad, s); });
     if (e) return hip_fail(e, "hidden adjoint");
   }
   }
-  // First layer.
+  // First layer: its gradient partials came out of the layer-1 adjoint kernel
+  // (one per 16-point tile), or the separate kernel sums them from zbar_1.
+  if (seed_fused) {
+    e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, (int)(npad / 16), (int64_t)w * ki.din + w, (int64_t)w * ki.din, w,
+                                 dW[0], db[0], f64(dW_f64, 0), f64(db_f64, 0), s); });
+    if (e) return hip_fail(e, "reduction");
+    return PINN_OK;
+  }
   e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_dw_seed(p->kind, p->prec, p->Zb[1], x, N, npad, w, p->part, p->thin_chunks, s); });
   if (e) return hip_fail(e, "first-layer gradient");
   e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, p->thin_chunks, (int64_t)w * ki.din + w, (int64_t)w * ki.din, w,
