@@ -28,7 +28,8 @@ EXPORTS = ["pinn_plan_create", "pinn_plan_destroy", "pinn_plan_memory", "pinn_je
            "pinn_jet_residual", "pinn_jet_backward", "pinn_last_error", "pinn_pde_channels",
            "pinn_pde_residuals", "pinn_plan_profile", "pinn_plan_profile_read", "pinn_plan_get_tuning",
            "pinn_plan_set_tuning", "pinn_plan_autotune", "pinn_batch_create", "pinn_batch_destroy",
-           "pinn_batch_configure", "pinn_batch_step", "pinn_batch_autotune"]
+           "pinn_batch_configure", "pinn_batch_step", "pinn_batch_autotune", "pinn_graph_capture",
+           "pinn_graph_launch", "pinn_graph_destroy"]
 KERNEL_CLASSES = {"layer_fwd": 1, "layer_bwd": 2, "dw_hidden": 3, "out_fwd": 4, "out_bwd": 5,
                   "seed_fwd": 6, "other": 7, "bwd_dw": 8}
 
@@ -79,6 +80,9 @@ def _load():
     lib.pinn_batch_step.argtypes = [vp, NetP, PdeP, pp, i64p, vp, pp, pp, vp]
     lib.pinn_batch_autotune.argtypes = [vp, NetP, PdeP, pp, i64p, vp, pp, pp, i32,
                                         ctypes.POINTER(ctypes.c_int32), dptr, vp]
+    lib.pinn_graph_capture.argtypes = [vp, NetP, PdeP, vp, i64, vp, vp, pp, pp, pp]
+    lib.pinn_graph_launch.argtypes = [vp, vp]
+    lib.pinn_graph_destroy.argtypes = [vp]
     lib.pinn_last_error.restype = ctypes.c_char_p
     lib.pinn_last_error.argtypes = []
     lib.pinn_pde_channels.argtypes = [i32]
@@ -87,7 +91,8 @@ def _load():
                  "pinn_jet_residual", "pinn_jet_backward", "pinn_pde_channels", "pinn_pde_residuals",
                  "pinn_plan_profile", "pinn_plan_profile_read", "pinn_plan_get_tuning", "pinn_plan_set_tuning",
                  "pinn_plan_autotune", "pinn_batch_create", "pinn_batch_destroy", "pinn_batch_configure",
-                 "pinn_batch_step", "pinn_batch_autotune"):
+                 "pinn_batch_step", "pinn_batch_autotune", "pinn_graph_capture", "pinn_graph_launch",
+                 "pinn_graph_destroy"):
         getattr(lib, name).restype = ctypes.c_int32
     return lib
 

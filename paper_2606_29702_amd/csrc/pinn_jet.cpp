@@ -899,6 +899,97 @@ pinn_status pinn_plan_autotune(pinn_plan plan, const pinn_net *net, const pinn_p
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
+// One plan's step captured into a HIP graph.
+// ---------------------------------------------------------------------------
+struct pinn_graph_s {
+  pinn_plan plan = nullptr;
+  hipStream_t origin = nullptr;  // private capture and launch stream (default priority)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~pinn_graph_s() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (origin) (void)hipStreamDestroy(origin);
+  }
+};
+
+extern "C" {
+
+pinn_status pinn_graph_capture(pinn_plan plan, const pinn_net *net, const pinn_pde *pde, const float *x,
+                               int64_t N, float *r, float *loss, float *const *dW, float *const *db,
+                               pinn_graph *out) {
+  g_err.clear();
+  if (!out) return fail(PINN_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  pinn_status st = check_call(plan, net, x, N);
+  if (st) return st;
+  st = check_pde(pde, plan->kind);
+  if (st) return st;
+  if (!dW || !db) return fail(PINN_ERR_ARG, "dW or db is NULL");
+  for (int l = 0; l < plan->L; ++l)
+    if (!dW[l] || !db[l]) return fail(PINN_ERR_ARG, "dW[%d] or db[%d] is NULL", l, l);
+  auto *gr = new pinn_graph_s();
+  gr->plan = plan;
+  hipError_t e = hipStreamCreateWithFlags(&gr->origin, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&gr->ev_in, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&gr->ev_out, hipEventDisableTiming);
+  if (e) {
+    delete gr;
+    return hip_fail(e, "graph stream");
+  }
+  plan->prof_class = 0;  // no event timing inside a graph
+  e = hipStreamBeginCapture(gr->origin, hipStreamCaptureModeRelaxed);
+  if (e) {
+    delete gr;
+    return hip_fail(e, "graph capture");
+  }
+  st = pinn_jet_residual(plan, net, pde, x, N, r, loss, nullptr, nullptr, gr->origin);
+  if (st == PINN_OK)
+    st = pinn_jet_backward(plan, net, pde, x, N, nullptr, dW, db, nullptr, nullptr, gr->origin);
+  const std::string msg = g_err;
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(gr->origin, &g);
+  if (st || e) {
+    if (g) (void)hipGraphDestroy(g);
+    delete gr;
+    if (st) return fail(st, "%s", msg.c_str());
+    return hip_fail(e, "graph capture");
+  }
+  e = hipGraphInstantiate(&gr->exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e) {
+    delete gr;
+    return hip_fail(e, "graph instantiate");
+  }
+  *out = gr;
+  return PINN_OK;
+}
+
+pinn_status pinn_graph_launch(pinn_graph gr, void *stream) {
+  g_err.clear();
+  if (!gr) return fail(PINN_ERR_ARG, "graph is NULL");
+  hipStream_t caller = (hipStream_t)stream;
+  hipError_t e = hipEventRecord(gr->ev_in, caller);
+  if (e == hipSuccess) e = hipStreamWaitEvent(gr->origin, gr->ev_in, 0);
+  if (e == hipSuccess) e = hipGraphLaunch(gr->exec, gr->origin);
+  if (e == hipSuccess) e = hipEventRecord(gr->ev_out, gr->origin);
+  if (e == hipSuccess) e = hipStreamWaitEvent(caller, gr->ev_out, 0);
+  return e ? hip_fail(e, "graph launch") : PINN_OK;
+}
+
+pinn_status pinn_graph_destroy(pinn_graph gr) {
+  g_err.clear();
+  if (!gr) return fail(PINN_ERR_ARG, "graph is NULL");
+  // launches already queued must not run on a destroyed graph
+  const hipError_t e = hipStreamSynchronize(gr->origin);
+  delete gr;
+  return e ? hip_fail(e, "graph destroy") : PINN_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
 // Ensembles: many independent networks stepped together.
 // ---------------------------------------------------------------------------
 struct pinn_batch_s {

@@ -181,6 +181,51 @@ class PinnPlan:
         return (grads, g64) if want_f64 else grads
 
 
+    def capture_step(self, params, x: torch.Tensor) -> "PinnGraph":
+        """The residual + loss-gradient step on (params, x) as a replayable
+        HIP graph (pinn_graph_capture); outputs live on the returned object."""
+        return PinnGraph(self, params, x)
+
+
+class PinnGraph:
+    """One captured step of a plan.  launch() replays it on the current
+    stream, reading the current contents of the parameter and point tensors
+    given at capture; r, loss and grads are overwritten by every launch."""
+
+    def __init__(self, plan: PinnPlan, params, x: torch.Tensor):
+        _check_tensor(x, "x")
+        self.plan = plan
+        self.params = params  # kept alive: the graph holds their pointers
+        self.x = x
+        nv = _NetView(params)
+        N = x.shape[0]
+        dev = x.device
+        self.r = torch.empty((plan.n_res, N), device=dev, dtype=torch.float32)
+        self.loss = torch.empty((), device=dev, dtype=torch.float32)
+        self.grads = [(torch.empty_like(W), torch.empty_like(b)) for W, b in params]
+        dWp, self._k1 = ptr_array([g[0].data_ptr() for g in self.grads])
+        dbp, self._k2 = ptr_array([g[1].data_ptr() for g in self.grads])
+        handle = ctypes.c_void_p()
+        check(lib.pinn_graph_capture(plan.handle, ctypes.byref(nv.net), ctypes.byref(_pde(plan.pde, plan.coef)),
+                                     ctypes.c_void_p(x.data_ptr()), N, ctypes.c_void_p(self.r.data_ptr()),
+                                     ctypes.c_void_p(self.loss.data_ptr()), dWp, dbp, ctypes.byref(handle)))
+        self.handle = handle
+
+    def launch(self) -> None:
+        check(lib.pinn_graph_launch(self.handle, _stream()))
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            check(lib.pinn_graph_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class JetResidual(torch.autograd.Function):
     """(r, loss) = JetResidual.apply(plan, x, W1, b1, ..., WL, bL).
 

@@ -126,3 +126,34 @@ def test_plan_autotune_and_tuning_validation(lib):
         plan.set_tuning(t0["dw_splits"], 24)
     plan.set_tuning(t0["dw_splits"], 16)
     plan.close()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_plan_graph_replays_match_eager(lib, prec):
+    """A captured step replayed several times, with eager steps and in-place
+    weight updates in between, equals the eager step on the same values bit
+    for bit, every replay."""
+    prob = pi.make_problem("ns", N=3000, seed=17, bias_std=0.3, dims=[2, 64, 64, 64, 3])
+    params = [(torch.tensor(W, device="cuda"), torch.tensor(b, device="cuda")) for W, b in prob.params]
+    x = torch.tensor(prob.x, device="cuda")
+    plan = lib.PinnPlan([2, 64, 64, 64, 3], "ns", 3000, precision=prec,
+                        coef=prob.coef)
+    eager = lib.PinnPlan([2, 64, 64, 64, 3], "ns", 3000, precision=prec, coef=prob.coef)
+    graph = plan.capture_step(params, x)
+    for rep in range(3):
+        graph.launch()
+        r_e, loss_e, _, _ = eager.residual(params, x)
+        g_e = eager.backward(params, x)
+        torch.cuda.synchronize()
+        assert torch.equal(graph.r, r_e), rep
+        assert torch.equal(graph.loss, loss_e), rep
+        for (a, b), (c, d) in zip(graph.grads, g_e):
+            assert torch.equal(a, c) and torch.equal(b, d), rep
+        # an optimizer-like in-place update between replays
+        with torch.no_grad():
+            for W, b in params:
+                W.mul_(0.99)
+                b.add_(0.01)
+    graph.close()
+    plan.close()
+    eager.close()
