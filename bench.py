@@ -135,9 +135,20 @@ def time_path(prob, prec, steps, warmup, profile_dominant=True, tuning=None):
     t1 = time.perf_counter()
     dom_ms, dom_n = plan.profile_read() if profile_dominant else (float("nan"), 0)
     plan.profile("off")
+    # the same step captured once as a HIP graph and replayed (context)
+    graph = plan.capture_step(params, x)
+    graph.launch()
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    for _ in range(steps):
+        graph.launch()
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - g0) * 1e3 / steps
+    graph.close()
     plan.close()
     return dict(ms_per_step=(t1 - t0) * 1e3 / steps, class_ms=class_ms, dominant=dominant,
-                dominant_avg_ms=dom_ms / max(dom_n, 1), dominant_launches=dom_n, tuning=tuning)
+                dominant_avg_ms=dom_ms / max(dom_n, 1), dominant_launches=dom_n, tuning=tuning,
+                graph_ms_per_step=graph_ms)
 
 
 def nested_autograd_fp32(prob, steps):
@@ -357,6 +368,8 @@ def main():
                    "coef": list(prob.coef), "step": "forward jets + residual + MSE loss + dtheta"},
         "roofline": roof,
         "kernel_ms_per_step": {k: round(v[0], 4) for k, v in main_run["class_ms"].items()},
+        "graph_replay": {"ms_per_step": round(main_run["graph_ms_per_step"], 4),
+                         "value": round(N / (main_run["graph_ms_per_step"] * 1e-3), 1), "unit": "pts/s"},
         "tuning": main_run["tuning"],
     }
 
