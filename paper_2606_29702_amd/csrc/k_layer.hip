@@ -295,51 +295,22 @@ __device__ __forceinline__ void lds_gemm(f32x4 (&acc)[TPW][C], const WFrags<T, T
   }
 }
 
-template <class CH, class T, int NW, int TPW, int P, bool TOP, int DOUT, int ZSRC>
-__global__ __launch_bounds__(NW * 64) void k_layer_bwd_lds(BwdArgs args) {
+// Epilogue of the backward layer kernels, per wave: the lane's point n and
+// this wave's TPW neuron tiles starting at tile jt0.  z of the layer comes
+// from the saved state, the recompute accumulators acc_z (plus the bias) or
+// x; Abar from acc_a or, at the top, W_L^T ubar; then the jet adjoint.  Writes
+// Zbar to Zb_out, or (first layer with seed_part) adds the first layer's
+// gradient into the partial row `part_row`.
+template <class CH, class T, int TPW, bool TOP, int DOUT, int ZSRC>
+__device__ __forceinline__ void bwd_epilogue(const BwdArgs &args, const f32x4 (&acc_a)[TPW][CH::C],
+                                             const f32x4 (&acc_z)[TPW][CH::C], int64_t n, int jt0,
+                                             int64_t part_row, int lane) {
   constexpr int C = CH::C, D = CH::DIN;
   constexpr bool FAST = sizeof(T) == 2;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   const int w = args.w;
-  const int pitch = C * w + 8;
-  T *lds_b = reinterpret_cast<T *>(smem_raw);                         // Zbar_l tile
-  T *lds_a = lds_b + (TOP ? 0 : P * pitch);                           // stack tile of layer l-2
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r = lane & 15, g = lane >> 4;
-  const int64_t nb = (int64_t)blockIdx.x * P;
   const int64_t ps = (int64_t)C * w;
-  const int NJ = w / 16;
-  const int tile0 = wave * TPW;
-  const int nt = tile0 / NJ, jt0 = tile0 % NJ;
-  // weight fragments of the first contraction steps, loaded first (16
-  // registers per GEMM)
-  constexpr int KP = (sizeof(T) == 2 ? 4 : 2) / TPW > 0 ? (sizeof(T) == 2 ? 4 : 2) / TPW : 1;
-  WFrags<T, TPW, KP> wf_a, wf_z;
-  if constexpr (!TOP) load_wfrags(wf_a, static_cast<const T *>(args.WT), jt0, w, lane);
-  if constexpr (ZSRC == Z_FROM_GEMM) load_wfrags(wf_z, static_cast<const T *>(args.Wz), jt0, w, lane);
-  // both tiles in one pass (Zbar_l first, then the stack of layer l-2), so that
-  // a thread's loads of the two are in flight together
-  {
-    const T *zb_in = static_cast<const T *>(args.Zb_in) + nb * ps;
-    const T *a_prev = static_cast<const T *>(args.A_prev) + nb * ps;
-    if constexpr (!TOP && ZSRC == Z_FROM_GEMM)
-      stage_rows<T, 12, true>(lds_b, zb_in, a_prev, P, C * w, pitch, tid, NW * 64);
-    else if constexpr (!TOP)
-      stage_rows<T, 12, false>(lds_b, zb_in, nullptr, P, C * w, pitch, tid, NW * 64);
-    else if constexpr (ZSRC == Z_FROM_GEMM)
-      stage_rows<T, 12, false>(lds_a, a_prev, nullptr, P, C * w, pitch, tid, NW * 64);
-  }
-  __syncthreads();
-
-  f32x4 acc_a[TPW][C];
-  if constexpr (!TOP)
-    lds_gemm<T, C, TPW, KP>(acc_a, wf_a, static_cast<const T *>(args.WT), lds_b, pitch, jt0, nt, w, lane);
-  f32x4 acc_z[TPW][C];
-  if constexpr (ZSRC == Z_FROM_GEMM)
-    lds_gemm<T, C, TPW, KP>(acc_z, wf_z, static_cast<const T *>(args.Wz), lds_a, pitch, jt0, nt, w, lane);
-
   T *Zb_out = static_cast<T *>(args.Zb_out);
-  const int64_t n = nb + nt * 16 + r;
   // the point's inputs: for the first layer's z, or for its gradient
   float xin[D];
   if (ZSRC == Z_FROM_X || (ZSRC == Z_FROM_S && !TOP && args.seed_part)) {
@@ -421,7 +392,7 @@ __global__ __launch_bounds__(NW * 64) void k_layer_bwd_lds(BwdArgs args) {
         // zbar_0 x_q plus the first-order channel of direction q; db_1[j] =
         // sum of zbar_0.  The 16 points of the tile are the 16 lanes r of
         // each lane group, summed by a butterfly.
-        float *sp = args.seed_part + (int64_t)blockIdx.x * ((int64_t)w * D + w);
+        float *sp = args.seed_part + part_row * ((int64_t)w * D + w);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           float v[D + 1];
@@ -444,6 +415,150 @@ __global__ __launch_bounds__(NW * 64) void k_layer_bwd_lds(BwdArgs args) {
 #pragma unroll
     for (int c = 0; c < C; ++c) store4(Zb_out + n * ps + c * w + mb, out[0][c], out[1][c], out[2][c], out[3][c]);
   }
+}
+
+template <class CH, class T, int NW, int TPW, int P, bool TOP, int DOUT, int ZSRC>
+__global__ __launch_bounds__(NW * 64) void k_layer_bwd_lds(BwdArgs args) {
+  constexpr int C = CH::C, D = CH::DIN;
+  constexpr bool FAST = sizeof(T) == 2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int w = args.w;
+  const int pitch = C * w + 8;
+  T *lds_b = reinterpret_cast<T *>(smem_raw);                         // Zbar_l tile
+  T *lds_a = lds_b + (TOP ? 0 : P * pitch);                           // stack tile of layer l-2
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int64_t nb = (int64_t)blockIdx.x * P;
+  const int64_t ps = (int64_t)C * w;
+  const int NJ = w / 16;
+  const int tile0 = wave * TPW;
+  const int nt = tile0 / NJ, jt0 = tile0 % NJ;
+  // weight fragments of the first contraction steps, loaded first (16
+  // registers per GEMM)
+  constexpr int KP = (sizeof(T) == 2 ? 4 : 2) / TPW > 0 ? (sizeof(T) == 2 ? 4 : 2) / TPW : 1;
+  WFrags<T, TPW, KP> wf_a, wf_z;
+  if constexpr (!TOP) load_wfrags(wf_a, static_cast<const T *>(args.WT), jt0, w, lane);
+  if constexpr (ZSRC == Z_FROM_GEMM) load_wfrags(wf_z, static_cast<const T *>(args.Wz), jt0, w, lane);
+  // both tiles in one pass (Zbar_l first, then the stack of layer l-2), so that
+  // a thread's loads of the two are in flight together
+  {
+    const T *zb_in = static_cast<const T *>(args.Zb_in) + nb * ps;
+    const T *a_prev = static_cast<const T *>(args.A_prev) + nb * ps;
+    if constexpr (!TOP && ZSRC == Z_FROM_GEMM)
+      stage_rows<T, 12, true>(lds_b, zb_in, a_prev, P, C * w, pitch, tid, NW * 64);
+    else if constexpr (!TOP)
+      stage_rows<T, 12, false>(lds_b, zb_in, nullptr, P, C * w, pitch, tid, NW * 64);
+    else if constexpr (ZSRC == Z_FROM_GEMM)
+      stage_rows<T, 12, false>(lds_a, a_prev, nullptr, P, C * w, pitch, tid, NW * 64);
+  }
+  __syncthreads();
+
+  f32x4 acc_a[TPW][C];
+  if constexpr (!TOP)
+    lds_gemm<T, C, TPW, KP>(acc_a, wf_a, static_cast<const T *>(args.WT), lds_b, pitch, jt0, nt, w, lane);
+  f32x4 acc_z[TPW][C];
+  if constexpr (ZSRC == Z_FROM_GEMM)
+    lds_gemm<T, C, TPW, KP>(acc_z, wf_z, static_cast<const T *>(args.Wz), lds_a, pitch, jt0, nt, w, lane);
+
+  bwd_epilogue<CH, T, TPW, TOP, DOUT, ZSRC>(args, acc_a, acc_z, nb + nt * 16 + r, jt0, blockIdx.x, lane);
+}
+
+// Backward layer kernel for wide layers (w >= 256), where a whole stack tile
+// does not fit in LDS.  A workgroup of NW waves (TPW neuron tiles each)
+// computes a 16-point x 16 NW TPW-neuron output tile.  The neuron tile is the
+// fastest-varying part of blockIdx.x, so the workgroups that share a point
+// tile run next to each other and its stack data is reused from L2.  The contraction (the neurons
+// of the layer below) runs in chunks of KC: each chunk of the Zbar and A_{l-2}
+// tiles ([point][channel][KC], rows padded by 8 elements) is staged through
+// LDS with every thread's loads issued together, then feeds the Abar and z
+// GEMMs.  The epilogue is that of the full-tile kernel.
+template <class CH, class T, int NW, int TPW, int KC, bool TOP, int DOUT, int ZSRC>
+__global__ __launch_bounds__(NW * 64) void k_layer_bwd_kc(BwdArgs args) {
+  using M = Mma<T>;
+  constexpr int C = CH::C, P = 16;
+  constexpr int TILEN = NW * TPW * 16;
+  constexpr int PITCH = C * KC + 8;
+  constexpr bool ZB = !TOP, AZ = ZSRC == Z_FROM_GEMM;
+  constexpr int P16 = 16 / (int)sizeof(T);       // elements per 16-byte piece
+  constexpr int PPC = KC / P16;                  // pieces per (point, channel) row of a chunk
+  constexpr int PIECES = P * C * PPC;            // pieces per tile chunk
+  constexpr int PER_T = (PIECES + NW * 64 - 1) / (NW * 64);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *lds_b = reinterpret_cast<T *>(smem_raw);
+  T *lds_a = lds_b + (ZB ? P * PITCH : 0);
+  const int w = args.w;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int ntn = w / TILEN;  // neuron tiles per point tile (consecutive workgroups)
+  const int64_t ptile = blockIdx.x / ntn;
+  const int ntile = (int)(blockIdx.x - ptile * ntn);
+  const int64_t nb = ptile * P;
+  const int jt0 = ntile * (TILEN / 16) + wave * TPW;
+  const int64_t ps = (int64_t)C * w;
+  const T *zb_src = static_cast<const T *>(args.Zb_in) + nb * ps;
+  const T *a_src = static_cast<const T *>(args.A_prev) + nb * ps;
+  const T *WT = static_cast<const T *>(args.WT);
+  const T *Wz = static_cast<const T *>(args.Wz);
+  f32x4 acc_a[TPW][C], acc_z[TPW][C];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t)
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      acc_a[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+      acc_z[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  for (int k0 = 0; k0 < w; k0 += KC) {
+    {
+      uint4 vb[PER_T], va[PER_T];
+#pragma unroll
+      for (int u = 0; u < PER_T; ++u) {
+        const int q0 = tid + u * NW * 64;
+        const int q = q0 < PIECES ? q0 : PIECES - 1;  // re-read the last piece (in bounds)
+        const int p = q / (C * PPC), rem = q - p * (C * PPC), c = rem / PPC, j = rem - c * PPC;
+        const int64_t goff = (int64_t)p * ps + (int64_t)c * w + k0 + j * P16;
+        if (ZB) vb[u] = *reinterpret_cast<const uint4 *>(zb_src + goff);
+        if (AZ) va[u] = *reinterpret_cast<const uint4 *>(a_src + goff);
+      }
+#pragma unroll
+      for (int u = 0; u < PER_T; ++u) {
+        const int q = tid + u * NW * 64;
+        if (q < PIECES) {
+          const int p = q / (C * PPC), rem = q - p * (C * PPC), c = rem / PPC, j = rem - c * PPC;
+          const int loff = p * PITCH + c * KC + j * P16;
+          if (ZB) *reinterpret_cast<uint4 *>(lds_b + loff) = vb[u];
+          if (AZ) *reinterpret_cast<uint4 *>(lds_a + loff) = va[u];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 32) {
+      if constexpr (ZB) {
+        typename M::frag fb[C], fa[TPW];
+#pragma unroll
+        for (int c = 0; c < C; ++c) fb[c] = M::load(lds_b + r * PITCH + c * KC + kk + 8 * g);
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) fa[t] = M::load(WT + (int64_t)((jt0 + t) * 16 + r) * w + k0 + kk + 8 * g);
+#pragma unroll
+        for (int t = 0; t < TPW; ++t)
+#pragma unroll
+          for (int c = 0; c < C; ++c) M::mma(acc_a[t][c], fa[t], fb[c]);
+      }
+      if constexpr (AZ) {
+        typename M::frag fb[C], fa[TPW];
+#pragma unroll
+        for (int c = 0; c < C; ++c) fb[c] = M::load(lds_a + r * PITCH + c * KC + kk + 8 * g);
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) fa[t] = M::load(Wz + (int64_t)((jt0 + t) * 16 + r) * w + k0 + kk + 8 * g);
+#pragma unroll
+        for (int t = 0; t < TPW; ++t)
+#pragma unroll
+          for (int c = 0; c < C; ++c) M::mma(acc_z[t][c], fa[t], fb[c]);
+      }
+    }
+    __syncthreads();  // the chunk buffers are restaged next
+  }
+  bwd_epilogue<CH, T, TPW, TOP, DOUT, ZSRC>(args, acc_a, acc_z, nb + r, jt0, ptile, lane);
 }
 
 namespace {
@@ -490,8 +605,21 @@ inline BwdLdsCfg bwd_lds_cfg(int C, int w, int osz, bool two_tiles) {
 template <class CH, class T, bool TOP, int DOUT, int ZSRC>
 hipError_t launch_bwd_t(const BwdArgs &a, int64_t N_pad, hipStream_t st) {
   const int w = a.w;
+  // wide layers: neuron-tiled, contraction staged through LDS in chunks
+  if (w >= 256 && w % 128 == 0) {
+    constexpr int KC = sizeof(T) == 2 ? 128 : 64;
+    const int tiles = (TOP ? 0 : 1) + (ZSRC == Z_FROM_GEMM ? 1 : 0);
+    const size_t lds = (size_t)tiles * 16 * (CH::C * KC + 8) * sizeof(T);
+    const dim3 grid((unsigned)((N_pad / 16) * (w / 128)));
+    auto kfn = k_layer_bwd_kc<CH, T, 8, 1, KC, TOP, DOUT, ZSRC>;
+    hipError_t e = hipFuncSetAttribute((const void *)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(lds > 0 ? lds : 16));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kfn, grid, dim3(8 * 64), lds, st, a);
+    return hipGetLastError();
+  }
   const BwdLdsCfg cfg = bwd_lds_cfg(CH::C, w, (int)sizeof(T), !TOP && ZSRC == Z_FROM_GEMM);
-  // the first-layer gradient partials are produced by the LDS-staged kernel only
+  // the first-layer gradient partials are produced by the LDS-staged kernels only
   if (a.seed_part && !(cfg.P > 0 && CH::C * w * (int)sizeof(T) % 16 == 0)) return hipErrorInvalidValue;
   if (cfg.P > 0 && CH::C * w * (int)sizeof(T) % 16 == 0) {
     const int tiles = (TOP ? 0 : 1) + (ZSRC == Z_FROM_GEMM ? 1 : 0);
@@ -570,7 +698,7 @@ hipError_t launch_layer_fwd(int kind, int prec, const void *A_in, const void *Wo
 
 bool seed_grad_fused_supported(int C, int w, int prec) {
   const int osz = prec == P_FP32 ? 4 : 2;
-  return bwd_lds_cfg(C, w, osz, false).P > 0 && C * w * osz % 16 == 0;
+  return (w >= 256 && w % 128 == 0) || (bwd_lds_cfg(C, w, osz, false).P > 0 && C * w * osz % 16 == 0);
 }
 
 hipError_t launch_layer_bwd(int kind, int prec, const LayerBwd &L, int64_t N_pad, hipStream_t st) {
