@@ -561,6 +561,108 @@ __global__ __launch_bounds__(NW * 64) void k_layer_bwd_kc(BwdArgs args) {
   bwd_epilogue<CH, T, TPW, TOP, DOUT, ZSRC>(args, acc_a, acc_z, nb + r, jt0, ptile, lane);
 }
 
+// The wide-layer kernel for 16-bit operands with its chunks double-buffered:
+// two sets of chunk buffers are separate static LDS objects, and while one
+// chunk feeds the GEMMs the next one streams into the other set with
+// direct-to-LDS loads (one 1 KB-or-less wave load per point and tile: the C
+// channel rows of KC elements of a point are contiguous in LDS).  A chunk's
+// weight fragments are loaded before the next chunk's prefetch is issued,
+// since the load counter completes in order.
+template <class CH, class T, int NW, int KC, bool TOP, int DOUT, int ZSRC>
+__global__ __launch_bounds__(NW * 64) void k_layer_bwd_kc2(BwdArgs args) {
+  using M = Mma<T>;
+  constexpr int C = CH::C, P = 16, TPW = 1;
+  constexpr int TILEN = NW * TPW * 16;
+  constexpr int PITCH = C * KC + 8;
+  constexpr bool ZB = !TOP, AZ = ZSRC == Z_FROM_GEMM;
+  constexpr int TILES = (ZB ? 1 : 0) + (AZ ? 1 : 0);
+  constexpr int LPP = C * KC / 8;  // lanes (16-byte pieces) per point row of a chunk
+  static_assert(sizeof(T) == 2 && LPP <= 64 && KC % 32 == 0, "chunk shape");
+  // one LDS object per buffer and tile
+  __shared__ __align__(16) T zbA[ZB ? P * PITCH : 8], azA[AZ ? P * PITCH : 8];
+  __shared__ __align__(16) T zbB[ZB ? P * PITCH : 8], azB[AZ ? P * PITCH : 8];
+  const int w = args.w;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int ntn = w / TILEN;
+  const int64_t ptile = blockIdx.x / ntn;
+  const int ntile = (int)(blockIdx.x - ptile * ntn);
+  const int64_t nb = ptile * P;
+  const int jt0 = ntile * (TILEN / 16) + wave * TPW;
+  const int64_t ps = (int64_t)C * w;
+  const T *zb_src = static_cast<const T *>(args.Zb_in) + nb * ps;
+  const T *a_src = static_cast<const T *>(args.A_prev) + nb * ps;
+  const T *WT = static_cast<const T *>(args.WT);
+  const T *Wz = static_cast<const T *>(args.Wz);
+  // chunk k0 of both tiles into (zs, as): wave v loads the points v, v + NW, ...
+  auto prefetch = [&](T *zs, T *as, int k0) __attribute__((always_inline)) {
+    const int c = lane / (KC / 8), j = lane - c * (KC / 8);
+    for (int p = wave; p < P; p += NW) {
+      if (lane < LPP) {
+        const int64_t goff = (int64_t)p * ps + (int64_t)c * w + k0 + 8 * j;
+        if constexpr (ZB)
+          __builtin_amdgcn_global_load_lds((const void *)(zb_src + goff),
+                                           (__attribute__((address_space(3))) void *)(zs + p * PITCH), 16, 0, 0);
+        if constexpr (AZ)
+          __builtin_amdgcn_global_load_lds(
+              (const void *)(a_src + goff),
+              (__attribute__((address_space(3))) void *)(as + p * PITCH), 16, 0, 0);
+      }
+    }
+  };
+  f32x4 acc_a[TPW][C], acc_z[TPW][C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    acc_a[0][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    acc_z[0][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  const T *wra = WT + (int64_t)(jt0 * 16 + r) * w + 8 * g;
+  const T *wrz = Wz + (int64_t)(jt0 * 16 + r) * w + 8 * g;
+  // one chunk from (cz, ca) while the next one streams into (nz, na)
+  auto chunk = [&](int k0, const T *cz, const T *ca, T *nz, T *na) __attribute__((always_inline)) {
+    typename M::frag fa[KC / 32], fz[KC / 32];
+#pragma unroll
+    for (int kk = 0; kk < KC / 32; ++kk) {
+      if constexpr (ZB) fa[kk] = M::load(wra + k0 + 32 * kk);
+      if constexpr (AZ) fz[kk] = M::load(wrz + k0 + 32 * kk);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_sched_barrier(0);  // the fragment loads stay ahead of the prefetch
+    if (k0 + KC < w) prefetch(nz, na, k0 + KC);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int kk = 0; kk < KC / 32; ++kk) {
+      if constexpr (ZB) {
+        typename M::frag fb[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) fb[c] = M::load(cz + r * PITCH + c * KC + 32 * kk + 8 * g);
+#pragma unroll
+        for (int c = 0; c < C; ++c) M::mma(acc_a[0][c], fa[kk], fb[c]);
+      }
+      if constexpr (AZ) {
+        typename M::frag fb[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) fb[c] = M::load(ca + r * PITCH + c * KC + 32 * kk + 8 * g);
+#pragma unroll
+        for (int c = 0; c < C; ++c) M::mma(acc_z[0][c], fz[kk], fb[c]);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // the next chunk has landed
+    __syncthreads();                // and this one is consumed
+  };
+  prefetch(zbA, azA, 0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int k0 = 0; k0 < w;) {
+    chunk(k0, zbA, azA, zbB, azB);
+    k0 += KC;
+    if (k0 >= w) break;
+    chunk(k0, zbB, azB, zbA, azA);
+    k0 += KC;
+  }
+  bwd_epilogue<CH, T, TPW, TOP, DOUT, ZSRC>(args, acc_a, acc_z, nb + r, jt0, ptile, lane);
+}
+
 namespace {
 
 template <class CH, class T>
@@ -606,6 +708,16 @@ template <class CH, class T, bool TOP, int DOUT, int ZSRC>
 hipError_t launch_bwd_t(const BwdArgs &a, int64_t N_pad, hipStream_t st) {
   const int w = a.w;
   // wide layers: neuron-tiled, contraction staged through LDS in chunks
+  // 16-bit operands with 8 channels (one full wave load per point and tile):
+  // the double-buffered form; measured slower than the single-buffered one at
+  // fewer channels (KS, C = 6: more registers, lower occupancy)
+  if constexpr (sizeof(T) == 2 && CH::C == 8) {
+    if (w >= 256 && w % 128 == 0) {
+      const dim3 grid((unsigned)((N_pad / 16) * (w / 128)));
+      hipLaunchKernelGGL((k_layer_bwd_kc2<CH, T, 8, 64, TOP, DOUT, ZSRC>), grid, dim3(8 * 64), 0, st, a);
+      return hipGetLastError();
+    }
+  }
   if (w >= 256 && w % 128 == 0) {
     constexpr int KC = sizeof(T) == 2 ? 128 : 64;
     const int tiles = (TOP ? 0 : 1) + (ZSRC == Z_FROM_GEMM ? 1 : 0);
