@@ -89,13 +89,13 @@ def gpu_params(prob):
     return [(torch.tensor(W, device="cuda"), torch.tensor(b, device="cuda")) for W, b in prob.params]
 
 
-def time_path(prob, prec, steps, warmup, profile_dominant=True, tuning=None):
+def time_path(prob, prec, steps, warmup, profile_dominant=True, tuning=None, save_cap=0):
     """Times `steps` residual+backward steps; returns ms/step and per-class kernel times."""
     import torch
     from paper_2606_29702_amd import PinnPlan
     wl = prob.workload
     N = prob.x.shape[0]
-    plan = PinnPlan(wl.dims, wl.pde, N, precision=prec, coef=prob.coef)
+    plan = PinnPlan(wl.dims, wl.pde, N, precision=prec, coef=prob.coef, save_cap_bytes=save_cap)
     params = gpu_params(prob)
     x = torch.tensor(prob.x, device="cuda")
 
@@ -301,6 +301,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-context", action="store_true", help="skip the FP32, nested-autograd and ensemble context runs")
     ap.add_argument("--copy-probe-mib", type=int, default=0, help="only run a plain device copy of this size")
+    ap.add_argument("--save-cap-gib", type=float, default=0.0,
+                    help="bound on the saved layer state (checkpointed backward); 0 = store every layer")
     ap.add_argument("--tuning", default=None,
                     help="dw_splits,fwd_points,bwd_fused instead of running the autotuner (e.g. for profiling)")
     args = ap.parse_args()
@@ -325,7 +327,8 @@ def main():
 
     log(f"workload {args.workload}: dims {wl.dims}, N {N}, C {C}, precision {args.precision}")
     tuning = tuple(int(v) for v in args.tuning.split(",")) if args.tuning else None
-    main_run = time_path(prob, args.precision, args.steps, args.warmup, tuning=tuning)
+    save_cap = int(args.save_cap_gib * (1 << 30))
+    main_run = time_path(prob, args.precision, args.steps, args.warmup, tuning=tuning, save_cap=save_cap)
     ms = main_run["ms_per_step"]
     value = N / (ms * 1e-3)
     log(f"{args.precision}: {ms:.3f} ms/step, {value/1e6:.2f} Mpts/s, dominant {main_run['dominant']} "
@@ -365,7 +368,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.precision, "data": "synthetic",
         "config": {"workload": args.workload, "dims": wl.dims, "N": N, "channels": C,
-                   "coef": list(prob.coef), "step": "forward jets + residual + MSE loss + dtheta"},
+                   "coef": list(prob.coef), "step": "forward jets + residual + MSE loss + dtheta",
+                   "save_cap_bytes": save_cap},
         "roofline": roof,
         "kernel_ms_per_step": {k: round(v[0], 4) for k, v in main_run["class_ms"].items()},
         "graph_replay": {"ms_per_step": round(main_run["graph_ms_per_step"], 4),
