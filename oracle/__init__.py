@@ -46,6 +46,9 @@ def _load():
                                     ctypes.c_int, dp, ctypes.c_int, ip, ip, ctypes.c_int64, dp,
                                     dp, dp, dp, ctypes.c_int]
         lib.orc_eval_cs.restype = ctypes.c_int
+        lib.orc_adam.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_double]
+        lib.orc_adam.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -157,3 +160,14 @@ def complex_step(params, delta: np.ndarray, x, channels, pde: str = "none",
     if st != 0:
         raise ValueError(f"orc_eval_cs failed with status {st}")
     return djets, dr, None if dloss is None else float(dloss[0])
+
+
+def adam_step(theta: np.ndarray, g: np.ndarray, m: np.ndarray, v: np.ndarray, step: int,
+              lr: float = 1e-3, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8) -> None:
+    """One Adam step in FP64, in place on theta, m and v (flat float64 arrays)."""
+    for a in (theta, g, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous and a.shape == theta.shape
+    st = _load().orc_adam(theta.size, _dp(theta), _dp(g), _dp(m), _dp(v), int(step), float(lr), float(b1),
+                          float(b2), float(eps))
+    if st != 0:
+        raise ValueError(f"orc_adam status {st}")

@@ -555,3 +555,19 @@ extern "C" int orc_eval_cs(int n_layers, const int *dims, const double *theta, c
   }
   return 0;
 }
+
+// Adam, one step, element by element in FP64 (Kingma & Ba, Algorithm 1).
+extern "C" int orc_adam(int64_t n, double *theta, const double *g, double *m, double *v, int64_t step,
+                        double lr, double b1, double b2, double eps) {
+  if (n < 0 || step < 1 || !theta || !g || !m || !v) return -1;
+  const double c1 = 1.0 - std::pow(b1, (double)step);
+  const double c2 = 1.0 - std::pow(b2, (double)step);
+  for (int64_t i = 0; i < n; ++i) {
+    m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+    v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+    const double mhat = m[i] / c1;
+    const double vhat = v[i] / c2;
+    theta[i] -= lr * mhat / (std::sqrt(vhat) + eps);
+  }
+  return 0;
+}

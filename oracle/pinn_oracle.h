@@ -71,6 +71,14 @@ int orc_eval_cs(int n_layers, const int *dims, const double *theta,
                 int64_t N, const double *x,
                 double *djets, double *dr, double *dloss, int n_threads);
 
+/* One Adam step (Kingma & Ba, Algorithm 1; the optimizer of the paper's
+ * training runs, Sec. 3.1) on n parameters, in place:
+ *   m <- b1 m + (1 - b1) g;   v <- b2 v + (1 - b2) g^2
+ *   theta <- theta - lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps)
+ * step counts from 1.  Status 0, or -1 for a bad argument. */
+int orc_adam(int64_t n, double *theta, const double *g, double *m, double *v, int64_t step,
+             double lr, double b1, double b2, double eps);
+
 #ifdef __cplusplus
 }
 #endif

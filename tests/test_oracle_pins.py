@@ -303,3 +303,43 @@ def test_channel_set_validation():
         oracle.evaluate(params, x, [(0, 0), (2, 1)], want_grad=False)
     with pytest.raises(ValueError):  # Burgers needs u_xx
         oracle.evaluate(params, x, [(0, 0), (1, 1), (0, 1)], "burgers", (0.01,))
+
+
+# ---------------------------------------------------------------- Adam
+def test_adam_constant_gradient_closed_form():
+    """A constant gradient gives m_hat = g and v_hat = g^2 at every step, so
+    theta_t = theta_0 - t lr g / (|g| + eps) exactly (up to rounding)."""
+    rng = np.random.default_rng(5)
+    g = rng.standard_normal(64) * np.logspace(-4, 2, 64)
+    th0 = rng.standard_normal(64)
+    th, m, v = th0.copy(), np.zeros(64), np.zeros(64)
+    lr, eps = 1e-3, 1e-8
+    for t in range(1, 8):
+        oracle.adam_step(th, g, m, v, t, lr=lr, eps=eps)
+        want = th0 - t * lr * g / (np.abs(g) + eps)
+        assert np.allclose(th, want, rtol=0, atol=1e-13), t
+
+
+def test_adam_matches_torch_optimizer():
+    """Five steps with varying gradients against torch.optim.Adam in float64
+    (an independent implementation of the same algorithm)."""
+    rng = np.random.default_rng(6)
+    th0 = rng.standard_normal(40)
+    grads = [rng.standard_normal(40) * (k + 1) for k in range(5)]
+    p = torch.tensor(th0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([p], lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+    th, m, v = th0.copy(), np.zeros(40), np.zeros(40)
+    for k, gk in enumerate(grads):
+        opt.zero_grad()
+        p.grad = torch.tensor(gk, dtype=torch.float64)
+        opt.step()
+        oracle.adam_step(th, gk.copy(), m, v, k + 1)
+        assert np.allclose(th, p.detach().numpy(), rtol=0, atol=1e-14), k
+
+
+def test_adam_zero_gradient_leaves_parameters():
+    th0 = np.linspace(-1.0, 1.0, 11)
+    th, m, v = th0.copy(), np.zeros(11), np.zeros(11)
+    for t in range(1, 4):
+        oracle.adam_step(th, np.zeros(11), m, v, t)
+    assert np.array_equal(th, th0)
