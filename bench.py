@@ -135,6 +135,22 @@ def time_path(prob, prec, steps, warmup, profile_dominant=True, tuning=None, sav
     t1 = time.perf_counter()
     dom_ms, dom_n = plan.profile_read() if profile_dominant else (float("nan"), 0)
     plan.profile("off")
+    # a training step: the same step plus the fused Adam update (lr 1e-3, as in
+    # the paper's runs), on a copy of the parameters (context)
+    from paper_2606_29702_amd import AdamState
+    tparams = [(W.clone(), b.clone()) for W, b in params]
+    tgrads = [(torch.empty_like(W), torch.empty_like(b)) for W, b in tparams]
+    opt = AdamState(tparams, lr=1e-3)
+    for _ in range(max(warmup, 5)):
+        plan.residual(tparams, x)
+        opt.step(plan.backward(tparams, x, out=tgrads))
+    torch.cuda.synchronize()
+    a0 = time.perf_counter()
+    for _ in range(steps):
+        plan.residual(tparams, x)
+        opt.step(plan.backward(tparams, x, out=tgrads))
+    torch.cuda.synchronize()
+    train_ms = (time.perf_counter() - a0) * 1e3 / steps
     # the same step captured once as a HIP graph and replayed (context)
     graph = plan.capture_step(params, x)
     graph.launch()
@@ -148,7 +164,7 @@ def time_path(prob, prec, steps, warmup, profile_dominant=True, tuning=None, sav
     plan.close()
     return dict(ms_per_step=(t1 - t0) * 1e3 / steps, class_ms=class_ms, dominant=dominant,
                 dominant_avg_ms=dom_ms / max(dom_n, 1), dominant_launches=dom_n, tuning=tuning,
-                graph_ms_per_step=graph_ms)
+                graph_ms_per_step=graph_ms, train_ms_per_step=train_ms)
 
 
 def nested_autograd_fp32(prob, steps):
@@ -372,6 +388,9 @@ def main():
                    "save_cap_bytes": save_cap},
         "roofline": roof,
         "kernel_ms_per_step": {k: round(v[0], 4) for k, v in main_run["class_ms"].items()},
+        "train_step_adam": {"ms_per_step": round(main_run["train_ms_per_step"], 4),
+                            "value": round(N / (main_run["train_ms_per_step"] * 1e-3), 1), "unit": "pts/s",
+                            "note": "residual + dtheta + fused Adam update (pinn_adam_step)"},
         "graph_replay": {"ms_per_step": round(main_run["graph_ms_per_step"], 4),
                          "value": round(N / (main_run["graph_ms_per_step"] * 1e-3), 1), "unit": "pts/s"},
         "tuning": main_run["tuning"],

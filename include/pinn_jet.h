@@ -233,6 +233,31 @@ pinn_status pinn_graph_capture(pinn_plan plan, const pinn_net *net, const pinn_p
 pinn_status pinn_graph_launch(pinn_graph graph, void *stream);
 pinn_status pinn_graph_destroy(pinn_graph graph);
 
+/* Optimizer step: Adam (Kingma & Ba, Algorithm 1), the optimizer of the
+ * paper's training runs (full-batch Adam, Sec. 3.1), as one launch over every
+ * parameter tensor of a network.  For each layer l and each element,
+ *   m <- b1 m + (1 - b1) g,  v <- b2 v + (1 - b2) g^2,
+ *   theta <- theta - lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps)
+ * in FP32, in place on W[l], b[l] and the moment buffers.
+ *   n_layers, dims   as in pinn_net (1 <= n_layers <= 16)
+ *   W, b             host arrays of device pointers to the parameters
+ *                    (written); dW, db the gradients (read), e.g. those of
+ *                    pinn_jet_backward
+ *   mW, vW, mb, vb   host arrays of device pointers to the first and second
+ *                    moments, shaped like W and b, owned by the caller, zero
+ *                    before step 1
+ *   step             1, 2, ... (the bias corrections use it)
+ *   hp               lr > 0, 0 <= beta1, beta2 < 1, eps > 0
+ * Stream-ordered and asynchronous; allocates nothing, so it may be captured
+ * into a graph with the step that produces the gradients.  PINN_ERR_ARG on a
+ * NULL pointer, a bad shape or a bad hyperparameter (checked on the host). */
+typedef struct {
+  double lr, beta1, beta2, eps;
+} pinn_adam;
+pinn_status pinn_adam_step(int32_t n_layers, const int32_t *dims, float *const *W, float *const *b,
+                           const float *const *dW, const float *const *db, float *const *mW, float *const *vW,
+                           float *const *mb, float *const *vb, int64_t step, const pinn_adam *hp, void *stream);
+
 /* Launch timing, a measurement aid for benchmarks.  pinn_plan_profile selects
  * one kernel class (0 = off) and clears the accumulator; from then on every
  * launch of that class made through this plan is bracketed by a pair of

@@ -1,0 +1,37 @@
+// One Adam step (Kingma & Ba, Algorithm 1) over all parameter tensors of a
+// network in one launch: the optimizer of the paper's training runs (full-batch
+// Adam, Sec. 3.1).  FP32 parameters, gradients and moments; the bias
+// corrections 1 - beta^step come precomputed.
+#include "dev_common.hpp"
+#include "kernels.hpp"
+
+namespace pj {
+
+// blockIdx.y picks the tensor (segment); the x dimension strides over it.
+__global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
+  const int s = blockIdx.y;
+  const int64_t n = a.n[s];
+  float *__restrict__ p = a.p[s];
+  const float *__restrict__ g = a.g[s];
+  float *__restrict__ m = a.m[s];
+  float *__restrict__ v = a.v[s];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const float gi = g[i];
+    const float mi = a.b1 * m[i] + (1.f - a.b1) * gi;
+    const float vi = a.b2 * v[i] + (1.f - a.b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
+  }
+}
+
+hipError_t launch_adam(const AdamArgs &a, hipStream_t st) {
+  int64_t nmax = 0;
+  for (int s = 0; s < a.nseg; ++s) nmax = a.n[s] > nmax ? a.n[s] : nmax;
+  const int64_t blocks = (nmax + 255) / 256;
+  const dim3 grid((unsigned)(blocks < 1024 ? (blocks > 0 ? blocks : 1) : 1024), (unsigned)a.nseg);
+  hipLaunchKernelGGL(k_adam, grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace pj

@@ -168,4 +168,17 @@ hipError_t launch_reduce_parts2(const float *part, int splits, int64_t stride, i
                                 int64_t M2, float *a32, float *b32, double *a64, double *b64,
                                 hipStream_t st);
 
+// One Adam step over up to kAdamSegs parameter tensors (k_adam.hip).
+constexpr int kAdamSegs = 32;
+struct AdamArgs {
+  float *p[kAdamSegs];
+  const float *g[kAdamSegs];
+  float *m[kAdamSegs];
+  float *v[kAdamSegs];
+  int64_t n[kAdamSegs];
+  int nseg;
+  float lr, b1, b2, eps, c1, c2;  // c1 = 1 - b1^step, c2 = 1 - b2^step
+};
+hipError_t launch_adam(const AdamArgs &a, hipStream_t st);
+
 }  // namespace pj

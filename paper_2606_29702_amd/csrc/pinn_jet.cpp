@@ -899,6 +899,49 @@ pinn_status pinn_plan_autotune(pinn_plan plan, const pinn_net *net, const pinn_p
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
+// Adam step over all parameters of a network.
+// ---------------------------------------------------------------------------
+extern "C" pinn_status pinn_adam_step(int32_t n_layers, const int32_t *dims, float *const *W, float *const *b,
+                                      const float *const *dW, const float *const *db, float *const *mW,
+                                      float *const *vW, float *const *mb, float *const *vb, int64_t step,
+                                      const pinn_adam *hp, void *stream) {
+  g_err.clear();
+  if (n_layers < 1 || 2 * n_layers > pj::kAdamSegs)
+    return fail(PINN_ERR_ARG, "n_layers = %d outside [1, %d]", n_layers, pj::kAdamSegs / 2);
+  if (!dims || !W || !b || !dW || !db || !mW || !vW || !mb || !vb || !hp)
+    return fail(PINN_ERR_ARG, "NULL argument");
+  if (step < 1) return fail(PINN_ERR_ARG, "step = %lld, must be >= 1", (long long)step);
+  if (!(hp->lr > 0.0) || !(hp->beta1 >= 0.0 && hp->beta1 < 1.0) || !(hp->beta2 >= 0.0 && hp->beta2 < 1.0) ||
+      !(hp->eps > 0.0))
+    return fail(PINN_ERR_ARG, "Adam hyperparameters out of range");
+  pj::AdamArgs a{};
+  for (int l = 0; l < n_layers; ++l) {
+    if (dims[l] < 1 || dims[l + 1] < 1) return fail(PINN_ERR_ARG, "dims[%d..%d] must be positive", l, l + 1);
+    if (!W[l] || !b[l] || !dW[l] || !db[l] || !mW[l] || !vW[l] || !mb[l] || !vb[l])
+      return fail(PINN_ERR_ARG, "layer %d: NULL pointer", l);
+    a.p[2 * l] = W[l];
+    a.g[2 * l] = dW[l];
+    a.m[2 * l] = mW[l];
+    a.v[2 * l] = vW[l];
+    a.n[2 * l] = (int64_t)dims[l] * dims[l + 1];
+    a.p[2 * l + 1] = b[l];
+    a.g[2 * l + 1] = db[l];
+    a.m[2 * l + 1] = mb[l];
+    a.v[2 * l + 1] = vb[l];
+    a.n[2 * l + 1] = dims[l + 1];
+  }
+  a.nseg = 2 * n_layers;
+  a.lr = (float)hp->lr;
+  a.b1 = (float)hp->beta1;
+  a.b2 = (float)hp->beta2;
+  a.eps = (float)hp->eps;
+  a.c1 = (float)(1.0 - std::pow(hp->beta1, (double)step));
+  a.c2 = (float)(1.0 - std::pow(hp->beta2, (double)step));
+  const hipError_t e = pj::launch_adam(a, (hipStream_t)stream);
+  return e ? hip_fail(e, "adam") : PINN_OK;
+}
+
+// ---------------------------------------------------------------------------
 // One plan's step captured into a HIP graph.
 // ---------------------------------------------------------------------------
 struct pinn_graph_s {

@@ -153,9 +153,10 @@ class PinnPlan:
         return r, loss, loss64, jets
 
     def backward(self, params, x: torch.Tensor, r_bar: Optional[torch.Tensor] = None,
-                 want_f64: bool = False):
+                 want_f64: bool = False, out=None):
         """Gradient [(dW, db), ...] of the loss (r_bar None) or of <r_bar, r>;
-        with want_f64 also the FP64 reductions."""
+        with want_f64 also the FP64 reductions.  `out`, a list of (dW, db)
+        tensors shaped like params, receives the gradient instead of new ones."""
         nv = _NetView(params)
         N = x.shape[0]
         dev = x.device
@@ -163,7 +164,7 @@ class PinnPlan:
             _check_tensor(r_bar, "r_bar")
             if tuple(r_bar.shape) != (self.n_res, N):
                 raise ValueError("r_bar must be (n_res, N)")
-        grads = [(torch.empty_like(W), torch.empty_like(b)) for W, b in params]
+        grads = out if out is not None else [(torch.empty_like(W), torch.empty_like(b)) for W, b in params]
         dWp, k1 = ptr_array([g[0].data_ptr() for g in grads])
         dbp, k2 = ptr_array([g[1].data_ptr() for g in grads])
         g64 = None

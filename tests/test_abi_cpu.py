@@ -120,3 +120,22 @@ def test_single_hip_runtime_in_process():
     """The library binds to the HIP runtime torch loaded (one runtime per process)."""
     maps = set(l.split()[-1] for l in open("/proc/self/maps") if "libamdhip64" in l)
     assert len(maps) == 1, maps
+
+
+def test_adam_step_rejects_bad_arguments():
+    """Host-side validation of pinn_adam_step: nothing reaches the device."""
+    from paper_2606_29702_amd._lib import Adam
+    dims = (ctypes.c_int32 * 3)(2, 4, 1)
+    hp = Adam(1e-3, 0.9, 0.999, 1e-8)
+    assert lib.pinn_adam_step(2, dims, None, None, None, None, None, None, None, None, 1, ctypes.byref(hp),
+                              None) == -1
+    assert "NULL" in lib.pinn_last_error().decode()
+    assert lib.pinn_adam_step(0, dims, None, None, None, None, None, None, None, None, 1, ctypes.byref(hp),
+                              None) == -1
+    one = (ctypes.c_void_p * 2)(ctypes.c_void_p(16), ctypes.c_void_p(16))
+    pp = ctypes.cast(one, ctypes.POINTER(ctypes.c_void_p))
+    assert lib.pinn_adam_step(2, dims, pp, pp, pp, pp, pp, pp, pp, pp, 0, ctypes.byref(hp), None) == -1
+    assert "step" in lib.pinn_last_error().decode()
+    bad = Adam(1e-3, 1.0, 0.999, 1e-8)
+    assert lib.pinn_adam_step(2, dims, pp, pp, pp, pp, pp, pp, pp, pp, 1, ctypes.byref(bad), None) == -1
+    assert "hyperparameters" in lib.pinn_last_error().decode()

@@ -157,3 +157,31 @@ def test_plan_graph_replays_match_eager(lib, prec):
     graph.close()
     plan.close()
     eager.close()
+
+
+def test_adam_step_matches_oracle(lib):
+    """Three fused Adam steps on a network's parameters against the FP64
+    oracle's Adam from the same FP32 starting values and gradients."""
+    dims = [2, 64, 64, 3]
+    rng = np.random.default_rng(23)
+    params = [(torch.tensor(rng.standard_normal((dims[l + 1], dims[l])), dtype=torch.float32, device="cuda"),
+               torch.tensor(rng.standard_normal(dims[l + 1]), dtype=torch.float32, device="cuda"))
+              for l in range(len(dims) - 1)]
+    flat0 = np.concatenate([np.concatenate([W.double().cpu().numpy().ravel(), b.double().cpu().numpy().ravel()])
+                            for W, b in params])
+    th, m, v = flat0.copy(), np.zeros_like(flat0), np.zeros_like(flat0)
+    opt = lib.AdamState(params, lr=1e-3)
+    for t in range(1, 4):
+        grads = [(torch.tensor(rng.standard_normal(W.shape) * t, dtype=torch.float32, device="cuda"),
+                  torch.tensor(rng.standard_normal(b.shape) * t, dtype=torch.float32, device="cuda"))
+                 for W, b in params]
+        g = np.concatenate([np.concatenate([dW.double().cpu().numpy().ravel(), db.double().cpu().numpy().ravel()])
+                            for dW, db in grads])
+        opt.step(grads)
+        oracle.adam_step(th, g, m, v, t)
+        torch.cuda.synchronize()
+        got = np.concatenate([np.concatenate([W.double().cpu().numpy().ravel(), b.double().cpu().numpy().ravel()])
+                              for W, b in params])
+        err = np.max(np.abs(got - th) / np.maximum(np.abs(th), 1.0))
+        print(f"step {t}: max err {err:.2e}")
+        assert err <= 1e-6, t
