@@ -141,7 +141,10 @@ def time_path(prob, prec, steps, warmup, profile_dominant=True, tuning=None, sav
     tparams = [(W.clone(), b.clone()) for W, b in params]
     tgrads = [(torch.empty_like(W), torch.empty_like(b)) for W, b in tparams]
     opt = AdamState(tparams, lr=1e-3)
-    for _ in range(max(warmup, 5)):
+    # a long warm-up: the HIP runtime's launch resources grow while the host
+    # runs ahead of the GPU, which stalls the host once every few hundred
+    # launches until they settle
+    for _ in range(max(warmup, 100)):
         plan.residual(tparams, x)
         opt.step(plan.backward(tparams, x, out=tgrads))
     torch.cuda.synchronize()
