@@ -141,9 +141,9 @@ def time_path(prob, prec, steps, warmup, profile_dominant=True, tuning=None, sav
     tparams = [(W.clone(), b.clone()) for W, b in params]
     tgrads = [(torch.empty_like(W), torch.empty_like(b)) for W, b in tparams]
     opt = AdamState(tparams, lr=1e-3)
-    # a long warm-up: the HIP runtime's launch resources grow while the host
-    # runs ahead of the GPU, which stalls the host once every few hundred
-    # launches until they settle
+    # a long warm-up: early in a long eager loop, with the host far ahead of the
+    # GPU, a host call occasionally blocks for tens of milliseconds (seen with
+    # and without the Adam step); later steps run at full rate
     for _ in range(max(warmup, 100)):
         plan.residual(tparams, x)
         opt.step(plan.backward(tparams, x, out=tgrads))
