@@ -208,31 +208,6 @@ pinn_status pinn_batch_autotune(pinn_batch batch, const pinn_net *nets, const pi
                                 float *const *const *db, int32_t reps, int32_t *best_streams, double *best_ms,
                                 void *stream);
 
-/* One training-step graph of a plan: pinn_jet_residual (r, loss) followed by
- * pinn_jet_backward of the loss (r_bar = NULL) recorded into a HIP graph.
- * The graph is the standard route for callers that replay a fixed step:
- * one launch per step, no host work per step.
- *   pinn_graph_capture  validates like the two step calls, then records them
- *                       on a private stream (nothing executes) and instantiates
- *                       the graph.  r and loss may be NULL.  dW and db are host
- *                       arrays of device pointers as in pinn_jet_backward; the
- *                       pointer values (not the arrays) are kept.
- *   pinn_graph_launch   runs the step after the work already queued on
- *                       `stream`; work queued on `stream` afterwards waits for
- *                       it.  Each launch reads the current contents of W, b and
- *                       x and overwrites r, loss, dW and db.
- *   pinn_graph_destroy  releases the graph (not the plan).
- * The graph uses the plan's workspace and saved state: the plan must outlive
- * it, its tuning is frozen in the graph, and calls on the plan must not
- * overlap a launch on another stream.  Launch timing (pinn_plan_profile) is
- * switched off while capturing. */
-typedef struct pinn_graph_s *pinn_graph;
-pinn_status pinn_graph_capture(pinn_plan plan, const pinn_net *net, const pinn_pde *pde, const float *x,
-                               int64_t N, float *r, float *loss, float *const *dW, float *const *db,
-                               pinn_graph *out);
-pinn_status pinn_graph_launch(pinn_graph graph, void *stream);
-pinn_status pinn_graph_destroy(pinn_graph graph);
-
 /* Optimizer step: Adam (Kingma & Ba, Algorithm 1), the optimizer of the
  * paper's training runs (full-batch Adam, Sec. 3.1), as one launch over every
  * parameter tensor of a network.  For each layer l and each element,
@@ -257,6 +232,42 @@ typedef struct {
 pinn_status pinn_adam_step(int32_t n_layers, const int32_t *dims, float *const *W, float *const *b,
                            const float *const *dW, const float *const *db, float *const *mW, float *const *vW,
                            float *const *mb, float *const *vb, int64_t step, const pinn_adam *hp, void *stream);
+
+/* One training-step graph of a plan: pinn_jet_residual (r, loss) followed by
+ * pinn_jet_backward of the loss (r_bar = NULL) recorded into a HIP graph.
+ * The graph is the standard route for callers that replay a fixed step:
+ * one launch per step, no host work per step.
+ *   pinn_graph_capture  validates like the two step calls, then records them
+ *                       on a private stream (nothing executes) and instantiates
+ *                       the graph.  r and loss may be NULL.  dW and db are host
+ *                       arrays of device pointers as in pinn_jet_backward; the
+ *                       pointer values (not the arrays) are kept.
+ *   pinn_graph_launch   runs the step after the work already queued on
+ *                       `stream`; work queued on `stream` afterwards waits for
+ *                       it.  Each launch reads the current contents of W, b and
+ *                       x and overwrites r, loss, dW and db.
+ *   pinn_graph_destroy  releases the graph (not the plan).
+ * The graph uses the plan's workspace and saved state: the plan must outlive
+ * it, its tuning is frozen in the graph, and calls on the plan must not
+ * overlap a launch on another stream.  Launch timing (pinn_plan_profile) is
+ * switched off while capturing. */
+typedef struct pinn_graph_s *pinn_graph;
+pinn_status pinn_graph_capture(pinn_plan plan, const pinn_net *net, const pinn_pde *pde, const float *x,
+                               int64_t N, float *r, float *loss, float *const *dW, float *const *db,
+                               pinn_graph *out);
+/* A training-step graph: the step above followed by the Adam update of
+ * pinn_adam_step applied to the parameters net->W, net->b (updated in place by
+ * every launch; the pointers in net must be writable), with the moments
+ * mW, vW, mb, vb and hyperparameters hp as in pinn_adam_step.  The step count
+ * lives in device memory: *step_dev (caller-owned int64, 0 before the first
+ * launch) is the number of updates done; each launch uses *step_dev + 1 and
+ * then advances it. */
+pinn_status pinn_graph_capture_train(pinn_plan plan, const pinn_net *net, const pinn_pde *pde, const float *x,
+                                     int64_t N, float *r, float *loss, float *const *dW, float *const *db,
+                                     float *const *mW, float *const *vW, float *const *mb, float *const *vb,
+                                     const pinn_adam *hp, int64_t *step_dev, pinn_graph *out);
+pinn_status pinn_graph_launch(pinn_graph graph, void *stream);
+pinn_status pinn_graph_destroy(pinn_graph graph);
 
 /* Launch timing, a measurement aid for benchmarks.  pinn_plan_profile selects
  * one kernel class (0 = off) and clears the accumulator; from then on every

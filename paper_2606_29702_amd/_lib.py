@@ -29,7 +29,7 @@ EXPORTS = ["pinn_plan_create", "pinn_plan_destroy", "pinn_plan_memory", "pinn_je
            "pinn_pde_residuals", "pinn_plan_profile", "pinn_plan_profile_read", "pinn_plan_get_tuning",
            "pinn_plan_set_tuning", "pinn_plan_autotune", "pinn_batch_create", "pinn_batch_destroy",
            "pinn_batch_configure", "pinn_batch_step", "pinn_batch_autotune", "pinn_graph_capture",
-           "pinn_graph_launch", "pinn_graph_destroy", "pinn_adam_step"]
+           "pinn_graph_launch", "pinn_graph_destroy", "pinn_adam_step", "pinn_graph_capture_train"]
 KERNEL_CLASSES = {"layer_fwd": 1, "layer_bwd": 2, "dw_hidden": 3, "out_fwd": 4, "out_bwd": 5,
                   "seed_fwd": 6, "other": 7, "bwd_dw": 8}
 
@@ -90,6 +90,8 @@ def _load():
     lib.pinn_graph_destroy.argtypes = [vp]
     lib.pinn_adam_step.argtypes = [i32, ctypes.POINTER(ctypes.c_int32), pp, pp, pp, pp, pp, pp, pp, pp, i64,
                                    ctypes.POINTER(Adam), vp]
+    lib.pinn_graph_capture_train.argtypes = [vp, NetP, PdeP, vp, i64, vp, vp, pp, pp, pp, pp, pp, pp,
+                                             ctypes.POINTER(Adam), vp, pp]
     lib.pinn_last_error.restype = ctypes.c_char_p
     lib.pinn_last_error.argtypes = []
     lib.pinn_pde_channels.argtypes = [i32]
@@ -99,7 +101,7 @@ def _load():
                  "pinn_plan_profile", "pinn_plan_profile_read", "pinn_plan_get_tuning", "pinn_plan_set_tuning",
                  "pinn_plan_autotune", "pinn_batch_create", "pinn_batch_destroy", "pinn_batch_configure",
                  "pinn_batch_step", "pinn_batch_autotune", "pinn_graph_capture", "pinn_graph_launch",
-                 "pinn_graph_destroy", "pinn_adam_step"):
+                 "pinn_graph_destroy", "pinn_adam_step", "pinn_graph_capture_train"):
         getattr(lib, name).restype = ctypes.c_int32
     return lib
 

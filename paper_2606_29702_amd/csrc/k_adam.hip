@@ -1,14 +1,17 @@
 // One Adam step (Kingma & Ba, Algorithm 1) over all parameter tensors of a
 // network in one launch: the optimizer of the paper's training runs (full-batch
-// Adam, Sec. 3.1).  FP32 parameters, gradients and moments; the bias
-// corrections 1 - beta^step come precomputed.
+// Adam, Sec. 3.1).  FP32 parameters, gradients and moments.
 #include "dev_common.hpp"
 #include "kernels.hpp"
 
 namespace pj {
 
 // blockIdx.y picks the tensor (segment); the x dimension strides over it.
+// The step count comes by value or, for graph replays, from device memory; the
+// bias corrections 1 - beta^step are formed here in either case.
 __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
+  const int64_t t = a.step_dev ? *a.step_dev + 1 : a.step;
+  const float c1 = 1.f - powf(a.b1, (float)t), c2 = 1.f - powf(a.b2, (float)t);
   const int s = blockIdx.y;
   const int64_t n = a.n[s];
   float *__restrict__ p = a.p[s];
@@ -21,8 +24,18 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
     const float vi = a.b2 * v[i] + (1.f - a.b2) * gi * gi;
     m[i] = mi;
     v[i] = vi;
-    p[i] -= a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
+    p[i] -= a.lr * (mi / c1) / (sqrtf(vi / c2) + a.eps);
   }
+}
+
+// Advances a device step counter after a graph's Adam update.
+__global__ void k_step_count(int64_t *step) {
+  if (threadIdx.x == 0) *step += 1;
+}
+
+hipError_t launch_step_count(int64_t *step, hipStream_t st) {
+  hipLaunchKernelGGL(k_step_count, dim3(1), dim3(64), 0, st, step);
+  return hipGetLastError();
 }
 
 hipError_t launch_adam(const AdamArgs &a, hipStream_t st) {

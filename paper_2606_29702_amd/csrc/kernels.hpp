@@ -177,8 +177,11 @@ struct AdamArgs {
   float *v[kAdamSegs];
   int64_t n[kAdamSegs];
   int nseg;
-  float lr, b1, b2, eps, c1, c2;  // c1 = 1 - b1^step, c2 = 1 - b2^step
+  float lr, b1, b2, eps;
+  int64_t step;             // 1, 2, ... when step_dev is null
+  const int64_t *step_dev;  // else: steps completed so far, in device memory
 };
 hipError_t launch_adam(const AdamArgs &a, hipStream_t st);
+hipError_t launch_step_count(int64_t *step, hipStream_t st);  // *step += 1
 
 }  // namespace pj

@@ -901,42 +901,52 @@ pinn_status pinn_plan_autotune(pinn_plan plan, const pinn_net *net, const pinn_p
 // ---------------------------------------------------------------------------
 // Adam step over all parameters of a network.
 // ---------------------------------------------------------------------------
+// Validates the Adam arguments and fills the kernel argument block.
+static pinn_status adam_args(int32_t n_layers, const int32_t *dims, float *const *W, float *const *b,
+                             const float *const *dW, const float *const *db, float *const *mW, float *const *vW,
+                             float *const *mb, float *const *vb, const pinn_adam *hp, pj::AdamArgs *a) {
+  if (n_layers < 1 || 2 * n_layers > pj::kAdamSegs)
+    return fail(PINN_ERR_ARG, "n_layers = %d outside [1, %d]", n_layers, pj::kAdamSegs / 2);
+  if (!dims || !W || !b || !dW || !db || !mW || !vW || !mb || !vb || !hp)
+    return fail(PINN_ERR_ARG, "NULL argument");
+  if (!(hp->lr > 0.0) || !(hp->beta1 >= 0.0 && hp->beta1 < 1.0) || !(hp->beta2 >= 0.0 && hp->beta2 < 1.0) ||
+      !(hp->eps > 0.0))
+    return fail(PINN_ERR_ARG, "Adam hyperparameters out of range");
+  *a = pj::AdamArgs{};
+  for (int l = 0; l < n_layers; ++l) {
+    if (dims[l] < 1 || dims[l + 1] < 1) return fail(PINN_ERR_ARG, "dims[%d..%d] must be positive", l, l + 1);
+    if (!W[l] || !b[l] || !dW[l] || !db[l] || !mW[l] || !vW[l] || !mb[l] || !vb[l])
+      return fail(PINN_ERR_ARG, "layer %d: NULL pointer", l);
+    a->p[2 * l] = W[l];
+    a->g[2 * l] = dW[l];
+    a->m[2 * l] = mW[l];
+    a->v[2 * l] = vW[l];
+    a->n[2 * l] = (int64_t)dims[l] * dims[l + 1];
+    a->p[2 * l + 1] = b[l];
+    a->g[2 * l + 1] = db[l];
+    a->m[2 * l + 1] = mb[l];
+    a->v[2 * l + 1] = vb[l];
+    a->n[2 * l + 1] = dims[l + 1];
+  }
+  a->nseg = 2 * n_layers;
+  a->lr = (float)hp->lr;
+  a->b1 = (float)hp->beta1;
+  a->b2 = (float)hp->beta2;
+  a->eps = (float)hp->eps;
+  return PINN_OK;
+}
+
 extern "C" pinn_status pinn_adam_step(int32_t n_layers, const int32_t *dims, float *const *W, float *const *b,
                                       const float *const *dW, const float *const *db, float *const *mW,
                                       float *const *vW, float *const *mb, float *const *vb, int64_t step,
                                       const pinn_adam *hp, void *stream) {
   g_err.clear();
-  if (n_layers < 1 || 2 * n_layers > pj::kAdamSegs)
-    return fail(PINN_ERR_ARG, "n_layers = %d outside [1, %d]", n_layers, pj::kAdamSegs / 2);
-  if (!dims || !W || !b || !dW || !db || !mW || !vW || !mb || !vb || !hp)
-    return fail(PINN_ERR_ARG, "NULL argument");
+  pj::AdamArgs a;
+  pinn_status st = adam_args(n_layers, dims, W, b, dW, db, mW, vW, mb, vb, hp, &a);
+  if (st) return st;
   if (step < 1) return fail(PINN_ERR_ARG, "step = %lld, must be >= 1", (long long)step);
-  if (!(hp->lr > 0.0) || !(hp->beta1 >= 0.0 && hp->beta1 < 1.0) || !(hp->beta2 >= 0.0 && hp->beta2 < 1.0) ||
-      !(hp->eps > 0.0))
-    return fail(PINN_ERR_ARG, "Adam hyperparameters out of range");
-  pj::AdamArgs a{};
-  for (int l = 0; l < n_layers; ++l) {
-    if (dims[l] < 1 || dims[l + 1] < 1) return fail(PINN_ERR_ARG, "dims[%d..%d] must be positive", l, l + 1);
-    if (!W[l] || !b[l] || !dW[l] || !db[l] || !mW[l] || !vW[l] || !mb[l] || !vb[l])
-      return fail(PINN_ERR_ARG, "layer %d: NULL pointer", l);
-    a.p[2 * l] = W[l];
-    a.g[2 * l] = dW[l];
-    a.m[2 * l] = mW[l];
-    a.v[2 * l] = vW[l];
-    a.n[2 * l] = (int64_t)dims[l] * dims[l + 1];
-    a.p[2 * l + 1] = b[l];
-    a.g[2 * l + 1] = db[l];
-    a.m[2 * l + 1] = mb[l];
-    a.v[2 * l + 1] = vb[l];
-    a.n[2 * l + 1] = dims[l + 1];
-  }
-  a.nseg = 2 * n_layers;
-  a.lr = (float)hp->lr;
-  a.b1 = (float)hp->beta1;
-  a.b2 = (float)hp->beta2;
-  a.eps = (float)hp->eps;
-  a.c1 = (float)(1.0 - std::pow(hp->beta1, (double)step));
-  a.c2 = (float)(1.0 - std::pow(hp->beta2, (double)step));
+  a.step = step;
+  a.step_dev = nullptr;
   const hipError_t e = pj::launch_adam(a, (hipStream_t)stream);
   return e ? hip_fail(e, "adam") : PINN_OK;
 }
@@ -957,12 +967,11 @@ struct pinn_graph_s {
   }
 };
 
-extern "C" {
-
-pinn_status pinn_graph_capture(pinn_plan plan, const pinn_net *net, const pinn_pde *pde, const float *x,
-                               int64_t N, float *r, float *loss, float *const *dW, float *const *db,
-                               pinn_graph *out) {
-  g_err.clear();
+// Records residual + loss-gradient backward (and, with `adam`, the Adam update
+// and the step counter's advance) on a private stream and instantiates it.
+static pinn_status graph_capture(pinn_plan plan, const pinn_net *net, const pinn_pde *pde, const float *x,
+                                 int64_t N, float *r, float *loss, float *const *dW, float *const *db,
+                                 const pj::AdamArgs *adam, int64_t *step_dev, pinn_graph *out) {
   if (!out) return fail(PINN_ERR_ARG, "out is NULL");
   *out = nullptr;
   pinn_status st = check_call(plan, net, x, N);
@@ -990,14 +999,19 @@ pinn_status pinn_graph_capture(pinn_plan plan, const pinn_net *net, const pinn_p
   st = pinn_jet_residual(plan, net, pde, x, N, r, loss, nullptr, nullptr, gr->origin);
   if (st == PINN_OK)
     st = pinn_jet_backward(plan, net, pde, x, N, nullptr, dW, db, nullptr, nullptr, gr->origin);
+  hipError_t ek = hipSuccess;
+  if (st == PINN_OK && adam) {
+    ek = pj::launch_adam(*adam, gr->origin);
+    if (ek == hipSuccess) ek = pj::launch_step_count(step_dev, gr->origin);
+  }
   const std::string msg = g_err;
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(gr->origin, &g);
-  if (st || e) {
+  if (st || e || ek) {
     if (g) (void)hipGraphDestroy(g);
     delete gr;
     if (st) return fail(st, "%s", msg.c_str());
-    return hip_fail(e, "graph capture");
+    return hip_fail(ek ? ek : e, "graph capture");
   }
   e = hipGraphInstantiate(&gr->exec, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
@@ -1007,6 +1021,32 @@ pinn_status pinn_graph_capture(pinn_plan plan, const pinn_net *net, const pinn_p
   }
   *out = gr;
   return PINN_OK;
+}
+
+extern "C" {
+
+pinn_status pinn_graph_capture(pinn_plan plan, const pinn_net *net, const pinn_pde *pde, const float *x,
+                               int64_t N, float *r, float *loss, float *const *dW, float *const *db,
+                               pinn_graph *out) {
+  g_err.clear();
+  return graph_capture(plan, net, pde, x, N, r, loss, dW, db, nullptr, nullptr, out);
+}
+
+pinn_status pinn_graph_capture_train(pinn_plan plan, const pinn_net *net, const pinn_pde *pde, const float *x,
+                                     int64_t N, float *r, float *loss, float *const *dW, float *const *db,
+                                     float *const *mW, float *const *vW, float *const *mb, float *const *vb,
+                                     const pinn_adam *hp, int64_t *step_dev, pinn_graph *out) {
+  g_err.clear();
+  if (!net || !step_dev) return fail(PINN_ERR_ARG, "net or step_dev is NULL");
+  if (!out) return fail(PINN_ERR_ARG, "out is NULL");
+  pj::AdamArgs a;
+  // the net's parameters are the ones the replays update in place
+  pinn_status st = adam_args(net->n_layers, net->dims, const_cast<float *const *>(net->W),
+                             const_cast<float *const *>(net->b), dW, db, mW, vW, mb, vb, hp, &a);
+  if (st) return st;
+  a.step = 0;
+  a.step_dev = step_dev;
+  return graph_capture(plan, net, pde, x, N, r, loss, dW, db, &a, step_dev, out);
 }
 
 pinn_status pinn_graph_launch(pinn_graph gr, void *stream) {

@@ -182,10 +182,13 @@ class PinnPlan:
         return (grads, g64) if want_f64 else grads
 
 
-    def capture_step(self, params, x: torch.Tensor) -> "PinnGraph":
+    def capture_step(self, params, x: torch.Tensor, adam=None) -> "PinnGraph":
         """The residual + loss-gradient step on (params, x) as a replayable
-        HIP graph (pinn_graph_capture); outputs live on the returned object."""
-        return PinnGraph(self, params, x)
+        HIP graph (pinn_graph_capture); outputs live on the returned object.
+        With `adam` (an AdamState on the same params) the graph also applies
+        the Adam update (pinn_graph_capture_train), counting steps on the
+        device."""
+        return PinnGraph(self, params, x, adam)
 
 
 class PinnGraph:
@@ -193,7 +196,7 @@ class PinnGraph:
     stream, reading the current contents of the parameter and point tensors
     given at capture; r, loss and grads are overwritten by every launch."""
 
-    def __init__(self, plan: PinnPlan, params, x: torch.Tensor):
+    def __init__(self, plan: PinnPlan, params, x: torch.Tensor, adam=None):
         _check_tensor(x, "x")
         self.plan = plan
         self.params = params  # kept alive: the graph holds their pointers
@@ -207,9 +210,21 @@ class PinnGraph:
         dWp, self._k1 = ptr_array([g[0].data_ptr() for g in self.grads])
         dbp, self._k2 = ptr_array([g[1].data_ptr() for g in self.grads])
         handle = ctypes.c_void_p()
-        check(lib.pinn_graph_capture(plan.handle, ctypes.byref(nv.net), ctypes.byref(_pde(plan.pde, plan.coef)),
-                                     ctypes.c_void_p(x.data_ptr()), N, ctypes.c_void_p(self.r.data_ptr()),
-                                     ctypes.c_void_p(self.loss.data_ptr()), dWp, dbp, ctypes.byref(handle)))
+        self._nv = nv
+        self.adam = adam
+        if adam is None:
+            check(lib.pinn_graph_capture(plan.handle, ctypes.byref(nv.net), ctypes.byref(_pde(plan.pde, plan.coef)),
+                                         ctypes.c_void_p(x.data_ptr()), N, ctypes.c_void_p(self.r.data_ptr()),
+                                         ctypes.c_void_p(self.loss.data_ptr()), dWp, dbp, ctypes.byref(handle)))
+        else:
+            if [p.data_ptr() for pair in adam.params for p in pair] != [p.data_ptr() for pair in params for p in pair]:
+                raise ValueError("the AdamState must hold the same parameter tensors")
+            self.step = torch.zeros((), device=dev, dtype=torch.int64)  # updates done so far
+            check(lib.pinn_graph_capture_train(
+                plan.handle, ctypes.byref(nv.net), ctypes.byref(_pde(plan.pde, plan.coef)),
+                ctypes.c_void_p(x.data_ptr()), N, ctypes.c_void_p(self.r.data_ptr()),
+                ctypes.c_void_p(self.loss.data_ptr()), dWp, dbp, adam._mW[0], adam._vW[0], adam._mb[0],
+                adam._vb[0], ctypes.byref(adam.hp), ctypes.c_void_p(self.step.data_ptr()), ctypes.byref(handle)))
         self.handle = handle
 
     def launch(self) -> None:

@@ -185,3 +185,33 @@ def test_adam_step_matches_oracle(lib):
         err = np.max(np.abs(got - th) / np.maximum(np.abs(th), 1.0))
         print(f"step {t}: max err {err:.2e}")
         assert err <= 1e-6, t
+
+
+def test_training_graph_matches_eager_training(lib):
+    """A captured training step (residual, gradient, Adam) replayed four times
+    equals four eager training steps bit for bit: parameters, loss and the
+    device step counter."""
+    dims = [2, 64, 64, 64, 3]
+    prob = pi.make_problem("ns", N=4000, seed=29, bias_std=0.3, dims=dims)
+    x = torch.tensor(prob.x, device="cuda")
+    pg = [(torch.tensor(W, device="cuda"), torch.tensor(b, device="cuda")) for W, b in prob.params]
+    pe = [(W.clone(), b.clone()) for W, b in pg]
+    plan_g = lib.PinnPlan(dims, "ns", 4000, precision="bf16", coef=prob.coef)
+    plan_e = lib.PinnPlan(dims, "ns", 4000, precision="bf16", coef=prob.coef)
+    opt_g = lib.AdamState(pg, lr=1e-3)
+    opt_e = lib.AdamState(pe, lr=1e-3)
+    graph = plan_g.capture_step(pg, x, adam=opt_g)
+    grads_e = [(torch.empty_like(W), torch.empty_like(b)) for W, b in pe]
+    for k in range(4):
+        graph.launch()
+        _, loss_e, _, _ = plan_e.residual(pe, x)
+        plan_e.backward(pe, x, out=grads_e)
+        opt_e.step(grads_e)
+        torch.cuda.synchronize()
+        assert torch.equal(graph.loss, loss_e), k
+        for (a, b), (c, d) in zip(pg, pe):
+            assert torch.equal(a, c) and torch.equal(b, d), k
+        assert int(graph.step) == k + 1
+    graph.close()
+    plan_g.close()
+    plan_e.close()
