@@ -101,6 +101,23 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
+// 8-byte LDS transpose read of 16-bit elements (gfx950 ds_read_b64_tr_b16):
+// within each group of 16 lanes, output lane 4a + e receives element e of the
+// 8-byte reads of lanes a, a + 4, a + 8, a + 12 (checked on the GPU).  So when
+// lane s of a group reads row k0 + s / 4 at columns c0 + 4 (s % 4) .. + 3,
+// lane r receives column c0 + r of rows k0 .. k0 + 3: four consecutive
+// contraction elements of an MFMA operand, from a tile stored row-major.
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+template <class T>
+__device__ __forceinline__ auto lds_tr16(const T *p) {
+  const i16x4 v =
+      __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) i16x4 *)(const_cast<T *>(p)));
+  if constexpr (__is_same(T, bf16_t))
+    return __builtin_bit_cast(bf16x4, v);
+  else
+    return __builtin_bit_cast(f16x4, v);
+}
+
 // Row blocks moved between global memory, where the rows of a block are
 // contiguous, and LDS, where row p starts at element p * pitch.  The unit is a
 // 16-byte piece: piece q of a block sits at element q * (16 / sizeof(T)) in

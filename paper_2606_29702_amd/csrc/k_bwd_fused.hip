@@ -20,19 +20,6 @@ namespace pj {
 
 typedef __bf16 bf16x4v __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x4v __attribute__((ext_vector_type(4)));
-typedef short i16x4v __attribute__((ext_vector_type(4)));
-
-// 8-byte LDS transpose read of 16-bit elements (gfx950), as the 4-element
-// MFMA operand of type T.
-template <class T>
-__device__ __forceinline__ auto lds_tr16(const T *p) {
-  const i16x4v v = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
-      (__attribute__((address_space(3))) i16x4v *)(const_cast<T *>(p)));
-  if constexpr (sizeof(T) == 2 && __is_same(T, bf16_t))
-    return __builtin_bit_cast(bf16x4v, v);
-  else
-    return __builtin_bit_cast(f16x4v, v);
-}
 
 // MFMA with a 16-long contraction: lane l supplies the 4 consecutive
 // contraction elements 4*(l/16) .. 4*(l/16)+3 of row (l%16) of A and of

@@ -7,8 +7,9 @@
 // The stacks are stored [rows][w] with the neuron index contiguous, so the
 // contraction index is strided in memory.  A workgroup stages 32 rows x TILE
 // columns of each operand through LDS (double-buffered: the next chunk's
-// global loads are in flight while the current chunk is multiplied) and every
-// lane gathers its 8 contraction elements down a column of the staged tile.
+// global loads are in flight while the current chunk is multiplied).  Each
+// lane takes its 8 contraction elements down a column of the staged tile: two
+// LDS transpose reads for 16-bit types, a gather for FP32.
 #include "dev_common.hpp"
 #include "kernels.hpp"
 
@@ -50,6 +51,21 @@ __device__ __forceinline__ Mma<float>::frag gather_col<float>(const float *p, in
   for (int e = 0; e < 4; ++e) {
     f.lo[e] = p[e * pitch];
     f.hi[e] = p[(e + 4) * pitch];
+  }
+  return f;
+}
+
+// The same operand by two LDS transpose reads (16-bit types): contraction
+// rows k0 .. k0 + 3 and k0 + 4 .. k0 + 7 of column c0 + lane % 16.
+template <class T>
+__device__ __forceinline__ typename Mma<T>::frag tr_col(const T *tile, int pitch, int k0, int c0, int r) {
+  const T *p = tile + (k0 + (r >> 2)) * pitch + c0 + 4 * (r & 3);
+  const auto lo = lds_tr16<T>(p), hi = lds_tr16<T>(p + 4 * pitch);
+  typename Mma<T>::frag f;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    f[e] = lo[e];
+    f[e + 4] = hi[e];
   }
   return f;
 }
@@ -135,12 +151,19 @@ __global__ __launch_bounds__(256) void k_dw_hidden(const T *__restrict__ Zb, con
 #pragma unroll
     for (int ks = 0; ks < RC / 32; ++ks) {
       typename M::frag fa[NT], fb[NT];
+      if constexpr (sizeof(T) == 2) {
 #pragma unroll
-      for (int jt = 0; jt < NT; ++jt)
-        fa[jt] = gather_col<T>(Zs + (32 * ks + 8 * g) * P + H * wj + 16 * jt + r16, P);
+        for (int jt = 0; jt < NT; ++jt) fa[jt] = tr_col<T>(Zs, P, 32 * ks + 8 * g, H * wj + 16 * jt, r16);
 #pragma unroll
-      for (int kt = 0; kt < NT; ++kt)
-        fb[kt] = gather_col<T>(As + (32 * ks + 8 * g) * P + H * wk + 16 * kt + r16, P);
+        for (int kt = 0; kt < NT; ++kt) fb[kt] = tr_col<T>(As, P, 32 * ks + 8 * g, H * wk + 16 * kt, r16);
+      } else {
+#pragma unroll
+        for (int jt = 0; jt < NT; ++jt)
+          fa[jt] = gather_col<T>(Zs + (32 * ks + 8 * g) * P + H * wj + 16 * jt + r16, P);
+#pragma unroll
+        for (int kt = 0; kt < NT; ++kt)
+          fb[kt] = gather_col<T>(As + (32 * ks + 8 * g) * P + H * wk + 16 * kt + r16, P);
+      }
 #pragma unroll
       for (int jt = 0; jt < NT; ++jt)
 #pragma unroll
