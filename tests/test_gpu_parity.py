@@ -182,6 +182,37 @@ def test_inner_product_identity_gpu(lib):
     plan.close()
 
 
+def test_taylor_remainder_gpu(lib):
+    """The GPU loss and the GPU gradient agree to second order (Eq. 13-14):
+    |L(theta + h delta) - L(theta) - h <g, delta>| falls like h^2.  Losses and
+    the gradient are the FP64 reductions of the FP32 path (no oracle)."""
+    prob = small_problem("burgers", seed=8)
+    wl = prob.workload
+    N = prob.x.shape[0]
+    plan = lib.PinnPlan(wl.dims, "burgers", N, verify_f64=True, coef=prob.coef)
+    x = torch.tensor(prob.x, device="cuda")
+    rng = np.random.default_rng(9)
+    deltas = [(rng.normal(size=W.shape) * 0.1, rng.normal(size=b.shape) * 0.1) for W, b in prob.params]
+
+    def loss_at(h):
+        ps = [(torch.tensor((W + h * dW).astype(np.float32), device="cuda"),
+               torch.tensor((b + h * db).astype(np.float32), device="cuda"))
+              for (W, b), (dW, db) in zip(prob.params, deltas)]
+        _, _, loss64, _ = plan.residual(ps, x)
+        torch.cuda.synchronize()
+        return float(loss64), ps
+
+    L0, p0 = loss_at(0.0)
+    _, g64 = plan.backward(p0, x, want_f64=True)
+    gd = float(flat(g64) @ np.concatenate([np.concatenate([dW.ravel(), db.ravel()]) for dW, db in deltas]))
+    hs = [0.08, 0.04, 0.02, 0.01]
+    rem = [abs(loss_at(h)[0] - L0 - h * gd) for h in hs]
+    slopes = [math.log(rem[i] / rem[i + 1]) / math.log(2.0) for i in range(len(hs) - 1)]
+    print("taylor remainders", [f"{r:.3e}" for r in rem], "slopes", [f"{s_:.2f}" for s_ in slopes])
+    assert all(1.7 <= s_ <= 2.3 for s_ in slopes), slopes
+    plan.close()
+
+
 def test_determinism(lib):
     prob = small_problem("heat", seed=8)
     a = run_gpu(lib, prob, "bf16")
