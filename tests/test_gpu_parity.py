@@ -244,6 +244,13 @@ def test_state_errors(lib):
     with pytest.raises(PinnError) as e:
         plan.residual(params, torch.zeros((N + 1, 2), device="cuda"))
     assert e.value.status == -1
+    # an empty point set is rejected on the host (N >= 1), for every entry point
+    empty = torch.zeros((0, 2), device="cuda")
+    for call in (lambda: plan.forward(params, empty), lambda: plan.residual(params, empty),
+                 lambda: plan.capture_step(params, empty)):
+        with pytest.raises(PinnError) as e:
+            call()
+        assert e.value.status == -1
     plan.close()
 
 
