@@ -22,7 +22,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liborc.so")
 
 ACT = {"tanh": 0, "identity": 1, "square": 2, "cube": 3, "sin": 4}
-PDE = {"none": 0, "burgers": 1, "ns": 2, "ks": 3, "heat": 4}
+PDE = {"none": 0, "burgers": 1, "ns": 2, "ks": 3, "heat": 4, "aniso": 5}
+MIXED2 = -2  # channel order code of a mixed second derivative
 
 _lib = None
 
@@ -106,8 +107,10 @@ class OracleResult:
 def _common(params, channels, coef):
     dims = np.ascontiguousarray(dims_of(params), dtype=np.int32)
     ch = list(channels)
-    ch_dir = np.ascontiguousarray([max(c[0], 0) if c[1] > 0 else 0 for c in ch], dtype=np.int32)
-    ch_ord = np.ascontiguousarray([c[1] for c in ch], dtype=np.int32)
+    # a channel is (direction, order); a mixed second derivative is ((i, j), 2)
+    ch_dir = np.ascontiguousarray([8 * c[0][0] + c[0][1] if isinstance(c[0], tuple)
+                                   else (max(c[0], 0) if c[1] > 0 else 0) for c in ch], dtype=np.int32)
+    ch_ord = np.ascontiguousarray([MIXED2 if isinstance(c[0], tuple) else c[1] for c in ch], dtype=np.int32)
     cf = np.zeros(4, dtype=np.float64)
     cf[:len(coef)] = np.asarray(coef, dtype=np.float64)
     return dims, ch_dir, ch_ord, cf

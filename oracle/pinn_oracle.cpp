@@ -39,6 +39,10 @@ struct ChannelSet {
   /* at[i][k]: channel index of d^k/dx_i^k, or -1.  at[i][0] = 0 (the value). */
   int at[kMaxDir][kMaxOrder + 1];
   int top[kMaxDir]; /* highest order present along direction i */
+  /* mixed second-order channels d^2/dx_i dx_j (i < j), Eq. 3 with i != j:
+     channel mix_c[m] with first-order partners mix_ci[m], mix_cj[m] */
+  int n_mix = 0;
+  int mix_c[kMaxCh], mix_ci[kMaxCh], mix_cj[kMaxCh];
 };
 
 int build_channels(int n_ch, const int *ch_dir, const int *ch_ord, int d_in, ChannelSet *cs) {
@@ -52,8 +56,22 @@ int build_channels(int n_ch, const int *ch_dir, const int *ch_ord, int d_in, Cha
   if (ch_ord[0] != 0) return -1;
   cs->dir[0] = -1;
   cs->ord[0] = 0;
+  cs->n_mix = 0;
+  int mix_i[kMaxCh], mix_j[kMaxCh];
   for (int c = 1; c < n_ch; ++c) {
     int i = ch_dir[c], k = ch_ord[c];
+    if (k == ORC_MIXED2) { /* d^2 / dx_i dx_j, i < j, coded as ch_dir = i * 8 + j */
+      const int mi = i / 8, mj = i % 8;
+      if (i < 0 || mi >= mj || mj >= d_in) return -1;
+      for (int m = 0; m < cs->n_mix; ++m)
+        if (mix_i[m] == mi && mix_j[m] == mj) return -1; /* duplicate */
+      cs->dir[c] = -1;
+      cs->ord[c] = 2;
+      mix_i[cs->n_mix] = mi;
+      mix_j[cs->n_mix] = mj;
+      cs->mix_c[cs->n_mix++] = c;
+      continue;
+    }
     if (i < 0 || i >= d_in || k < 1 || k > kMaxOrder) return -1;
     if (cs->at[i][k] != -1) return -1; /* duplicate */
     cs->dir[c] = i;
@@ -66,6 +84,11 @@ int build_channels(int n_ch, const int *ch_dir, const int *ch_ord, int d_in, Cha
     cs->top[i] = k;
     for (int kk = k + 1; kk <= kMaxOrder; ++kk)
       if (cs->at[i][kk] >= 0) return -1; /* order chain must be a prefix 1..k */
+  }
+  for (int m = 0; m < cs->n_mix; ++m) { /* a mixed channel needs both first-order channels */
+    cs->mix_ci[m] = cs->at[mix_i[m]][1];
+    cs->mix_cj[m] = cs->at[mix_j[m]][1];
+    if (cs->mix_ci[m] < 0 || cs->mix_cj[m] < 0) return -1;
   }
   return 0;
 }
@@ -216,18 +239,29 @@ void forward_point(const NetView &nv, const T *theta, const ChannelSet &cs, int 
         for (int k = 1; k <= cs.top[dir]; ++k)
           an[(size_t)cs.at[dir][k] * n_out + i] = faa_di_bruno(k, phi, zz);
       }
+      /* mixed second order (Eq. 3, i != j): a_ij = phi'' z_i z_j + phi' z_ij */
+      for (int m = 0; m < cs.n_mix; ++m) {
+        const T zi = z[(size_t)cs.mix_ci[m] * n_out + i], zj = z[(size_t)cs.mix_cj[m] * n_out + i];
+        const T zij = z[(size_t)cs.mix_c[m] * n_out + i];
+        an[(size_t)cs.mix_c[m] * n_out + i] = phi[2] * zi * zj + phi[1] * zij;
+      }
     }
   }
 }
 
 /* Residual channel lookups.  Returns -2 when a needed channel is missing. */
 struct PdeChannels {
-  int u, ut, ux, uxx, uxxxx, uy, uyy, uz, uzz;
+  int u, ut, ux, uxx, uxxxx, uy, uyy, uz, uzz, uxy;
 };
 
 int pde_channels(int kind, int d_in, int d_out, const ChannelSet &cs, PdeChannels *pc) {
   auto need = [&](int dir, int k) { return (dir < d_in) ? cs.at[dir][k] : -1; };
-  *pc = PdeChannels{0, -1, -1, -1, -1, -1, -1, -1, -1};
+  *pc = PdeChannels{0, -1, -1, -1, -1, -1, -1, -1, -1, -1};
+  auto need_mix = [&](int i, int j) {
+    for (int m = 0; m < cs.n_mix; ++m)
+      if (cs.mix_ci[m] == cs.at[i][1] && cs.mix_cj[m] == cs.at[j][1]) return cs.mix_c[m];
+    return -1;
+  };
   switch (kind) {
     case ORC_PDE_NONE: return 0;
     case ORC_PDE_BURGERS:
@@ -246,6 +280,12 @@ int pde_channels(int kind, int d_in, int d_out, const ChannelSet &cs, PdeChannel
       if (d_in != 4 || d_out != 1) return -1;
       pc->uxx = need(0, 2); pc->uyy = need(1, 2); pc->uzz = need(2, 2); pc->ut = need(3, 1);
       return (pc->uxx < 0 || pc->uyy < 0 || pc->uzz < 0 || pc->ut < 0) ? -2 : 0;
+    case ORC_PDE_ANISO:
+      if (d_in != 2 || d_out != 1) return -1;
+      pc->uxx = need(0, 2); pc->uyy = need(1, 2);
+      if (pc->uxx < 0 || pc->uyy < 0) return -2;
+      pc->uxy = need_mix(0, 1);
+      return pc->uxy < 0 ? -2 : 0;
     default: return -1;
   }
 }
@@ -283,6 +323,11 @@ void residual_point(int kind, const double *coef, const PdeChannels &pc, const d
     case ORC_PDE_HEAT: {
       const double ka = coef[0];
       r[0] = U(0, pc.ut) - ka * (U(0, pc.uxx) + U(0, pc.uyy) + U(0, pc.uzz)) - heat_source(xp);
+      break;
+    }
+    case ORC_PDE_ANISO: {
+      const double c = coef[0];
+      r[0] = U(0, pc.uxx) + 2.0 * c * U(0, pc.uxy) + U(0, pc.uyy);
       break;
     }
     default: break;
@@ -348,6 +393,13 @@ void residual_adjoint_point(int kind, const double *coef, const PdeChannels &pc,
       UB(0, pc.uzz) += -ka * rbar[0];
       break;
     }
+    case ORC_PDE_ANISO: {
+      const double c = coef[0];
+      UB(0, pc.uxx) += rbar[0];
+      UB(0, pc.uyy) += rbar[0];
+      UB(0, pc.uxy) += 2.0 * c * rbar[0];
+      break;
+    }
     default: break;
   }
 }
@@ -401,6 +453,16 @@ void backward_point(const NetView &nv, const double *theta, const ChannelSet &cs
             zbp[(size_t)cs.at[dir][m] * n_in + j] += faa_di_bruno_dz(k, m, phi, zz) * ab;
         }
       }
+      /* adjoint of a_ij = phi''(z_0) z_i z_j + phi'(z_0) z_ij */
+      for (int m = 0; m < cs.n_mix; ++m) {
+        const double ab = abar[(size_t)cs.mix_c[m] * n_in + j];
+        const double zi = zp[(size_t)cs.mix_ci[m] * n_in + j], zj = zp[(size_t)cs.mix_cj[m] * n_in + j];
+        const double zij = zp[(size_t)cs.mix_c[m] * n_in + j];
+        z0bar += (phi[3] * zi * zj + phi[2] * zij) * ab;
+        zbp[(size_t)cs.mix_ci[m] * n_in + j] += phi[2] * zj * ab;
+        zbp[(size_t)cs.mix_cj[m] * n_in + j] += phi[2] * zi * ab;
+        zbp[(size_t)cs.mix_c[m] * n_in + j] += phi[1] * ab;
+      }
       zbp[j] = z0bar;
     }
     zbar.swap(zbp);
@@ -437,6 +499,7 @@ extern "C" int orc_n_res(int pde_kind) {
     case ORC_PDE_NS: return 3;
     case ORC_PDE_KS: return 1;
     case ORC_PDE_HEAT: return 1;
+    case ORC_PDE_ANISO: return 1;
     default: return 0;
   }
 }

@@ -13,7 +13,8 @@
  *     followed by b_l (dims[l+1]).  The activation acts after layers 0..L-2;
  *     the last layer is linear.
  *   Channel set: C channels, channel 0 is the value.  Channel c > 0 is the pure
- *     derivative of order ch_ord[c] (1..4) along input direction ch_dir[c].
+ *     derivative of order ch_ord[c] (1..4) along input direction ch_dir[c], or
+ *     a mixed second derivative (ch_ord[c] = ORC_MIXED2, see below).
  *     For every (dir, k>1) channel the (dir, k-1) channel must also be present.
  *   Jets: d_out x C x N.   Residuals: n_res x N.
  *   Loss: sum over residual components of (1/N) sum_n r^2.
@@ -41,9 +42,16 @@ enum {
   ORC_PDE_BURGERS = 1, /* coef = {nu}; inputs (x, t); r = u_t + u u_x - nu u_xx */
   ORC_PDE_NS = 2,      /* coef = {Re}; inputs (x, y); outputs (u, v, p); Eq. 16 */
   ORC_PDE_KS = 3,      /* coef = {alpha, beta, gamma}; r = u_t + a u u_x + b u_xx + g u_xxxx */
-  ORC_PDE_HEAT = 4     /* coef = {kappa}; inputs (x, y, z, t);
+  ORC_PDE_HEAT = 4,    /* coef = {kappa}; inputs (x, y, z, t);
                           r = u_t - kappa (u_xx + u_yy + u_zz) - sin(pi x) sin(pi y) sin(pi z) e^-t */
+  ORC_PDE_ANISO = 5    /* coef = {c}; inputs (x, y); r = u_xx + 2 c u_xy + u_yy: a test
+                          operator with a mixed derivative (not one of the paper's problems) */
 };
+
+/* Channel order code for a mixed second derivative d^2/dx_i dx_j (i < j, Eq. 3
+ * with i != j): ch_ord = ORC_MIXED2 and ch_dir = 8 i + j.  Both first-order
+ * channels (i, 1) and (j, 1) must be present. */
+enum { ORC_MIXED2 = -2 };
 
 /* Status: 0 ok, -1 bad argument, -2 channel set does not cover the PDE. */
 

@@ -40,8 +40,9 @@ def nested_jets(params64, x, channels, act=torch.tanh):
                 jets[(o, c)] = u
                 continue
             g = u
-            for _ in range(k):
-                g = torch.autograd.grad(g.sum(), X, create_graph=True)[0][:, dr]
+            dirs = list(dr) if isinstance(dr, tuple) else [dr] * k  # mixed: ((i, j), 2)
+            for d_ in dirs:
+                g = torch.autograd.grad(g.sum(), X, create_graph=True)[0][:, d_]
             jets[(o, c)] = g
     return jets, X
 
@@ -65,6 +66,9 @@ def residuals(pde, jets, channels, X, coef):
     if pde == "ks":  # inputs (x, t)
         a, b, g = coef
         return [J(0, 1, 1) + a * J(0, 0, 0) * J(0, 0, 1) + b * J(0, 0, 2) + g * J(0, 0, 4)]
+    if pde == "aniso":  # inputs (x, y): u_xx + 2 c u_xy + u_yy
+        c = coef[0]
+        return [J(0, 0, 2) + 2.0 * c * jets[(0, idx[((0, 1), 2)])] + J(0, 1, 2)]
     if pde == "heat":  # inputs (x, y, z, t)
         ka = coef[0]
         Xd = X.detach()

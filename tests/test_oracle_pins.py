@@ -343,3 +343,63 @@ def test_adam_zero_gradient_leaves_parameters():
     for t in range(1, 4):
         oracle.adam_step(th, np.zeros(11), m, v, t)
     assert np.array_equal(th, th0)
+
+
+# ---------------------------------------------------------------- mixed derivatives (Eq. 3, i != j)
+MIXED_CHANNELS = [(0, 0), (0, 1), (1, 1), (0, 2), (1, 2), ((0, 1), 2)]
+
+
+def test_mixed_derivative_one_layer_closed_form():
+    """u = sum_k v_k tanh(w_k . x + b_k): u_xy = sum_k v_k w_k0 w_k1 tanh''(z_k)
+    and u_xx, u_yy likewise, written out for this network."""
+    rng = np.random.default_rng(31)
+    W1, b1 = rng.normal(size=(7, 2)), rng.normal(size=7)
+    W2, b2 = rng.normal(size=(1, 7)), rng.normal(size=1)
+    x = rng.uniform(-1, 1, size=(9, 2))
+    res = oracle.evaluate([(W1, b1), (W2, b2)], x, MIXED_CHANNELS, want_residual=False, want_grad=False)
+    z = x @ W1.T + b1
+    s = np.tanh(z)
+    d2 = -2.0 * s * (1.0 - s * s)
+    want = {5: (d2 * W1[:, 0] * W1[:, 1]) @ W2[0], 3: (d2 * W1[:, 0] ** 2) @ W2[0], 4: (d2 * W1[:, 1] ** 2) @ W2[0]}
+    for c, v in want.items():
+        assert np.allclose(res.jets[0, c], v, rtol=0, atol=1e-13), c
+
+
+def test_mixed_derivative_against_nested_autograd():
+    """Jets, the anisotropic residual u_xx + 2c u_xy + u_yy, its loss and the
+    parameter gradient of a 2-16x3-1 tanh network against nested
+    torch.autograd in FP64."""
+    rng = np.random.default_rng(32)
+    dims = [2, 16, 16, 16, 1]
+    params = [(rng.normal(size=(dims[l + 1], dims[l])) / np.sqrt(dims[l]), rng.normal(size=dims[l + 1]) * 0.3)
+              for l in range(len(dims) - 1)]
+    x = rng.uniform(0, 1, size=(40, 2))
+    coef = (0.7,)
+    res = oracle.evaluate(params, x, MIXED_CHANNELS, "aniso", coef)
+    J, R, Lval, G = autograd_ref.evaluate(params, x, MIXED_CHANNELS, "aniso", coef)
+    assert np.allclose(res.jets, J, rtol=0, atol=1e-12)
+    assert np.allclose(res.r, R, rtol=0, atol=1e-12)
+    assert abs(res.loss - Lval) <= 1e-12 * abs(Lval)
+    assert np.allclose(res.grad, G, rtol=0, atol=1e-11 * max(1.0, np.abs(G).max()))
+
+
+def test_mixed_derivative_gradient_complex_step():
+    """<g, delta> of the anisotropic loss equals its complex-step directional
+    derivative (the adjoint of the mixed channel against the forward one)."""
+    rng = np.random.default_rng(33)
+    dims = [2, 12, 12, 1]
+    params = [(rng.normal(size=(dims[l + 1], dims[l])) / np.sqrt(dims[l]), rng.normal(size=dims[l + 1]) * 0.3)
+              for l in range(len(dims) - 1)]
+    x = rng.uniform(0, 1, size=(30, 2))
+    res = oracle.evaluate(params, x, MIXED_CHANNELS, "aniso", (0.4,))
+    delta = rng.normal(size=res.grad.size)
+    _, _, dL = oracle.complex_step(params, delta, x, MIXED_CHANNELS, "aniso", (0.4,))
+    assert abs(float(dL) - float(res.grad @ delta)) <= 1e-11 * max(1.0, abs(float(dL)))
+
+
+def test_mixed_channel_needs_its_first_order_channels():
+    rng = np.random.default_rng(34)
+    params = [(rng.normal(size=(4, 2)), np.zeros(4)), (rng.normal(size=(1, 4)), np.zeros(1))]
+    with pytest.raises(ValueError):
+        oracle.evaluate(params, np.zeros((2, 2)), [(0, 0), (0, 1), ((0, 1), 2)], want_residual=False,
+                        want_grad=False)
