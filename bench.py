@@ -326,7 +326,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="ns", choices=["burgers", "ns", "ks", "heat"])
+    ap.add_argument("--workload", default="ns", choices=["burgers", "ns", "ks", "heat", "aniso"])
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-context", action="store_true", help="skip the FP32, nested-autograd and ensemble context runs")

@@ -69,8 +69,12 @@ enum {
  *                    channels: u, u_t, u_x, u_xx, u_xxx, u_xxxx
  *   PINN_HEAT_3D     inputs (x, y, z, t), output u, coef = {kappa}
  *                    r = u_t - kappa (u_xx + u_yy + u_zz) - sin(pi x) sin(pi y) sin(pi z) e^-t
- *                    channels: u, u_t, u_x, u_y, u_z, u_xx, u_yy, u_zz          */
-enum { PINN_BURGERS_1D = 1, PINN_NS2D_STEADY = 2, PINN_KS_1D = 3, PINN_HEAT_3D = 4 };
+ *                    channels: u, u_t, u_x, u_y, u_z, u_xx, u_yy, u_zz
+ *   PINN_ANISO_2D    inputs (x, y), output u, coef = {c}; a test operator with a
+ *                    mixed derivative (Eq. 3 with i != j), not one of the paper's
+ *                    problems: r = u_xx + 2 c u_xy + u_yy
+ *                    channels: u, u_x, u_y, u_xx, u_yy, u_xy                       */
+enum { PINN_BURGERS_1D = 1, PINN_NS2D_STEADY = 2, PINN_KS_1D = 3, PINN_HEAT_3D = 4, PINN_ANISO_2D = 5 };
 
 /* Operand type of the hidden-layer GEMMs.  Accumulation, the activation jet,
  * its adjoint, the residual and the loss are always FP32. */

@@ -14,6 +14,8 @@ namespace pj {
 
 // Burgers, inputs (x, t): u, u_t, u_x, u_xx
 struct ChBurgers {
+  static constexpr int NMIX = 0;  // no mixed channels
+  __host__ __device__ static constexpr int mix(int, int) { return 0; }
   static constexpr int C = 4, NDIR = 2, MAXK = 2, DIN = 2;
   __host__ __device__ static constexpr int K(int d) { return d == 0 ? 2 : 1; }
   __host__ __device__ static constexpr int at(int d, int k) {
@@ -24,6 +26,8 @@ struct ChBurgers {
 
 // Navier-Stokes, inputs (x, y): value, d/dx, d/dy, d2/dx2, d2/dy2
 struct ChNS {
+  static constexpr int NMIX = 0;  // no mixed channels
+  __host__ __device__ static constexpr int mix(int, int) { return 0; }
   static constexpr int C = 5, NDIR = 2, MAXK = 2, DIN = 2;
   __host__ __device__ static constexpr int K(int) { return 2; }
   __host__ __device__ static constexpr int at(int d, int k) {
@@ -34,6 +38,8 @@ struct ChNS {
 
 // Kuramoto-Sivashinsky, inputs (x, t): u, u_t, u_x, u_xx, u_xxx, u_xxxx
 struct ChKS {
+  static constexpr int NMIX = 0;  // no mixed channels
+  __host__ __device__ static constexpr int mix(int, int) { return 0; }
   static constexpr int C = 6, NDIR = 2, MAXK = 4, DIN = 2;
   __host__ __device__ static constexpr int K(int d) { return d == 0 ? 4 : 1; }
   __host__ __device__ static constexpr int at(int d, int k) {
@@ -44,12 +50,28 @@ struct ChKS {
 
 // Heat, inputs (x, y, z, t): u, u_t, u_x, u_y, u_z, u_xx, u_yy, u_zz
 struct ChHeat {
+  static constexpr int NMIX = 0;  // no mixed channels
+  __host__ __device__ static constexpr int mix(int, int) { return 0; }
   static constexpr int C = 8, NDIR = 4, MAXK = 2, DIN = 4;
   __host__ __device__ static constexpr int K(int d) { return d == 3 ? 1 : 2; }
   __host__ __device__ static constexpr int at(int d, int k) {
     return k == 0 ? 0 : (d == 3 ? 1 : (k == 1 ? 2 + d : 5 + d));
   }
   __host__ __device__ static constexpr int in(int d) { return d; }
+};
+
+// Anisotropic test operator, inputs (x, y): u, u_x, u_y, u_xx, u_yy, u_xy.
+// The last channel is a mixed second derivative (Eq. 3 with i != j): mix(m, 0)
+// is its channel, mix(m, 1) and mix(m, 2) the first-order channels it pairs.
+struct ChAniso {
+  static constexpr int C = 6, NDIR = 2, MAXK = 2, DIN = 2;
+  static constexpr int NMIX = 1;
+  __host__ __device__ static constexpr int K(int) { return 2; }
+  __host__ __device__ static constexpr int at(int d, int k) {
+    return k == 0 ? 0 : (k == 1 ? 1 + d : 3 + d);
+  }
+  __host__ __device__ static constexpr int in(int d) { return d; }
+  __host__ __device__ static constexpr int mix(int, int q) { return q == 0 ? 5 : (q == 1 ? 1 : 2); }
 };
 
 // tanh and its derivatives as polynomials in s = tanh(z), from ds/dz = 1 - s^2.
@@ -122,6 +144,10 @@ __device__ __forceinline__ void jet_forward(const float (&z)[CH::C], float (&a)[
       }
     }
   }
+  // mixed second derivatives: a_ij = s'' z_i z_j + s' z_ij
+#pragma unroll
+  for (int m = 0; m < CH::NMIX; ++m)
+    a[CH::mix(m, 0)] = t.s2 * z[CH::mix(m, 1)] * z[CH::mix(m, 2)] + t.s1 * z[CH::mix(m, 0)];
 }
 
 // Adjoint of jet_forward.  Inputs: the cotangent ab of the activation jet,
@@ -170,6 +196,16 @@ __device__ __forceinline__ void jet_adjoint(const float (&ab)[CH::C], float s, f
       zb[c2] = g2;
     }
     zb[c1] = g1;
+  }
+  // adjoint of a_ij = s''(z_0) z_i z_j + s'(z_0) z_ij
+#pragma unroll
+  for (int m = 0; m < CH::NMIX; ++m) {
+    const int cm = CH::mix(m, 0), ci = CH::mix(m, 1), cj = CH::mix(m, 2);
+    const float abm = ab[cm];
+    zb0 += (t.s3 * zs[ci] * zs[cj] + t.s2 * zs[cm]) * abm;
+    zb[ci] += t.s2 * zs[cj] * abm;
+    zb[cj] += t.s2 * zs[ci] * abm;
+    zb[cm] = t.s1 * abm;
   }
   zb[0] = zb0;
 }
@@ -268,6 +304,24 @@ struct PdeHeat {
     ub[0][5] = -k.c[0] * rb[0];
     ub[0][6] = -k.c[0] * rb[0];
     ub[0][7] = -k.c[0] * rb[0];
+  }
+};
+
+// Anisotropic test operator with a mixed derivative (not one of the paper's
+// problems): r = u_xx + 2 c u_xy + u_yy.
+struct PdeAniso {
+  using CH = ChAniso;
+  static constexpr int DOUT = 1, NRES = 1;
+  __device__ static void residual(const float (&u)[1][6], const float *, const Coef &k, float (&r)[1]) {
+    r[0] = u[0][3] + 2.f * k.c[0] * u[0][5] + u[0][4];
+  }
+  __device__ static void adjoint(const float (&)[1][6], const float (&rb)[1], const Coef &k, float (&ub)[1][6]) {
+    ub[0][0] = 0.f;
+    ub[0][1] = 0.f;
+    ub[0][2] = 0.f;
+    ub[0][3] = rb[0];
+    ub[0][4] = rb[0];
+    ub[0][5] = 2.f * k.c[0] * rb[0];
   }
 };
 

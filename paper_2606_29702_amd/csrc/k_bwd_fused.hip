@@ -561,6 +561,7 @@ hipError_t launch_bwd_dw(int kind, int prec, const LayerBwd &L, float *part, int
     case K_NS: return by_prec(PdeNS{});
     case K_KS: return by_prec(PdeKS{});
     case K_HEAT: return by_prec(PdeHeat{});
+    case K_ANISO: return by_prec(PdeAniso{});
     default: return hipErrorInvalidValue;
   }
 }

@@ -504,6 +504,7 @@ hipError_t by_kind(int kind, F &&f) {
     case K_NS: return f(PdeNS{});
     case K_KS: return f(PdeKS{});
     case K_HEAT: return f(PdeHeat{});
+    case K_ANISO: return f(PdeAniso{});
     default: return hipErrorInvalidValue;
   }
 }

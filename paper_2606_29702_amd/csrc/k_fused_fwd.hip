@@ -353,6 +353,7 @@ hipError_t launch_fwd_fused(int kind, int prec, const FusedFwdArgs &a, int P, hi
     case K_NS: return by_prec(PdeNS{});
     case K_KS: return by_prec(PdeKS{});
     case K_HEAT: return by_prec(PdeHeat{});
+    case K_ANISO: return by_prec(PdeAniso{});
     default: return hipErrorInvalidValue;
   }
 }

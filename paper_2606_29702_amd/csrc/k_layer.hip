@@ -794,6 +794,7 @@ hipError_t dispatch(int kind, int prec, F &&f) {
     case K_NS: return by_prec(PdeNS{});
     case K_KS: return by_prec(PdeKS{});
     case K_HEAT: return by_prec(PdeHeat{});
+    case K_ANISO: return by_prec(PdeAniso{});
     default: return hipErrorInvalidValue;
   }
 }

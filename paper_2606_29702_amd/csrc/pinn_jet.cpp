@@ -40,6 +40,7 @@ bool kind_info(int kind, KindInfo *ki) {
     case PINN_NS2D_STEADY: *ki = {2, 3, 5, 3}; return true;
     case PINN_KS_1D: *ki = {2, 1, 6, 1}; return true;
     case PINN_HEAT_3D: *ki = {4, 1, 8, 1}; return true;
+    case PINN_ANISO_2D: *ki = {2, 1, 6, 1}; return true;
     default: return false;
   }
 }

@@ -36,9 +36,11 @@ CHANNELS = {
     "ks": [(0, 0), (1, 1), (0, 1), (0, 2), (0, 3), (0, 4)],
     # inputs (x, y, z, t): u, u_t, u_x, u_y, u_z, u_xx, u_yy, u_zz
     "heat": [(0, 0), (3, 1), (0, 1), (1, 1), (2, 1), (0, 2), (1, 2), (2, 2)],
+    # inputs (x, y): u, u_x, u_y, u_xx, u_yy, u_xy (a mixed second derivative)
+    "aniso": [(0, 0), (0, 1), (1, 1), (0, 2), (1, 2), ((0, 1), 2)],
 }
 
-N_RES = {"burgers": 1, "ns": 3, "ks": 1, "heat": 1}
+N_RES = {"burgers": 1, "ns": 3, "ks": 1, "heat": 1, "aniso": 1}
 
 
 @dataclass
@@ -75,6 +77,10 @@ WORKLOADS = {
                    "Kuramoto-Sivashinsky u_t + u u_x + u_xx + u_xxxx, 2-256x8-1 tanh"),
     "heat": Workload("heat", "heat", _mlp(4, 512, 8, 1), (0.1,), [(0.0, 1.0)] * 4, 262144,
                      "3-D heat u_t - 0.1 Lap u - f, 4-512x8-1 tanh"),
+    # a test operator with a mixed derivative (Eq. 3 with i != j); not one of
+    # the paper's problems, shaped like the NS network
+    "aniso": Workload("aniso", "aniso", _mlp(2, 128, 6, 1), (0.5,), [(0.0, 1.0), (0.0, 1.0)], 65536,
+                      "anisotropic operator u_xx + 2c u_xy + u_yy, c = 0.5, 2-128x6-1 tanh"),
 }
 
 

@@ -28,6 +28,7 @@ SMALL = {
     "ns": dict(dims=[2, 64, 64, 64, 3], N=257),
     "ks": dict(dims=[2, 64, 64, 64, 1], N=200),
     "heat": dict(dims=[4, 64, 64, 1], N=130),
+    "aniso": dict(dims=[2, 64, 64, 64, 1], N=257),
 }
 
 
@@ -84,7 +85,7 @@ def run_gpu(lib, prob, prec, verify=True, max_points=None):
     return res
 
 
-CASES = [("burgers", False), ("ns", False), ("ks", False), ("ks", True), ("heat", False)]
+CASES = [("burgers", False), ("ns", False), ("ks", False), ("ks", True), ("heat", False), ("aniso", False)]
 
 
 @pytest.mark.parametrize("pde,unsat", CASES)
@@ -332,7 +333,7 @@ def test_fused_and_separate_weight_gradients_agree(lib, pde, dims, prec):
 
 
 @pytest.mark.parametrize("pde,dims", [("ns", [2, 128, 128, 128, 128, 3]), ("burgers", [2, 32, 32, 32, 32, 1]),
-                                      ("heat", [4, 64, 64, 64, 1])])
+                                      ("heat", [4, 64, 64, 64, 1]), ("aniso", [2, 128, 128, 128, 1])])
 def test_fused_backward_many_tiles(lib, pde, dims):
     """BF16 fused backward with several 16-point tiles per persistent
     workgroup (the next tile streams in while the current one is processed):
