@@ -1,0 +1,39 @@
+"""The channel closure (host side) reproduces every PDE kind's channel set
+from the derivatives its residual uses, and is minimal."""
+import pytest
+
+import pinn_inputs as pi
+from paper_2606_29702_amd.closure import channels, closure, kind_for
+
+# derivatives each residual uses, as tuples of input directions
+USES = {
+    "burgers": [(), (1,), (0,), (0, 0)],                     # u_t + u u_x - nu u_xx, inputs (x, t)
+    "ns": [(), (0,), (1,), (0, 0), (1, 1)],                  # Eq. 16, inputs (x, y)
+    "ks": [(), (1,), (0,), (0, 0), (0, 0, 0, 0)],            # u_t + u u_x + u_xx + u_xxxx
+    "heat": [(3,), (0, 0), (1, 1), (2, 2)],                  # u_t - kappa Lap u - f, inputs (x, y, z, t)
+    "aniso": [(0, 0), (0, 1), (1, 1)],                       # u_xx + 2c u_xy + u_yy
+}
+
+
+@pytest.mark.parametrize("kind", sorted(USES))
+def test_closure_reproduces_the_channel_sets(kind):
+    chans = channels(USES[kind])
+    assert set(chans) == set(pi.CHANNELS[kind])
+    assert len(chans) == len(pi.CHANNELS[kind])
+    assert kind_for(chans, pi.CHANNELS) == kind
+
+
+def test_closure_is_minimal():
+    # dropping any non-value derivative either loses a required one or leaves
+    # a set the recursion cannot close
+    required = [(0, 0, 0, 0), (0, 1)]
+    full = closure(required)
+    assert full == [(), (0,), (1,), (0, 0), (0, 0, 0), (0, 0, 0, 0), (0, 1)]
+    for drop in full[1:]:
+        rest = [d for d in full if d != drop]
+        assert not set(required) <= set(rest) or closure(rest) != rest
+
+
+def test_unsupported_mixed_order_is_rejected():
+    with pytest.raises(ValueError):
+        closure([(0, 0, 1)])
