@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liborc.so")
 
 ACT = {"tanh": 0, "identity": 1, "square": 2, "cube": 3, "sin": 4}
-PDE = {"none": 0, "burgers": 1, "ns": 2, "ks": 3, "heat": 4, "aniso": 5}
+PDE = {"none": 0, "burgers": 1, "ns": 2, "ks": 3, "heat": 4, "aniso": 5, "burgers_bc": 6}
 MIXED2 = -2  # channel order code of a mixed second derivative
 
 _lib = None

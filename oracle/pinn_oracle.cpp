@@ -280,6 +280,9 @@ int pde_channels(int kind, int d_in, int d_out, const ChannelSet &cs, PdeChannel
       if (d_in != 4 || d_out != 1) return -1;
       pc->uxx = need(0, 2); pc->uyy = need(1, 2); pc->uzz = need(2, 2); pc->ut = need(3, 1);
       return (pc->uxx < 0 || pc->uyy < 0 || pc->uzz < 0 || pc->ut < 0) ? -2 : 0;
+    case ORC_PDE_BURGERS_BC:
+      if (d_in != 2 || d_out != 1) return -1;
+      return 0;
     case ORC_PDE_ANISO:
       if (d_in != 2 || d_out != 1) return -1;
       pc->uxx = need(0, 2); pc->uyy = need(1, 2);
@@ -328,6 +331,11 @@ void residual_point(int kind, const double *coef, const PdeChannels &pc, const d
     case ORC_PDE_ANISO: {
       const double c = coef[0];
       r[0] = U(0, pc.uxx) + 2.0 * c * U(0, pc.uxy) + U(0, pc.uyy);
+      break;
+    }
+    case ORC_PDE_BURGERS_BC: {
+      const double pi = 3.14159265358979323846;
+      r[0] = U(0, 0) + std::sin(pi * xp[0]);
       break;
     }
     default: break;
@@ -393,6 +401,9 @@ void residual_adjoint_point(int kind, const double *coef, const PdeChannels &pc,
       UB(0, pc.uzz) += -ka * rbar[0];
       break;
     }
+    case ORC_PDE_BURGERS_BC:
+      UB(0, 0) += rbar[0];
+      break;
     case ORC_PDE_ANISO: {
       const double c = coef[0];
       UB(0, pc.uxx) += rbar[0];
@@ -500,6 +511,7 @@ extern "C" int orc_n_res(int pde_kind) {
     case ORC_PDE_KS: return 1;
     case ORC_PDE_HEAT: return 1;
     case ORC_PDE_ANISO: return 1;
+    case ORC_PDE_BURGERS_BC: return 1;
     default: return 0;
   }
 }

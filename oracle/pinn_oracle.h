@@ -44,8 +44,11 @@ enum {
   ORC_PDE_KS = 3,      /* coef = {alpha, beta, gamma}; r = u_t + a u u_x + b u_xx + g u_xxxx */
   ORC_PDE_HEAT = 4,    /* coef = {kappa}; inputs (x, y, z, t);
                           r = u_t - kappa (u_xx + u_yy + u_zz) - sin(pi x) sin(pi y) sin(pi z) e^-t */
-  ORC_PDE_ANISO = 5    /* coef = {c}; inputs (x, y); r = u_xx + 2 c u_xy + u_yy: a test
+  ORC_PDE_ANISO = 5,   /* coef = {c}; inputs (x, y); r = u_xx + 2 c u_xy + u_yy: a test
                           operator with a mixed derivative (not one of the paper's problems) */
+  ORC_PDE_BURGERS_BC = 6 /* inputs (x, t); r = u + sin(pi x): the Burgers initial condition
+                            u(x, 0) = -sin(pi x) and boundary values u(+-1, t) = 0 at points on
+                            those segments; value channel only */
 };
 
 /* Channel order code for a mixed second derivative d^2/dx_i dx_j (i < j, Eq. 3

@@ -66,6 +66,8 @@ def residuals(pde, jets, channels, X, coef):
     if pde == "ks":  # inputs (x, t)
         a, b, g = coef
         return [J(0, 1, 1) + a * J(0, 0, 0) * J(0, 0, 1) + b * J(0, 0, 2) + g * J(0, 0, 4)]
+    if pde == "burgers_bc":  # inputs (x, t): u + sin(pi x) on the initial and boundary segments
+        return [J(0, 0, 0) + torch.sin(math.pi * X.detach()[:, 0])]
     if pde == "aniso":  # inputs (x, y): u_xx + 2 c u_xy + u_yy
         c = coef[0]
         return [J(0, 0, 2) + 2.0 * c * jets[(0, idx[((0, 1), 2)])] + J(0, 1, 2)]

@@ -403,3 +403,41 @@ def test_mixed_channel_needs_its_first_order_channels():
     with pytest.raises(ValueError):
         oracle.evaluate(params, np.zeros((2, 2)), [(0, 0), (0, 1), ((0, 1), 2)], want_residual=False,
                         want_grad=False)
+
+
+# ---------------------------------------------------------------- initial / boundary data (Burgers)
+def _bc_points(rng, n):
+    """Points on the Burgers initial segment t = 0 and the walls x = +-1."""
+    k = n // 2
+    ic = np.stack([rng.uniform(-1, 1, k), np.zeros(k)], 1)
+    wall = np.stack([rng.choice([-1.0, 1.0], n - k), rng.uniform(0, 1, n - k)], 1)
+    return np.concatenate([ic, wall])
+
+
+def test_burgers_bc_residual_is_the_data_misfit():
+    """r = u - g with g = -sin(pi x) on t = 0 and g = 0 on x = +-1, where u is a
+    plain MLP evaluation (no jets)."""
+    rng = np.random.default_rng(41)
+    dims = [2, 16, 16, 1]
+    params = [(rng.normal(size=(dims[l + 1], dims[l])), rng.normal(size=dims[l + 1])) for l in range(3)]
+    x = _bc_points(rng, 40)
+    res = oracle.evaluate(params, x, [(0, 0)], "burgers_bc", ())
+    h = x
+    for l, (W, b) in enumerate(params):
+        h = h @ W.T + b
+        if l < 2:
+            h = np.tanh(h)
+    g = np.where(x[:, 1] == 0.0, -np.sin(np.pi * x[:, 0]), 0.0)
+    assert np.allclose(res.r[0], h[:, 0] - g, rtol=0, atol=1e-12)
+
+
+def test_burgers_bc_against_nested_autograd():
+    rng = np.random.default_rng(42)
+    dims = [2, 16, 16, 16, 1]
+    params = [(rng.normal(size=(dims[l + 1], dims[l])) / 2, rng.normal(size=dims[l + 1]) * 0.3) for l in range(4)]
+    x = _bc_points(rng, 50)
+    res = oracle.evaluate(params, x, [(0, 0)], "burgers_bc", ())
+    J, R, Lval, G = autograd_ref.evaluate(params, x, [(0, 0)], "burgers_bc", ())
+    assert np.allclose(res.r, R, rtol=0, atol=1e-13)
+    assert abs(res.loss - Lval) <= 1e-13 * abs(Lval)
+    assert np.allclose(res.grad, G, rtol=0, atol=1e-12 * max(1.0, np.abs(G).max()))
