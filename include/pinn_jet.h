@@ -73,8 +73,13 @@ enum {
  *   PINN_ANISO_2D    inputs (x, y), output u, coef = {c}; a test operator with a
  *                    mixed derivative (Eq. 3 with i != j), not one of the paper's
  *                    problems: r = u_xx + 2 c u_xy + u_yy
- *                    channels: u, u_x, u_y, u_xx, u_yy, u_xy                       */
-enum { PINN_BURGERS_1D = 1, PINN_NS2D_STEADY = 2, PINN_KS_1D = 3, PINN_HEAT_3D = 4, PINN_ANISO_2D = 5 };
+ *                    channels: u, u_x, u_y, u_xx, u_yy, u_xy
+ *   PINN_BURGERS_BC  inputs (x, t), output u, no coefficient: the Burgers initial
+ *                    and boundary data term at points on t = 0 and x = +-1,
+ *                    r = u + sin(pi x) (u(x, 0) = -sin(pi x), u(+-1, t) = 0)
+ *                    channels: u                                                   */
+enum { PINN_BURGERS_1D = 1, PINN_NS2D_STEADY = 2, PINN_KS_1D = 3, PINN_HEAT_3D = 4, PINN_ANISO_2D = 5,
+       PINN_BURGERS_BC = 6 };
 
 /* Operand type of the hidden-layer GEMMs.  Accumulation, the activation jet,
  * its adjoint, the residual and the loss are always FP32. */

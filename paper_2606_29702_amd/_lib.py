@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libpinnjet.so")
 PINN_OK = 0
 STATUS_NAMES = {0: "PINN_OK", -1: "PINN_ERR_ARG", -2: "PINN_ERR_UNSUPPORTED", -3: "PINN_ERR_NOMEM",
                 -4: "PINN_ERR_DEVICE", -5: "PINN_ERR_STATE", -6: "PINN_ERR_CAP"}
-KINDS = {"burgers": 1, "ns": 2, "ks": 3, "heat": 4, "aniso": 5}
+KINDS = {"burgers": 1, "ns": 2, "ks": 3, "heat": 4, "aniso": 5, "burgers_bc": 6}
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
 PINN_VERIFY_F64 = 1
 

@@ -60,6 +60,17 @@ struct ChHeat {
   __host__ __device__ static constexpr int in(int d) { return d; }
 };
 
+// Value only, inputs (x, t): the channel set of the initial and boundary
+// data terms, which need no derivative.
+struct ChValue2 {
+  static constexpr int NMIX = 0;
+  __host__ __device__ static constexpr int mix(int, int) { return 0; }
+  static constexpr int C = 1, NDIR = 0, MAXK = 0, DIN = 2;
+  __host__ __device__ static constexpr int K(int) { return 0; }
+  __host__ __device__ static constexpr int at(int, int) { return 0; }
+  __host__ __device__ static constexpr int in(int d) { return d; }
+};
+
 // Anisotropic test operator, inputs (x, y): u, u_x, u_y, u_xx, u_yy, u_xy.
 // The last channel is a mixed second derivative (Eq. 3 with i != j): mix(m, 0)
 // is its channel, mix(m, 1) and mix(m, 2) the first-order channels it pairs.
@@ -304,6 +315,20 @@ struct PdeHeat {
     ub[0][5] = -k.c[0] * rb[0];
     ub[0][6] = -k.c[0] * rb[0];
     ub[0][7] = -k.c[0] * rb[0];
+  }
+};
+
+// Burgers initial and boundary data: r = u - g with g = -sin(pi x), which is
+// the initial condition u(x, 0) = -sin(pi x) on t = 0 and vanishes on the
+// walls x = +-1 (the points lie on those segments).
+struct PdeBurgersBC {
+  using CH = ChValue2;
+  static constexpr int DOUT = 1, NRES = 1;
+  __device__ static void residual(const float (&u)[1][1], const float *x, const Coef &, float (&r)[1]) {
+    r[0] = u[0][0] + sinpif(x[0]);
+  }
+  __device__ static void adjoint(const float (&)[1][1], const float (&rb)[1], const Coef &, float (&ub)[1][1]) {
+    ub[0][0] = rb[0];
   }
 };
 

@@ -562,6 +562,7 @@ hipError_t launch_bwd_dw(int kind, int prec, const LayerBwd &L, float *part, int
     case K_KS: return by_prec(PdeKS{});
     case K_HEAT: return by_prec(PdeHeat{});
     case K_ANISO: return by_prec(PdeAniso{});
+    case K_BURGERS_BC: return by_prec(PdeBurgersBC{});
     default: return hipErrorInvalidValue;
   }
 }

@@ -505,6 +505,7 @@ hipError_t by_kind(int kind, F &&f) {
     case K_KS: return f(PdeKS{});
     case K_HEAT: return f(PdeHeat{});
     case K_ANISO: return f(PdeAniso{});
+    case K_BURGERS_BC: return f(PdeBurgersBC{});
     default: return hipErrorInvalidValue;
   }
 }

@@ -354,6 +354,7 @@ hipError_t launch_fwd_fused(int kind, int prec, const FusedFwdArgs &a, int P, hi
     case K_KS: return by_prec(PdeKS{});
     case K_HEAT: return by_prec(PdeHeat{});
     case K_ANISO: return by_prec(PdeAniso{});
+    case K_BURGERS_BC: return by_prec(PdeBurgersBC{});
     default: return hipErrorInvalidValue;
   }
 }

@@ -795,6 +795,7 @@ hipError_t dispatch(int kind, int prec, F &&f) {
     case K_KS: return by_prec(PdeKS{});
     case K_HEAT: return by_prec(PdeHeat{});
     case K_ANISO: return by_prec(PdeAniso{});
+    case K_BURGERS_BC: return by_prec(PdeBurgersBC{});
     default: return hipErrorInvalidValue;
   }
 }

@@ -17,7 +17,7 @@
 namespace pj {
 
 enum Prec { P_FP32 = 0, P_BF16 = 1, P_FP16 = 2 };
-enum Kind { K_BURGERS = 1, K_NS = 2, K_KS = 3, K_HEAT = 4, K_ANISO = 5 };
+enum Kind { K_BURGERS = 1, K_NS = 2, K_KS = 3, K_HEAT = 4, K_ANISO = 5, K_BURGERS_BC = 6 };
 
 constexpr int kPointTile = 128;  // N_pad granularity shared by all kernels
 

@@ -41,6 +41,7 @@ bool kind_info(int kind, KindInfo *ki) {
     case PINN_KS_1D: *ki = {2, 1, 6, 1}; return true;
     case PINN_HEAT_3D: *ki = {4, 1, 8, 1}; return true;
     case PINN_ANISO_2D: *ki = {2, 1, 6, 1}; return true;
+    case PINN_BURGERS_BC: *ki = {2, 1, 1, 1}; return true;
     default: return false;
   }
 }

@@ -18,7 +18,7 @@ CHANNELS = {k: lib.pinn_pde_channels(v) for k, v in KINDS.items()}
 RESIDUALS = {k: lib.pinn_pde_residuals(v) for k, v in KINDS.items()}
 
 DEFAULT_COEF = {"burgers": (0.01 / 3.141592653589793,), "ns": (100.0,), "ks": (1.0, 1.0, 1.0),
-                "heat": (0.1,), "aniso": (0.5,)}
+                "heat": (0.1,), "aniso": (0.5,), "burgers_bc": ()}
 
 
 def _stream() -> ctypes.c_void_p:

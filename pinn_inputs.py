@@ -38,9 +38,11 @@ CHANNELS = {
     "heat": [(0, 0), (3, 1), (0, 1), (1, 1), (2, 1), (0, 2), (1, 2), (2, 2)],
     # inputs (x, y): u, u_x, u_y, u_xx, u_yy, u_xy (a mixed second derivative)
     "aniso": [(0, 0), (0, 1), (1, 1), (0, 2), (1, 2), ((0, 1), 2)],
+    # inputs (x, t): u only (initial and boundary data of Burgers)
+    "burgers_bc": [(0, 0)],
 }
 
-N_RES = {"burgers": 1, "ns": 3, "ks": 1, "heat": 1, "aniso": 1}
+N_RES = {"burgers": 1, "ns": 3, "ks": 1, "heat": 1, "aniso": 1, "burgers_bc": 1}
 
 
 @dataclass
@@ -81,7 +83,20 @@ WORKLOADS = {
     # the paper's problems, shaped like the NS network
     "aniso": Workload("aniso", "aniso", _mlp(2, 128, 6, 1), (0.5,), [(0.0, 1.0), (0.0, 1.0)], 65536,
                       "anisotropic operator u_xx + 2c u_xy + u_yy, c = 0.5, 2-128x6-1 tanh"),
+    # the data term of the Burgers problem: points on the initial segment
+    # t = 0 (half) and on the walls x = +-1 (half); the network of "burgers"
+    "burgers_bc": Workload("burgers_bc", "burgers_bc", _mlp(2, 32, 3, 1), (), [(-1.0, 1.0), (0.0, 1.0)], 256,
+                           "Burgers initial/boundary data u + sin(pi x) = 0 on t = 0 and x = +-1"),
 }
+
+
+def boundary_points(N: int, rng: np.random.Generator):
+    """Burgers initial/boundary points: half on t = 0 with x uniform on [-1, 1],
+    half on the walls x = -1, +1 (alternating) with t uniform on [0, 1]."""
+    k = N // 2
+    ic = np.stack([rng.uniform(-1.0, 1.0, k), np.zeros(k)], 1)
+    wall = np.stack([np.where(np.arange(N - k) % 2 == 0, -1.0, 1.0), rng.uniform(0.0, 1.0, N - k)], 1)
+    return np.concatenate([ic, wall]).astype(np.float32)
 
 
 def xavier_params(dims: Sequence[int], rng: np.random.Generator, bias_std: float = 0.0):
@@ -124,7 +139,7 @@ def make_problem(name: str, N: Optional[int] = None, seed: int = 0, bias_std: fl
                       wl.domain, int(N) if N is not None else wl.N, wl.note)
     rng = np.random.Generator(np.random.PCG64(seed))
     params = xavier_params(wl.dims, rng, bias_std)
-    x = uniform_points(wl.N, wl.domain, rng)
+    x = boundary_points(wl.N, rng) if wl.pde == "burgers_bc" else uniform_points(wl.N, wl.domain, rng)
     return Problem(wl, params, x, wl.coef, CHANNELS[wl.pde])
 
 

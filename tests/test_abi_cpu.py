@@ -95,8 +95,8 @@ def test_null_weight_pointer():
 
 
 def test_channel_and_residual_counts():
-    assert [lib.pinn_pde_channels(k) for k in (1, 2, 3, 4, 5)] == [4, 5, 6, 8, 6]
-    assert [lib.pinn_pde_residuals(k) for k in (1, 2, 3, 4, 5)] == [1, 3, 1, 1, 1]
+    assert [lib.pinn_pde_channels(k) for k in (1, 2, 3, 4, 5, 6)] == [4, 5, 6, 8, 6, 1]
+    assert [lib.pinn_pde_residuals(k) for k in (1, 2, 3, 4, 5, 6)] == [1, 3, 1, 1, 1, 1]
     assert lib.pinn_pde_channels(0) == 0
 
 

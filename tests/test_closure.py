@@ -12,6 +12,7 @@ USES = {
     "ks": [(), (1,), (0,), (0, 0), (0, 0, 0, 0)],            # u_t + u u_x + u_xx + u_xxxx
     "heat": [(3,), (0, 0), (1, 1), (2, 2)],                  # u_t - kappa Lap u - f, inputs (x, y, z, t)
     "aniso": [(0, 0), (0, 1), (1, 1)],                       # u_xx + 2c u_xy + u_yy
+    "burgers_bc": [()],                                      # u + sin(pi x)
 }
 
 

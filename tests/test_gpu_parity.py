@@ -22,6 +22,9 @@ FP32_TOL = 1e-5
 # measured-error ceilings of the 16-bit operand paths (relative L2)
 LOWP_TOL = {"bf16": {"r": 2e-2, "grad": 5e-2, "jets": 2e-2},
             "fp16": {"r": 5e-3, "grad": 1e-2, "jets": 5e-3}}
+# the data term carries the value channel alone, a sum over the last layer
+# that cancels more than the derivative channels do (BF16 jets measured 2.7e-2)
+LOWP_JETS_KIND = {("burgers_bc", "bf16"): 5e-2, ("burgers_bc", "fp16"): 1e-2}
 
 SMALL = {
     "burgers": dict(dims=[2, 32, 32, 32, 1], N=300),
@@ -29,6 +32,7 @@ SMALL = {
     "ks": dict(dims=[2, 64, 64, 64, 1], N=200),
     "heat": dict(dims=[4, 64, 64, 1], N=130),
     "aniso": dict(dims=[2, 64, 64, 64, 1], N=257),
+    "burgers_bc": dict(dims=[2, 32, 32, 32, 1], N=256),
 }
 
 
@@ -85,7 +89,8 @@ def run_gpu(lib, prob, prec, verify=True, max_points=None):
     return res
 
 
-CASES = [("burgers", False), ("ns", False), ("ks", False), ("ks", True), ("heat", False), ("aniso", False)]
+CASES = [("burgers", False), ("ns", False), ("ks", False), ("ks", True), ("heat", False), ("aniso", False),
+         ("burgers_bc", False)]
 
 
 @pytest.mark.parametrize("pde,unsat", CASES)
@@ -112,7 +117,8 @@ def test_lowprec_parity(lib, pde, unsat, prec):
     cos = float(g["grad"] @ ref.grad / (np.linalg.norm(g["grad"]) * np.linalg.norm(ref.grad)))
     print(pde, prec, "unsat" if unsat else "", {k: f"{v:.2e}" for k, v in errs.items()}, f"cos {cos:.6f}")
     for k, v in errs.items():
-        assert v <= LOWP_TOL[prec][k], (k, v)
+        tol = LOWP_JETS_KIND.get((pde, prec), LOWP_TOL[prec][k]) if k == "jets" else LOWP_TOL[prec][k]
+        assert v <= tol, (k, v)
     assert cos > 0.99
 
 
@@ -382,3 +388,38 @@ def test_fused_backward_checkpointed_bitwise(lib, pde, dims):
         plan.close()
     assert np.array_equal(outs[0][0], outs[1][0])
     assert np.array_equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_weighted_residual_and_data_loss(lib, prec):
+    """The Burgers training loss with its initial/boundary term,
+    L = L_pde + w L_data, from two plans on one network (interior points and
+    points on t = 0, x = +-1): the data plan's backward with the cotangent
+    w 2 r / N_data gives w dL_data/dtheta; the sum matches the oracle."""
+    dims = [2, 32, 32, 32, 1]
+    pde = pi.make_problem("burgers", N=600, seed=51, bias_std=0.3, dims=dims)
+    bc = pi.make_problem("burgers_bc", N=200, seed=52, dims=dims)
+    params_np = pde.params
+    params = dev_params(params_np)
+    w_data = 10.0
+    plan_r = lib.PinnPlan(dims, "burgers", 600, precision=prec, coef=pde.coef)
+    plan_d = lib.PinnPlan(dims, "burgers_bc", 200, precision=prec)
+    xr = torch.tensor(pde.x, device="cuda")
+    xd = torch.tensor(bc.x, device="cuda")
+    _, loss_r, _, _ = plan_r.residual(params, xr)
+    g_r = flat(plan_r.backward(params, xr))
+    r_d, loss_d, _, _ = plan_d.residual(params, xd)
+    g_d = flat(plan_d.backward(params, xd, r_bar=(w_data * 2.0 / 200) * r_d))
+    torch.cuda.synchronize()
+    ref_r = oracle.evaluate(params_np, pde.x, pde.channels, "burgers", pde.coef)
+    ref_d = oracle.evaluate(params_np, bc.x, bc.channels, "burgers_bc", ())
+    want = ref_r.grad + w_data * ref_d.grad
+    got = g_r + g_d
+    loss = float(loss_r) + w_data * float(loss_d)
+    want_loss = ref_r.loss + w_data * ref_d.loss
+    tol = FP32_TOL if prec == "fp32" else LOWP_TOL[prec]["grad"]
+    print(prec, f"grad rel {rel(got, want):.2e} loss rel {abs(loss - want_loss) / want_loss:.2e}")
+    assert rel(got, want) <= tol
+    assert abs(loss - want_loss) <= (FP32_TOL if prec == "fp32" else 2e-2) * want_loss
+    plan_r.close()
+    plan_d.close()
