@@ -1,0 +1,82 @@
+"""The 64-network Burgers ensemble at its real sizes (widths 32-256, depths
+3-8, N from 2048 to 65536 per network, seed 0), in BF16 and FP32:
+
+  * every member's residual at 256 sampled points of its full point set, and
+    its gradient on its first 2048 points, against the oracle;
+  * the batched step (side streams, graph replay) at full size equals the
+    members' single-plan steps bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import pinn_inputs as pi
+from tests.parity import cosine, flat, rel
+
+pytestmark = pytest.mark.gpu
+
+BAR = {"fp32": {"r": 1e-5, "grad": 1e-5}, "bf16": {"r": 2e-2, "grad": 5e-2}}
+CH = pi.CHANNELS["burgers"]
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_29702_amd as pj
+    return pj
+
+
+@pytest.fixture(scope="module")
+def ens():
+    members = pi.make_ensemble(seed=0)
+    params = [[(torch.tensor(W, device="cuda"), torch.tensor(b, device="cuda")) for W, b in m.params]
+              for m in members]
+    xs = [torch.tensor(m.x, device="cuda") for m in members]
+    return members, params, xs
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_every_member_against_the_oracle(lib, ens, prec):
+    members, params, xs = ens
+    rng = np.random.default_rng(91)
+    worst = {"r": 0.0, "grad": 0.0}
+    for i, (m, p, x) in enumerate(zip(members, params, xs)):
+        plan = lib.PinnPlan(m.dims, "burgers", m.N, precision=prec, coef=(m.nu,))
+        r, _, _, _ = plan.residual(p, x)
+        torch.cuda.synchronize()
+        idx = np.sort(rng.choice(m.N, 256, replace=False))
+        ref = oracle.evaluate(m.params, m.x[idx], CH, "burgers", (m.nu,), want_jets=False, want_grad=False)
+        er = rel(r.cpu().numpy()[:, idx], ref.r)
+        n = min(m.N, 2048)
+        plan.residual(p, x[:n].contiguous())
+        g = flat(plan.backward(p, x[:n].contiguous()))
+        refg = oracle.evaluate(m.params, m.x[:n], CH, "burgers", (m.nu,), want_jets=False)
+        eg = rel(g, refg.grad)
+        print(prec, f"member {i:2d} w={m.width:3d} H={m.hidden} N={m.N:5d} nu={m.nu:.2e}: "
+              f"r {er:.2e} grad {eg:.2e} cos {cosine(g, refg.grad):.6f}")
+        worst["r"] = max(worst["r"], er)
+        worst["grad"] = max(worst["grad"], eg)
+        plan.close()
+    print(prec, "worst", worst)
+    assert worst["r"] <= BAR[prec]["r"] and worst["grad"] <= BAR[prec]["grad"], worst
+
+
+def test_full_size_batch_equals_single_plans(lib, ens):
+    members, params, xs = ens
+    batch = lib.PinnBatch([m.dims for m in members], "burgers", [(m.nu,) for m in members],
+                          [m.N for m in members], precision="bf16")
+    for _ in range(2):  # capture, then a replay
+        loss, grads = batch.step(params, xs)
+    torch.cuda.synchronize()
+    for i in (0, 1, 17, 40, 63):
+        m = members[i]
+        plan = lib.PinnPlan(m.dims, "burgers", m.N, precision="bf16", coef=(m.nu,))
+        _, l1, _, _ = plan.residual(params[i], xs[i])
+        g1 = plan.backward(params[i], xs[i])
+        torch.cuda.synchronize()
+        assert float(loss[i]) == float(l1), i
+        assert np.array_equal(flat(grads[i]), flat(g1)), i
+        plan.close()
+    batch.close()

@@ -22,6 +22,7 @@ pytestmark = pytest.mark.gpu
 
 FP32_TOL = 1e-5
 BF16 = {"r": 2e-2, "grad": 5e-2}
+FP16 = {"r": 5e-3, "grad": 1e-2}
 
 
 @pytest.fixture(scope="module")
@@ -111,3 +112,23 @@ def test_heat_full_under_cap(lib):
     refg = oracle.evaluate(prob.params, prob.x[:n], prob.channels, "heat", prob.coef)
     print("heat", rel(r[:, idx], ref.r), rel(g, refg.grad))
     assert rel(g, refg.grad) <= BF16["grad"]
+
+
+def test_heat_fp32_full_width(lib):
+    """The plain FP32 path at w = 512 (heat network 4-512x8-1), store-all, on
+    the workload's first 2048 points: every residual and the gradient."""
+    prob = pi.make_problem("heat")
+    n = 2048
+    r, loss, g, _ = run(lib, prob, "fp32", n=n)
+    ref = oracle.evaluate(prob.params, prob.x[:n], prob.channels, "heat", prob.coef, want_jets=False)
+    print("heat fp32", rel(r, ref.r), rel(g, ref.grad))
+    assert rel(r, ref.r) <= FP32_TOL and rel(g, ref.grad) <= FP32_TOL
+    assert abs(loss - ref.loss) <= 4 * FP32_TOL * ref.loss
+
+
+def test_ns_fp16_full(lib):
+    prob = pi.make_problem("ns")
+    r, loss, g, _ = run(lib, prob, "fp16")
+    ref = oracle.evaluate(prob.params, prob.x, prob.channels, "ns", prob.coef, want_jets=False)
+    print("fp16 ns", rel(r, ref.r), rel(g, ref.grad), abs(loss - ref.loss) / ref.loss)
+    assert rel(r, ref.r) <= FP16["r"] and rel(g, ref.grad) <= FP16["grad"]

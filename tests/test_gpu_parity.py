@@ -423,3 +423,38 @@ def test_weighted_residual_and_data_loss(lib, prec):
     assert abs(loss - want_loss) <= (FP32_TOL if prec == "fp32" else 2e-2) * want_loss
     plan_r.close()
     plan_d.close()
+
+
+# KS at the paper's coefficients (5, 0.5, 0.005) (Sec. 3.1.1) and at a generic
+# triple: with distinct coefficients a permutation of alpha, beta, gamma in the
+# kernel's residual or adjoint changes r and the gradient far beyond the bars.
+KS_COEFS = [(5.0, 0.5, 0.005), (0.7, -1.3, 2.1)]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+@pytest.mark.parametrize("coef", KS_COEFS)
+def test_ks_coefficients_gpu(lib, coef, prec):
+    prob = small_problem("ks", seed=71, unsaturated=True)
+    prob.coef = coef
+    g = run_gpu(lib, prob, prec)
+    ref = oracle.evaluate(prob.params, prob.x, prob.channels, "ks", coef)
+    errs = dict(jets=rel(g["jets"], ref.jets), r=rel(g["r"], ref.r), grad=rel(g["grad"], ref.grad))
+    print("ks", coef, prec, {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= (FP32_TOL if prec == "fp32" else LOWP_TOL[prec][k]), (k, v)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("coef", KS_COEFS)
+def test_ks_coefficients_full_width(lib, coef, prec):
+    """The KS workload network 2-256x8-1 on its first 2048 points at distinct
+    coefficients: residual and gradient against the oracle."""
+    prob = pi.make_problem("ks")
+    prob.x = prob.x[:2048]
+    prob.coef = coef
+    g = run_gpu(lib, prob, prec, verify=False)
+    ref = oracle.evaluate(prob.params, prob.x, prob.channels, "ks", coef, want_jets=False)
+    er, eg = rel(g["r"], ref.r), rel(g["grad"], ref.grad)
+    print("ks full width", coef, prec, f"r {er:.2e} grad {eg:.2e}")
+    assert er <= (FP32_TOL if prec == "fp32" else LOWP_TOL[prec]["r"])
+    assert eg <= (FP32_TOL if prec == "fp32" else LOWP_TOL[prec]["grad"])

@@ -1,0 +1,136 @@
+"""Tile-level parity at the full NS workload (2-128x6-3, N = 65536) in the
+launch configuration the benchmark uses (autotuned tuning).
+
+The kernels work on 16-point tiles; the persistent backward kernels visit
+tile blockIdx.x, blockIdx.x + gridDim.x, ... with double-buffered staging.
+A whole-vector relative error cannot see one wrong, dropped or duplicated
+tile among 4096, so these tests look at single tiles:
+
+  * every point's residual and jets against the oracle, as the largest
+    per-tile error (parity.tile_err);
+  * cotangents supported on one tile only (first tiles, tiles at the
+    grid-stride wrap positions of every grid size the plan can pick, the
+    last tile, the ragged tail): J^T r_bar from the GPU against the oracle's
+    on those 16 points;
+  * additivity of the gradient over point sets: J^T r_bar over all points
+    equals the sum over two halves (the per-point arithmetic is the same;
+    only the FP32 accumulation order differs), while one tile's share is far
+    above that tolerance.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import pinn_inputs as pi
+from tests.parity import cosine, flat, rel, tile_err
+
+pytestmark = pytest.mark.gpu
+
+# largest per-tile error of r and of the jets (measured ceilings with margin)
+TILE_BAR = {"fp32": {"r": 1e-4, "jets": 1e-4}, "bf16": {"r": 0.25, "jets": 0.25}, "fp16": {"r": 0.05, "jets": 0.05}}
+# J^T r_bar of a single tile against the oracle (relative L2)
+ONE_TILE_BAR = {"fp32": 1e-5, "bf16": 5e-2, "fp16": 1e-2}
+# gradient additivity: FP32 accumulation order only
+ADD_BAR = 1e-5
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_29702_amd as pj
+    return pj
+
+
+@pytest.fixture(scope="module")
+def ns():
+    prob = pi.make_problem("ns")
+    params = [(torch.tensor(W, device="cuda"), torch.tensor(b, device="cuda")) for W, b in prob.params]
+    x = torch.tensor(prob.x, device="cuda")
+    return prob, params, x
+
+
+@pytest.fixture(scope="module")
+def ns_ref(ns):
+    prob, _, _ = ns
+    return oracle.evaluate(prob.params, prob.x, prob.channels, "ns", prob.coef, want_grad=False)
+
+
+def tuned_plan(lib, prob, params, x, prec, N=None):
+    N = N or x.shape[0]
+    plan = lib.PinnPlan(prob.workload.dims, "ns", N, precision=prec, coef=prob.coef)
+    plan.autotune(params, x[:N], reps=2)
+    return plan
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_every_tile_of_the_forward(lib, ns, ns_ref, prec):
+    prob, params, x = ns
+    plan = tuned_plan(lib, prob, params, x, prec)
+    r, _, _, jets = plan.residual(params, x, want_jets=True)
+    torch.cuda.synchronize()
+    r, jets = r.cpu().numpy(), jets.cpu().numpy()
+    e = dict(r=rel(r, ns_ref.r), jets=rel(jets, ns_ref.jets), r_tile=tile_err(r, ns_ref.r),
+             jets_tile=tile_err(jets, ns_ref.jets))
+    print(prec, plan.tuning(), {k: f"{v:.2e}" for k, v in e.items()})
+    assert e["r_tile"] <= TILE_BAR[prec]["r"] and e["jets_tile"] <= TILE_BAR[prec]["jets"], e
+    plan.close()
+
+
+# tiles 0, 1, the wrap positions of grids of 256, 512 and 1024 workgroups,
+# and the last full tile before the ragged tail
+ONE_TILES = [0, 1, 255, 256, 257, 511, 512, 513, 1023, 1024, 1025, 2048, 4094]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_single_tile_cotangents(lib, ns, prec):
+    prob, params, x = ns
+    N = prob.x.shape[0] - 5  # ragged tail: the last tile holds 11 points
+    plan = tuned_plan(lib, prob, params, x, prec, N=N)
+    xs = x[:N].contiguous()
+    last = (N - 1) // 16
+    rng = np.random.default_rng(81)
+    worst = 0.0
+    for t in ONE_TILES + [last]:
+        lo, hi = 16 * t, min(16 * t + 16, N)
+        w = rng.normal(size=(3, hi - lo))
+        rb = np.zeros((3, N), dtype=np.float32)
+        rb[:, lo:hi] = w
+        plan.residual(params, xs)
+        g = flat(plan.backward(params, xs, r_bar=torch.tensor(rb, device="cuda")))
+        ref = oracle.evaluate(prob.params, prob.x[lo:hi], prob.channels, "ns", prob.coef,
+                              r_bar=rb[:, lo:hi].astype(np.float64), want_jets=False)
+        e = rel(g, ref.grad)
+        worst = max(worst, e)
+        assert e <= ONE_TILE_BAR[prec] and cosine(g, ref.grad) > 0.999, (t, e)
+    print(prec, plan.tuning(), f"worst single-tile gradient error {worst:.2e}")
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_gradient_additivity(lib, ns, prec):
+    prob, params, x = ns
+    N = prob.x.shape[0]
+    h = N // 2  # a multiple of the 128-point padding granule
+    plan = tuned_plan(lib, prob, params, x, prec)
+    half = lib.PinnPlan(prob.workload.dims, "ns", h, precision=prec, coef=prob.coef)
+    half.set_tuning(**{**plan.tuning(), "dw_splits": half.tuning()["dw_splits"]})
+    rb = torch.tensor(np.random.default_rng(82).normal(size=(3, N)).astype(np.float32), device="cuda")
+
+    def grad(pl, xs, r_bar):
+        pl.residual(params, xs)
+        return flat(pl.backward(params, xs, r_bar=r_bar.contiguous()))
+
+    g_all = grad(plan, x, rb)
+    g_sum = grad(half, x[:h].contiguous(), rb[:, :h]) + grad(half, x[h:].contiguous(), rb[:, h:])
+    one = np.zeros((3, N), dtype=np.float32)
+    one[:, 16 * 777:16 * 778] = rb[:, 16 * 777:16 * 778].cpu().numpy()
+    g_one = grad(plan, x, torch.tensor(one, device="cuda"))
+    e = rel(g_sum, g_all)
+    share = float(np.linalg.norm(g_one) / np.linalg.norm(g_all))
+    print(prec, f"additivity {e:.2e}, one tile's share {share:.2e}")
+    assert e <= ADD_BAR
+    assert share >= 20 * ADD_BAR  # a dropped or doubled tile would show
+    plan.close()
+    half.close()

@@ -441,3 +441,69 @@ def test_burgers_bc_against_nested_autograd():
     assert np.allclose(res.r, R, rtol=0, atol=1e-13)
     assert abs(res.loss - Lval) <= 1e-13 * abs(Lval)
     assert np.allclose(res.grad, G, rtol=0, atol=1e-12 * max(1.0, np.abs(G).max()))
+
+
+# ---------------------------------------------------------------- KS coefficients
+# The KS residual r = u_t + alpha u u_x + beta u_xx + gamma u_xxxx (Sec. 3.1.1)
+# pinned at the paper's coefficients (5, 0.5, 0.005) and at a generic triple
+# with distinct magnitudes and signs.  At (1, 1, 1) any permutation of the
+# coefficients in the residual or in its adjoint would go unseen.
+KS_COEFS = [(5.0, 0.5, 0.005), (0.7, -1.3, 2.1)]
+
+
+@pytest.mark.parametrize("coef", KS_COEFS)
+def test_ks_coefficients_against_nested_autograd(coef):
+    """Residual, loss and gradient at distinct coefficients against nested
+    torch.autograd in FP64 (whose residual is written independently)."""
+    prob = small_problem("ks", seed=61)
+    J, R, Lval, G = autograd_ref.evaluate(prob.params, prob.x, prob.channels, "ks", coef)
+    res = oracle.evaluate(prob.params, prob.x, prob.channels, "ks", coef)
+    assert rel(res.r, R) < 1e-13
+    assert abs(res.loss - Lval) <= 1e-13 * abs(Lval)
+    assert rel(res.grad, G) < 1e-12
+
+
+@pytest.mark.parametrize("coef", KS_COEFS)
+def test_ks_coefficients_are_distinguishable(coef):
+    """The pins above can see a permutation: exchanging any two coefficients
+    moves the residual and the gradient far outside their tolerances."""
+    prob = small_problem("ks", seed=61)
+    _, R, _, G = autograd_ref.evaluate(prob.params, prob.x, prob.channels, "ks", coef)
+    for i, j in ((0, 1), (0, 2), (1, 2)):
+        sw = list(coef)
+        sw[i], sw[j] = sw[j], sw[i]
+        res = oracle.evaluate(prob.params, prob.x, prob.channels, "ks", tuple(sw))
+        assert rel(res.r, R) > 1e-6 and rel(res.grad, G) > 1e-6, (i, j)
+
+
+@pytest.mark.parametrize("coef", KS_COEFS)
+def test_ks_coefficients_complex_step_and_inner_product(coef):
+    """<g, delta> against the complex step of the loss, and <J delta, w> =
+    <delta, J^T w> (Eq. 15) with an explicit cotangent, at distinct coefficients."""
+    prob = small_problem("ks", seed=62)
+    res = oracle.evaluate(prob.params, prob.x, prob.channels, "ks", coef)
+    rng = np.random.default_rng(63)
+    delta = rng.normal(size=res.grad.size)
+    _, Jd, dl = oracle.complex_step(prob.params, delta, prob.x, prob.channels, "ks", coef)
+    assert abs(res.grad @ delta - dl) <= 1e-12 * abs(dl)
+    w = rng.normal(size=(1, prob.x.shape[0]))
+    JTw = oracle.evaluate(prob.params, prob.x, prob.channels, "ks", coef, r_bar=w).grad
+    lhs, rhs = float(np.sum(Jd * w)), float(delta @ JTw)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("coef", KS_COEFS)
+def test_ks_coefficients_taylor_slope_two(coef):
+    prob = small_problem("ks", seed=64)
+    theta = oracle.pack_theta(prob.params)
+    dims = oracle.dims_of(prob.params)
+    res = oracle.evaluate(prob.params, prob.x, prob.channels, "ks", coef)
+    delta = np.random.default_rng(65).normal(size=theta.size)
+    delta *= 1.0 / np.linalg.norm(delta)
+    gd = res.grad @ delta
+    # alpha = 5 makes the cubic term large at h = 0.1; the asymptotic range starts lower
+    hs = [1e-2 / 2 ** k for k in range(6)]
+    errs = [abs(oracle.evaluate(oracle.unpack_theta(theta + h * delta, dims), prob.x, prob.channels, "ks", coef,
+                                want_grad=False).loss - res.loss - h * gd) for h in hs]
+    slopes = [math.log(errs[i] / errs[i + 1]) / math.log(2.0) for i in range(len(errs) - 1)]
+    assert all(1.8 < s < 2.2 for s in slopes[1:]), slopes
