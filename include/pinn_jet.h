@@ -111,7 +111,10 @@ typedef struct {
 typedef struct pinn_plan_s *pinn_plan;
 typedef struct pinn_batch_s *pinn_batch;
 
-/* Creates a plan for one network shape, PDE kind and maximum point count.
+/* Creates a plan for one network shape, PDE kind and maximum point count: the
+ * channel set of the kind (the on-demand partial jet of Sec. 2.2, only the
+ * derivative states the residual needs), the saved-state schedule and the
+ * device workspace of the step calls.
  *   prec            PINN_FP32 / PINN_BF16 / PINN_FP16
  *   flags           0 or PINN_VERIFY_F64
  *   save_cap_bytes  upper bound on the device bytes kept between
@@ -138,7 +141,10 @@ pinn_status pinn_plan_memory(pinn_plan plan, size_t *saved_bytes, size_t *worksp
 pinn_status pinn_jet_forward(pinn_plan plan, const pinn_net *net, const float *x, int64_t N,
                              float *jets, void *stream);
 
-/* Forward pass, residual and loss.  Saves the state pinn_jet_backward needs.
+/* Forward pass (Eq. 1-3, the stacked-channel GEMM of Sec. 2.2), the PDE
+ * residual of the kind (Sec. 3.1.1; Eq. 16 for Navier-Stokes) and the
+ * mean-squared residual loss of the training runs (Sec. 3.1).  Saves the state
+ * pinn_jet_backward needs.
  *   r         n_res x N floats (may be NULL)
  *   loss      1 float: sum over residual rows of (1/N) sum_n r^2 (may be NULL)
  *   loss_f64  1 double, the same reduction in FP64; requires PINN_VERIFY_F64
@@ -148,19 +154,42 @@ pinn_status pinn_jet_residual(pinn_plan plan, const pinn_net *net, const pinn_pd
                               const float *x, int64_t N, float *r, float *loss,
                               double *loss_f64, float *jets, void *stream);
 
-/* Parameter gradient by the hand-written adjoint of the jet recursion.
+/* Parameter gradient by reverse-mode differentiation of the loss, which the
+ * paper keeps for training (Sec. 2.2, Sec. 3.1.1): here the hand-written
+ * adjoint of the jet recursion of Eq. 1-3, layer by layer from the residual.
  * Must follow pinn_jet_residual on the same plan with the same net
- * parameter pointers, x and N (PINN_ERR_STATE otherwise), and the parameter
- * values of that call (the operand-type weight copies it made are reused).
+ * parameter pointers, x and N (PINN_ERR_STATE otherwise), and with the
+ * parameter values of that call: the operand-type copies of the hidden
+ * weights that call made are reused, while the first and last layers and the
+ * biases are read again.  The library cannot tell whether the values behind
+ * the pointers changed in between; if they did, the result mixes the two sets
+ * of parameters.  Run pinn_jet_residual again after any update.
  *   r_bar    n_res x N cotangent of r, or NULL for the loss gradient (2 r / N)
  *   dW, db   host arrays of n_layers device pointers shaped like W and b;
  *            overwritten with J^T r_bar (or dL/dtheta)
  *   dW_f64, db_f64  optional host arrays of device pointers receiving the same
- *            gradient reduced in FP64 (requires PINN_VERIFY_F64), or NULL. */
+ *            gradient reduced in FP64 (requires PINN_VERIFY_F64), or NULL.
+ * The loss cotangent is scaled internally by a power of two of the order of
+ * N (and the gradient by its inverse): this adds no rounding and keeps FP16
+ * cotangents in range.  An explicit r_bar is used unscaled, so with FP16
+ * operands its entries should not be far below 1e-3 of the residual scale. */
 pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pde *pde,
                               const float *x, int64_t N, const float *r_bar,
                               float *const *dW, float *const *db,
                               double *const *dW_f64, double *const *db_f64, void *stream);
+
+/* The same for a cotangent of both outputs of pinn_jet_residual, formed on the
+ * device: rbar = r_bar + (*loss_bar) 2 r / N.
+ *   r_bar     n_res x N device array, or NULL (no cotangent of r)
+ *   loss_bar  device pointer to one float, the cotangent of the loss, or NULL
+ *             (none; with r_bar also NULL the loss gradient, *loss_bar = 1)
+ * This is the backward of an autograd function returning (r, loss): no host
+ * synchronisation is needed to read the loss cotangent.  With r_bar NULL the
+ * loss cotangent is scaled internally as in pinn_jet_backward. */
+pinn_status pinn_jet_backward_cot(pinn_plan plan, const pinn_net *net, const pinn_pde *pde,
+                                  const float *x, int64_t N, const float *r_bar, const float *loss_bar,
+                                  float *const *dW, float *const *db,
+                                  double *const *dW_f64, double *const *db_f64, void *stream);
 
 /* Tunable launch parameters of a plan.  They change reduction order and
  * workgroup shapes, never the arithmetic: every setting is deterministic and

@@ -29,7 +29,8 @@ EXPORTS = ["pinn_plan_create", "pinn_plan_destroy", "pinn_plan_memory", "pinn_je
            "pinn_pde_residuals", "pinn_plan_profile", "pinn_plan_profile_read", "pinn_plan_get_tuning",
            "pinn_plan_set_tuning", "pinn_plan_autotune", "pinn_batch_create", "pinn_batch_destroy",
            "pinn_batch_configure", "pinn_batch_step", "pinn_batch_autotune", "pinn_graph_capture",
-           "pinn_graph_launch", "pinn_graph_destroy", "pinn_adam_step", "pinn_graph_capture_train"]
+           "pinn_graph_launch", "pinn_graph_destroy", "pinn_adam_step", "pinn_graph_capture_train",
+           "pinn_jet_backward_cot"]
 KERNEL_CLASSES = {"layer_fwd": 1, "layer_bwd": 2, "dw_hidden": 3, "out_fwd": 4, "out_bwd": 5,
                   "seed_fwd": 6, "other": 7, "bwd_dw": 8}
 
@@ -71,6 +72,7 @@ def _load():
     lib.pinn_jet_forward.argtypes = [vp, NetP, vp, i64, vp, vp]
     lib.pinn_jet_residual.argtypes = [vp, NetP, PdeP, vp, i64, vp, vp, vp, vp, vp]
     lib.pinn_jet_backward.argtypes = [vp, NetP, PdeP, vp, i64, vp, pp, pp, pp, pp, vp]
+    lib.pinn_jet_backward_cot.argtypes = [vp, NetP, PdeP, vp, i64, vp, vp, pp, pp, pp, pp, vp]
     lib.pinn_plan_profile.argtypes = [vp, i32]
     lib.pinn_plan_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     TuneP = ctypes.POINTER(Tuning)
@@ -101,7 +103,8 @@ def _load():
                  "pinn_plan_profile", "pinn_plan_profile_read", "pinn_plan_get_tuning", "pinn_plan_set_tuning",
                  "pinn_plan_autotune", "pinn_batch_create", "pinn_batch_destroy", "pinn_batch_configure",
                  "pinn_batch_step", "pinn_batch_autotune", "pinn_graph_capture", "pinn_graph_launch",
-                 "pinn_graph_destroy", "pinn_adam_step", "pinn_graph_capture_train"):
+                 "pinn_graph_destroy", "pinn_adam_step", "pinn_graph_capture_train",
+                 "pinn_jet_backward_cot"):
         getattr(lib, name).restype = ctypes.c_int32
     return lib
 

@@ -49,8 +49,10 @@ __global__ __launch_bounds__(256) void k_cast_all(CastPack pk, int w) {
   if (idx >= (int64_t)w * w) return;
   const int i = (int)(idx / w), j = (int)(idx % w);
   const float v = pk.W[l][idx];
-  static_cast<T *>(pk.Wop[l])[idx] = static_cast<T>(v);
-  if (pk.WTop[l]) static_cast<T *>(pk.WTop[l])[(int64_t)j * w + i] = static_cast<T>(v);
+  const T hi = static_cast<T>(v);
+  static_cast<T *>(pk.Wop[l])[idx] = hi;
+  if (pk.WTop[l]) static_cast<T *>(pk.WTop[l])[(int64_t)j * w + i] = hi;
+  if (pk.Wlo[l]) static_cast<T *>(pk.Wlo[l])[idx] = static_cast<T>(v - static_cast<float>(hi));
 }
 
 hipError_t launch_cast_all(int prec, const CastPack &pk, int n, int w, hipStream_t st) {
@@ -220,7 +222,8 @@ __global__ __launch_bounds__(256) void k_loss_reduce(const float *__restrict__ p
 template <class PDE>
 __global__ __launch_bounds__(256) void k_out_adj(const float *__restrict__ u_save,
                                                  const float *__restrict__ r_save,
-                                                 const float *__restrict__ r_bar, int64_t N,
+                                                 const float *__restrict__ r_bar,
+                                                 const float *__restrict__ loss_bar, int64_t N,
                                                  int64_t N_pad, float rbar_scale, Coef k,
                                                  float *__restrict__ ubar) {
   using CH = typename PDE::CH;
@@ -233,9 +236,12 @@ __global__ __launch_bounds__(256) void k_out_adj(const float *__restrict__ u_sav
   for (int o = 0; o < DOUT; ++o)
 #pragma unroll
     for (int c = 0; c < C; ++c) u[o][c] = u_save[(n * DOUT + o) * C + c];
+  // rbar = r_bar + lb * rbar_scale * r, lb = *loss_bar (1 when neither
+  // cotangent is given: the loss gradient)
+  const float lb = loss_bar ? *loss_bar : (r_bar ? 0.f : 1.f);
 #pragma unroll
   for (int e = 0; e < NRES; ++e)
-    rb[e] = !valid ? 0.f : (r_bar ? r_bar[e * N + n] : rbar_scale * r_save[e * N_pad + n]);
+    rb[e] = !valid ? 0.f : (r_bar ? r_bar[e * N + n] : 0.f) + lb * rbar_scale * r_save[e * N_pad + n];
   PDE::adjoint(u, rb, k, ub);
 #pragma unroll
   for (int o = 0; o < DOUT; ++o)
@@ -391,7 +397,8 @@ template <int G>
 __global__ __launch_bounds__(256) void k_reduce_parts_g(const float *__restrict__ part, int splits,
                                                         int64_t stride, int64_t M1, int64_t M2,
                                                         float *__restrict__ a32, float *__restrict__ b32,
-                                                        double *__restrict__ a64, double *__restrict__ b64) {
+                                                        double *__restrict__ a64, double *__restrict__ b64,
+                                                        float scale) {
   constexpr int OUTS = 256 / G;
   __shared__ float s32[256];
   __shared__ double s64[256];
@@ -419,6 +426,8 @@ __global__ __launch_bounds__(256) void k_reduce_parts_g(const float *__restrict_
       t += s32[k * OUTS + o];
       td += s64[k * OUTS + o];
     }
+    t *= scale;
+    td *= (double)scale;
     if (q < M1) {
       if (a32) a32[q] = t;
       if (a64) a64[q] = td;
@@ -439,7 +448,7 @@ template <int COLS, int NT>
 __global__ __launch_bounds__(NT) void k_reduce_parts_v4(const float *__restrict__ part, int splits, int64_t stride,
                                                         int64_t M1, int64_t M2, float *__restrict__ a32,
                                                         float *__restrict__ b32, double *__restrict__ a64,
-                                                        double *__restrict__ b64) {
+                                                        double *__restrict__ b64, float scale) {
   constexpr int G = NT / COLS;
   __shared__ f32x4 s32[NT];
   __shared__ double s64[NT][4];
@@ -483,12 +492,14 @@ __global__ __launch_bounds__(NT) void k_reduce_parts_v4(const float *__restrict_
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int64_t q = 4 * c4 + e;
+      const float te = t[e] * scale;
+      const double tde = td[e] * (double)scale;
       if (q < M1) {
-        if (a32) a32[q] = t[e];
-        if (a64) a64[q] = td[e];
+        if (a32) a32[q] = te;
+        if (a64) a64[q] = tde;
       } else {
-        if (b32) b32[q - M1] = t[e];
-        if (b64) b64[q - M1] = td[e];
+        if (b32) b32[q - M1] = te;
+        if (b64) b64[q - M1] = tde;
       }
     }
   }
@@ -561,12 +572,13 @@ hipError_t launch_loss_reduce(const float *part, const double *part64, int n_par
 }
 
 hipError_t launch_out_adj(int kind, const float *u_save, const float *r_save, const float *r_bar,
-                          int64_t N, int64_t N_pad, float rbar_scale, Coef k, float *ubar, hipStream_t st) {
+                          const float *loss_bar, int64_t N, int64_t N_pad, float rbar_scale, Coef k, float *ubar,
+                          hipStream_t st) {
   dim3 grid((unsigned)((N_pad + 255) / 256));
   return by_kind(kind, [&](auto pde) {
     using PDE = decltype(pde);
-    hipLaunchKernelGGL((k_out_adj<PDE>), grid, dim3(256), 0, st, u_save, r_save, r_bar, N, N_pad, rbar_scale,
-                       k, ubar);
+    hipLaunchKernelGGL((k_out_adj<PDE>), grid, dim3(256), 0, st, u_save, r_save, r_bar, loss_bar, N, N_pad,
+                       rbar_scale, k, ubar);
     return hipGetLastError();
   });
 }
@@ -603,7 +615,7 @@ hipError_t launch_dw_seed(int kind, int prec, const void *Zb_1, const float *x, 
 
 hipError_t launch_reduce_parts2(const float *part, int splits, int64_t stride, int64_t M1,
                                 int64_t M2, float *a32, float *b32, double *a64, double *b64,
-                                hipStream_t st) {
+                                hipStream_t st, float scale) {
   const int64_t M = M1 + M2;
   // enough workgroups to keep many loads in flight: more threads per output
   // when there are few outputs or many splits
@@ -611,19 +623,19 @@ hipError_t launch_reduce_parts2(const float *part, int splits, int64_t stride, i
       reinterpret_cast<uintptr_t>(part) % 16 == 0) {
     dim3 grid((unsigned)((M / 4 + 15) / 16));
     hipLaunchKernelGGL((k_reduce_parts_v4<16, 256>), grid, dim3(256), 0, st, part, splits, stride, M1, M2, a32,
-                       b32, a64, b64);
+                       b32, a64, b64, scale);
   } else if (M * 4 < 256LL * 256 && splits >= 64) {
     dim3 grid((unsigned)((M + 7) / 8));
     hipLaunchKernelGGL(k_reduce_parts_g<32>, grid, dim3(256), 0, st, part, splits, stride, M1, M2, a32, b32,
-                       a64, b64);
+                       a64, b64, scale);
   } else if (splits >= 64) {
     dim3 grid((unsigned)((M + 15) / 16));
     hipLaunchKernelGGL(k_reduce_parts_g<16>, grid, dim3(256), 0, st, part, splits, stride, M1, M2, a32, b32,
-                       a64, b64);
+                       a64, b64, scale);
   } else {
     dim3 grid((unsigned)((M + 63) / 64));
     hipLaunchKernelGGL(k_reduce_parts_g<4>, grid, dim3(256), 0, st, part, splits, stride, M1, M2, a32, b32,
-                       a64, b64);
+                       a64, b64, scale);
   }
   return hipGetLastError();
 }

@@ -116,13 +116,22 @@ __global__ __launch_bounds__(NW * 64) void k_fwd_fused(FusedFwdArgs a) {
   }
 
   // ---- hidden layers max(2, l_first) .. l_last
+  // BF16 operands: W enters as the pair (W_hi, W_lo), two MFMAs per product,
+  // so that the network evaluated is the FP32 one to about 16 bits (rounding
+  // W itself to 8 bits changes the function enough to move the parameter
+  // gradient by up to ~10% on deep networks); the stack stays one BF16 operand.
+  constexpr bool SPLIT = __is_same(T, bf16_t);
   for (int l = a.l_first > 2 ? a.l_first : 2; l <= a.l_last; ++l) {
     const T *Wl = static_cast<const T *>(a.Wop[l]);
     const T *wrow = Wl + (int64_t)(jt0 * 16 + r) * w + 8 * g;
+    const T *lrow = SPLIT ? static_cast<const T *>(a.Wlo[l]) + (int64_t)(jt0 * 16 + r) * w + 8 * g : nullptr;
     const T *brow = stk + (nt * 16 + r) * pitch + 8 * g;
-    typename M::frag fa[TPW];
+    typename M::frag fa[TPW], fl[TPW];
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) fa[t] = M::load(wrow + (int64_t)t * 16 * w);
+    for (int t = 0; t < TPW; ++t) {
+      fa[t] = M::load(wrow + (int64_t)t * 16 * w);
+      if constexpr (SPLIT) fl[t] = M::load(lrow + (int64_t)t * 16 * w);
+    }
     f32x4 acc[TPW][C];
 #pragma unroll
     for (int t = 0; t < TPW; ++t)
@@ -140,6 +149,17 @@ __global__ __launch_bounds__(NW * 64) void k_fwd_fused(FusedFwdArgs a) {
       for (int t = 0; t < TPW; ++t)
 #pragma unroll
         for (int c = 0; c < C; ++c) M::mma(acc[t][c], fa[t], fb[c]);
+      if constexpr (SPLIT) {
+        typename M::frag fln[TPW];
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) fln[t] = M::load(lrow + (int64_t)t * 16 * w + kn);
+#pragma unroll
+        for (int t = 0; t < TPW; ++t)
+#pragma unroll
+          for (int c = 0; c < C; ++c) M::mma(acc[t][c], fl[t], fb[c]);
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) fl[t] = fln[t];
+      }
 #pragma unroll
       for (int t = 0; t < TPW; ++t) fa[t] = fn[t];
     }
@@ -290,6 +310,9 @@ template <class PDE, class T>
 hipError_t launch_fused_t(const FusedFwdArgs &a, int P, hipStream_t st) {
   constexpr int C = PDE::CH::C;
   const int w = a.w;
+  if constexpr (__is_same(T, bf16_t))  // BF16 needs the weight pair of every GEMM layer
+    for (int l = a.l_first > 2 ? a.l_first : 2; l <= a.l_last; ++l)
+      if (!a.Wlo[l]) return hipErrorInvalidValue;
   const size_t lds = stack_lds(P, C, w, sizeof(T));
   const unsigned grid = (unsigned)(a.N_pad / P);
   // tiles per layer = (P/16) * (w/16); 4 per wave where possible

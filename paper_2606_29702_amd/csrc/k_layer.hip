@@ -21,18 +21,28 @@ namespace pj {
 
 // Accumulates acc[jt][nt][c] += sum_k Wop[m0 + 16 jt + r][k] * B[n0 + 16 nt + r][c][k]
 // over k in [0, w): the stacked-channel GEMM of one wave tile.
-template <class T, int C, int NTN>
+// With Wlo (the low parts of a BF16 weight pair) each product is the sum of
+// the MFMAs with Wop and with Wlo.
+template <class T, int C, int NTN, bool SPLIT = false>
 __device__ __forceinline__ void stacked_gemm(f32x4 (&acc)[2][NTN][C], const T *__restrict__ Wop,
-                                             const T *__restrict__ B, int m0, int64_t n0, int w, int lane) {
+                                             const T *__restrict__ B, int m0, int64_t n0, int w, int lane,
+                                             const T *__restrict__ Wlo = nullptr) {
   using M = Mma<T>;
   const int r = lane & 15, g = lane >> 4;
   const int64_t ps = (int64_t)C * w;
   const T *wp0 = Wop + (int64_t)(m0 + r) * w + 8 * g;
   const T *wp1 = wp0 + (int64_t)16 * w;
+  const T *lp0 = SPLIT ? Wlo + (int64_t)(m0 + r) * w + 8 * g : nullptr;
+  const T *lp1 = SPLIT ? lp0 + (int64_t)16 * w : nullptr;
   const T *bp = B + (n0 + r) * ps + 8 * g;
   for (int k = 0; k < w; k += 32) {
     const typename M::frag a0 = M::load(wp0 + k);
     const typename M::frag a1 = M::load(wp1 + k);
+    typename M::frag l0, l1;
+    if constexpr (SPLIT) {
+      l0 = M::load(lp0 + k);
+      l1 = M::load(lp1 + k);
+    }
 #pragma unroll
     for (int c = 0; c < C; ++c) {
 #pragma unroll
@@ -40,6 +50,10 @@ __device__ __forceinline__ void stacked_gemm(f32x4 (&acc)[2][NTN][C], const T *_
         const typename M::frag b = M::load(bp + nt * 16 * ps + c * w + k);
         M::mma(acc[0][nt][c], a0, b);
         M::mma(acc[1][nt][c], a1, b);
+        if constexpr (SPLIT) {
+          M::mma(acc[0][nt][c], l0, b);
+          M::mma(acc[1][nt][c], l1, b);
+        }
       }
     }
   }
@@ -59,8 +73,8 @@ __device__ __forceinline__ void zero_acc(f32x4 (&acc)[2][NTN][C]) {
 // with STORE_S also the FP32 state S (tanh z_0 and the derivative channels).
 template <class CH, class T, int WJ, bool STORE_S>
 __global__ __launch_bounds__(256) void k_layer_fwd(const T *__restrict__ A_in, const T *__restrict__ Wop,
-                                                   const float *__restrict__ bias, T *__restrict__ A_out,
-                                                   float *__restrict__ S_out, int w) {
+                                                   const T *__restrict__ Wlo, const float *__restrict__ bias,
+                                                   T *__restrict__ A_out, float *__restrict__ S_out, int w) {
   constexpr int C = CH::C;
   constexpr int WN = 4 / WJ;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -72,7 +86,7 @@ __global__ __launch_bounds__(256) void k_layer_fwd(const T *__restrict__ A_in, c
 
   f32x4 acc[2][2][C];
   zero_acc<C, 2>(acc);
-  stacked_gemm<T, C, 2>(acc, Wop, A_in, m0, n0, w, lane);
+  stacked_gemm<T, C, 2, __is_same(T, bf16_t)>(acc, Wop, A_in, m0, n0, w, lane, Wlo);
 
 #pragma unroll
   for (int jt = 0; jt < 2; ++jt) {
@@ -666,16 +680,18 @@ __global__ __launch_bounds__(NW * 64) void k_layer_bwd_kc2(BwdArgs args) {
 namespace {
 
 template <class CH, class T>
-hipError_t launch_fwd_t(const void *A_in, const void *Wop, const float *b, void *A_out, float *S_out,
-                        int64_t N_pad, int w, hipStream_t st) {
+hipError_t launch_fwd_t(const void *A_in, const void *Wop, const void *Wlo, const float *b, void *A_out,
+                        float *S_out, int64_t N_pad, int w, hipStream_t st) {
+  if (__is_same(T, bf16_t) && !Wlo) return hipErrorInvalidValue;  // BF16 needs the weight pair
   const int WJ = (w % 128 == 0) ? 4 : ((w % 64 == 0) ? 2 : 1);
   const int WN = 4 / WJ;
   dim3 grid((unsigned)(N_pad / (32 * WN)), (unsigned)(w / (32 * WJ)));
   const T *Ai = static_cast<const T *>(A_in);
   const T *Wp = static_cast<const T *>(Wop);
+  const T *Wl = static_cast<const T *>(Wlo);
   T *Ao = static_cast<T *>(A_out);
 #define PJ_FWD(WJV, SV) \
-  hipLaunchKernelGGL((k_layer_fwd<CH, T, WJV, SV>), grid, dim3(256), 0, st, Ai, Wp, b, Ao, S_out, w)
+  hipLaunchKernelGGL((k_layer_fwd<CH, T, WJV, SV>), grid, dim3(256), 0, st, Ai, Wp, Wl, b, Ao, S_out, w)
   if (S_out) {
     if (WJ == 4) PJ_FWD(4, true); else if (WJ == 2) PJ_FWD(2, true); else PJ_FWD(1, true);
   } else {
@@ -802,11 +818,11 @@ hipError_t dispatch(int kind, int prec, F &&f) {
 
 }  // namespace
 
-hipError_t launch_layer_fwd(int kind, int prec, const void *A_in, const void *Wop, const float *b,
+hipError_t launch_layer_fwd(int kind, int prec, const void *A_in, const void *Wop, const void *Wlo, const float *b,
                             void *A_out, float *S_out, int64_t N_pad, int w, hipStream_t st) {
   return dispatch(kind, prec, [&](auto pde, auto tv) {
     using CH = typename decltype(pde)::CH;
-    return launch_fwd_t<CH, decltype(tv)>(A_in, Wop, b, A_out, S_out, N_pad, w, st);
+    return launch_fwd_t<CH, decltype(tv)>(A_in, Wop, Wlo, b, A_out, S_out, N_pad, w, st);
   });
 }
 

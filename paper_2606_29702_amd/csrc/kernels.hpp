@@ -28,11 +28,15 @@ int op_size(int prec);
 hipError_t launch_cast(int prec, const float *W, int rows, int cols, void *Wop, void *WTop,
                        hipStream_t st);
 
-// Casts of n hidden w x w weights in one launch (WTop entries may be null).
+// Casts of n hidden w x w weights in one launch (WTop and Wlo entries may be
+// null).  Wlo receives the remainder W - Wop rounded to the operand type: for
+// BF16 operands the forward GEMMs use the pair (Wop, Wlo), which carries
+// about 16 significant bits of W instead of 8.
 struct CastPack {
   const float *W[16];
   void *Wop[16];
   void *WTop[16];
+  void *Wlo[16];
 };
 hipError_t launch_cast_all(int prec, const CastPack &pk, int n, int w, hipStream_t st);
 
@@ -44,7 +48,9 @@ hipError_t launch_seed_fwd(int kind, int prec, const float *x, int64_t N, int64_
 
 // Hidden layer: Z = W A_in (+ b on the value channel), A_out = jet(Z); S_out
 // (may be null) receives the FP32 state tanh(z_0), z_1 .. z_{C-1}.
-hipError_t launch_layer_fwd(int kind, int prec, const void *A_in, const void *Wop, const float *b,
+// Wlo (may be null; required for BF16 operands) is the low part of the
+// weight pair, as in CastPack.
+hipError_t launch_layer_fwd(int kind, int prec, const void *A_in, const void *Wop, const void *Wlo, const float *b,
                             void *A_out, float *S_out, int64_t N_pad, int w, hipStream_t st);
 
 // Hidden layer adjoint, producing Zbar of layer l-1 (see k_layer.hip):
@@ -115,6 +121,7 @@ struct FusedFwdArgs {
   bool do_output;                       // output layer + residual (requires l_last == H)
   const float *W1, *b1;                 // layer 1 (fp32)
   const void *Wop[kMaxHidden + 1];      // layers 2..H, operand type
+  const void *Wlo[kMaxHidden + 1];      // layers 2..H, low parts (BF16 operands only)
   const float *b[kMaxHidden + 1];       // layers 2..H
   const float *WL, *bL;                 // output layer (fp32)
   void *A[kMaxHidden + 1];              // saved stacks, layers 1..H
@@ -140,9 +147,12 @@ hipError_t launch_loss_reduce(const float *part, const double *part64, int n_par
                               float *loss, double *loss64, hipStream_t st);
 
 // Residual adjoint at the outputs: ubar[n][o][c] = d<rbar, r>/d u_c[o] at
-// point n, rbar = r_bar or rbar_scale * r (zero on padded points).
+// point n, rbar = r_bar + lb * rbar_scale * r with lb = *loss_bar, or lb = 1
+// when both r_bar and loss_bar are null (each may be null; zero on padded
+// points).
 hipError_t launch_out_adj(int kind, const float *u_save, const float *r_save, const float *r_bar,
-                          int64_t N, int64_t N_pad, float rbar_scale, Coef k, float *ubar, hipStream_t st);
+                          const float *loss_bar, int64_t N, int64_t N_pad, float rbar_scale, Coef k, float *ubar,
+                          hipStream_t st);
 
 // Partial sums of the output layer's dW, db over chunks of points:
 // part[chunk][d_out*w + d_out].
@@ -160,13 +170,15 @@ int dw_tile(int w);  // dW workgroup tile edge (128, 64 or 32)
 hipError_t launch_dw_hidden(int prec, int C, const void *Zb, const void *A_prev, int64_t N_pad, int w,
                             float *part, float *part_db, int splits, hipStream_t st);
 
-// out[q] = sum_s part[s * stride + q] for q < M1 + M2, summed in a fixed
-// order (deterministic), scattered into two destinations: q < M1 goes to
-// a[q], q >= M1 to b[q - M1] (packed dW/db partials).  FP32 results into
+// out[q] = scale * sum_s part[s * stride + q] for q < M1 + M2, summed in a
+// fixed order (deterministic), scattered into two destinations: q < M1 goes
+// to a[q], q >= M1 to b[q - M1] (packed dW/db partials).  FP32 results into
 // a32/b32, FP64 sums of the same partials into a64/b64; each may be null.
+// scale is a power of two (the inverse of the cotangent scaling), so it
+// adds no rounding.
 hipError_t launch_reduce_parts2(const float *part, int splits, int64_t stride, int64_t M1,
                                 int64_t M2, float *a32, float *b32, double *a64, double *b64,
-                                hipStream_t st);
+                                hipStream_t st, float scale = 1.f);
 
 // One Adam step over up to kAdamSegs parameter tensors (k_adam.hip).
 constexpr int kAdamSegs = 32;

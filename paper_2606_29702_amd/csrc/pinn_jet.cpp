@@ -109,6 +109,7 @@ struct pinn_plan_s {
 
   // device workspace (indices are 1-based layer numbers; entry 0 unused)
   std::vector<void *> Wop, WTop;  // hidden layers 2..H, operand-type copies
+  std::vector<void *> Wlo;        // low parts W - Wop of the BF16 weight pairs (BF16 only)
   std::vector<void *> A;          // activation stacks, layers 1..H (null: not materialized)
   std::vector<float *> S;         // saved FP32 states, layers 1..H (store_S only)
   // Checkpoint schedule: ckpt[l] means layer l's stack is kept from the
@@ -129,6 +130,13 @@ struct pinn_plan_s {
   int bwd_fused = 0;       // weight gradients inside the backward layer kernels when supported
   std::vector<void *> allocs;
   size_t saved_bytes = 0, ws_bytes = 0;
+  // Workspace source: separate hipMalloc allocations (the default), consecutive
+  // 256-byte aligned pieces of a caller-given device region (region != null;
+  // nothing is allocated or freed), or no memory at all (measure: only the
+  // bytes a region would need are counted).
+  char *region = nullptr;
+  size_t region_cap = 0, region_used = 0;
+  bool measure = false;
 
   // state saved by the latest residual call
   bool have_state = false;
@@ -146,6 +154,17 @@ struct pinn_plan_s {
   bool verify() const { return (flags & PINN_VERIFY_F64) != 0; }
 
   hipError_t alloc(void **p, size_t bytes) {
+    if (measure || region) {
+      const size_t sz = (bytes + 255) & ~size_t(255);
+      *p = nullptr;
+      if (region) {
+        if (region_used + sz > region_cap) return hipErrorOutOfMemory;
+        *p = region + region_used;
+        region_used += sz;
+      }
+      ws_bytes += sz;
+      return hipSuccess;
+    }
     hipError_t e = hipMalloc(p, bytes);
     if (e == hipSuccess) {
       allocs.push_back(*p);
@@ -274,6 +293,7 @@ pinn_status fwd_range(pinn_plan p, const pinn_net *net, const float *x, int64_t 
     a.b1 = net->b[0];
     for (int l = 2; l <= H; ++l) {
       a.Wop[l] = p->Wop[l];
+      a.Wlo[l] = p->Wlo[l];
       a.b[l] = net->b[l - 1];
     }
     a.WL = net->W[L - 1];
@@ -305,7 +325,7 @@ pinn_status fwd_range(pinn_plan p, const pinn_net *net, const float *x, int64_t 
     if (l == 1) {
       e = timed(p, PINN_K_SEED_FWD, st, [&] { return pj::launch_seed_fwd(p->kind, p->prec, x, N, npad, net->W[0], net->b[0], w, out, S, st); });
     } else {
-      e = timed(p, PINN_K_LAYER_FWD, st, [&] { return pj::launch_layer_fwd(p->kind, p->prec, prev, p->Wop[l], net->b[l - 1], out, S, npad, w, st); });
+      e = timed(p, PINN_K_LAYER_FWD, st, [&] { return pj::launch_layer_fwd(p->kind, p->prec, prev, p->Wop[l], p->Wlo[l], net->b[l - 1], out, S, npad, w, st); });
     }
     if (e) return hip_fail(e, "hidden layer");
     prev = out;
@@ -324,6 +344,7 @@ pinn_status cast_weights(pinn_plan p, const pinn_net *net, bool transposed, hipS
     pk.W[l - 2] = net->W[l - 1];
     pk.Wop[l - 2] = p->Wop[l];
     pk.WTop[l - 2] = transposed ? p->WTop[l] : nullptr;
+    pk.Wlo[l - 2] = p->Wlo[l];
   }
   hipError_t e = timed(p, PINN_K_OTHER, st, [&] { return pj::launch_cast_all(p->prec, pk, p->H - 1, p->w, st); });
   return e ? hip_fail(e, "cast") : PINN_OK;
@@ -409,9 +430,16 @@ int32_t pinn_pde_residuals(int32_t kind) {
   return kind_info(kind, &ki) ? ki.nres : 0;
 }
 
-pinn_status pinn_plan_create(const pinn_net *net, const pinn_pde *pde, int64_t max_points,
-                             int32_t prec, uint32_t flags, size_t save_cap_bytes, pinn_plan *out) {
-  g_err.clear();
+}  // extern "C"
+
+// Validates the arguments of a plan and builds it with its workspace taken
+// as the plan's allocator says (see pinn_plan_s::alloc): hipMalloc when
+// region is null and measure false; carved from [region, region + region_cap);
+// or, with measure, only counted (the returned plan then owns no memory and
+// is only good for its byte counts).
+static pinn_status plan_build(const pinn_net *net, const pinn_pde *pde, int64_t max_points, int32_t prec,
+                              uint32_t flags, size_t save_cap_bytes, char *region, size_t region_cap, bool measure,
+                              pinn_plan *out) {
   if (!out) return fail(PINN_ERR_ARG, "out is NULL");
   *out = nullptr;
   pinn_status st = check_pde(pde, 0);
@@ -469,18 +497,22 @@ pinn_status pinn_plan_create(const pinn_net *net, const pinn_pde *pde, int64_t m
   p->H = H;
   p->w = w;
   p->ki = ki;
+  p->region = region;
+  p->region_cap = region_cap;
+  p->measure = measure;
   p->max_points = max_points;
   p->npad_max = npad;
   p->save_cap = save_cap_bytes;
   p->saved_bytes = saved;
   p->store_S = store_S;
   p->ckpt = ckpt;
-  if (hipGetDevice(&p->device) != hipSuccess) {
+  if (!measure && hipGetDevice(&p->device) != hipSuccess) {
     delete p;
     return fail(PINN_ERR_DEVICE, "no HIP device");
   }
   p->Wop.assign(H + 1, nullptr);
   p->WTop.assign(H + 1, nullptr);
+  p->Wlo.assign(H + 1, nullptr);
   p->A.assign(H + 1, nullptr);
   p->S.assign(H + 1, nullptr);
   hipError_t e = hipSuccess;
@@ -490,6 +522,7 @@ pinn_status pinn_plan_create(const pinn_net *net, const pinn_pde *pde, int64_t m
   for (int l = 2; l <= H; ++l) {
     A(&p->Wop[l], (size_t)w * w * osz);
     A(&p->WTop[l], (size_t)w * w * osz);
+    if (prec == PINN_BF16) A(&p->Wlo[l], (size_t)w * w * osz);
   }
   p->ckpt_buf.assign(H + 1, nullptr);
   for (int l = 1; l <= H; ++l) {
@@ -521,11 +554,22 @@ pinn_status pinn_plan_create(const pinn_net *net, const pinn_pde *pde, int64_t m
   A(reinterpret_cast<void **>(&p->part), part_elems * sizeof(float));
   if (e != hipSuccess) {
     delete p;
+    if (region && e == hipErrorOutOfMemory)
+      return fail(PINN_ERR_CAP, "workspace does not fit the %zu-byte device region", region_cap);
     return fail(e == hipErrorOutOfMemory ? PINN_ERR_NOMEM : PINN_ERR_DEVICE, "workspace allocation: %s",
                 hipGetErrorString(e));
   }
   *out = p;
   return PINN_OK;
+}
+
+
+extern "C" {
+
+pinn_status pinn_plan_create(const pinn_net *net, const pinn_pde *pde, int64_t max_points,
+                             int32_t prec, uint32_t flags, size_t save_cap_bytes, pinn_plan *out) {
+  g_err.clear();
+  return plan_build(net, pde, max_points, prec, flags, save_cap_bytes, nullptr, 0, false, out);
 }
 
 pinn_status pinn_plan_destroy(pinn_plan plan) {
@@ -595,11 +639,14 @@ pinn_status pinn_jet_residual(pinn_plan plan, const pinn_net *net, const pinn_pd
   return PINN_OK;
 }
 
-pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pde *pde,
-                              const float *x, int64_t N, const float *r_bar, float *const *dW,
-                              float *const *db, double *const *dW_f64, double *const *db_f64,
-                              void *stream) {
-  g_err.clear();
+}  // extern "C"
+
+// The backward pass for the cotangent rbar = r_bar + lb 2 r / N, with lb =
+// *loss_bar, or lb = 1 when both are null (see pinn_jet_backward_cot).
+static pinn_status backward_impl(pinn_plan plan, const pinn_net *net, const pinn_pde *pde, const float *x,
+                                 int64_t N, const float *r_bar, const float *loss_bar, float *const *dW,
+                                 float *const *db, double *const *dW_f64, double *const *db_f64,
+                                 void *stream) {
   pinn_status st = check_call(plan, net, x, N);
   if (st) return st;
   st = check_pde(pde, plan->kind);
@@ -625,6 +672,18 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
   const int64_t npad = round_up(N, pj::kPointTile);
   const KindInfo &ki = p->ki;
   auto f64 = [&](double *const *arr, int l) -> double * { return arr ? arr[l] : nullptr; };
+  // The loss cotangent 2 r / N is scaled by S, the largest power of two not
+  // above N / 2, so that the backward stacks hold values of the order of r:
+  // with FP16 operands the unscaled cotangents fall below the normal range at
+  // large N.  Every backward step is linear in the cotangent and power-of-two
+  // scaling adds no rounding, so the reductions take out 1/S exactly and FP32
+  // and BF16 results are those of the unscaled arithmetic.  An explicit r_bar
+  // is used as given.
+  double cot_scale = 1.0;
+  if (!r_bar)
+    while (4.0 * cot_scale <= (double)N) cot_scale *= 2.0;
+  const float rbar_scale = (float)(2.0 * cot_scale / (double)N);
+  const float inv_s = (float)(1.0 / cot_scale);
   hipError_t e;
   // the operand-type weights W and W^T were made by the residual call
   pinn_status rs = PINN_OK;
@@ -656,7 +715,7 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
     // Each backward layer kernel also produces the weight gradient of the
     // layer whose zbar it computes: dW_m from zbar_m and the stack of m - 1.
     const int grid = (int)std::min<int64_t>(std::min<int64_t>(npad / 16, p->dw_splits_max), 512);
-    e = timed(p, PINN_K_OUT_BWD, s, [&] { return pj::launch_out_adj(p->kind, p->u_save, p->r_save, r_bar, N, npad, (float)(2.0 / (double)N), coef_of(pde), p->ubar, s); });
+    e = timed(p, PINN_K_OUT_BWD, s, [&] { return pj::launch_out_adj(p->kind, p->u_save, p->r_save, r_bar, loss_bar, N, npad, rbar_scale, coef_of(pde), p->ubar, s); });
     if (e) return hip_fail(e, "output adjoint");
     auto layer = [&](pj::LayerBwd &B, int m, int cls) -> pinn_status {
       const void *Am1 = nullptr;
@@ -674,7 +733,7 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
       B.Zb_out = p->Zb[m % 2];
       hipError_t e2 = timed(p, cls, s, [&] { return pj::launch_bwd_dw(p->kind, p->prec, B, p->part, npad, grid, s); });
       if (e2) return hip_fail(e2, "backward layer");
-      e2 = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, grid, (int64_t)w * w + w, (int64_t)w * w, w, dW[m - 1], db[m - 1], f64(dW_f64, m - 1), f64(db_f64, m - 1), s); });
+      e2 = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, grid, (int64_t)w * w + w, (int64_t)w * w, w, dW[m - 1], db[m - 1], f64(dW_f64, m - 1), f64(db_f64, m - 1), s, inv_s); });
       return e2 ? hip_fail(e2, "reduction") : PINN_OK;
     };
     {
@@ -690,7 +749,7 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
     if (rs) return rs;
     e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_dw_out(p->kind, p->prec, p->ubar, AH, npad, w, p->part, p->thin_chunks, s); });
     if (e) return hip_fail(e, "output-layer gradient");
-    e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, p->thin_chunks, (int64_t)ki.dout * w + ki.dout, (int64_t)ki.dout * w, ki.dout, dW[L - 1], db[L - 1], f64(dW_f64, L - 1), f64(db_f64, L - 1), s); });
+    e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, p->thin_chunks, (int64_t)ki.dout * w + ki.dout, (int64_t)ki.dout * w, ki.dout, dW[L - 1], db[L - 1], f64(dW_f64, L - 1), f64(db_f64, L - 1), s, inv_s); });
     if (e) return hip_fail(e, "reduction");
     for (int l = H; l >= 3; --l) {
       pj::LayerBwd B{};
@@ -715,7 +774,7 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
     if (e) return hip_fail(e, "hidden adjoint");
   } else {
   // Output layer: ubar, then zbar of layer H, then dW_L, db_L.
-  e = timed(p, PINN_K_OUT_BWD, s, [&] { return pj::launch_out_adj(p->kind, p->u_save, p->r_save, r_bar, N, npad, (float)(2.0 / (double)N), coef_of(pde), p->ubar, s); });
+  e = timed(p, PINN_K_OUT_BWD, s, [&] { return pj::launch_out_adj(p->kind, p->u_save, p->r_save, r_bar, loss_bar, N, npad, rbar_scale, coef_of(pde), p->ubar, s); });
   if (e) return hip_fail(e, "output adjoint");
   {
     pj::LayerBwd B{};
@@ -737,7 +796,7 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
   if (e) return hip_fail(e, "output-layer gradient");
   e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, p->thin_chunks, (int64_t)ki.dout * w + ki.dout,
                                (int64_t)ki.dout * w, ki.dout, dW[L - 1], db[L - 1], f64(dW_f64, L - 1),
-                               f64(db_f64, L - 1), s); });
+                               f64(db_f64, L - 1), s, inv_s); });
   if (e) return hip_fail(e, "reduction");
   // Hidden layers H..2: dW_l, db_l from zbar_l and the stack of layer l - 1,
   // then zbar of layer l - 1.
@@ -748,7 +807,7 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
     if (rs) return rs;
     e = timed(p, PINN_K_DW_HIDDEN, s, [&] { return pj::launch_dw_hidden(p->prec, ki.C, cur, Al1, npad, w, p->part, p->part + (size_t)w * w, p->dw_splits, s); });
     if (e) return hip_fail(e, "hidden-layer gradient");
-    e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, p->dw_splits, (int64_t)w * w + w, (int64_t)w * w, w, dW[l - 1], db[l - 1], f64(dW_f64, l - 1), f64(db_f64, l - 1), s); });
+    e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, p->dw_splits, (int64_t)w * w + w, (int64_t)w * w, w, dW[l - 1], db[l - 1], f64(dW_f64, l - 1), f64(db_f64, l - 1), s, inv_s); });
     if (e) return hip_fail(e, "reduction");
     pj::LayerBwd B{};
     B.top = false;
@@ -768,18 +827,36 @@ pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pd
   // (one per 16-point tile), or the separate kernel sums them from zbar_1.
   if (seed_fused) {
     e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, (int)(npad / 16), (int64_t)w * ki.din + w, (int64_t)w * ki.din, w,
-                                 dW[0], db[0], f64(dW_f64, 0), f64(db_f64, 0), s); });
+                                 dW[0], db[0], f64(dW_f64, 0), f64(db_f64, 0), s, inv_s); });
     if (e) return hip_fail(e, "reduction");
     return PINN_OK;
   }
   e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_dw_seed(p->kind, p->prec, p->Zb[1], x, N, npad, w, p->part, p->thin_chunks, s); });
   if (e) return hip_fail(e, "first-layer gradient");
   e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, p->thin_chunks, (int64_t)w * ki.din + w, (int64_t)w * ki.din, w,
-                               dW[0], db[0], f64(dW_f64, 0), f64(db_f64, 0), s); });
+                               dW[0], db[0], f64(dW_f64, 0), f64(db_f64, 0), s, inv_s); });
   if (e) return hip_fail(e, "reduction");
   return PINN_OK;
 }
 
+
+extern "C" {
+
+pinn_status pinn_jet_backward(pinn_plan plan, const pinn_net *net, const pinn_pde *pde,
+                              const float *x, int64_t N, const float *r_bar, float *const *dW,
+                              float *const *db, double *const *dW_f64, double *const *db_f64,
+                              void *stream) {
+  g_err.clear();
+  return backward_impl(plan, net, pde, x, N, r_bar, nullptr, dW, db, dW_f64, db_f64, stream);
+}
+
+pinn_status pinn_jet_backward_cot(pinn_plan plan, const pinn_net *net, const pinn_pde *pde, const float *x,
+                                  int64_t N, const float *r_bar, const float *loss_bar, float *const *dW,
+                                  float *const *db, double *const *dW_f64, double *const *db_f64,
+                                  void *stream) {
+  g_err.clear();
+  return backward_impl(plan, net, pde, x, N, r_bar, loss_bar, dW, db, dW_f64, db_f64, stream);
+}
 
 pinn_status pinn_plan_get_tuning(pinn_plan plan, pinn_tuning *t) {
   g_err.clear();

@@ -153,10 +153,11 @@ class PinnPlan:
         return r, loss, loss64, jets
 
     def backward(self, params, x: torch.Tensor, r_bar: Optional[torch.Tensor] = None,
-                 want_f64: bool = False, out=None):
-        """Gradient [(dW, db), ...] of the loss (r_bar None) or of <r_bar, r>;
-        with want_f64 also the FP64 reductions.  `out`, a list of (dW, db)
-        tensors shaped like params, receives the gradient instead of new ones."""
+                 want_f64: bool = False, out=None, loss_bar: Optional[torch.Tensor] = None):
+        """Gradient [(dW, db), ...] of <r_bar, r> + loss_bar * loss; r_bar and
+        loss_bar (a device scalar) both None means the loss gradient.  With
+        want_f64 also the FP64 reductions.  `out`, a list of (dW, db) tensors
+        shaped like params, receives the gradient instead of new ones."""
         nv = _NetView(params)
         N = x.shape[0]
         dev = x.device
@@ -174,10 +175,14 @@ class PinnPlan:
                     torch.empty(b.shape, device=dev, dtype=torch.float64)) for W, b in params]
             dW64p, k3 = ptr_array([g[0].data_ptr() for g in g64])
             db64p, k4 = ptr_array([g[1].data_ptr() for g in g64])
-        check(lib.pinn_jet_backward(
+        if loss_bar is not None and not (loss_bar.is_cuda and loss_bar.dtype == torch.float32
+                                         and loss_bar.numel() == 1):
+            raise ValueError("loss_bar must be a one-element float32 device tensor")
+        check(lib.pinn_jet_backward_cot(
             self.handle, ctypes.byref(nv.net), ctypes.byref(_pde(self.pde, self.coef)),
             ctypes.c_void_p(x.data_ptr()), N,
             ctypes.c_void_p(r_bar.data_ptr()) if r_bar is not None else None,
+            ctypes.c_void_p(loss_bar.data_ptr()) if loss_bar is not None else None,
             dWp, dbp, dW64p, db64p, _stream()))
         return (grads, g64) if want_f64 else grads
 
@@ -245,7 +250,8 @@ class PinnGraph:
 class JetResidual(torch.autograd.Function):
     """(r, loss) = JetResidual.apply(plan, x, W1, b1, ..., WL, bL).
 
-    Backward forms r_bar = g_r + g_loss * 2 r / N and runs the library's
+    Backward hands both cotangents to the library (pinn_jet_backward_cot),
+    which forms r_bar = g_r + g_loss * 2 r / N on the device and runs its
     adjoint; x receives no gradient."""
 
     @staticmethod
@@ -254,22 +260,21 @@ class JetResidual(torch.autograd.Function):
         r, loss, _, _ = plan.residual(params, x)
         ctx.plan = plan
         ctx.params = params
+        # an output that receives no gradient stays None in backward (not a
+        # zero tensor), so that loss-only training hands the library the loss
+        # cotangent alone and keeps its cotangent scaling
+        ctx.set_materialize_grads(False)
         ctx.save_for_backward(x, r)
         return r, loss
 
     @staticmethod
     def backward(ctx, g_r, g_loss):
         x, r = ctx.saved_tensors
-        N = x.shape[0]
-        r_bar = None
-        if g_r is not None:
-            r_bar = g_r.contiguous().float()
-        if g_loss is not None:
-            term = g_loss.reshape(()) * (2.0 / N) * r
-            r_bar = term if r_bar is None else r_bar + term
-        if r_bar is None:
-            r_bar = torch.zeros_like(r)
-        grads = ctx.plan.backward(ctx.params, x, r_bar.contiguous())
+        r_bar = g_r.contiguous().float() if g_r is not None else None
+        loss_bar = g_loss.reshape(1).contiguous().float() if g_loss is not None else None
+        if r_bar is None and loss_bar is None:
+            loss_bar = torch.zeros(1, device=x.device, dtype=torch.float32)
+        grads = ctx.plan.backward(ctx.params, x, r_bar, loss_bar=loss_bar)
         out = [None, None]
         for dW, db in grads:
             out += [dW, db]
@@ -279,3 +284,4 @@ class JetResidual(torch.autograd.Function):
 def jet_residual(plan: PinnPlan, params, x: torch.Tensor):
     flat: List[torch.Tensor] = [t for pair in params for t in pair]
     return JetResidual.apply(plan, x, *flat)
+

@@ -73,7 +73,7 @@ def test_batch_graph_replays_match_eager_and_single_plans(lib, prec):
         assert eager[0][i] == np.float32(ref_loss[i])
         assert np.array_equal(eager[1][i], ref_g[i]), i
     # against the oracle: FP32 at the FP32 bar; BF16 at its measured ceiling
-    # (rel. L2 up to ~0.1 for deep members, gradient cosine above 0.99)
+    # (rel. L2 up to 3.1e-3, margin 3)
     for i, m in enumerate(ens):
         ref = oracle.evaluate(m.params, m.x, pi.CHANNELS["burgers"], "burgers", (m.nu,))
         e = rel(eager[1][i], ref.grad)
@@ -82,7 +82,7 @@ def test_batch_graph_replays_match_eager_and_single_plans(lib, prec):
         if prec == "fp32":
             assert e <= 1e-5, (i, e)
         else:
-            assert e <= 0.2 and cos >= 0.99, (i, e, cos)
+            assert e <= 1e-2 and cos >= 0.9999, (i, e, cos)
     batch.close()
 
 
@@ -119,7 +119,7 @@ def test_plan_autotune_and_tuning_validation(lib):
     plan.residual(params, x)
     g = flat(plan.backward(params, x))
     ref = oracle.evaluate(prob.params, prob.x, prob.channels, "ns", prob.coef)
-    assert rel(g, ref.grad) <= 5e-2
+    assert rel(g, ref.grad) <= 1e-2
     with pytest.raises(PinnError):
         plan.set_tuning(0, 0)
     with pytest.raises(PinnError):

@@ -16,7 +16,13 @@ from tests.parity import cosine, flat, rel
 
 pytestmark = pytest.mark.gpu
 
-BAR = {"fp32": {"r": 1e-5, "grad": 1e-5}, "bf16": {"r": 2e-2, "grad": 5e-2}}
+# Measured ceilings over the 64 members, with margin.  BF16: dtheta 4.6e-3;
+# r up to 6.9e-2 on member 15 (w = 256, H = 5), from the BF16 rounding of the
+# stacks, which its derivative channels amplify.  FP32: dtheta 3.8e-7; r
+# 1.07e-5 on the same member: FP32 accumulation over K = 256 in the hidden
+# GEMMs (an FP64 emulation with FP32 products and sums gives 1.05e-5, with
+# FP64 sums 1.2e-6), so its bar is 2e-5 and every other FP32 bar stays 1e-5.
+BAR = {"fp32": {"r": 2e-5, "grad": 1e-5}, "bf16": {"r": 0.1, "grad": 1e-2}}
 CH = pi.CHANNELS["burgers"]
 
 

@@ -21,8 +21,10 @@ import pinn_inputs as pi
 pytestmark = pytest.mark.gpu
 
 FP32_TOL = 1e-5
-BF16 = {"r": 2e-2, "grad": 5e-2}
-FP16 = {"r": 5e-3, "grad": 1e-2}
+# measured ceilings with a margin of about 2 (BF16: r 7.3e-3, dtheta 2.9e-3;
+# FP16: r 1.3e-3, dtheta 9.5e-4)
+BF16 = {"r": 1.5e-2, "grad": 1e-2}
+FP16 = {"r": 3e-3, "grad": 5e-3}
 
 
 @pytest.fixture(scope="module")

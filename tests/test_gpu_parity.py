@@ -19,12 +19,13 @@ import pinn_inputs as pi
 pytestmark = pytest.mark.gpu
 
 FP32_TOL = 1e-5
-# measured-error ceilings of the 16-bit operand paths (relative L2)
-LOWP_TOL = {"bf16": {"r": 2e-2, "grad": 5e-2, "jets": 2e-2},
-            "fp16": {"r": 5e-3, "grad": 1e-2, "jets": 5e-3}}
-# the data term carries the value channel alone, a sum over the last layer
-# that cancels more than the derivative channels do (BF16 jets measured 2.7e-2)
-LOWP_JETS_KIND = {("burgers_bc", "bf16"): 5e-2, ("burgers_bc", "fp16"): 1e-2}
+# measured-error ceilings of the 16-bit operand paths (relative L2), with a
+# margin of about 2: BF16 measured r 7.3e-3, dtheta 3.1e-3, jets 1.4e-2;
+# FP16 r 1.3e-3, dtheta 2.1e-3, jets 2.8e-3 (BF16 hidden weights enter the
+# forward GEMMs as a hi + lo pair; the loss cotangent is scaled so that FP16
+# backward stacks stay in range)
+LOWP_TOL = {"bf16": {"r": 1.5e-2, "grad": 1e-2, "jets": 3e-2},
+            "fp16": {"r": 3e-3, "grad": 5e-3, "jets": 6e-3}}
 
 SMALL = {
     "burgers": dict(dims=[2, 32, 32, 32, 1], N=300),
@@ -117,8 +118,7 @@ def test_lowprec_parity(lib, pde, unsat, prec):
     cos = float(g["grad"] @ ref.grad / (np.linalg.norm(g["grad"]) * np.linalg.norm(ref.grad)))
     print(pde, prec, "unsat" if unsat else "", {k: f"{v:.2e}" for k, v in errs.items()}, f"cos {cos:.6f}")
     for k, v in errs.items():
-        tol = LOWP_JETS_KIND.get((pde, prec), LOWP_TOL[prec][k]) if k == "jets" else LOWP_TOL[prec][k]
-        assert v <= tol, (k, v)
+        assert v <= LOWP_TOL[prec][k], (k, v)
     assert cos > 0.99
 
 
@@ -329,13 +329,13 @@ def test_fused_and_separate_weight_gradients_agree(lib, pde, dims, prec):
         gs.append(flat(plan.backward(params, x)))
         plan.close()
     ref = oracle.evaluate(prob.params, prob.x, prob.channels, pde, prob.coef)
-    # BF16: the measured ceiling of deep Burgers networks (cf. the ensemble test)
-    tol = FP32_TOL if prec == "fp32" else 0.2
+    tol = FP32_TOL if prec == "fp32" else LOWP_TOL[prec]["grad"]
     for g in gs:
         cos = float(g @ ref.grad / (np.linalg.norm(g) * np.linalg.norm(ref.grad)))
         print(pde, prec, f"grad rel {rel(g, ref.grad):.2e} cos {cos:.6f}")
         assert rel(g, ref.grad) <= tol and cos > 0.99
-    assert rel(gs[0], gs[1]) <= (2e-6 if prec == "fp32" else 2e-2)
+    print(pde, prec, f"fused vs separate {rel(gs[0], gs[1]):.2e}")
+    assert rel(gs[0], gs[1]) <= (2e-6 if prec == "fp32" else 1e-2)
 
 
 @pytest.mark.parametrize("pde,dims", [("ns", [2, 128, 128, 128, 128, 3]), ("burgers", [2, 32, 32, 32, 32, 1]),
@@ -361,8 +361,9 @@ def test_fused_backward_many_tiles(lib, pde, dims):
     for g in gs:
         cos = float(g @ ref.grad / (np.linalg.norm(g) * np.linalg.norm(ref.grad)))
         print(pde, f"grad rel {rel(g, ref.grad):.2e} cos {cos:.6f}")
-        assert rel(g, ref.grad) <= 0.2 and cos > 0.99
-    assert rel(gs[0], gs[2]) <= 2e-2
+        assert rel(g, ref.grad) <= LOWP_TOL["bf16"]["grad"] and cos > 0.9999
+    print(pde, f"fused vs separate {rel(gs[0], gs[2]):.2e}")
+    assert rel(gs[0], gs[2]) <= 1e-2
 
 
 @pytest.mark.parametrize("pde,dims", [("ns", [2, 128, 128, 128, 128, 128, 3]), ("heat", [4, 64, 64, 64, 64, 1])])
@@ -420,7 +421,7 @@ def test_weighted_residual_and_data_loss(lib, prec):
     tol = FP32_TOL if prec == "fp32" else LOWP_TOL[prec]["grad"]
     print(prec, f"grad rel {rel(got, want):.2e} loss rel {abs(loss - want_loss) / want_loss:.2e}")
     assert rel(got, want) <= tol
-    assert abs(loss - want_loss) <= (FP32_TOL if prec == "fp32" else 2e-2) * want_loss
+    assert abs(loss - want_loss) <= (FP32_TOL if prec == "fp32" else 1e-3) * want_loss
     plan_r.close()
     plan_d.close()
 
@@ -458,3 +459,47 @@ def test_ks_coefficients_full_width(lib, coef, prec):
     print("ks full width", coef, prec, f"r {er:.2e} grad {eg:.2e}")
     assert er <= (FP32_TOL if prec == "fp32" else LOWP_TOL[prec]["r"])
     assert eg <= (FP32_TOL if prec == "fp32" else LOWP_TOL[prec]["grad"])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_loss_cotangent_scaling_is_exact(lib, prec):
+    """The loss gradient (cotangent 2 r / N scaled internally by a power of two)
+    equals the backward of the explicit, unscaled cotangent 2 r / N bit for
+    bit in FP32 and BF16: every backward step is linear in the cotangent and
+    power-of-two scaling adds no rounding."""
+    prob = pi.make_problem("ns", N=5000, seed=73, bias_std=0.3, dims=[2, 128, 128, 128, 3])
+    plan = lib.PinnPlan(prob.workload.dims, "ns", 5000, precision=prec, coef=prob.coef)
+    params = dev_params(prob.params)
+    x = torch.tensor(prob.x, device="cuda")
+    r, _, _, _ = plan.residual(params, x)
+    g_loss = flat(plan.backward(params, x))
+    g_expl = flat(plan.backward(params, x, r_bar=(2.0 / 5000) * r))
+    assert np.array_equal(g_loss, g_expl)
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_device_loss_cotangent(lib, prec):
+    """pinn_jet_backward_cot with a loss cotangent held in device memory (no r
+    cotangent): the gradient of lb * loss, against the oracle; and the
+    autograd function's loss-only backward, at a point count where unscaled
+    FP16 cotangents would fall below the normal range."""
+    N = 20000
+    prob = pi.make_problem("ns", N=N, seed=74, bias_std=0.3, dims=[2, 128, 128, 128, 3])
+    plan = lib.PinnPlan(prob.workload.dims, "ns", N, precision=prec, coef=prob.coef)
+    params = dev_params(prob.params, grad=True)
+    x = torch.tensor(prob.x, device="cuda")
+    ref = oracle.evaluate(prob.params, prob.x, prob.channels, "ns", prob.coef, want_jets=False)
+    lb = torch.tensor([0.37], device="cuda")
+    plan.residual(params, x)
+    g = flat(plan.backward(params, x, loss_bar=lb))
+    tol = FP32_TOL if prec == "fp32" else LOWP_TOL[prec]["grad"]
+    assert rel(g, 0.37 * ref.grad) <= tol
+    _, loss = lib.jet_residual(plan, params, x)
+    (2.0 * loss).backward()
+    torch.cuda.synchronize()
+    got = flat([(W.grad, b.grad) for W, b in params])
+    e = rel(got, 2.0 * ref.grad)
+    print(prec, f"autograd loss-only grad rel {e:.2e}")
+    assert e <= tol
+    plan.close()

@@ -27,10 +27,13 @@ from tests.parity import cosine, flat, rel, tile_err
 
 pytestmark = pytest.mark.gpu
 
-# largest per-tile error of r and of the jets (measured ceilings with margin)
-TILE_BAR = {"fp32": {"r": 1e-4, "jets": 1e-4}, "bf16": {"r": 0.25, "jets": 0.25}, "fp16": {"r": 0.05, "jets": 0.05}}
-# J^T r_bar of a single tile against the oracle (relative L2)
-ONE_TILE_BAR = {"fp32": 1e-5, "bf16": 5e-2, "fp16": 1e-2}
+# largest per-tile error of r and of the jets (measured ceilings 1.3e-6, 1.0e-2
+# and 1.7e-3, with a margin of about 2): a wrong or missing tile gives O(1)
+TILE_BAR = {"fp32": {"r": 1e-5, "jets": 1e-5}, "bf16": {"r": 2.5e-2, "jets": 2.5e-2},
+            "fp16": {"r": 4e-3, "jets": 4e-3}}
+# J^T r_bar of a single tile against the oracle (relative L2; measured 1.7e-6,
+# 1.6e-2 and 2.2e-3)
+ONE_TILE_BAR = {"fp32": 1e-5, "bf16": 3e-2, "fp16": 5e-3}
 # gradient additivity: FP32 accumulation order only
 ADD_BAR = 1e-5
 
