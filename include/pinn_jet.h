@@ -326,6 +326,33 @@ enum {
 pinn_status pinn_plan_profile(pinn_plan plan, int32_t kernel_class);
 pinn_status pinn_plan_profile_read(pinn_plan plan, double *total_ms, int64_t *launches);
 
+/* One residual + loss + loss-gradient step that allocates no device memory,
+ * for callers that cannot allocate: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  It computes what
+ * pinn_jet_residual (r, loss) followed by pinn_jet_backward with r_bar = NULL
+ * compute on a plan created for exactly N points with the default tuning, no
+ * save cap and no flags, with the same kernels: the results are bit for bit
+ * those of that plan.
+ *   net, pde, prec, x, N   as in pinn_plan_create and pinn_jet_residual
+ *   r, loss                as in pinn_jet_residual (either may be NULL)
+ *   dW, db                 as in pinn_jet_backward (required)
+ * Workspace: a static device array of PINN_NOALLOC_SCRATCH_BYTES (64 MiB)
+ * that every GPU the library runs on holds until the process ends; its
+ * device address is looked up once per device, on the first call made with
+ * that device current.  The workspace grows with N and with the network
+ * (about 10 KB per point for the 2-128x6-3 Navier-Stokes network, about
+ * 1 KB per point for 2-32x3-1 Burgers); PINN_ERR_CAP when it exceeds the
+ * array.  No part of the array has to start at zero: every workspace element
+ * a call reads is written earlier in the same call.  All calls on one GPU
+ * share its array, so calls that overlap on one GPU (from two host threads,
+ * or on two streams with no ordering between them) race and give wrong
+ * results; calls ordered on one stream are safe.  Stream-ordered and
+ * asynchronous like the other step calls. */
+#define PINN_NOALLOC_SCRATCH_BYTES (64u << 20)
+pinn_status pinn_jet_step_noalloc(const pinn_net *net, const pinn_pde *pde, int32_t prec, const float *x,
+                                  int64_t N, float *r, float *loss, float *const *dW, float *const *db,
+                                  void *stream);
+
 /* Message for the last non-OK status on this host thread ("" if none). */
 const char *pinn_last_error(void);
 

@@ -30,7 +30,7 @@ EXPORTS = ["pinn_plan_create", "pinn_plan_destroy", "pinn_plan_memory", "pinn_je
            "pinn_plan_set_tuning", "pinn_plan_autotune", "pinn_batch_create", "pinn_batch_destroy",
            "pinn_batch_configure", "pinn_batch_step", "pinn_batch_autotune", "pinn_graph_capture",
            "pinn_graph_launch", "pinn_graph_destroy", "pinn_adam_step", "pinn_graph_capture_train",
-           "pinn_jet_backward_cot"]
+           "pinn_jet_step_noalloc", "pinn_jet_backward_cot"]
 KERNEL_CLASSES = {"layer_fwd": 1, "layer_bwd": 2, "dw_hidden": 3, "out_fwd": 4, "out_bwd": 5,
                   "seed_fwd": 6, "other": 7, "bwd_dw": 8}
 
@@ -94,6 +94,7 @@ def _load():
                                    ctypes.POINTER(Adam), vp]
     lib.pinn_graph_capture_train.argtypes = [vp, NetP, PdeP, vp, i64, vp, vp, pp, pp, pp, pp, pp, pp,
                                              ctypes.POINTER(Adam), vp, pp]
+    lib.pinn_jet_step_noalloc.argtypes = [NetP, PdeP, i32, vp, i64, vp, vp, pp, pp, vp]
     lib.pinn_last_error.restype = ctypes.c_char_p
     lib.pinn_last_error.argtypes = []
     lib.pinn_pde_channels.argtypes = [i32]
@@ -103,7 +104,7 @@ def _load():
                  "pinn_plan_profile", "pinn_plan_profile_read", "pinn_plan_get_tuning", "pinn_plan_set_tuning",
                  "pinn_plan_autotune", "pinn_batch_create", "pinn_batch_destroy", "pinn_batch_configure",
                  "pinn_batch_step", "pinn_batch_autotune", "pinn_graph_capture", "pinn_graph_launch",
-                 "pinn_graph_destroy", "pinn_adam_step", "pinn_graph_capture_train",
+                 "pinn_graph_destroy", "pinn_adam_step", "pinn_graph_capture_train", "pinn_jet_step_noalloc",
                  "pinn_jet_backward_cot"):
         getattr(lib, name).restype = ctypes.c_int32
     return lib

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "plan_region.hpp"
 
 namespace {
 
@@ -563,6 +564,27 @@ static pinn_status plan_build(const pinn_net *net, const pinn_pde *pde, int64_t 
   return PINN_OK;
 }
 
+namespace pj_host {
+
+void set_error(const char *msg) { g_err = msg; }
+
+pinn_status plan_region_bytes(const pinn_net *net, const pinn_pde *pde, int64_t max_points, int32_t prec,
+                              size_t *bytes) {
+  pinn_plan p = nullptr;
+  pinn_status st = plan_build(net, pde, max_points, prec, 0, 0, nullptr, 0, true, &p);
+  if (st) return st;
+  *bytes = p->ws_bytes;
+  delete p;
+  return PINN_OK;
+}
+
+pinn_status plan_create_in_region(const pinn_net *net, const pinn_pde *pde, int64_t max_points, int32_t prec,
+                                  void *region, size_t region_bytes, pinn_plan *out) {
+  if (!region) return fail(PINN_ERR_ARG, "region is NULL");
+  return plan_build(net, pde, max_points, prec, 0, 0, static_cast<char *>(region), region_bytes, false, out);
+}
+
+}  // namespace pj_host
 
 extern "C" {
 

@@ -285,3 +285,28 @@ def jet_residual(plan: PinnPlan, params, x: torch.Tensor):
     flat: List[torch.Tensor] = [t for pair in params for t in pair]
     return JetResidual.apply(plan, x, *flat)
 
+
+def jet_step_noalloc(params, x: torch.Tensor, pde: str, coef: Optional[Sequence[float]] = None,
+                     precision: str = "fp32", r: Optional[torch.Tensor] = None,
+                     loss: Optional[torch.Tensor] = None, grads=None):
+    """One residual + loss + loss-gradient step through pinn_jet_step_noalloc
+    (no device allocation in the library; its workspace is a static device
+    array).  r (n_res, N), loss () and grads [(dW, db), ...] are created here
+    unless given; returns (r, loss, grads)."""
+    _check_tensor(x, "x")
+    nv = _NetView(params)
+    N = x.shape[0]
+    dev = x.device
+    coef = tuple(coef) if coef is not None else DEFAULT_COEF[pde]
+    if r is None:
+        r = torch.empty((RESIDUALS[pde], N), device=dev, dtype=torch.float32)
+    if loss is None:
+        loss = torch.empty((), device=dev, dtype=torch.float32)
+    if grads is None:
+        grads = [(torch.empty_like(W), torch.empty_like(b)) for W, b in params]
+    dWp, k1 = ptr_array([g[0].data_ptr() for g in grads])
+    dbp, k2 = ptr_array([g[1].data_ptr() for g in grads])
+    check(lib.pinn_jet_step_noalloc(ctypes.byref(nv.net), ctypes.byref(_pde(pde, coef)), PRECISIONS[precision],
+                                    ctypes.c_void_p(x.data_ptr()), N, ctypes.c_void_p(r.data_ptr()),
+                                    ctypes.c_void_p(loss.data_ptr()), dWp, dbp, _stream()))
+    return r, loss, grads
