@@ -47,6 +47,15 @@ def _load():
                                     ctypes.c_int, dp, ctypes.c_int, ip, ip, ctypes.c_int64, dp,
                                     dp, dp, dp, ctypes.c_int]
         lib.orc_eval_cs.restype = ctypes.c_int
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        seg_args = [ctypes.c_int, ip, i64p, i64p, dp, ip, ip, dp]
+        lib.orc_eval_segments.argtypes = ([ctypes.c_int, ip, dp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, ip,
+                                           ip, ctypes.c_int64, dp] + seg_args + [dp, dp, dp, ctypes.c_int])
+        lib.orc_eval_segments.restype = ctypes.c_int
+        lib.orc_eval_segments_cs.argtypes = ([ctypes.c_int, ip, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                              dp, ctypes.c_int, ip, ip, ctypes.c_int64, dp] + seg_args +
+                                             [dp, ctypes.c_int])
+        lib.orc_eval_segments_cs.restype = ctypes.c_int
         lib.orc_adam.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_double]
         lib.orc_adam.restype = ctypes.c_int
@@ -163,6 +172,68 @@ def complex_step(params, delta: np.ndarray, x, channels, pde: str = "none",
     if st != 0:
         raise ValueError(f"orc_eval_cs failed with status {st}")
     return djets, dr, None if dloss is None else float(dloss[0])
+
+
+SEG = {"pde": 0, "dirichlet": 1, "periodic": 2}
+DATA = {"zero": 0, "const": 1, "sin": 2}
+
+
+def _segments(segments):
+    """[{'type', 'begin', 'count', 'weight', 'mask', 'data', 'param'}, ...] -> ctypes arrays."""
+    n = len(segments)
+    typ = np.ascontiguousarray([SEG[s["type"]] for s in segments], dtype=np.int32)
+    beg = np.ascontiguousarray([s["begin"] for s in segments], dtype=np.int64)
+    cnt = np.ascontiguousarray([s["count"] for s in segments], dtype=np.int64)
+    wt = np.ascontiguousarray([s.get("weight", 1.0) for s in segments], dtype=np.float64)
+    mask = np.ascontiguousarray([s.get("mask", 0) for s in segments], dtype=np.int32)
+    data = np.ascontiguousarray([DATA[s.get("data", "zero")] for s in segments], dtype=np.int32)
+    par = np.zeros((n, 4))
+    for i, s in enumerate(segments):
+        p = s.get("param", ())
+        par[i, :len(p)] = p
+    par = np.ascontiguousarray(par)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    arrays = (typ, beg, cnt, wt, mask, data, par)
+    args = [n, _ip(typ), beg.ctypes.data_as(i64p), cnt.ctypes.data_as(i64p), _dp(wt), _ip(mask), _ip(data), _dp(par)]
+    return args, arrays
+
+
+def evaluate_segments(params, x, channels, pde: str, coef: Sequence[float], segments, act: str = "tanh",
+                      want_grad: bool = True, threads: int = 0):
+    """Composite loss over point segments (all points evaluated together, then
+    split): returns (seg_loss (n_seg,), loss, grad packed like theta or None)."""
+    lib = _load()
+    dims, ch_dir, ch_ord, cf = _common(params, channels, coef)
+    theta = pack_theta(params)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    sargs, keep = _segments(segments)
+    seg_loss = np.zeros(len(segments))
+    loss = np.zeros(1)
+    grad = np.zeros(theta.size) if want_grad else None
+    st = lib.orc_eval_segments(len(dims) - 1, _ip(dims), _dp(theta), ACT[act], PDE[pde], _dp(cf), len(ch_dir),
+                               _ip(ch_dir), _ip(ch_ord), xx.shape[0], _dp(xx), *sargs, _dp(seg_loss), _dp(loss),
+                               _dp(grad), int(threads))
+    if st != 0:
+        raise ValueError(f"orc_eval_segments failed with status {st}")
+    return seg_loss, float(loss[0]), grad
+
+
+def complex_step_segments(params, delta, x, channels, pde: str, coef: Sequence[float], segments,
+                          act: str = "tanh", h: float = 1e-30, threads: int = 0) -> float:
+    """Directional derivative of the composite loss along delta (complex step)."""
+    lib = _load()
+    dims, ch_dir, ch_ord, cf = _common(params, channels, coef)
+    theta = pack_theta(params)
+    dl = np.ascontiguousarray(delta, dtype=np.float64)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    sargs, keep = _segments(segments)
+    out = np.zeros(1)
+    st = lib.orc_eval_segments_cs(len(dims) - 1, _ip(dims), _dp(theta), _dp(dl), float(h), ACT[act], PDE[pde],
+                                  _dp(cf), len(ch_dir), _ip(ch_dir), _ip(ch_ord), xx.shape[0], _dp(xx), *sargs,
+                                  _dp(out), int(threads))
+    if st != 0:
+        raise ValueError(f"orc_eval_segments_cs failed with status {st}")
+    return float(out[0])
 
 
 def adam_step(theta: np.ndarray, g: np.ndarray, m: np.ndarray, v: np.ndarray, step: int,

@@ -20,6 +20,7 @@
 
 #include <cmath>
 #include <complex>
+#include <type_traits>
 #include <vector>
 #include <omp.h>
 
@@ -577,6 +578,206 @@ extern "C" int orc_eval(int n_layers, const int *dims, const double *theta, int 
     for (int64_t ch = 0; ch < n_chunks; ++ch)
       for (int64_t q = 0; q < nv.n_theta; ++q) grad[q] += chunk_grad[ch][q];
   }
+  return 0;
+}
+
+namespace {
+
+/* The segments of a composite loss, checked against the point set. */
+struct Segments {
+  int n;
+  const int *type;
+  const int64_t *begin, *count;
+  const double *weight;
+  const int *mask, *data;
+  const double *param;
+};
+
+int check_segments(const Segments &S, int64_t N, int C, int d_out, int n_res) {
+  if (S.n < 1 || !S.type || !S.begin || !S.count || !S.weight || !S.mask || !S.data || !S.param) return -1;
+  std::vector<char> used((size_t)N, 0);
+  for (int s = 0; s < S.n; ++s) {
+    const int64_t b = S.begin[s], c = S.count[s];
+    if (b < 0 || c < 1 || b + c > N) return -1;
+    switch (S.type[s]) {
+      case ORC_SEG_PDE:
+        if (n_res == 0) return -1;
+        break;
+      case ORC_SEG_DIRICHLET:
+        if (S.data[s] < ORC_DATA_ZERO || S.data[s] > ORC_DATA_SIN) return -1;
+        for (int q = 0; q < d_out * C; ++q)
+          if ((S.mask[s] >> q & 1) && q % C != 0) return -1; /* values only */
+        if (S.mask[s] == 0 || (S.mask[s] >> (d_out * C)) != 0) return -1;
+        break;
+      case ORC_SEG_PERIODIC:
+        if (c % 2 != 0 || S.mask[s] == 0 || (S.mask[s] >> (d_out * C)) != 0) return -1;
+        break;
+      default: return -1;
+    }
+    for (int64_t n = b; n < b + c; ++n) {
+      if (used[n]) return -1; /* overlapping segments */
+      used[n] = 1;
+    }
+  }
+  return 0;
+}
+
+/* Boundary or initial data g_o(x) of a Dirichlet segment. */
+double seg_data_value(int data, const double *param, int o, const double *xp) {
+  const double pi = 3.14159265358979323846;
+  switch (data) {
+    case ORC_DATA_CONST: return param[o];
+    case ORC_DATA_SIN: return param[0] * std::sin(param[1] * pi * xp[0]);
+    default: return 0.0;
+  }
+}
+
+/* Loss terms from the outputs of all points (u[n] = d_out x C, channel-major
+ * as in forward_point's last layer); with ubar, also d loss / d u per point. */
+template <class T>
+void segment_loss(const Segments &S, int pde_kind, const double *coef, const PdeChannels &pc, int C, int d_out,
+                  int n_res, const double *x, int d, const std::vector<std::vector<T>> &u, T *seg_loss, T *loss,
+                  std::vector<std::vector<double>> *ubar) {
+  auto U = [&](int64_t n, int o, int c) { return u[n][(size_t)c * d_out + o]; };
+  T total = T(0);
+  std::vector<T> rr(n_res > 0 ? n_res : 1);
+  std::vector<double> rb(n_res > 0 ? n_res : 1), ub((size_t)C * d_out);
+  for (int s = 0; s < S.n; ++s) {
+    const int64_t b = S.begin[s], cnt = S.count[s];
+    const double w = S.weight[s];
+    T acc = T(0);
+    if (S.type[s] == ORC_SEG_PDE) {
+      for (int64_t n = b; n < b + cnt; ++n) {
+        residual_point(pde_kind, coef, pc, x + n * d, u[n], C, rr.data());
+        for (int k = 0; k < n_res; ++k) acc += rr[k] * rr[k];
+        if (ubar) { /* d (w / cnt sum r^2) / d u = the residual adjoint with rbar = 2 w r / cnt */
+          for (int k = 0; k < n_res; ++k) rb[k] = 2.0 * w * std::real(rr[k]) / (double)cnt;
+          std::vector<double> ur((size_t)C * d_out);
+          for (size_t q = 0; q < ur.size(); ++q) ur[q] = std::real(u[n][q]);
+          residual_adjoint_point(pde_kind, coef, pc, ur, C, rb.data(), ub);
+          for (size_t q = 0; q < ub.size(); ++q) (*ubar)[n][q] += ub[q];
+        }
+      }
+      acc = acc / (double)cnt;
+    } else if (S.type[s] == ORC_SEG_DIRICHLET) {
+      for (int64_t n = b; n < b + cnt; ++n)
+        for (int o = 0; o < d_out; ++o) {
+          if (!(S.mask[s] >> (o * C) & 1)) continue;
+          const T r = U(n, o, 0) - seg_data_value(S.data[s], S.param + 4 * s, o, x + n * d);
+          acc += r * r;
+          if (ubar) (*ubar)[n][(size_t)0 * d_out + o] += 2.0 * w * std::real(r) / (double)cnt;
+        }
+      acc = acc / (double)cnt;
+    } else { /* periodic pairs */
+      const int64_t pairs = cnt / 2;
+      for (int64_t k = 0; k < pairs; ++k) {
+        const int64_t na = b + 2 * k, nb = na + 1;
+        for (int o = 0; o < d_out; ++o)
+          for (int c = 0; c < C; ++c) {
+            if (!(S.mask[s] >> (o * C + c) & 1)) continue;
+            const T r = U(na, o, c) - U(nb, o, c);
+            acc += r * r;
+            if (ubar) {
+              const double g = 2.0 * w * std::real(r) / (double)pairs;
+              (*ubar)[na][(size_t)c * d_out + o] += g;
+              (*ubar)[nb][(size_t)c * d_out + o] -= g;
+            }
+          }
+      }
+      acc = acc / (double)pairs;
+    }
+    if (seg_loss) seg_loss[s] = acc;
+    total += w * acc;
+  }
+  if (loss) *loss = total;
+}
+
+template <class T>
+int eval_segments(int n_layers, const int *dims, const T *theta, int act, int pde_kind, const double *coef,
+                  int n_ch, const int *ch_dir, const int *ch_ord, int64_t N, const double *x, const Segments &S,
+                  T *seg_loss, T *loss, double *grad, int n_threads) {
+  Problem P;
+  int st = setup(n_layers, dims, act, pde_kind, n_ch, ch_dir, ch_ord, N, &P);
+  if (st) return st;
+  if (!theta || N < 1 || !x) return -1;
+  const NetView &nv = P.nv;
+  const int C = P.cs.C, d = dims[0], d_out = dims[n_layers];
+  if (check_segments(S, N, C, d_out, P.n_res)) return -1;
+  /* 1. the network and its partial jet at every point, all segments together */
+  std::vector<std::vector<T>> u((size_t)N);
+#pragma omp parallel num_threads(n_threads_or_default(n_threads))
+  {
+    PointWork<T> pw;
+    pw.init(nv, C);
+#pragma omp for schedule(dynamic, 64)
+    for (int64_t n = 0; n < N; ++n) {
+      forward_point(nv, theta, P.cs, act, x + n * d, pw);
+      u[n] = pw.z[nv.L - 1];
+    }
+  }
+  /* 2. split: each segment's terms and the weighted loss; d loss / d u */
+  std::vector<std::vector<double>> ubar;
+  if (grad) ubar.assign((size_t)N, std::vector<double>((size_t)C * d_out, 0.0));
+  segment_loss<T>(S, pde_kind, coef, P.pc, C, d_out, P.n_res, x, d, u, seg_loss, loss, grad ? &ubar : nullptr);
+  if constexpr (!std::is_same<T, double>::value) return 0; /* complex step: the loss only */
+  if (!grad) return 0;
+  /* 3. reverse mode, point by point from its cotangent, summed in chunk order */
+  const int64_t n_chunks = (N + kChunk - 1) / kChunk;
+  std::vector<std::vector<double>> chunk_grad((size_t)n_chunks);
+#pragma omp parallel num_threads(n_threads_or_default(n_threads))
+  {
+    PointWork<double> pw;
+    pw.init(nv, C);
+    std::vector<double> zbar;
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t ch = 0; ch < n_chunks; ++ch) {
+      chunk_grad[ch].assign(nv.n_theta, 0.0);
+      const int64_t n_end = std::min<int64_t>(N, (ch + 1) * kChunk);
+      for (int64_t n = ch * kChunk; n < n_end; ++n) {
+        bool any = false;
+        for (double v : ubar[n]) any = any || v != 0.0;
+        if (!any) continue;
+        forward_point(nv, (const double *)theta, P.cs, act, x + n * d, pw);
+        zbar = ubar[n];
+        backward_point(nv, (const double *)theta, P.cs, act, pw, zbar, chunk_grad[ch].data());
+      }
+    }
+  }
+  for (int64_t q = 0; q < nv.n_theta; ++q) grad[q] = 0.0;
+  for (int64_t ch = 0; ch < n_chunks; ++ch)
+    for (int64_t q = 0; q < nv.n_theta; ++q) grad[q] += chunk_grad[ch][q];
+  return 0;
+}
+
+} /* namespace */
+
+extern "C" int orc_eval_segments(int n_layers, const int *dims, const double *theta, int act, int pde_kind,
+                                 const double *coef, int n_ch, const int *ch_dir, const int *ch_ord, int64_t N,
+                                 const double *x, int n_seg, const int *seg_type, const int64_t *seg_begin,
+                                 const int64_t *seg_count, const double *seg_weight, const int *seg_mask,
+                                 const int *seg_data, const double *seg_param, double *seg_loss, double *loss,
+                                 double *grad, int n_threads) {
+  const Segments S{n_seg, seg_type, seg_begin, seg_count, seg_weight, seg_mask, seg_data, seg_param};
+  return eval_segments<double>(n_layers, dims, theta, act, pde_kind, coef, n_ch, ch_dir, ch_ord, N, x, S,
+                               seg_loss, loss, grad, n_threads);
+}
+
+extern "C" int orc_eval_segments_cs(int n_layers, const int *dims, const double *theta, const double *delta,
+                                    double h, int act, int pde_kind, const double *coef, int n_ch,
+                                    const int *ch_dir, const int *ch_ord, int64_t N, const double *x, int n_seg,
+                                    const int *seg_type, const int64_t *seg_begin, const int64_t *seg_count,
+                                    const double *seg_weight, const int *seg_mask, const int *seg_data,
+                                    const double *seg_param, double *dloss, int n_threads) {
+  if (!theta || !delta || !(h > 0.0) || !dloss || n_layers < 1 || !dims) return -1;
+  const Segments S{n_seg, seg_type, seg_begin, seg_count, seg_weight, seg_mask, seg_data, seg_param};
+  const NetView nv = make_view(n_layers, dims);
+  std::vector<cplx> th((size_t)nv.n_theta);
+  for (int64_t q = 0; q < nv.n_theta; ++q) th[q] = cplx(theta[q], h * delta[q]);
+  cplx l(0.0, 0.0);
+  const int st = eval_segments<cplx>(n_layers, dims, th.data(), act, pde_kind, coef, n_ch, ch_dir, ch_ord, N, x,
+                                     S, nullptr, &l, nullptr, n_threads);
+  if (st) return st;
+  *dloss = l.imag() / h;
   return 0;
 }
 

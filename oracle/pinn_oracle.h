@@ -82,6 +82,39 @@ int orc_eval_cs(int n_layers, const int *dims, const double *theta,
                 int64_t N, const double *x,
                 double *djets, double *dr, double *dloss, int n_threads);
 
+/* Composite training loss over segments of one point set (Sec. 3.1.1: the
+ * initial-condition, boundary and PDE points are concatenated, the network is
+ * evaluated once on all of them, and the outputs are split to assemble the
+ * loss terms).  Segment s covers points [begin[s], begin[s] + count[s]) and
+ * contributes weight[s] * seg_loss[s] to the loss, with seg_loss[s] the mean
+ * over its units (points, or point pairs) of the sum of its squared residuals:
+ *   ORC_SEG_PDE        the PDE residual of pde_kind at each point
+ *   ORC_SEG_DIRICHLET  u_o - g_o(x) at each point for every output o whose
+ *                      value bit (o * C) is set in mask[s]; g_o by data[s]:
+ *                      ORC_DATA_ZERO 0, ORC_DATA_CONST param[s][o],
+ *                      ORC_DATA_SIN param[s][0] sin(param[s][1] pi x_0)
+ *   ORC_SEG_PERIODIC   point pairs (begin + 2k, begin + 2k + 1), count even:
+ *                      u_oc(first) - u_oc(second) for every (o, c) whose bit
+ *                      o * C + c is set in mask[s]
+ * Segments must not overlap.  grad (may be NULL) receives d loss / d theta.
+ * seg_loss has n_seg entries; loss and seg_loss may be NULL. */
+enum { ORC_SEG_PDE = 0, ORC_SEG_DIRICHLET = 1, ORC_SEG_PERIODIC = 2 };
+enum { ORC_DATA_ZERO = 0, ORC_DATA_CONST = 1, ORC_DATA_SIN = 2 };
+int orc_eval_segments(int n_layers, const int *dims, const double *theta, int act, int pde_kind,
+                      const double *coef, int n_ch, const int *ch_dir, const int *ch_ord, int64_t N,
+                      const double *x, int n_seg, const int *seg_type, const int64_t *seg_begin,
+                      const int64_t *seg_count, const double *seg_weight, const int *seg_mask,
+                      const int *seg_data, const double *seg_param, double *seg_loss, double *loss,
+                      double *grad, int n_threads);
+
+/* Complex-step directional derivative of that loss along delta (theta space). */
+int orc_eval_segments_cs(int n_layers, const int *dims, const double *theta, const double *delta, double h,
+                         int act, int pde_kind, const double *coef, int n_ch, const int *ch_dir,
+                         const int *ch_ord, int64_t N, const double *x, int n_seg, const int *seg_type,
+                         const int64_t *seg_begin, const int64_t *seg_count, const double *seg_weight,
+                         const int *seg_mask, const int *seg_data, const double *seg_param, double *dloss,
+                         int n_threads);
+
 /* One Adam step (Kingma & Ba, Algorithm 1; the optimizer of the paper's
  * training runs, Sec. 3.1) on n parameters, in place:
  *   m <- b1 m + (1 - b1) g;   v <- b2 v + (1 - b2) g^2

@@ -175,3 +175,76 @@ def make_ensemble(n_nets: int = 64, seed: int = 0, widths=(32, 64, 128, 256), de
         x = uniform_points(N, dom, rng) if with_points else None
         out.append(EnsembleMember(w, H, nu, N, params, x))
     return out
+
+
+# ---------------------------------------------------------------- training sets
+# The paper's complete training runs (Sec. 3.1.1) use an all-points layout: the
+# initial-condition, boundary and PDE points are concatenated, evaluated once
+# and split afterwards.  A training set is the concatenated points plus the
+# list of loss segments over them (the library's segment records: type, begin,
+# count, weight, mask, data, param).  Counts default to the paper's; tests pass
+# smaller ones.  The paper does not print the Burgers initial profile or the
+# term weights; the defaults here are the readings stated with each function.
+
+@dataclass
+class TrainingSet:
+    name: str
+    dims: List[int]
+    coef: Tuple[float, ...]
+    x: np.ndarray          # (N, d) float32, segments in order
+    segments: list
+    params: list
+
+
+def burgers_segments(n_pde: int, n_ic: int, n_pairs: int, w_ic: float = 10.0, w_pde: float = 1.0,
+                     w_per: float = 1.0):
+    """PDE points, initial points (u(x, 0) = -sin(2 pi x)), then periodic pairs
+    (x = 0 and x = 1 at one t) comparing u (channel 0) and u_x (channel 2 of
+    the Burgers channel set)."""
+    return [dict(type="pde", begin=0, count=n_pde, weight=w_pde),
+            dict(type="dirichlet", begin=n_pde, count=n_ic, weight=w_ic, mask=1, data="sin", param=(-1.0, 2.0)),
+            dict(type="periodic", begin=n_pde + n_ic, count=2 * n_pairs, weight=w_per, mask=(1 << 0) | (1 << 2))]
+
+
+def cavity_segments(n_pde: int, n_wall: int, n_lid: int, C: int = 5, w_wall: float = 1.0, w_lid: float = 1.0,
+                    w_pde: float = 1.0):
+    """PDE points, no-slip wall points (u = v = 0), lid points (u = 1, v = 0)."""
+    uv = (1 << 0) | (1 << C)
+    return [dict(type="pde", begin=0, count=n_pde, weight=w_pde),
+            dict(type="dirichlet", begin=n_pde, count=n_wall, weight=w_wall, mask=uv, data="zero"),
+            dict(type="dirichlet", begin=n_pde + n_wall, count=n_lid, weight=w_lid, mask=uv, data="const",
+                 param=(1.0, 0.0))]
+
+
+def burgers_training_set(seed: int = 0, n_pde: int = 10000, n_ic: int = 101, n_pairs: int = 1000,
+                         width: int = 64, hidden: int = 6, bias_std: float = 0.0, **weights) -> TrainingSet:
+    """Viscous Burgers on (x, t) in [0, 1]^2, nu = 0.01: PDE points uniform,
+    initial points on t = 0 at evenly spaced x, periodic time samples uniform
+    on [0, 1] with each sample giving the pair (0, t), (1, t)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dims = _mlp(2, width, hidden, 1)
+    params = xavier_params(dims, rng, bias_std)
+    pde = rng.random((n_pde, 2))
+    ic = np.stack([np.linspace(0.0, 1.0, n_ic), np.zeros(n_ic)], 1)
+    t = rng.random(n_pairs)
+    pairs = np.stack([np.tile([0.0, 1.0], n_pairs), np.repeat(t, 2)], 1)
+    x = np.concatenate([pde, ic, pairs]).astype(np.float32)
+    return TrainingSet("burgers", dims, (0.01,), x, burgers_segments(n_pde, n_ic, n_pairs, **weights), params)
+
+
+def cavity_training_set(seed: int = 0, n_pde: int = 10000, n_wall: int = 1499, n_lid: int = 499,
+                        width: int = 64, hidden: int = 6, bias_std: float = 0.0, **weights) -> TrainingSet:
+    """Lid-driven cavity on the unit square at Re = 100: PDE points uniform,
+    wall points spread over the left, right and bottom sides by arc length,
+    lid points uniform on y = 1."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dims = _mlp(2, width, hidden, 3)
+    params = xavier_params(dims, rng, bias_std)
+    pde = rng.random((n_pde, 2))
+    s = 3.0 * rng.random(n_wall)  # arc length along left (0..1), bottom (1..2), right (2..3)
+    wall = np.where((s < 1.0)[:, None], np.stack([np.zeros(n_wall), s], 1),
+                    np.where((s < 2.0)[:, None], np.stack([s - 1.0, np.zeros(n_wall)], 1),
+                             np.stack([np.ones(n_wall), s - 2.0], 1)))
+    lid = np.stack([rng.random(n_lid), np.ones(n_lid)], 1)
+    x = np.concatenate([pde, wall, lid]).astype(np.float32)
+    return TrainingSet("ns", dims, (100.0,), x, cavity_segments(n_pde, n_wall, n_lid, **weights), params)

@@ -96,3 +96,55 @@ def evaluate(params, x, channels, pde, coef, act=torch.tanh):
     R = np.stack([r.detach().numpy() for r in rs])
     G = np.concatenate([g.detach().numpy().reshape(-1) for g in grads])
     return J, R, float(loss.detach()), G
+
+
+def evaluate_segments(params, x, channels, pde, coef, segments, act=torch.tanh):
+    """The composite loss of Sec. 3.1.1 written with nested autograd in FP64:
+    all points through the network at once, outputs split by segment; each
+    segment's mean of squared terms times its weight.  Returns (seg_losses,
+    loss, grad packed W, b per layer)."""
+    p64 = torch_params(params)
+    jets, X = nested_jets(p64, x, channels, act)
+    idx = {ch: c for c, ch in enumerate(channels)}
+    d_out = params[-1][0].shape[0]
+    C = len(channels)
+    terms = []
+    for s in segments:
+        b, n = s["begin"], s["count"]
+        sl = slice(b, b + n)
+        if s["type"] == "pde":
+            rs = residuals(pde, {k: v[sl] for k, v in jets.items()}, channels, X[sl], coef)
+            t = sum((r * r).sum() for r in rs) / n
+        elif s["type"] == "dirichlet":
+            par = list(s.get("param", ())) + [0.0] * 4
+            xs = X.detach()[sl, 0]
+            t = 0.0
+            for o in range(d_out):
+                if not (s["mask"] >> (o * C)) & 1:
+                    continue
+                if s.get("data", "zero") == "const":
+                    g = torch.full_like(xs, par[o])
+                elif s.get("data", "zero") == "sin":
+                    g = par[0] * torch.sin(par[1] * math.pi * xs)
+                else:
+                    g = torch.zeros_like(xs)
+                r = jets[(o, idx[(0, 0)])][sl] - g
+                t = t + (r * r).sum()
+            t = t / n
+        else:  # periodic pairs: first minus second of each consecutive pair
+            t = 0.0
+            for o in range(d_out):
+                for c in range(C):
+                    if not (s["mask"] >> (o * C + c)) & 1:
+                        continue
+                    v = jets[(o, c)][sl]
+                    r = v[0::2] - v[1::2]
+                    t = t + (r * r).sum()
+            t = t / (n // 2)
+        terms.append(t)
+    loss = sum(s.get("weight", 1.0) * t for s, t in zip(segments, terms))
+    leaves = [t for pair in p64 for t in pair]
+    grads = torch.autograd.grad(loss, leaves, allow_unused=True)
+    grads = [torch.zeros_like(t) if g is None else g for g, t in zip(grads, leaves)]
+    G = np.concatenate([g.detach().numpy().reshape(-1) for g in grads])
+    return np.array([float(t.detach()) for t in terms]), float(loss.detach()), G

@@ -507,3 +507,100 @@ def test_ks_coefficients_taylor_slope_two(coef):
                                 want_grad=False).loss - res.loss - h * gd) for h in hs]
     slopes = [math.log(errs[i] / errs[i + 1]) / math.log(2.0) for i in range(len(errs) - 1)]
     assert all(1.8 < s < 2.2 for s in slopes[1:]), slopes
+
+
+# ---------------------------------------------------------------- composite training loss (Sec. 3.1.1)
+def burgers_paper_segments(n_pde, n_ic, n_pairs):
+    """Every weight differs from 1 so that a weight dropped anywhere shows."""
+    return pi.burgers_segments(n_pde, n_ic, n_pairs, w_ic=10.0, w_pde=0.7, w_per=1.3)
+
+
+def ns_cavity_segments(n_pde, n_wall, n_lid):
+    return pi.cavity_segments(n_pde, n_wall, n_lid, C=len(pi.CHANNELS["ns"]), w_wall=2.0, w_lid=3.0, w_pde=0.6)
+
+
+def _segment_problem(kind, seed):
+    rng = np.random.default_rng(seed)
+    if kind == "burgers":
+        dims = [2, 10, 10, 10, 1]
+        params = rand_params(dims, seed)
+        n_pde, n_ic, n_pairs = 40, 12, 10
+        x = np.concatenate([np.stack([rng.uniform(0, 1, n_pde), rng.uniform(0, 1, n_pde)], 1),
+                            np.stack([rng.uniform(0, 1, n_ic), np.zeros(n_ic)], 1),
+                            np.stack([np.tile([0.0, 1.0], n_pairs), np.repeat(rng.uniform(0, 1, n_pairs), 2)], 1)])
+        return params, x, pi.CHANNELS["burgers"], (0.01,), burgers_paper_segments(n_pde, n_ic, n_pairs)
+    dims = [2, 10, 10, 10, 3]
+    params = rand_params(dims, seed)
+    n_pde, n_wall, n_lid = 40, 15, 9
+    wall = np.stack([rng.choice([0.0, 1.0], n_wall), rng.uniform(0, 1, n_wall)], 1)
+    lid = np.stack([rng.uniform(0, 1, n_lid), np.ones(n_lid)], 1)
+    x = np.concatenate([rng.uniform(0, 1, (n_pde, 2)), wall, lid])
+    return params, x, pi.CHANNELS["ns"], (100.0,), ns_cavity_segments(n_pde, n_wall, n_lid)
+
+
+@pytest.mark.parametrize("kind", ["burgers", "ns"])
+def test_composite_loss_against_nested_autograd(kind):
+    """Segment losses, the weighted loss and its gradient against the composite
+    loss written with nested torch.autograd in FP64."""
+    params, x, ch, coef, segs = _segment_problem(kind, 71)
+    sl, L, g = oracle.evaluate_segments(params, x, ch, kind, coef, segs)
+    sl_ref, L_ref, g_ref = autograd_ref.evaluate_segments(params, x, ch, kind, coef, segs)
+    assert np.allclose(sl, sl_ref, rtol=1e-12, atol=0)
+    assert abs(L - L_ref) <= 1e-12 * abs(L_ref)
+    assert rel(g, g_ref) < 1e-11
+
+
+@pytest.mark.parametrize("kind", ["burgers", "ns"])
+def test_composite_loss_complex_step_and_taylor(kind):
+    params, x, ch, coef, segs = _segment_problem(kind, 72)
+    _, L, g = oracle.evaluate_segments(params, x, ch, kind, coef, segs)
+    delta = np.random.default_rng(73).normal(size=g.size)
+    dl = oracle.complex_step_segments(params, delta, x, ch, kind, coef, segs)
+    assert abs(g @ delta - dl) <= 1e-12 * abs(dl)
+    theta = oracle.pack_theta(params)
+    dims = oracle.dims_of(params)
+    delta /= np.linalg.norm(delta)
+    hs = [1e-2 / 2 ** k for k in range(5)]
+    errs = [abs(oracle.evaluate_segments(oracle.unpack_theta(theta + h * delta, dims), x, ch, kind, coef, segs,
+                                         want_grad=False)[1] - L - h * (g @ delta)) for h in hs]
+    slopes = [math.log(errs[i] / errs[i + 1]) / math.log(2.0) for i in range(len(errs) - 1)]
+    assert all(1.8 < s < 2.2 for s in slopes), slopes
+
+
+def test_single_pde_segment_is_the_plain_loss():
+    """One PDE segment over every point is the residual-only loss of evaluate()."""
+    prob = small_problem("ns", seed=74)
+    N = prob.x.shape[0]
+    sl, L, g = oracle.evaluate_segments(prob.params, prob.x, prob.channels, "ns", prob.coef,
+                                        [dict(type="pde", begin=0, count=N)])
+    ref = oracle.evaluate(prob.params, prob.x, prob.channels, "ns", prob.coef)
+    assert abs(L - ref.loss) <= 1e-14 * ref.loss and abs(sl[0] - ref.loss) <= 1e-14 * ref.loss
+    assert rel(g, ref.grad) < 1e-14
+
+
+def test_data_and_periodic_terms_by_hand():
+    """The Dirichlet and periodic terms of a plain MLP evaluation (numpy), with
+    u_x of the periodic pairs from the oracle's own forward pass checked by
+    central differences."""
+    params, x, ch, coef, segs = _segment_problem("burgers", 75)
+    sl, _, _ = oracle.evaluate_segments(params, x, ch, "burgers", coef, segs, want_grad=False)
+
+    def mlp(X):
+        h = X
+        for l, (W, b) in enumerate(params):
+            h = h @ np.asarray(W).T + b
+            if l < len(params) - 1:
+                h = np.tanh(h)
+        return h[:, 0]
+
+    ic = segs[1]
+    xi = x[ic["begin"]:ic["begin"] + ic["count"]]
+    want_ic = np.mean((mlp(xi) + np.sin(2 * np.pi * xi[:, 0])) ** 2)
+    assert abs(sl[1] - want_ic) <= 1e-13 * want_ic
+    pr = segs[2]
+    xp = x[pr["begin"]:pr["begin"] + pr["count"]]
+    u = mlp(xp)
+    hx = 1e-5
+    ux = (mlp(xp + [hx, 0.0]) - mlp(xp - [hx, 0.0])) / (2 * hx)
+    want_p = np.mean((u[0::2] - u[1::2]) ** 2 + (ux[0::2] - ux[1::2]) ** 2)
+    assert abs(sl[2] - want_p) <= 1e-8 * want_p
