@@ -1,17 +1,20 @@
 #!/usr/bin/env python3
-"""Throughput of one partial-jet PINN step on one MI355X.
+"""Throughput of the partial-jet PINN step on one MI355X.
 
 A step is the whole hot path on one batch of collocation points: forward
 partial-jet pass through every layer, residual, mean-squared loss and the
-hand-written adjoint down to dL/dtheta (pinn_jet_residual + pinn_jet_backward).
-Inputs (network parameters and points) are resident in device memory before
-the timed region starts.
+hand-written adjoint down to dL/dtheta.  Inputs (network parameters and points)
+are resident in device memory before the timed region starts.
 
-Default workload: steady Navier-Stokes at Re = 100, MLP 2-128x6-3 tanh, 65536
-points uniform in [0, 1]^2, channels (value, d/dx, d/dy, d2/dx2, d2/dy2).  The
-headline value is the BF16-operand path (FP32 accumulation, FP32 jets,
-residual and loss); the plain FP32 path on the same GPU, nested torch.autograd
-(FP32) and the FP64 CPU oracle are reported beside it.
+Default workload (the headline): the 64-network viscous Burgers ensemble of
+seed 0.  Widths are drawn from {32, 64, 128, 256}, depths from 3 to 8, nu
+log-uniform on [1e-3, 1e-1], N uniform on [2048, 65536] per network (2,091,275
+points in all).  It is stepped with BF16 GEMM operands by the grouped batch
+(pinn_batch_step: one launch per phase for all networks, captured in one HIP
+graph), against 64 sequential calls of the plain FP32 jet path on the same
+GPU.  Beside it: the FP64 CPU oracle on the host cores (all of them, and one),
+the BF16 error against that oracle per member, and legs for the steady
+Navier-Stokes and 3-D heat workloads.
 
 Prints one JSON line.
 """
@@ -19,6 +22,8 @@ import argparse
 import json
 import math
 import os
+import platform
+import statistics
 import sys
 import time
 
@@ -29,7 +34,8 @@ if ROOT not in sys.path:
 METRIC = "collocation pts/s, residual+dθ step: BF16/batched vs plain FP32 jet, same GPU"
 PEAK = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3}  # dense MFMA TFLOP/s
 HBM_PEAK = 8000.0  # GB/s
-GEMM_CLASSES = ("layer_fwd", "layer_bwd", "dw_hidden", "bwd_dw")
+GEMM_CLASSES = ("layer_fwd", "layer_bwd", "dw_hidden", "bwd_dw", "out_bwd")
+ALL_CLASSES = ("layer_fwd", "layer_bwd", "dw_hidden", "bwd_dw", "out_fwd", "out_bwd", "seed_fwd", "other")
 
 
 def log(msg):
@@ -67,6 +73,17 @@ def profiled_traffic(workload, prec, kernel_class):
     return float(vals[kernel_class])
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
 def copy_probe(mib):
     """A plain device copy of known size (calibration of the HBM byte counters)."""
     import torch
@@ -79,173 +96,119 @@ def copy_probe(mib):
     log(f"copy probe: {mib} MiB read + {mib} MiB written per copy, 3 copies")
 
 
-def make_inputs(workload, N=None, seed=0):
-    import pinn_inputs as pi
-    return pi.make_problem(workload, N=N, seed=seed)
+# --------------------------------------------------------------------------- algorithmic work
+def gemm_unit(w, C, N):
+    """G = 2 w^2 C N: one stacked-channel w x w GEMM over N points."""
+    return 2.0 * w * w * C * N
 
 
-def gpu_params(prob):
-    import torch
-    return [(torch.tensor(W, device="cuda"), torch.tensor(b, device="cuda")) for W, b in prob.params]
-
-
-def time_path(prob, prec, steps, warmup, profile_dominant=True, tuning=None, save_cap=0):
-    """Times `steps` residual+backward steps; returns ms/step and per-class kernel times."""
-    import torch
-    from paper_2606_29702_amd import PinnPlan
-    wl = prob.workload
-    N = prob.x.shape[0]
-    plan = PinnPlan(wl.dims, wl.pde, N, precision=prec, coef=prob.coef, save_cap_bytes=save_cap)
-    params = gpu_params(prob)
-    x = torch.tensor(prob.x, device="cuda")
-
-    def step():
-        plan.residual(params, x)
-        plan.backward(params, x)
-
-    # the library's autotuner picks split-K, forward tiling and backward variant,
-    # unless a tuning is given
-    if tuning is None:
-        tuning, _ = plan.autotune(params, x, reps=10)
+def class_flops(w, H, C, N, fused):
+    """Algorithmic hidden-layer GEMM flops per step by kernel class (the z
+    recompute of the backward kernels is a design cost and not counted):
+      forward           (H - 1) G            [layer_fwd]
+      fused backward    top layer dW: G       [out_bwd]
+                        layers H-1..2: 2 G    [bwd_dw]   (adjoint GEMM + dW)
+                        layer 1 adjoint: G    [layer_bwd]
+      separate backward dW per layer: G       [dw_hidden] x (H - 1)
+                        adjoint per layer: G  [layer_bwd] x (H - 1)
+    Both add up to 3 (H - 1) G."""
+    G = gemm_unit(w, C, N)
+    f = dict.fromkeys(ALL_CLASSES, 0.0)
+    f["layer_fwd"] = (H - 1) * G
+    if H < 2:
+        return f
+    if fused:
+        f["out_bwd"] = G
+        f["bwd_dw"] = 2 * (H - 2) * G
+        f["layer_bwd"] = G
     else:
-        plan.set_tuning(*tuning)
-        tuning = plan.tuning()
-    # warmup; one profiled step per kernel class to find the dominant class
-    class_ms = {}
-    for i in range(max(warmup, 1)):
-        step()
-    torch.cuda.synchronize()
-    for cls in ("layer_fwd", "layer_bwd", "dw_hidden", "bwd_dw", "out_fwd", "out_bwd", "seed_fwd", "other"):
-        plan.profile(cls)
-        step()
-        ms, n = plan.profile_read()
-        class_ms[cls] = (ms, n)
-    plan.profile("off")
-    dominant = max(class_ms, key=lambda c: class_ms[c][0])
-    torch.cuda.synchronize()
-
-    # timed region; launches of the dominant class are bracketed by events
-    if profile_dominant:
-        plan.profile(dominant)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    dom_ms, dom_n = plan.profile_read() if profile_dominant else (float("nan"), 0)
-    plan.profile("off")
-    # a training step: the same step plus the fused Adam update (lr 1e-3, as in
-    # the paper's runs), on a copy of the parameters (context)
-    from paper_2606_29702_amd import AdamState
-    tparams = [(W.clone(), b.clone()) for W, b in params]
-    tgrads = [(torch.empty_like(W), torch.empty_like(b)) for W, b in tparams]
-    opt = AdamState(tparams, lr=1e-3)
-    # a long warm-up: early in a long eager loop, with the host far ahead of the
-    # GPU, a host call occasionally blocks for tens of milliseconds (seen with
-    # and without the Adam step); later steps run at full rate
-    for _ in range(max(warmup, 100)):
-        plan.residual(tparams, x)
-        opt.step(plan.backward(tparams, x, out=tgrads))
-    torch.cuda.synchronize()
-    a0 = time.perf_counter()
-    for _ in range(steps):
-        plan.residual(tparams, x)
-        opt.step(plan.backward(tparams, x, out=tgrads))
-    torch.cuda.synchronize()
-    train_ms = (time.perf_counter() - a0) * 1e3 / steps
-    # the training step captured as one graph (pinn_graph_capture_train)
-    tgraph = plan.capture_step(tparams, x, adam=opt)
-    for _ in range(5):
-        tgraph.launch()
-    torch.cuda.synchronize()
-    a0 = time.perf_counter()
-    for _ in range(steps):
-        tgraph.launch()
-    torch.cuda.synchronize()
-    train_graph_ms = (time.perf_counter() - a0) * 1e3 / steps
-    tgraph.close()
-    # the same step captured once as a HIP graph and replayed (context)
-    graph = plan.capture_step(params, x)
-    graph.launch()
-    torch.cuda.synchronize()
-    g0 = time.perf_counter()
-    for _ in range(steps):
-        graph.launch()
-    torch.cuda.synchronize()
-    graph_ms = (time.perf_counter() - g0) * 1e3 / steps
-    graph.close()
-    plan.close()
-    return dict(ms_per_step=(t1 - t0) * 1e3 / steps, class_ms=class_ms, dominant=dominant,
-                dominant_avg_ms=dom_ms / max(dom_n, 1), dominant_launches=dom_n, tuning=tuning,
-                graph_ms_per_step=graph_ms, train_ms_per_step=train_ms, train_graph_ms_per_step=train_graph_ms)
+        f["dw_hidden"] = (H - 1) * G
+        f["layer_bwd"] = (H - 1) * G
+    return f
 
 
-def nested_autograd_fp32(prob, steps):
-    """The paper's AD baseline (Sec. 3.1.1): coordinate derivatives by nested
-    torch.autograd, then reverse mode for dtheta.  FP32 on the GPU; context only."""
+def roofline_from(cls, flops_per_step, cls_ms, launches, prec, workload, steps_timed):
+    """Dominant kernel class roofline: algorithmic flops per launch over the
+    average launch time measured with HIP events."""
+    avg_ms = cls_ms / max(launches, 1)
+    per_launch = flops_per_step * steps_timed / max(launches, 1)
+    achieved = per_launch / (avg_ms * 1e-3) / 1e12
+    traffic = profiled_traffic(workload, prec, cls)
+    return dict(bound="mfma", achieved=round(achieved, 3), peak=PEAK[prec], unit="TFLOP/s",
+                frac=round(achieved / PEAK[prec], 5), traffic=None if traffic is None else round(traffic),
+                traffic_unit="bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+                kernel_class=cls, avg_launch_us=round(avg_ms * 1e3, 2), launches=launches,
+                flops_per_launch=per_launch,
+                hbm_frac=None if traffic is None else round(traffic / (avg_ms * 1e-3) / 1e9 / HBM_PEAK, 4))
+
+
+# --------------------------------------------------------------------------- the ensemble
+def ensemble_inputs(seed=0):
     import torch
-    from tests import autograd_ref  # noqa: F401  (same formulas; FP32 tensors here)
-    wl = prob.workload
-    params = [(torch.tensor(W, device="cuda", requires_grad=True), torch.tensor(b, device="cuda", requires_grad=True))
-              for W, b in prob.params]
-    X0 = torch.tensor(prob.x, device="cuda")
-    channels = prob.channels
+    import pinn_inputs as pi
+    ens = pi.make_ensemble(seed=seed)
+    params = [[(torch.tensor(W, device="cuda"), torch.tensor(b, device="cuda")) for W, b in m.params] for m in ens]
+    xs = [torch.tensor(m.x, device="cuda") for m in ens]
+    return ens, params, xs
 
-    def step():
-        X = X0.clone().requires_grad_(True)
-        h = X
-        for l, (W, b) in enumerate(params):
-            h = h @ W.T + b
-            if l < len(params) - 1:
-                h = torch.tanh(h)
-        jets = {}
-        for o in range(h.shape[1]):
-            u = h[:, o]
-            for c, (d, k) in enumerate(channels):
-                g = u
-                for _ in range(k):
-                    g = torch.autograd.grad(g.sum(), X, create_graph=True)[0][:, d]
-                jets[(o, c)] = g
-        rs = autograd_ref.residuals(wl.pde, jets, channels, X, prob.coef)
-        N = X.shape[0]
-        loss = sum((r * r).sum() / N for r in rs)
-        grads = torch.autograd.grad(loss, [t for p in params for t in p], allow_unused=True)
-        return grads
 
-    step()
+def time_batch(batch, params, xs, steps, warmup):
+    import torch
+    for _ in range(max(warmup, 1)):
+        batch.step(params, xs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        step()
+        batch.step(params, xs)
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) * 1e3 / steps
 
 
-def ensemble(steps, seed=0):
-    """The 64-network Burgers ensemble: one BF16 step of all networks (side
-    streams, HIP graph replay, autotuned stream count) against 64 sequential
-    plain-FP32 calls on one stream, same GPU."""
-    import torch
-    import pinn_inputs as pi
-    from paper_2606_29702_amd import PinnBatch, PinnPlan
-    ens = pi.make_ensemble(seed=seed)
-    total = sum(m.N for m in ens)
-    params = [[(torch.tensor(W, device="cuda"), torch.tensor(b, device="cuda")) for W, b in m.params] for m in ens]
-    xs = [torch.tensor(m.x, device="cuda") for m in ens]
-    batch = PinnBatch([m.dims for m in ens], "burgers", [(m.nu,) for m in ens], [m.N for m in ens],
-                      precision="bf16")
-    n_streams, _ = batch.autotune(params, xs, reps=2)
-    for _ in range(2):
-        batch.step(params, xs)
-    torch.cuda.synchronize()
+def ensemble_headline(ens, params, xs, prec, steps, warmup, runs, replays):
+    """The grouped BF16 ensemble step: autotuned, then exactly `steps` timed graph
+    replays; the kernel class with the most time is then timed with events
+    over `steps` eager steps of the same schedule."""
+    from paper_2606_29702_amd import PinnBatch
+    batch = PinnBatch([m.dims for m in ens], "burgers", [(m.nu,) for m in ens], [m.N for m in ens], precision=prec)
     t0 = time.perf_counter()
+    lanes, _ = batch.autotune(params, xs, reps=3)
+    tune_s = time.perf_counter() - t0
+    ms = time_batch(batch, params, xs, steps, warmup)
+    # timing protocol: independent runs of many replays, median per run
+    per_run = [time_batch(batch, params, xs, replays, 3) for _ in range(runs)]
+    # kernel classes: one eager step each, then the dominant class over `steps` steps
+    class_ms = {}
+    for cls in ALL_CLASSES:
+        batch.profile(cls)
+        batch.step(params, xs)
+        class_ms[cls] = batch.profile_read()
+    batch.profile("off")
+    dom = max(GEMM_CLASSES, key=lambda c: class_ms[c][0])
+    batch.profile(dom)
     for _ in range(steps):
         batch.step(params, xs)
-    torch.cuda.synchronize()
-    t_b = (time.perf_counter() - t0) / steps
+    dom_ms, dom_n = batch.profile_read()
+    batch.profile("off")
+    tunings = [batch.tuning(i) for i in range(len(ens))]
+    launches = batch.launches()
     batch.close()
+    flops = dict.fromkeys(ALL_CLASSES, 0.0)
+    for m, t in zip(ens, tunings):
+        for k, v in class_flops(m.width, m.hidden, 4, m.N, bool(t["bwd_fused"]) and m.width <= 128).items():
+            flops[k] += v
+    total_flops = sum(flops.values())
+    return dict(ms=ms, per_run_ms=per_run, lanes=lanes, tune_s=tune_s, class_ms=class_ms, dominant=dom,
+                dom_ms=dom_ms, dom_n=dom_n, flops=flops, total_flops=total_flops, launches=launches,
+                tunings=tunings)
+
+
+def ensemble_fp32_sequential(ens, params, xs, steps):
+    """The plain FP32 jet path, one network after another on one stream."""
+    import torch
+    from paper_2606_29702_amd import PinnPlan
     plans = [PinnPlan(m.dims, "burgers", m.N, precision="fp32", coef=(m.nu,)) for m in ens]
+    for pl, p, x in zip(plans, params, xs):
+        pl.autotune(p, x, reps=3)
 
     def seq():
         for pl, p, x in zip(plans, params, xs):
@@ -258,184 +221,443 @@ def ensemble(steps, seed=0):
     for _ in range(steps):
         seq()
     torch.cuda.synchronize()
-    t_s = (time.perf_counter() - t0) / steps
+    ms = (time.perf_counter() - t0) * 1e3 / steps
     for pl in plans:
         pl.close()
-    return {"nets": len(ens), "points": total, "value": round(total / t_b, 1), "unit": "pts/s",
-            "ms_per_step": round(t_b * 1e3, 3), "side_streams": n_streams,
-            "fp32_sequential": {"value": round(total / t_s, 1), "ms_per_step": round(t_s * 1e3, 3)},
-            "speedup_vs_fp32_sequential": round(t_s / t_b, 3)}
+    return ms
 
 
-def cpu_baseline(prob, target_s=15.0):
-    """The FP64 oracle on the host cores over a bounded sample of the same points."""
-    import numpy as np
+def ensemble_cpu_baseline(ens, target_s, threads):
+    """The FP64 oracle on the same mix of networks: the first ceil(f N_i)
+    points of every member, f chosen for about target_s seconds."""
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
-    # calibrate on growing samples until one takes a second, then scale to target_s
-    n, dt = 128, 0.0
-    while True:
+    import pinn_inputs as pi
+    ch = pi.CHANNELS["burgers"]
+
+    def run(f):
+        n_tot = 0
         t0 = time.perf_counter()
-        oracle.evaluate(prob.params, prob.x[:n], prob.channels, prob.workload.pde, prob.coef, threads=threads)
-        dt = time.perf_counter() - t0
-        if dt >= 1.0 or n >= prob.x.shape[0]:
-            break
-        n *= 2
-    full = prob.x.shape[0]
-    # the whole workload fits in the budget: repeat it to about target_s
-    passes = max(1, int(round(target_s / dt))) if n >= full else 1
-    n = int(min(full, max(n, n * target_s / dt)))
-    n = max(64, n // 64 * 64)
-    t0 = time.perf_counter()
-    for _ in range(passes):
-        res = oracle.evaluate(prob.params, prob.x[:n], prob.channels, prob.workload.pde, prob.coef,
-                              threads=threads)
-    dt = time.perf_counter() - t0
-    what = f"first {n} of the {full} points" if passes == 1 else f"all {n} points, {passes} passes"
-    return dict(value=passes * n / dt, unit="pts/s", cores=threads, kind="oracle",
-                sample=f"{what}, residual + loss + dtheta in FP64 ({dt:.1f} s)"), n, res
+        for m in ens:
+            n = max(1, int(math.ceil(f * m.N)))
+            oracle.evaluate(m.params, m.x[:n], ch, "burgers", (m.nu,), want_jets=False, threads=threads)
+            n_tot += n
+        return n_tot, time.perf_counter() - t0
+
+    f = 1e-4
+    n, dt = run(f)
+    while dt < 0.5 and f < 1.0:
+        f *= 4
+        n, dt = run(f)
+    f = min(1.0, f * target_s / dt)
+    n, dt = run(f)
+    return dict(value=round(n / dt, 1), unit="pts/s", cores=threads, kind="oracle",
+                sample=f"first {f:.2%} of the points of each of the {len(ens)} networks ({n} points), "
+                       f"residual + loss + dtheta in FP64 ({dt:.1f} s)")
 
 
-def accuracy(prob, n, ref, prec):
-    """GPU path on the oracle's sample against the oracle (rel. L2)."""
+def ensemble_accuracy(ens, prec, n_pts=256):
+    """Each member on its first n_pts points: the GPU path against the oracle."""
     import numpy as np
+    import torch
+    import oracle
+    import pinn_inputs as pi
+    from paper_2606_29702_amd import PinnPlan
+    worst_r = worst_g = 0.0
+    min_cos = 1.0
+    for m in ens:
+        x_np = m.x[:n_pts]
+        plan = PinnPlan(m.dims, "burgers", n_pts, precision=prec, coef=(m.nu,))
+        params = [(torch.tensor(W, device="cuda"), torch.tensor(b, device="cuda")) for W, b in m.params]
+        x = torch.tensor(x_np, device="cuda")
+        r, _, _, _ = plan.residual(params, x)
+        grads = plan.backward(params, x)
+        torch.cuda.synchronize()
+        g = np.concatenate([np.concatenate([dW.double().cpu().numpy().ravel(), db.double().cpu().numpy().ravel()])
+                            for dW, db in grads])
+        ref = oracle.evaluate(m.params, x_np, pi.CHANNELS["burgers"], "burgers", (m.nu,), want_jets=False)
+        plan.close()
+        worst_r = max(worst_r, float(np.linalg.norm(r.double().cpu().numpy() - ref.r) / np.linalg.norm(ref.r)))
+        worst_g = max(worst_g, float(np.linalg.norm(g - ref.grad) / np.linalg.norm(ref.grad)))
+        min_cos = min(min_cos, float(g @ ref.grad / (np.linalg.norm(g) * np.linalg.norm(ref.grad))))
+    return dict(points_per_member=n_pts, members=len(ens), worst_r_rel_l2=worst_r, worst_grad_rel_l2=worst_g,
+                min_grad_cosine=min_cos)
+
+
+# --------------------------------------------------------------------------- single-network legs
+def time_plan(prob, prec, steps, warmup, save_cap=0, tuning=None):
+    """A single-network step: autotuned (or given tuning), `steps` timed eager
+    steps with the dominant kernel class bracketed by events."""
     import torch
     from paper_2606_29702_amd import PinnPlan
     wl = prob.workload
-    plan = PinnPlan(wl.dims, wl.pde, n, precision=prec, coef=prob.coef)
-    params = gpu_params(prob)
-    x = torch.tensor(prob.x[:n], device="cuda")
-    r, loss, _, _ = plan.residual(params, x)
-    grads = plan.backward(params, x)
+    N = prob.x.shape[0]
+    plan = PinnPlan(wl.dims, wl.pde, N, precision=prec, coef=prob.coef, save_cap_bytes=save_cap)
+    params = [(torch.tensor(W, device="cuda"), torch.tensor(b, device="cuda")) for W, b in prob.params]
+    x = torch.tensor(prob.x, device="cuda")
+
+    def step():
+        plan.residual(params, x)
+        plan.backward(params, x)
+
+    if tuning is None:
+        tuning, _ = plan.autotune(params, x, reps=3)
+    else:
+        plan.set_tuning(*tuning)
+        tuning = plan.tuning()
+    for _ in range(max(warmup, 1)):
+        step()
     torch.cuda.synchronize()
-    g = np.concatenate([np.concatenate([dW.double().cpu().numpy().ravel(), db.double().cpu().numpy().ravel()])
-                        for dW, db in grads])
-    rr = r.double().cpu().numpy()
+    class_ms = {}
+    for cls in ALL_CLASSES:
+        plan.profile(cls)
+        step()
+        class_ms[cls] = plan.profile_read()
+    plan.profile("off")
+    dom = max(GEMM_CLASSES, key=lambda c: class_ms[c][0])
+    plan.profile(dom)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    dom_ms, dom_n = plan.profile_read()
+    plan.profile("off")
     plan.close()
-
-    def rel(a, b):
-        return float(np.linalg.norm(a.ravel() - b.ravel()) / np.linalg.norm(b.ravel()))
-
-    return dict(r_rel_l2=rel(rr, ref.r), grad_rel_l2=rel(g, ref.grad),
-                grad_cosine=float(g @ ref.grad / (np.linalg.norm(g) * np.linalg.norm(ref.grad))),
-                points=n)
+    return dict(ms=ms, class_ms=class_ms, dominant=dom, dom_ms=dom_ms, dom_n=dom_n, tuning=tuning)
 
 
+def nested_autograd_fp32(prob, steps):
+    """The paper's AD baseline (Sec. 3.1.1): coordinate derivatives by nested
+    torch.autograd through a plain tanh MLP, then reverse mode for dtheta.
+    FP32 on the GPU; context only (NS residual, Eq. 16)."""
+    import torch
+    assert prob.workload.pde == "ns"
+    Re = prob.coef[0]
+    params = [(torch.tensor(W, device="cuda", requires_grad=True), torch.tensor(b, device="cuda", requires_grad=True))
+              for W, b in prob.params]
+    X0 = torch.tensor(prob.x, device="cuda")
+
+    def step():
+        X = X0.clone().requires_grad_(True)
+        h = X
+        for l, (W, b) in enumerate(params):
+            h = h @ W.T + b
+            if l < len(params) - 1:
+                h = torch.tanh(h)
+        d = {}
+        for o in range(3):
+            g = torch.autograd.grad(h[:, o].sum(), X, create_graph=True)[0]
+            d[o, "x"], d[o, "y"] = g[:, 0], g[:, 1]
+            d[o, "xx"] = torch.autograd.grad(d[o, "x"].sum(), X, create_graph=True)[0][:, 0]
+            d[o, "yy"] = torch.autograd.grad(d[o, "y"].sum(), X, create_graph=True)[0][:, 1]
+        u, v = h[:, 0], h[:, 1]
+        rc = d[0, "x"] + d[1, "y"]
+        ru = u * d[0, "x"] + v * d[0, "y"] + d[2, "x"] - (d[0, "xx"] + d[0, "yy"]) / Re
+        rv = u * d[1, "x"] + v * d[1, "y"] + d[2, "y"] - (d[1, "xx"] + d[1, "yy"]) / Re
+        N = X.shape[0]
+        loss = ((rc * rc).sum() + (ru * ru).sum() + (rv * rv).sum()) / N
+        return torch.autograd.grad(loss, [t for p in params for t in p])
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def nested_autograd_training(ts, steps, lr=1e-3):
+    """The paper's AD baseline for a complete training step (Sec. 3.1.1): the
+    composite loss (all points through the network at once, outputs split by
+    segment) with coordinate derivatives by nested torch.autograd, reverse
+    mode for dtheta and torch.optim.Adam.  FP32 on the GPU; returns ms per step."""
+    import torch
+    params = [t for W, b in ts.params for t in (torch.tensor(W, device="cuda", requires_grad=True),
+                                                 torch.tensor(b, device="cuda", requires_grad=True))]
+    opt = torch.optim.Adam(params, lr=lr)
+    X0 = torch.tensor(ts.x, device="cuda")
+    L = len(params) // 2
+
+    def d(f, X, i):
+        return torch.autograd.grad(f.sum(), X, create_graph=True)[0][:, i]
+
+    def step():
+        X = X0.clone().requires_grad_(True)
+        h = X
+        for l in range(L):
+            h = h @ params[2 * l].T + params[2 * l + 1]
+            if l < L - 1:
+                h = torch.tanh(h)
+        loss = 0.0
+        if ts.name == "burgers":
+            u = h[:, 0]
+            u_x, u_t = d(u, X, 0), d(u, X, 1)
+            u_xx = d(u_x, X, 0)
+            for sg in ts.segments:
+                a, n, w = sg["begin"], sg["count"], sg["weight"]
+                if sg["type"] == "pde":
+                    r = u_t[a:a + n] + u[a:a + n] * u_x[a:a + n] - ts.coef[0] * u_xx[a:a + n]
+                    loss = loss + w * (r * r).mean()
+                elif sg["type"] == "dirichlet":
+                    amp, k = sg["param"][0], sg["param"][1]
+                    r = u[a:a + n] - amp * torch.sin(k * math.pi * X0[a:a + n, 0])
+                    loss = loss + w * (r * r).mean()
+                else:
+                    uu, ux = u[a:a + n], u_x[a:a + n]
+                    loss = loss + w * (((uu[0::2] - uu[1::2]) ** 2 + (ux[0::2] - ux[1::2]) ** 2).mean())
+        else:
+            Re = ts.coef[0]
+            g = {}
+            for o in range(3):
+                g[o, "x"], g[o, "y"] = d(h[:, o], X, 0), d(h[:, o], X, 1)
+                if o < 2:
+                    g[o, "xx"], g[o, "yy"] = d(g[o, "x"], X, 0), d(g[o, "y"], X, 1)
+            u, v = h[:, 0], h[:, 1]
+            for sg in ts.segments:
+                a, n, w = sg["begin"], sg["count"], sg["weight"]
+                sl = slice(a, a + n)
+                if sg["type"] == "pde":
+                    rc = g[0, "x"][sl] + g[1, "y"][sl]
+                    ru = (u[sl] * g[0, "x"][sl] + v[sl] * g[0, "y"][sl] + g[2, "x"][sl]
+                          - (g[0, "xx"][sl] + g[0, "yy"][sl]) / Re)
+                    rv = (u[sl] * g[1, "x"][sl] + v[sl] * g[1, "y"][sl] + g[2, "y"][sl]
+                          - (g[1, "xx"][sl] + g[1, "yy"][sl]) / Re)
+                    loss = loss + w * (rc * rc + ru * ru + rv * rv).mean()
+                else:
+                    par = list(sg.get("param", ())) + [0.0, 0.0]
+                    u0 = par[0] if sg.get("data") == "const" else 0.0
+                    v0 = par[1] if sg.get("data") == "const" else 0.0
+                    loss = loss + w * ((u[sl] - u0) ** 2 + (v[sl] - v0) ** 2).mean()
+        opt.zero_grad(set_to_none=False)
+        grads = torch.autograd.grad(loss, params)
+        for p_, g_ in zip(params, grads):
+            p_.grad = g_
+        opt.step()
+
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def pi_training_set(name):
+    import pinn_inputs as pi
+    return pi.burgers_training_set(seed=0) if name == "burgers" else pi.cavity_training_set(seed=0)
+
+
+def training_leg(name, prec, steps):
+    """A complete training run as the paper times it (Sec. 3.1.1): `steps`
+    full-batch Adam steps on the composite loss of the paper's training set
+    (all points evaluated together), eager calls of pinn_jet_loss,
+    pinn_jet_loss_backward and pinn_adam_step."""
+    import torch
+    from paper_2606_29702_amd import AdamState, PinnPlan
+    ts = pi_training_set(name)
+    N = ts.x.shape[0]
+    plan = PinnPlan(ts.dims, ts.name, N, precision=prec, coef=ts.coef)
+    params = [(torch.tensor(W, device="cuda"), torch.tensor(b, device="cuda")) for W, b in ts.params]
+    x = torch.tensor(ts.x, device="cuda")
+    opt = AdamState(params, lr=1e-3)
+    grads = [(torch.empty_like(W), torch.empty_like(b)) for W, b in params]
+
+    def step():
+        plan.loss(params, x, ts.segments)
+        plan.loss_backward(params, x, ts.segments, out=grads)
+        opt.step(grads)
+
+    for _ in range(5):
+        step()
+    torch.cuda.synchronize()
+    l0 = float(plan.loss(params, x, ts.segments)[0])
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    l1 = float(plan.loss(params, x, ts.segments)[0])
+    plan.close()
+    return dict(workload=f"{name} training set", dims=ts.dims, points=N, precision=prec, steps=steps,
+                ms_per_step=round(ms, 4), run_s=round(ms * steps * 1e-3, 4),
+                value=round(N / (ms * 1e-3), 1), unit="pts/s", loss_first=l0, loss_last=l1)
+
+
+def plan_leg(name, prec, steps, warmup, save_cap=0, fp32_context=True):
+    import pinn_inputs as pi
+    prob = pi.make_problem(name)
+    wl = prob.workload
+    N = prob.x.shape[0]
+    C = len(prob.channels)
+    w, H = wl.width, wl.hidden
+    run = time_plan(prob, prec, steps, warmup, save_cap=save_cap)
+    tun = run["tuning"]
+    fused = bool(tun["bwd_fused"]) and w <= 128
+    fl = class_flops(w, H, C, N, fused)
+    dom = run["dominant"]
+    roof = roofline_from(dom, fl[dom], run["dom_ms"], run["dom_n"], prec, name, steps)
+    out = dict(workload=name, dims=wl.dims, N=N, channels=C, precision=prec, save_cap_bytes=save_cap,
+               ms_per_step=round(run["ms"], 4), value=round(N / (run["ms"] * 1e-3), 1), unit="pts/s",
+               step_mfma_frac=round(sum(fl.values()) / (run["ms"] * 1e-3) / 1e12 / PEAK[prec], 4),
+               roofline=roof, tuning=tun,
+               kernel_ms_per_step={k: round(v[0], 4) for k, v in run["class_ms"].items()})
+    if fp32_context:
+        f32 = time_plan(prob, "fp32", max(3, steps // 4), 2)
+        out["fp32_jet"] = {"ms_per_step": round(f32["ms"], 4), "value": round(N / (f32["ms"] * 1e-3), 1),
+                           "speedup": round(f32["ms"] / run["ms"], 3)}
+    return out
+
+
+# --------------------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="ns", choices=["burgers", "ns", "ks", "heat", "aniso"])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "fp32"])
+    ap.add_argument("--runs", type=int, default=3, help="independent timing runs of the protocol")
+    ap.add_argument("--replays", type=int, default=100, help="graph replays per protocol run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-context", action="store_true", help="skip the FP32, nested-autograd and ensemble context runs")
+    ap.add_argument("--no-context", action="store_true",
+                    help="skip the FP32 comparison, the accuracy leg and the single-network legs")
+    ap.add_argument("--legs", default="ns,heat", help="single-network legs (ns, ks, heat, burgers, aniso) or ''")
+    ap.add_argument("--workload", default="ensemble",
+                    help="'ensemble' (the headline) or one single-network workload, timed alone")
+    ap.add_argument("--save-cap-gib", type=float, default=0.0, help="saved-state cap of a single-network workload")
+    ap.add_argument("--tuning", default=None, help="dw_splits,fwd_points,bwd_fused for a single-network workload")
     ap.add_argument("--copy-probe-mib", type=int, default=0, help="only run a plain device copy of this size")
-    ap.add_argument("--save-cap-gib", type=float, default=0.0,
-                    help="bound on the saved layer state (checkpointed backward); 0 = store every layer")
-    ap.add_argument("--tuning", default=None,
-                    help="dw_splits,fwd_points,bwd_fused instead of running the autotuner (e.g. for profiling)")
+    ap.add_argument("--training", default="burgers,ns",
+                    help="paper training runs (1000 Adam steps on the composite loss): burgers, ns or ''")
+    ap.add_argument("--training-steps", type=int, default=1000)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the partial-jet step is run on a single MI355X "
-              "(multi-GPU data parallelism over points is a design note, not built). Use --gpus 1.",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: the step runs on a single MI355X (data parallelism over points or "
+              "networks across GPUs is a design note, not built). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
-
     if args.copy_probe_mib:
         copy_probe(args.copy_probe_mib)
         return
 
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    prob = make_inputs(args.workload)
-    wl = prob.workload
-    N = prob.x.shape[0]
-    C = len(prob.channels)
-    w, H = wl.width, wl.hidden
+    prec = args.precision
 
-    log(f"workload {args.workload}: dims {wl.dims}, N {N}, C {C}, precision {args.precision}")
-    tuning = tuple(int(v) for v in args.tuning.split(",")) if args.tuning else None
-    save_cap = int(args.save_cap_gib * (1 << 30))
-    main_run = time_path(prob, args.precision, args.steps, args.warmup, tuning=tuning, save_cap=save_cap)
-    ms = main_run["ms_per_step"]
-    value = N / (ms * 1e-3)
-    log(f"{args.precision}: {ms:.3f} ms/step, {value/1e6:.2f} Mpts/s, dominant {main_run['dominant']} "
-        f"{main_run['dominant_avg_ms']*1e3:.1f} us/launch")
+    if args.workload == "training":  # only the paper's training runs
+        out = {}
+        for name in [t for t in args.training.split(",") if t]:
+            out[name] = {p: training_leg(name, p, args.training_steps) for p in ("fp32", prec)}
+            ad = nested_autograd_training(pi_training_set(name), 50)
+            out[name]["nested_autograd_fp32"] = {"ms_per_step": round(ad, 4)}
+            log(f"training {name}: {out[name]}")
+        print(json.dumps({"training_runs": out}), flush=True)
+        return
 
-    dom = main_run["dominant"]
-    if dom in GEMM_CLASSES:
-        # algorithmic flops per launch: G = 2 w^2 C N is one stacked-channel
-        # w x w GEMM over the N points.  The whole-network forward kernel does
-        # the H - 1 hidden-layer GEMMs of a step; a backward layer kernel one
-        # (abar); the fused backward kernel two (abar and dW); a dW kernel one.
-        # The z recompute in the backward kernels is a design cost, not counted.
-        G = 2.0 * w * w * C * N
-        n_dom = max(main_run["class_ms"][dom][1], 1)  # launches in one step
-        per_step = {"layer_fwd": (H - 1) * G, "layer_bwd": n_dom * G, "dw_hidden": n_dom * G,
-                    "bwd_dw": 2 * n_dom * G}[dom]
-        flops = per_step / n_dom
-        achieved = flops / (main_run["dominant_avg_ms"] * 1e-3) / 1e12
-        traffic = profiled_traffic(args.workload, args.precision, dom)
-        roof = dict(bound="mfma", achieved=round(achieved, 3), peak=PEAK[args.precision], unit="TFLOP/s",
-                    frac=round(achieved / PEAK[args.precision], 5),
-                    traffic=None if traffic is None else round(traffic),
-                    traffic_unit="bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
-                    achieved_hbm_GBps=None if traffic is None else
-                    round(traffic / (main_run["dominant_avg_ms"] * 1e-3) / 1e9, 1), kernel=dom,
-                    avg_launch_us=round(main_run["dominant_avg_ms"] * 1e3, 2),
-                    launches=main_run["dominant_launches"], flops_per_launch=flops,
-                    hbm_frac=None if traffic is None else
-                    round(traffic / (main_run["dominant_avg_ms"] * 1e-3) / 1e9 / HBM_PEAK, 4))
-    else:
-        roof = dict(bound="hbm", achieved=None, peak=HBM_PEAK, unit="GB/s", frac=None, traffic=None,
-                    kernel=dom, avg_launch_us=round(main_run["dominant_avg_ms"] * 1e3, 2))
+    if args.workload != "ensemble":  # one single-network workload (profiling runs)
+        import pinn_inputs as pi
+        prob = pi.make_problem(args.workload)
+        tuning = tuple(int(v) for v in args.tuning.split(",")) if args.tuning else None
+        cap = int(args.save_cap_gib * (1 << 30))
+        run = time_plan(prob, prec, args.steps, args.warmup, save_cap=cap, tuning=tuning)
+        wl = prob.workload
+        N = prob.x.shape[0]
+        fl = class_flops(wl.width, wl.hidden, len(prob.channels), N, bool(run["tuning"]["bwd_fused"]) and wl.width <= 128)
+        dom = run["dominant"]
+        out = {"metric": METRIC, "value": round(N / (run["ms"] * 1e-3), 1), "unit": "pts/s", "n_gpus": 1,
+               "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(run["ms"], 4),
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": prec,
+               "data": "synthetic", "config": {"workload": args.workload, "dims": wl.dims, "N": N,
+                                               "save_cap_bytes": cap},
+               "roofline": roofline_from(dom, fl[dom], run["dom_ms"], run["dom_n"], prec, args.workload, args.steps),
+               "tuning": run["tuning"]}
+        print(json.dumps(out), flush=True)
+        return
 
+    ens, params, xs = ensemble_inputs()
+    total_N = sum(m.N for m in ens)
+    log(f"ensemble: {len(ens)} networks, {total_N} points, precision {prec}")
+    head = ensemble_headline(ens, params, xs, prec, args.steps, args.warmup, args.runs, args.replays)
+    ms = head["ms"]
+    value = total_N / (ms * 1e-3)
+    dom = head["dominant"]
+    roof = roofline_from(dom, head["flops"][dom], head["dom_ms"], head["dom_n"], prec, "ensemble", args.steps)
+    log(f"{prec} grouped ensemble: {ms:.3f} ms/step, {value/1e6:.2f} Mpts/s, {head['launches']} launches, "
+        f"dominant {dom} {roof['avg_launch_us']} us/launch, {roof['frac']:.4f} of peak")
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "pts/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": args.precision, "data": "synthetic",
-        "config": {"workload": args.workload, "dims": wl.dims, "N": N, "channels": C,
-                   "coef": list(prob.coef), "step": "forward jets + residual + MSE loss + dtheta",
-                   "save_cap_bytes": save_cap},
+        "dtype": prec, "data": "synthetic",
+        "config": {"workload": "burgers ensemble, 64 networks, seed 0", "networks": len(ens), "points": total_N,
+                   "widths": sorted({m.width for m in ens}), "depths": [min(m.hidden for m in ens),
+                                                                         max(m.hidden for m in ens)],
+                   "step": "forward jets + residual + MSE loss + dtheta, every network",
+                   "execution": "grouped launches (one per phase for all networks), one HIP graph"},
         "roofline": roof,
-        "kernel_ms_per_step": {k: round(v[0], 4) for k, v in main_run["class_ms"].items()},
-        "train_step_adam": {"ms_per_step": round(main_run["train_ms_per_step"], 4),
-                            "value": round(N / (main_run["train_ms_per_step"] * 1e-3), 1), "unit": "pts/s",
-                            "note": "residual + dtheta + fused Adam update (pinn_adam_step)",
-                            "graph_ms_per_step": round(main_run["train_graph_ms_per_step"], 4)},
-        "graph_replay": {"ms_per_step": round(main_run["graph_ms_per_step"], 4),
-                         "value": round(N / (main_run["graph_ms_per_step"] * 1e-3), 1), "unit": "pts/s"},
-        "tuning": main_run["tuning"],
+        "step_mfma_frac": round(head["total_flops"] / (ms * 1e-3) / 1e12 / PEAK[prec], 4),
+        "hidden_gemm_tflop_per_step": round(head["total_flops"] / 1e12, 4),
+        "grouped_launches_per_step": head["launches"],
+        "lanes": head["lanes"],
+        "autotune_s": round(head["tune_s"], 2),
+        "timing_protocol": {"runs": args.runs, "replays_per_run": args.replays,
+                            "ms_per_step_each_run": [round(v, 4) for v in head["per_run_ms"]],
+                            "median_ms_per_step": round(statistics.median(head["per_run_ms"]), 4)},
+        "kernel_ms_per_step": {k: round(v[0], 4) for k, v in head["class_ms"].items()},
     }
 
     if not args.no_context:
-        fp32 = time_path(prob, "fp32", max(5, args.steps // 5), 3, profile_dominant=False)
-        out["fp32_jet"] = {"value": round(N / (fp32["ms_per_step"] * 1e-3), 1), "unit": "pts/s",
-                           "ms_per_step": round(fp32["ms_per_step"], 4)}
-        out["speedup_vs_fp32_jet"] = round(fp32["ms_per_step"] / ms, 3)
-        log(f"fp32 jet: {fp32['ms_per_step']:.3f} ms/step")
-        try:
-            ad_ms = nested_autograd_fp32(prob, 3)
-            out["nested_autograd_fp32"] = {"value": round(N / (ad_ms * 1e-3), 1), "unit": "pts/s",
-                                           "ms_per_step": round(ad_ms, 3)}
-            log(f"nested autograd fp32: {ad_ms:.3f} ms/step")
-        except RuntimeError as e:  # out of memory at large N is reported, not fatal
-            out["nested_autograd_fp32"] = {"error": str(e)[:200]}
-            torch.cuda.empty_cache()
-
-    if not args.no_context:
-        out["ensemble_burgers_64"] = ensemble(steps=5)
-        log(f"ensemble: {out['ensemble_burgers_64']}")
+        f32_ms = ensemble_fp32_sequential(ens, params, xs, max(3, args.steps // 4))
+        out["fp32_sequential"] = {"ms_per_step": round(f32_ms, 4), "value": round(total_N / (f32_ms * 1e-3), 1),
+                                  "unit": "pts/s", "note": "64 plain FP32 jet steps, one network after another"}
+        out["speedup_vs_fp32_sequential"] = round(f32_ms / ms, 3)
+        log(f"fp32 sequential: {f32_ms:.3f} ms/step (batched {prec} is {f32_ms / ms:.2f}x)")
+        out["accuracy_vs_oracle"] = ensemble_accuracy(ens, prec)
+        log(f"accuracy: {out['accuracy_vs_oracle']}")
 
     if not args.no_cpu_baseline:
-        cb, n_s, ref = cpu_baseline(prob)
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+        cb = ensemble_cpu_baseline(ens, 15.0, threads)
+        cb["cpu_model"] = cpu_model()
+        one = ensemble_cpu_baseline(ens, 5.0, 1)
+        cb["one_core"] = {"value": one["value"], "unit": "pts/s", "sample": one["sample"]}
         out["cpu_baseline"] = cb
-        log(f"cpu oracle: {cb['value']:.1f} pts/s on {cb['cores']} threads")
-        out["accuracy_vs_oracle"] = accuracy(prob, n_s, ref, args.precision)
-        log(f"accuracy: {out['accuracy_vs_oracle']}")
+        log(f"cpu oracle: {cb['value']:.1f} pts/s on {threads} threads ({cb['cpu_model']}), "
+            f"{one['value']:.1f} on one")
+
+    if not args.no_context and args.legs:
+        legs = {}
+        for name in [s for s in args.legs.split(",") if s]:
+            cap = (8 << 30) if name == "heat" else 0  # heat: saved state capped at 8 GiB
+            legs[name] = plan_leg(name, prec, max(5, args.steps // 2), 2, save_cap=cap, fp32_context=name != "heat")
+            log(f"leg {name}: {legs[name]['ms_per_step']} ms/step, roofline {legs[name]['roofline']['frac']}")
+        if "ns" in legs:
+            import pinn_inputs as pi
+            try:
+                ad_ms = nested_autograd_fp32(pi.make_problem("ns"), 3)
+                legs["ns"]["nested_autograd_fp32"] = {"ms_per_step": round(ad_ms, 3),
+                                                      "value": round(65536 / (ad_ms * 1e-3), 1)}
+            except RuntimeError as e:  # out of memory is reported, not fatal
+                legs["ns"]["nested_autograd_fp32"] = {"error": str(e)[:200]}
+        out["legs"] = legs
+
+    if not args.no_context and args.training:
+        runs = {}
+        for name in [t for t in args.training.split(",") if t]:
+            r = {p: training_leg(name, p, args.training_steps) for p in ("fp32", prec)}
+            try:
+                ad = nested_autograd_training(pi_training_set(name), 50)
+                r["nested_autograd_fp32"] = {"ms_per_step": round(ad, 4),
+                                             "speedup_fp32_jet": round(ad / r["fp32"]["ms_per_step"], 3)}
+            except RuntimeError as e:
+                r["nested_autograd_fp32"] = {"error": str(e)[:200]}
+            runs[name] = r
+            log(f"training {name}: fp32 {r['fp32']['ms_per_step']} ms/step, {prec} {r[prec]['ms_per_step']} ms/step, "
+                f"nested AD {r['nested_autograd_fp32']}")
+        out["training_runs"] = runs
 
     print(json.dumps(out), flush=True)
 

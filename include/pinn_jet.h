@@ -110,6 +110,7 @@ typedef struct {
 
 typedef struct pinn_plan_s *pinn_plan;
 typedef struct pinn_batch_s *pinn_batch;
+struct pinn_adam_s;
 
 /* Creates a plan for one network shape, PDE kind and maximum point count: the
  * channel set of the kind (the on-demand partial jet of Sec. 2.2, only the
@@ -191,6 +192,56 @@ pinn_status pinn_jet_backward_cot(pinn_plan plan, const pinn_net *net, const pin
                                   float *const *dW, float *const *db,
                                   double *const *dW_f64, double *const *db_f64, void *stream);
 
+/* Composite training loss (Sec. 3.1.1).  The paper's training runs combine
+ * the PDE residual with initial-condition and boundary terms, each weighted,
+ * and evaluate them in an "all-points batching" layout: the initial, boundary
+ * and PDE points are concatenated, the network and its partial jet are
+ * evaluated once on all of them, and the outputs are split afterwards to
+ * assemble the loss terms.  A segment is one such term over a range of the
+ * points:
+ *   PINN_SEG_PDE        the plan's PDE residual at each point
+ *   PINN_SEG_DIRICHLET  a data term u_o - g_o(x) at each point, for every
+ *                       output o whose value bit (o * C) is set in mask; g_o:
+ *                       PINN_DATA_ZERO 0, PINN_DATA_CONST param[o],
+ *                       PINN_DATA_SIN param[0] sin(param[1] pi x_0)
+ *                       (initial conditions, no-slip walls, a moving lid)
+ *   PINN_SEG_PERIODIC   consecutive point pairs (begin + 2k, begin + 2k + 1):
+ *                       u_oc(first) - u_oc(second) for every output o and
+ *                       channel c whose bit o * C + c is set in mask
+ *                       (periodic boundary terms for u and its derivatives)
+ * C is the kind's channel count; channel c of output o as in the jets array.
+ * Each segment contributes weight * seg_loss, seg_loss being the mean over its
+ * units (points, or pairs) of the sum of its squared terms.  Segments lie in
+ * [0, N) and do not overlap; points outside every segment are evaluated but
+ * do not enter the loss.  1 <= n_segments <= PINN_MAX_SEGMENTS. */
+enum { PINN_SEG_PDE = 0, PINN_SEG_DIRICHLET = 1, PINN_SEG_PERIODIC = 2 };
+enum { PINN_DATA_ZERO = 0, PINN_DATA_CONST = 1, PINN_DATA_SIN = 2 };
+#define PINN_MAX_SEGMENTS 8
+typedef struct {
+  int32_t type;      /* PINN_SEG_* */
+  int32_t data;      /* PINN_DATA_* (Dirichlet segments) */
+  int64_t begin, count;
+  double weight;     /* >= 0 */
+  uint32_t mask;
+  double param[4];
+} pinn_segment;
+
+/* The composite loss: the forward pass over all N points, then each segment's
+ * terms.  loss (1 float) receives sum_s weight_s seg_loss_s and seg_loss
+ * (n_segments floats) the segments' own losses; either may be NULL.  Saves
+ * the state pinn_jet_loss_backward needs (segments: host array).  Errors as
+ * pinn_jet_residual; PINN_ERR_ARG for a malformed segment list. */
+pinn_status pinn_jet_loss(pinn_plan plan, const pinn_net *net, const pinn_pde *pde, const pinn_segment *segments,
+                          int32_t n_segments, const float *x, int64_t N, float *loss, float *seg_loss,
+                          void *stream);
+/* d loss / d theta of the composite loss, by reverse mode from every point's
+ * output cotangent (a periodic pair's term reaches both of its points); the
+ * same backward kernels as pinn_jet_backward.  Must follow pinn_jet_loss on the
+ * same plan with the same segments, x, N and parameters (PINN_ERR_STATE). */
+pinn_status pinn_jet_loss_backward(pinn_plan plan, const pinn_net *net, const pinn_pde *pde,
+                                   const pinn_segment *segments, int32_t n_segments, const float *x, int64_t N,
+                                   float *const *dW, float *const *db, void *stream);
+
 /* Tunable launch parameters of a plan.  They change reduction order and
  * workgroup shapes, never the arithmetic: every setting is deterministic and
  * agrees with the others to rounding.
@@ -214,26 +265,57 @@ pinn_status pinn_plan_set_tuning(pinn_plan plan, const pinn_tuning *tuning);
  * for each candidate tuning on the caller's data, in two interleaved rounds,
  * keeps the candidate with the fastest round and returns it with its
  * milliseconds per step.  Synchronises the stream and
- * allocates temporary gradient buffers; invalidates the saved state. */
+ * allocates temporary gradient buffers; invalidates the saved state.
+ * Results are cached for the process, per (device architecture, PDE kind,
+ * operand type, width, depth, point-count bucket ceil(log2 N)): a later call
+ * with a cached key applies the cached choice without timing (the split count
+ * is scaled to the plan's N) and returns the cached milliseconds. */
 pinn_status pinn_plan_autotune(pinn_plan plan, const pinn_net *net, const pinn_pde *pde, const float *x,
                                int64_t N, int32_t reps, pinn_tuning *best, double *best_ms, void *stream);
 
-/* Ensembles (many independent networks, each with its own shape, PDE
- * coefficients and point count, stepped together).
+/* The tuning cache of pinn_plan_autotune: drop every entry; the number of
+ * entries; write it to / merge it from a text file (one entry per line:
+ * arch kind prec w H nbucket split_mode fwd_points bwd_fused ms).
+ * PINN_ERR_ARG on an unreadable or malformed file (nothing is merged). */
+pinn_status pinn_tuning_cache_clear(void);
+pinn_status pinn_tuning_cache_size(int64_t *entries);
+pinn_status pinn_tuning_cache_save(const char *path);
+pinn_status pinn_tuning_cache_load(const char *path);
+
+/* Ensembles: many independent networks, each with its own width, depth, PDE
+ * coefficients and point count, stepped together.  (The paper batches
+ * collocation points within one network, Sec. 3.1.1; an ensemble of
+ * networks is this library's extension of that batching.)
  *   pinn_batch_create   one plan per network (arguments as pinn_plan_create,
  *                       no save cap); nets[i], pdes[i], max_points[i] host arrays.
  *   pinn_batch_step     for every network i: residual, loss[i] (device array of
  *                       n floats) and the loss gradient into dW[i][l], db[i][l]
- *                       (host arrays of host arrays of device pointers).  The
- *                       networks run concurrently on a pool of side streams
- *                       forked from and joined back into `stream`.  With graphs
- *                       enabled (the default) the first call captures the whole
- *                       step into a HIP graph and later calls with the same
- *                       pointers, sizes and coefficients replay it; any change
- *                       triggers a new capture.
- *   pinn_batch_configure  side-stream count (1..16) and graph on/off.
- *   pinn_batch_autotune   times `reps` steps for each side-stream count
- *                       (1, 2, 4, 8, 16 up to n) and keeps the fastest. */
+ *                       (host arrays of host arrays of device pointers).
+ *                       The kernels are grouped across networks: at every
+ *                       phase of the step one launch runs the same kernel
+ *                       for all networks that are at that phase, each network
+ *                       on its own grid of workgroups with its own argument
+ *                       block (so each network's results are those of its
+ *                       single-plan calls, bit for bit).  Networks of one
+ *                       hidden width form a lane; lanes run on separate
+ *                       streams forked from and joined into `stream`.  The
+ *                       first call builds this schedule (a synchronous upload
+ *                       of the argument blocks) and, with graphs on (the
+ *                       default), captures it into one HIP graph; later calls
+ *                       with the same pointers, sizes, coefficients and
+ *                       tunings replay it.  Any change rebuilds it.
+ *   pinn_batch_train_step  the same step followed by the Adam update of every
+ *                       network (as pinn_adam_step; moments mW[i][l], vW[i][l],
+ *                       mb[i][l], vb[i][l] per network, zero before step 1;
+ *                       nets[i].W, b updated in place) and one advance of the
+ *                       device step counter *step_dev (0 before the first
+ *                       step), all in the same graph.
+ *   pinn_batch_configure  the number of lanes (1..16; widths beyond it share
+ *                       lanes) and graph on/off.
+ *   pinn_batch_launches  grouped launches per step of the current schedule.
+ *   pinn_batch_autotune  runs pinn_plan_autotune on every network (networks
+ *                       sharing a cache key are timed once), then times
+ *                       `reps` steps for 1, 2 and 4 lanes and keeps the fastest. */
 pinn_status pinn_batch_create(int32_t n, const pinn_net *nets, const pinn_pde *pdes, const int64_t *max_points,
                               int32_t prec, uint32_t flags, pinn_batch *out);
 pinn_status pinn_batch_destroy(pinn_batch batch);
@@ -241,6 +323,20 @@ pinn_status pinn_batch_configure(pinn_batch batch, int32_t n_streams, int32_t us
 pinn_status pinn_batch_step(pinn_batch batch, const pinn_net *nets, const pinn_pde *pdes, const float *const *x,
                             const int64_t *N, float *loss, float *const *const *dW, float *const *const *db,
                             void *stream);
+pinn_status pinn_batch_train_step(pinn_batch batch, const pinn_net *nets, const pinn_pde *pdes,
+                                  const float *const *x, const int64_t *N, float *loss, float *const *const *dW,
+                                  float *const *const *db, float *const *const *mW, float *const *const *vW,
+                                  float *const *const *mb, float *const *const *vb, const struct pinn_adam_s *hp,
+                                  int64_t *step_dev, void *stream);
+pinn_status pinn_batch_launches(pinn_batch batch, int64_t *launches);
+/* The tuning of network i (0 <= i < n), as pinn_plan_get_tuning. */
+pinn_status pinn_batch_get_tuning(pinn_batch batch, int32_t i, pinn_tuning *tuning);
+/* Launch timing of one kernel class over a batch's steps, as
+ * pinn_plan_profile: each grouped launch of that class is bracketed by a pair
+ * of hipEvents on its lane's stream.  While a class is selected the steps run
+ * without the graph (the same grouped launches, enqueued one by one). */
+pinn_status pinn_batch_profile(pinn_batch batch, int32_t kernel_class);
+pinn_status pinn_batch_profile_read(pinn_batch batch, double *total_ms, int64_t *launches);
 pinn_status pinn_batch_autotune(pinn_batch batch, const pinn_net *nets, const pinn_pde *pdes,
                                 const float *const *x, const int64_t *N, float *loss, float *const *const *dW,
                                 float *const *const *db, int32_t reps, int32_t *best_streams, double *best_ms,
@@ -264,7 +360,7 @@ pinn_status pinn_batch_autotune(pinn_batch batch, const pinn_net *nets, const pi
  * Stream-ordered and asynchronous; allocates nothing, so it may be captured
  * into a graph with the step that produces the gradients.  PINN_ERR_ARG on a
  * NULL pointer, a bad shape or a bad hyperparameter (checked on the host). */
-typedef struct {
+typedef struct pinn_adam_s {
   double lr, beta1, beta2, eps;
 } pinn_adam;
 pinn_status pinn_adam_step(int32_t n_layers, const int32_t *dims, float *const *W, float *const *b,

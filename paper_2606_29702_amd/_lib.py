@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpinnjet.so")
 
 PINN_OK = 0
+PINN_ERR_ARG, PINN_ERR_UNSUPPORTED = -1, -2
 STATUS_NAMES = {0: "PINN_OK", -1: "PINN_ERR_ARG", -2: "PINN_ERR_UNSUPPORTED", -3: "PINN_ERR_NOMEM",
                 -4: "PINN_ERR_DEVICE", -5: "PINN_ERR_STATE", -6: "PINN_ERR_CAP"}
 KINDS = {"burgers": 1, "ns": 2, "ks": 3, "heat": 4, "aniso": 5, "burgers_bc": 6}
@@ -30,7 +31,10 @@ EXPORTS = ["pinn_plan_create", "pinn_plan_destroy", "pinn_plan_memory", "pinn_je
            "pinn_plan_set_tuning", "pinn_plan_autotune", "pinn_batch_create", "pinn_batch_destroy",
            "pinn_batch_configure", "pinn_batch_step", "pinn_batch_autotune", "pinn_graph_capture",
            "pinn_graph_launch", "pinn_graph_destroy", "pinn_adam_step", "pinn_graph_capture_train",
-           "pinn_jet_step_noalloc", "pinn_jet_backward_cot"]
+           "pinn_jet_step_noalloc", "pinn_jet_backward_cot", "pinn_batch_train_step", "pinn_batch_launches",
+           "pinn_batch_profile", "pinn_batch_profile_read", "pinn_batch_get_tuning",
+           "pinn_tuning_cache_clear", "pinn_tuning_cache_size", "pinn_tuning_cache_save", "pinn_tuning_cache_load",
+           "pinn_jet_loss", "pinn_jet_loss_backward"]
 KERNEL_CLASSES = {"layer_fwd": 1, "layer_bwd": 2, "dw_hidden": 3, "out_fwd": 4, "out_bwd": 5,
                   "seed_fwd": 6, "other": 7, "bwd_dw": 8}
 
@@ -48,6 +52,16 @@ class Net(ctypes.Structure):
 
 class Pde(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("coef", ctypes.c_double * 4)]
+
+
+class Segment(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int32), ("data", ctypes.c_int32), ("begin", ctypes.c_int64),
+                ("count", ctypes.c_int64), ("weight", ctypes.c_double), ("mask", ctypes.c_uint32),
+                ("param", ctypes.c_double * 4)]
+
+
+SEG_TYPES = {"pde": 0, "dirichlet": 1, "periodic": 2}
+SEG_DATA = {"zero": 0, "const": 1, "sin": 2}
 
 
 class Adam(ctypes.Structure):
@@ -85,6 +99,19 @@ def _load():
     lib.pinn_batch_destroy.argtypes = [vp]
     lib.pinn_batch_configure.argtypes = [vp, i32, i32]
     lib.pinn_batch_step.argtypes = [vp, NetP, PdeP, pp, i64p, vp, pp, pp, vp]
+    lib.pinn_batch_train_step.argtypes = [vp, NetP, PdeP, pp, i64p, vp, pp, pp, pp, pp, pp, pp, ctypes.POINTER(Adam),
+                                          vp, vp]
+    SegP = ctypes.POINTER(Segment)
+    lib.pinn_jet_loss.argtypes = [vp, NetP, PdeP, SegP, i32, vp, i64, vp, vp, vp]
+    lib.pinn_jet_loss_backward.argtypes = [vp, NetP, PdeP, SegP, i32, vp, i64, pp, pp, vp]
+    lib.pinn_batch_launches.argtypes = [vp, i64p]
+    lib.pinn_batch_get_tuning.argtypes = [vp, i32, TuneP]
+    lib.pinn_batch_profile.argtypes = [vp, i32]
+    lib.pinn_batch_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.pinn_tuning_cache_clear.argtypes = []
+    lib.pinn_tuning_cache_size.argtypes = [i64p]
+    lib.pinn_tuning_cache_save.argtypes = [ctypes.c_char_p]
+    lib.pinn_tuning_cache_load.argtypes = [ctypes.c_char_p]
     lib.pinn_batch_autotune.argtypes = [vp, NetP, PdeP, pp, i64p, vp, pp, pp, i32,
                                         ctypes.POINTER(ctypes.c_int32), dptr, vp]
     lib.pinn_graph_capture.argtypes = [vp, NetP, PdeP, vp, i64, vp, vp, pp, pp, pp]
@@ -105,7 +132,10 @@ def _load():
                  "pinn_plan_autotune", "pinn_batch_create", "pinn_batch_destroy", "pinn_batch_configure",
                  "pinn_batch_step", "pinn_batch_autotune", "pinn_graph_capture", "pinn_graph_launch",
                  "pinn_graph_destroy", "pinn_adam_step", "pinn_graph_capture_train", "pinn_jet_step_noalloc",
-                 "pinn_jet_backward_cot"):
+                 "pinn_jet_backward_cot", "pinn_batch_train_step", "pinn_batch_launches", "pinn_batch_profile",
+                 "pinn_batch_profile_read", "pinn_batch_get_tuning", "pinn_tuning_cache_clear",
+                 "pinn_tuning_cache_size", "pinn_tuning_cache_save", "pinn_tuning_cache_load", "pinn_jet_loss",
+                 "pinn_jet_loss_backward"):
         getattr(lib, name).restype = ctypes.c_int32
     return lib
 

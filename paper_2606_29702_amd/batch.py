@@ -1,6 +1,8 @@
 """Ensembles of independent partial-jet PINNs stepped together (C ABI
-pinn_batch_*): one plan per network, the networks run concurrently on side
-streams, and the whole step is captured once into a HIP graph and replayed.
+pinn_batch_*): one plan per network; every phase of the step is one grouped
+launch over all networks at that phase (each on its own grid), networks of
+one width share a stream, and the whole step (optionally with the Adam
+update) is captured once into a HIP graph and replayed.
 
 Gradient and loss buffers are owned by the batch object and reused across
 steps, so that repeated steps with the same parameter and point tensors
@@ -13,7 +15,7 @@ from typing import List, Optional, Sequence, Tuple
 
 import torch
 
-from ._lib import KINDS, PRECISIONS, Net, Pde, check, lib, ptr_array
+from ._lib import Adam as _AdamHP, KINDS, PRECISIONS, Net, Pde, Tuning, check, lib, ptr_array
 from .jet import DEFAULT_COEF, _check_tensor, _stream
 
 
@@ -116,3 +118,64 @@ class PinnBatch:
                                       ctypes.cast(dbs, pp), int(reps), ctypes.byref(bs), ctypes.byref(ms),
                                       _stream()))
         return bs.value, ms.value
+
+    def profile(self, kernel_class: str) -> None:
+        """Start timing grouped launches of one kernel class ('off' to stop); steps run eagerly meanwhile."""
+        from ._lib import KERNEL_CLASSES
+        cls = 0 if kernel_class == "off" else KERNEL_CLASSES[kernel_class]
+        check(lib.pinn_batch_profile(self.handle, cls))
+
+    def profile_read(self):
+        """(summed kernel milliseconds, launches) since profile(); waits for the events."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        check(lib.pinn_batch_profile_read(self.handle, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def tuning(self, i: int) -> dict:
+        """The tuning of network i (split count, forward point tile, fused weight gradient)."""
+        t = Tuning()
+        check(lib.pinn_batch_get_tuning(self.handle, int(i), ctypes.byref(t)))
+        return {"dw_splits": t.dw_splits, "fwd_points": t.fwd_points, "bwd_fused": t.bwd_fused}
+
+    def launches(self) -> int:
+        """Grouped launches per step of the current schedule."""
+        n = ctypes.c_int64()
+        check(lib.pinn_batch_launches(self.handle, ctypes.byref(n)))
+        return n.value
+
+    def train_step(self, params_list, xs, adam: "BatchAdam"):
+        """One residual + gradient + Adam step of every network (parameters
+        updated in place; the step count advances on the device)."""
+        nets, xp, Ns, dWs, dbs, _ = self._marshal(params_list, xs)
+        pp = ctypes.POINTER(ctypes.c_void_p)
+        check(lib.pinn_batch_train_step(self.handle, nets, self._pdes, ctypes.cast(xp, pp), Ns,
+                                        ctypes.c_void_p(self.loss.data_ptr()), ctypes.cast(dWs, pp),
+                                        ctypes.cast(dbs, pp), ctypes.cast(adam._mW, pp), ctypes.cast(adam._vW, pp),
+                                        ctypes.cast(adam._mb, pp), ctypes.cast(adam._vb, pp), ctypes.byref(adam.hp),
+                                        ctypes.c_void_p(adam.step.data_ptr()), _stream()))
+        return self.loss, self.grads
+
+
+class BatchAdam:
+    """Adam moments (zero) for the parameters of every network of a batch, and
+    the device step counter of the batch's training step."""
+
+    def __init__(self, params_list, lr: float = 1e-3, betas: Tuple[float, float] = (0.9, 0.999),
+                 eps: float = 1e-8):
+        self.hp = _AdamHP(float(lr), float(betas[0]), float(betas[1]), float(eps))
+        self.m = [[(torch.zeros_like(W), torch.zeros_like(b)) for W, b in ps] for ps in params_list]
+        self.v = [[(torch.zeros_like(W), torch.zeros_like(b)) for W, b in ps] for ps in params_list]
+        dev = params_list[0][0][0].device
+        self.step = torch.zeros((), device=dev, dtype=torch.int64)
+        self._keep = []
+
+        def table(pairs, k):
+            arrs = []
+            for ps in pairs:
+                p, keep = ptr_array([t[k].data_ptr() for t in ps])
+                self._keep.append(keep)
+                arrs.append(ctypes.cast(p, ctypes.c_void_p))
+            return (ctypes.c_void_p * len(arrs))(*arrs)
+
+        self._mW, self._mb = table(self.m, 0), table(self.m, 1)
+        self._vW, self._vb = table(self.v, 0), table(self.v, 1)

@@ -19,7 +19,12 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpinnjet.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
+# -ffp-contract=on: a*b + c is fused into one FMA only within a single source
+# expression, never across statements.  Kernels that inline the same device
+# code (the direct and grouped launches of a body, the stored-state and
+# recompute variants of the backward) then round identically, which the
+# bitwise checkpoint, graph and ensemble equalities rely on.
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 

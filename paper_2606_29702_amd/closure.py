@@ -8,14 +8,26 @@ i != j a mixed second derivative, and so on.  The recursion for a pure
 derivative of order k along x_i uses the pure derivatives of orders 1..k-1
 along x_i; a mixed second derivative along (x_i, x_j) uses the first
 derivatives along x_i and x_j.  Host-side helper: the GPU kernels carry
-compile-time channel sets, one per PDE kind, and `kind_for` names the kind
-whose set is exactly a given closure.
+compile-time channel sets, one per PDE kind (KIND_CHANNELS), `kind_for` names
+the kind whose set is exactly a given closure and `resolve_kind` picks the
+compiled kind for a residual's derivative list (PinnPlan.for_derivatives).
 """
 from __future__ import annotations
 
 from typing import Iterable, List, Optional, Sequence, Tuple
 
 Deriv = Tuple[int, ...]
+
+# The channel sets the compiled kernels carry, in the library's ABI order
+# (channel c of output o is jets[o][c]): (direction, order), order 0 the value.
+KIND_CHANNELS = {
+    "burgers": [(0, 0), (1, 1), (0, 1), (0, 2)],                             # inputs (x, t)
+    "ns": [(0, 0), (0, 1), (1, 1), (0, 2), (1, 2)],                          # inputs (x, y)
+    "ks": [(0, 0), (1, 1), (0, 1), (0, 2), (0, 3), (0, 4)],                  # inputs (x, t)
+    "heat": [(0, 0), (3, 1), (0, 1), (1, 1), (2, 1), (0, 2), (1, 2), (2, 2)],  # inputs (x, y, z, t)
+    "aniso": [(0, 0), (0, 1), (1, 1), (0, 2), (1, 2), ((0, 1), 2)],          # inputs (x, y)
+    "burgers_bc": [(0, 0)],                                                  # inputs (x, t)
+}
 
 
 def _as_channel(dv: Deriv):
@@ -63,3 +75,16 @@ def kind_for(channel_list: Sequence, kind_channels: dict) -> Optional[str]:
         if set(chans) == want:
             return kind
     return None
+
+
+def resolve_kind(required: Iterable[Deriv], pde: Optional[str] = None) -> Optional[str]:
+    """The compiled kind that serves a residual using the derivatives
+    `required`: with `pde` given, that kind if its channel set contains the
+    closure (else None); without, the one kind whose set equals the closure
+    (None if no kind or several do)."""
+    want = set(channels(required))
+    if pde is not None:
+        have = KIND_CHANNELS.get(pde)
+        return pde if have is not None and want <= set(have) else None
+    hits = [k for k, chans in KIND_CHANNELS.items() if set(chans) == want]
+    return hits[0] if len(hits) == 1 else None

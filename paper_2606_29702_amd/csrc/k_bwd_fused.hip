@@ -14,6 +14,7 @@
 // contracts over the rows (point, channel) of the tile, 16 at a time
 // (MFMA 16x16x16), with each lane gathering its 4 rows down a column.
 #include "dev_common.hpp"
+#include "group.hpp"
 #include "kernels.hpp"
 
 namespace pj {
@@ -83,184 +84,195 @@ __device__ __forceinline__ void tile_gemm(f32x4 (&acc)[TPW][C], const T *__restr
 }
 
 template <class CH, class T, int W, int NW, int TPW, bool TOP, int DOUT, int ZSRC>
-__global__ __launch_bounds__(NW * 64) void k_bwd_dw(BwdArgs args, float *__restrict__ part, int64_t n_tiles) {
-  using M16 = Mma16<T>;
-  constexpr int C = CH::C, P = 16;
-  constexpr bool FAST = sizeof(T) == 2;
-  constexpr int pitch = C * W + 8;
-  constexpr int JW = W / NW;      // gradient rows owned by one wave
-  constexpr int JT = JW / 16, KT = W / 16;
-  constexpr int ROWS = P * C;     // contraction rows per tile (multiple of 16)
-  static_assert(JW % 16 == 0 && ROWS % 16 == 0, "tile shape");
-  // 16-byte pieces per thread when staging both tiles: all in flight at once
-  constexpr int SNB = (2 * P * C * W * (int)sizeof(T) / 16 + NW * 64 - 1) / (NW * 64);
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *lds_b = reinterpret_cast<T *>(smem_raw);  // Zbar_{m+1}, then Zbar_m
-  T *lds_a = lds_b + P * pitch;                // A_{m-1}
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int r = lane & 15, g = lane >> 4;
-  constexpr int64_t ps = (int64_t)C * W;
-  const int jt0 = wave * TPW;  // neuron tiles of this wave in the layer GEMMs (one 16-point tile)
+struct KBwdDw {
+  static constexpr int NT = NW * 64;
+  struct Args {
+    BwdArgs args;
+    float * part;
+    int64_t n_tiles;
+  };
+  static __device__ __forceinline__ void run(const Args &a_, VBlock vb) {
+    const BwdArgs &args = a_.args;
+    float *__restrict__ part = a_.part;
+    int64_t n_tiles = a_.n_tiles;
+    using M16 = Mma16<T>;
+    constexpr int C = CH::C, P = 16;
+    constexpr bool FAST = sizeof(T) == 2;
+    constexpr int pitch = C * W + 8;
+    constexpr int JW = W / NW;      // gradient rows owned by one wave
+    constexpr int JT = JW / 16, KT = W / 16;
+    constexpr int ROWS = P * C;     // contraction rows per tile (multiple of 16)
+    static_assert(JW % 16 == 0 && ROWS % 16 == 0, "tile shape");
+    // 16-byte pieces per thread when staging both tiles: all in flight at once
+    constexpr int SNB = (2 * P * C * W * (int)sizeof(T) / 16 + NW * 64 - 1) / (NW * 64);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *lds_b = reinterpret_cast<T *>(smem_raw);  // Zbar_{m+1}, then Zbar_m
+    T *lds_a = lds_b + P * pitch;                // A_{m-1}
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    constexpr int64_t ps = (int64_t)C * W;
+    const int jt0 = wave * TPW;  // neuron tiles of this wave in the layer GEMMs (one 16-point tile)
 
-  f32x4 dacc[JT][KT];
-#pragma unroll
-  for (int a = 0; a < JT; ++a)
-#pragma unroll
-    for (int b = 0; b < KT; ++b) dacc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-  float db = 0.f;
+    f32x4 dacc[JT][KT];
+  #pragma unroll
+    for (int a = 0; a < JT; ++a)
+  #pragma unroll
+      for (int b = 0; b < KT; ++b) dacc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float db = 0.f;
 
-  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    const int64_t nb = tile * P;
-    if constexpr (!TOP)
-      stage_rows<T, SNB, true>(lds_b, static_cast<const T *>(args.Zb_in) + nb * ps,
-                              static_cast<const T *>(args.A_prev) + nb * ps, P, C * W, pitch, tid, NW * 64);
-    else
-      stage_rows<T, SNB, false>(lds_a, static_cast<const T *>(args.A_prev) + nb * ps, nullptr, P, C * W, pitch, tid,
-                               NW * 64);
-    __syncthreads();
+    for (int64_t tile = vb.x; tile < n_tiles; tile += vb.gx) {
+      const int64_t nb = tile * P;
+      if constexpr (!TOP)
+        stage_rows<T, SNB, true>(lds_b, static_cast<const T *>(args.Zb_in) + nb * ps,
+                                static_cast<const T *>(args.A_prev) + nb * ps, P, C * W, pitch, tid, NW * 64);
+      else
+        stage_rows<T, SNB, false>(lds_a, static_cast<const T *>(args.A_prev) + nb * ps, nullptr, P, C * W, pitch, tid,
+                                 NW * 64);
+      __syncthreads();
 
-    f32x4 acc_a[TPW][C];
-    if constexpr (!TOP) tile_gemm<T, C, TPW>(acc_a, static_cast<const T *>(args.WT), lds_b, pitch, jt0, W, lane);
-    f32x4 acc_z[TPW][C];
-    if constexpr (ZSRC == Z_FROM_GEMM)
-      tile_gemm<T, C, TPW>(acc_z, static_cast<const T *>(args.Wz), lds_a, pitch, jt0, W, lane);
-    __syncthreads();  // the Zbar_{m+1} tile is consumed; it now receives Zbar_m
+      f32x4 acc_a[TPW][C];
+      if constexpr (!TOP) tile_gemm<T, C, TPW>(acc_a, static_cast<const T *>(args.WT), lds_b, pitch, jt0, W, lane);
+      f32x4 acc_z[TPW][C];
+      if constexpr (ZSRC == Z_FROM_GEMM)
+        tile_gemm<T, C, TPW>(acc_z, static_cast<const T *>(args.Wz), lds_a, pitch, jt0, W, lane);
+      __syncthreads();  // the Zbar_{m+1} tile is consumed; it now receives Zbar_m
 
-    const int64_t n = nb + r;
-    T *Zb_out = static_cast<T *>(args.Zb_out);
-#pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-      const int mb = (jt0 + t) * 16 + 4 * g;
-      float zz[4][C], s1[4];
-      if constexpr (ZSRC == Z_FROM_S) {
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-          const f32x4 v = *reinterpret_cast<const f32x4 *>(args.S_in + n * ps + c * W + mb);
-#pragma unroll
-          for (int i = 0; i < 4; ++i) zz[i][c] = v[i];
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) s1[i] = (1.f - zz[i][0]) * (1.f + zz[i][0]);
-      } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-#pragma unroll
-          for (int c = 0; c < C; ++c) zz[i][c] = acc_z[t][c][i];
-          const TanhS ts = tanh_eval<FAST>(zz[i][0] + args.bz[mb + i]);
-          zz[i][0] = ts.s;
-          s1[i] = ts.s1;
-        }
-      }
-      float ab[4][C];
-      if constexpr (TOP) {
-        float ub[DOUT][C];
-#pragma unroll
-        for (int o = 0; o < DOUT; ++o)
-#pragma unroll
-          for (int c = 0; c < C; ++c) ub[o][c] = args.ubar[(n * DOUT + o) * C + c];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
+      const int64_t n = nb + r;
+      T *Zb_out = static_cast<T *>(args.Zb_out);
+  #pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        const int mb = (jt0 + t) * 16 + 4 * g;
+        float zz[4][C], s1[4];
+        if constexpr (ZSRC == Z_FROM_S) {
+  #pragma unroll
           for (int c = 0; c < C; ++c) {
-            float sacc = 0.f;
-#pragma unroll
-            for (int o = 0; o < DOUT; ++o) sacc += args.WL[o * W + mb + i] * ub[o][c];
-            ab[i][c] = sacc;
+            const f32x4 v = *reinterpret_cast<const f32x4 *>(args.S_in + n * ps + c * W + mb);
+  #pragma unroll
+            for (int i = 0; i < 4; ++i) zz[i][c] = v[i];
           }
-      } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int c = 0; c < C; ++c) ab[i][c] = acc_a[t][c][i];
-      }
-      float out[4][C];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        float zb[C];
-        jet_adjoint<CH>(ab[i], zz[i][0], s1[i], zz[i], zb);
-#pragma unroll
-        for (int c = 0; c < C; ++c) out[i][c] = zb[c];
-      }
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        store4(Zb_out + n * ps + c * W + mb, out[0][c], out[1][c], out[2][c], out[3][c]);
-        store4(lds_b + r * pitch + c * W + mb, out[0][c], out[1][c], out[2][c], out[3][c]);
-      }
-    }
-    __syncthreads();  // Zbar_m tile complete in LDS
-
-    // db_m: value rows (channel 0) of the tile
-    if (tid < W) {
-#pragma unroll
-      for (int p = 0; p < P; ++p) db += to_f32(lds_b[p * pitch + tid]);
-    }
-    // dW_m += Zbar_m^T A_{m-1} over the tile's rows (point, channel), 16 rows
-    // per step.  Below the top layer the steps stay rolled, which keeps the
-    // gathered operands of a single step in registers (two waves per SIMD
-    // instead of one); the top-layer variant keeps fewer accumulators live and
-    // unrolls.
-    auto dw_step = [&](int s) {
-      int off[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int row = 16 * s + 4 * g + e;
-        off[e] = (row / C) * pitch + (row % C) * W;
-      }
-      typename M16::frag fa[JT], fb[KT];
-      if constexpr (sizeof(T) == 2) {
-        // LDS transpose read: within each group of 16 lanes, output lane
-        // 4a + e receives element e of the 8-byte reads of lanes a, a + 4,
-        // a + 8, a + 12.  Lane r of group g therefore reads row
-        // 16 s + 4 g + r / 4 at columns 4 (r % 4) .. + 3 of the 16-column
-        // tile, and receives column r of rows 16 s + 4 g .. + 3: its operand.
-        const int row = 16 * s + 4 * g + (r >> 2);
-        const int roff = (row / C) * pitch + (row % C) * W + 4 * (r & 3);
-#pragma unroll
-        for (int jt = 0; jt < JT; ++jt) fa[jt] = lds_tr16<T>(lds_b + roff + wave * JW + jt * 16);
-#pragma unroll
-        for (int kt = 0; kt < KT; ++kt) fb[kt] = lds_tr16<T>(lds_a + roff + kt * 16);
-      } else {
-#pragma unroll
-        for (int jt = 0; jt < JT; ++jt) {
-          const int j = wave * JW + jt * 16 + r;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) fa[jt][e] = lds_b[off[e] + j];
+  #pragma unroll
+          for (int i = 0; i < 4; ++i) s1[i] = (1.f - zz[i][0]) * (1.f + zz[i][0]);
+        } else {
+  #pragma unroll
+          for (int i = 0; i < 4; ++i) {
+  #pragma unroll
+            for (int c = 0; c < C; ++c) zz[i][c] = acc_z[t][c][i];
+            const TanhS ts = tanh_eval<FAST>(zz[i][0] + args.bz[mb + i]);
+            zz[i][0] = ts.s;
+            s1[i] = ts.s1;
+          }
         }
-#pragma unroll
-        for (int kt = 0; kt < KT; ++kt) {
+        float ab[4][C];
+        if constexpr (TOP) {
+          float ub[DOUT][C];
+  #pragma unroll
+          for (int o = 0; o < DOUT; ++o)
+  #pragma unroll
+            for (int c = 0; c < C; ++c) ub[o][c] = args.ubar[(n * DOUT + o) * C + c];
+  #pragma unroll
+          for (int i = 0; i < 4; ++i)
+  #pragma unroll
+            for (int c = 0; c < C; ++c) {
+              float sacc = 0.f;
+  #pragma unroll
+              for (int o = 0; o < DOUT; ++o) sacc += args.WL[o * W + mb + i] * ub[o][c];
+              ab[i][c] = sacc;
+            }
+        } else {
+  #pragma unroll
+          for (int i = 0; i < 4; ++i)
+  #pragma unroll
+            for (int c = 0; c < C; ++c) ab[i][c] = acc_a[t][c][i];
+        }
+        float out[4][C];
+  #pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          float zb[C];
+          jet_adjoint<CH>(ab[i], zz[i][0], s1[i], zz[i], zb);
+  #pragma unroll
+          for (int c = 0; c < C; ++c) out[i][c] = zb[c];
+        }
+  #pragma unroll
+        for (int c = 0; c < C; ++c) {
+          store4(Zb_out + n * ps + c * W + mb, out[0][c], out[1][c], out[2][c], out[3][c]);
+          store4(lds_b + r * pitch + c * W + mb, out[0][c], out[1][c], out[2][c], out[3][c]);
+        }
+      }
+      __syncthreads();  // Zbar_m tile complete in LDS
+
+      // db_m: value rows (channel 0) of the tile
+      if (tid < W) {
+  #pragma unroll
+        for (int p = 0; p < P; ++p) db += to_f32(lds_b[p * pitch + tid]);
+      }
+      // dW_m += Zbar_m^T A_{m-1} over the tile's rows (point, channel), 16 rows
+      // per step.  Below the top layer the steps stay rolled, which keeps the
+      // gathered operands of a single step in registers (two waves per SIMD
+      // instead of one); the top-layer variant keeps fewer accumulators live and
+      // unrolls.
+      auto dw_step = [&](int s) {
+        int off[4];
+  #pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = 16 * s + 4 * g + e;
+          off[e] = (row / C) * pitch + (row % C) * W;
+        }
+        typename M16::frag fa[JT], fb[KT];
+        if constexpr (sizeof(T) == 2) {
+          // LDS transpose read: within each group of 16 lanes, output lane
+          // 4a + e receives element e of the 8-byte reads of lanes a, a + 4,
+          // a + 8, a + 12.  Lane r of group g therefore reads row
+          // 16 s + 4 g + r / 4 at columns 4 (r % 4) .. + 3 of the 16-column
+          // tile, and receives column r of rows 16 s + 4 g .. + 3: its operand.
+          const int row = 16 * s + 4 * g + (r >> 2);
+          const int roff = (row / C) * pitch + (row % C) * W + 4 * (r & 3);
+  #pragma unroll
+          for (int jt = 0; jt < JT; ++jt) fa[jt] = lds_tr16<T>(lds_b + roff + wave * JW + jt * 16);
+  #pragma unroll
+          for (int kt = 0; kt < KT; ++kt) fb[kt] = lds_tr16<T>(lds_a + roff + kt * 16);
+        } else {
+  #pragma unroll
+          for (int jt = 0; jt < JT; ++jt) {
+            const int j = wave * JW + jt * 16 + r;
+  #pragma unroll
+            for (int e = 0; e < 4; ++e) fa[jt][e] = lds_b[off[e] + j];
+          }
+  #pragma unroll
+          for (int kt = 0; kt < KT; ++kt) {
+            const int k = kt * 16 + r;
+  #pragma unroll
+            for (int e = 0; e < 4; ++e) fb[kt][e] = lds_a[off[e] + k];
+          }
+        }
+  #pragma unroll
+        for (int jt = 0; jt < JT; ++jt)
+  #pragma unroll
+          for (int kt = 0; kt < KT; ++kt) M16::mma(dacc[jt][kt], fa[jt], fb[kt]);
+      };
+      if constexpr (TOP) {
+  #pragma unroll
+        for (int s = 0; s < ROWS / 16; ++s) dw_step(s);
+      } else {
+  #pragma unroll 1
+        for (int s = 0; s < ROWS / 16; ++s) dw_step(s);
+      }
+      __syncthreads();  // before the next tile is staged over both buffers
+    }
+
+    float *pp = part + (int64_t)vb.x * ((int64_t)W * W + W);
+  #pragma unroll
+    for (int jt = 0; jt < JT; ++jt)
+  #pragma unroll
+      for (int kt = 0; kt < KT; ++kt)
+  #pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int j = wave * JW + jt * 16 + 4 * g + i;
           const int k = kt * 16 + r;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) fb[kt][e] = lds_a[off[e] + k];
+          pp[(int64_t)j * W + k] = dacc[jt][kt][i];
         }
-      }
-#pragma unroll
-      for (int jt = 0; jt < JT; ++jt)
-#pragma unroll
-        for (int kt = 0; kt < KT; ++kt) M16::mma(dacc[jt][kt], fa[jt], fb[kt]);
-    };
-    if constexpr (TOP) {
-#pragma unroll
-      for (int s = 0; s < ROWS / 16; ++s) dw_step(s);
-    } else {
-#pragma unroll 1
-      for (int s = 0; s < ROWS / 16; ++s) dw_step(s);
-    }
-    __syncthreads();  // before the next tile is staged over both buffers
+    if (tid < W) pp[(int64_t)W * W + tid] = db;
   }
-
-  float *pp = part + (int64_t)blockIdx.x * ((int64_t)W * W + W);
-#pragma unroll
-  for (int jt = 0; jt < JT; ++jt)
-#pragma unroll
-    for (int kt = 0; kt < KT; ++kt)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int j = wave * JW + jt * 16 + 4 * g + i;
-        const int k = kt * 16 + r;
-        pp[(int64_t)j * W + k] = dacc[jt][kt][i];
-      }
-  if (tid < W) pp[(int64_t)W * W + tid] = db;
-}
+};
 
 // Double-buffered form of k_bwd_dw for 16-bit operands below the top layer,
 // with z recomputed from A_{m-1}.  The tiles are stored in LDS without row
@@ -340,162 +352,173 @@ __device__ __forceinline__ void swz_gemm(f32x4 (&acc)[TPW][C], const T *__restri
 }
 
 template <class CH, class T, int W, int NW, int TPW, int DOUT>
-__global__ __launch_bounds__(NW * 64) void k_bwd_dw_db(BwdArgs args, float *__restrict__ part, int64_t n_tiles) {
-  using M = Mma<T>;
-  using M16 = Mma16<T>;
-  using L = SwzTile<T, CH::C, W>;
-  constexpr int C = CH::C, P = 16;
-  constexpr int JW = W / NW;
-  constexpr int JT = JW / 16, KT = W / 16, KS = W / 32;
-  constexpr int ROWS = P * C;
-  static_assert(JW % 16 == 0 && ROWS % 16 == 0, "tile shape");
-  // two buffer pairs [Zbar][A] as separate objects, so that the compiler can
-  // tell the pair being prefetched from the pair being read
-  __shared__ __align__(16) T pair0[2 * L::ELEMS];
-  __shared__ __align__(16) T pair1[2 * L::ELEMS];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int r = lane & 15, g = lane >> 4;
-  constexpr int64_t ps = (int64_t)C * W;
-  const int jt0 = wave * TPW;
-  const T *Zb_in = static_cast<const T *>(args.Zb_in);
-  const T *A_prev = static_cast<const T *>(args.A_prev);
-  const T *WT = static_cast<const T *>(args.WT);
-  const T *Wz = static_cast<const T *>(args.Wz);
-  T *Zb_out = static_cast<T *>(args.Zb_out);
-
-  f32x4 dacc[JT][KT];
-#pragma unroll
-  for (int a = 0; a < JT; ++a)
-#pragma unroll
-    for (int b = 0; b < KT; ++b) dacc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-  float db = 0.f;
-
-  if (blockIdx.x < n_tiles) {
-    const int64_t nb = (int64_t)blockIdx.x * P;
-    prefetch_tile<T, C, W, NW>(pair0, Zb_in + nb * ps, wave, lane);
-    prefetch_tile<T, C, W, NW>(pair0 + L::ELEMS, A_prev + nb * ps, wave, lane);
-  }
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-
-  // one tile in buffer pair `cur`; the next one streams into pair `nxt`
-  auto step = [&](int64_t tile, T *cur, T *nxt) __attribute__((always_inline)) {
-    const int64_t nb = tile * P;
-    T *zb_t = cur;
-    T *a_t = cur + L::ELEMS;
-
-    // the GEMMs (their weight fragments stream from L2 ahead of use)
-    f32x4 acc_a[TPW][C], acc_z[TPW][C];
-    swz_gemm<T, C, TPW, W>(acc_a, WT, zb_t, jt0, lane);
-    swz_gemm<T, C, TPW, W>(acc_z, Wz, a_t, jt0, lane);
-    // tanh of the recomputed z_0 (with the bias, a global load) before the
-    // prefetch below is issued: the load counter completes in order, so any
-    // load waited on after the prefetch would wait for the prefetch too
-    float sv[TPW][4], s1v[TPW][4];
-#pragma unroll
-    for (int t = 0; t < TPW; ++t)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const TanhS ts = tanh_eval<true>(acc_z[t][0][i] + args.bz[(jt0 + t) * 16 + 4 * g + i]);
-        sv[t][i] = ts.s;
-        s1v[t][i] = ts.s1;
-      }
-    __syncthreads();  // the Zbar_{m+1} tile is consumed; it now receives Zbar_m
-
-    // the next tile streams into the other buffer pair during the adjoint and
-    // dW; every load issued so far completes first, so that no later wait on
-    // them also waits for the prefetch
-    __builtin_amdgcn_s_waitcnt(0);
-    const int64_t next = tile + gridDim.x;
-    if (next < n_tiles) {
-      prefetch_tile<T, C, W, NW>(nxt, Zb_in + next * P * ps, wave, lane);
-      prefetch_tile<T, C, W, NW>(nxt + L::ELEMS, A_prev + next * P * ps, wave, lane);
-    }
-
-    const int64_t n = nb + r;
-#pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-      const int mb = (jt0 + t) * 16 + 4 * g;
-      float zz[4][C], s1[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-#pragma unroll
-        for (int c = 1; c < C; ++c) zz[i][c] = acc_z[t][c][i];
-        zz[i][0] = sv[t][i];
-        s1[i] = s1v[t][i];
-      }
-      float out[4][C];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        float ab[C], zb[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) ab[c] = acc_a[t][c][i];
-        jet_adjoint<CH>(ab, zz[i][0], s1[i], zz[i], zb);
-#pragma unroll
-        for (int c = 0; c < C; ++c) out[i][c] = zb[c];
-      }
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        store4(Zb_out + n * ps + c * W + mb, out[0][c], out[1][c], out[2][c], out[3][c]);
-        store4(zb_t + L::at(r, c * W + mb), out[0][c], out[1][c], out[2][c], out[3][c]);
-      }
-    }
-    // Zbar_m tile complete in LDS.  A plain barrier after the LDS stores have
-    // completed: a full __syncthreads() would also wait for the prefetch.
-    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
-    __builtin_amdgcn_s_barrier();
-
-    if (tid < W) {
-#pragma unroll
-      for (int p = 0; p < P; ++p) db += to_f32(zb_t[L::at(p, tid)]);
-    }
-    // dW_m += Zbar_m^T A_{m-1}: 16 rows (point, channel) per step; LDS
-    // transpose reads give each lane column r of rows 16 s + 4 g .. + 3
-#pragma unroll 1
-    for (int s = 0; s < ROWS / 16; ++s) {
-      const int row = 16 * s + 4 * g + (r >> 2);
-      const int p = row / C, ch = row - p * C;
-      const int half = 4 * (r & 1);
-      typename M16::frag fa[JT], fb[KT];
-#pragma unroll
-      for (int jt = 0; jt < JT; ++jt) {
-        const int piece = ((ch * W + wave * JW + jt * 16) >> 3) + ((r & 3) >> 1);
-        fa[jt] = lds_tr16<T>(zb_t + p * L::RE + ((piece ^ p) << 3) + half);
-      }
-#pragma unroll
-      for (int kt = 0; kt < KT; ++kt) {
-        const int piece = ((ch * W + kt * 16) >> 3) + ((r & 3) >> 1);
-        fb[kt] = lds_tr16<T>(a_t + p * L::RE + ((piece ^ p) << 3) + half);
-      }
-#pragma unroll
-      for (int jt = 0; jt < JT; ++jt)
-#pragma unroll
-        for (int kt = 0; kt < KT; ++kt) M16::mma(dacc[jt][kt], fa[jt], fb[kt]);
-    }
-    __builtin_amdgcn_s_waitcnt(0);  // the next tile has landed
-    __syncthreads();                // and this tile's buffers are free
+struct KBwdDwDb {
+  static constexpr int NT = NW * 64;
+  struct Args {
+    BwdArgs args;
+    float * part;
+    int64_t n_tiles;
   };
-  for (int64_t tile = blockIdx.x; tile < n_tiles;) {
-    step(tile, pair0, pair1);
-    tile += gridDim.x;
-    if (tile >= n_tiles) break;
-    step(tile, pair1, pair0);
-    tile += gridDim.x;
-  }
+  static __device__ __forceinline__ void run(const Args &a_, VBlock vb) {
+    const BwdArgs &args = a_.args;
+    float *__restrict__ part = a_.part;
+    int64_t n_tiles = a_.n_tiles;
+    using M = Mma<T>;
+    using M16 = Mma16<T>;
+    using L = SwzTile<T, CH::C, W>;
+    constexpr int C = CH::C, P = 16;
+    constexpr int JW = W / NW;
+    constexpr int JT = JW / 16, KT = W / 16, KS = W / 32;
+    constexpr int ROWS = P * C;
+    static_assert(JW % 16 == 0 && ROWS % 16 == 0, "tile shape");
+    // two buffer pairs [Zbar][A] as separate objects, so that the compiler can
+    // tell the pair being prefetched from the pair being read
+    __shared__ __align__(16) T pair0[2 * L::ELEMS];
+    __shared__ __align__(16) T pair1[2 * L::ELEMS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    constexpr int64_t ps = (int64_t)C * W;
+    const int jt0 = wave * TPW;
+    const T *Zb_in = static_cast<const T *>(args.Zb_in);
+    const T *A_prev = static_cast<const T *>(args.A_prev);
+    const T *WT = static_cast<const T *>(args.WT);
+    const T *Wz = static_cast<const T *>(args.Wz);
+    T *Zb_out = static_cast<T *>(args.Zb_out);
 
-  float *pp = part + (int64_t)blockIdx.x * ((int64_t)W * W + W);
-#pragma unroll
-  for (int jt = 0; jt < JT; ++jt)
-#pragma unroll
-    for (int kt = 0; kt < KT; ++kt)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int j = wave * JW + jt * 16 + 4 * g + i;
-        const int k = kt * 16 + r;
-        pp[(int64_t)j * W + k] = dacc[jt][kt][i];
+    f32x4 dacc[JT][KT];
+  #pragma unroll
+    for (int a = 0; a < JT; ++a)
+  #pragma unroll
+      for (int b = 0; b < KT; ++b) dacc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float db = 0.f;
+
+    if (vb.x < n_tiles) {
+      const int64_t nb = (int64_t)vb.x * P;
+      prefetch_tile<T, C, W, NW>(pair0, Zb_in + nb * ps, wave, lane);
+      prefetch_tile<T, C, W, NW>(pair0 + L::ELEMS, A_prev + nb * ps, wave, lane);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+
+    // one tile in buffer pair `cur`; the next one streams into pair `nxt`
+    auto step = [&](int64_t tile, T *cur, T *nxt) __attribute__((always_inline)) {
+      const int64_t nb = tile * P;
+      T *zb_t = cur;
+      T *a_t = cur + L::ELEMS;
+
+      // the GEMMs (their weight fragments stream from L2 ahead of use)
+      f32x4 acc_a[TPW][C], acc_z[TPW][C];
+      swz_gemm<T, C, TPW, W>(acc_a, WT, zb_t, jt0, lane);
+      swz_gemm<T, C, TPW, W>(acc_z, Wz, a_t, jt0, lane);
+      // tanh of the recomputed z_0 (with the bias, a global load) before the
+      // prefetch below is issued: the load counter completes in order, so any
+      // load waited on after the prefetch would wait for the prefetch too
+      float sv[TPW][4], s1v[TPW][4];
+  #pragma unroll
+      for (int t = 0; t < TPW; ++t)
+  #pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const TanhS ts = tanh_eval<true>(acc_z[t][0][i] + args.bz[(jt0 + t) * 16 + 4 * g + i]);
+          sv[t][i] = ts.s;
+          s1v[t][i] = ts.s1;
+        }
+      __syncthreads();  // the Zbar_{m+1} tile is consumed; it now receives Zbar_m
+
+      // the next tile streams into the other buffer pair during the adjoint and
+      // dW; every load issued so far completes first, so that no later wait on
+      // them also waits for the prefetch
+      __builtin_amdgcn_s_waitcnt(0);
+      const int64_t next = tile + vb.gx;
+      if (next < n_tiles) {
+        prefetch_tile<T, C, W, NW>(nxt, Zb_in + next * P * ps, wave, lane);
+        prefetch_tile<T, C, W, NW>(nxt + L::ELEMS, A_prev + next * P * ps, wave, lane);
       }
-  if (tid < W) pp[(int64_t)W * W + tid] = db;
-}
+
+      const int64_t n = nb + r;
+  #pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        const int mb = (jt0 + t) * 16 + 4 * g;
+        float zz[4][C], s1[4];
+  #pragma unroll
+        for (int i = 0; i < 4; ++i) {
+  #pragma unroll
+          for (int c = 1; c < C; ++c) zz[i][c] = acc_z[t][c][i];
+          zz[i][0] = sv[t][i];
+          s1[i] = s1v[t][i];
+        }
+        float out[4][C];
+  #pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          float ab[C], zb[C];
+  #pragma unroll
+          for (int c = 0; c < C; ++c) ab[c] = acc_a[t][c][i];
+          jet_adjoint<CH>(ab, zz[i][0], s1[i], zz[i], zb);
+  #pragma unroll
+          for (int c = 0; c < C; ++c) out[i][c] = zb[c];
+        }
+  #pragma unroll
+        for (int c = 0; c < C; ++c) {
+          store4(Zb_out + n * ps + c * W + mb, out[0][c], out[1][c], out[2][c], out[3][c]);
+          store4(zb_t + L::at(r, c * W + mb), out[0][c], out[1][c], out[2][c], out[3][c]);
+        }
+      }
+      // Zbar_m tile complete in LDS.  A plain barrier after the LDS stores have
+      // completed: a full __syncthreads() would also wait for the prefetch.
+      __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+      __builtin_amdgcn_s_barrier();
+
+      if (tid < W) {
+  #pragma unroll
+        for (int p = 0; p < P; ++p) db += to_f32(zb_t[L::at(p, tid)]);
+      }
+      // dW_m += Zbar_m^T A_{m-1}: 16 rows (point, channel) per step; LDS
+      // transpose reads give each lane column r of rows 16 s + 4 g .. + 3
+  #pragma unroll 1
+      for (int s = 0; s < ROWS / 16; ++s) {
+        const int row = 16 * s + 4 * g + (r >> 2);
+        const int p = row / C, ch = row - p * C;
+        const int half = 4 * (r & 1);
+        typename M16::frag fa[JT], fb[KT];
+  #pragma unroll
+        for (int jt = 0; jt < JT; ++jt) {
+          const int piece = ((ch * W + wave * JW + jt * 16) >> 3) + ((r & 3) >> 1);
+          fa[jt] = lds_tr16<T>(zb_t + p * L::RE + ((piece ^ p) << 3) + half);
+        }
+  #pragma unroll
+        for (int kt = 0; kt < KT; ++kt) {
+          const int piece = ((ch * W + kt * 16) >> 3) + ((r & 3) >> 1);
+          fb[kt] = lds_tr16<T>(a_t + p * L::RE + ((piece ^ p) << 3) + half);
+        }
+  #pragma unroll
+        for (int jt = 0; jt < JT; ++jt)
+  #pragma unroll
+          for (int kt = 0; kt < KT; ++kt) M16::mma(dacc[jt][kt], fa[jt], fb[kt]);
+      }
+      __builtin_amdgcn_s_waitcnt(0);  // the next tile has landed
+      __syncthreads();                // and this tile's buffers are free
+    };
+    for (int64_t tile = vb.x; tile < n_tiles;) {
+      step(tile, pair0, pair1);
+      tile += vb.gx;
+      if (tile >= n_tiles) break;
+      step(tile, pair1, pair0);
+      tile += vb.gx;
+    }
+
+    float *pp = part + (int64_t)vb.x * ((int64_t)W * W + W);
+  #pragma unroll
+    for (int jt = 0; jt < JT; ++jt)
+  #pragma unroll
+      for (int kt = 0; kt < KT; ++kt)
+  #pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int j = wave * JW + jt * 16 + 4 * g + i;
+          const int k = kt * 16 + r;
+          pp[(int64_t)j * W + k] = dacc[jt][kt][i];
+        }
+    if (tid < W) pp[(int64_t)W * W + tid] = db;
+  }
+};
 
 namespace {
 
@@ -503,17 +526,10 @@ template <class CH, class T, int W, bool TOP, int DOUT, int ZSRC>
 hipError_t launch_w(const BwdArgs &a, float *part, int64_t n_tiles, int grid, hipStream_t st) {
   constexpr int NW = W == 32 ? 2 : (W == 256 ? 8 : 4);
   constexpr int TPW = (W / 16) / NW;
-  if constexpr (!TOP && ZSRC == Z_FROM_GEMM && bwd_db_ok<T>(CH::C, W)) {
-    hipLaunchKernelGGL((k_bwd_dw_db<CH, T, W, NW, TPW, DOUT>), dim3((unsigned)grid), dim3(NW * 64), 0, st, a, part,
-                       n_tiles);
-    return hipGetLastError();
-  }
+  if constexpr (!TOP && ZSRC == Z_FROM_GEMM && bwd_db_ok<T>(CH::C, W))
+    return launch_body<KBwdDwDb<CH, T, W, NW, TPW, DOUT>>({a, part, n_tiles}, dim3((unsigned)grid), 0, st);
   constexpr size_t lds = (size_t)2 * 16 * (CH::C * W + 8) * sizeof(T);
-  auto kfn = k_bwd_dw<CH, T, W, NW, TPW, TOP, DOUT, ZSRC>;
-  hipError_t e = hipFuncSetAttribute((const void *)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kfn, dim3((unsigned)grid), dim3(NW * 64), lds, st, a, part, n_tiles);
-  return hipGetLastError();
+  return launch_body<KBwdDw<CH, T, W, NW, TPW, TOP, DOUT, ZSRC>>({a, part, n_tiles}, dim3((unsigned)grid), lds, st);
 }
 
 template <class PDE, class T>

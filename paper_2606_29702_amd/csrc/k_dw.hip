@@ -11,6 +11,7 @@
 // lane takes its 8 contraction elements down a column of the staged tile: two
 // LDS transpose reads for 16-bit types, a gather for FP32.
 #include "dev_common.hpp"
+#include "group.hpp"
 #include "kernels.hpp"
 
 namespace pj {
@@ -71,140 +72,157 @@ __device__ __forceinline__ typename Mma<T>::frag tr_col(const T *tile, int pitch
 }
 
 template <class T, int TILE, int RC>
-__global__ __launch_bounds__(256) void k_dw_hidden(const T *__restrict__ Zb, const T *__restrict__ A,
-                                                   int64_t rows_total, int64_t rows_per_split, int w,
-                                                   int C, float *__restrict__ part,
-                                                   float *__restrict__ part_db) {
-  // Workgroup tile: TILE x TILE of dW; wave (wj, wk) owns a (TILE/2)^2 quarter,
-  // i.e. NT x NT MFMA 16x16 tiles.  RC rows (a multiple of 32) are staged per chunk.
-  using M = Mma<T>;
-  using LY = DwLayout<T, TILE, RC>;
-  constexpr int P = LY::pitch;
-  constexpr int NT = TILE / 32;
-  constexpr int H = TILE / 2;
-  __shared__ __align__(16) T lds[2][2][LY::tile_elems];  // [buffer][Zbar, A][rows x pitch]
-  const int t = threadIdx.x;
-  const int lane = t & 63, wave = t >> 6;
-  const int wj = wave & 1, wk = wave >> 1;
-  const int r16 = lane & 15, g = lane >> 4;
-  const int j0 = blockIdx.x * TILE, k0 = blockIdx.y * TILE;
-  const int64_t rb = (int64_t)blockIdx.z * rows_per_split;
-  const int64_t re = rb + rows_per_split < rows_total ? rb + rows_per_split : rows_total;
-  const bool do_db = blockIdx.y == 0;
+struct KDwHidden {
+  static constexpr int NT = 256;
+  struct Args {
+    const T * Zb;
+    const T * A;
+    int64_t rows_total;
+    int64_t rows_per_split;
+    int w;
+    int C;
+    float * part;
+    float * part_db;
+  };
+  static __device__ __forceinline__ void run(const Args &a_, VBlock vb) {
+    const T *__restrict__ Zb = a_.Zb;
+    const T *__restrict__ A = a_.A;
+    int64_t rows_total = a_.rows_total;
+    int64_t rows_per_split = a_.rows_per_split;
+    int w = a_.w;
+    int C = a_.C;
+    float *__restrict__ part = a_.part;
+    float *__restrict__ part_db = a_.part_db;
+    // Workgroup tile: TILE x TILE of dW; wave (wj, wk) owns a (TILE/2)^2 quarter,
+    // i.e. NT x NT MFMA 16x16 tiles.  RC rows (a multiple of 32) are staged per chunk.
+    using M = Mma<T>;
+    using LY = DwLayout<T, TILE, RC>;
+    constexpr int P = LY::pitch;
+    constexpr int NT = TILE / 32;
+    constexpr int H = TILE / 2;
+    __shared__ __align__(16) T lds[2][2][LY::tile_elems];  // [buffer][Zbar, A][rows x pitch]
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const int wj = wave & 1, wk = wave >> 1;
+    const int r16 = lane & 15, g = lane >> 4;
+    const int nt_ = w / TILE, bx_ = vb.x % nt_, by_ = vb.x / nt_, bz_ = vb.y;  // weight tile, split
+    const int j0 = bx_ * TILE, k0 = by_ * TILE;
+    const int64_t rb = (int64_t)bz_ * rows_per_split;
+    const int64_t re = rb + rows_per_split < rows_total ? rb + rows_per_split : rows_total;
+    const bool do_db = by_ == 0;
 
-  f32x4 acc[NT][NT];
-#pragma unroll
-  for (int a = 0; a < NT; ++a)
-#pragma unroll
-    for (int b = 0; b < NT; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-  float db = 0.f;
+    f32x4 acc[NT][NT];
+  #pragma unroll
+    for (int a = 0; a < NT; ++a)
+  #pragma unroll
+      for (int b = 0; b < NT; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float db = 0.f;
 
-  uint2 stage[2][LY::per_thread][LY::words];
-  auto fetch = [&](int64_t r0) {
-#pragma unroll
-    for (int u = 0; u < LY::per_thread; ++u) {
-      const int q = t + 256 * u;
-      if (q < LY::copies) {
-        const int row = q / LY::per_row, col = (q % LY::per_row) * 8;
-        const uint2 *sz = reinterpret_cast<const uint2 *>(Zb + (r0 + row) * w + j0 + col);
-        const uint2 *sa = reinterpret_cast<const uint2 *>(A + (r0 + row) * w + k0 + col);
-#pragma unroll
-        for (int v = 0; v < LY::words; ++v) {
-          stage[0][u][v] = sz[v];
-          stage[1][u][v] = sa[v];
+    uint2 stage[2][LY::per_thread][LY::words];
+    auto fetch = [&](int64_t r0) {
+  #pragma unroll
+      for (int u = 0; u < LY::per_thread; ++u) {
+        const int q = t + 256 * u;
+        if (q < LY::copies) {
+          const int row = q / LY::per_row, col = (q % LY::per_row) * 8;
+          const uint2 *sz = reinterpret_cast<const uint2 *>(Zb + (r0 + row) * w + j0 + col);
+          const uint2 *sa = reinterpret_cast<const uint2 *>(A + (r0 + row) * w + k0 + col);
+  #pragma unroll
+          for (int v = 0; v < LY::words; ++v) {
+            stage[0][u][v] = sz[v];
+            stage[1][u][v] = sa[v];
+          }
         }
       }
-    }
-  };
-  auto commit = [&](int buf) {
-#pragma unroll
-    for (int u = 0; u < LY::per_thread; ++u) {
-      const int q = t + 256 * u;
-      if (q < LY::copies) {
-        const int row = q / LY::per_row, col = (q % LY::per_row) * 8;
-#pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          uint2 *d = reinterpret_cast<uint2 *>(&lds[buf][m][row * P + col]);
-#pragma unroll
-          for (int v = 0; v < LY::words; ++v) d[v] = stage[m][u][v];
+    };
+    auto commit = [&](int buf) {
+  #pragma unroll
+      for (int u = 0; u < LY::per_thread; ++u) {
+        const int q = t + 256 * u;
+        if (q < LY::copies) {
+          const int row = q / LY::per_row, col = (q % LY::per_row) * 8;
+  #pragma unroll
+          for (int m = 0; m < 2; ++m) {
+            uint2 *d = reinterpret_cast<uint2 *>(&lds[buf][m][row * P + col]);
+  #pragma unroll
+            for (int v = 0; v < LY::words; ++v) d[v] = stage[m][u][v];
+          }
         }
       }
-    }
-  };
+    };
 
-  if (rb < re) {
-    fetch(rb);
-    commit(0);
-  }
-  __syncthreads();
-  int buf = 0;
-  for (int64_t r0 = rb; r0 < re; r0 += RC) {
-    const bool more = r0 + RC < re;
-    if (more) fetch(r0 + RC);
-    const T *Zs = lds[buf][0];
-    const T *As = lds[buf][1];
-    if (do_db && t < TILE) {
-      // rows r with r % C == 0 are value rows
-      const int first = (int)((C - (r0 % C)) % C);
-      for (int rr = first; rr < RC; rr += C) db += to_f32(Zs[rr * P + t]);
+    if (rb < re) {
+      fetch(rb);
+      commit(0);
     }
-#pragma unroll
-    for (int ks = 0; ks < RC / 32; ++ks) {
-      typename M::frag fa[NT], fb[NT];
-      if constexpr (sizeof(T) == 2) {
-#pragma unroll
-        for (int jt = 0; jt < NT; ++jt) fa[jt] = tr_col<T>(Zs, P, 32 * ks + 8 * g, H * wj + 16 * jt, r16);
-#pragma unroll
-        for (int kt = 0; kt < NT; ++kt) fb[kt] = tr_col<T>(As, P, 32 * ks + 8 * g, H * wk + 16 * kt, r16);
-      } else {
-#pragma unroll
-        for (int jt = 0; jt < NT; ++jt)
-          fa[jt] = gather_col<T>(Zs + (32 * ks + 8 * g) * P + H * wj + 16 * jt + r16, P);
-#pragma unroll
-        for (int kt = 0; kt < NT; ++kt)
-          fb[kt] = gather_col<T>(As + (32 * ks + 8 * g) * P + H * wk + 16 * kt + r16, P);
-      }
-#pragma unroll
-      for (int jt = 0; jt < NT; ++jt)
-#pragma unroll
-        for (int kt = 0; kt < NT; ++kt) M::mma(acc[jt][kt], fa[jt], fb[kt]);
-    }
-    if (more) commit(buf ^ 1);
     __syncthreads();
-    buf ^= 1;
-  }
-
-  float *pp = part + (int64_t)blockIdx.z * ((int64_t)w * w + w);
-#pragma unroll
-  for (int jt = 0; jt < NT; ++jt)
-#pragma unroll
-    for (int kt = 0; kt < NT; ++kt)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int j = j0 + H * wj + 16 * jt + 4 * g + i;
-        const int k = k0 + H * wk + 16 * kt + r16;
-        pp[(int64_t)j * w + k] = acc[jt][kt][i];
+    int buf = 0;
+    for (int64_t r0 = rb; r0 < re; r0 += RC) {
+      const bool more = r0 + RC < re;
+      if (more) fetch(r0 + RC);
+      const T *Zs = lds[buf][0];
+      const T *As = lds[buf][1];
+      if (do_db && t < TILE) {
+        // rows r with r % C == 0 are value rows
+        const int first = (int)((C - (r0 % C)) % C);
+        for (int rr = first; rr < RC; rr += C) db += to_f32(Zs[rr * P + t]);
       }
-  if (do_db && t < TILE) part_db[(int64_t)blockIdx.z * ((int64_t)w * w + w) + j0 + t] = db;
-}
+  #pragma unroll
+      for (int ks = 0; ks < RC / 32; ++ks) {
+        typename M::frag fa[NT], fb[NT];
+        if constexpr (sizeof(T) == 2) {
+  #pragma unroll
+          for (int jt = 0; jt < NT; ++jt) fa[jt] = tr_col<T>(Zs, P, 32 * ks + 8 * g, H * wj + 16 * jt, r16);
+  #pragma unroll
+          for (int kt = 0; kt < NT; ++kt) fb[kt] = tr_col<T>(As, P, 32 * ks + 8 * g, H * wk + 16 * kt, r16);
+        } else {
+  #pragma unroll
+          for (int jt = 0; jt < NT; ++jt)
+            fa[jt] = gather_col<T>(Zs + (32 * ks + 8 * g) * P + H * wj + 16 * jt + r16, P);
+  #pragma unroll
+          for (int kt = 0; kt < NT; ++kt)
+            fb[kt] = gather_col<T>(As + (32 * ks + 8 * g) * P + H * wk + 16 * kt + r16, P);
+        }
+  #pragma unroll
+        for (int jt = 0; jt < NT; ++jt)
+  #pragma unroll
+          for (int kt = 0; kt < NT; ++kt) M::mma(acc[jt][kt], fa[jt], fb[kt]);
+      }
+      if (more) commit(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+
+    float *pp = part + (int64_t)bz_ * ((int64_t)w * w + w);
+  #pragma unroll
+    for (int jt = 0; jt < NT; ++jt)
+  #pragma unroll
+      for (int kt = 0; kt < NT; ++kt)
+  #pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int j = j0 + H * wj + 16 * jt + 4 * g + i;
+          const int k = k0 + H * wk + 16 * kt + r16;
+          pp[(int64_t)j * w + k] = acc[jt][kt][i];
+        }
+    if (do_db && t < TILE) part_db[(int64_t)bz_ * ((int64_t)w * w + w) + j0 + t] = db;
+  }
+};
 
 int dw_tile(int w) { return (w % 128 == 0) ? 128 : ((w % 64 == 0) ? 64 : 32); }
 
 namespace {
 template <class T>
-void launch_dw_t(const T *Zb, const T *A, int64_t rows, int64_t rps, int w, int C, float *part,
-                 float *part_db, int splits, hipStream_t st) {
+hipError_t launch_dw_t(const T *Zb, const T *A, int64_t rows, int64_t rps, int w, int C, float *part,
+                       float *part_db, int splits, hipStream_t st) {
   const int tile = dw_tile(w);
-  dim3 grid((unsigned)(w / tile), (unsigned)(w / tile), (unsigned)splits);
+  // x: the (w/tile)^2 weight tiles, y: the splits
+  dim3 grid((unsigned)((w / tile) * (w / tile)), (unsigned)splits);
   // 128-wide tiles stage 64 rows per chunk (more bytes in flight per workgroup)
   if (tile == 128 && rps % 64 == 0)
-    hipLaunchKernelGGL((k_dw_hidden<T, 128, 64>), grid, dim3(256), 0, st, Zb, A, rows, rps, w, C, part, part_db);
-  else if (tile == 128)
-    hipLaunchKernelGGL((k_dw_hidden<T, 128, 32>), grid, dim3(256), 0, st, Zb, A, rows, rps, w, C, part, part_db);
-  else if (tile == 64)
-    hipLaunchKernelGGL((k_dw_hidden<T, 64, 32>), grid, dim3(256), 0, st, Zb, A, rows, rps, w, C, part, part_db);
-  else
-    hipLaunchKernelGGL((k_dw_hidden<T, 32, 32>), grid, dim3(256), 0, st, Zb, A, rows, rps, w, C, part, part_db);
+    return launch_body<KDwHidden<T, 128, 64>>({Zb, A, rows, rps, w, C, part, part_db}, grid, 0, st);
+  if (tile == 128) return launch_body<KDwHidden<T, 128, 32>>({Zb, A, rows, rps, w, C, part, part_db}, grid, 0, st);
+  if (tile == 64) return launch_body<KDwHidden<T, 64, 32>>({Zb, A, rows, rps, w, C, part, part_db}, grid, 0, st);
+  return launch_body<KDwHidden<T, 32, 32>>({Zb, A, rows, rps, w, C, part, part_db}, grid, 0, st);
 }
 }  // namespace
 
@@ -215,17 +233,14 @@ hipError_t launch_dw_hidden(int prec, int C, const void *Zb, const void *A_prev,
   rps = (rps + 31) / 32 * 32;
   switch (prec) {
     case P_FP32:
-      launch_dw_t<float>((const float *)Zb, (const float *)A_prev, rows, rps, w, C, part, part_db, splits, st);
-      break;
+      return launch_dw_t<float>((const float *)Zb, (const float *)A_prev, rows, rps, w, C, part, part_db, splits, st);
     case P_BF16:
-      launch_dw_t<bf16_t>((const bf16_t *)Zb, (const bf16_t *)A_prev, rows, rps, w, C, part, part_db, splits, st);
-      break;
+      return launch_dw_t<bf16_t>((const bf16_t *)Zb, (const bf16_t *)A_prev, rows, rps, w, C, part, part_db, splits,
+                                 st);
     case P_FP16:
-      launch_dw_t<f16_t>((const f16_t *)Zb, (const f16_t *)A_prev, rows, rps, w, C, part, part_db, splits, st);
-      break;
+      return launch_dw_t<f16_t>((const f16_t *)Zb, (const f16_t *)A_prev, rows, rps, w, C, part, part_db, splits, st);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 }  // namespace pj

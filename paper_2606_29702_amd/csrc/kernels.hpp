@@ -180,6 +180,29 @@ hipError_t launch_reduce_parts2(const float *part, int splits, int64_t stride, i
                                 int64_t M2, float *a32, float *b32, double *a64, double *b64,
                                 hipStream_t st, float scale = 1.f);
 
+// Segments of a composite training loss over one point set (k_seg.hip).
+constexpr int kMaxSegments = 8;
+enum { SEG_PDE = 0, SEG_DIRICHLET = 1, SEG_PERIODIC = 2 };
+enum { SEG_DATA_ZERO = 0, SEG_DATA_CONST = 1, SEG_DATA_SIN = 2 };
+struct SegPack {
+  int n;
+  int type[kMaxSegments], data[kMaxSegments];
+  int64_t begin[kMaxSegments], count[kMaxSegments];
+  float weight[kMaxSegments];           // loss weights
+  float cot[kMaxSegments];              // S * weight * 2 / units: the scaled cotangent factor
+  unsigned mask[kMaxSegments];          // bit o * C + c: output o, channel c
+  float param[kMaxSegments][4];         // data function parameters
+  int blk_start[kMaxSegments + 1];      // loss-kernel workgroups of each segment (256 units each)
+};
+// Segment terms from the forward pass's outputs: partials per workgroup into
+// part (blk_start[n] floats), then seg_loss[s] and the weighted loss (either
+// may be null).
+hipError_t launch_seg_loss(int kind, const SegPack &sp, const float *u_save, const float *r_save, const float *x,
+                           int64_t N_pad, float *part, float *seg_loss, float *loss, hipStream_t st);
+// Scaled cotangent of the loss at every point's outputs (zero outside the segments).
+hipError_t launch_seg_adj(int kind, const SegPack &sp, const float *u_save, const float *r_save, const float *x,
+                          int64_t N_pad, Coef k, float *ubar, hipStream_t st);
+
 // One Adam step over up to kAdamSegs parameter tensors (k_adam.hip).
 constexpr int kAdamSegs = 32;
 struct AdamArgs {

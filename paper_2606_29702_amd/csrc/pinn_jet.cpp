@@ -6,13 +6,17 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <tuple>
 #include <vector>
 
+#include "group.hpp"
 #include "kernels.hpp"
 #include "plan_region.hpp"
 
@@ -139,6 +143,10 @@ struct pinn_plan_s {
   size_t region_cap = 0, region_used = 0;
   bool measure = false;
 
+  // segments of the latest pinn_jet_loss call (valid with have_state)
+  bool have_seg = false;
+  pj::SegPack seg{};
+  double seg_scale = 1.0;
   // state saved by the latest residual call
   bool have_state = false;
   int64_t st_N = 0;
@@ -210,6 +218,12 @@ int dw_splits_for(int64_t npad, int C, int w) {
 // it with a pair of events on the same stream.
 template <class F>
 hipError_t timed(pinn_plan p, int cls, hipStream_t st, F &&launch) {
+  if (pj::current_recorder()) {  // recording (ensemble): tag the records with the class
+    pj::current_record_class() = cls;
+    const hipError_t e = launch();
+    pj::current_record_class() = 0;
+    return e;
+  }
   if (p->prof_class != cls) return launch();
   if (p->ev_used + 2 > p->ev_pool.size()) {
     if (p->ev_pool.size() < 2048) {
@@ -638,6 +652,7 @@ pinn_status pinn_jet_forward(pinn_plan plan, const pinn_net *net, const float *x
   if (st) return st;
   if (!jets) return fail(PINN_ERR_ARG, "jets is NULL");
   plan->have_state = false;
+  plan->have_seg = false;
   return run_forward(plan, net, nullptr, x, N, jets, nullptr, nullptr, nullptr, false, (hipStream_t)stream);
 }
 
@@ -651,6 +666,7 @@ pinn_status pinn_jet_residual(pinn_plan plan, const pinn_net *net, const pinn_pd
   if (st) return st;
   if (loss_f64 && !plan->verify()) return fail(PINN_ERR_ARG, "loss_f64 needs a PINN_VERIFY_F64 plan");
   plan->have_state = false;
+  plan->have_seg = false;
   st = run_forward(plan, net, pde, x, N, jets, r, loss, loss_f64, true, (hipStream_t)stream);
   if (st) return st;
   plan->have_state = true;
@@ -668,7 +684,7 @@ pinn_status pinn_jet_residual(pinn_plan plan, const pinn_net *net, const pinn_pd
 static pinn_status backward_impl(pinn_plan plan, const pinn_net *net, const pinn_pde *pde, const float *x,
                                  int64_t N, const float *r_bar, const float *loss_bar, float *const *dW,
                                  float *const *db, double *const *dW_f64, double *const *db_f64,
-                                 void *stream) {
+                                 void *stream, bool segments = false) {
   pinn_status st = check_call(plan, net, x, N);
   if (st) return st;
   st = check_pde(pde, plan->kind);
@@ -702,10 +718,19 @@ static pinn_status backward_impl(pinn_plan plan, const pinn_net *net, const pinn
   // and BF16 results are those of the unscaled arithmetic.  An explicit r_bar
   // is used as given.
   double cot_scale = 1.0;
-  if (!r_bar)
+  if (segments) {
+    cot_scale = p->seg_scale;  // chosen with the segments' weights and sizes
+  } else if (!r_bar) {
     while (4.0 * cot_scale <= (double)N) cot_scale *= 2.0;
+  }
   const float rbar_scale = (float)(2.0 * cot_scale / (double)N);
   const float inv_s = (float)(1.0 / cot_scale);
+  // the cotangent at the outputs: the residual adjoint, or the segments'
+  auto output_adjoint = [&]() -> hipError_t {
+    if (segments)
+      return timed(p, PINN_K_OUT_BWD, s, [&] { return pj::launch_seg_adj(p->kind, p->seg, p->u_save, p->r_save, x, npad, coef_of(pde), p->ubar, s); });
+    return timed(p, PINN_K_OUT_BWD, s, [&] { return pj::launch_out_adj(p->kind, p->u_save, p->r_save, r_bar, loss_bar, N, npad, rbar_scale, coef_of(pde), p->ubar, s); });
+  };
   hipError_t e;
   // the operand-type weights W and W^T were made by the residual call
   pinn_status rs = PINN_OK;
@@ -737,7 +762,7 @@ static pinn_status backward_impl(pinn_plan plan, const pinn_net *net, const pinn
     // Each backward layer kernel also produces the weight gradient of the
     // layer whose zbar it computes: dW_m from zbar_m and the stack of m - 1.
     const int grid = (int)std::min<int64_t>(std::min<int64_t>(npad / 16, p->dw_splits_max), 512);
-    e = timed(p, PINN_K_OUT_BWD, s, [&] { return pj::launch_out_adj(p->kind, p->u_save, p->r_save, r_bar, loss_bar, N, npad, rbar_scale, coef_of(pde), p->ubar, s); });
+    e = output_adjoint();
     if (e) return hip_fail(e, "output adjoint");
     auto layer = [&](pj::LayerBwd &B, int m, int cls) -> pinn_status {
       const void *Am1 = nullptr;
@@ -796,7 +821,7 @@ static pinn_status backward_impl(pinn_plan plan, const pinn_net *net, const pinn
     if (e) return hip_fail(e, "hidden adjoint");
   } else {
   // Output layer: ubar, then zbar of layer H, then dW_L, db_L.
-  e = timed(p, PINN_K_OUT_BWD, s, [&] { return pj::launch_out_adj(p->kind, p->u_save, p->r_save, r_bar, loss_bar, N, npad, rbar_scale, coef_of(pde), p->ubar, s); });
+  e = output_adjoint();
   if (e) return hip_fail(e, "output adjoint");
   {
     pj::LayerBwd B{};
@@ -880,6 +905,125 @@ pinn_status pinn_jet_backward_cot(pinn_plan plan, const pinn_net *net, const pin
   return backward_impl(plan, net, pde, x, N, r_bar, loss_bar, dW, db, dW_f64, db_f64, stream);
 }
 
+}  // extern "C"
+
+// Checks a segment list against the plan and N and packs it for the kernels:
+// units, the cotangent scale S (a power of two that brings the largest
+// per-unit cotangent weight * 2 / units to at most 1) and the loss kernel's
+// workgroup ranges.
+static pinn_status seg_pack(pinn_plan p, const pinn_segment *segs, int32_t n_seg, int64_t N, pj::SegPack *sp,
+                            double *scale) {
+  if (!segs) return fail(PINN_ERR_ARG, "segments is NULL");
+  if (n_seg < 1 || n_seg > pj::kMaxSegments)
+    return fail(PINN_ERR_ARG, "n_segments = %d outside [1, %d]", n_seg, pj::kMaxSegments);
+  const int C = p->ki.C, dout = p->ki.dout;
+  const uint64_t all_bits = (uint64_t(1) << (dout * C)) - 1;
+  *sp = pj::SegPack{};
+  sp->n = n_seg;
+  double ratio = 1e300;  // min over segments of units / (2 weight)
+  int blk = 0;
+  for (int s = 0; s < n_seg; ++s) {
+    const pinn_segment &g = segs[s];
+    if (g.begin < 0 || g.count < 1 || g.begin + g.count > N)
+      return fail(PINN_ERR_ARG, "segment %d: points [%lld, %lld) outside [0, N = %lld)", s, (long long)g.begin,
+                  (long long)(g.begin + g.count), (long long)N);
+    if (!std::isfinite(g.weight) || g.weight < 0.0) return fail(PINN_ERR_ARG, "segment %d: bad weight", s);
+    for (int q = 0; q < 4; ++q)
+      if (!std::isfinite(g.param[q])) return fail(PINN_ERR_ARG, "segment %d: parameter %d not finite", s, q);
+    for (int t = 0; t < s; ++t)
+      if (g.begin < segs[t].begin + segs[t].count && segs[t].begin < g.begin + g.count)
+        return fail(PINN_ERR_ARG, "segments %d and %d overlap", t, s);
+    int64_t units = g.count;
+    switch (g.type) {
+      case PINN_SEG_PDE: break;
+      case PINN_SEG_DIRICHLET:
+        if (g.data != PINN_DATA_ZERO && g.data != PINN_DATA_CONST && g.data != PINN_DATA_SIN)
+          return fail(PINN_ERR_ARG, "segment %d: unknown data function %d", s, g.data);
+        if (g.mask == 0 || (uint64_t)g.mask > all_bits) return fail(PINN_ERR_ARG, "segment %d: bad mask", s);
+        for (int q = 0; q < dout * C; ++q)
+          if ((g.mask >> q & 1u) && q % C != 0)
+            return fail(PINN_ERR_ARG, "segment %d: a data term constrains output values (channel 0) only", s);
+        break;
+      case PINN_SEG_PERIODIC:
+        if (g.count % 2 != 0) return fail(PINN_ERR_ARG, "segment %d: periodic pairs need an even count", s);
+        if (g.mask == 0 || (uint64_t)g.mask > all_bits) return fail(PINN_ERR_ARG, "segment %d: bad mask", s);
+        units = g.count / 2;
+        break;
+      default: return fail(PINN_ERR_ARG, "segment %d: unknown type %d", s, g.type);
+    }
+    sp->type[s] = g.type;
+    sp->data[s] = g.data;
+    sp->begin[s] = g.begin;
+    sp->count[s] = g.count;
+    sp->weight[s] = (float)g.weight;
+    sp->mask[s] = g.mask;
+    for (int q = 0; q < 4; ++q) sp->param[s][q] = (float)g.param[q];
+    sp->blk_start[s] = blk;
+    blk += (int)((units + 255) / 256);
+    if (g.weight > 0.0) ratio = std::min(ratio, (double)units / (2.0 * g.weight));
+  }
+  sp->blk_start[n_seg] = blk;
+  double S = 1.0;
+  if (ratio < 1e300) {
+    while (S * 2.0 <= ratio && S < 0x1p30) S *= 2.0;
+    while (S > ratio && S > 0x1p-30) S *= 0.5;
+  }
+  for (int s = 0; s < n_seg; ++s) {
+    const double units = segs[s].type == PINN_SEG_PERIODIC ? segs[s].count / 2 : segs[s].count;
+    sp->cot[s] = (float)(S * segs[s].weight * 2.0 / units);
+  }
+  *scale = S;
+  return PINN_OK;
+}
+
+extern "C" {
+
+pinn_status pinn_jet_loss(pinn_plan plan, const pinn_net *net, const pinn_pde *pde, const pinn_segment *segs,
+                          int32_t n_seg, const float *x, int64_t N, float *loss, float *seg_loss, void *stream) {
+  g_err.clear();
+  pinn_status st = check_call(plan, net, x, N);
+  if (st) return st;
+  st = check_pde(pde, plan->kind);
+  if (st) return st;
+  pj::SegPack sp;
+  double S = 1.0;
+  st = seg_pack(plan, segs, n_seg, N, &sp, &S);
+  if (st) return st;
+  // the loss partials (one per 256 units, at most N / 256 + 8) use the
+  // gradient partial buffer, which holds at least 6 floats per point
+  plan->have_state = false;
+  plan->have_seg = false;
+  hipStream_t s = (hipStream_t)stream;
+  st = run_forward(plan, net, pde, x, N, nullptr, nullptr, nullptr, nullptr, true, s);
+  if (st) return st;
+  const int64_t npad = round_up(N, pj::kPointTile);
+  hipError_t e = timed(plan, PINN_K_OTHER, s, [&] { return pj::launch_seg_loss(plan->kind, sp, plan->u_save, plan->r_save, x, npad, plan->part, seg_loss, loss, s); });
+  if (e) return hip_fail(e, "segment loss");
+  plan->have_state = true;
+  plan->st_N = N;
+  plan->st_x = x;
+  plan->st_W.assign(net->W, net->W + net->n_layers);
+  plan->st_b.assign(net->b, net->b + net->n_layers);
+  plan->have_seg = true;
+  plan->seg = sp;
+  plan->seg_scale = S;
+  return PINN_OK;
+}
+
+pinn_status pinn_jet_loss_backward(pinn_plan plan, const pinn_net *net, const pinn_pde *pde,
+                                   const pinn_segment *segs, int32_t n_seg, const float *x, int64_t N,
+                                   float *const *dW, float *const *db, void *stream) {
+  g_err.clear();
+  if (!plan) return fail(PINN_ERR_ARG, "plan is NULL");
+  pj::SegPack sp;
+  double S = 1.0;
+  pinn_status st = seg_pack(plan, segs, n_seg, N, &sp, &S);
+  if (st) return st;
+  if (!plan->have_seg || std::memcmp(&sp, &plan->seg, sizeof sp) != 0)
+    return fail(PINN_ERR_STATE, "loss backward does not follow pinn_jet_loss with the same segments");
+  return backward_impl(plan, net, pde, x, N, nullptr, nullptr, dW, db, nullptr, nullptr, stream, true);
+}
+
 pinn_status pinn_plan_get_tuning(pinn_plan plan, pinn_tuning *t) {
   g_err.clear();
   if (!plan || !t) return fail(PINN_ERR_ARG, "plan or tuning is NULL");
@@ -904,6 +1048,44 @@ pinn_status pinn_plan_set_tuning(pinn_plan plan, const pinn_tuning *t) {
   return PINN_OK;
 }
 
+}  // extern "C"
+
+// Tuning cache: the autotuner's choice per (device architecture, PDE kind,
+// operand type, width, depth, point-count bucket ceil(log2 N)).  The split
+// count is kept relative to the plan's default (the candidates are half,
+// once and twice the default), so an entry applies to every N of its bucket.
+namespace {
+struct TuneKey {
+  std::string arch;
+  int kind, prec, w, H, nbucket;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(arch, kind, prec, w, H, nbucket) < std::tie(o.arch, o.kind, o.prec, o.w, o.H, o.nbucket);
+  }
+};
+struct TuneVal {
+  int split_mode;  // 0: half the default split count, 1: the default, 2: twice
+  int fwd_points, bwd_fused;
+  double ms;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
+
+std::string device_arch(int dev) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  return a.substr(0, a.find(':'));
+}
+
+TuneKey tune_key(pinn_plan p, int64_t N) {
+  int nb = 0;
+  while ((int64_t(1) << nb) < N) ++nb;
+  return TuneKey{device_arch(p->device), p->kind, p->prec, p->w, p->H, nb};
+}
+}  // namespace
+
+extern "C" {
+
 pinn_status pinn_plan_autotune(pinn_plan plan, const pinn_net *net, const pinn_pde *pde, const float *x,
                                int64_t N, int32_t reps, pinn_tuning *best, double *best_ms, void *stream) {
   g_err.clear();
@@ -914,6 +1096,23 @@ pinn_status pinn_plan_autotune(pinn_plan plan, const pinn_net *net, const pinn_p
   if (reps < 1 || reps > 1000) return fail(PINN_ERR_ARG, "reps = %d outside [1, 1000]", reps);
   hipStream_t s = (hipStream_t)stream;
   pinn_plan p = plan;
+  const TuneKey tk = tune_key(p, N);
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune.find(tk);
+    if (it != g_tune.end()) {  // cached: apply without timing
+      const int s0 = dw_splits_for(round_up(N, pj::kPointTile), p->ki.C, p->w);
+      const int sp = it->second.split_mode == 0 ? std::max(1, s0 / 2)
+                                                : (it->second.split_mode == 1 ? s0 : std::min(p->dw_splits_max, 2 * s0));
+      p->dw_splits = std::max(1, std::min(sp, p->dw_splits_max));
+      p->fwd_points = pj::fused_fwd_fits(it->second.fwd_points, p->ki.C, p->w, p->prec) ? it->second.fwd_points : 0;
+      p->bwd_fused = it->second.bwd_fused && pj::bwd_dw_fused_supported(p->ki.C, p->w, p->prec) ? 1 : 0;
+      p->have_state = false;
+      if (best) *best = pinn_tuning{p->dw_splits, p->fwd_points, p->bwd_fused};
+      if (best_ms) *best_ms = it->second.ms;
+      return PINN_OK;
+    }
+  }
   // gradient outputs for the trial steps
   std::vector<void *> bufs;
   std::vector<float *> dW(p->L), db(p->L);
@@ -992,8 +1191,71 @@ pinn_status pinn_plan_autotune(pinn_plan plan, const pinn_net *net, const pinn_p
   p->fwd_points = bt.fwd_points;
   p->bwd_fused = bt.bwd_fused;
   p->have_state = false;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[tk] = TuneVal{bt.dw_splits < s0 ? 0 : (bt.dw_splits == s0 ? 1 : 2), bt.fwd_points, bt.bwd_fused, bms};
+  }
   if (best) *best = bt;
   if (best_ms) *best_ms = bms;
+  return PINN_OK;
+}
+
+pinn_status pinn_tuning_cache_clear(void) {
+  g_err.clear();
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune.clear();
+  return PINN_OK;
+}
+
+pinn_status pinn_tuning_cache_size(int64_t *entries) {
+  g_err.clear();
+  if (!entries) return fail(PINN_ERR_ARG, "entries is NULL");
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  *entries = (int64_t)g_tune.size();
+  return PINN_OK;
+}
+
+pinn_status pinn_tuning_cache_save(const char *path) {
+  g_err.clear();
+  if (!path) return fail(PINN_ERR_ARG, "path is NULL");
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  FILE *f = fopen(path, "w");
+  if (!f) return fail(PINN_ERR_ARG, "cannot write %s", path);
+  fprintf(f, "# pinn tuning cache v1: arch kind prec w H nbucket split_mode fwd_points bwd_fused ms\n");
+  for (const auto &kv : g_tune)
+    fprintf(f, "%s %d %d %d %d %d %d %d %d %.6g\n", kv.first.arch.c_str(), kv.first.kind, kv.first.prec,
+            kv.first.w, kv.first.H, kv.first.nbucket, kv.second.split_mode, kv.second.fwd_points,
+            kv.second.bwd_fused, kv.second.ms);
+  const bool ok = fclose(f) == 0;
+  return ok ? PINN_OK : fail(PINN_ERR_ARG, "cannot write %s", path);
+}
+
+pinn_status pinn_tuning_cache_load(const char *path) {
+  g_err.clear();
+  if (!path) return fail(PINN_ERR_ARG, "path is NULL");
+  FILE *f = fopen(path, "r");
+  if (!f) return fail(PINN_ERR_ARG, "cannot read %s", path);
+  std::map<TuneKey, TuneVal> got;
+  char line[512];
+  int lineno = 0;
+  while (fgets(line, sizeof line, f)) {
+    ++lineno;
+    if (line[0] == '#' || line[0] == '\n') continue;
+    char arch[64];
+    TuneKey k;
+    TuneVal v;
+    if (sscanf(line, "%63s %d %d %d %d %d %d %d %d %lf", arch, &k.kind, &k.prec, &k.w, &k.H, &k.nbucket,
+               &v.split_mode, &v.fwd_points, &v.bwd_fused, &v.ms) != 10 ||
+        v.split_mode < 0 || v.split_mode > 2 || (v.bwd_fused != 0 && v.bwd_fused != 1)) {
+      fclose(f);
+      return fail(PINN_ERR_ARG, "%s:%d: malformed tuning cache entry", path, lineno);
+    }
+    k.arch = arch;
+    got[k] = v;
+  }
+  fclose(f);
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  for (const auto &kv : got) g_tune[kv.first] = kv.second;
   return PINN_OK;
 }
 
@@ -1175,19 +1437,72 @@ pinn_status pinn_graph_destroy(pinn_graph gr) {
 
 // ---------------------------------------------------------------------------
 // Ensembles: many independent networks stepped together.
+//
+// Every member has its own plan.  A step first records, per member, the
+// launches its residual, backward (and Adam) calls would make (the plan code
+// runs unchanged with a Recorder installed), uploads all argument blocks to
+// device memory once, and merges the members' launch lists into grouped
+// launches: at each point the kernel body at the front of the most members is
+// launched once for all of them (group.hpp), each member on its own virtual
+// grid.  Members of one hidden width share a stream (a lane); lanes run
+// concurrently.  The schedule is kept while the pointers, sizes and
+// coefficients stay the same, and with graphs on it is captured into one HIP
+// graph.  A member's results are those of its single-plan calls bit for bit.
 // ---------------------------------------------------------------------------
+namespace pj {
+Recorder *&current_recorder() {
+  static thread_local Recorder *r = nullptr;
+  return r;
+}
+int &current_record_class() {
+  static thread_local int c = 0;
+  return c;
+}
+}  // namespace pj
+
+namespace {
+
+struct GroupedLaunch {
+  pj::GroupTab tab;
+  int cls = 0;  // kernel class of the launch sites
+  int blocks = 0;
+  size_t lds = 0;
+  hipError_t (*launch)(const pj::GroupTab &, int, size_t, hipStream_t) = nullptr;
+};
+
+// Adam state of a training step over a batch (host arrays per member).
+struct BatchTrain {
+  float *const *const *mW, *const *const *vW, *const *const *mb, *const *const *vb;
+  const pinn_adam *hp;
+  int64_t *step_dev;
+};
+
+}  // namespace
+
 struct pinn_batch_s {
   int n = 0;
   std::vector<pinn_plan> plans;
-  std::vector<int> L;
-  int n_streams = 8;
-  std::vector<hipStream_t> streams;   // side streams (default priority)
-  std::vector<hipEvent_t> ev_join;    // one per side stream
+  std::vector<int> L, width;
+  int n_streams = 4;                  // lanes at most
+  std::vector<hipStream_t> streams;   // one per lane (default priority)
+  std::vector<hipEvent_t> ev_join;
   hipEvent_t ev_fork = nullptr, ev_in = nullptr, ev_out = nullptr;
   hipStream_t origin = nullptr;       // capture origin
   bool use_graph = true;
   hipGraphExec_t exec = nullptr;
-  std::vector<const void *> key;      // every pointer baked into the captured graph
+  std::vector<const void *> key;      // every pointer and size baked into the schedule
+  // the schedule
+  std::vector<std::vector<GroupedLaunch>> lanes;
+  std::vector<GroupedLaunch> tail;    // after the join (the Adam step counter)
+  void *dev_args = nullptr;
+  size_t dev_args_cap = 0;
+  size_t n_launches = 0;              // grouped launches per step
+  // launch timing of one kernel class (pinn_batch_profile): eager steps only
+  int prof_class = 0;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  double prof_ms = 0.0;
+  int64_t prof_launches = 0;
   ~pinn_batch_s() {
     if (exec) (void)hipGraphExecDestroy(exec);
     for (hipEvent_t e : ev_join) (void)hipEventDestroy(e);
@@ -1195,7 +1510,23 @@ struct pinn_batch_s {
       if (e) (void)hipEventDestroy(e);
     for (hipStream_t s : streams) (void)hipStreamDestroy(s);
     if (origin) (void)hipStreamDestroy(origin);
+    if (dev_args) (void)hipFree(dev_args);
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (pinn_plan p : plans) delete p;
+  }
+  hipError_t harvest() {
+    if (ev_used == 0) return hipSuccess;
+    for (size_t i = 0; i + 1 < ev_used; i += 2) {
+      hipError_t e = hipEventSynchronize(ev_pool[i + 1]);
+      if (e) return e;
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, ev_pool[i], ev_pool[i + 1]);
+      if (e) return e;
+      prof_ms += ms;
+      ++prof_launches;
+    }
+    ev_used = 0;
+    return hipSuccess;
   }
 };
 
@@ -1218,30 +1549,292 @@ hipError_t batch_streams(pinn_batch b, int n) {
   return hipSuccess;
 }
 
-// Enqueues one step of every network: fork from `origin` to the side streams,
-// network i on side stream i mod S (networks in the order given), join back.
-pinn_status batch_enqueue(pinn_batch b, const pinn_net *nets, const pinn_pde *pdes, const float *const *x,
-                          const int64_t *N, float *loss, float *const *const *dW, float *const *const *db,
-                          hipStream_t origin) {
+// Drops the schedule.  A step still running may read the argument table
+// and the graph, so the batch's streams are drained first.
+void invalidate(pinn_batch b) {
+  if (b->exec || !b->lanes.empty()) {
+    if (b->origin) (void)hipStreamSynchronize(b->origin);
+    for (hipStream_t s : b->streams) (void)hipStreamSynchronize(s);
+  }
+  if (b->exec) {
+    (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  b->key.clear();
+  b->lanes.clear();
+  b->tail.clear();
+}
+
+// Greedy merge of the members' launch records (in order per member) into
+// grouped launches; the records' argument blocks sit at base + off[i][k].
+void merge_lane(const std::vector<int> &members, const std::vector<std::vector<pj::LaunchRecord>> &recs,
+                const std::vector<std::vector<size_t>> &off, char *base, std::vector<GroupedLaunch> &out) {
+  std::vector<size_t> front(recs.size(), 0);
+  for (;;) {
+    // the body at the front of the most members (first seen on a tie)
+    std::vector<const void *> keys;
+    std::vector<int> counts;
+    for (int i : members) {
+      if (front[i] >= recs[i].size()) continue;
+      const void *k = recs[i][front[i]].key;
+      size_t q = 0;
+      while (q < keys.size() && keys[q] != k) ++q;
+      if (q == keys.size()) {
+        keys.push_back(k);
+        counts.push_back(0);
+      }
+      ++counts[q];
+    }
+    if (keys.empty()) break;
+    const void *K = keys[std::max_element(counts.begin(), counts.end()) - counts.begin()];
+    GroupedLaunch gl{};
+    auto flush = [&]() {
+      if (gl.tab.n > 0) out.push_back(gl);
+      gl = GroupedLaunch{};
+    };
+    for (int i : members) {
+      if (front[i] >= recs[i].size() || recs[i][front[i]].key != K) continue;
+      const pj::LaunchRecord &r = recs[i][front[i]];
+      if (gl.tab.n == pj::kGroupMax) flush();
+      const int e = gl.tab.n++;
+      gl.tab.start[e] = gl.blocks;
+      gl.tab.gx[e] = r.gx;
+      gl.tab.args[e] = base + off[i][front[i]];
+      gl.blocks += r.gx * r.gy;
+      gl.tab.start[e + 1] = gl.blocks;
+      gl.lds = std::max(gl.lds, r.lds);
+      gl.launch = r.launch_group;
+      gl.cls = r.cls;
+      ++front[i];
+    }
+    flush();
+  }
+}
+
+// Records every member's step and builds the grouped schedule.
+pinn_status batch_build(pinn_batch b, const pinn_net *nets, const pinn_pde *pdes, const float *const *x,
+                        const int64_t *N, float *loss, float *const *const *dW, float *const *const *db,
+                        const BatchTrain *train) {
+  invalidate(b);
+  std::vector<std::vector<pj::LaunchRecord>> recs(b->n);
+  for (int i = 0; i < b->n; ++i) {
+    pinn_plan p = b->plans[i];
+    p->prof_class = 0;
+    pj::Recorder rec;
+    pj::current_recorder() = &rec;
+    pinn_status st = pinn_jet_residual(p, &nets[i], &pdes[i], x[i], N[i], nullptr, loss + i, nullptr, nullptr,
+                                       nullptr);
+    if (st == PINN_OK)
+      st = pinn_jet_backward(p, &nets[i], &pdes[i], x[i], N[i], nullptr, dW[i], db[i], nullptr, nullptr, nullptr);
+    if (st == PINN_OK && train) {
+      pj::AdamArgs a;
+      st = adam_args(nets[i].n_layers, nets[i].dims, const_cast<float *const *>(nets[i].W),
+                     const_cast<float *const *>(nets[i].b), dW[i], db[i], train->mW[i], train->vW[i], train->mb[i],
+                     train->vb[i], train->hp, &a);
+      if (st == PINN_OK) {
+        a.step = 0;
+        a.step_dev = train->step_dev;
+        const hipError_t e = pj::launch_adam(a, nullptr);
+        if (e) st = hip_fail(e, "adam");
+      }
+    }
+    pj::current_recorder() = nullptr;
+    if (st) {
+      const std::string msg = g_err;
+      return fail(st, "network %d: %s", i, msg.c_str());
+    }
+    recs[i] = std::move(rec.recs);
+  }
+  // a training step ends with one advance of the step counter, after every
+  // member's update: recorded as one more launch list (entry n)
+  if (train) {
+    pj::Recorder rec;
+    pj::current_recorder() = &rec;
+    const hipError_t e2 = pj::launch_step_count(train->step_dev, nullptr);
+    pj::current_recorder() = nullptr;
+    if (e2) return hip_fail(e2, "step count");
+    recs.push_back(std::move(rec.recs));
+  }
+  // argument blocks, 16-byte aligned, in one device buffer
+  std::vector<std::vector<size_t>> off(recs.size());
+  size_t total = 0;
+  for (size_t i = 0; i < recs.size(); ++i)
+    for (const pj::LaunchRecord &r : recs[i]) {
+      off[i].push_back(total);
+      total += (r.args.size() + 15) & ~size_t(15);
+    }
+  std::vector<unsigned char> host(std::max<size_t>(total, 16));
+  for (size_t i = 0; i < recs.size(); ++i)
+    for (size_t k = 0; k < recs[i].size(); ++k)
+      std::memcpy(host.data() + off[i][k], recs[i][k].args.data(), recs[i][k].args.size());
+  if (total > b->dev_args_cap) {
+    if (b->dev_args) (void)hipFree(b->dev_args);
+    b->dev_args = nullptr;
+    b->dev_args_cap = 0;
+    hipError_t e = hipMalloc(&b->dev_args, total);
+    if (e) return hip_fail(e, "batch argument table");
+    b->dev_args_cap = total;
+  }
+  hipError_t e = hipMemcpy(b->dev_args, host.data(), total, hipMemcpyHostToDevice);
+  if (e) return hip_fail(e, "batch argument table");
+  // lanes: one per hidden width (widths in increasing order), folded onto the streams
+  std::vector<int> widths(b->width);
+  std::sort(widths.begin(), widths.end());
+  widths.erase(std::unique(widths.begin(), widths.end()), widths.end());
+  const int n_lanes = std::min<int>((int)widths.size(), b->n_streams);
+  std::vector<std::vector<int>> members(n_lanes);
+  for (int i = 0; i < b->n; ++i) {
+    const int wi = (int)(std::lower_bound(widths.begin(), widths.end(), b->width[i]) - widths.begin());
+    members[wi % n_lanes].push_back(i);
+  }
+  b->lanes.assign(n_lanes, {});
+  b->n_launches = 0;
+  char *base = static_cast<char *>(b->dev_args);
+  for (int l = 0; l < n_lanes; ++l) {
+    merge_lane(members[l], recs, off, base, b->lanes[l]);
+    b->n_launches += b->lanes[l].size();
+  }
+  if (train) {
+    merge_lane(std::vector<int>{b->n}, recs, off, base, b->tail);
+    b->n_launches += b->tail.size();
+  }
+  return PINN_OK;
+}
+
+// Enqueues the schedule: fork from `origin` to the lanes, join back.
+pinn_status batch_enqueue(pinn_batch b, hipStream_t origin) {
   hipError_t e = hipEventRecord(b->ev_fork, origin);
   if (e) return hip_fail(e, "fork");
-  for (int s = 0; s < b->n_streams; ++s) {
-    e = hipStreamWaitEvent(b->streams[s], b->ev_fork, 0);
+  const int n_lanes = (int)b->lanes.size();
+  for (int l = 0; l < n_lanes; ++l) {
+    hipStream_t s = b->streams[l];
+    e = hipStreamWaitEvent(s, b->ev_fork, 0);
     if (e) return hip_fail(e, "fork");
-  }
-  for (int i = 0; i < b->n; ++i) {
-    hipStream_t s = b->streams[i % b->n_streams];
-    pinn_status st = pinn_jet_residual(b->plans[i], &nets[i], &pdes[i], x[i], N[i], nullptr, loss + i, nullptr,
-                                       nullptr, s);
-    if (st) return st;
-    st = pinn_jet_backward(b->plans[i], &nets[i], &pdes[i], x[i], N[i], nullptr, dW[i], db[i], nullptr, nullptr, s);
-    if (st) return st;
-  }
-  for (int s = 0; s < b->n_streams; ++s) {
-    e = hipEventRecord(b->ev_join[s], b->streams[s]);
-    if (e == hipSuccess) e = hipStreamWaitEvent(origin, b->ev_join[s], 0);
+    for (const GroupedLaunch &g : b->lanes[l]) {
+      const bool tm = b->prof_class != 0 && g.cls == b->prof_class;
+      if (tm) {  // a pair of events around the launch, on its lane
+        if (b->ev_used + 2 > b->ev_pool.size()) {
+          if (b->ev_pool.size() >= 4096) {
+            e = b->harvest();
+            if (e) return hip_fail(e, "event timing");
+          }
+          while (b->ev_used + 2 > b->ev_pool.size()) {
+            hipEvent_t ev;
+            e = hipEventCreate(&ev);
+            if (e) return hip_fail(e, "event timing");
+            b->ev_pool.push_back(ev);
+          }
+        }
+        e = hipEventRecord(b->ev_pool[b->ev_used], s);
+        if (e) return hip_fail(e, "event timing");
+      }
+      e = g.launch(g.tab, g.blocks, g.lds, s);
+      if (e) return hip_fail(e, "grouped launch");
+      if (tm) {
+        e = hipEventRecord(b->ev_pool[b->ev_used + 1], s);
+        if (e) return hip_fail(e, "event timing");
+        b->ev_used += 2;
+      }
+    }
+    e = hipEventRecord(b->ev_join[l], s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(origin, b->ev_join[l], 0);
     if (e) return hip_fail(e, "join");
   }
+  for (const GroupedLaunch &g : b->tail) {
+    e = g.launch(g.tab, g.blocks, g.lds, origin);
+    if (e) return hip_fail(e, "grouped launch");
+  }
+  return PINN_OK;
+}
+
+pinn_status batch_check(pinn_batch b, const pinn_net *nets, const pinn_pde *pdes, const float *const *x,
+                        const int64_t *N, float *loss, float *const *const *dW, float *const *const *db,
+                        std::vector<const void *> &key) {
+  if (!nets || !pdes || !x || !N || !loss || !dW || !db) return fail(PINN_ERR_ARG, "a batch argument is NULL");
+  key.push_back(loss);
+  for (int i = 0; i < b->n; ++i) {
+    pinn_status st = check_call(b->plans[i], &nets[i], x[i], N[i]);
+    if (st == PINN_OK) st = check_pde(&pdes[i], b->plans[i]->kind);
+    if (st) {
+      std::string msg = g_err;
+      return fail(st, "network %d: %s", i, msg.c_str());
+    }
+    if (!dW[i] || !db[i]) return fail(PINN_ERR_ARG, "network %d: dW or db is NULL", i);
+    for (int l = 0; l < b->L[i]; ++l)
+      if (!dW[i][l] || !db[i][l]) return fail(PINN_ERR_ARG, "network %d: dW[%d] or db[%d] is NULL", i, l, l);
+    key.push_back(x[i]);
+    key.push_back(reinterpret_cast<const void *>((intptr_t)N[i]));
+    for (int q = 0; q < 4; ++q) {
+      double c = pdes[i].coef[q];
+      intptr_t bits;
+      std::memcpy(&bits, &c, sizeof bits);
+      key.push_back(reinterpret_cast<const void *>(bits));
+    }
+    for (int l = 0; l < b->L[i]; ++l) {
+      key.push_back(nets[i].W[l]);
+      key.push_back(nets[i].b[l]);
+      key.push_back(dW[i][l]);
+      key.push_back(db[i][l]);
+    }
+    // the tuning selects the kernels
+    key.push_back(reinterpret_cast<const void *>((intptr_t)b->plans[i]->dw_splits));
+    key.push_back(reinterpret_cast<const void *>((intptr_t)(b->plans[i]->fwd_points * 2 + b->plans[i]->bwd_fused)));
+  }
+  return PINN_OK;
+}
+
+pinn_status batch_run(pinn_batch b, const pinn_net *nets, const pinn_pde *pdes, const float *const *x,
+                      const int64_t *N, float *loss, float *const *const *dW, float *const *const *db,
+                      const BatchTrain *train, void *stream) {
+  std::vector<const void *> key;
+  pinn_status st = batch_check(b, nets, pdes, x, N, loss, dW, db, key);
+  if (st) return st;
+  if (train) {
+    key.push_back(train->step_dev);
+    for (int i = 0; i < b->n; ++i)
+      for (int l = 0; l < b->L[i]; ++l) {
+        key.push_back(train->mW[i][l]);
+        key.push_back(train->vW[i][l]);
+        key.push_back(train->mb[i][l]);
+        key.push_back(train->vb[i][l]);
+      }
+    const double *h = &train->hp->lr;
+    for (int q = 0; q < 4; ++q) {
+      intptr_t bits;
+      std::memcpy(&bits, h + q, sizeof bits);
+      key.push_back(reinterpret_cast<const void *>(bits));
+    }
+  }
+  key.push_back(reinterpret_cast<const void *>((intptr_t)b->n_streams));
+  hipStream_t caller = (hipStream_t)stream;
+  if (b->lanes.empty() || key != b->key) {
+    st = batch_build(b, nets, pdes, x, N, loss, dW, db, train);
+    if (st) return st;
+    b->key = key;
+  }
+  if (!b->use_graph || b->prof_class != 0) return batch_enqueue(b, caller);
+  hipError_t e;
+  if (!b->exec) {
+    e = hipStreamBeginCapture(b->origin, hipStreamCaptureModeRelaxed);
+    if (e) return hip_fail(e, "graph capture");
+    st = batch_enqueue(b, b->origin);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->origin, &g);
+    if (st) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e) return hip_fail(e, "graph capture");
+    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e) return hip_fail(e, "graph instantiate");
+  }
+  e = hipEventRecord(b->ev_in, caller);
+  if (e == hipSuccess) e = hipStreamWaitEvent(b->origin, b->ev_in, 0);
+  if (e == hipSuccess) e = hipGraphLaunch(b->exec, b->origin);
+  if (e == hipSuccess) e = hipEventRecord(b->ev_out, b->origin);
+  if (e == hipSuccess) e = hipStreamWaitEvent(caller, b->ev_out, 0);
+  if (e) return hip_fail(e, "graph launch");
   return PINN_OK;
 }
 
@@ -1268,9 +1861,10 @@ pinn_status pinn_batch_create(int32_t n, const pinn_net *nets, const pinn_pde *p
     }
     b->plans.push_back(p);
     b->L.push_back(nets[i].n_layers);
+    b->width.push_back(p->w);
   }
   b->n = n;
-  hipError_t e = batch_streams(b, std::min(8, n));
+  hipError_t e = batch_streams(b, 4);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
@@ -1286,6 +1880,8 @@ pinn_status pinn_batch_create(int32_t n, const pinn_net *nets, const pinn_pde *p
 pinn_status pinn_batch_destroy(pinn_batch b) {
   g_err.clear();
   if (!b) return fail(PINN_ERR_ARG, "batch is NULL");
+  (void)hipStreamSynchronize(b->origin);
+  for (hipStream_t s : b->streams) (void)hipStreamSynchronize(s);
   delete b;
   return PINN_OK;
 }
@@ -1298,11 +1894,7 @@ pinn_status pinn_batch_configure(pinn_batch b, int32_t n_streams, int32_t use_gr
   hipError_t e = batch_streams(b, n_streams);
   if (e) return hip_fail(e, "batch streams");
   b->use_graph = use_graph != 0;
-  if (b->exec) {
-    (void)hipGraphExecDestroy(b->exec);
-    b->exec = nullptr;
-  }
-  b->key.clear();
+  invalidate(b);
   return PINN_OK;
 }
 
@@ -1311,67 +1903,56 @@ pinn_status pinn_batch_step(pinn_batch b, const pinn_net *nets, const pinn_pde *
                             void *stream) {
   g_err.clear();
   if (!b) return fail(PINN_ERR_ARG, "batch is NULL");
-  if (!nets || !pdes || !x || !N || !loss || !dW || !db) return fail(PINN_ERR_ARG, "a batch argument is NULL");
-  // validate everything on the host before enqueueing anything
-  std::vector<const void *> key;
-  key.push_back(loss);
-  for (int i = 0; i < b->n; ++i) {
-    pinn_status st = check_call(b->plans[i], &nets[i], x[i], N[i]);
-    if (st == PINN_OK) st = check_pde(&pdes[i], b->plans[i]->kind);
-    if (st) {
-      std::string msg = g_err;
-      return fail(st, "network %d: %s", i, msg.c_str());
-    }
-    if (!dW[i] || !db[i]) return fail(PINN_ERR_ARG, "network %d: dW or db is NULL", i);
-    for (int l = 0; l < b->L[i]; ++l)
-      if (!dW[i][l] || !db[i][l]) return fail(PINN_ERR_ARG, "network %d: dW[%d] or db[%d] is NULL", i, l, l);
-    key.push_back(x[i]);
-    key.push_back(reinterpret_cast<const void *>((intptr_t)N[i]));
-    for (int q = 0; q < 4; ++q) {
-      double c = pdes[i].coef[q];
-      intptr_t bits;
-      std::memcpy(&bits, &c, sizeof bits);
-      key.push_back(reinterpret_cast<const void *>(bits));
-    }
-    for (int l = 0; l < b->L[i]; ++l) {
-      key.push_back(nets[i].W[l]);
-      key.push_back(nets[i].b[l]);
-      key.push_back(dW[i][l]);
-      key.push_back(db[i][l]);
-    }
-  }
-  hipStream_t caller = (hipStream_t)stream;
-  if (!b->use_graph) return batch_enqueue(b, nets, pdes, x, N, loss, dW, db, caller);
+  return batch_run(b, nets, pdes, x, N, loss, dW, db, nullptr, stream);
+}
 
-  hipError_t e;
-  if (!b->exec || key != b->key) {
-    // capture one step on the private origin stream, then instantiate it
-    if (b->exec) {
-      (void)hipGraphExecDestroy(b->exec);
-      b->exec = nullptr;
-    }
-    for (pinn_plan p : b->plans) p->prof_class = 0;  // no event timing inside a graph
-    e = hipStreamBeginCapture(b->origin, hipStreamCaptureModeRelaxed);
-    if (e) return hip_fail(e, "graph capture");
-    pinn_status st = batch_enqueue(b, nets, pdes, x, N, loss, dW, db, b->origin);
-    hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(b->origin, &g);
-    if (st) {
-      if (g) (void)hipGraphDestroy(g);
-      return st;
-    }
-    if (e) return hip_fail(e, "graph capture");
-    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e) return hip_fail(e, "graph instantiate");
-    b->key = key;
-  }
-  e = hipEventRecord(b->ev_in, caller);
-  if (e == hipSuccess) e = hipStreamWaitEvent(b->origin, b->ev_in, 0);
-  if (e == hipSuccess) e = hipGraphLaunch(b->exec, b->origin);
-  if (e == hipSuccess) e = hipEventRecord(b->ev_out, b->origin);
-  if (e == hipSuccess) e = hipStreamWaitEvent(caller, b->ev_out, 0);
-  if (e) return hip_fail(e, "graph launch");
+pinn_status pinn_batch_train_step(pinn_batch b, const pinn_net *nets, const pinn_pde *pdes, const float *const *x,
+                                  const int64_t *N, float *loss, float *const *const *dW, float *const *const *db,
+                                  float *const *const *mW, float *const *const *vW, float *const *const *mb,
+                                  float *const *const *vb, const struct pinn_adam_s *hp, int64_t *step_dev,
+                                  void *stream) {
+  g_err.clear();
+  if (!b) return fail(PINN_ERR_ARG, "batch is NULL");
+  if (!mW || !vW || !mb || !vb || !hp || !step_dev) return fail(PINN_ERR_ARG, "an Adam argument is NULL");
+  for (int i = 0; i < b->n; ++i)
+    if (!mW[i] || !vW[i] || !mb[i] || !vb[i]) return fail(PINN_ERR_ARG, "network %d: moment arrays NULL", i);
+  BatchTrain t{mW, vW, mb, vb, hp, step_dev};
+  return batch_run(b, nets, pdes, x, N, loss, dW, db, &t, stream);
+}
+
+pinn_status pinn_batch_profile(pinn_batch b, int32_t kernel_class) {
+  g_err.clear();
+  if (!b) return fail(PINN_ERR_ARG, "batch is NULL");
+  if (kernel_class < 0 || kernel_class > PINN_K_BWD_DW)
+    return fail(PINN_ERR_ARG, "unknown kernel class %d", kernel_class);
+  b->prof_class = kernel_class;
+  b->ev_used = 0;
+  b->prof_ms = 0.0;
+  b->prof_launches = 0;
+  return PINN_OK;
+}
+
+pinn_status pinn_batch_profile_read(pinn_batch b, double *total_ms, int64_t *launches) {
+  g_err.clear();
+  if (!b) return fail(PINN_ERR_ARG, "batch is NULL");
+  const hipError_t e = b->harvest();
+  if (e) return hip_fail(e, "event timing");
+  if (total_ms) *total_ms = b->prof_ms;
+  if (launches) *launches = b->prof_launches;
+  return PINN_OK;
+}
+
+pinn_status pinn_batch_get_tuning(pinn_batch b, int32_t i, pinn_tuning *t) {
+  g_err.clear();
+  if (!b || !t) return fail(PINN_ERR_ARG, "batch or tuning is NULL");
+  if (i < 0 || i >= b->n) return fail(PINN_ERR_ARG, "network %d outside [0, %d)", i, b->n);
+  return pinn_plan_get_tuning(b->plans[i], t);
+}
+
+pinn_status pinn_batch_launches(pinn_batch b, int64_t *launches) {
+  g_err.clear();
+  if (!b || !launches) return fail(PINN_ERR_ARG, "batch or launches is NULL");
+  *launches = (int64_t)b->n_launches;
   return PINN_OK;
 }
 
@@ -1381,6 +1962,20 @@ pinn_status pinn_batch_autotune(pinn_batch b, const pinn_net *nets, const pinn_p
   g_err.clear();
   if (!b) return fail(PINN_ERR_ARG, "batch is NULL");
   if (reps < 1 || reps > 1000) return fail(PINN_ERR_ARG, "reps = %d outside [1, 1000]", reps);
+  std::vector<const void *> key;
+  pinn_status st = batch_check(b, nets, pdes, x, N, loss, dW, db, key);
+  if (st) return st;
+  // every member's tuning (point tiles, fused or separate weight gradient,
+  // split count) from the plan autotuner, through its cache: members that
+  // share width, depth and point-count bucket are timed once
+  for (int i = 0; i < b->n; ++i) {
+    st = pinn_plan_autotune(b->plans[i], &nets[i], &pdes[i], x[i], N[i], reps, nullptr, nullptr, stream);
+    if (st) {
+      const std::string msg = g_err;
+      return fail(st, "network %d: %s", i, msg.c_str());
+    }
+  }
+  // then the number of lanes
   hipStream_t caller = (hipStream_t)stream;
   hipEvent_t t0, t1;
   hipError_t e = hipEventCreate(&t0);
@@ -1393,9 +1988,7 @@ pinn_status pinn_batch_autotune(pinn_batch b, const pinn_net *nets, const pinn_p
   const bool graph = b->use_graph;
   double bms = 1e300;
   int bs = b->n_streams;
-  pinn_status st = PINN_OK;
-  for (int ns : {1, 2, 4, 8, 16}) {
-    if (ns > b->n) break;
+  for (int ns : {1, 2, 4}) {
     st = pinn_batch_configure(b, ns, graph);
     for (int it = -1; it < reps && st == PINN_OK; ++it) {
       if (it == 0) e = hipEventRecord(t0, caller);

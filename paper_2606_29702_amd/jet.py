@@ -12,7 +12,8 @@ from typing import List, Optional, Sequence, Tuple
 import torch
 
 from . import _lib
-from ._lib import KINDS, PRECISIONS, Net, Pde, Tuning, check, lib, ptr_array
+from ._lib import KINDS, PRECISIONS, SEG_DATA, SEG_TYPES, Net, Pde, PinnError, Segment, Tuning, check, lib, ptr_array
+from .closure import channels, resolve_kind
 
 CHANNELS = {k: lib.pinn_pde_channels(v) for k, v in KINDS.items()}
 RESIDUALS = {k: lib.pinn_pde_residuals(v) for k, v in KINDS.items()}
@@ -77,6 +78,21 @@ class PinnPlan:
         check(lib.pinn_plan_create(ctypes.byref(net), ctypes.byref(_pde(pde, self.coef)), self.max_points,
                                    PRECISIONS[precision], flags, int(save_cap_bytes), ctypes.byref(handle)))
         self.handle = handle
+
+    @classmethod
+    def for_derivatives(cls, dims: Sequence[int], derivatives, max_points: int, pde: Optional[str] = None,
+                        **kwargs) -> "PinnPlan":
+        """A plan for a residual given by the coordinate derivatives it uses
+        (tuples of input directions, () the value): the channel closure of
+        Sec. 2.2 picks the compiled kind (or checks that `pde` carries it).
+        Raises PinnError PINN_ERR_UNSUPPORTED when no compiled kind does."""
+        derivatives = [tuple(d) for d in derivatives]
+        kind = resolve_kind(derivatives, pde)
+        if kind is None:
+            raise PinnError(_lib.PINN_ERR_UNSUPPORTED,
+                            f"no compiled kind carries the channel closure {channels(derivatives)}"
+                            + (f" (kind {pde!r})" if pde else ""))
+        return cls(dims, kind, max_points, **kwargs)
 
     def close(self) -> None:
         if getattr(self, "handle", None):
@@ -186,6 +202,48 @@ class PinnPlan:
             dWp, dbp, dW64p, db64p, _stream()))
         return (grads, g64) if want_f64 else grads
 
+
+    # ------------------------------------------------------------ composite loss
+    @staticmethod
+    def _segments(segments):
+        arr = (Segment * len(segments))()
+        for i, sg in enumerate(segments):
+            arr[i].type = SEG_TYPES[sg["type"]]
+            arr[i].data = SEG_DATA[sg.get("data", "zero")]
+            arr[i].begin = int(sg["begin"])
+            arr[i].count = int(sg["count"])
+            arr[i].weight = float(sg.get("weight", 1.0))
+            arr[i].mask = int(sg.get("mask", 0))
+            for q, v in enumerate(sg.get("param", ())):
+                arr[i].param[q] = float(v)
+        return arr
+
+    def loss(self, params, x: torch.Tensor, segments):
+        """Composite loss over point segments (all points evaluated together,
+        then split; see pinn_jet_loss).  segments: list of dicts with type
+        ('pde', 'dirichlet', 'periodic'), begin, count, weight, mask, data
+        ('zero', 'const', 'sin') and param.  Returns (loss (), seg_loss (n,))."""
+        _check_tensor(x, "x")
+        nv = _NetView(params)
+        segs = self._segments(segments)
+        loss = torch.empty((), device=x.device, dtype=torch.float32)
+        seg_loss = torch.empty(len(segments), device=x.device, dtype=torch.float32)
+        check(lib.pinn_jet_loss(self.handle, ctypes.byref(nv.net), ctypes.byref(_pde(self.pde, self.coef)), segs,
+                                len(segments), ctypes.c_void_p(x.data_ptr()), x.shape[0],
+                                ctypes.c_void_p(loss.data_ptr()), ctypes.c_void_p(seg_loss.data_ptr()), _stream()))
+        return loss, seg_loss
+
+    def loss_backward(self, params, x: torch.Tensor, segments, out=None):
+        """d loss / d theta of the composite loss of the preceding loss() call."""
+        nv = _NetView(params)
+        segs = self._segments(segments)
+        grads = out if out is not None else [(torch.empty_like(W), torch.empty_like(b)) for W, b in params]
+        dWp, k1 = ptr_array([g[0].data_ptr() for g in grads])
+        dbp, k2 = ptr_array([g[1].data_ptr() for g in grads])
+        check(lib.pinn_jet_loss_backward(self.handle, ctypes.byref(nv.net), ctypes.byref(_pde(self.pde, self.coef)),
+                                         segs, len(segments), ctypes.c_void_p(x.data_ptr()), x.shape[0], dWp, dbp,
+                                         _stream()))
+        return grads
 
     def capture_step(self, params, x: torch.Tensor, adam=None) -> "PinnGraph":
         """The residual + loss-gradient step on (params, x) as a replayable
@@ -310,3 +368,22 @@ def jet_step_noalloc(params, x: torch.Tensor, pde: str, coef: Optional[Sequence[
                                     ctypes.c_void_p(x.data_ptr()), N, ctypes.c_void_p(r.data_ptr()),
                                     ctypes.c_void_p(loss.data_ptr()), dWp, dbp, _stream()))
     return r, loss, grads
+
+
+def tuning_cache_clear() -> None:
+    """Drops every entry of the process's autotuning cache."""
+    check(lib.pinn_tuning_cache_clear())
+
+
+def tuning_cache_size() -> int:
+    n = ctypes.c_int64()
+    check(lib.pinn_tuning_cache_size(ctypes.byref(n)))
+    return n.value
+
+
+def tuning_cache_save(path: str) -> None:
+    check(lib.pinn_tuning_cache_save(path.encode()))
+
+
+def tuning_cache_load(path: str) -> None:
+    check(lib.pinn_tuning_cache_load(path.encode()))

@@ -38,3 +38,42 @@ def test_closure_is_minimal():
 def test_unsupported_mixed_order_is_rejected():
     with pytest.raises(ValueError):
         closure([(0, 0, 1)])
+
+
+def test_compiled_channel_sets_are_the_abi_orders():
+    from paper_2606_29702_amd.closure import KIND_CHANNELS
+    assert KIND_CHANNELS == pi.CHANNELS
+
+
+@pytest.mark.parametrize("kind", sorted(USES))
+def test_resolve_kind_from_derivatives(kind):
+    from paper_2606_29702_amd.closure import resolve_kind
+    assert resolve_kind(USES[kind]) == kind
+    assert resolve_kind(USES[kind], kind) == kind
+
+
+def test_resolve_kind_subsets_and_unsupported():
+    from paper_2606_29702_amd.closure import resolve_kind
+    # u_t + u_xx alone closes to the Burgers set; a residual using only u_x
+    # has no exactly matching kind but is carried by the Burgers kind
+    assert resolve_kind([(1,), (0, 0)]) == "burgers"
+    assert resolve_kind([(0,)]) is None
+    assert resolve_kind([(0,)], "burgers") == "burgers"
+    # a third derivative along y is carried by no compiled kind
+    assert resolve_kind([(1, 1, 1)]) is None
+    assert resolve_kind([(1, 1, 1)], "ks") is None
+    assert resolve_kind([(0, 1)], "ns") is None     # the mixed derivative is only in the aniso set
+    assert resolve_kind([(0, 1)], "aniso") == "aniso"
+    assert resolve_kind([()], "nonexistent") is None
+
+
+def test_plan_for_derivatives_rejects_unsupported_closures():
+    """Plan creation from a derivative list: an unsupported closure fails with
+    PINN_ERR_UNSUPPORTED before any device work."""
+    import paper_2606_29702_amd as pj
+    with pytest.raises(pj.PinnError) as ei:
+        pj.PinnPlan.for_derivatives([2, 32, 32, 1], [(1, 1, 1)], 128)
+    assert ei.value.status == -2
+    with pytest.raises(pj.PinnError) as ei:
+        pj.PinnPlan.for_derivatives([2, 32, 32, 3], [(0, 1)], 128, pde="ns")
+    assert ei.value.status == -2

@@ -98,11 +98,20 @@ def test_batch_recaptures_on_new_inputs_and_autotunes(lib):
     g2 = [flat(g) for g in grads2]
     np.testing.assert_allclose(loss2.cpu().numpy(), l1, rtol=1e-4)
     ns, ms = batch.autotune(params, xs2, reps=2)
-    assert ns in (1, 2, 4, 8, 16) and ms > 0
+    assert ns in (1, 2, 4) and ms > 0
+    # the autotuner may pick other tilings and split counts per member, which
+    # reorders sums: close to the earlier step, and steps with the tuned
+    # schedule repeat bit for bit
     loss3, grads3 = batch.step(params, xs2)
     torch.cuda.synchronize()
-    assert np.array_equal(loss3.cpu().numpy(), loss2.cpu().numpy())
-    for a, g in zip(g2, grads3):
+    l3, g3 = loss3.cpu().numpy().copy(), [flat(g) for g in grads3]
+    np.testing.assert_allclose(l3, loss2.cpu().numpy(), rtol=1e-3)
+    for a, g in zip(g2, g3):
+        assert rel(g, a) <= 1e-2
+    loss4, grads4 = batch.step(params, xs2)
+    torch.cuda.synchronize()
+    assert np.array_equal(loss4.cpu().numpy(), l3)
+    for a, g in zip(g3, grads4):
         assert np.array_equal(a, flat(g))
     batch.close()
 
@@ -215,3 +224,81 @@ def test_training_graph_matches_eager_training(lib):
     graph.close()
     plan_g.close()
     plan_e.close()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_batch_train_step_matches_eager_training(lib, prec):
+    """Three batched training steps (grouped launches with the Adam update in
+    one graph) equal three eager single-plan steps with AdamState per network,
+    bit for bit: parameters, losses and the device step counter."""
+    ens = small_ensemble(n=6, seed=7)
+    pb, xs = to_dev(ens)
+    pe = [[(W.clone(), b.clone()) for W, b in ps] for ps in pb]
+    batch = lib.PinnBatch([m.dims for m in ens], "burgers", [(m.nu,) for m in ens], [m.N for m in ens],
+                          precision=prec)
+    adam = lib.BatchAdam(pb, lr=1e-3)
+    plans = [lib.PinnPlan(m.dims, "burgers", m.N, precision=prec, coef=(m.nu,)) for m in ens]
+    opts = [lib.AdamState(ps, lr=1e-3) for ps in pe]
+    grads = [[(torch.empty_like(W), torch.empty_like(b)) for W, b in ps] for ps in pe]
+    for k in range(3):
+        loss_b, _ = batch.train_step(pb, xs, adam)
+        losses = []
+        for pl, ps, x, opt, g in zip(plans, pe, xs, opts, grads):
+            _, l, _, _ = pl.residual(ps, x)
+            pl.backward(ps, x, out=g)
+            opt.step(g)
+            losses.append(l)
+        torch.cuda.synchronize()
+        assert int(adam.step) == k + 1
+        for i in range(len(ens)):
+            assert float(loss_b[i]) == float(losses[i]), (k, i)
+            for (a, b), (c, d) in zip(pb[i], pe[i]):
+                assert torch.equal(a, c) and torch.equal(b, d), (k, i)
+    assert batch.launches() > 0
+    batch.close()
+    for pl in plans:
+        pl.close()
+
+
+def test_batch_profile_times_a_kernel_class(lib):
+    """Timing one kernel class runs the grouped launches eagerly with events
+    on their lanes; the results equal those of the graph replay."""
+    ens = small_ensemble(n=5, seed=8)
+    params, xs = to_dev(ens)
+    batch = lib.PinnBatch([m.dims for m in ens], "burgers", [(m.nu,) for m in ens], [m.N for m in ens])
+    loss, grads = batch.step(params, xs)
+    torch.cuda.synchronize()
+    ref = (loss.cpu().numpy().copy(), [flat(g) for g in grads])
+    batch.profile("layer_fwd")
+    loss, grads = batch.step(params, xs)
+    ms, n = batch.profile_read()
+    batch.profile("off")
+    torch.cuda.synchronize()
+    assert n >= 1 and ms > 0
+    assert np.array_equal(loss.cpu().numpy(), ref[0])
+    for a, g in zip(ref[1], grads):
+        assert np.array_equal(a, flat(g))
+    batch.close()
+
+
+def test_autotune_cache_hit(lib, tmp_path):
+    """A second plan with the same key (width, depth, kind, operand type,
+    point-count bucket) takes the cached tuning without timing; the cache
+    survives a save and a load."""
+    lib.tuning_cache_clear()
+    prob = pi.make_problem("ns", N=3000, seed=5, bias_std=0.2, dims=[2, 64, 64, 64, 3])
+    params = [(torch.tensor(W, device="cuda"), torch.tensor(b, device="cuda")) for W, b in prob.params]
+    x = torch.tensor(prob.x, device="cuda")
+    p1 = lib.PinnPlan(prob.workload.dims, "ns", 3000, precision="bf16", coef=prob.coef)
+    t1, ms1 = p1.autotune(params, x, reps=2)
+    assert lib.tuning_cache_size() == 1
+    p2 = lib.PinnPlan(prob.workload.dims, "ns", 3000, precision="bf16", coef=prob.coef)
+    t2, ms2 = p2.autotune(params, x, reps=2)
+    assert t2 == t1 and ms2 == ms1
+    path = str(tmp_path / "cache.txt")
+    lib.tuning_cache_save(path)
+    lib.tuning_cache_clear()
+    lib.tuning_cache_load(path)
+    assert lib.tuning_cache_size() == 1
+    p1.close()
+    p2.close()
