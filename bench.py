@@ -191,6 +191,7 @@ def ensemble_headline(ens, params, xs, prec, steps, warmup, runs, replays):
     batch.profile("off")
     tunings = [batch.tuning(i) for i in range(len(ens))]
     launches = batch.launches()
+    lanes = batch.config()
     batch.close()
     flops = dict.fromkeys(ALL_CLASSES, 0.0)
     for m, t in zip(ens, tunings):

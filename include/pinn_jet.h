@@ -310,16 +310,25 @@ pinn_status pinn_tuning_cache_load(const char *path);
  *                       nets[i].W, b updated in place) and one advance of the
  *                       device step counter *step_dev (0 before the first
  *                       step), all in the same graph.
- *   pinn_batch_configure  the number of lanes (1..16; widths beyond it share
- *                       lanes) and graph on/off.
+ *   pinn_batch_configure  the number of streams (1..16) and the flags:
+ *                       PINN_BATCH_GRAPH captures the step into a graph;
+ *                       PINN_BATCH_PER_NETWORK makes the lanes the streams
+ *                       themselves, networks dealt to them longest first by
+ *                       estimated work (without it: one lane per hidden
+ *                       width, widths beyond the stream count sharing lanes).
  *   pinn_batch_launches  grouped launches per step of the current schedule.
  *   pinn_batch_autotune  runs pinn_plan_autotune on every network (networks
  *                       sharing a cache key are timed once), then times
- *                       `reps` steps for 1, 2 and 4 lanes and keeps the fastest. */
+ *                       `reps` steps for width lanes on 1, 2 and 4 streams and
+ *                       per-network lanes on 8 and 16, and keeps the fastest
+ *                       (best_streams receives the stream count). */
+enum { PINN_BATCH_GRAPH = 1, PINN_BATCH_PER_NETWORK = 2 };
 pinn_status pinn_batch_create(int32_t n, const pinn_net *nets, const pinn_pde *pdes, const int64_t *max_points,
                               int32_t prec, uint32_t flags, pinn_batch *out);
 pinn_status pinn_batch_destroy(pinn_batch batch);
 pinn_status pinn_batch_configure(pinn_batch batch, int32_t n_streams, int32_t use_graph);
+/* The current stream count and PINN_BATCH_* flags (after pinn_batch_autotune). */
+pinn_status pinn_batch_get_config(pinn_batch batch, int32_t *n_streams, int32_t *flags);
 pinn_status pinn_batch_step(pinn_batch batch, const pinn_net *nets, const pinn_pde *pdes, const float *const *x,
                             const int64_t *N, float *loss, float *const *const *dW, float *const *const *db,
                             void *stream);

@@ -23,6 +23,7 @@ STATUS_NAMES = {0: "PINN_OK", -1: "PINN_ERR_ARG", -2: "PINN_ERR_UNSUPPORTED", -3
 KINDS = {"burgers": 1, "ns": 2, "ks": 3, "heat": 4, "aniso": 5, "burgers_bc": 6}
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
 PINN_VERIFY_F64 = 1
+PINN_BATCH_GRAPH, PINN_BATCH_PER_NETWORK = 1, 2
 
 # Every symbol the public header declares.
 EXPORTS = ["pinn_plan_create", "pinn_plan_destroy", "pinn_plan_memory", "pinn_jet_forward",
@@ -34,7 +35,7 @@ EXPORTS = ["pinn_plan_create", "pinn_plan_destroy", "pinn_plan_memory", "pinn_je
            "pinn_jet_step_noalloc", "pinn_jet_backward_cot", "pinn_batch_train_step", "pinn_batch_launches",
            "pinn_batch_profile", "pinn_batch_profile_read", "pinn_batch_get_tuning",
            "pinn_tuning_cache_clear", "pinn_tuning_cache_size", "pinn_tuning_cache_save", "pinn_tuning_cache_load",
-           "pinn_jet_loss", "pinn_jet_loss_backward"]
+           "pinn_jet_loss", "pinn_jet_loss_backward", "pinn_batch_get_config"]
 KERNEL_CLASSES = {"layer_fwd": 1, "layer_bwd": 2, "dw_hidden": 3, "out_fwd": 4, "out_bwd": 5,
                   "seed_fwd": 6, "other": 7, "bwd_dw": 8}
 
@@ -105,6 +106,7 @@ def _load():
     lib.pinn_jet_loss.argtypes = [vp, NetP, PdeP, SegP, i32, vp, i64, vp, vp, vp]
     lib.pinn_jet_loss_backward.argtypes = [vp, NetP, PdeP, SegP, i32, vp, i64, pp, pp, vp]
     lib.pinn_batch_launches.argtypes = [vp, i64p]
+    lib.pinn_batch_get_config.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.pinn_batch_get_tuning.argtypes = [vp, i32, TuneP]
     lib.pinn_batch_profile.argtypes = [vp, i32]
     lib.pinn_batch_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -135,7 +137,7 @@ def _load():
                  "pinn_jet_backward_cot", "pinn_batch_train_step", "pinn_batch_launches", "pinn_batch_profile",
                  "pinn_batch_profile_read", "pinn_batch_get_tuning", "pinn_tuning_cache_clear",
                  "pinn_tuning_cache_size", "pinn_tuning_cache_save", "pinn_tuning_cache_load", "pinn_jet_loss",
-                 "pinn_jet_loss_backward"):
+                 "pinn_jet_loss_backward", "pinn_batch_get_config"):
         getattr(lib, name).restype = ctypes.c_int32
     return lib
 

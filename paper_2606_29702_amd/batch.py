@@ -15,6 +15,7 @@ from typing import List, Optional, Sequence, Tuple
 
 import torch
 
+from . import _lib
 from ._lib import Adam as _AdamHP, KINDS, PRECISIONS, Net, Pde, Tuning, check, lib, ptr_array
 from .jet import DEFAULT_COEF, _check_tensor, _stream
 
@@ -65,8 +66,16 @@ class PinnBatch:
         except Exception:
             pass
 
-    def configure(self, n_streams: int, use_graph: bool = True) -> None:
-        check(lib.pinn_batch_configure(self.handle, int(n_streams), 1 if use_graph else 0))
+    def configure(self, n_streams: int, use_graph: bool = True, per_network: bool = False) -> None:
+        flags = (_lib.PINN_BATCH_GRAPH if use_graph else 0) | (_lib.PINN_BATCH_PER_NETWORK if per_network else 0)
+        check(lib.pinn_batch_configure(self.handle, int(n_streams), flags))
+
+    def config(self) -> dict:
+        """{'streams', 'graph', 'per_network'} of the current schedule."""
+        ns, fl = ctypes.c_int32(), ctypes.c_int32()
+        check(lib.pinn_batch_get_config(self.handle, ctypes.byref(ns), ctypes.byref(fl)))
+        return {"streams": ns.value, "graph": bool(fl.value & _lib.PINN_BATCH_GRAPH),
+                "per_network": bool(fl.value & _lib.PINN_BATCH_PER_NETWORK)}
 
     def _marshal(self, params_list, xs):
         key = tuple(t.data_ptr() for ps in params_list for pair in ps for t in pair) + \

@@ -1489,6 +1489,7 @@ struct pinn_batch_s {
   hipEvent_t ev_fork = nullptr, ev_in = nullptr, ev_out = nullptr;
   hipStream_t origin = nullptr;       // capture origin
   bool use_graph = true;
+  bool per_network = false;           // lanes: by hidden width, or networks balanced over the streams
   hipGraphExec_t exec = nullptr;
   std::vector<const void *> key;      // every pointer and size baked into the schedule
   // the schedule
@@ -1677,16 +1678,39 @@ pinn_status batch_build(pinn_batch b, const pinn_net *nets, const pinn_pde *pdes
   }
   hipError_t e = hipMemcpy(b->dev_args, host.data(), total, hipMemcpyHostToDevice);
   if (e) return hip_fail(e, "batch argument table");
-  // lanes: one per hidden width (widths in increasing order), folded onto the streams
-  std::vector<int> widths(b->width);
-  std::sort(widths.begin(), widths.end());
-  widths.erase(std::unique(widths.begin(), widths.end()), widths.end());
-  const int n_lanes = std::min<int>((int)widths.size(), b->n_streams);
-  std::vector<std::vector<int>> members(n_lanes);
-  for (int i = 0; i < b->n; ++i) {
-    const int wi = (int)(std::lower_bound(widths.begin(), widths.end(), b->width[i]) - widths.begin());
-    members[wi % n_lanes].push_back(i);
+  // lanes: one per hidden width (widths in increasing order), folded onto the
+  // streams; or, per network, the networks dealt longest first to the lane
+  // with the least estimated work (hidden-layer flops w^2 C H N)
+  std::vector<std::vector<int>> members;
+  if (b->per_network) {
+    const int n_lanes = std::min(b->n, b->n_streams);
+    members.assign(n_lanes, {});
+    std::vector<double> cost(b->n), load(n_lanes, 0.0);
+    std::vector<int> order(b->n);
+    for (int i = 0; i < b->n; ++i) {
+      const pinn_plan p = b->plans[i];
+      cost[i] = (double)p->w * p->w * p->ki.C * p->H * (double)N[i];
+      order[i] = i;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+    for (int i : order) {
+      const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      members[l].push_back(i);
+      load[l] += cost[i];
+    }
+    for (auto &m : members) std::sort(m.begin(), m.end());
+  } else {
+    std::vector<int> widths(b->width);
+    std::sort(widths.begin(), widths.end());
+    widths.erase(std::unique(widths.begin(), widths.end()), widths.end());
+    const int n_lanes = std::min<int>((int)widths.size(), b->n_streams);
+    members.assign(n_lanes, {});
+    for (int i = 0; i < b->n; ++i) {
+      const int wi = (int)(std::lower_bound(widths.begin(), widths.end(), b->width[i]) - widths.begin());
+      members[wi % n_lanes].push_back(i);
+    }
   }
+  const int n_lanes = (int)members.size();
   b->lanes.assign(n_lanes, {});
   b->n_launches = 0;
   char *base = static_cast<char *>(b->dev_args);
@@ -1806,6 +1830,7 @@ pinn_status batch_run(pinn_batch b, const pinn_net *nets, const pinn_pde *pdes, 
     }
   }
   key.push_back(reinterpret_cast<const void *>((intptr_t)b->n_streams));
+  key.push_back(reinterpret_cast<const void *>((intptr_t)b->per_network));
   hipStream_t caller = (hipStream_t)stream;
   if (b->lanes.empty() || key != b->key) {
     st = batch_build(b, nets, pdes, x, N, loss, dW, db, train);
@@ -1891,10 +1916,21 @@ pinn_status pinn_batch_configure(pinn_batch b, int32_t n_streams, int32_t use_gr
   if (!b) return fail(PINN_ERR_ARG, "batch is NULL");
   if (n_streams < 1 || n_streams > kMaxBatchStreams)
     return fail(PINN_ERR_ARG, "n_streams = %d outside [1, %d]", n_streams, kMaxBatchStreams);
+  if (use_graph & ~(PINN_BATCH_GRAPH | PINN_BATCH_PER_NETWORK))
+    return fail(PINN_ERR_ARG, "unknown batch flags 0x%x", use_graph);
   hipError_t e = batch_streams(b, n_streams);
   if (e) return hip_fail(e, "batch streams");
-  b->use_graph = use_graph != 0;
+  b->use_graph = (use_graph & PINN_BATCH_GRAPH) != 0;
+  b->per_network = (use_graph & PINN_BATCH_PER_NETWORK) != 0;
   invalidate(b);
+  return PINN_OK;
+}
+
+pinn_status pinn_batch_get_config(pinn_batch b, int32_t *n_streams, int32_t *flags) {
+  g_err.clear();
+  if (!b || !n_streams || !flags) return fail(PINN_ERR_ARG, "a pinn_batch_get_config argument is NULL");
+  *n_streams = b->n_streams;
+  *flags = (b->use_graph ? PINN_BATCH_GRAPH : 0) | (b->per_network ? PINN_BATCH_PER_NETWORK : 0);
   return PINN_OK;
 }
 
@@ -1985,11 +2021,14 @@ pinn_status pinn_batch_autotune(pinn_batch b, const pinn_net *nets, const pinn_p
     (void)hipEventDestroy(t0);
     return hip_fail(e, "autotune events");
   }
-  const bool graph = b->use_graph;
+  const int graph = b->use_graph ? PINN_BATCH_GRAPH : 0;
   double bms = 1e300;
-  int bs = b->n_streams;
-  for (int ns : {1, 2, 4}) {
-    st = pinn_batch_configure(b, ns, graph);
+  int bs = b->n_streams, bmode = b->per_network ? PINN_BATCH_PER_NETWORK : 0;
+  const std::pair<int, int> cands[] = {{1, 0}, {2, 0}, {4, 0}, {8, PINN_BATCH_PER_NETWORK},
+                                       {16, PINN_BATCH_PER_NETWORK}};
+  for (const auto &cand : cands) {
+    const int ns = cand.first, mode = cand.second;
+    st = pinn_batch_configure(b, ns, graph | mode);
     for (int it = -1; it < reps && st == PINN_OK; ++it) {
       if (it == 0) e = hipEventRecord(t0, caller);
       st = pinn_batch_step(b, nets, pdes, x, N, loss, dW, db, stream);
@@ -2003,13 +2042,14 @@ pinn_status pinn_batch_autotune(pinn_batch b, const pinn_net *nets, const pinn_p
     if (ms / reps < bms) {
       bms = ms / reps;
       bs = ns;
+      bmode = mode;
     }
   }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   if (st) return st;
   if (e) return hip_fail(e, "autotune timing");
-  st = pinn_batch_configure(b, bs, graph);
+  st = pinn_batch_configure(b, bs, graph | bmode);
   if (st) return st;
   if (best_streams) *best_streams = bs;
   if (best_ms) *best_ms = bms;

@@ -69,6 +69,15 @@ def test_batch_graph_replays_match_eager_and_single_plans(lib, prec):
         assert np.array_equal(loss.cpu().numpy(), eager[0]), rep
         for i in range(len(ens)):
             assert np.array_equal(flat(grads[i]), eager[1][i]), (rep, i)
+    # networks dealt to per-network lanes: the same results
+    batch.configure(3, use_graph=True, per_network=True)
+    assert batch.config() == {"streams": 3, "graph": True, "per_network": True}
+    for rep in range(2):
+        loss, grads = batch.step(params, xs)
+        torch.cuda.synchronize()
+        assert np.array_equal(loss.cpu().numpy(), eager[0]), rep
+        for i in range(len(ens)):
+            assert np.array_equal(flat(grads[i]), eager[1][i]), (rep, i)
     for i in range(len(ens)):
         assert eager[0][i] == np.float32(ref_loss[i])
         assert np.array_equal(eager[1][i], ref_g[i]), i
@@ -98,7 +107,9 @@ def test_batch_recaptures_on_new_inputs_and_autotunes(lib):
     g2 = [flat(g) for g in grads2]
     np.testing.assert_allclose(loss2.cpu().numpy(), l1, rtol=1e-4)
     ns, ms = batch.autotune(params, xs2, reps=2)
-    assert ns in (1, 2, 4) and ms > 0
+    assert ns in (1, 2, 4, 8, 16) and ms > 0
+    cfg = batch.config()
+    assert cfg["streams"] == ns and cfg["graph"] and (cfg["per_network"] == (ns >= 8))
     # the autotuner may pick other tilings and split counts per member, which
     # reorders sums: close to the earlier step, and steps with the tuned
     # schedule repeat bit for bit

@@ -196,13 +196,18 @@ def test_segment_errors(lib):
 
 def test_adam_trajectory_fp32_against_fp64(lib):
     """1000 full-batch Adam steps on the composite Burgers loss (the paper's
-    training protocol, at a small size): the GPU in FP32 against the oracle's
-    loss, gradient and Adam update in FP64.  Loss curves agree to 1e-3
-    relative at every step; the final parameters to 1e-3 relative L2 (FP32
-    rounding in the gradient, amplified by Adam's normalisation where a
-    gradient component is small, stays well below that over 1000 steps)."""
+    training protocol, at a small size), the GPU in FP32.
+    * At every 50th iterate of the GPU run, the oracle's FP64 loss and
+      gradient at the GPU's own parameters match the GPU's to the FP32 bar
+      (the gradient's error measured against the first gradient's norm).
+    * Against the oracle's own FP64 Adam run from the same start, the loss
+      curves agree to 1e-4 over the first 100 steps.  Later the FP32 run drifts
+      away, as the paper reports for its FP32 Burgers and NS runs (Adam's
+      normalisation amplifies rounding where gradient components are small,
+      most visibly around loss spikes); both runs still train to within 10 %
+      of each other's final loss."""
     ts = pi.burgers_training_set(seed=11, n_pde=300, n_ic=41, n_pairs=40, width=32, hidden=3, bias_std=0.1)
-    steps, lr = 1000, 1e-3
+    steps, lr, every = 1000, 1e-3, 50
     N = ts.x.shape[0]
     plan = lib.PinnPlan(ts.dims, "burgers", N, precision="fp32", coef=ts.coef)
     params = dev(ts.params)
@@ -210,12 +215,29 @@ def test_adam_trajectory_fp32_against_fp64(lib):
     opt = lib.AdamState(params, lr=lr)
     grads = [(torch.empty_like(W), torch.empty_like(b)) for W, b in params]
     gpu_loss = np.zeros(steps)
+    samples = []
     for k in range(steps):
         loss, _ = plan.loss(params, x, ts.segments)
         plan.loss_backward(params, x, ts.segments, out=grads)
+        if k % every == 0:
+            torch.cuda.synchronize()
+            samples.append((k, [(W.cpu().numpy().copy(), b.cpu().numpy().copy()) for W, b in params],
+                            float(loss), flat(grads)))
         opt.step(grads)
         gpu_loss[k] = float(loss)
     torch.cuda.synchronize()
+    g0 = None
+    for k, ps, L, g in samples:
+        _, L_ref, g_ref = oracle.evaluate_segments(ps, ts.x, pi.CHANNELS["burgers"], "burgers", ts.coef,
+                                                   ts.segments)
+        g0 = np.linalg.norm(g_ref) if g0 is None else g0
+        print(f"iterate {k}: loss rel {abs(L - L_ref) / abs(L_ref):.1e}, grad rel {rel(g, g_ref):.1e}, "
+              f"|g| / |g_0| {np.linalg.norm(g_ref) / g0:.2f}")
+        assert abs(L - L_ref) <= 1e-5 * abs(L_ref), (k, L, L_ref)
+        # the gradient is a sum of per-point terms that cancel more and more
+        # as the loss falls; FP32 rounding in those terms stays at the scale of
+        # the first gradient, so the bar is 1e-5 of |g_0|
+        assert np.linalg.norm(g - g_ref) <= 1e-5 * g0, (k, rel(g, g_ref))
     theta = oracle.pack_theta(ts.params).astype(np.float64)
     m = np.zeros_like(theta)
     v = np.zeros_like(theta)
@@ -225,8 +247,10 @@ def test_adam_trajectory_fp32_against_fp64(lib):
         _, L, g = oracle.evaluate_segments(ps, ts.x, pi.CHANNELS["burgers"], "burgers", ts.coef, ts.segments)
         ref_loss[k] = L
         oracle.adam_step(theta, g, m, v, k + 1, lr=lr)
-    assert np.all(np.abs(gpu_loss - ref_loss) <= 1e-3 * np.abs(ref_loss)), \
-        float(np.max(np.abs(gpu_loss - ref_loss) / np.abs(ref_loss)))
-    assert ref_loss[-1] < 0.5 * ref_loss[0]  # the run trains
-    assert rel(flat(params), theta) <= 1e-3
+    drift = np.abs(gpu_loss - ref_loss) / np.abs(ref_loss)
+    print("FP32 GPU vs FP64 oracle Adam run, max relative loss difference per 100 steps:",
+          " ".join(f"{drift[i:i + 100].max():.1e}" for i in range(0, steps, 100)))
+    assert drift[:100].max() <= 1e-4, drift[:100].max()
+    assert ref_loss[-1] < 0.2 * ref_loss[0] and gpu_loss[-1] < 0.2 * gpu_loss[0]  # both runs train
+    assert abs(gpu_loss[-1] - ref_loss[-1]) <= 0.1 * ref_loss[-1]
     plan.close()
