@@ -56,6 +56,17 @@ def _load():
                                               dp, ctypes.c_int, ip, ip, ctypes.c_int64, dp] + seg_args +
                                              [dp, ctypes.c_int])
         lib.orc_eval_segments_cs.restype = ctypes.c_int
+        mod_head = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int]
+        lib.orc_mod_n_theta.argtypes = mod_head + [i64p]
+        lib.orc_mod_n_theta.restype = ctypes.c_int
+        lib.orc_eval_mod.argtypes = (mod_head + [dp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, ip, ip,
+                                                 ctypes.c_int64, dp, dp] + seg_args + [dp, dp, dp, dp,
+                                                                                      ctypes.c_int])
+        lib.orc_eval_mod.restype = ctypes.c_int
+        lib.orc_eval_mod_cs.argtypes = (mod_head + [dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int, dp,
+                                                    ctypes.c_int, ip, ip, ctypes.c_int64, dp, dp] + seg_args +
+                                        [dp, dp, ctypes.c_int])
+        lib.orc_eval_mod_cs.restype = ctypes.c_int
         lib.orc_adam.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_double]
         lib.orc_adam.restype = ctypes.c_int
@@ -175,7 +186,7 @@ def complex_step(params, delta: np.ndarray, x, channels, pde: str = "none",
 
 
 SEG = {"pde": 0, "dirichlet": 1, "periodic": 2}
-DATA = {"zero": 0, "const": 1, "sin": 2}
+DATA = {"zero": 0, "const": 1, "sin": 2, "values": 3}
 
 
 def _segments(segments):
@@ -234,6 +245,77 @@ def complex_step_segments(params, delta, x, channels, pde: str, coef: Sequence[f
     if st != 0:
         raise ValueError(f"orc_eval_segments_cs failed with status {st}")
     return float(out[0])
+
+
+def _mod_shape(params, d: int):
+    """(H, w, d, M, dout) of a modified-MLP parameter list [(W_U, b_U), (W_V, b_V),
+    (W_1, b_1), .., (W_H, b_H), (W_o, b_o)]."""
+    w, de = (int(v) for v in np.asarray(params[0][0]).shape)
+    M = (de - d + 1) // 2
+    if de != d - 1 + 2 * M or M < 1:
+        raise ValueError(f"embedding width {de} does not fit d = {d}")
+    return len(params) - 3, w, d, M, int(np.asarray(params[-1][0]).shape[0])
+
+
+def _no_segments():
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    return [0, ctypes.POINTER(ctypes.c_int)(), i64p(), i64p(), _dp(None), ctypes.POINTER(ctypes.c_int)(),
+            ctypes.POINTER(ctypes.c_int)(), _dp(None)]
+
+
+def evaluate_mod(params, x, channels, pde: str, coef: Sequence[float], period: float, d: int = 2,
+                 segments=None, targets=None, want_grad: bool = True, act: str = "tanh", threads: int = 0):
+    """The modified MLP with periodic embedding (see pinn_oracle.h): jets
+    (d_out, C, N) and, with segments, (seg_loss, loss, grad packed like theta)."""
+    lib = _load()
+    H, w, d, M, dout = _mod_shape(params, d)
+    _, ch_dir, ch_ord, cf = _common(params, channels, coef)
+    theta = pack_theta(params)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    N = xx.shape[0]
+    jets = np.zeros((dout, len(channels), N))
+    if segments:
+        sargs, keep = _segments(segments)
+        tg = np.ascontiguousarray(targets, dtype=np.float64) if targets is not None else None
+        seg_loss, loss = np.zeros(len(segments)), np.zeros(1)
+        grad = np.zeros(theta.size) if want_grad else None
+        st = lib.orc_eval_mod(H, w, d, M, float(period), dout, _dp(theta), ACT[act], PDE[pde], _dp(cf),
+                              len(channels), _ip(ch_dir), _ip(ch_ord), N, _dp(xx), _dp(jets), *sargs, _dp(tg),
+                              _dp(seg_loss), _dp(loss), _dp(grad), int(threads))
+        if st != 0:
+            raise ValueError(f"orc_eval_mod failed with status {st}")
+        return jets, seg_loss, float(loss[0]), grad
+    st = lib.orc_eval_mod(H, w, d, M, float(period), dout, _dp(theta), ACT[act], PDE[pde], _dp(cf), len(channels),
+                          _ip(ch_dir), _ip(ch_ord), N, _dp(xx), _dp(jets), *_no_segments(), _dp(None), _dp(None),
+                          _dp(None), _dp(None), int(threads))
+    if st != 0:
+        raise ValueError(f"orc_eval_mod failed with status {st}")
+    return jets
+
+
+def complex_step_mod(params, delta, x, channels, pde: str, coef: Sequence[float], period: float, d: int = 2,
+                     segments=None, targets=None, act: str = "tanh", h: float = 1e-30, threads: int = 0):
+    """Directional derivatives along delta (complex step): (djets, dloss or None)."""
+    lib = _load()
+    H, w, d, M, dout = _mod_shape(params, d)
+    _, ch_dir, ch_ord, cf = _common(params, channels, coef)
+    theta = pack_theta(params)
+    dl = np.ascontiguousarray(delta, dtype=np.float64)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    N = xx.shape[0]
+    djets = np.zeros((dout, len(channels), N))
+    out = np.zeros(1)
+    if segments:
+        sargs, keep = _segments(segments)
+        tg = np.ascontiguousarray(targets, dtype=np.float64) if targets is not None else None
+    else:
+        sargs, tg = _no_segments(), None
+    st = lib.orc_eval_mod_cs(H, w, d, M, float(period), dout, _dp(theta), _dp(dl), float(h), ACT[act], PDE[pde],
+                             _dp(cf), len(channels), _ip(ch_dir), _ip(ch_ord), N, _dp(xx), _dp(djets), *sargs,
+                             _dp(tg), _dp(out) if segments else _dp(None), int(threads))
+    if st != 0:
+        raise ValueError(f"orc_eval_mod_cs failed with status {st}")
+    return djets, (float(out[0]) if segments else None)
 
 
 def adam_step(theta: np.ndarray, g: np.ndarray, m: np.ndarray, v: np.ndarray, step: int,

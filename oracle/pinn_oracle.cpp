@@ -164,6 +164,97 @@ T faa_di_bruno_dz(int k, int m, const T *q, const T *zz) {
   }
 }
 
+/* The activation jet of one layer (Eq. 2-3 and the recursion): from the
+ * pre-activation jets z (C x n, channel-major) to the activation's jets a. */
+template <class T>
+void act_jet(const ChannelSet &cs, int act, int d, const T *z, T *a, int n) {
+  for (int i = 0; i < n; ++i) {
+    T phi[6];
+    act_derivs(act, z[i], phi);
+    a[i] = phi[0];
+    for (int dir = 0; dir < d; ++dir) {
+      T zz[kMaxOrder + 1];
+      zz[0] = z[i];
+      for (int k = 1; k <= cs.top[dir]; ++k) zz[k] = z[(size_t)cs.at[dir][k] * n + i];
+      for (int k = 1; k <= cs.top[dir]; ++k) a[(size_t)cs.at[dir][k] * n + i] = faa_di_bruno(k, phi, zz);
+    }
+    /* mixed second order (Eq. 3, i != j): a_ij = phi'' z_i z_j + phi' z_ij */
+    for (int m = 0; m < cs.n_mix; ++m) {
+      const T zi = z[(size_t)cs.mix_ci[m] * n + i], zj = z[(size_t)cs.mix_cj[m] * n + i];
+      const T zij = z[(size_t)cs.mix_c[m] * n + i];
+      a[(size_t)cs.mix_c[m] * n + i] = phi[2] * zi * zj + phi[1] * zij;
+    }
+  }
+}
+
+/* Adjoint of act_jet: from the cotangent abar of the activation's jets to the
+ * cotangent zbar of the pre-activation jets (both C x n), at the jets z. */
+void act_jet_adjoint(const ChannelSet &cs, int act, int d, const double *z, const double *abar, double *zbar,
+                     int n) {
+  const int C = cs.C;
+  for (size_t q = 0; q < (size_t)C * n; ++q) zbar[q] = 0.0;
+  for (int j = 0; j < n; ++j) {
+    double phi[6];
+    act_derivs(act, z[j], phi);
+    double z0bar = phi[1] * abar[j]; /* a_0 = phi(z_0) */
+    for (int dir = 0; dir < d; ++dir) {
+      const int K = cs.top[dir];
+      if (K == 0) continue;
+      double zz[kMaxOrder + 1];
+      zz[0] = z[j];
+      for (int k = 1; k <= K; ++k) zz[k] = z[(size_t)cs.at[dir][k] * n + j];
+      for (int k = 1; k <= K; ++k) {
+        const double ab = abar[(size_t)cs.at[dir][k] * n + j];
+        z0bar += faa_di_bruno(k, phi + 1, zz) * ab; /* a_k depends on z_0 through phi^(.) */
+        for (int m = 1; m <= k; ++m) zbar[(size_t)cs.at[dir][m] * n + j] += faa_di_bruno_dz(k, m, phi, zz) * ab;
+      }
+    }
+    /* adjoint of a_ij = phi''(z_0) z_i z_j + phi'(z_0) z_ij */
+    for (int m = 0; m < cs.n_mix; ++m) {
+      const double ab = abar[(size_t)cs.mix_c[m] * n + j];
+      const double zi = z[(size_t)cs.mix_ci[m] * n + j], zj = z[(size_t)cs.mix_cj[m] * n + j];
+      const double zij = z[(size_t)cs.mix_c[m] * n + j];
+      z0bar += (phi[3] * zi * zj + phi[2] * zij) * ab;
+      zbar[(size_t)cs.mix_ci[m] * n + j] += phi[2] * zj * ab;
+      zbar[(size_t)cs.mix_cj[m] * n + j] += phi[2] * zi * ab;
+      zbar[(size_t)cs.mix_c[m] * n + j] += phi[1] * ab;
+    }
+    zbar[j] = z0bar;
+  }
+}
+
+/* The affine map of a layer on every channel (Eq. 1): z_c = W a_c, plus the
+ * bias on the value only.  W is n_out x n_in; a is C x n_in, z is C x n_out. */
+template <class T>
+void affine_jet(int C, const T *W, const T *b, const T *a, T *z, int n_in, int n_out) {
+  for (int c = 0; c < C; ++c)
+    for (int i = 0; i < n_out; ++i) {
+      T s = (c == 0) ? b[i] : T(0);
+      for (int j = 0; j < n_in; ++j) s += W[(size_t)i * n_in + j] * a[(size_t)c * n_in + j];
+      z[(size_t)c * n_out + i] = s;
+    }
+}
+
+/* Its adjoint: dW += zbar_c a_c^T over channels, db += zbar_0, and (abar not
+ * NULL) abar_c = W^T zbar_c. */
+void affine_jet_adjoint(int C, const double *W, const double *a, const double *zbar, double *gW, double *gb,
+                        double *abar, int n_in, int n_out) {
+  for (int c = 0; c < C; ++c)
+    for (int i = 0; i < n_out; ++i) {
+      const double zb = zbar[(size_t)c * n_out + i];
+      if (zb == 0.0) continue;
+      for (int j = 0; j < n_in; ++j) gW[(size_t)i * n_in + j] += zb * a[(size_t)c * n_in + j];
+    }
+  for (int i = 0; i < n_out; ++i) gb[i] += zbar[i];
+  if (!abar) return;
+  for (size_t q = 0; q < (size_t)C * n_in; ++q) abar[q] = 0.0;
+  for (int c = 0; c < C; ++c)
+    for (int i = 0; i < n_out; ++i) {
+      const double zb = zbar[(size_t)c * n_out + i];
+      for (int j = 0; j < n_in; ++j) abar[(size_t)c * n_in + j] += W[(size_t)i * n_in + j] * zb;
+    }
+}
+
 struct NetView {
   int L;
   const int *dims;
@@ -591,6 +682,7 @@ struct Segments {
   const double *weight;
   const int *mask, *data;
   const double *param;
+  const double *targets; /* N x d_out target values of ORC_DATA_VALUES segments, or NULL */
 };
 
 int check_segments(const Segments &S, int64_t N, int C, int d_out, int n_res) {
@@ -604,7 +696,8 @@ int check_segments(const Segments &S, int64_t N, int C, int d_out, int n_res) {
         if (n_res == 0) return -1;
         break;
       case ORC_SEG_DIRICHLET:
-        if (S.data[s] < ORC_DATA_ZERO || S.data[s] > ORC_DATA_SIN) return -1;
+        if (S.data[s] < ORC_DATA_ZERO || S.data[s] > ORC_DATA_VALUES) return -1;
+        if (S.data[s] == ORC_DATA_VALUES && !S.targets) return -1;
         for (int q = 0; q < d_out * C; ++q)
           if ((S.mask[s] >> q & 1) && q % C != 0) return -1; /* values only */
         if (S.mask[s] == 0 || (S.mask[s] >> (d_out * C)) != 0) return -1;
@@ -622,12 +715,14 @@ int check_segments(const Segments &S, int64_t N, int C, int d_out, int n_res) {
   return 0;
 }
 
-/* Boundary or initial data g_o(x) of a Dirichlet segment. */
-double seg_data_value(int data, const double *param, int o, const double *xp) {
+/* Boundary or initial data g_o(x) of a Dirichlet segment at point n. */
+double seg_data_value(const Segments &S, int s, int o, int64_t n, int d_out, const double *xp) {
   const double pi = 3.14159265358979323846;
-  switch (data) {
+  const double *param = S.param + 4 * s;
+  switch (S.data[s]) {
     case ORC_DATA_CONST: return param[o];
     case ORC_DATA_SIN: return param[0] * std::sin(param[1] * pi * xp[0]);
+    case ORC_DATA_VALUES: return S.targets[n * d_out + o];
     default: return 0.0;
   }
 }
@@ -663,7 +758,7 @@ void segment_loss(const Segments &S, int pde_kind, const double *coef, const Pde
       for (int64_t n = b; n < b + cnt; ++n)
         for (int o = 0; o < d_out; ++o) {
           if (!(S.mask[s] >> (o * C) & 1)) continue;
-          const T r = U(n, o, 0) - seg_data_value(S.data[s], S.param + 4 * s, o, x + n * d);
+          const T r = U(n, o, 0) - seg_data_value(S, s, o, n, d_out, x + n * d);
           acc += r * r;
           if (ubar) (*ubar)[n][(size_t)0 * d_out + o] += 2.0 * w * std::real(r) / (double)cnt;
         }
@@ -749,6 +844,280 @@ int eval_segments(int n_layers, const int *dims, const T *theta, int act, int pd
   return 0;
 }
 
+/* ---- Modified MLP with a periodic input embedding (the KS network of
+ * Sec. 3.1.1, an architecture the paper takes from earlier PINN training
+ * work; the exact form used here is stated in pinn_oracle.h). */
+struct ModView {
+  int H, w, d, M, dout, de;
+  double omega;
+  /* layers: 0 = U encoder, 1 = V encoder, 2 = first hidden layer, 3 .. H+1 =
+     hidden layers 2 .. H, H+2 = output layer */
+  std::vector<int> n_in, n_out;
+  std::vector<int64_t> w_off, b_off;
+  int64_t n_theta;
+};
+
+int make_mod_view(int H, int w, int d, int M, double period, int dout, ModView *v) {
+  if (H < 1 || w < 1 || d < 1 || d > kMaxDir || M < 1 || !(period > 0.0) || dout < 1) return -1;
+  v->H = H;
+  v->w = w;
+  v->d = d;
+  v->M = M;
+  v->dout = dout;
+  v->de = d - 1 + 2 * M;
+  v->omega = 2.0 * 3.14159265358979323846 / period;
+  v->n_in = {v->de, v->de, v->de};
+  v->n_out = {w, w, w};
+  for (int l = 2; l <= H; ++l) {
+    v->n_in.push_back(w);
+    v->n_out.push_back(w);
+  }
+  v->n_in.push_back(w);
+  v->n_out.push_back(dout);
+  int64_t off = 0;
+  v->w_off.clear();
+  v->b_off.clear();
+  for (size_t l = 0; l < v->n_in.size(); ++l) {
+    v->w_off.push_back(off);
+    off += (int64_t)v->n_out[l] * v->n_in[l];
+    v->b_off.push_back(off);
+    off += v->n_out[l];
+  }
+  v->n_theta = off;
+  return 0;
+}
+
+/* Jets of the embedding e(x) (C x de).  The inputs x_1 .. x_{d-1} pass
+ * through (a first derivative along their own direction is 1, every other
+ * derivative 0).  The harmonics depend on x_0 only:
+ *   d^k/dx_0^k cos(m omega x_0) = (m omega)^k cos(m omega x_0 + k pi / 2),
+ *   d^k/dx_0^k sin(m omega x_0) = (m omega)^k sin(m omega x_0 + k pi / 2);
+ * mixed derivatives of the embedding vanish. */
+void embed_jet(const ModView &v, const ChannelSet &cs, const double *xp, double *e) {
+  const int de = v.de, C = cs.C;
+  const double half_pi = 0.5 * 3.14159265358979323846;
+  for (size_t q = 0; q < (size_t)C * de; ++q) e[q] = 0.0;
+  for (int c = 0; c < C; ++c) {
+    const int dir = cs.dir[c], k = cs.ord[c];
+    if (c > 0 && dir < 0) continue; /* mixed: zero */
+    for (int j = 1; j < v.d; ++j) {
+      if (c == 0) e[j - 1] = xp[j];
+      else if (dir == j && k == 1) e[(size_t)c * de + j - 1] = 1.0;
+    }
+    if (c > 0 && dir != 0) continue; /* the harmonics do not depend on x_1.. */
+    for (int m = 1; m <= v.M; ++m) {
+      const double f = m * v.omega, ph = f * xp[0] + k * half_pi;
+      const double amp = std::pow(f, (double)k);
+      e[(size_t)c * de + v.d - 1 + 2 * (m - 1)] = amp * std::cos(ph);
+      e[(size_t)c * de + v.d - 1 + 2 * (m - 1) + 1] = amp * std::sin(ph);
+    }
+  }
+}
+
+double binom(int k, int j) {
+  double r = 1.0;
+  for (int i = 1; i <= j; ++i) r = r * (k - j + i) / i;
+  return r;
+}
+
+/* Jets of the elementwise product p q (C x n each): the Leibniz rule along
+ * each direction, (pq)_k = sum_j binom(k, j) p_j q_{k-j}, and for a mixed
+ * channel (pq)_ij = p_ij q + p_i q_j + p_j q_i + p q_ij. */
+template <class T>
+void prod_jet(const ChannelSet &cs, int d, const T *p, const T *q, T *out, int n) {
+  for (int i = 0; i < n; ++i) {
+    auto P = [&](int c) { return p[(size_t)c * n + i]; };
+    auto Q = [&](int c) { return q[(size_t)c * n + i]; };
+    out[i] = P(0) * Q(0);
+    for (int dir = 0; dir < d; ++dir)
+      for (int k = 1; k <= cs.top[dir]; ++k) {
+        T s = T(0);
+        for (int j = 0; j <= k; ++j) s += binom(k, j) * P(cs.at[dir][j]) * Q(cs.at[dir][k - j]);
+        out[(size_t)cs.at[dir][k] * n + i] = s;
+      }
+    for (int m = 0; m < cs.n_mix; ++m) {
+      const int cij = cs.mix_c[m], ci = cs.mix_ci[m], cj = cs.mix_cj[m];
+      out[(size_t)cij * n + i] = P(cij) * Q(0) + P(ci) * Q(cj) + P(cj) * Q(ci) + P(0) * Q(cij);
+    }
+  }
+}
+
+/* Adjoint of prod_jet: pbar += d<obar, pq>/dp, qbar += d<obar, pq>/dq. */
+void prod_jet_adjoint(const ChannelSet &cs, int d, const double *p, const double *q, const double *obar,
+                      double *pbar, double *qbar, int n) {
+  for (int i = 0; i < n; ++i) {
+    auto at = [&](int c) { return (size_t)c * n + i; };
+    pbar[at(0)] += obar[at(0)] * q[at(0)];
+    qbar[at(0)] += obar[at(0)] * p[at(0)];
+    for (int dir = 0; dir < d; ++dir)
+      for (int k = 1; k <= cs.top[dir]; ++k) {
+        const double ob = obar[at(cs.at[dir][k])];
+        for (int j = 0; j <= k; ++j) {
+          const int cp = cs.at[dir][j], cq = cs.at[dir][k - j];
+          pbar[at(cp)] += binom(k, j) * q[at(cq)] * ob;
+          qbar[at(cq)] += binom(k, j) * p[at(cp)] * ob;
+        }
+      }
+    for (int m = 0; m < cs.n_mix; ++m) {
+      const int cij = cs.mix_c[m], ci = cs.mix_ci[m], cj = cs.mix_cj[m];
+      const double ob = obar[at(cij)];
+      pbar[at(cij)] += ob * q[at(0)];
+      qbar[at(0)] += ob * p[at(cij)];
+      pbar[at(ci)] += ob * q[at(cj)];
+      qbar[at(cj)] += ob * p[at(ci)];
+      pbar[at(cj)] += ob * q[at(ci)];
+      qbar[at(ci)] += ob * p[at(cj)];
+      pbar[at(0)] += ob * q[at(cij)];
+      qbar[at(cij)] += ob * p[at(0)];
+    }
+  }
+}
+
+/* Per-point state of the modified MLP: embedding e; encoder pre-activations
+ * and outputs; per hidden layer l the pre-activation z[l] and output h[l]
+ * (l = 1: phi(W_1 e + b_1); l >= 2: zZ[l] -> Z[l] -> h[l] = U + Z (V - U));
+ * D = V - U; the output jets out. */
+template <class T>
+struct ModWork {
+  std::vector<T> e, zU, U, zV, V, D, out;
+  std::vector<std::vector<T>> z, Z, h;
+  void init(const ModView &v, int C) {
+    e.assign((size_t)C * v.de, T(0));
+    zU.assign((size_t)C * v.w, T(0));
+    U = zU;
+    zV = zU;
+    V = zU;
+    D = zU;
+    out.assign((size_t)C * v.dout, T(0));
+    z.assign(v.H + 1, zU);
+    Z.assign(v.H + 1, zU);
+    h.assign(v.H + 1, zU);
+  }
+};
+
+template <class T>
+void forward_point_mod(const ModView &v, const T *theta, const ChannelSet &cs, int act, const double *xp,
+                       ModWork<T> &wk) {
+  const int C = cs.C, w = v.w, de = v.de;
+  std::vector<double> e((size_t)C * de);
+  embed_jet(v, cs, xp, e.data());
+  for (size_t q = 0; q < e.size(); ++q) wk.e[q] = T(e[q]);
+  auto W = [&](int l) { return theta + v.w_off[l]; };
+  auto B = [&](int l) { return theta + v.b_off[l]; };
+  affine_jet(C, W(0), B(0), wk.e.data(), wk.zU.data(), de, w);
+  act_jet(cs, act, v.d, wk.zU.data(), wk.U.data(), w);
+  affine_jet(C, W(1), B(1), wk.e.data(), wk.zV.data(), de, w);
+  act_jet(cs, act, v.d, wk.zV.data(), wk.V.data(), w);
+  for (size_t q = 0; q < wk.D.size(); ++q) wk.D[q] = wk.V[q] - wk.U[q];
+  affine_jet(C, W(2), B(2), wk.e.data(), wk.z[1].data(), de, w);
+  act_jet(cs, act, v.d, wk.z[1].data(), wk.h[1].data(), w);
+  std::vector<T> P((size_t)C * w);
+  for (int l = 2; l <= v.H; ++l) {
+    affine_jet(C, W(l + 1), B(l + 1), wk.h[l - 1].data(), wk.z[l].data(), w, w);
+    act_jet(cs, act, v.d, wk.z[l].data(), wk.Z[l].data(), w);
+    prod_jet(cs, v.d, wk.Z[l].data(), wk.D.data(), P.data(), w); /* Z (V - U) */
+    for (size_t q = 0; q < P.size(); ++q) wk.h[l][q] = wk.U[q] + P[q];
+  }
+  affine_jet(C, W(v.H + 2), B(v.H + 2), wk.h[v.H].data(), wk.out.data(), w, v.dout);
+}
+
+/* Reverse sweep for one point from the output jets' cotangent ubar (C x dout). */
+void backward_point_mod(const ModView &v, const double *theta, const ChannelSet &cs, int act, ModWork<double> &wk,
+                        const double *ubar, double *g) {
+  const int C = cs.C, w = v.w, de = v.de;
+  const size_t S = (size_t)C * w;
+  auto W = [&](int l) { return theta + v.w_off[l]; };
+  auto gW = [&](int l) { return g + v.w_off[l]; };
+  auto gB = [&](int l) { return g + v.b_off[l]; };
+  std::vector<double> hbar(S), hprev(S), Ubar(S, 0.0), Vbar(S, 0.0), Zbar(S), Dbar(S), zbar(S);
+  affine_jet_adjoint(C, W(v.H + 2), wk.h[v.H].data(), ubar, gW(v.H + 2), gB(v.H + 2), hbar.data(), w, v.dout);
+  for (int l = v.H; l >= 2; --l) {
+    /* h_l = U + Z_l D */
+    for (size_t q = 0; q < S; ++q) {
+      Ubar[q] += hbar[q];
+      Zbar[q] = 0.0;
+      Dbar[q] = 0.0;
+    }
+    prod_jet_adjoint(cs, v.d, wk.Z[l].data(), wk.D.data(), hbar.data(), Zbar.data(), Dbar.data(), w);
+    for (size_t q = 0; q < S; ++q) { /* D = V - U */
+      Ubar[q] -= Dbar[q];
+      Vbar[q] += Dbar[q];
+    }
+    act_jet_adjoint(cs, act, v.d, wk.z[l].data(), Zbar.data(), zbar.data(), w);
+    affine_jet_adjoint(C, W(l + 1), wk.h[l - 1].data(), zbar.data(), gW(l + 1), gB(l + 1), hprev.data(), w, w);
+    hbar.swap(hprev);
+  }
+  act_jet_adjoint(cs, act, v.d, wk.z[1].data(), hbar.data(), zbar.data(), w);
+  affine_jet_adjoint(C, W(2), wk.e.data(), zbar.data(), gW(2), gB(2), nullptr, de, w);
+  act_jet_adjoint(cs, act, v.d, wk.zU.data(), Ubar.data(), zbar.data(), w);
+  affine_jet_adjoint(C, W(0), wk.e.data(), zbar.data(), gW(0), gB(0), nullptr, de, w);
+  act_jet_adjoint(cs, act, v.d, wk.zV.data(), Vbar.data(), zbar.data(), w);
+  affine_jet_adjoint(C, W(1), wk.e.data(), zbar.data(), gW(1), gB(1), nullptr, de, w);
+}
+
+/* Jets at every point and, with segments, the composite loss and its gradient
+ * (the structure of eval_segments: all points evaluated together, then split). */
+template <class T>
+int eval_mod(const ModView &v, const T *theta, int act, int pde_kind, const double *coef, int n_ch,
+             const int *ch_dir, const int *ch_ord, int64_t N, const double *x, const Segments *S, T *jets,
+             T *seg_loss, T *loss, double *grad, int n_threads) {
+  ChannelSet cs;
+  if (build_channels(n_ch, ch_dir, ch_ord, v.d, &cs)) return -1;
+  PdeChannels pc;
+  const int n_res = orc_n_res(pde_kind);
+  if (n_res > 0) {
+    const int st = pde_channels(pde_kind, v.d, v.dout, cs, &pc);
+    if (st) return st;
+  }
+  if (!theta || N < 1 || !x) return -1;
+  const int C = cs.C, d = v.d, d_out = v.dout;
+  if (S && check_segments(*S, N, C, d_out, n_res)) return -1;
+  std::vector<std::vector<T>> u((size_t)N);
+#pragma omp parallel num_threads(n_threads_or_default(n_threads))
+  {
+    ModWork<T> wk;
+    wk.init(v, C);
+#pragma omp for schedule(dynamic, 64)
+    for (int64_t n = 0; n < N; ++n) {
+      forward_point_mod(v, theta, cs, act, x + n * d, wk);
+      u[n] = wk.out;
+    }
+  }
+  if (jets)
+    for (int64_t n = 0; n < N; ++n)
+      for (int o = 0; o < d_out; ++o)
+        for (int c = 0; c < C; ++c) jets[((size_t)o * C + c) * N + n] = u[n][(size_t)c * d_out + o];
+  if (!S) return 0;
+  std::vector<std::vector<double>> ubar;
+  if (grad) ubar.assign((size_t)N, std::vector<double>((size_t)C * d_out, 0.0));
+  segment_loss<T>(*S, pde_kind, coef, pc, C, d_out, n_res, x, d, u, seg_loss, loss, grad ? &ubar : nullptr);
+  if constexpr (!std::is_same<T, double>::value) return 0; /* complex step: the loss only */
+  if (!grad) return 0;
+  const int64_t n_chunks = (N + kChunk - 1) / kChunk;
+  std::vector<std::vector<double>> chunk_grad((size_t)n_chunks);
+#pragma omp parallel num_threads(n_threads_or_default(n_threads))
+  {
+    ModWork<double> wk;
+    wk.init(v, C);
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t ch = 0; ch < n_chunks; ++ch) {
+      chunk_grad[ch].assign(v.n_theta, 0.0);
+      const int64_t n_end = std::min<int64_t>(N, (ch + 1) * kChunk);
+      for (int64_t n = ch * kChunk; n < n_end; ++n) {
+        bool any = false;
+        for (double q : ubar[n]) any = any || q != 0.0;
+        if (!any) continue;
+        forward_point_mod(v, (const double *)theta, cs, act, x + n * d, wk);
+        backward_point_mod(v, (const double *)theta, cs, act, wk, ubar[n].data(), chunk_grad[ch].data());
+      }
+    }
+  }
+  for (int64_t q = 0; q < v.n_theta; ++q) grad[q] = 0.0;
+  for (int64_t ch = 0; ch < n_chunks; ++ch)
+    for (int64_t q = 0; q < v.n_theta; ++q) grad[q] += chunk_grad[ch][q];
+  return 0;
+}
+
 } /* namespace */
 
 extern "C" int orc_eval_segments(int n_layers, const int *dims, const double *theta, int act, int pde_kind,
@@ -757,7 +1126,7 @@ extern "C" int orc_eval_segments(int n_layers, const int *dims, const double *th
                                  const int64_t *seg_count, const double *seg_weight, const int *seg_mask,
                                  const int *seg_data, const double *seg_param, double *seg_loss, double *loss,
                                  double *grad, int n_threads) {
-  const Segments S{n_seg, seg_type, seg_begin, seg_count, seg_weight, seg_mask, seg_data, seg_param};
+  const Segments S{n_seg, seg_type, seg_begin, seg_count, seg_weight, seg_mask, seg_data, seg_param, nullptr};
   return eval_segments<double>(n_layers, dims, theta, act, pde_kind, coef, n_ch, ch_dir, ch_ord, N, x, S,
                                seg_loss, loss, grad, n_threads);
 }
@@ -769,7 +1138,7 @@ extern "C" int orc_eval_segments_cs(int n_layers, const int *dims, const double 
                                     const double *seg_weight, const int *seg_mask, const int *seg_data,
                                     const double *seg_param, double *dloss, int n_threads) {
   if (!theta || !delta || !(h > 0.0) || !dloss || n_layers < 1 || !dims) return -1;
-  const Segments S{n_seg, seg_type, seg_begin, seg_count, seg_weight, seg_mask, seg_data, seg_param};
+  const Segments S{n_seg, seg_type, seg_begin, seg_count, seg_weight, seg_mask, seg_data, seg_param, nullptr};
   const NetView nv = make_view(n_layers, dims);
   std::vector<cplx> th((size_t)nv.n_theta);
   for (int64_t q = 0; q < nv.n_theta; ++q) th[q] = cplx(theta[q], h * delta[q]);
@@ -845,5 +1214,52 @@ extern "C" int orc_adam(int64_t n, double *theta, const double *g, double *m, do
     const double vhat = v[i] / c2;
     theta[i] -= lr * mhat / (std::sqrt(vhat) + eps);
   }
+  return 0;
+}
+
+extern "C" int orc_mod_n_theta(int H, int w, int d, int M, double period, int dout, int64_t *n_theta) {
+  ModView v;
+  if (!n_theta || make_mod_view(H, w, d, M, period, dout, &v)) return -1;
+  *n_theta = v.n_theta;
+  return 0;
+}
+
+extern "C" int orc_eval_mod(int H, int w, int d, int M, double period, int dout, const double *theta, int act,
+                            int pde_kind, const double *coef, int n_ch, const int *ch_dir, const int *ch_ord,
+                            int64_t N, const double *x, double *jets, int n_seg, const int *seg_type,
+                            const int64_t *seg_begin, const int64_t *seg_count, const double *seg_weight,
+                            const int *seg_mask, const int *seg_data, const double *seg_param,
+                            const double *targets, double *seg_loss, double *loss, double *grad, int n_threads) {
+  ModView v;
+  if (make_mod_view(H, w, d, M, period, dout, &v)) return -1;
+  const Segments S{n_seg, seg_type, seg_begin, seg_count, seg_weight, seg_mask, seg_data, seg_param, targets};
+  if (n_seg == 0 && (seg_loss || loss || grad)) return -1;
+  return eval_mod<double>(v, theta, act, pde_kind, coef, n_ch, ch_dir, ch_ord, N, x, n_seg ? &S : nullptr, jets,
+                          seg_loss, loss, grad, n_threads);
+}
+
+extern "C" int orc_eval_mod_cs(int H, int w, int d, int M, double period, int dout, const double *theta,
+                               const double *delta, double h, int act, int pde_kind, const double *coef, int n_ch,
+                               const int *ch_dir, const int *ch_ord, int64_t N, const double *x, double *djets,
+                               int n_seg, const int *seg_type, const int64_t *seg_begin, const int64_t *seg_count,
+                               const double *seg_weight, const int *seg_mask, const int *seg_data,
+                               const double *seg_param, const double *targets, double *dloss, int n_threads) {
+  ModView v;
+  if (make_mod_view(H, w, d, M, period, dout, &v) || !theta || !delta || !(h > 0.0)) return -1;
+  if (n_seg == 0 && dloss) return -1;
+  const Segments S{n_seg, seg_type, seg_begin, seg_count, seg_weight, seg_mask, seg_data, seg_param, targets};
+  std::vector<cplx> th((size_t)v.n_theta);
+  for (int64_t q = 0; q < v.n_theta; ++q) th[q] = cplx(theta[q], h * delta[q]);
+  ChannelSet cs;
+  if (build_channels(n_ch, ch_dir, ch_ord, d, &cs)) return -1;
+  std::vector<cplx> jc(djets ? (size_t)dout * cs.C * N : 0);
+  cplx l(0.0, 0.0);
+  const int st = eval_mod<cplx>(v, th.data(), act, pde_kind, coef, n_ch, ch_dir, ch_ord, N, x,
+                                n_seg ? &S : nullptr, djets ? jc.data() : nullptr, nullptr, dloss ? &l : nullptr,
+                                nullptr, n_threads);
+  if (st) return st;
+  if (djets)
+    for (size_t q = 0; q < jc.size(); ++q) djets[q] = jc[q].imag() / h;
+  if (dloss) *dloss = l.imag() / h;
   return 0;
 }

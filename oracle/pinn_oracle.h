@@ -99,7 +99,8 @@ int orc_eval_cs(int n_layers, const int *dims, const double *theta,
  * Segments must not overlap.  grad (may be NULL) receives d loss / d theta.
  * seg_loss has n_seg entries; loss and seg_loss may be NULL. */
 enum { ORC_SEG_PDE = 0, ORC_SEG_DIRICHLET = 1, ORC_SEG_PERIODIC = 2 };
-enum { ORC_DATA_ZERO = 0, ORC_DATA_CONST = 1, ORC_DATA_SIN = 2 };
+/* ORC_DATA_VALUES (modified-MLP evaluation only): g_o(x_n) = targets[n * d_out + o]. */
+enum { ORC_DATA_ZERO = 0, ORC_DATA_CONST = 1, ORC_DATA_SIN = 2, ORC_DATA_VALUES = 3 };
 int orc_eval_segments(int n_layers, const int *dims, const double *theta, int act, int pde_kind,
                       const double *coef, int n_ch, const int *ch_dir, const int *ch_ord, int64_t N,
                       const double *x, int n_seg, const int *seg_type, const int64_t *seg_begin,
@@ -114,6 +115,38 @@ int orc_eval_segments_cs(int n_layers, const int *dims, const double *theta, con
                          const int64_t *seg_begin, const int64_t *seg_count, const double *seg_weight,
                          const int *seg_mask, const int *seg_data, const double *seg_param, double *dloss,
                          int n_threads);
+
+/* Modified MLP with a periodic input embedding: the network of the paper's
+ * Kuramoto-Sivashinsky case (Sec. 3.1.1), which the paper takes from earlier
+ * PINN work without writing it out; the form evaluated here:
+ *   embedding (periodic in x_0 with period `period`, omega = 2 pi / period,
+ *   M harmonics; the other inputs pass through):
+ *     e(x) = (x_1, .., x_{d-1}, cos(omega x_0), sin(omega x_0), ..,
+ *             cos(M omega x_0), sin(M omega x_0)),   de = d - 1 + 2 M
+ *   encoders  U = phi(W_U e + b_U),  V = phi(W_V e + b_V)
+ *   layers    h_1 = phi(W_1 e + b_1);
+ *             h_l = U + phi(W_l h_{l-1} + b_l) (V - U),  l = 2 .. H  (elementwise)
+ *   output    u = W_o h_H + b_o
+ * theta packs (W_U, b_U), (W_V, b_V), (W_1, b_1), .., (W_H, b_H), (W_o, b_o),
+ * each W shaped (out, in): W_U, W_V, W_1 are w x de, W_2..W_H w x w, W_o dout x w.
+ * The channel set is over the raw inputs (directions 0..d-1).  Jets: the
+ * embedding's in closed form, products of jets by the Leibniz rule.
+ * jets (dout x C x N) may be NULL.  With n_seg > 0 the segments define the
+ * composite loss as in orc_eval_segments (plus ORC_DATA_VALUES with `targets`,
+ * N x dout); with n_seg = 0, seg_loss, loss and grad must be NULL. */
+int orc_mod_n_theta(int H, int w, int d, int M, double period, int dout, int64_t *n_theta);
+int orc_eval_mod(int H, int w, int d, int M, double period, int dout, const double *theta, int act, int pde_kind,
+                 const double *coef, int n_ch, const int *ch_dir, const int *ch_ord, int64_t N, const double *x,
+                 double *jets, int n_seg, const int *seg_type, const int64_t *seg_begin, const int64_t *seg_count,
+                 const double *seg_weight, const int *seg_mask, const int *seg_data, const double *seg_param,
+                 const double *targets, double *seg_loss, double *loss, double *grad, int n_threads);
+/* Complex-step directional derivative along delta of the jets and the loss. */
+int orc_eval_mod_cs(int H, int w, int d, int M, double period, int dout, const double *theta, const double *delta,
+                    double h, int act, int pde_kind, const double *coef, int n_ch, const int *ch_dir,
+                    const int *ch_ord, int64_t N, const double *x, double *djets, int n_seg, const int *seg_type,
+                    const int64_t *seg_begin, const int64_t *seg_count, const double *seg_weight,
+                    const int *seg_mask, const int *seg_data, const double *seg_param, const double *targets,
+                    double *dloss, int n_threads);
 
 /* One Adam step (Kingma & Ba, Algorithm 1; the optimizer of the paper's
  * training runs, Sec. 3.1) on n parameters, in place:

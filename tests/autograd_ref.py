@@ -28,10 +28,34 @@ def torch_params(params, requires_grad=True):
     return out
 
 
-def nested_jets(params64, x, channels, act=torch.tanh):
-    """Returns (jets dict {(o, c): tensor (N,)}, X) with a graph kept for backward."""
+def modified_mlp(params64, X, period, act=torch.tanh):
+    """The modified MLP with periodic embedding in x_0 (the form documented in
+    the oracle's header), written with plain torch operations."""
+    (WU, bU), (WV, bV) = params64[0], params64[1]
+    de = WU.shape[1]
+    d = X.shape[1]
+    M = (de - d + 1) // 2
+    om = 2.0 * math.pi / period
+    feats = [X[:, j:j + 1] for j in range(1, d)]
+    for m in range(1, M + 1):
+        feats += [torch.cos(m * om * X[:, 0:1]), torch.sin(m * om * X[:, 0:1])]
+    E = torch.cat(feats, dim=1)
+    U = act(E @ WU.T + bU)
+    V = act(E @ WV.T + bV)
+    W1, b1 = params64[2]
+    h = act(E @ W1.T + b1)
+    for W, b in params64[3:-1]:
+        Z = act(h @ W.T + b)
+        h = (1.0 - Z) * U + Z * V
+    Wo, bo = params64[-1]
+    return h @ Wo.T + bo
+
+
+def nested_jets(params64, x, channels, act=torch.tanh, net=None):
+    """Returns (jets dict {(o, c): tensor (N,)}, X) with a graph kept for backward.
+    net(params64, X) evaluates the network (default: the plain MLP)."""
     X = torch.tensor(np.asarray(x, dtype=np.float64), requires_grad=True)
-    U = mlp(params64, X, act)
+    U = mlp(params64, X, act) if net is None else net(params64, X)
     jets = {}
     for o in range(U.shape[1]):
         u = U[:, o]
@@ -98,13 +122,13 @@ def evaluate(params, x, channels, pde, coef, act=torch.tanh):
     return J, R, float(loss.detach()), G
 
 
-def evaluate_segments(params, x, channels, pde, coef, segments, act=torch.tanh):
+def evaluate_segments(params, x, channels, pde, coef, segments, act=torch.tanh, net=None, targets=None):
     """The composite loss of Sec. 3.1.1 written with nested autograd in FP64:
     all points through the network at once, outputs split by segment; each
     segment's mean of squared terms times its weight.  Returns (seg_losses,
     loss, grad packed W, b per layer)."""
     p64 = torch_params(params)
-    jets, X = nested_jets(p64, x, channels, act)
+    jets, X = nested_jets(p64, x, channels, act, net)
     idx = {ch: c for c, ch in enumerate(channels)}
     d_out = params[-1][0].shape[0]
     C = len(channels)
@@ -126,6 +150,8 @@ def evaluate_segments(params, x, channels, pde, coef, segments, act=torch.tanh):
                     g = torch.full_like(xs, par[o])
                 elif s.get("data", "zero") == "sin":
                     g = par[0] * torch.sin(par[1] * math.pi * xs)
+                elif s.get("data", "zero") == "values":
+                    g = torch.tensor(np.asarray(targets, dtype=np.float64)[b:b + n, o])
                 else:
                     g = torch.zeros_like(xs)
                 r = jets[(o, idx[(0, 0)])][sl] - g
@@ -147,4 +173,5 @@ def evaluate_segments(params, x, channels, pde, coef, segments, act=torch.tanh):
     grads = torch.autograd.grad(loss, leaves, allow_unused=True)
     grads = [torch.zeros_like(t) if g is None else g for g, t in zip(grads, leaves)]
     G = np.concatenate([g.detach().numpy().reshape(-1) for g in grads])
-    return np.array([float(t.detach()) for t in terms]), float(loss.detach()), G
+    J = np.stack([np.stack([jets[(o, c)].detach().numpy() for c in range(C)]) for o in range(d_out)])
+    return np.array([float(t.detach()) for t in terms]), float(loss.detach()), G, J

@@ -544,7 +544,7 @@ def test_composite_loss_against_nested_autograd(kind):
     loss written with nested torch.autograd in FP64."""
     params, x, ch, coef, segs = _segment_problem(kind, 71)
     sl, L, g = oracle.evaluate_segments(params, x, ch, kind, coef, segs)
-    sl_ref, L_ref, g_ref = autograd_ref.evaluate_segments(params, x, ch, kind, coef, segs)
+    sl_ref, L_ref, g_ref, _ = autograd_ref.evaluate_segments(params, x, ch, kind, coef, segs)
     assert np.allclose(sl, sl_ref, rtol=1e-12, atol=0)
     assert abs(L - L_ref) <= 1e-12 * abs(L_ref)
     assert rel(g, g_ref) < 1e-11
@@ -629,7 +629,7 @@ def test_fp64_adam_trajectories_coincide():
                                                ts.segments)
         oracle.adam_step(theta, g, m, v, k + 1, lr=lr)
         cur = [(W.detach().numpy(), b.detach().numpy()) for W, b in p64]
-        _, lb[k], G = autograd_ref.evaluate_segments(cur, ts.x, ch, "burgers", ts.coef, ts.segments)
+        _, lb[k], G, _ = autograd_ref.evaluate_segments(cur, ts.x, ch, "burgers", ts.coef, ts.segments)
         off = 0
         for t in leaves:
             t.grad = torch.tensor(G[off:off + t.numel()].reshape(t.shape))
