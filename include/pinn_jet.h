@@ -203,7 +203,10 @@ pinn_status pinn_jet_backward_cot(pinn_plan plan, const pinn_net *net, const pin
  *   PINN_SEG_DIRICHLET  a data term u_o - g_o(x) at each point, for every
  *                       output o whose value bit (o * C) is set in mask; g_o:
  *                       PINN_DATA_ZERO 0, PINN_DATA_CONST param[o],
- *                       PINN_DATA_SIN param[0] sin(param[1] pi x_0)
+ *                       PINN_DATA_SIN param[0] sin(param[1] pi x_0),
+ *                       PINN_DATA_VALUES values[k * d_out + o] at the
+ *                       segment's k-th point (device array of count * d_out
+ *                       floats: sampled initial data)
  *                       (initial conditions, no-slip walls, a moving lid)
  *   PINN_SEG_PERIODIC   consecutive point pairs (begin + 2k, begin + 2k + 1):
  *                       u_oc(first) - u_oc(second) for every output o and
@@ -215,7 +218,7 @@ pinn_status pinn_jet_backward_cot(pinn_plan plan, const pinn_net *net, const pin
  * [0, N) and do not overlap; points outside every segment are evaluated but
  * do not enter the loss.  1 <= n_segments <= PINN_MAX_SEGMENTS. */
 enum { PINN_SEG_PDE = 0, PINN_SEG_DIRICHLET = 1, PINN_SEG_PERIODIC = 2 };
-enum { PINN_DATA_ZERO = 0, PINN_DATA_CONST = 1, PINN_DATA_SIN = 2 };
+enum { PINN_DATA_ZERO = 0, PINN_DATA_CONST = 1, PINN_DATA_SIN = 2, PINN_DATA_VALUES = 3 };
 #define PINN_MAX_SEGMENTS 8
 typedef struct {
   int32_t type;      /* PINN_SEG_* */
@@ -224,6 +227,7 @@ typedef struct {
   double weight;     /* >= 0 */
   uint32_t mask;
   double param[4];
+  const float *values; /* PINN_DATA_VALUES only (else ignored); read at every call */
 } pinn_segment;
 
 /* The composite loss: the forward pass over all N points, then each segment's
@@ -241,6 +245,35 @@ pinn_status pinn_jet_loss(pinn_plan plan, const pinn_net *net, const pinn_pde *p
 pinn_status pinn_jet_loss_backward(pinn_plan plan, const pinn_net *net, const pinn_pde *pde,
                                    const pinn_segment *segments, int32_t n_segments, const float *x, int64_t N,
                                    float *const *dW, float *const *db, void *stream);
+
+/* Modified MLP with a periodic input embedding: the network of the paper's
+ * Kuramoto-Sivashinsky case (Sec. 3.1.1), where periodicity in x is imposed
+ * by the input embedding; the paper adopts the architecture from earlier PINN
+ * training work without writing it out.  The form computed:
+ *   e(x) = (x_1 .. x_{d-1}, cos(w0 x_0), sin(w0 x_0), .., cos(M w0 x_0),
+ *           sin(M w0 x_0)),  w0 = 2 pi / period,  de = d - 1 + 2 M
+ *   U = tanh(W_U e + b_U),  V = tanh(W_V e + b_V),  h_1 = tanh(W_1 e + b_1)
+ *   h_l = U + tanh(W_l h_{l-1} + b_l) (V - U)   elementwise, l = 2 .. hidden
+ *   u = W_o h_hidden + b_o
+ * pinn_plan_create_modified: FP32 operands only (PINN_ERR_UNSUPPORTED for
+ * other precisions and for flags other than 0); kinds PINN_KS_1D and
+ * PINN_BURGERS_1D (input x_0 periodic); width a multiple of 64 in [64, 256];
+ * 2 <= hidden <= 16; 1 <= harmonics <= 8; period > 0.
+ * Step calls on such a plan take a pinn_net with n_layers = hidden + 3 (dims
+ * ignored; may be NULL) and W[l], b[l] in the order: U encoder (w x de),
+ * V encoder (w x de), first layer (w x de), layers 2 .. hidden (w x w),
+ * output (d_out x w).  Supported: pinn_jet_forward, pinn_jet_residual (no
+ * loss_f64), pinn_jet_backward and pinn_jet_backward_cot (no FP64 outputs),
+ * pinn_jet_loss, pinn_jet_loss_backward; the other plan calls return
+ * PINN_ERR_UNSUPPORTED. */
+typedef struct {
+  int32_t hidden;
+  int32_t width;
+  int32_t harmonics;
+  double period;
+} pinn_modified;
+pinn_status pinn_plan_create_modified(const pinn_modified *arch, const pinn_pde *pde, int64_t max_points,
+                                      int32_t prec, uint32_t flags, pinn_plan *out);
 
 /* Tunable launch parameters of a plan.  They change reduction order and
  * workgroup shapes, never the arithmetic: every setting is deterministic and

@@ -35,7 +35,7 @@ EXPORTS = ["pinn_plan_create", "pinn_plan_destroy", "pinn_plan_memory", "pinn_je
            "pinn_jet_step_noalloc", "pinn_jet_backward_cot", "pinn_batch_train_step", "pinn_batch_launches",
            "pinn_batch_profile", "pinn_batch_profile_read", "pinn_batch_get_tuning",
            "pinn_tuning_cache_clear", "pinn_tuning_cache_size", "pinn_tuning_cache_save", "pinn_tuning_cache_load",
-           "pinn_jet_loss", "pinn_jet_loss_backward", "pinn_batch_get_config"]
+           "pinn_jet_loss", "pinn_jet_loss_backward", "pinn_batch_get_config", "pinn_plan_create_modified"]
 KERNEL_CLASSES = {"layer_fwd": 1, "layer_bwd": 2, "dw_hidden": 3, "out_fwd": 4, "out_bwd": 5,
                   "seed_fwd": 6, "other": 7, "bwd_dw": 8}
 
@@ -58,11 +58,16 @@ class Pde(ctypes.Structure):
 class Segment(ctypes.Structure):
     _fields_ = [("type", ctypes.c_int32), ("data", ctypes.c_int32), ("begin", ctypes.c_int64),
                 ("count", ctypes.c_int64), ("weight", ctypes.c_double), ("mask", ctypes.c_uint32),
-                ("param", ctypes.c_double * 4)]
+                ("param", ctypes.c_double * 4), ("values", ctypes.c_void_p)]
 
 
 SEG_TYPES = {"pde": 0, "dirichlet": 1, "periodic": 2}
-SEG_DATA = {"zero": 0, "const": 1, "sin": 2}
+SEG_DATA = {"zero": 0, "const": 1, "sin": 2, "values": 3}
+
+
+class Modified(ctypes.Structure):
+    _fields_ = [("hidden", ctypes.c_int32), ("width", ctypes.c_int32), ("harmonics", ctypes.c_int32),
+                ("period", ctypes.c_double)]
 
 
 class Adam(ctypes.Structure):
@@ -106,6 +111,7 @@ def _load():
     lib.pinn_jet_loss.argtypes = [vp, NetP, PdeP, SegP, i32, vp, i64, vp, vp, vp]
     lib.pinn_jet_loss_backward.argtypes = [vp, NetP, PdeP, SegP, i32, vp, i64, pp, pp, vp]
     lib.pinn_batch_launches.argtypes = [vp, i64p]
+    lib.pinn_plan_create_modified.argtypes = [ctypes.POINTER(Modified), PdeP, i64, i32, ctypes.c_uint32, pp]
     lib.pinn_batch_get_config.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.pinn_batch_get_tuning.argtypes = [vp, i32, TuneP]
     lib.pinn_batch_profile.argtypes = [vp, i32]
@@ -137,7 +143,7 @@ def _load():
                  "pinn_jet_backward_cot", "pinn_batch_train_step", "pinn_batch_launches", "pinn_batch_profile",
                  "pinn_batch_profile_read", "pinn_batch_get_tuning", "pinn_tuning_cache_clear",
                  "pinn_tuning_cache_size", "pinn_tuning_cache_save", "pinn_tuning_cache_load", "pinn_jet_loss",
-                 "pinn_jet_loss_backward", "pinn_batch_get_config"):
+                 "pinn_jet_loss_backward", "pinn_batch_get_config", "pinn_plan_create_modified"):
         getattr(lib, name).restype = ctypes.c_int32
     return lib
 

@@ -24,10 +24,12 @@ __device__ __forceinline__ int seg_of(const SegPack &sp, int64_t n) {
   return -1;
 }
 
-__device__ __forceinline__ float seg_data(const SegPack &sp, int s, int o, float x0) {
+template <int DOUT>
+__device__ __forceinline__ float seg_data(const SegPack &sp, int s, int o, float x0, int64_t n) {
   switch (sp.data[s]) {
     case SEG_DATA_CONST: return sp.param[s][o];
     case SEG_DATA_SIN: return sp.param[s][0] * sinpif(sp.param[s][1] * x0);
+    case SEG_DATA_VALUES: return sp.values[s][(n - sp.begin[s]) * DOUT + o];
     default: return 0.f;
   }
 }
@@ -70,7 +72,7 @@ struct KSegLoss {
 #pragma unroll
         for (int o = 0; o < DOUT; ++o)
           if (sp.mask[s] >> (o * C) & 1u) {
-            const float r = a.u_save[(n * DOUT + o) * C] - seg_data(sp, s, o, x0);
+            const float r = a.u_save[(n * DOUT + o) * C] - seg_data<DOUT>(sp, s, o, x0, n);
             v += r * r;
           }
       } else {
@@ -168,7 +170,7 @@ struct KSegAdj {
 #pragma unroll
         for (int o = 0; o < DOUT; ++o)
           if (sp.mask[s] >> (o * C) & 1u)
-            ub[o][0] = cot * (a.u_save[(n * DOUT + o) * C] - seg_data(sp, s, o, x0));
+            ub[o][0] = cot * (a.u_save[(n * DOUT + o) * C] - seg_data<DOUT>(sp, s, o, x0, n));
       } else {
         const int64_t j = n - sp.begin[s];
         const int64_t na = n - (j & 1), nb = na + 1;  // the pair, first and second

@@ -180,10 +180,43 @@ hipError_t launch_reduce_parts2(const float *part, int splits, int64_t stride, i
                                 int64_t M2, float *a32, float *b32, double *a64, double *b64,
                                 hipStream_t st, float scale = 1.f);
 
+// Modified MLP with a periodic input embedding (k_mod.hip), FP32 operands.
+constexpr int kModMaxHarmonics = 8;
+constexpr int kModMaxDe = 1 + 2 * kModMaxHarmonics;  // embedding width for two inputs
+struct ModArgs {
+  const float *x;
+  int64_t N, N_pad;
+  int w, M, de;
+  float omega;
+  const float *WU, *bU, *WV, *bV, *W1, *b1;
+  float *U, *V, *h1;
+};
+bool mod_kind_supported(int kind);
+// U, V and h_1 from the embedding of x.
+hipError_t launch_mod_enc(int kind, const ModArgs &m, hipStream_t st);
+// Gated layer: h_out = U + tanh jet(W h_in + b) (V - U); S_out the state.
+hipError_t launch_mod_layer(int kind, const float *h_in, const float *W, const float *b, const float *U,
+                            const float *V, float *h_out, float *S_out, int64_t N_pad, int w, hipStream_t st);
+// hbar = W^T zbar on every channel (WT = W^T, w x w).
+hipError_t launch_mod_abar(int kind, const float *WT, const float *zbar, float *hbar, int64_t N_pad, int w,
+                           hipStream_t st);
+// Adjoint of a gated layer: Ubar, Vbar accumulated (set when top) and zbar;
+// top: hbar = W_o^T ubar formed in the kernel.
+hipError_t launch_mod_gate_bwd(int kind, bool top, const float *hbar, const float *ubar, const float *Wo,
+                               const float *S, const float *U, const float *V, float *Ubar, float *Vbar,
+                               float *zbar, int64_t N_pad, int w, hipStream_t st);
+// Adjoint of h_1, U and V at their pre-activations: zb3 = 3 stacks (h_1, U, V),
+// E = the embedding jets [N_pad][C][de].
+hipError_t launch_mod_enc_bwd(int kind, const ModArgs &m, const float *h1bar, const float *Ubar, const float *Vbar,
+                              float *zb3, float *E, hipStream_t st);
+// Weight-gradient partials of h_1, U and V: part[layer][chunk][w*de + w].
+hipError_t launch_mod_dw_enc(int kind, const float *zb3, const float *E, float *part, int64_t N_pad, int w, int de,
+                             int n_chunks, hipStream_t st);
+
 // Segments of a composite training loss over one point set (k_seg.hip).
 constexpr int kMaxSegments = 8;
 enum { SEG_PDE = 0, SEG_DIRICHLET = 1, SEG_PERIODIC = 2 };
-enum { SEG_DATA_ZERO = 0, SEG_DATA_CONST = 1, SEG_DATA_SIN = 2 };
+enum { SEG_DATA_ZERO = 0, SEG_DATA_CONST = 1, SEG_DATA_SIN = 2, SEG_DATA_VALUES = 3 };
 struct SegPack {
   int n;
   int type[kMaxSegments], data[kMaxSegments];
@@ -192,6 +225,7 @@ struct SegPack {
   float cot[kMaxSegments];              // S * weight * 2 / units: the scaled cotangent factor
   unsigned mask[kMaxSegments];          // bit o * C + c: output o, channel c
   float param[kMaxSegments][4];         // data function parameters
+  const float *values[kMaxSegments];    // SEG_DATA_VALUES: count x d_out targets (device)
   int blk_start[kMaxSegments + 1];      // loss-kernel workgroups of each segment (256 units each)
 };
 // Segment terms from the forward pass's outputs: partials per workgroup into

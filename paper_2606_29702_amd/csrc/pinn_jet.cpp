@@ -143,6 +143,16 @@ struct pinn_plan_s {
   size_t region_cap = 0, region_used = 0;
   bool measure = false;
 
+  // modified MLP with periodic embedding (pinn_plan_create_modified); arch 0
+  // is the plain MLP.  Layer l's stack h[l] (l = 1..H), gated-layer states
+  // S[l] (l = 2..H), encoder stacks and the adjoint buffers; FP32 throughout.
+  int arch = 0;
+  int mod_M = 0, mod_de = 0;
+  double mod_period = 0.0;
+  float *mU = nullptr, *mV = nullptr, *mUbar = nullptr, *mVbar = nullptr;
+  float *mhbar = nullptr, *mzbar = nullptr, *mzb3 = nullptr, *mE = nullptr, *mWscratch = nullptr;
+  std::vector<float *> mh, mS, mWT;
+
   // segments of the latest pinn_jet_loss call (valid with have_state)
   bool have_seg = false;
   pj::SegPack seg{};
@@ -249,11 +259,20 @@ hipError_t timed(pinn_plan p, int cls, hipStream_t st, F &&launch) {
 
 pinn_status check_call(pinn_plan plan, const pinn_net *net, const float *x, int64_t N) {
   if (!plan) return fail(PINN_ERR_ARG, "plan is NULL");
-  int w = 0;
-  pinn_status st = check_net(net, plan->kind, &w);
-  if (st) return st;
-  if (net->n_layers != plan->L || w != plan->w)
-    return fail(PINN_ERR_ARG, "network shape differs from the plan's");
+  if (plan->arch) {  // modified MLP: shapes are the plan's, the net carries the pointers
+    if (!net) return fail(PINN_ERR_ARG, "net is NULL");
+    if (net->n_layers != plan->L)
+      return fail(PINN_ERR_ARG, "a modified-MLP net has hidden + 3 = %d layers, not %d", plan->L, net->n_layers);
+    if (!net->W || !net->b) return fail(PINN_ERR_ARG, "net W or b is NULL");
+    for (int l = 0; l < net->n_layers; ++l)
+      if (!net->W[l] || !net->b[l]) return fail(PINN_ERR_ARG, "W[%d] or b[%d] is NULL", l, l);
+  } else {
+    int w = 0;
+    pinn_status st = check_net(net, plan->kind, &w);
+    if (st) return st;
+    if (net->n_layers != plan->L || w != plan->w)
+      return fail(PINN_ERR_ARG, "network shape differs from the plan's");
+  }
   if (!x) return fail(PINN_ERR_ARG, "x is NULL");
   if (N < 1 || N > plan->max_points)
     return fail(PINN_ERR_ARG, "N = %lld outside [1, max_points = %lld]", (long long)N,
@@ -367,9 +386,13 @@ pinn_status cast_weights(pinn_plan p, const pinn_net *net, bool transposed, hipS
 
 // Forward pass through all layers, the residual and the loss.  With
 // save_state the checkpoint layers' stacks (and FP32 states) are kept.
+pinn_status mod_forward(pinn_plan p, const pinn_net *net, const pinn_pde *pde, const float *x, int64_t N,
+                        float *jets, float *r, float *loss, hipStream_t st);
+
 pinn_status run_forward(pinn_plan p, const pinn_net *net, const pinn_pde *pde, const float *x,
                         int64_t N, float *jets, float *r, float *loss, double *loss_f64,
                         bool save_state, hipStream_t st) {
+  if (p->arch) return mod_forward(p, net, pde, x, N, jets, r, loss, st);
   const int64_t npad = round_up(N, pj::kPointTile);
   const int H = p->H;
   // operand-type weights; a residual call (save_state) also makes the
@@ -608,6 +631,93 @@ pinn_status pinn_plan_create(const pinn_net *net, const pinn_pde *pde, int64_t m
   return plan_build(net, pde, max_points, prec, flags, save_cap_bytes, nullptr, 0, false, out);
 }
 
+pinn_status pinn_plan_create_modified(const pinn_modified *arch, const pinn_pde *pde, int64_t max_points,
+                                      int32_t prec, uint32_t flags, pinn_plan *out) {
+  g_err.clear();
+  if (!out) return fail(PINN_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!arch) return fail(PINN_ERR_ARG, "arch is NULL");
+  pinn_status st = check_pde(pde, 0);
+  if (st) return st;
+  if (!pj::mod_kind_supported(pde->kind))
+    return fail(PINN_ERR_UNSUPPORTED, "the modified MLP supports the KS and Burgers kinds (input x_0 periodic)");
+  if (prec != PINN_FP32) return fail(PINN_ERR_UNSUPPORTED, "the modified MLP runs with FP32 operands only");
+  if (flags) return fail(PINN_ERR_UNSUPPORTED, "the modified MLP takes no flags");
+  if (arch->hidden < 2 || arch->hidden > 16) return fail(PINN_ERR_UNSUPPORTED, "hidden = %d outside [2, 16]", arch->hidden);
+  if (arch->width < 64 || arch->width > 256 || arch->width % 64)
+    return fail(PINN_ERR_UNSUPPORTED, "width %d is not a multiple of 64 in [64, 256]", arch->width);
+  if (arch->harmonics < 1 || arch->harmonics > pj::kModMaxHarmonics)
+    return fail(PINN_ERR_UNSUPPORTED, "harmonics = %d outside [1, %d]", arch->harmonics, pj::kModMaxHarmonics);
+  if (!(arch->period > 0.0) || !std::isfinite(arch->period)) return fail(PINN_ERR_ARG, "period must be positive");
+  if (max_points < 1 || max_points > kMaxPoints)
+    return fail(PINN_ERR_ARG, "max_points = %lld outside [1, %lld]", (long long)max_points, (long long)kMaxPoints);
+  KindInfo ki;
+  kind_info(pde->kind, &ki);
+  const int H = arch->hidden, w = arch->width, C = ki.C;
+  const int64_t npad = round_up(max_points, pj::kPointTile);
+  pinn_plan p = new (std::nothrow) pinn_plan_s;
+  if (!p) return fail(PINN_ERR_NOMEM, "host allocation failed");
+  p->kind = pde->kind;
+  p->prec = PINN_FP32;
+  p->L = H + 3;
+  p->H = H;
+  p->w = w;
+  p->ki = ki;
+  p->max_points = max_points;
+  p->npad_max = npad;
+  p->arch = 1;
+  p->mod_M = arch->harmonics;
+  p->mod_de = ki.din - 1 + 2 * arch->harmonics;
+  p->mod_period = arch->period;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return fail(PINN_ERR_DEVICE, "no HIP device");
+  }
+  const size_t stack = (size_t)npad * C * w * sizeof(float);
+  hipError_t e = hipSuccess;
+  auto A = [&](float **ptr, size_t bytes) {
+    void *q = nullptr;
+    if (e == hipSuccess) e = p->alloc(&q, bytes);
+    *ptr = static_cast<float *>(q);
+  };
+  A(&p->mU, stack);
+  A(&p->mV, stack);
+  A(&p->mUbar, stack);
+  A(&p->mVbar, stack);
+  A(&p->mhbar, stack);
+  A(&p->mzbar, stack);
+  A(&p->mzb3, 3 * stack);
+  A(&p->mE, (size_t)npad * C * p->mod_de * sizeof(float));
+  A(&p->mWscratch, (size_t)w * w * sizeof(float));
+  p->mh.assign(H + 1, nullptr);
+  p->mS.assign(H + 1, nullptr);
+  p->mWT.assign(H + 1, nullptr);
+  for (int l = 1; l <= H; ++l) A(&p->mh[l], stack);
+  for (int l = 2; l <= H; ++l) {
+    A(&p->mS[l], stack);
+    A(&p->mWT[l], (size_t)w * w * sizeof(float));
+  }
+  A(&p->u_save, (size_t)npad * ki.dout * C * sizeof(float));
+  A(&p->r_save, (size_t)npad * ki.nres * sizeof(float));
+  A(&p->ubar, (size_t)npad * ki.dout * C * sizeof(float));
+  A(&p->loss_part, (size_t)(npad / 16) * sizeof(float));
+  p->dw_splits = dw_splits_for(npad, C, w);
+  p->dw_splits_max = p->dw_splits;
+  p->thin_chunks = (int)std::max<int64_t>(1, npad / 64);
+  const size_t part_elems = std::max<size_t>(
+      std::max<size_t>((size_t)p->dw_splits * ((size_t)w * w + w), (size_t)p->thin_chunks * (ki.dout * w + ki.dout)),
+      (size_t)3 * p->thin_chunks * ((size_t)w * p->mod_de + w));
+  A(&p->part, part_elems * sizeof(float));
+  if (e != hipSuccess) {
+    delete p;
+    return fail(e == hipErrorOutOfMemory ? PINN_ERR_NOMEM : PINN_ERR_DEVICE, "workspace allocation: %s",
+                hipGetErrorString(e));
+  }
+  p->saved_bytes = (size_t)(2 * H + 1) * stack;
+  *out = p;
+  return PINN_OK;
+}
+
 pinn_status pinn_plan_destroy(pinn_plan plan) {
   g_err.clear();
   if (!plan) return fail(PINN_ERR_ARG, "plan is NULL");
@@ -679,6 +789,78 @@ pinn_status pinn_jet_residual(pinn_plan plan, const pinn_net *net, const pinn_pd
 
 }  // extern "C"
 
+namespace {
+
+// Forward pass of a modified-MLP plan: embedding and encoders, the gated
+// layers, then the plain path's output layer, residual and loss partials.
+pinn_status mod_forward(pinn_plan p, const pinn_net *net, const pinn_pde *pde, const float *x, int64_t N,
+                        float *jets, float *r, float *loss, hipStream_t st) {
+  const int64_t npad = round_up(N, pj::kPointTile);
+  const int H = p->H, L = p->L, w = p->w;
+  pinn_pde dflt{};
+  if (!pde) {
+    dflt.kind = p->kind;
+    dflt.coef[0] = 1.0;
+    pde = &dflt;
+  }
+  pj::ModArgs m{x, N, npad, w, p->mod_M, p->mod_de, (float)(2.0 * M_PI / p->mod_period),
+                net->W[0], net->b[0], net->W[1], net->b[1], net->W[2], net->b[2], p->mU, p->mV, p->mh[1]};
+  hipError_t e = timed(p, PINN_K_SEED_FWD, st, [&] { return pj::launch_mod_enc(p->kind, m, st); });
+  if (e) return hip_fail(e, "embedding and encoders");
+  for (int l = 2; l <= H; ++l) {
+    e = timed(p, PINN_K_LAYER_FWD, st, [&] { return pj::launch_mod_layer(p->kind, p->mh[l - 1], net->W[l + 1], net->b[l + 1], p->mU, p->mV, p->mh[l], p->mS[l], npad, w, st); });
+    if (e) return hip_fail(e, "gated layer");
+  }
+  e = timed(p, PINN_K_OUT_FWD, st, [&] { return pj::launch_out_fwd(p->kind, PINN_FP32, p->mh[H], net->W[L - 1], net->b[L - 1], x, N, npad, w, coef_of(pde), jets, r, p->u_save, p->r_save, p->loss_part, nullptr, st); });
+  if (e) return hip_fail(e, "output layer");
+  if (loss) {
+    e = timed(p, PINN_K_OTHER, st, [&] { return pj::launch_loss_reduce(p->loss_part, nullptr, (int)(npad / 16), 1.0 / (double)N, loss, nullptr, st); });
+    if (e) return hip_fail(e, "loss reduction");
+  }
+  return PINN_OK;
+}
+
+// Backward pass of a modified-MLP plan from the output cotangent in p->ubar
+// (scaled by 1 / inv_s): output layer, the gated layers top down (their weight
+// gradients by the split-K kernel, the stack below through W^T), then the
+// first layer and the two encoders.
+pinn_status mod_backward(pinn_plan p, const pinn_net *net, const float *x, int64_t N, float *const *dW,
+                         float *const *db, float inv_s, hipStream_t s) {
+  const int64_t npad = round_up(N, pj::kPointTile);
+  const int H = p->H, L = p->L, w = p->w, C = p->ki.C, dout = p->ki.dout, de = p->mod_de;
+  hipError_t e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_dw_out(p->kind, PINN_FP32, p->ubar, p->mh[H], npad, w, p->part, p->thin_chunks, s); });
+  if (e) return hip_fail(e, "output-layer gradient");
+  e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, p->thin_chunks, (int64_t)dout * w + dout, (int64_t)dout * w, dout, dW[L - 1], db[L - 1], nullptr, nullptr, s, inv_s); });
+  if (e) return hip_fail(e, "reduction");
+  for (int l = H; l >= 2; --l) {
+    e = timed(p, PINN_K_LAYER_BWD, s, [&] { return pj::launch_mod_gate_bwd(p->kind, l == H, p->mhbar, p->ubar, net->W[L - 1], p->mS[l], p->mU, p->mV, p->mUbar, p->mVbar, p->mzbar, npad, w, s); });
+    if (e) return hip_fail(e, "gated-layer adjoint");
+    e = timed(p, PINN_K_DW_HIDDEN, s, [&] { return pj::launch_dw_hidden(PINN_FP32, C, p->mzbar, p->mh[l - 1], npad, w, p->part, p->part + (size_t)w * w, p->dw_splits, s); });
+    if (e) return hip_fail(e, "gated-layer gradient");
+    e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, p->dw_splits, (int64_t)w * w + w, (int64_t)w * w, w, dW[l + 1], db[l + 1], nullptr, nullptr, s, inv_s); });
+    if (e) return hip_fail(e, "reduction");
+    e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_cast(PINN_FP32, net->W[l + 1], w, w, p->mWscratch, p->mWT[l], s); });
+    if (e) return hip_fail(e, "transpose");
+    e = timed(p, PINN_K_LAYER_BWD, s, [&] { return pj::launch_mod_abar(p->kind, p->mWT[l], p->mzbar, p->mhbar, npad, w, s); });
+    if (e) return hip_fail(e, "gated-layer input adjoint");
+  }
+  pj::ModArgs m{x, N, npad, w, p->mod_M, de, (float)(2.0 * M_PI / p->mod_period),
+                net->W[0], net->b[0], net->W[1], net->b[1], net->W[2], net->b[2], nullptr, nullptr, nullptr};
+  e = timed(p, PINN_K_LAYER_BWD, s, [&] { return pj::launch_mod_enc_bwd(p->kind, m, p->mhbar, p->mUbar, p->mVbar, p->mzb3, p->mE, s); });
+  if (e) return hip_fail(e, "encoder adjoint");
+  e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_mod_dw_enc(p->kind, p->mzb3, p->mE, p->part, npad, w, de, p->thin_chunks, s); });
+  if (e) return hip_fail(e, "encoder gradients");
+  const int64_t stride = (int64_t)w * de + w;
+  const int dst[3] = {2, 0, 1};  // zb3 holds h_1, U, V
+  for (int q = 0; q < 3; ++q) {
+    e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part + (size_t)q * p->thin_chunks * stride, p->thin_chunks, stride, (int64_t)w * de, w, dW[dst[q]], db[dst[q]], nullptr, nullptr, s, inv_s); });
+    if (e) return hip_fail(e, "reduction");
+  }
+  return PINN_OK;
+}
+
+}  // namespace
+
 // The backward pass for the cotangent rbar = r_bar + lb 2 r / N, with lb =
 // *loss_bar, or lb = 1 when both are null (see pinn_jet_backward_cot).
 static pinn_status backward_impl(pinn_plan plan, const pinn_net *net, const pinn_pde *pde, const float *x,
@@ -731,6 +913,11 @@ static pinn_status backward_impl(pinn_plan plan, const pinn_net *net, const pinn
       return timed(p, PINN_K_OUT_BWD, s, [&] { return pj::launch_seg_adj(p->kind, p->seg, p->u_save, p->r_save, x, npad, coef_of(pde), p->ubar, s); });
     return timed(p, PINN_K_OUT_BWD, s, [&] { return pj::launch_out_adj(p->kind, p->u_save, p->r_save, r_bar, loss_bar, N, npad, rbar_scale, coef_of(pde), p->ubar, s); });
   };
+  if (p->arch) {
+    const hipError_t e0 = output_adjoint();
+    if (e0) return hip_fail(e0, "output adjoint");
+    return mod_backward(p, net, x, N, dW, db, inv_s, s);
+  }
   hipError_t e;
   // the operand-type weights W and W^T were made by the residual call
   pinn_status rs = PINN_OK;
@@ -937,8 +1124,11 @@ static pinn_status seg_pack(pinn_plan p, const pinn_segment *segs, int32_t n_seg
     switch (g.type) {
       case PINN_SEG_PDE: break;
       case PINN_SEG_DIRICHLET:
-        if (g.data != PINN_DATA_ZERO && g.data != PINN_DATA_CONST && g.data != PINN_DATA_SIN)
+        if (g.data != PINN_DATA_ZERO && g.data != PINN_DATA_CONST && g.data != PINN_DATA_SIN &&
+            g.data != PINN_DATA_VALUES)
           return fail(PINN_ERR_ARG, "segment %d: unknown data function %d", s, g.data);
+        if (g.data == PINN_DATA_VALUES && !g.values)
+          return fail(PINN_ERR_ARG, "segment %d: PINN_DATA_VALUES without values", s);
         if (g.mask == 0 || (uint64_t)g.mask > all_bits) return fail(PINN_ERR_ARG, "segment %d: bad mask", s);
         for (int q = 0; q < dout * C; ++q)
           if ((g.mask >> q & 1u) && q % C != 0)
@@ -958,6 +1148,7 @@ static pinn_status seg_pack(pinn_plan p, const pinn_segment *segs, int32_t n_seg
     sp->weight[s] = (float)g.weight;
     sp->mask[s] = g.mask;
     for (int q = 0; q < 4; ++q) sp->param[s][q] = (float)g.param[q];
+    sp->values[s] = g.type == PINN_SEG_DIRICHLET && g.data == PINN_DATA_VALUES ? g.values : nullptr;
     sp->blk_start[s] = blk;
     blk += (int)((units + 255) / 256);
     if (g.weight > 0.0) ratio = std::min(ratio, (double)units / (2.0 * g.weight));
@@ -1089,6 +1280,7 @@ extern "C" {
 pinn_status pinn_plan_autotune(pinn_plan plan, const pinn_net *net, const pinn_pde *pde, const float *x,
                                int64_t N, int32_t reps, pinn_tuning *best, double *best_ms, void *stream) {
   g_err.clear();
+  if (plan && plan->arch) return fail(PINN_ERR_UNSUPPORTED, "a modified-MLP plan has no tunings");
   pinn_status st = check_call(plan, net, x, N);
   if (st) return st;
   st = check_pde(pde, plan->kind);
@@ -1392,6 +1584,7 @@ pinn_status pinn_graph_capture(pinn_plan plan, const pinn_net *net, const pinn_p
                                int64_t N, float *r, float *loss, float *const *dW, float *const *db,
                                pinn_graph *out) {
   g_err.clear();
+  if (plan && plan->arch) return fail(PINN_ERR_UNSUPPORTED, "graph capture of a modified-MLP plan");
   return graph_capture(plan, net, pde, x, N, r, loss, dW, db, nullptr, nullptr, out);
 }
 
@@ -1400,6 +1593,7 @@ pinn_status pinn_graph_capture_train(pinn_plan plan, const pinn_net *net, const 
                                      float *const *mW, float *const *vW, float *const *mb, float *const *vb,
                                      const pinn_adam *hp, int64_t *step_dev, pinn_graph *out) {
   g_err.clear();
+  if (plan && plan->arch) return fail(PINN_ERR_UNSUPPORTED, "graph capture of a modified-MLP plan");
   if (!net || !step_dev) return fail(PINN_ERR_ARG, "net or step_dev is NULL");
   if (!out) return fail(PINN_ERR_ARG, "out is NULL");
   pj::AdamArgs a;

@@ -12,7 +12,8 @@ from typing import List, Optional, Sequence, Tuple
 import torch
 
 from . import _lib
-from ._lib import KINDS, PRECISIONS, SEG_DATA, SEG_TYPES, Net, Pde, PinnError, Segment, Tuning, check, lib, ptr_array
+from ._lib import (KINDS, PRECISIONS, SEG_DATA, SEG_TYPES, Modified, Net, Pde, PinnError, Segment, Tuning, check, lib,
+                   ptr_array)
 from .closure import channels, resolve_kind
 
 CHANNELS = {k: lib.pinn_pde_channels(v) for k, v in KINDS.items()}
@@ -216,13 +217,18 @@ class PinnPlan:
             arr[i].mask = int(sg.get("mask", 0))
             for q, v in enumerate(sg.get("param", ())):
                 arr[i].param[q] = float(v)
+            if sg.get("data") == "values":
+                vals = sg["values"]
+                _check_tensor(vals, "values")
+                arr[i].values = vals.data_ptr()
         return arr
 
     def loss(self, params, x: torch.Tensor, segments):
         """Composite loss over point segments (all points evaluated together,
         then split; see pinn_jet_loss).  segments: list of dicts with type
         ('pde', 'dirichlet', 'periodic'), begin, count, weight, mask, data
-        ('zero', 'const', 'sin') and param.  Returns (loss (), seg_loss (n,))."""
+        ('zero', 'const', 'sin', 'values') and param; 'values' takes a device
+        tensor of count x d_out float32 targets.  Returns (loss (), seg_loss (n,))."""
         _check_tensor(x, "x")
         nv = _NetView(params)
         segs = self._segments(segments)
@@ -252,6 +258,31 @@ class PinnPlan:
         the Adam update (pinn_graph_capture_train), counting steps on the
         device."""
         return PinnGraph(self, params, x, adam)
+
+
+class ModifiedPlan(PinnPlan):
+    """A plan for the modified MLP with periodic input embedding (the KS
+    network of Sec. 3.1.1; pinn_plan_create_modified), FP32 operands.
+    Parameters are [(W_U, b_U), (W_V, b_V), (W_1, b_1), .., (W_H, b_H),
+    (W_o, b_o)]; forward, residual, backward, loss and loss_backward as for
+    PinnPlan."""
+
+    def __init__(self, hidden: int, width: int, harmonics: int, period: float, pde: str, max_points: int,
+                 coef: Optional[Sequence[float]] = None):
+        self.pde = pde
+        self.coef = tuple(coef) if coef is not None else DEFAULT_COEF[pde]
+        self.precision = "fp32"
+        self.verify_f64 = False
+        self.C = CHANNELS[pde]
+        self.n_res = RESIDUALS[pde]
+        self.max_points = int(max_points)
+        self.hidden, self.width, self.harmonics, self.period = int(hidden), int(width), int(harmonics), float(period)
+        self.dims = [2] + [self.width] * self.hidden + [1]  # inputs (x, t), output u (KS, Burgers)
+        arch = Modified(self.hidden, self.width, self.harmonics, self.period)
+        handle = ctypes.c_void_p()
+        check(lib.pinn_plan_create_modified(ctypes.byref(arch), ctypes.byref(_pde(pde, self.coef)), self.max_points,
+                                            PRECISIONS["fp32"], 0, ctypes.byref(handle)))
+        self.handle = handle
 
 
 class PinnGraph:

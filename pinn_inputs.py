@@ -248,3 +248,53 @@ def cavity_training_set(seed: int = 0, n_pde: int = 10000, n_wall: int = 1499, n
     lid = np.stack([rng.random(n_lid), np.ones(n_lid)], 1)
     x = np.concatenate([pde, wall, lid]).astype(np.float32)
     return TrainingSet("ns", dims, (100.0,), x, cavity_segments(n_pde, n_wall, n_lid, **weights), params)
+
+
+def modified_params(hidden: int, width: int, harmonics: int, rng: np.random.Generator, d_in: int = 2, d_out: int = 1,
+                    bias_std: float = 0.0):
+    """Xavier-normal parameters of the modified MLP with periodic embedding, in
+    the order (W_U, b_U), (W_V, b_V), (W_1, b_1), .., (W_H, b_H), (W_o, b_o);
+    embedding width de = d_in - 1 + 2 harmonics."""
+    de = d_in - 1 + 2 * harmonics
+    shapes = [(width, de), (width, de), (width, de)] + [(width, width)] * (hidden - 1) + [(d_out, width)]
+    out = []
+    for fo, fi in shapes:
+        W = rng.normal(0.0, math.sqrt(2.0 / (fi + fo)), size=(fo, fi)).astype(np.float32)
+        b = (rng.normal(0.0, bias_std, size=(fo,)) if bias_std > 0 else np.zeros(fo)).astype(np.float32)
+        out.append((W, b))
+    return out
+
+
+@dataclass
+class ModifiedSet:
+    hidden: int
+    width: int
+    harmonics: int
+    period: float
+    coef: Tuple[float, ...]
+    x: np.ndarray           # (N, 2) float32: PDE points, then initial points
+    targets: np.ndarray     # (N, 1) float32: initial data at the initial points (0 elsewhere)
+    segments: list
+    params: list
+
+
+def ks_training_set(seed: int = 0, n_pde: int = 4096, n_ic: int = 512, width: int = 64, hidden: int = 6,
+                    harmonics: int = 1, t_end: float = 1.0, w_ic: float = 1.0, bias_std: float = 0.0) -> ModifiedSet:
+    """Kuramoto-Sivashinsky training set of the paper's size (4096 PDE and 512
+    initial points), r = u_t + 5 u u_x + 0.5 u_xx + 0.005 u_xxxx, on x in
+    [0, 2 pi) (periodic, imposed by the embedding) and t in [0, t_end]; the
+    initial data u(x, 0) = cos x (1 + sin x) stands in for the paper's
+    reference solution.  Modified MLP with `harmonics` embedding frequencies."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    params = modified_params(hidden, width, harmonics, rng, bias_std=bias_std)
+    period = 2.0 * math.pi
+    pde = np.stack([period * rng.random(n_pde), t_end * rng.random(n_pde)], 1)
+    xi = np.arange(n_ic) * (period / n_ic)
+    ic = np.stack([xi, np.zeros(n_ic)], 1)
+    x = np.concatenate([pde, ic]).astype(np.float32)
+    targets = np.zeros((x.shape[0], 1), dtype=np.float32)
+    x0 = x[n_pde:, 0].astype(np.float64)
+    targets[n_pde:, 0] = (np.cos(x0) * (1.0 + np.sin(x0))).astype(np.float32)
+    segs = [dict(type="pde", begin=0, count=n_pde, weight=1.0),
+            dict(type="dirichlet", begin=n_pde, count=n_ic, weight=w_ic, mask=1, data="values")]
+    return ModifiedSet(hidden, width, harmonics, period, (5.0, 0.5, 0.005), x, targets, segs, params)
