@@ -453,6 +453,101 @@ def nested_autograd_training(ts, steps, lr=1e-3):
     return (time.perf_counter() - t0) * 1e3 / steps
 
 
+def ks_training_leg(steps):
+    """The paper's KS training run (Sec. 3.1.1) on the modified MLP with
+    periodic embedding: `steps` Adam steps on the composite loss (4096 PDE
+    points + 512 initial points), FP32, eager calls."""
+    import torch
+    import pinn_inputs as pi
+    from paper_2606_29702_amd import AdamState, ModifiedPlan
+    ts = pi.ks_training_set(seed=0)
+    N = ts.x.shape[0]
+    plan = ModifiedPlan(ts.hidden, ts.width, ts.harmonics, ts.period, "ks", N, coef=ts.coef)
+    params = [(torch.tensor(W, device="cuda"), torch.tensor(b, device="cuda")) for W, b in ts.params]
+    x = torch.tensor(ts.x, device="cuda")
+    segs = [dict(sg) for sg in ts.segments]
+    ic = segs[1]
+    ic["values"] = torch.tensor(ts.targets[ic["begin"]:ic["begin"] + ic["count"]], device="cuda").contiguous()
+    opt = AdamState(params, lr=1e-3)
+    grads = [(torch.empty_like(W), torch.empty_like(b)) for W, b in params]
+
+    def step():
+        plan.loss(params, x, segs)
+        plan.loss_backward(params, x, segs, out=grads)
+        opt.step(grads)
+
+    for _ in range(5):
+        step()
+    torch.cuda.synchronize()
+    l0 = float(plan.loss(params, x, segs)[0])
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    l1 = float(plan.loss(params, x, segs)[0])
+    plan.close()
+    return dict(workload="ks training set, modified MLP with periodic embedding", hidden=ts.hidden, width=ts.width,
+                harmonics=ts.harmonics, points=N, precision="fp32", steps=steps, ms_per_step=round(ms, 4),
+                run_s=round(ms * steps * 1e-3, 4), value=round(N / (ms * 1e-3), 1), unit="pts/s",
+                loss_first=l0, loss_last=l1)
+
+
+def nested_autograd_ks(steps, lr=1e-3):
+    """The AD baseline for the KS run: the same modified MLP and loss with
+    u_t, u_x .. u_xxxx by nested torch.autograd, torch.optim.Adam, FP32."""
+    import torch
+    import pinn_inputs as pi
+    ts = pi.ks_training_set(seed=0)
+    params = [t for W, b in ts.params for t in (torch.tensor(W, device="cuda", requires_grad=True),
+                                                 torch.tensor(b, device="cuda", requires_grad=True))]
+    opt = torch.optim.Adam(params, lr=lr)
+    X0 = torch.tensor(ts.x, device="cuda")
+    tg = torch.tensor(ts.targets, device="cuda")[:, 0]
+    a, bb, g = ts.coef
+    n_pde = ts.segments[0]["count"]
+    w_ic = ts.segments[1]["weight"]
+    om = 2.0 * math.pi / ts.period
+
+    def net(X):
+        feats = [X[:, 1:2]]
+        for m in range(1, ts.harmonics + 1):
+            feats += [torch.cos(m * om * X[:, 0:1]), torch.sin(m * om * X[:, 0:1])]
+        E = torch.cat(feats, 1)
+        U = torch.tanh(E @ params[0].T + params[1])
+        V = torch.tanh(E @ params[2].T + params[3])
+        h = torch.tanh(E @ params[4].T + params[5])
+        for l in range(3, len(params) // 2 - 1):
+            Z = torch.tanh(h @ params[2 * l].T + params[2 * l + 1])
+            h = (1.0 - Z) * U + Z * V
+        return (h @ params[-2].T + params[-1])[:, 0]
+
+    def d(f, X, i):
+        return torch.autograd.grad(f.sum(), X, create_graph=True)[0][:, i]
+
+    def step():
+        X = X0.clone().requires_grad_(True)
+        u = net(X)
+        ut, ux = d(u, X, 1), d(u, X, 0)
+        uxx = d(ux, X, 0)
+        uxxxx = d(d(uxx, X, 0), X, 0)
+        r = (ut + a * u * ux + bb * uxx + g * uxxxx)[:n_pde]
+        loss = (r * r).mean() + w_ic * ((u[n_pde:] - tg[n_pde:]) ** 2).mean()
+        grads = torch.autograd.grad(loss, params)
+        for p_, g_ in zip(params, grads):
+            p_.grad = g_
+        opt.step()
+
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
 def pi_training_set(name):
     import pinn_inputs as pi
     return pi.burgers_training_set(seed=0) if name == "burgers" else pi.cavity_training_set(seed=0)
@@ -519,6 +614,29 @@ def plan_leg(name, prec, steps, warmup, save_cap=0, fp32_context=True):
     return out
 
 
+def training_runs(names, prec, steps):
+    """The paper's complete training runs (1000 full-batch Adam steps on the
+    composite loss): the jet path in FP32 (and `prec` for the plain MLPs)
+    beside the nested-autograd FP32 baseline on the same GPU."""
+    runs = {}
+    for name in [t for t in names.split(",") if t]:
+        if name == "ks":
+            r = {"fp32": ks_training_leg(steps)}
+            ad_fn = lambda: nested_autograd_ks(50)  # noqa: E731
+        else:
+            r = {p: training_leg(name, p, steps) for p in ("fp32", prec)}
+            ad_fn = lambda: nested_autograd_training(pi_training_set(name), 50)  # noqa: E731
+        try:
+            ad = ad_fn()
+            r["nested_autograd_fp32"] = {"ms_per_step": round(ad, 4),
+                                         "speedup_fp32_jet": round(ad / r["fp32"]["ms_per_step"], 3)}
+        except RuntimeError as e:  # out of memory is reported, not fatal
+            r["nested_autograd_fp32"] = {"error": str(e)[:200]}
+        runs[name] = r
+        log(f"training {name}: " + ", ".join(f"{k} {v.get('ms_per_step')} ms/step" for k, v in r.items()))
+    return runs
+
+
 # --------------------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
@@ -537,8 +655,8 @@ def main():
     ap.add_argument("--save-cap-gib", type=float, default=0.0, help="saved-state cap of a single-network workload")
     ap.add_argument("--tuning", default=None, help="dw_splits,fwd_points,bwd_fused for a single-network workload")
     ap.add_argument("--copy-probe-mib", type=int, default=0, help="only run a plain device copy of this size")
-    ap.add_argument("--training", default="burgers,ns",
-                    help="paper training runs (1000 Adam steps on the composite loss): burgers, ns or ''")
+    ap.add_argument("--training", default="burgers,ns,ks",
+                    help="paper training runs (1000 Adam steps on the composite loss): burgers, ns, ks or ''")
     ap.add_argument("--training-steps", type=int, default=1000)
     args = ap.parse_args()
 
@@ -555,13 +673,7 @@ def main():
     prec = args.precision
 
     if args.workload == "training":  # only the paper's training runs
-        out = {}
-        for name in [t for t in args.training.split(",") if t]:
-            out[name] = {p: training_leg(name, p, args.training_steps) for p in ("fp32", prec)}
-            ad = nested_autograd_training(pi_training_set(name), 50)
-            out[name]["nested_autograd_fp32"] = {"ms_per_step": round(ad, 4)}
-            log(f"training {name}: {out[name]}")
-        print(json.dumps({"training_runs": out}), flush=True)
+        print(json.dumps({"training_runs": training_runs(args.training, prec, args.training_steps)}), flush=True)
         return
 
     if args.workload != "ensemble":  # one single-network workload (profiling runs)
@@ -652,19 +764,7 @@ def main():
         out["legs"] = legs
 
     if not args.no_context and args.training:
-        runs = {}
-        for name in [t for t in args.training.split(",") if t]:
-            r = {p: training_leg(name, p, args.training_steps) for p in ("fp32", prec)}
-            try:
-                ad = nested_autograd_training(pi_training_set(name), 50)
-                r["nested_autograd_fp32"] = {"ms_per_step": round(ad, 4),
-                                             "speedup_fp32_jet": round(ad / r["fp32"]["ms_per_step"], 3)}
-            except RuntimeError as e:
-                r["nested_autograd_fp32"] = {"error": str(e)[:200]}
-            runs[name] = r
-            log(f"training {name}: fp32 {r['fp32']['ms_per_step']} ms/step, {prec} {r[prec]['ms_per_step']} ms/step, "
-                f"nested AD {r['nested_autograd_fp32']}")
-        out["training_runs"] = runs
+        out["training_runs"] = training_runs(args.training, prec, args.training_steps)
 
     print(json.dumps(out), flush=True)
 

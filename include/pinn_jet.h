@@ -281,7 +281,9 @@ pinn_status pinn_plan_create_modified(const pinn_modified *arch, const pinn_pde 
  *   dw_splits   number of split-K partials of each hidden-layer weight gradient
  *               (1 .. twice the plan's default)
  *   fwd_points  points per workgroup of the whole-network forward kernel
- *               (0 = the largest tiling whose stack fits in LDS, else 16 or 32)
+ *               (0 = the default tiling; else 16, 32, or for 16-bit operands
+ *               at widths 64-256 also 64, where each wave works on four
+ *               16-point tiles and reuses every weight fragment across them)
  *   bwd_fused   1: hidden-layer weight gradients are accumulated inside the
  *               persistent backward layer kernels where the width allows
  *               (32, 64, 128); 0: separate split-K gradient kernels.  Default:

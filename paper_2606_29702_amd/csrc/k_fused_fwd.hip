@@ -15,8 +15,10 @@
 // per-point outputs.
 //
 // Wave layout: the P/16 x w/16 MFMA output tiles of a layer are split over NW
-// waves, TPW consecutive neuron tiles of one 16-point tile per wave, so that
-// every B operand read from LDS feeds TPW MFMAs.
+// waves, TPW consecutive neuron tiles of PTW consecutive 16-point tiles per
+// wave, so that every B operand read from LDS feeds TPW MFMAs and every weight
+// fragment PTW x C of them (more points per workgroup read the weights fewer
+// times per point).
 #include "dev_common.hpp"
 #include "group.hpp"
 #include "kernels.hpp"
@@ -41,7 +43,7 @@ __device__ __forceinline__ void copy_out_rows(T *g, const T *lds, int row_elems,
           *reinterpret_cast<const uint4 *>(lds + row * pitch + c * per16);
 }
 
-template <class PDE, class T, int NW, int TPW, int P>
+template <class PDE, class T, int NW, int TPW, int P, int PTW = 1>
 struct KFwdFused {
   static constexpr int NT = NW * 64;
   struct Args {
@@ -66,14 +68,13 @@ struct KFwdFused {
     const int64_t gps = (int64_t)C * w;  // elements per point in a global stack
 
     // Wave layout of every layer: this wave owns the TPW neuron tiles jt0 ..
-    // jt0 + TPW - 1 of the 16-point tile nt; lane (r, g) holds point nt * 16 + r
-    // and, in tile t, neurons (jt0 + t) * 16 + 4 g + 0..3.
+    // jt0 + TPW - 1 of the PTW 16-point tiles nt0 .. nt0 + PTW - 1; lane (r, g)
+    // holds point (nt0 + q) * 16 + r of tile q and, in neuron tile t, neurons
+    // (jt0 + t) * 16 + 4 g + 0..3.
     const int NJ = w / 16;
-    const int tile0 = wave * TPW;
-    const int nt = tile0 / NJ;
-    const int jt0 = tile0 % NJ;
-    const int p_l = nt * 16 + r;  // this lane's point within the block
-    const int64_t n_l = nb + p_l;
+    const int NG = NJ / TPW;  // neuron groups
+    const int nt0 = (wave / NG) * PTW;
+    const int jt0 = (wave % NG) * TPW;
     // this thread's place in the stack copy-out (row and 16-byte column)
     const int per_row16 = C * w * (int)sizeof(T) / 16;
     const int out_row0 = tid / per_row16, out_col = tid - out_row0 * per_row16;
@@ -81,6 +82,10 @@ struct KFwdFused {
     // ---- input of layer l_first: the seed layer from x, or a saved stack
     if (a.l_first == 1) {
       // layer 1: z = W1 x + b1, d z / d x_i = W1[:, i], then the jet
+  #pragma unroll
+      for (int qt = 0; qt < PTW; ++qt) {
+      const int p_l = (nt0 + qt) * 16 + r;  // this lane's point within the block
+      const int64_t n_l = nb + p_l;
       float xin[D];
   #pragma unroll
       for (int i = 0; i < D; ++i) xin[i] = n_l < a.N ? a.x[n_l * D + i] : 0.f;
@@ -114,6 +119,7 @@ struct KFwdFused {
           if (a.S[1]) store4(a.S[1] + n_l * gps + c * w + mb, sv[0][c], sv[1][c], sv[2][c], sv[3][c]);
         }
       }
+      }
       __syncthreads();
       if (a.A[1]) copy_out_rows<T, NT, P>(static_cast<T *>(a.A[1]) + nb * gps, stk, C * w, pitch, out_row0, out_col);
     } else {
@@ -132,41 +138,47 @@ struct KFwdFused {
       const T *Wl = static_cast<const T *>(a.Wop[l]);
       const T *wrow = Wl + (int64_t)(jt0 * 16 + r) * w + 8 * g;
       const T *lrow = SPLIT ? static_cast<const T *>(a.Wlo[l]) + (int64_t)(jt0 * 16 + r) * w + 8 * g : nullptr;
-      const T *brow = stk + (nt * 16 + r) * pitch + 8 * g;
+      const T *brow = stk + (nt0 * 16 + r) * pitch + 8 * g;
       typename M::frag fa[TPW], fl[TPW];
   #pragma unroll
       for (int t = 0; t < TPW; ++t) {
         fa[t] = M::load(wrow + (int64_t)t * 16 * w);
         if constexpr (SPLIT) fl[t] = M::load(lrow + (int64_t)t * 16 * w);
       }
-      f32x4 acc[TPW][C];
+      f32x4 acc[PTW][TPW][C];
   #pragma unroll
-      for (int t = 0; t < TPW; ++t)
+      for (int qt = 0; qt < PTW; ++qt)
   #pragma unroll
-        for (int c = 0; c < C; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < TPW; ++t)
+  #pragma unroll
+          for (int c = 0; c < C; ++c) acc[qt][t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
       for (int k = 0; k < w; k += 32) {
-        typename M::frag fb[C];
-  #pragma unroll
-        for (int c = 0; c < C; ++c) fb[c] = M::load(brow + c * w + k);
         typename M::frag fn[TPW];
         const int kn = k + 32 < w ? k + 32 : k;  // prefetch the next weight fragments
   #pragma unroll
         for (int t = 0; t < TPW; ++t) fn[t] = M::load(wrow + (int64_t)t * 16 * w + kn);
-  #pragma unroll
-        for (int t = 0; t < TPW; ++t)
-  #pragma unroll
-          for (int c = 0; c < C; ++c) M::mma(acc[t][c], fa[t], fb[c]);
-        if constexpr (SPLIT) {
-          typename M::frag fln[TPW];
+        typename M::frag fln[TPW];
+        if constexpr (SPLIT)
   #pragma unroll
           for (int t = 0; t < TPW; ++t) fln[t] = M::load(lrow + (int64_t)t * 16 * w + kn);
   #pragma unroll
+        for (int qt = 0; qt < PTW; ++qt) {
+          typename M::frag fb[C];
+  #pragma unroll
+          for (int c = 0; c < C; ++c) fb[c] = M::load(brow + qt * 16 * pitch + c * w + k);
+  #pragma unroll
           for (int t = 0; t < TPW; ++t)
   #pragma unroll
-            for (int c = 0; c < C; ++c) M::mma(acc[t][c], fl[t], fb[c]);
+            for (int c = 0; c < C; ++c) M::mma(acc[qt][t][c], fa[t], fb[c]);
+          if constexpr (SPLIT)
+  #pragma unroll
+            for (int t = 0; t < TPW; ++t)
+  #pragma unroll
+              for (int c = 0; c < C; ++c) M::mma(acc[qt][t][c], fl[t], fb[c]);
+        }
+        if constexpr (SPLIT)
   #pragma unroll
           for (int t = 0; t < TPW; ++t) fl[t] = fln[t];
-        }
   #pragma unroll
         for (int t = 0; t < TPW; ++t) fa[t] = fn[t];
       }
@@ -174,8 +186,10 @@ struct KFwdFused {
 
       const float *bl = a.b[l];
       float *Sl = a.S[l];
-      const int p = p_l;
-      const int64_t n = n_l;
+  #pragma unroll
+      for (int qt = 0; qt < PTW; ++qt) {
+      const int p = (nt0 + qt) * 16 + r;
+      const int64_t n = nb + p;
   #pragma unroll
       for (int t = 0; t < TPW; ++t) {
         const int mb = (jt0 + t) * 16 + 4 * g;
@@ -184,7 +198,7 @@ struct KFwdFused {
         for (int i = 0; i < 4; ++i) {
           float z[C], act[C], s;
   #pragma unroll
-          for (int c = 0; c < C; ++c) z[c] = acc[t][c][i];
+          for (int c = 0; c < C; ++c) z[c] = acc[qt][t][c][i];
           z[0] += bl[mb + i];
           jet_forward<CH, sizeof(T) == 2>(z, act, s);
   #pragma unroll
@@ -198,6 +212,7 @@ struct KFwdFused {
           store4(stk + p * pitch + c * w + mb, out[0][c], out[1][c], out[2][c], out[3][c]);
           if (Sl) store4(Sl + n * gps + c * w + mb, sv[0][c], sv[1][c], sv[2][c], sv[3][c]);
         }
+      }
       }
       __syncthreads();  // layer l's stack complete in LDS
 
@@ -326,6 +341,16 @@ hipError_t launch_fused_t(const FusedFwdArgs &a, int P, hipStream_t st) {
   // tiles per layer = (P/16) * (w/16); 4 per wave where possible
   const int tiles = (P / 16) * (w / 16);
 #define PJ_FUSED(NWV, TPWV, PV) return launch_body<KFwdFused<PDE, T, NWV, TPWV, PV>>({a}, dim3(grid), lds, st)
+#define PJ_FUSED_P(NWV, TPWV, PV, PTWV) \
+  return launch_body<KFwdFused<PDE, T, NWV, TPWV, PV, PTWV>>({a}, dim3(grid), lds, st)
+  if (P == 64) {  // 16-bit operands: four point tiles per wave
+    if constexpr (sizeof(T) == 2) {
+      if (tiles == 16) PJ_FUSED_P(4, 1, 64, 4);    // w = 64
+      if (tiles == 32) PJ_FUSED_P(4, 2, 64, 4);    // w = 128
+      if (tiles == 64) PJ_FUSED_P(8, 2, 64, 4);    // w = 256
+    }
+    return hipErrorInvalidValue;
+  }
   if (P == 32) {
     if (tiles == 4) PJ_FUSED(4, 1, 32);          // w = 32
     if (tiles == 8) PJ_FUSED(4, 2, 32);          // w = 64
@@ -338,6 +363,7 @@ hipError_t launch_fused_t(const FusedFwdArgs &a, int P, hipStream_t st) {
   if (tiles == 8) PJ_FUSED(4, 2, 16);            // w = 128
   return hipErrorInvalidValue;
 #undef PJ_FUSED
+#undef PJ_FUSED_P
 }
 
 }  // namespace
@@ -346,6 +372,7 @@ bool fused_fwd_fits(int P, int C, int w, int prec) {
   const size_t cap = 144 * 1024;
   const int tiles = (P / 16) * (w / 16);
   if (stack_lds(P, C, w, op_size(prec)) > cap) return false;
+  if (P == 64) return prec != P_FP32 && (tiles == 16 || tiles == 32 || tiles == 64);
   if (P == 32) return tiles == 4 || tiles == 8 || tiles == 16 || tiles == 32;
   if (P == 16) return tiles == 8 || tiles == 16 || tiles == 32;
   return false;

@@ -1334,7 +1334,7 @@ pinn_status pinn_plan_autotune(pinn_plan plan, const pinn_net *net, const pinn_p
   std::vector<pinn_tuning> cand;
   const bool can_fuse = pj::bwd_dw_fused_supported(p->ki.C, p->w, p->prec);
   for (int sp : {std::max(1, s0 / 2), s0, std::min(p->dw_splits_max, 2 * s0)})
-    for (int fp : {0, 16, 32})
+    for (int fp : {0, 16, 32, 64})
     for (int bf : {0, 1}) {
       // 0 (layer-by-layer forward) only when no whole-network tiling exists
       const bool any_fused = pj::fused_fwd_points(p->ki.C, p->w, p->prec) > 0;
