@@ -287,11 +287,16 @@ pinn_status pinn_plan_create_modified(const pinn_modified *arch, const pinn_pde 
  *   bwd_fused   1: hidden-layer weight gradients are accumulated inside the
  *               persistent backward layer kernels where the width allows
  *               (32, 64, 128); 0: separate split-K gradient kernels.  Default:
- *               1 for 16-bit operands where supported, else 0. */
+ *               1 for 16-bit operands where supported, else 0.
+ *   bwd_points  points per workgroup of the wide-layer backward kernel
+ *               (widths >= 256): 0 = 16 (the default); 32 or 64 for 16-bit
+ *               operands with up to 6 channels, each weight fragment then
+ *               serving two or four 16-point tiles. */
 typedef struct {
   int32_t dw_splits;
   int32_t fwd_points;
   int32_t bwd_fused;
+  int32_t bwd_points;
 } pinn_tuning;
 pinn_status pinn_plan_get_tuning(pinn_plan plan, pinn_tuning *tuning);
 pinn_status pinn_plan_set_tuning(pinn_plan plan, const pinn_tuning *tuning);
@@ -310,7 +315,8 @@ pinn_status pinn_plan_autotune(pinn_plan plan, const pinn_net *net, const pinn_p
 
 /* The tuning cache of pinn_plan_autotune: drop every entry; the number of
  * entries; write it to / merge it from a text file (one entry per line:
- * arch kind prec w H nbucket split_mode fwd_points bwd_fused ms).
+ * arch kind prec w H nbucket split_mode fwd_points bwd_fused ms bwd_points;
+ * lines without the last column load with bwd_points 0).
  * PINN_ERR_ARG on an unreadable or malformed file (nothing is merged). */
 pinn_status pinn_tuning_cache_clear(void);
 pinn_status pinn_tuning_cache_size(int64_t *entries);

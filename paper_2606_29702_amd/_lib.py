@@ -76,7 +76,8 @@ class Adam(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("dw_splits", ctypes.c_int32), ("fwd_points", ctypes.c_int32), ("bwd_fused", ctypes.c_int32)]
+    _fields_ = [("dw_splits", ctypes.c_int32), ("fwd_points", ctypes.c_int32), ("bwd_fused", ctypes.c_int32),
+                ("bwd_points", ctypes.c_int32)]
 
 
 def _load():

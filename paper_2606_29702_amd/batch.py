@@ -141,10 +141,12 @@ class PinnBatch:
         return ms.value, n.value
 
     def tuning(self, i: int) -> dict:
-        """The tuning of network i (split count, forward point tile, fused weight gradient)."""
+        """The tuning of network i (split count, forward point tile, fused weight
+        gradient, wide backward point tile)."""
         t = Tuning()
         check(lib.pinn_batch_get_tuning(self.handle, int(i), ctypes.byref(t)))
-        return {"dw_splits": t.dw_splits, "fwd_points": t.fwd_points, "bwd_fused": t.bwd_fused}
+        return {"dw_splits": t.dw_splits, "fwd_points": t.fwd_points, "bwd_fused": t.bwd_fused,
+                "bwd_points": t.bwd_points}
 
     def launches(self) -> int:
         """Grouped launches per step of the current schedule."""

@@ -511,14 +511,16 @@ struct KLayerBwdLds {
 
 // Backward layer kernel for wide layers (w >= 256), where a whole stack tile
 // does not fit in LDS.  A workgroup of NW waves (TPW neuron tiles each)
-// computes a 16-point x 16 NW TPW-neuron output tile.  The neuron tile is the
+// computes a P-point x 16 NW TPW-neuron output tile, P = 16 PTW: every wave
+// takes all PTW point tiles, so each weight fragment it loads feeds PTW x C
+// MFMAs.  The neuron tile is the
 // fastest-varying part of the block index, so the workgroups that share a point
 // tile run next to each other and its stack data is reused from L2.  The contraction (the neurons
 // of the layer below) runs in chunks of KC: each chunk of the Zbar and A_{l-2}
 // tiles ([point][channel][KC], rows padded by 8 elements) is staged through
 // LDS with every thread's loads issued together, then feeds the Abar and z
 // GEMMs.  The epilogue is that of the full-tile kernel.
-template <class CH, class T, int NW, int TPW, int KC, bool TOP, int DOUT, int ZSRC>
+template <class CH, class T, int NW, int TPW, int KC, bool TOP, int DOUT, int ZSRC, int PTW = 1>
 struct KLayerBwdKc {
   static constexpr int NT = NW * 64;
   struct Args {
@@ -527,7 +529,7 @@ struct KLayerBwdKc {
   static __device__ __forceinline__ void run(const Args &a_, VBlock vb) {
     const BwdArgs &args = a_.args;
     using M = Mma<T>;
-    constexpr int C = CH::C, P = 16;
+    constexpr int C = CH::C, P = 16 * PTW;
     constexpr int TILEN = NW * TPW * 16;
     constexpr int PITCH = C * KC + 8;
     constexpr bool ZB = !TOP, AZ = ZSRC == Z_FROM_GEMM;
@@ -551,14 +553,16 @@ struct KLayerBwdKc {
     const T *a_src = static_cast<const T *>(args.A_prev) + nb * ps;
     const T *WT = static_cast<const T *>(args.WT);
     const T *Wz = static_cast<const T *>(args.Wz);
-    f32x4 acc_a[TPW][C], acc_z[TPW][C];
+    f32x4 acc_a[PTW][TPW][C], acc_z[PTW][TPW][C];
   #pragma unroll
-    for (int t = 0; t < TPW; ++t)
+    for (int q = 0; q < PTW; ++q)
   #pragma unroll
-      for (int c = 0; c < C; ++c) {
-        acc_a[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-        acc_z[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-      }
+      for (int t = 0; t < TPW; ++t)
+  #pragma unroll
+        for (int c = 0; c < C; ++c) {
+          acc_a[q][t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+          acc_z[q][t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
     for (int k0 = 0; k0 < w; k0 += KC) {
       {
         uint4 vb[PER_T], va[PER_T];
@@ -586,31 +590,41 @@ struct KLayerBwdKc {
   #pragma unroll
       for (int kk = 0; kk < KC; kk += 32) {
         if constexpr (ZB) {
-          typename M::frag fb[C], fa[TPW];
-  #pragma unroll
-          for (int c = 0; c < C; ++c) fb[c] = M::load(lds_b + r * PITCH + c * KC + kk + 8 * g);
+          typename M::frag fa[TPW];
   #pragma unroll
           for (int t = 0; t < TPW; ++t) fa[t] = M::load(WT + (int64_t)((jt0 + t) * 16 + r) * w + k0 + kk + 8 * g);
   #pragma unroll
-          for (int t = 0; t < TPW; ++t)
+          for (int q = 0; q < PTW; ++q) {
+            typename M::frag fb[C];
   #pragma unroll
-            for (int c = 0; c < C; ++c) M::mma(acc_a[t][c], fa[t], fb[c]);
+            for (int c = 0; c < C; ++c) fb[c] = M::load(lds_b + (q * 16 + r) * PITCH + c * KC + kk + 8 * g);
+  #pragma unroll
+            for (int t = 0; t < TPW; ++t)
+  #pragma unroll
+              for (int c = 0; c < C; ++c) M::mma(acc_a[q][t][c], fa[t], fb[c]);
+          }
         }
         if constexpr (AZ) {
-          typename M::frag fb[C], fa[TPW];
-  #pragma unroll
-          for (int c = 0; c < C; ++c) fb[c] = M::load(lds_a + r * PITCH + c * KC + kk + 8 * g);
+          typename M::frag fa[TPW];
   #pragma unroll
           for (int t = 0; t < TPW; ++t) fa[t] = M::load(Wz + (int64_t)((jt0 + t) * 16 + r) * w + k0 + kk + 8 * g);
   #pragma unroll
-          for (int t = 0; t < TPW; ++t)
+          for (int q = 0; q < PTW; ++q) {
+            typename M::frag fb[C];
   #pragma unroll
-            for (int c = 0; c < C; ++c) M::mma(acc_z[t][c], fa[t], fb[c]);
+            for (int c = 0; c < C; ++c) fb[c] = M::load(lds_a + (q * 16 + r) * PITCH + c * KC + kk + 8 * g);
+  #pragma unroll
+            for (int t = 0; t < TPW; ++t)
+  #pragma unroll
+              for (int c = 0; c < C; ++c) M::mma(acc_z[q][t][c], fa[t], fb[c]);
+          }
         }
       }
       __syncthreads();  // the chunk buffers are restaged next
     }
-    bwd_epilogue<CH, T, TPW, TOP, DOUT, ZSRC>(args, acc_a, acc_z, nb + r, jt0, ptile, lane);
+  #pragma unroll
+    for (int q = 0; q < PTW; ++q)
+      bwd_epilogue<CH, T, TPW, TOP, DOUT, ZSRC>(args, acc_a[q], acc_z[q], nb + q * 16 + r, jt0, ptile * PTW + q, lane);
   }
 };
 
@@ -768,7 +782,7 @@ inline BwdLdsCfg bwd_lds_cfg(int C, int w, int osz, bool two_tiles) {
 }
 
 template <class CH, class T, bool TOP, int DOUT, int ZSRC>
-hipError_t launch_bwd_t(const BwdArgs &a, int64_t N_pad, hipStream_t st) {
+hipError_t launch_bwd_t(const BwdArgs &a, int64_t N_pad, int points, hipStream_t st) {
   const int w = a.w;
   // wide layers: neuron-tiled, contraction staged through LDS in chunks
   // 16-bit operands with 8 channels (one full wave load per point and tile):
@@ -781,8 +795,23 @@ hipError_t launch_bwd_t(const BwdArgs &a, int64_t N_pad, hipStream_t st) {
     }
   }
   if (w >= 256 && w % 128 == 0) {
-    constexpr int KC = sizeof(T) == 2 ? 128 : 64;
     const int tiles = (TOP ? 0 : 1) + (ZSRC == Z_FROM_GEMM ? 1 : 0);
+    // points per workgroup (wide_bwd_points): 32 or 64 share each weight
+    // fragment across two or four point tiles (16-bit operands, up to 6
+    // channels); chunks of 64 neurons at 64 points keep the LDS in bounds
+    if constexpr (sizeof(T) == 2 && CH::C <= 6) {
+      if (points == 32) {
+        const size_t lds = (size_t)tiles * 32 * (CH::C * 128 + 8) * sizeof(T);
+        const dim3 grid((unsigned)((N_pad / 32) * (w / 128)));
+        return launch_body<KLayerBwdKc<CH, T, 8, 1, 128, TOP, DOUT, ZSRC, 2>>({a}, grid, lds, st);
+      }
+      if (points == 64) {
+        const size_t lds = (size_t)tiles * 64 * (CH::C * 64 + 8) * sizeof(T);
+        const dim3 grid((unsigned)((N_pad / 64) * (w / 128)));
+        return launch_body<KLayerBwdKc<CH, T, 8, 1, 64, TOP, DOUT, ZSRC, 4>>({a}, grid, lds, st);
+      }
+    }
+    constexpr int KC = sizeof(T) == 2 ? 128 : 64;
     const size_t lds = (size_t)tiles * 16 * (CH::C * KC + 8) * sizeof(T);
     const dim3 grid((unsigned)((N_pad / 16) * (w / 128)));
     return launch_body<KLayerBwdKc<CH, T, 8, 1, KC, TOP, DOUT, ZSRC>>({a}, grid, lds, st);
@@ -816,17 +845,17 @@ hipError_t launch_bwd_t(const BwdArgs &a, int64_t N_pad, hipStream_t st) {
 }
 
 template <class PDE, class T>
-hipError_t launch_bwd_kind(const BwdArgs &a, bool top, int zsrc, int64_t N_pad, hipStream_t st) {
+hipError_t launch_bwd_kind(const BwdArgs &a, bool top, int zsrc, int64_t N_pad, int points, hipStream_t st) {
   using CH = typename PDE::CH;
   constexpr int DO = PDE::DOUT;
   if (top) {
-    if (zsrc == Z_FROM_S) return launch_bwd_t<CH, T, true, DO, Z_FROM_S>(a, N_pad, st);
-    if (zsrc == Z_FROM_GEMM) return launch_bwd_t<CH, T, true, DO, Z_FROM_GEMM>(a, N_pad, st);
-    return launch_bwd_t<CH, T, true, DO, Z_FROM_X>(a, N_pad, st);
+    if (zsrc == Z_FROM_S) return launch_bwd_t<CH, T, true, DO, Z_FROM_S>(a, N_pad, points, st);
+    if (zsrc == Z_FROM_GEMM) return launch_bwd_t<CH, T, true, DO, Z_FROM_GEMM>(a, N_pad, points, st);
+    return launch_bwd_t<CH, T, true, DO, Z_FROM_X>(a, N_pad, points, st);
   }
-  if (zsrc == Z_FROM_S) return launch_bwd_t<CH, T, false, DO, Z_FROM_S>(a, N_pad, st);
-  if (zsrc == Z_FROM_GEMM) return launch_bwd_t<CH, T, false, DO, Z_FROM_GEMM>(a, N_pad, st);
-  return launch_bwd_t<CH, T, false, DO, Z_FROM_X>(a, N_pad, st);
+  if (zsrc == Z_FROM_S) return launch_bwd_t<CH, T, false, DO, Z_FROM_S>(a, N_pad, points, st);
+  if (zsrc == Z_FROM_GEMM) return launch_bwd_t<CH, T, false, DO, Z_FROM_GEMM>(a, N_pad, points, st);
+  return launch_bwd_t<CH, T, false, DO, Z_FROM_X>(a, N_pad, points, st);
 }
 
 template <class F>
@@ -860,6 +889,11 @@ hipError_t launch_layer_fwd(int kind, int prec, const void *A_in, const void *Wo
   });
 }
 
+bool wide_bwd_points_supported(int points, int C, int w, int prec) {
+  if (points == 16) return w >= 256 && w % 128 == 0;
+  return (points == 32 || points == 64) && prec != P_FP32 && C <= 6 && w >= 256 && w % 128 == 0;
+}
+
 bool seed_grad_fused_supported(int C, int w, int prec) {
   const int osz = prec == P_FP32 ? 4 : 2;
   return (w >= 256 && w % 128 == 0) || (bwd_lds_cfg(C, w, osz, false).P > 0 && C * w * osz % 16 == 0);
@@ -871,7 +905,7 @@ hipError_t launch_layer_bwd(int kind, int prec, const LayerBwd &L, int64_t N_pad
             L.seed_part};
   const int zsrc = L.S_in ? Z_FROM_S : (L.A_prev ? Z_FROM_GEMM : Z_FROM_X);
   return dispatch(kind, prec, [&](auto pde, auto tv) {
-    return launch_bwd_kind<decltype(pde), decltype(tv)>(a, L.top, zsrc, N_pad, st);
+    return launch_bwd_kind<decltype(pde), decltype(tv)>(a, L.top, zsrc, N_pad, L.points, st);
   });
 }
 

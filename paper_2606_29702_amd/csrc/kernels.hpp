@@ -73,7 +73,11 @@ struct LayerBwd {
   // layer's weight-gradient partials seed_part[tile][w*DIN + w] (dW_1
   // row-major, then db_1; one partial per 16-point tile) instead of Zb_out
   float *seed_part = nullptr;
+  // points per workgroup of the wide-layer kernel (w >= 256): 16 (0: the
+  // default), or 32 / 64 where wide_bwd_points_supported
+  int points = 0;
 };
+bool wide_bwd_points_supported(int points, int C, int w, int prec);
 hipError_t launch_layer_bwd(int kind, int prec, const LayerBwd &L, int64_t N_pad, hipStream_t st);
 // Whether launch_layer_bwd can produce seed_part for this shape.
 bool seed_grad_fused_supported(int C, int w, int prec);

@@ -133,6 +133,7 @@ struct pinn_plan_s {
   int dw_splits_max = 1;   // partial buffer capacity (autotune candidates stay below it)
   int fwd_points = 0;      // fused forward points per workgroup; 0 = largest that fits
   int bwd_fused = 0;       // weight gradients inside the backward layer kernels when supported
+  int bwd_points = 0;      // points per workgroup of the wide backward kernel; 0 = default (16)
   std::vector<void *> allocs;
   size_t saved_bytes = 0, ws_bytes = 0;
   // Workspace source: separate hipMalloc allocations (the default), consecutive
@@ -863,6 +864,12 @@ pinn_status mod_backward(pinn_plan p, const pinn_net *net, const float *x, int64
 
 // The backward pass for the cotangent rbar = r_bar + lb 2 r / N, with lb =
 // *loss_bar, or lb = 1 when both are null (see pinn_jet_backward_cot).
+// The layer description with the plan's wide-kernel tiling.
+static pj::LayerBwd with_points(pj::LayerBwd B, pinn_plan p) {
+  B.points = p->bwd_points;
+  return B;
+}
+
 static pinn_status backward_impl(pinn_plan plan, const pinn_net *net, const pinn_pde *pde, const float *x,
                                  int64_t N, const float *r_bar, const float *loss_bar, float *const *dW,
                                  float *const *db, double *const *dW_f64, double *const *db_f64,
@@ -1004,7 +1011,7 @@ static pinn_status backward_impl(pinn_plan plan, const pinn_net *net, const pinn
     B.seed_part = seed_fused ? p->part : nullptr;
     rs = zsrc(B, 1);
     if (rs) return rs;
-    e = timed(p, PINN_K_LAYER_BWD, s, [&] { return pj::launch_layer_bwd(p->kind, p->prec, B, npad, s); });
+    e = timed(p, PINN_K_LAYER_BWD, s, [&] { return pj::launch_layer_bwd(p->kind, p->prec, with_points(B, p), npad, s); });
     if (e) return hip_fail(e, "hidden adjoint");
   } else {
   // Output layer: ubar, then zbar of layer H, then dW_L, db_L.
@@ -1020,7 +1027,7 @@ static pinn_status backward_impl(pinn_plan plan, const pinn_net *net, const pinn
     B.Zb_out = p->Zb[H % 2];
     rs = zsrc(B, H);
     if (rs) return rs;
-    e = timed(p, PINN_K_OUT_BWD, s, [&] { return pj::launch_layer_bwd(p->kind, p->prec, B, npad, s); });
+    e = timed(p, PINN_K_OUT_BWD, s, [&] { return pj::launch_layer_bwd(p->kind, p->prec, with_points(B, p), npad, s); });
     if (e) return hip_fail(e, "last hidden adjoint");
   }
   const void *AH = nullptr;
@@ -1053,7 +1060,7 @@ static pinn_status backward_impl(pinn_plan plan, const pinn_net *net, const pinn
     B.seed_part = (l == 2 && seed_fused) ? p->part : nullptr;
     rs = zsrc(B, l - 1);
     if (rs) return rs;
-    e = timed(p, PINN_K_LAYER_BWD, s, [&] { return pj::launch_layer_bwd(p->kind, p->prec, B, npad, s); });
+    e = timed(p, PINN_K_LAYER_BWD, s, [&] { return pj::launch_layer_bwd(p->kind, p->prec, with_points(B, p), npad, s); });
     if (e) return hip_fail(e, "hidden adjoint");
   }
   }
@@ -1221,6 +1228,7 @@ pinn_status pinn_plan_get_tuning(pinn_plan plan, pinn_tuning *t) {
   t->dw_splits = plan->dw_splits;
   t->fwd_points = plan->fwd_points;
   t->bwd_fused = plan->bwd_fused;
+  t->bwd_points = plan->bwd_points;
   return PINN_OK;
 }
 
@@ -1232,9 +1240,12 @@ pinn_status pinn_plan_set_tuning(pinn_plan plan, const pinn_tuning *t) {
   if (t->fwd_points != 0 && !pj::fused_fwd_fits(t->fwd_points, plan->ki.C, plan->w, plan->prec))
     return fail(PINN_ERR_ARG, "fwd_points = %d has no fused forward tiling at this width", t->fwd_points);
   if (t->bwd_fused != 0 && t->bwd_fused != 1) return fail(PINN_ERR_ARG, "bwd_fused must be 0 or 1");
+  if (t->bwd_points != 0 && !pj::wide_bwd_points_supported(t->bwd_points, plan->ki.C, plan->w, plan->prec))
+    return fail(PINN_ERR_ARG, "bwd_points = %d has no wide backward tiling at this width", t->bwd_points);
   plan->dw_splits = t->dw_splits;
   plan->fwd_points = t->fwd_points;
   plan->bwd_fused = t->bwd_fused;
+  plan->bwd_points = t->bwd_points;
   plan->have_state = false;
   return PINN_OK;
 }
@@ -1257,6 +1268,7 @@ struct TuneVal {
   int split_mode;  // 0: half the default split count, 1: the default, 2: twice
   int fwd_points, bwd_fused;
   double ms;
+  int bwd_points;
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune;
@@ -1299,8 +1311,10 @@ pinn_status pinn_plan_autotune(pinn_plan plan, const pinn_net *net, const pinn_p
       p->dw_splits = std::max(1, std::min(sp, p->dw_splits_max));
       p->fwd_points = pj::fused_fwd_fits(it->second.fwd_points, p->ki.C, p->w, p->prec) ? it->second.fwd_points : 0;
       p->bwd_fused = it->second.bwd_fused && pj::bwd_dw_fused_supported(p->ki.C, p->w, p->prec) ? 1 : 0;
+      p->bwd_points =
+          pj::wide_bwd_points_supported(it->second.bwd_points, p->ki.C, p->w, p->prec) ? it->second.bwd_points : 0;
       p->have_state = false;
-      if (best) *best = pinn_tuning{p->dw_splits, p->fwd_points, p->bwd_fused};
+      if (best) *best = pinn_tuning{p->dw_splits, p->fwd_points, p->bwd_fused, p->bwd_points};
       if (best_ms) *best_ms = it->second.ms;
       return PINN_OK;
     }
@@ -1329,21 +1343,24 @@ pinn_status pinn_plan_autotune(pinn_plan plan, const pinn_net *net, const pinn_p
     cleanup();
     return hip_fail(e, "autotune setup");
   }
-  const pinn_tuning orig{p->dw_splits, p->fwd_points, p->bwd_fused};
+  const pinn_tuning orig{p->dw_splits, p->fwd_points, p->bwd_fused, p->bwd_points};
   const int s0 = dw_splits_for(round_up(N, pj::kPointTile), p->ki.C, p->w);
   std::vector<pinn_tuning> cand;
   const bool can_fuse = pj::bwd_dw_fused_supported(p->ki.C, p->w, p->prec);
   for (int sp : {std::max(1, s0 / 2), s0, std::min(p->dw_splits_max, 2 * s0)})
     for (int fp : {0, 16, 32, 64})
-    for (int bf : {0, 1}) {
+    for (int bf : {0, 1})
+    for (int bp : {0, 32, 64}) {
       // 0 (layer-by-layer forward) only when no whole-network tiling exists
       const bool any_fused = pj::fused_fwd_points(p->ki.C, p->w, p->prec) > 0;
       if (fp == 0 ? any_fused : !pj::fused_fwd_fits(fp, p->ki.C, p->w, p->prec)) continue;
       if (bf == 1 && !can_fuse) continue;
-      pinn_tuning t{sp, fp, bf};
+      if (bp != 0 && !pj::wide_bwd_points_supported(bp, p->ki.C, p->w, p->prec)) continue;
+      pinn_tuning t{sp, fp, bf, bp};
       bool dup = false;
       for (auto &c : cand)
-        dup = dup || (c.dw_splits == t.dw_splits && c.fwd_points == t.fwd_points && c.bwd_fused == t.bwd_fused);
+        dup = dup || (c.dw_splits == t.dw_splits && c.fwd_points == t.fwd_points && c.bwd_fused == t.bwd_fused &&
+                      c.bwd_points == t.bwd_points);
       if (!dup) cand.push_back(t);
     }
   // two interleaved timing rounds; a candidate's time is its faster round
@@ -1354,6 +1371,7 @@ pinn_status pinn_plan_autotune(pinn_plan plan, const pinn_net *net, const pinn_p
       p->dw_splits = c.dw_splits;
       p->fwd_points = c.fwd_points;
       p->bwd_fused = c.bwd_fused;
+      p->bwd_points = c.bwd_points;
       for (int it = -1; it < reps && st == PINN_OK; ++it) {
         if (it == 0) e = hipEventRecord(t0, s);
         st = pinn_jet_residual(p, net, pde, x, N, nullptr, nullptr, nullptr, nullptr, stream);
@@ -1382,10 +1400,12 @@ pinn_status pinn_plan_autotune(pinn_plan plan, const pinn_net *net, const pinn_p
   p->dw_splits = bt.dw_splits;
   p->fwd_points = bt.fwd_points;
   p->bwd_fused = bt.bwd_fused;
+  p->bwd_points = bt.bwd_points;
   p->have_state = false;
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    g_tune[tk] = TuneVal{bt.dw_splits < s0 ? 0 : (bt.dw_splits == s0 ? 1 : 2), bt.fwd_points, bt.bwd_fused, bms};
+    g_tune[tk] = TuneVal{bt.dw_splits < s0 ? 0 : (bt.dw_splits == s0 ? 1 : 2), bt.fwd_points, bt.bwd_fused, bms,
+                         bt.bwd_points};
   }
   if (best) *best = bt;
   if (best_ms) *best_ms = bms;
@@ -1413,11 +1433,11 @@ pinn_status pinn_tuning_cache_save(const char *path) {
   std::lock_guard<std::mutex> lock(g_tune_mu);
   FILE *f = fopen(path, "w");
   if (!f) return fail(PINN_ERR_ARG, "cannot write %s", path);
-  fprintf(f, "# pinn tuning cache v1: arch kind prec w H nbucket split_mode fwd_points bwd_fused ms\n");
+  fprintf(f, "# pinn tuning cache v2: arch kind prec w H nbucket split_mode fwd_points bwd_fused ms bwd_points\n");
   for (const auto &kv : g_tune)
-    fprintf(f, "%s %d %d %d %d %d %d %d %d %.6g\n", kv.first.arch.c_str(), kv.first.kind, kv.first.prec,
+    fprintf(f, "%s %d %d %d %d %d %d %d %d %.6g %d\n", kv.first.arch.c_str(), kv.first.kind, kv.first.prec,
             kv.first.w, kv.first.H, kv.first.nbucket, kv.second.split_mode, kv.second.fwd_points,
-            kv.second.bwd_fused, kv.second.ms);
+            kv.second.bwd_fused, kv.second.ms, kv.second.bwd_points);
   const bool ok = fclose(f) == 0;
   return ok ? PINN_OK : fail(PINN_ERR_ARG, "cannot write %s", path);
 }
@@ -1436,9 +1456,11 @@ pinn_status pinn_tuning_cache_load(const char *path) {
     char arch[64];
     TuneKey k;
     TuneVal v;
-    if (sscanf(line, "%63s %d %d %d %d %d %d %d %d %lf", arch, &k.kind, &k.prec, &k.w, &k.H, &k.nbucket,
-               &v.split_mode, &v.fwd_points, &v.bwd_fused, &v.ms) != 10 ||
-        v.split_mode < 0 || v.split_mode > 2 || (v.bwd_fused != 0 && v.bwd_fused != 1)) {
+    v.bwd_points = 0;  // v1 lines have no wide-backward column
+    const int got_n = sscanf(line, "%63s %d %d %d %d %d %d %d %d %lf %d", arch, &k.kind, &k.prec, &k.w, &k.H,
+                             &k.nbucket, &v.split_mode, &v.fwd_points, &v.bwd_fused, &v.ms, &v.bwd_points);
+    if ((got_n != 10 && got_n != 11) || v.split_mode < 0 || v.split_mode > 2 || (v.bwd_fused != 0 && v.bwd_fused != 1) ||
+        (v.bwd_points != 0 && v.bwd_points != 32 && v.bwd_points != 64)) {
       fclose(f);
       return fail(PINN_ERR_ARG, "%s:%d: malformed tuning cache entry", path, lineno);
     }
@@ -1997,6 +2019,7 @@ pinn_status batch_check(pinn_batch b, const pinn_net *nets, const pinn_pde *pdes
     // the tuning selects the kernels
     key.push_back(reinterpret_cast<const void *>((intptr_t)b->plans[i]->dw_splits));
     key.push_back(reinterpret_cast<const void *>((intptr_t)(b->plans[i]->fwd_points * 2 + b->plans[i]->bwd_fused)));
+    key.push_back(reinterpret_cast<const void *>((intptr_t)b->plans[i]->bwd_points));
   }
   return PINN_OK;
 }

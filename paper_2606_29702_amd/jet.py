@@ -114,10 +114,11 @@ class PinnPlan:
     def tuning(self) -> dict:
         t = Tuning()
         check(lib.pinn_plan_get_tuning(self.handle, ctypes.byref(t)))
-        return {"dw_splits": t.dw_splits, "fwd_points": t.fwd_points, "bwd_fused": t.bwd_fused}
+        return {"dw_splits": t.dw_splits, "fwd_points": t.fwd_points, "bwd_fused": t.bwd_fused,
+                "bwd_points": t.bwd_points}
 
-    def set_tuning(self, dw_splits: int, fwd_points: int = 0, bwd_fused: int = 1) -> None:
-        t = Tuning(int(dw_splits), int(fwd_points), int(bwd_fused))
+    def set_tuning(self, dw_splits: int, fwd_points: int = 0, bwd_fused: int = 1, bwd_points: int = 0) -> None:
+        t = Tuning(int(dw_splits), int(fwd_points), int(bwd_fused), int(bwd_points))
         check(lib.pinn_plan_set_tuning(self.handle, ctypes.byref(t)))
 
     def autotune(self, params, x: torch.Tensor, reps: int = 3) -> Tuple[dict, float]:
@@ -128,7 +129,8 @@ class PinnPlan:
         check(lib.pinn_plan_autotune(self.handle, ctypes.byref(nv.net), ctypes.byref(_pde(self.pde, self.coef)),
                                      ctypes.c_void_p(x.data_ptr()), x.shape[0], int(reps), ctypes.byref(t),
                                      ctypes.byref(ms), _stream()))
-        return {"dw_splits": t.dw_splits, "fwd_points": t.fwd_points, "bwd_fused": t.bwd_fused}, ms.value
+        return {"dw_splits": t.dw_splits, "fwd_points": t.fwd_points, "bwd_fused": t.bwd_fused,
+                "bwd_points": t.bwd_points}, ms.value
 
     def profile(self, kernel_class: str) -> None:
         """Start timing launches of one kernel class ('off' to stop)."""

@@ -148,17 +148,21 @@ def test_tuning_cache_file_round_trip(tmp_path):
     n = ctypes.c_int64(-1)
     assert lib.pinn_tuning_cache_size(ctypes.byref(n)) == 0 and n.value == 0
     good = tmp_path / "tune.txt"
-    good.write_text("# header\ngfx950 2 1 128 6 16 1 16 1 0.7\ngfx950 1 1 256 8 15 2 32 0 3.25\n")
+    # a line of the first format (no wide-backward column) and one of the current
+    good.write_text("# header\ngfx950 2 1 128 6 16 1 16 1 0.7\ngfx950 1 1 256 8 15 2 32 0 3.25 64\n")
     assert lib.pinn_tuning_cache_load(str(good).encode()) == 0
     assert lib.pinn_tuning_cache_size(ctypes.byref(n)) == 0 and n.value == 2
     out = tmp_path / "out.txt"
     assert lib.pinn_tuning_cache_save(str(out).encode()) == 0
     lines = [l for l in out.read_text().splitlines() if not l.startswith("#")]
     assert sorted(l.split()[:9] for l in lines) == sorted(l.split()[:9] for l in good.read_text().splitlines()[1:])
-    bad = tmp_path / "bad.txt"
-    bad.write_text("gfx950 2 1 128 6 16 7 16 1 0.7\n")  # split mode 7 does not exist
-    assert lib.pinn_tuning_cache_load(str(bad).encode()) == -1
-    assert "malformed" in lib.pinn_last_error().decode()
+    assert sorted(l.split()[10] for l in lines) == ["0", "64"]
+    for bad_line in ("gfx950 2 1 128 6 16 7 16 1 0.7\n",      # split mode 7 does not exist
+                     "gfx950 2 1 128 6 16 1 16 1 0.7 48\n"):  # no 48-point wide backward tiling
+        bad = tmp_path / "bad.txt"
+        bad.write_text(bad_line)
+        assert lib.pinn_tuning_cache_load(str(bad).encode()) == -1
+        assert "malformed" in lib.pinn_last_error().decode()
     assert lib.pinn_tuning_cache_size(ctypes.byref(n)) == 0 and n.value == 2
     assert lib.pinn_tuning_cache_load(str(tmp_path / "missing.txt").encode()) == -1
     assert lib.pinn_tuning_cache_clear() == 0

@@ -550,3 +550,39 @@ def test_forward_tilings_agree_bitwise(lib, pde, dims, prec):
     assert rel(outs[64][0], orc.r) <= LOWP_TOL[prec]["r"]
     assert rel(outs[64][3], orc.grad) <= LOWP_TOL[prec]["grad"]
     plan.close()
+
+
+@pytest.mark.parametrize("pde,dims,prec", [("ks", [2, 256, 256, 256, 1], "bf16"),
+                                           ("burgers", [2, 256, 256, 256, 256, 1], "bf16"),
+                                           ("burgers", [2, 256, 256, 256, 1], "fp16")])
+def test_wide_backward_tilings_agree(lib, pde, dims, prec):
+    """16, 32 and 64 points per workgroup of the wide-layer backward kernel
+    (two or four point tiles sharing every weight fragment): the same
+    per-element arithmetic, so the gradients agree bit for bit with BF16
+    operands and to FP16 rounding with FP16 ones; the 64-point tiling against
+    the oracle at the 16-bit bars."""
+    N = 1000
+    prob = pi.make_problem(pde, N=N, seed=14, bias_std=0.2, dims=dims)
+    if pde == "ks":
+        prob.x = np.stack([np.random.default_rng(3).uniform(-1.5, 1.5, N),
+                           np.random.default_rng(4).uniform(0, 1, N)], 1).astype(np.float32)
+    params = dev_params(prob.params)
+    x = torch.tensor(prob.x, device="cuda")
+    plan = lib.PinnPlan(dims, pde, N, precision=prec, coef=prob.coef)
+    t = plan.tuning()
+    grads = {}
+    for bp in (0, 32, 64):
+        plan.set_tuning(t["dw_splits"], t["fwd_points"], t["bwd_fused"], bp)
+        plan.residual(params, x)
+        grads[bp] = flat(plan.backward(params, x))
+    torch.cuda.synchronize()
+    for bp in (32, 64):
+        if prec == "fp16":
+            assert rel(grads[bp], grads[0]) <= 1e-3, bp
+        else:
+            assert np.array_equal(grads[bp], grads[0]), bp
+    orc = oracle.evaluate(prob.params, prob.x, prob.channels, pde, prob.coef)
+    assert rel(grads[64], orc.grad) <= LOWP_TOL[prec]["grad"]
+    with pytest.raises(lib.PinnError):
+        plan.set_tuning(t["dw_splits"], t["fwd_points"], t["bwd_fused"], 48)
+    plan.close()
