@@ -167,3 +167,21 @@ def test_tuning_cache_file_round_trip(tmp_path):
     assert lib.pinn_tuning_cache_load(str(tmp_path / "missing.txt").encode()) == -1
     assert lib.pinn_tuning_cache_clear() == 0
     assert lib.pinn_tuning_cache_size(ctypes.byref(n)) == 0 and n.value == 0
+
+
+def test_adam_chain_runs():
+    """pinn_adam_step takes a chain of layer sizes; the binding splits a
+    parameter list into chains: one for a plain MLP, three for the modified
+    MLP (U and V encoders, then the chain from the embedding)."""
+    from paper_2606_29702_amd.optim import chain_runs
+    plain = [(64, 2)] + [(64, 64)] * 5 + [(1, 64)]
+    assert chain_runs(plain) == [(0, 7)]
+    modified = [(64, 3), (64, 3), (64, 3)] + [(64, 64)] * 5 + [(1, 64)]
+    assert chain_runs(modified) == [(0, 1), (1, 2), (2, 9)]
+    # every run is a chain and the runs cover every layer once
+    for shapes in (plain, modified):
+        covered = []
+        for a, e in chain_runs(shapes):
+            covered += list(range(a, e))
+            assert all(shapes[l][1] == shapes[l - 1][0] for l in range(a + 1, e))
+        assert covered == list(range(len(shapes)))
