@@ -164,10 +164,11 @@ def time_batch(batch, params, xs, steps, warmup):
     return (time.perf_counter() - t0) * 1e3 / steps
 
 
-def ensemble_headline(ens, params, xs, prec, steps, warmup, runs, replays):
+def ensemble_headline(ens, params, xs, prec, steps, warmup, runs, replays, counter_window=0):
     """The grouped BF16 ensemble step: autotuned, then exactly `steps` timed graph
     replays; the kernel class with the most time is then timed with events
     over `steps` eager steps of the same schedule."""
+    import torch
     from paper_2606_29702_amd import PinnBatch
     batch = PinnBatch([m.dims for m in ens], "burgers", [(m.nu,) for m in ens], [m.N for m in ens], precision=prec)
     t0 = time.perf_counter()
@@ -198,6 +199,17 @@ def ensemble_headline(ens, params, xs, prec, steps, warmup, runs, replays):
     tunings = [batch.tuning(i) for i in range(len(ens))]
     launches = batch.launches()
     lanes = batch.config()
+    if counter_window:
+        # the last GPU work of the run: `counter_window` eager steps on one
+        # stream, whose dispatches a profiler run maps to kernel classes
+        batch.configure(1, use_graph=False, per_network=False)
+        batch.step(params, xs)
+        torch.cuda.synchronize()
+        classes = batch.schedule_classes()
+        for _ in range(counter_window):
+            batch.step(params, xs)
+        torch.cuda.synchronize()
+        log("counter window: " + json.dumps({"steps": counter_window, "classes": classes}))
     batch.close()
     flops = dict.fromkeys(ALL_CLASSES, 0.0)
     for m, t in zip(ens, tunings):
@@ -655,6 +667,8 @@ def main():
     ap.add_argument("--save-cap-gib", type=float, default=0.0, help="saved-state cap of a single-network workload")
     ap.add_argument("--tuning", default=None, help="dw_splits,fwd_points,bwd_fused for a single-network workload")
     ap.add_argument("--copy-probe-mib", type=int, default=0, help="only run a plain device copy of this size")
+    ap.add_argument("--counter-window", type=int, default=0,
+                    help="end the ensemble measurement with this many eager one-stream steps (counter profiles)")
     ap.add_argument("--training", default="burgers,ns,ks",
                     help="paper training runs (1000 Adam steps on the composite loss): burgers, ns, ks or ''")
     ap.add_argument("--training-steps", type=int, default=1000)
@@ -699,7 +713,8 @@ def main():
     ens, params, xs = ensemble_inputs()
     total_N = sum(m.N for m in ens)
     log(f"ensemble: {len(ens)} networks, {total_N} points, precision {prec}")
-    head = ensemble_headline(ens, params, xs, prec, args.steps, args.warmup, args.runs, args.replays)
+    head = ensemble_headline(ens, params, xs, prec, args.steps, args.warmup, args.runs, args.replays,
+                             args.counter_window)
     ms = head["ms"]
     value = total_N / (ms * 1e-3)
     dom = head["dominant"]
@@ -736,6 +751,12 @@ def main():
         log(f"fp32 sequential: {f32_ms:.3f} ms/step (batched {prec} is {f32_ms / ms:.2f}x)")
         out["accuracy_vs_oracle"] = ensemble_accuracy(ens, prec)
         log(f"accuracy: {out['accuracy_vs_oracle']}")
+        if prec != "fp16":  # the other 16-bit operand type, same MFMA peak, no split weights
+            f16 = ensemble_headline(ens, params, xs, "fp16", max(5, args.steps // 2), 2, 1, 20)
+            out["ensemble_fp16"] = {"ms_per_step": round(f16["ms"], 4),
+                                    "value": round(total_N / (f16["ms"] * 1e-3), 1), "unit": "pts/s",
+                                    "accuracy_vs_oracle": ensemble_accuracy(ens, "fp16")}
+            log(f"fp16 grouped ensemble: {out['ensemble_fp16']}")
 
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)

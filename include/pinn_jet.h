@@ -74,9 +74,12 @@ enum {
  *                    mixed derivative (Eq. 3 with i != j), not one of the paper's
  *                    problems: r = u_xx + 2 c u_xy + u_yy
  *                    channels: u, u_x, u_y, u_xx, u_yy, u_xy
- *   PINN_BURGERS_BC  inputs (x, t), output u, no coefficient: the Burgers initial
- *                    and boundary data term at points on t = 0 and x = +-1,
- *                    r = u + sin(pi x) (u(x, 0) = -sin(pi x), u(+-1, t) = 0)
+ *   PINN_BURGERS_BC  inputs (x, t), output u, no coefficient: a value-channel
+ *                    test operator, r = u + sin(pi x), the Dirichlet data of the
+ *                    [-1, 1] Burgers workload at points on t = 0 and x = +-1.  It
+ *                    is not the paper's Burgers loss, whose initial and periodic
+ *                    boundary terms (u and u_x) are composite-loss segments of
+ *                    the PINN_BURGERS_1D kind (pinn_jet_loss)
  *                    channels: u                                                   */
 enum { PINN_BURGERS_1D = 1, PINN_NS2D_STEADY = 2, PINN_KS_1D = 3, PINN_HEAT_3D = 4, PINN_ANISO_2D = 5,
        PINN_BURGERS_BC = 6 };
@@ -288,10 +291,11 @@ pinn_status pinn_plan_create_modified(const pinn_modified *arch, const pinn_pde 
  *               persistent backward layer kernels where the width allows
  *               (32, 64, 128); 0: separate split-K gradient kernels.  Default:
  *               1 for 16-bit operands where supported, else 0.
- *   bwd_points  points per workgroup of the wide-layer backward kernel
- *               (widths >= 256): 0 = 16 (the default); 32 or 64 for 16-bit
- *               operands with up to 6 channels, each weight fragment then
- *               serving two or four 16-point tiles. */
+ *   bwd_points  the wide-layer backward kernel (widths >= 256, 16-bit
+ *               operands): 0 = the default; 16 = 16 points per workgroup with
+ *               the LDS chunks double-buffered (up to 8 channels); 32 or 64
+ *               points per workgroup (up to 6 channels), each weight fragment
+ *               then serving two or four 16-point tiles. */
 typedef struct {
   int32_t dw_splits;
   int32_t fwd_points;
@@ -368,6 +372,12 @@ pinn_status pinn_batch_create(int32_t n, const pinn_net *nets, const pinn_pde *p
                               int32_t prec, uint32_t flags, pinn_batch *out);
 pinn_status pinn_batch_destroy(pinn_batch batch);
 pinn_status pinn_batch_configure(pinn_batch batch, int32_t n_streams, int32_t use_graph);
+/* The kernel class (PINN_K_*) of every grouped launch of the current
+ * schedule, lane by lane in launch order, then the launches after the join;
+ * *n_out receives the count (classes may be NULL to query it; PINN_ERR_ARG
+ * when cap is below it).  With one lane this is the dispatch order of an
+ * eager step, which ties per-dispatch profiler records to kernel classes. */
+pinn_status pinn_batch_schedule_classes(pinn_batch batch, int32_t *classes, int64_t cap, int64_t *n_out);
 /* The current stream count and PINN_BATCH_* flags (after pinn_batch_autotune). */
 pinn_status pinn_batch_get_config(pinn_batch batch, int32_t *n_streams, int32_t *flags);
 pinn_status pinn_batch_step(pinn_batch batch, const pinn_net *nets, const pinn_pde *pdes, const float *const *x,

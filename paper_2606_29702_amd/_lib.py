@@ -35,7 +35,8 @@ EXPORTS = ["pinn_plan_create", "pinn_plan_destroy", "pinn_plan_memory", "pinn_je
            "pinn_jet_step_noalloc", "pinn_jet_backward_cot", "pinn_batch_train_step", "pinn_batch_launches",
            "pinn_batch_profile", "pinn_batch_profile_read", "pinn_batch_get_tuning",
            "pinn_tuning_cache_clear", "pinn_tuning_cache_size", "pinn_tuning_cache_save", "pinn_tuning_cache_load",
-           "pinn_jet_loss", "pinn_jet_loss_backward", "pinn_batch_get_config", "pinn_plan_create_modified"]
+           "pinn_jet_loss", "pinn_jet_loss_backward", "pinn_batch_get_config", "pinn_plan_create_modified",
+           "pinn_batch_schedule_classes"]
 KERNEL_CLASSES = {"layer_fwd": 1, "layer_bwd": 2, "dw_hidden": 3, "out_fwd": 4, "out_bwd": 5,
                   "seed_fwd": 6, "other": 7, "bwd_dw": 8}
 
@@ -114,6 +115,7 @@ def _load():
     lib.pinn_batch_launches.argtypes = [vp, i64p]
     lib.pinn_plan_create_modified.argtypes = [ctypes.POINTER(Modified), PdeP, i64, i32, ctypes.c_uint32, pp]
     lib.pinn_batch_get_config.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.pinn_batch_schedule_classes.argtypes = [vp, ctypes.POINTER(i32), i64, i64p]
     lib.pinn_batch_get_tuning.argtypes = [vp, i32, TuneP]
     lib.pinn_batch_profile.argtypes = [vp, i32]
     lib.pinn_batch_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -144,7 +146,8 @@ def _load():
                  "pinn_jet_backward_cot", "pinn_batch_train_step", "pinn_batch_launches", "pinn_batch_profile",
                  "pinn_batch_profile_read", "pinn_batch_get_tuning", "pinn_tuning_cache_clear",
                  "pinn_tuning_cache_size", "pinn_tuning_cache_save", "pinn_tuning_cache_load", "pinn_jet_loss",
-                 "pinn_jet_loss_backward", "pinn_batch_get_config", "pinn_plan_create_modified"):
+                 "pinn_jet_loss_backward", "pinn_batch_get_config", "pinn_plan_create_modified",
+                 "pinn_batch_schedule_classes"):
         getattr(lib, name).restype = ctypes.c_int32
     return lib
 

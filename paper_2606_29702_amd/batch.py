@@ -148,6 +148,16 @@ class PinnBatch:
         return {"dw_splits": t.dw_splits, "fwd_points": t.fwd_points, "bwd_fused": t.bwd_fused,
                 "bwd_points": t.bwd_points}
 
+    def schedule_classes(self) -> List[str]:
+        """The kernel class of every grouped launch of the current schedule, in
+        launch order lane by lane (see pinn_batch_schedule_classes)."""
+        n = ctypes.c_int64()
+        check(lib.pinn_batch_schedule_classes(self.handle, None, 0, ctypes.byref(n)))
+        arr = (ctypes.c_int32 * max(n.value, 1))()
+        check(lib.pinn_batch_schedule_classes(self.handle, arr, n.value, ctypes.byref(n)))
+        names = {v: k for k, v in _lib.KERNEL_CLASSES.items()}
+        return [names.get(arr[i], "other") for i in range(n.value)]
+
     def launches(self) -> int:
         """Grouped launches per step of the current schedule."""
         n = ctypes.c_int64()

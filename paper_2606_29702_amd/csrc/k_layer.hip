@@ -785,11 +785,11 @@ template <class CH, class T, bool TOP, int DOUT, int ZSRC>
 hipError_t launch_bwd_t(const BwdArgs &a, int64_t N_pad, int points, hipStream_t st) {
   const int w = a.w;
   // wide layers: neuron-tiled, contraction staged through LDS in chunks
-  // 16-bit operands with 8 channels (one full wave load per point and tile):
-  // the double-buffered form; measured slower than the single-buffered one at
-  // fewer channels (KS, C = 6: more registers, lower occupancy)
-  if constexpr (sizeof(T) == 2 && CH::C == 8) {
-    if (w >= 256 && w % 128 == 0) {
+  // 16-bit operands with 8 channels (one full wave load per point and tile),
+  // or up to 8 with points == 16: the double-buffered form (slower than the
+  // single-buffered one at 6 channels on KS: more registers, lower occupancy)
+  if constexpr (sizeof(T) == 2 && CH::C <= 8) {
+    if (w >= 256 && w % 128 == 0 && (CH::C == 8 || points == 16)) {
       const dim3 grid((unsigned)((N_pad / 16) * (w / 128)));
       return launch_body<KLayerBwdKc2<CH, T, 8, 64, TOP, DOUT, ZSRC>>({a}, grid, 0, st);
     }
@@ -890,8 +890,9 @@ hipError_t launch_layer_fwd(int kind, int prec, const void *A_in, const void *Wo
 }
 
 bool wide_bwd_points_supported(int points, int C, int w, int prec) {
-  if (points == 16) return w >= 256 && w % 128 == 0;
-  return (points == 32 || points == 64) && prec != P_FP32 && C <= 6 && w >= 256 && w % 128 == 0;
+  if (prec == P_FP32 || w < 256 || w % 128 != 0) return false;
+  if (points == 16) return C <= 8;  // the double-buffered 16-point kernel
+  return (points == 32 || points == 64) && C <= 6;
 }
 
 bool seed_grad_fused_supported(int C, int w, int prec) {

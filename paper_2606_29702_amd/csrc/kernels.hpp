@@ -73,8 +73,8 @@ struct LayerBwd {
   // layer's weight-gradient partials seed_part[tile][w*DIN + w] (dW_1
   // row-major, then db_1; one partial per 16-point tile) instead of Zb_out
   float *seed_part = nullptr;
-  // points per workgroup of the wide-layer kernel (w >= 256): 16 (0: the
-  // default), or 32 / 64 where wide_bwd_points_supported
+  // the wide-layer kernel (w >= 256): 0 the default, 16 the double-buffered
+  // 16-point form, 32 / 64 points per workgroup, where wide_bwd_points_supported
   int points = 0;
 };
 bool wide_bwd_points_supported(int points, int C, int w, int prec);

@@ -315,12 +315,15 @@ class PinnGraph:
         else:
             if [p.data_ptr() for pair in adam.params for p in pair] != [p.data_ptr() for pair in params for p in pair]:
                 raise ValueError("the AdamState must hold the same parameter tensors")
+            if len(adam.runs) != 1:
+                raise ValueError("a captured training step takes the parameters of a plain MLP (one chain)")
+            run = adam.runs[0]
             self.step = torch.zeros((), device=dev, dtype=torch.int64)  # updates done so far
             check(lib.pinn_graph_capture_train(
                 plan.handle, ctypes.byref(nv.net), ctypes.byref(_pde(plan.pde, plan.coef)),
                 ctypes.c_void_p(x.data_ptr()), N, ctypes.c_void_p(self.r.data_ptr()),
-                ctypes.c_void_p(self.loss.data_ptr()), dWp, dbp, adam._mW[0], adam._vW[0], adam._mb[0],
-                adam._vb[0], ctypes.byref(adam.hp), ctypes.c_void_p(self.step.data_ptr()), ctypes.byref(handle)))
+                ctypes.c_void_p(self.loss.data_ptr()), dWp, dbp, run["mW"][0], run["vW"][0], run["mb"][0],
+                run["vb"][0], ctypes.byref(adam.hp), ctypes.c_void_p(self.step.data_ptr()), ctypes.byref(handle)))
         self.handle = handle
 
     def launch(self) -> None:

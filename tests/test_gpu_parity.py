@@ -556,8 +556,9 @@ def test_forward_tilings_agree_bitwise(lib, pde, dims, prec):
                                            ("burgers", [2, 256, 256, 256, 256, 1], "bf16"),
                                            ("burgers", [2, 256, 256, 256, 1], "fp16")])
 def test_wide_backward_tilings_agree(lib, pde, dims, prec):
-    """16, 32 and 64 points per workgroup of the wide-layer backward kernel
-    (two or four point tiles sharing every weight fragment): the same
+    """The wide-layer backward kernel with 16 points per workgroup (single- or
+    double-buffered chunks), 32 and 64 (two or four point tiles sharing every
+    weight fragment): the same
     per-element arithmetic, so the gradients agree bit for bit with BF16
     operands and to FP16 rounding with FP16 ones; the 64-point tiling against
     the oracle at the 16-bit bars."""
@@ -571,12 +572,12 @@ def test_wide_backward_tilings_agree(lib, pde, dims, prec):
     plan = lib.PinnPlan(dims, pde, N, precision=prec, coef=prob.coef)
     t = plan.tuning()
     grads = {}
-    for bp in (0, 32, 64):
+    for bp in (0, 16, 32, 64):
         plan.set_tuning(t["dw_splits"], t["fwd_points"], t["bwd_fused"], bp)
         plan.residual(params, x)
         grads[bp] = flat(plan.backward(params, x))
     torch.cuda.synchronize()
-    for bp in (32, 64):
+    for bp in (16, 32, 64):
         if prec == "fp16":
             assert rel(grads[bp], grads[0]) <= 1e-3, bp
         else:
