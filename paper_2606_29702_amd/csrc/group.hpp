@@ -26,7 +26,26 @@ namespace pj {
 
 struct VBlock {
   int x, y, gx, gy;
+  int p0;  // physical index of the virtual grid's first workgroup
 };
+
+// Workgroups of one launch are dealt round-robin to the 8 XCDs (physical
+// index i runs on XCD i % 8), and each XCD has its own L2.  xcd_order maps the
+// virtual block to a logical index in [0, gx * gy) such that consecutive
+// logical indices run on the same XCD: a kernel that gives consecutive logical
+// indices work on the same data (the neuron tiles of one point tile, the
+// weight tiles of one split) then reads that data into one L2 instead of
+// several.  The map is a bijection; blocks before the first and after the last
+// whole round of 8 keep their index.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_order(const VBlock &vb) {
+  const int G = vb.gx * vb.gy, v = vb.x + vb.y * vb.gx;
+  const int h = (kXcds - vb.p0 % kXcds) % kXcds;  // head blocks before the first whole round
+  const int R = G > h ? (G - h) / kXcds : 0;      // whole rounds
+  const int u = v - h;
+  if (u < 0 || u >= kXcds * R) return v;
+  return h + (u % kXcds) * R + u / kXcds;
+}
 
 constexpr int kGroupMax = 64;  // members per grouped launch
 
@@ -39,7 +58,7 @@ struct GroupTab {
 
 template <class B>
 __global__ __launch_bounds__(B::NT) void k_direct(typename B::Args a) {
-  B::run(a, VBlock{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, (int)gridDim.y});
+  B::run(a, VBlock{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, (int)gridDim.y, 0});
 }
 
 template <class B>
@@ -53,7 +72,7 @@ __global__ __launch_bounds__(B::NT) void k_grouped(GroupTab t) {
   }
   const int v = b - t.start[lo], gx = t.gx[lo];
   const int gy = (t.start[lo + 1] - t.start[lo]) / gx;
-  B::run(*static_cast<const typename B::Args *>(t.args[lo]), VBlock{v % gx, v / gx, gx, gy});
+  B::run(*static_cast<const typename B::Args *>(t.args[lo]), VBlock{v % gx, v / gx, gx, gy, t.start[lo]});
 }
 
 // One recorded launch.

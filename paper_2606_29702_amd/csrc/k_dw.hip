@@ -105,7 +105,9 @@ struct KDwHidden {
     const int lane = t & 63, wave = t >> 6;
     const int wj = wave & 1, wk = wave >> 1;
     const int r16 = lane & 15, g = lane >> 4;
-    const int nt_ = w / TILE, bx_ = vb.x % nt_, by_ = vb.x / nt_, bz_ = vb.y;  // weight tile, split
+    // weight tile and split; the tiles of one split share an XCD's L2
+    const int lb = xcd_order(vb), ntiles = vb.gx;
+    const int nt_ = w / TILE, tile = lb % ntiles, bx_ = tile % nt_, by_ = tile / nt_, bz_ = lb / ntiles;
     const int j0 = bx_ * TILE, k0 = by_ * TILE;
     const int64_t rb = (int64_t)bz_ * rows_per_split;
     const int64_t re = rb + rows_per_split < rows_total ? rb + rows_per_split : rows_total;

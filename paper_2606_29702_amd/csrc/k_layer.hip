@@ -513,10 +513,10 @@ struct KLayerBwdLds {
 // does not fit in LDS.  A workgroup of NW waves (TPW neuron tiles each)
 // computes a P-point x 16 NW TPW-neuron output tile, P = 16 PTW: every wave
 // takes all PTW point tiles, so each weight fragment it loads feeds PTW x C
-// MFMAs.  The neuron tile is the
-// fastest-varying part of the block index, so the workgroups that share a point
-// tile run next to each other and its stack data is reused from L2.  The contraction (the neurons
-// of the layer below) runs in chunks of KC: each chunk of the Zbar and A_{l-2}
+// MFMAs.  The neuron tile is the fastest-varying part of the logical block
+// index (xcd_order), so the workgroups that share a point tile run on one XCD
+// and read its stack data into that XCD's L2 once.  The contraction (the
+// neurons of the layer below) runs in chunks of KC: each chunk of the Zbar and A_{l-2}
 // tiles ([point][channel][KC], rows padded by 8 elements) is staged through
 // LDS with every thread's loads issued together, then feeds the Abar and z
 // GEMMs.  The epilogue is that of the full-tile kernel.
@@ -544,8 +544,9 @@ struct KLayerBwdKc {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, g = lane >> 4;
     const int ntn = w / TILEN;  // neuron tiles per point tile (consecutive workgroups)
-    const int64_t ptile = vb.x / ntn;
-    const int ntile = (int)(vb.x - ptile * ntn);
+    const int lb = xcd_order(vb);  // the neuron tiles of a point tile share an XCD's L2
+    const int64_t ptile = lb / ntn;
+    const int ntile = (int)(lb - ptile * ntn);
     const int64_t nb = ptile * P;
     const int jt0 = ntile * (TILEN / 16) + wave * TPW;
     const int64_t ps = (int64_t)C * w;
@@ -658,8 +659,9 @@ struct KLayerBwdKc2 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, g = lane >> 4;
     const int ntn = w / TILEN;
-    const int64_t ptile = vb.x / ntn;
-    const int ntile = (int)(vb.x - ptile * ntn);
+    const int lb = xcd_order(vb);  // the neuron tiles of a point tile share an XCD's L2
+    const int64_t ptile = lb / ntn;
+    const int ntile = (int)(lb - ptile * ntn);
     const int64_t nb = ptile * P;
     const int jt0 = ntile * (TILEN / 16) + wave * TPW;
     const int64_t ps = (int64_t)C * w;
