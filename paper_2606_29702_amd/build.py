@@ -2,8 +2,8 @@
 
 Every source under csrc/ is compiled by hipcc for gfx950 only, in parallel,
 then linked into one shared library next to this file.  Packed FP32 VALU
-instructions are disabled for all device code.  Except in k_layer.hip (where
-it measured slower), MFMA instructions are selected in their VGPR form
+instructions are disabled for all device code.  Except in the k_layer
+sources (where it measured slower), MFMA instructions are selected in their VGPR form
 (accumulators in ordinary VGPRs), which keeps the compiler from shuffling
 loop-carried accumulators through AGPRs.
 """
@@ -30,12 +30,12 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-ffp-c
 
 
 MFMA_VGPR = ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]
-NO_MFMA_VGPR = {"k_layer.hip"}
+NO_MFMA_VGPR_PREFIX = "k_layer"
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    extra = [] if os.path.basename(src) in NO_MFMA_VGPR else MFMA_VGPR
+    extra = [] if os.path.basename(src).startswith(NO_MFMA_VGPR_PREFIX) else MFMA_VGPR
     cmd = [HIPCC] + FLAGS + extra + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

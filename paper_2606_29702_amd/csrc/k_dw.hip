@@ -18,9 +18,14 @@ namespace pj {
 
 template <class T, int TILE, int RC>
 struct DwLayout {
-  // Row pitch in elements: rows stay 8-byte aligned and rows 8 apart fall
-  // 16 banks apart, so the four lane groups of a column gather do not collide.
-  static constexpr int pitch = TILE + 8 / (int)sizeof(T);
+  // Row pitch in elements.  16-bit types: the transpose reads of one 16-lane
+  // group take 32 bytes from each of 4 consecutive rows; a pitch of
+  // TILE + 16 elements (32 bytes past a multiple of 128) puts those rows 8
+  // banks apart, so the group's 128 bytes fall in 32 distinct banks, and
+  // keeps rows 16-byte aligned for whole-piece stores.  FP32: rows stay
+  // 8-byte aligned and rows 8 apart fall 16 banks apart, so the four lane
+  // groups of a column gather do not collide.
+  static constexpr int pitch = TILE + (sizeof(T) == 2 ? 16 : 2);
   static constexpr int tile_elems = RC * pitch;         // RC rows staged per chunk
   static constexpr int per_row = TILE / 8;              // 8-element copies per row
   static constexpr int copies = RC * per_row;           // per operand per chunk
@@ -129,10 +134,18 @@ struct KDwHidden {
           const int row = q / LY::per_row, col = (q % LY::per_row) * 8;
           const uint2 *sz = reinterpret_cast<const uint2 *>(Zb + (r0 + row) * w + j0 + col);
           const uint2 *sa = reinterpret_cast<const uint2 *>(A + (r0 + row) * w + k0 + col);
+          if constexpr (sizeof(T) == 2) {  // one 16-byte load per piece
+            const uint4 vz = *reinterpret_cast<const uint4 *>(sz), va = *reinterpret_cast<const uint4 *>(sa);
+            stage[0][u][0] = uint2{vz.x, vz.y};
+            stage[0][u][1] = uint2{vz.z, vz.w};
+            stage[1][u][0] = uint2{va.x, va.y};
+            stage[1][u][1] = uint2{va.z, va.w};
+          } else {
   #pragma unroll
-          for (int v = 0; v < LY::words; ++v) {
-            stage[0][u][v] = sz[v];
-            stage[1][u][v] = sa[v];
+            for (int v = 0; v < LY::words; ++v) {
+              stage[0][u][v] = sz[v];
+              stage[1][u][v] = sa[v];
+            }
           }
         }
       }
@@ -145,9 +158,14 @@ struct KDwHidden {
           const int row = q / LY::per_row, col = (q % LY::per_row) * 8;
   #pragma unroll
           for (int m = 0; m < 2; ++m) {
-            uint2 *d = reinterpret_cast<uint2 *>(&lds[buf][m][row * P + col]);
+            if constexpr (sizeof(T) == 2) {  // one 16-byte store per piece
+              *reinterpret_cast<uint4 *>(&lds[buf][m][row * P + col]) =
+                  uint4{stage[m][u][0].x, stage[m][u][0].y, stage[m][u][1].x, stage[m][u][1].y};
+            } else {
+              uint2 *d = reinterpret_cast<uint2 *>(&lds[buf][m][row * P + col]);
   #pragma unroll
-            for (int v = 0; v < LY::words; ++v) d[v] = stage[m][u][v];
+              for (int v = 0; v < LY::words; ++v) d[v] = stage[m][u][v];
+            }
           }
         }
       }

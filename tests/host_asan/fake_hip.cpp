@@ -15,8 +15,11 @@
 // (each launch advances it by a cost derived from its grid and a seed), so the
 // autotuners pick different candidates under different seeds.
 //
-// Violations print "FAKE_HIP VIOLATION: ..." and abort.
+// Violations print "FAKE_HIP VIOLATION: ..." and abort.  With FAKE_HIP_TRACE
+// set to a file name, every launch is also listed there (kernel, grid, block,
+// dynamic LDS).
 #include <hip/hip_runtime.h>
+#include <cxxabi.h>
 #include <sys/mman.h>
 
 #include <cstdarg>
@@ -93,9 +96,14 @@ struct State {
   double capture_cost = 0.0;
   uint64_t launches = 0;
   uint64_t seed = 0;
+  FILE *trace = nullptr;
 };
 State &S() {
-  static State *s = new State;  // never destroyed: module destructors may still call in
+  static State *s = [] {
+    State *n = new State;  // never destroyed: module destructors may still call in
+    if (const char *path = getenv("FAKE_HIP_TRACE")) n->trace = fopen(path, "w");
+    return n;
+  }();
   return *s;
 }
 
@@ -209,6 +217,13 @@ hipError_t hipLaunchKernel(const void *fn, dim3 grid, dim3 block, void **args, s
       if (!find_live(t.args[e], 1)) violation("%s: member %d's argument block %p is not live device memory",
                                               f.name.c_str(), e, t.args[e]);
     }
+  }
+  if (S().trace) {
+    int status = 0;
+    char *dm = abi::__cxa_demangle(f.name.c_str(), nullptr, nullptr, &status);
+    fprintf(S().trace, "%s grid %u x %u block %llu lds %zu%s\n", status == 0 && dm ? dm : f.name.c_str(), grid.x,
+            grid.y, (unsigned long long)threads, shm, S().capturing ? " (captured)" : "");
+    free(dm);
   }
   const double cost = ((double)grid.x * grid.y * grid.z * threads) * 1e-7 *
                       (1.0 + (double)(mix(S().seed ^ (uintptr_t)fn) % 1000) / 1000.0);
