@@ -295,7 +295,10 @@ pinn_status pinn_plan_create_modified(const pinn_modified *arch, const pinn_pde 
  *               operands): 0 = the default; 16 = 16 points per workgroup with
  *               the LDS chunks double-buffered (up to 8 channels); 32 or 64
  *               points per workgroup (up to 6 channels), each weight fragment
- *               then serving two or four 16-point tiles. */
+ *               then serving two or four 16-point tiles; 128 (width 256, up
+ *               to 6 channels) = eight 16-point tiles per workgroup streamed
+ *               through LDS with the weights held in registers and the next
+ *               tile's loads in flight during the current tile's MFMAs. */
 typedef struct {
   int32_t dw_splits;
   int32_t fwd_points;

@@ -633,6 +633,140 @@ struct KLayerBwdKc {
   }
 };
 
+// Staging of one point tile of the streaming wide kernel ([P][C][W] rows of
+// Zbar and A_{l-2}): global loads into registers, then stores into the LDS
+// tiles (rows padded by 8 elements).
+template <class T, int C, int NT, int W, int P, int PER_T, bool ZB, bool AZ>
+__device__ __forceinline__ void ks_load_unit(u32x4 (&rz)[PER_T], u32x4 (&ra)[PER_T], const T *zb_all, const T *a_all,
+                                             int64_t nb, int64_t ps, int tid) {
+  constexpr int P16 = 16 / (int)sizeof(T), PPR = C * W / P16, PIECES = P * PPR;
+#pragma unroll
+  for (int i = 0; i < PER_T; ++i) {
+    const int q0 = tid + i * NT;
+    const int q = q0 < PIECES ? q0 : PIECES - 1;  // re-read the last piece (in bounds)
+    const int p = q / PPR, j = q - p * PPR;
+    const int64_t goff = (nb + p) * ps + j * P16;
+    if constexpr (ZB) rz[i] = *reinterpret_cast<const u32x4 *>(zb_all + goff);
+    if constexpr (AZ) ra[i] = *reinterpret_cast<const u32x4 *>(a_all + goff);
+  }
+}
+
+template <class T, int C, int NT, int W, int P, int PER_T, bool ZB, bool AZ>
+__device__ __forceinline__ void ks_store_unit(const u32x4 (&rz)[PER_T], const u32x4 (&ra)[PER_T], T *lds_b, T *lds_a,
+                                              int tid) {
+  constexpr int P16 = 16 / (int)sizeof(T), PPR = C * W / P16, PIECES = P * PPR, PITCH = C * W + 8;
+#pragma unroll
+  for (int i = 0; i < PER_T; ++i) {
+    const int q = tid + i * NT;
+    if (q < PIECES) {
+      const int p = q / PPR, j = q - p * PPR;
+      const int loff = p * PITCH + j * P16;
+      if constexpr (ZB) *reinterpret_cast<u32x4 *>(lds_b + loff) = rz[i];
+      if constexpr (AZ) *reinterpret_cast<u32x4 *>(lds_a + loff) = ra[i];
+    }
+  }
+}
+
+// The backward layer at width W = 256 for 16-bit operands, streaming: a
+// workgroup keeps its waves' weight fragments (16 rows of W^T and, for the z
+// recompute, of W_z, over the whole contraction) in registers and works
+// through PPW point tiles of P = 16 PTW points in turn.  Each point tile is
+// staged whole (all W neurons of every channel) through one LDS buffer; the
+// global loads of the next tile are issued before the current tile is
+// multiplied, so that HBM traffic stays in flight during the MFMAs and the
+// epilogue.  Logical block order as in KLayerBwdKc (the neuron tiles of a
+// group of point tiles share an XCD).  The contraction runs in the same order
+// as in KLayerBwdKc, so both give the same bits.
+template <class CH, class T, int NW, int W, bool TOP, int DOUT, int ZSRC, int PTW, int PPW>
+struct KLayerBwdKs {
+  static constexpr int NT = NW * 64;
+  struct Args {
+    BwdArgs args;
+  };
+  static __device__ __forceinline__ void run(const Args &a_, VBlock vb) {
+    const BwdArgs &args = a_.args;
+    using M = Mma<T>;
+    constexpr int C = CH::C, P = 16 * PTW, TPW = 1;
+    constexpr int TILEN = NW * TPW * 16;
+    constexpr int KS = W / 32;  // contraction steps
+    constexpr int PITCH = C * W + 8;
+    constexpr bool ZB = !TOP, AZ = ZSRC == Z_FROM_GEMM;
+    constexpr int PER_T = (P * C * W * (int)sizeof(T) / 16 + NT - 1) / NT;  // 16-byte pieces per thread
+    static_assert(sizeof(T) == 2 && W % 32 == 0, "shape");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *lds_b = reinterpret_cast<T *>(smem_raw);
+    T *lds_a = lds_b + (ZB ? P * PITCH : 0);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    constexpr int ntn = W / TILEN;
+    const int lb = xcd_order(vb);
+    const int64_t group = lb / ntn;
+    const int ntile = (int)(lb - group * ntn);
+    const int jt0 = ntile * (TILEN / 16) + wave * TPW;
+    const int64_t n_ptiles = (args.N + kPointTile - 1) / kPointTile * (kPointTile / P);
+    const int64_t pt0 = group * PPW;
+    const int n_tiles = (int)(n_ptiles - pt0 < PPW ? n_ptiles - pt0 : PPW);
+    if (n_tiles <= 0) return;  // uniform over the workgroup
+    const int64_t ps = (int64_t)C * W;
+    const T *WT = static_cast<const T *>(args.WT);
+    const T *Wz = static_cast<const T *>(args.Wz);
+    const T *zb_all = static_cast<const T *>(args.Zb_in);
+    const T *a_all = static_cast<const T *>(args.A_prev);
+    // the waves' weight rows over the whole contraction
+    typename M::frag wa[ZB ? KS : 1], wz[AZ ? KS : 1];
+  #pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      if constexpr (ZB) wa[s] = M::load(WT + (int64_t)(jt0 * 16 + r) * W + s * 32 + 8 * g);
+      if constexpr (AZ) wz[s] = M::load(Wz + (int64_t)(jt0 * 16 + r) * W + s * 32 + 8 * g);
+    }
+    u32x4 rz[PER_T], ra[PER_T];  // the next tile's pieces (a plain vector type keeps them in registers)
+    ks_load_unit<T, C, NT, W, P, PER_T, ZB, AZ>(rz, ra, zb_all, a_all, pt0 * P, ps, tid);
+    f32x4 acc_a[PTW][TPW][C], acc_z[PTW][TPW][C];
+    for (int t = 0; t < n_tiles; ++t) {
+      if (t > 0) __syncthreads();  // every wave is done with the previous tile's LDS data
+      ks_store_unit<T, C, NT, W, P, PER_T, ZB, AZ>(rz, ra, lds_b, lds_a, tid);
+      __syncthreads();
+      if (t + 1 < n_tiles)  // in flight during this tile's MFMAs and epilogue
+        ks_load_unit<T, C, NT, W, P, PER_T, ZB, AZ>(rz, ra, zb_all, a_all, (pt0 + t + 1) * P, ps, tid);
+  #pragma unroll
+      for (int q = 0; q < PTW; ++q)
+  #pragma unroll
+        for (int c = 0; c < C; ++c) {
+          acc_a[q][0][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+          acc_z[q][0][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+  #pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        if constexpr (ZB) {
+  #pragma unroll
+          for (int q = 0; q < PTW; ++q) {
+            typename M::frag fb[C];
+  #pragma unroll
+            for (int c = 0; c < C; ++c) fb[c] = M::load(lds_b + (q * 16 + r) * PITCH + c * W + s * 32 + 8 * g);
+  #pragma unroll
+            for (int c = 0; c < C; ++c) M::mma(acc_a[q][0][c], wa[s], fb[c]);
+          }
+        }
+        if constexpr (AZ) {
+  #pragma unroll
+          for (int q = 0; q < PTW; ++q) {
+            typename M::frag fb[C];
+  #pragma unroll
+            for (int c = 0; c < C; ++c) fb[c] = M::load(lds_a + (q * 16 + r) * PITCH + c * W + s * 32 + 8 * g);
+  #pragma unroll
+            for (int c = 0; c < C; ++c) M::mma(acc_z[q][0][c], wz[s], fb[c]);
+          }
+        }
+      }
+      const int64_t nb = (pt0 + t) * P;
+  #pragma unroll
+      for (int q = 0; q < PTW; ++q)
+        bwd_epilogue<CH, T, TPW, TOP, DOUT, ZSRC>(args, acc_a[q], acc_z[q], nb + q * 16 + r, jt0,
+                                                  (pt0 + t) * PTW + q, lane);
+    }
+  }
+};
+
 // The wide-layer kernel for 16-bit operands with its chunks double-buffered:
 // two sets of chunk buffers are separate static LDS objects, and while one
 // chunk feeds the GEMMs the next one streams into the other set with
@@ -806,6 +940,12 @@ hipError_t launch_bwd_t(const BwdArgs &a, int64_t N_pad, int points, hipStream_t
     // fragment across two or four point tiles (16-bit operands, up to 6
     // channels); chunks of 64 neurons at 64 points keep the LDS in bounds
     if constexpr (sizeof(T) == 2 && CH::C <= 6) {
+      if (points == 128 && w == 256 && N_pad == (a.N + kPointTile - 1) / kPointTile * kPointTile) {
+        // eight 16-point tiles per workgroup, weights in registers, staging pipelined
+        const size_t lds = (size_t)tiles * 16 * (CH::C * 256 + 8) * sizeof(T);
+        const dim3 grid((unsigned)((N_pad / 16 + 7) / 8 * (256 / 128)));
+        return launch_body<KLayerBwdKs<CH, T, 8, 256, TOP, DOUT, ZSRC, 1, 8>>({a}, grid, lds, st);
+      }
       if (points == 32) {
         const size_t lds = (size_t)tiles * 32 * (CH::C * 128 + 8) * sizeof(T);
         const dim3 grid((unsigned)((N_pad / 32) * (w / 128)));

@@ -558,9 +558,10 @@ def test_forward_tilings_agree_bitwise(lib, pde, dims, prec):
 def test_wide_backward_tilings_agree(lib, pde, dims, prec):
     """The wide-layer backward kernel with 16 points per workgroup (single- or
     double-buffered chunks), 32 and 64 (two or four point tiles sharing every
-    weight fragment): the same
-    per-element arithmetic, so the gradients agree bit for bit with BF16
-    operands and to FP16 rounding with FP16 ones; the 64-point tiling against
+    weight fragment), and the streaming form at width 256 (eight 16-point
+    tiles per workgroup, weights in registers): the same per-element
+    arithmetic, so the gradients agree bit for bit with BF16 operands and to
+    FP16 rounding with FP16 ones; the 64-point and streaming tilings against
     the oracle at the 16-bit bars."""
     N = 1000
     prob = pi.make_problem(pde, N=N, seed=14, bias_std=0.2, dims=dims)
@@ -572,18 +573,20 @@ def test_wide_backward_tilings_agree(lib, pde, dims, prec):
     plan = lib.PinnPlan(dims, pde, N, precision=prec, coef=prob.coef)
     t = plan.tuning()
     grads = {}
-    for bp in (0, 16, 32, 64):
+    tilings = (0, 16, 32, 64) + ((128,) if dims[1] == 256 and len(prob.channels) <= 6 else ())
+    for bp in tilings:
         plan.set_tuning(t["dw_splits"], t["fwd_points"], t["bwd_fused"], bp)
         plan.residual(params, x)
         grads[bp] = flat(plan.backward(params, x))
     torch.cuda.synchronize()
-    for bp in (16, 32, 64):
+    for bp in tilings[1:]:
         if prec == "fp16":
             assert rel(grads[bp], grads[0]) <= 1e-3, bp
         else:
             assert np.array_equal(grads[bp], grads[0]), bp
     orc = oracle.evaluate(prob.params, prob.x, prob.channels, pde, prob.coef)
     assert rel(grads[64], orc.grad) <= LOWP_TOL[prec]["grad"]
+    assert rel(grads[tilings[-1]], orc.grad) <= LOWP_TOL[prec]["grad"]
     with pytest.raises(lib.PinnError):
         plan.set_tuning(t["dw_splits"], t["fwd_points"], t["bwd_fused"], 48)
     plan.close()
