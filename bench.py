@@ -127,19 +127,59 @@ def class_flops(w, H, C, N, fused):
     return f
 
 
-def roofline_from(cls, flops_per_step, cls_ms, launches, prec, workload, steps_timed):
+def class_stack_bytes(w, H, C, N_pad, fused, osz):
+    """The design's stack traffic per step by kernel class (bytes): the layer
+    stacks ([N_pad][C][w], osz bytes per element) each class reads or writes
+    once.  It is a design cost (the algorithmic minimum is x, r and dtheta);
+    it bounds the MFMA fraction a class can reach when its stacks come from
+    HBM:
+      forward (store-all)  writes A_1 .. A_H                     H stacks
+      separate backward    adjoint, layers H .. 3: reads Zbar_l and A_{l-2}
+                           (z recompute), writes Zbar_{l-1};  layer 2 reads
+                           Zbar_2 (first-layer gradient from x)  3 (H - 2) + 1
+                           dW per layer: Zbar_l and A_{l-1}      2 (H - 1)
+                           top layer: A_{H-1} in, Zbar_H out     2
+      fused backward       layers H-1 .. 2: Zbar_l, A_{l-1}, A_{l-2} in,
+                           Zbar_{l-1} out                        4 (H - 2)
+                           top layer with its dW                 2
+                           layer 1 adjoint                       1"""
+    S = float(C) * w * osz * N_pad
+    b = dict.fromkeys(ALL_CLASSES, 0.0)
+    b["layer_fwd"] = H * S
+    if H < 2:
+        return b
+    b["out_bwd"] = 2 * S
+    if fused:
+        b["bwd_dw"] = 4 * (H - 2) * S
+        b["layer_bwd"] = S
+    else:
+        b["layer_bwd"] = (3 * (H - 2) + 1) * S
+        b["dw_hidden"] = 2 * (H - 1) * S
+    return b
+
+
+def roofline_from(cls, flops_per_step, cls_ms, launches, prec, workload, steps_timed, stack_bytes_per_step=None):
     """Dominant kernel class roofline: algorithmic flops per launch over the
-    average launch time measured with HIP events."""
+    average launch time measured with HIP events.  With the class's design
+    stack traffic, also the HBM fraction that traffic takes and the MFMA
+    fraction it would allow at the HBM peak (the bound that applies when the
+    stacks stream from HBM)."""
     avg_ms = cls_ms / max(launches, 1)
     per_launch = flops_per_step * steps_timed / max(launches, 1)
     achieved = per_launch / (avg_ms * 1e-3) / 1e12
     traffic = profiled_traffic(workload, prec, cls)
-    return dict(bound="mfma", achieved=round(achieved, 3), peak=PEAK[prec], unit="TFLOP/s",
-                frac=round(achieved / PEAK[prec], 5), traffic=None if traffic is None else round(traffic),
-                traffic_unit="bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
-                kernel_class=cls, avg_launch_us=round(avg_ms * 1e3, 2), launches=launches,
-                flops_per_launch=per_launch,
-                hbm_frac=None if traffic is None else round(traffic / (avg_ms * 1e-3) / 1e9 / HBM_PEAK, 4))
+    out = dict(bound="mfma", achieved=round(achieved, 3), peak=PEAK[prec], unit="TFLOP/s",
+               frac=round(achieved / PEAK[prec], 5), traffic=None if traffic is None else round(traffic),
+               traffic_unit="bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+               kernel_class=cls, avg_launch_us=round(avg_ms * 1e3, 2), launches=launches,
+               flops_per_launch=per_launch,
+               hbm_frac=None if traffic is None else round(traffic / (avg_ms * 1e-3) / 1e9 / HBM_PEAK, 4))
+    if stack_bytes_per_step:
+        sb = stack_bytes_per_step * steps_timed / max(launches, 1)
+        out["stack_bytes_per_launch"] = round(sb)
+        out["stack_hbm_frac"] = round(sb / (avg_ms * 1e-3) / 1e9 / HBM_PEAK, 4)
+        out["stack_bound_mfma_frac"] = round(min(1.0, (per_launch / sb) / (PEAK[prec] * 1e12 / (HBM_PEAK * 1e9))), 4)
+    return out
 
 
 # --------------------------------------------------------------------------- the ensemble
@@ -212,13 +252,18 @@ def ensemble_headline(ens, params, xs, prec, steps, warmup, runs, replays, count
         log("counter window: " + json.dumps({"steps": counter_window, "classes": classes}))
     batch.close()
     flops = dict.fromkeys(ALL_CLASSES, 0.0)
+    stack_bytes = dict.fromkeys(ALL_CLASSES, 0.0)
+    osz = 4 if prec == "fp32" else 2
     for m, t in zip(ens, tunings):
-        for k, v in class_flops(m.width, m.hidden, 4, m.N, bool(t["bwd_fused"]) and m.width <= 128).items():
+        fused = bool(t["bwd_fused"]) and m.width <= 128
+        for k, v in class_flops(m.width, m.hidden, 4, m.N, fused).items():
             flops[k] += v
+        for k, v in class_stack_bytes(m.width, m.hidden, 4, -(-m.N // 128) * 128, fused, osz).items():
+            stack_bytes[k] += v
     total_flops = sum(flops.values())
     return dict(ms=ms, per_run_ms=per_run, lanes=lanes, tune_s=tune_s, class_ms=class_ms, dominant=dom,
                 dom_ms=dom_ms, dom_n=dom_n, flops=flops, total_flops=total_flops, launches=launches,
-                tunings=tunings)
+                tunings=tunings, stack_bytes=stack_bytes)
 
 
 def ensemble_fp32_sequential(ens, params, xs, steps):
@@ -612,8 +657,9 @@ def plan_leg(name, prec, steps, warmup, save_cap=0, fp32_context=True):
     tun = run["tuning"]
     fused = bool(tun["bwd_fused"]) and w <= 128
     fl = class_flops(w, H, C, N, fused)
+    sb = class_stack_bytes(w, H, C, -(-N // 128) * 128, fused, 4 if prec == "fp32" else 2)
     dom = run["dominant"]
-    roof = roofline_from(dom, fl[dom], run["dom_ms"], run["dom_n"], prec, name, steps)
+    roof = roofline_from(dom, fl[dom], run["dom_ms"], run["dom_n"], prec, name, steps, sb[dom])
     out = dict(workload=name, dims=wl.dims, N=N, channels=C, precision=prec, save_cap_bytes=save_cap,
                ms_per_step=round(run["ms"], 4), value=round(N / (run["ms"] * 1e-3), 1), unit="pts/s",
                step_mfma_frac=round(sum(fl.values()) / (run["ms"] * 1e-3) / 1e12 / PEAK[prec], 4),
@@ -698,14 +744,18 @@ def main():
         run = time_plan(prob, prec, args.steps, args.warmup, save_cap=cap, tuning=tuning)
         wl = prob.workload
         N = prob.x.shape[0]
-        fl = class_flops(wl.width, wl.hidden, len(prob.channels), N, bool(run["tuning"]["bwd_fused"]) and wl.width <= 128)
+        fused = bool(run["tuning"]["bwd_fused"]) and wl.width <= 128
+        fl = class_flops(wl.width, wl.hidden, len(prob.channels), N, fused)
+        sb = class_stack_bytes(wl.width, wl.hidden, len(prob.channels), -(-N // 128) * 128, fused,
+                               4 if prec == "fp32" else 2)
         dom = run["dominant"]
         out = {"metric": METRIC, "value": round(N / (run["ms"] * 1e-3), 1), "unit": "pts/s", "n_gpus": 1,
                "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(run["ms"], 4),
                "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": prec,
                "data": "synthetic", "config": {"workload": args.workload, "dims": wl.dims, "N": N,
                                                "save_cap_bytes": cap},
-               "roofline": roofline_from(dom, fl[dom], run["dom_ms"], run["dom_n"], prec, args.workload, args.steps),
+               "roofline": roofline_from(dom, fl[dom], run["dom_ms"], run["dom_n"], prec, args.workload, args.steps,
+                                         sb[dom]),
                "tuning": run["tuning"]}
         print(json.dumps(out), flush=True)
         return
@@ -718,7 +768,8 @@ def main():
     ms = head["ms"]
     value = total_N / (ms * 1e-3)
     dom = head["dominant"]
-    roof = roofline_from(dom, head["flops"][dom], head["dom_ms"], head["dom_n"], prec, "ensemble", args.steps)
+    roof = roofline_from(dom, head["flops"][dom], head["dom_ms"], head["dom_n"], prec, "ensemble", args.steps,
+                         head["stack_bytes"][dom])
     log(f"{prec} grouped ensemble: {ms:.3f} ms/step, {value/1e6:.2f} Mpts/s, {head['launches']} launches, "
         f"dominant {dom} {roof['avg_launch_us']} us/launch, {roof['frac']:.4f} of peak")
     out = {
