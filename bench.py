@@ -266,6 +266,17 @@ def ensemble_headline(ens, params, xs, prec, steps, warmup, runs, replays, count
                 tunings=tunings, stack_bytes=stack_bytes)
 
 
+def tunings_by_width(ens, tunings):
+    """How many members of each width the autotuner gave each tiling."""
+    out = {}
+    for m, t in zip(ens, tunings):
+        key = f"fwd{t['fwd_points']}/{'fused' if t['bwd_fused'] and m.width <= 128 else 'split'}" + (
+            f"/bwd{t['bwd_points']}" if m.width >= 256 else "")
+        d = out.setdefault(str(m.width), {})
+        d[key] = d.get(key, 0) + 1
+    return out
+
+
 def ensemble_fp32_sequential(ens, params, xs, steps):
     """The plain FP32 jet path, one network after another on one stream."""
     import torch
@@ -802,6 +813,7 @@ def main():
         "step_mfma_frac": round(head["total_flops"] / (ms * 1e-3) / 1e12 / PEAK[prec], 4),
         "hidden_gemm_tflop_per_step": round(head["total_flops"] / 1e12, 4),
         "grouped_launches_per_step": head["launches"],
+        "tunings_by_width": tunings_by_width(ens, head["tunings"]),
         "lanes": head["lanes"],
         "autotune_s": round(head["tune_s"], 2),
         "timing_protocol": {"runs": args.runs, "replays_per_run": args.replays,
