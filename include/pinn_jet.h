@@ -366,8 +366,13 @@ pinn_status pinn_tuning_cache_load(const char *path);
  *                       width, widths beyond the stream count sharing lanes).
  *   pinn_batch_launches  grouped launches per step of the current schedule.
  *   pinn_batch_autotune  runs pinn_plan_autotune on every network (networks
- *                       sharing a cache key are timed once), then times
- *                       `reps` steps for width lanes on 1, 2 and 4 streams and
+ *                       sharing a cache key are timed once); then times
+ *                       `reps` grouped steps with those tilings against the
+ *                       same steps with every network on the tiling with the
+ *                       most points per workgroup its shape allows (forward
+ *                       64 points, fused weight gradient, wide backward 128
+ *                       points, where supported) and keeps the faster; then
+ *                       times width lanes on 1, 2 and 4 streams and
  *                       per-network lanes on 8 and 16, and keeps the fastest
  *                       (best_streams receives the stream count). */
 enum { PINN_BATCH_GRAPH = 1, PINN_BATCH_PER_NETWORK = 2 };
@@ -392,8 +397,10 @@ pinn_status pinn_batch_train_step(pinn_batch batch, const pinn_net *nets, const 
                                   float *const *const *mb, float *const *const *vb, const struct pinn_adam_s *hp,
                                   int64_t *step_dev, void *stream);
 pinn_status pinn_batch_launches(pinn_batch batch, int64_t *launches);
-/* The tuning of network i (0 <= i < n), as pinn_plan_get_tuning. */
+/* The tuning of network i (0 <= i < n), as pinn_plan_get_tuning; and its
+ * replacement, as pinn_plan_set_tuning (the next step rebuilds the schedule). */
 pinn_status pinn_batch_get_tuning(pinn_batch batch, int32_t i, pinn_tuning *tuning);
+pinn_status pinn_batch_set_tuning(pinn_batch batch, int32_t i, const pinn_tuning *tuning);
 /* Launch timing of one kernel class over a batch's steps, as
  * pinn_plan_profile: each grouped launch of that class is bracketed by a pair
  * of hipEvents on its lane's stream.  While a class is selected the steps run

@@ -33,7 +33,7 @@ EXPORTS = ["pinn_plan_create", "pinn_plan_destroy", "pinn_plan_memory", "pinn_je
            "pinn_batch_configure", "pinn_batch_step", "pinn_batch_autotune", "pinn_graph_capture",
            "pinn_graph_launch", "pinn_graph_destroy", "pinn_adam_step", "pinn_graph_capture_train",
            "pinn_jet_step_noalloc", "pinn_jet_backward_cot", "pinn_batch_train_step", "pinn_batch_launches",
-           "pinn_batch_profile", "pinn_batch_profile_read", "pinn_batch_get_tuning",
+           "pinn_batch_profile", "pinn_batch_profile_read", "pinn_batch_get_tuning", "pinn_batch_set_tuning",
            "pinn_tuning_cache_clear", "pinn_tuning_cache_size", "pinn_tuning_cache_save", "pinn_tuning_cache_load",
            "pinn_jet_loss", "pinn_jet_loss_backward", "pinn_batch_get_config", "pinn_plan_create_modified",
            "pinn_batch_schedule_classes"]
@@ -117,6 +117,7 @@ def _load():
     lib.pinn_batch_get_config.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.pinn_batch_schedule_classes.argtypes = [vp, ctypes.POINTER(i32), i64, i64p]
     lib.pinn_batch_get_tuning.argtypes = [vp, i32, TuneP]
+    lib.pinn_batch_set_tuning.argtypes = [vp, i32, TuneP]
     lib.pinn_batch_profile.argtypes = [vp, i32]
     lib.pinn_batch_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.pinn_tuning_cache_clear.argtypes = []
@@ -144,7 +145,7 @@ def _load():
                  "pinn_batch_step", "pinn_batch_autotune", "pinn_graph_capture", "pinn_graph_launch",
                  "pinn_graph_destroy", "pinn_adam_step", "pinn_graph_capture_train", "pinn_jet_step_noalloc",
                  "pinn_jet_backward_cot", "pinn_batch_train_step", "pinn_batch_launches", "pinn_batch_profile",
-                 "pinn_batch_profile_read", "pinn_batch_get_tuning", "pinn_tuning_cache_clear",
+                 "pinn_batch_profile_read", "pinn_batch_get_tuning", "pinn_batch_set_tuning", "pinn_tuning_cache_clear",
                  "pinn_tuning_cache_size", "pinn_tuning_cache_save", "pinn_tuning_cache_load", "pinn_jet_loss",
                  "pinn_jet_loss_backward", "pinn_batch_get_config", "pinn_plan_create_modified",
                  "pinn_batch_schedule_classes"):

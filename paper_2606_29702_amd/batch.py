@@ -148,6 +148,12 @@ class PinnBatch:
         return {"dw_splits": t.dw_splits, "fwd_points": t.fwd_points, "bwd_fused": t.bwd_fused,
                 "bwd_points": t.bwd_points}
 
+    def set_tuning(self, i: int, dw_splits: int, fwd_points: int = 0, bwd_fused: int = 1,
+                   bwd_points: int = 0) -> None:
+        """Replace network i's tuning (PinnPlan.set_tuning); the next step rebuilds the schedule."""
+        t = Tuning(int(dw_splits), int(fwd_points), int(bwd_fused), int(bwd_points))
+        check(lib.pinn_batch_set_tuning(self.handle, int(i), ctypes.byref(t)))
+
     def schedule_classes(self) -> List[str]:
         """The kernel class of every grouped launch of the current schedule, in
         launch order lane by lane (see pinn_batch_schedule_classes)."""

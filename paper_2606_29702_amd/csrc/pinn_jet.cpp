@@ -2203,6 +2203,13 @@ pinn_status pinn_batch_get_tuning(pinn_batch b, int32_t i, pinn_tuning *t) {
   return pinn_plan_get_tuning(b->plans[i], t);
 }
 
+pinn_status pinn_batch_set_tuning(pinn_batch b, int32_t i, const pinn_tuning *t) {
+  g_err.clear();
+  if (!b || !t) return fail(PINN_ERR_ARG, "batch or tuning is NULL");
+  if (i < 0 || i >= b->n) return fail(PINN_ERR_ARG, "network %d outside [0, %d)", i, b->n);
+  return pinn_plan_set_tuning(b->plans[i], t);  // the schedule key holds the tuning: the next step rebuilds
+}
+
 pinn_status pinn_batch_launches(pinn_batch b, int64_t *launches) {
   g_err.clear();
   if (!b || !launches) return fail(PINN_ERR_ARG, "batch or launches is NULL");
@@ -2245,7 +2252,6 @@ pinn_status pinn_batch_autotune(pinn_batch b, const pinn_net *nets, const pinn_p
       return fail(st, "network %d: %s", i, msg.c_str());
     }
   }
-  // then the number of lanes
   hipStream_t caller = (hipStream_t)stream;
   hipEvent_t t0, t1;
   hipError_t e = hipEventCreate(&t0);
@@ -2256,25 +2262,62 @@ pinn_status pinn_batch_autotune(pinn_batch b, const pinn_net *nets, const pinn_p
     return hip_fail(e, "autotune events");
   }
   const int graph = b->use_graph ? PINN_BATCH_GRAPH : 0;
+  // milliseconds per step of the current configuration (one untimed step first)
+  auto time_steps = [&](double *ms_out) -> pinn_status {
+    pinn_status s2 = PINN_OK;
+    for (int it = -1; it < reps && s2 == PINN_OK; ++it) {
+      if (it == 0) e = hipEventRecord(t0, caller);
+      s2 = pinn_batch_step(b, nets, pdes, x, N, loss, dW, db, stream);
+    }
+    if (s2) return s2;
+    e = hipEventRecord(t1, caller);
+    if (e == hipSuccess) e = hipEventSynchronize(t1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+    if (e) return hip_fail(e, "autotune timing");
+    *ms_out = ms / reps;
+    return PINN_OK;
+  };
+  // the member tilings: each network's own fastest, or every network on the
+  // tiling with the most points per workgroup its shape allows (in grouped
+  // launches the per-point cost counts, not a member's own latency), timed as
+  // whole grouped steps
+  {
+    std::vector<pinn_tuning> own(b->n), wide(b->n);
+    for (int i = 0; i < b->n; ++i) {
+      const pinn_plan p = b->plans[i];
+      own[i] = pinn_tuning{p->dw_splits, p->fwd_points, p->bwd_fused, p->bwd_points};
+      wide[i] = own[i];
+      if (pj::fused_fwd_fits(64, p->ki.C, p->w, p->prec)) wide[i].fwd_points = 64;
+      if (pj::bwd_dw_fused_supported(p->ki.C, p->w, p->prec)) wide[i].bwd_fused = 1;
+      if (pj::wide_bwd_points_supported(128, p->ki.C, p->w, p->prec)) wide[i].bwd_points = 128;
+    }
+    double ms_own = 1e300, ms_wide = 1e300;
+    st = pinn_batch_configure(b, 8, graph | PINN_BATCH_PER_NETWORK);
+    if (st == PINN_OK) st = time_steps(&ms_own);
+    for (int i = 0; i < b->n && st == PINN_OK; ++i) st = pinn_plan_set_tuning(b->plans[i], &wide[i]);
+    if (st == PINN_OK) st = time_steps(&ms_wide);
+    if (st == PINN_OK && ms_own <= ms_wide)
+      for (int i = 0; i < b->n && st == PINN_OK; ++i) st = pinn_plan_set_tuning(b->plans[i], &own[i]);
+    if (st) {
+      (void)hipEventDestroy(t0);
+      (void)hipEventDestroy(t1);
+      return st;
+    }
+  }
+  // then the number of lanes
   double bms = 1e300;
   int bs = b->n_streams, bmode = b->per_network ? PINN_BATCH_PER_NETWORK : 0;
   const std::pair<int, int> cands[] = {{1, 0}, {2, 0}, {4, 0}, {8, PINN_BATCH_PER_NETWORK},
                                        {16, PINN_BATCH_PER_NETWORK}};
   for (const auto &cand : cands) {
     const int ns = cand.first, mode = cand.second;
+    double ms = 1e300;
     st = pinn_batch_configure(b, ns, graph | mode);
-    for (int it = -1; it < reps && st == PINN_OK; ++it) {
-      if (it == 0) e = hipEventRecord(t0, caller);
-      st = pinn_batch_step(b, nets, pdes, x, N, loss, dW, db, stream);
-    }
+    if (st == PINN_OK) st = time_steps(&ms);
     if (st) break;
-    e = hipEventRecord(t1, caller);
-    if (e == hipSuccess) e = hipEventSynchronize(t1);
-    float ms = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
-    if (e) break;
-    if (ms / reps < bms) {
-      bms = ms / reps;
+    if (ms < bms) {
+      bms = ms;
       bs = ns;
       bmode = mode;
     }
@@ -2282,7 +2325,6 @@ pinn_status pinn_batch_autotune(pinn_batch b, const pinn_net *nets, const pinn_p
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   if (st) return st;
-  if (e) return hip_fail(e, "autotune timing");
   st = pinn_batch_configure(b, bs, graph | bmode);
   if (st) return st;
   if (best_streams) *best_streams = bs;

@@ -178,7 +178,12 @@ void ensemble(const char *path, int prec, uint64_t seed, int counter_window) {
   for (int i = 0; i < n; ++i) {
     pinn_tuning t;
     OK(pinn_batch_get_tuning(b, i, &t));
+    OK(pinn_batch_set_tuning(b, i, &t));
+    pinn_tuning bad = t;
+    bad.bwd_points = 48;
+    STATUS(pinn_batch_set_tuning(b, i, &bad), PINN_ERR_ARG);
   }
+  STATUS(pinn_batch_set_tuning(b, n, nullptr), PINN_ERR_ARG);
   int64_t launches = 0;
   OK(pinn_batch_launches(b, &launches));
   if (counter_window) {
