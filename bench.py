@@ -234,7 +234,8 @@ def ensemble_headline(ens, params, xs, prec, steps, warmup, runs, replays, count
         batch.step(params, xs)
     dom_ms, dom_n = batch.profile_read()
     batch.profile("off")
-    batch.configure(cfg["streams"], use_graph=cfg["graph"], per_network=cfg["per_network"])
+    batch.configure(cfg["streams"], use_graph=cfg["graph"], per_network=cfg["per_network"],
+                    width_lanes=cfg["width_lanes"])
     batch.step(params, xs)
     tunings = [batch.tuning(i) for i in range(len(ens))]
     launches = batch.launches()

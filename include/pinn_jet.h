@@ -363,7 +363,14 @@ pinn_status pinn_tuning_cache_load(const char *path);
  *                       PINN_BATCH_PER_NETWORK makes the lanes the streams
  *                       themselves, networks dealt to them longest first by
  *                       estimated work (without it: one lane per hidden
- *                       width, widths beyond the stream count sharing lanes).
+ *                       width, widths beyond the stream count sharing lanes);
+ *                       PINN_BATCH_WIDTH_LANES (with PINN_BATCH_PER_NETWORK)
+ *                       keeps each lane to networks of one width: every width
+ *                       gets a lane, the remaining lanes go one at a time to
+ *                       the width with the most estimated work per lane, and
+ *                       each width's networks are dealt to its lanes longest
+ *                       first (when there are fewer streams than widths, the
+ *                       flag has no effect).
  *   pinn_batch_launches  grouped launches per step of the current schedule.
  *   pinn_batch_autotune  runs pinn_plan_autotune on every network (networks
  *                       sharing a cache key are timed once); then times
@@ -372,10 +379,12 @@ pinn_status pinn_tuning_cache_load(const char *path);
  *                       most points per workgroup its shape allows (forward
  *                       64 points, fused weight gradient, wide backward 128
  *                       points, where supported) and keeps the faster; then
- *                       times width lanes on 1, 2 and 4 streams and
- *                       per-network lanes on 8 and 16, and keeps the fastest
- *                       (best_streams receives the stream count). */
-enum { PINN_BATCH_GRAPH = 1, PINN_BATCH_PER_NETWORK = 2 };
+ *                       times width lanes on 1, 2 and 4 streams, per-network
+ *                       lanes on 8 and 16, and per-network lanes by width on
+ *                       8, 12 and 16, and keeps the fastest (best_streams
+ *                       receives the stream count; pinn_batch_get_config the
+ *                       flags). */
+enum { PINN_BATCH_GRAPH = 1, PINN_BATCH_PER_NETWORK = 2, PINN_BATCH_WIDTH_LANES = 4 };
 pinn_status pinn_batch_create(int32_t n, const pinn_net *nets, const pinn_pde *pdes, const int64_t *max_points,
                               int32_t prec, uint32_t flags, pinn_batch *out);
 pinn_status pinn_batch_destroy(pinn_batch batch);

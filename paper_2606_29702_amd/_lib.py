@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "PINN_OK", -1: "PINN_ERR_ARG", -2: "PINN_ERR_UNSUPPORTED", -3
 KINDS = {"burgers": 1, "ns": 2, "ks": 3, "heat": 4, "aniso": 5, "burgers_bc": 6}
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
 PINN_VERIFY_F64 = 1
-PINN_BATCH_GRAPH, PINN_BATCH_PER_NETWORK = 1, 2
+PINN_BATCH_GRAPH, PINN_BATCH_PER_NETWORK, PINN_BATCH_WIDTH_LANES = 1, 2, 4
 
 # Every symbol the public header declares.
 EXPORTS = ["pinn_plan_create", "pinn_plan_destroy", "pinn_plan_memory", "pinn_jet_forward",

@@ -66,16 +66,21 @@ class PinnBatch:
         except Exception:
             pass
 
-    def configure(self, n_streams: int, use_graph: bool = True, per_network: bool = False) -> None:
-        flags = (_lib.PINN_BATCH_GRAPH if use_graph else 0) | (_lib.PINN_BATCH_PER_NETWORK if per_network else 0)
+    def configure(self, n_streams: int, use_graph: bool = True, per_network: bool = False,
+                  width_lanes: bool = False) -> None:
+        """Streams (lanes) and flags of the schedule; width_lanes (with
+        per_network) keeps each lane to networks of one width."""
+        flags = (_lib.PINN_BATCH_GRAPH if use_graph else 0) | (_lib.PINN_BATCH_PER_NETWORK if per_network else 0) | \
+            (_lib.PINN_BATCH_WIDTH_LANES if width_lanes else 0)
         check(lib.pinn_batch_configure(self.handle, int(n_streams), flags))
 
     def config(self) -> dict:
-        """{'streams', 'graph', 'per_network'} of the current schedule."""
+        """{'streams', 'graph', 'per_network', 'width_lanes'} of the current schedule."""
         ns, fl = ctypes.c_int32(), ctypes.c_int32()
         check(lib.pinn_batch_get_config(self.handle, ctypes.byref(ns), ctypes.byref(fl)))
         return {"streams": ns.value, "graph": bool(fl.value & _lib.PINN_BATCH_GRAPH),
-                "per_network": bool(fl.value & _lib.PINN_BATCH_PER_NETWORK)}
+                "per_network": bool(fl.value & _lib.PINN_BATCH_PER_NETWORK),
+                "width_lanes": bool(fl.value & _lib.PINN_BATCH_WIDTH_LANES)}
 
     def _marshal(self, params_list, xs):
         key = tuple(t.data_ptr() for ps in params_list for pair in ps for t in pair) + \

@@ -1707,6 +1707,7 @@ struct pinn_batch_s {
   hipStream_t origin = nullptr;       // capture origin
   bool use_graph = true;
   bool per_network = false;           // lanes: by hidden width, or networks balanced over the streams
+  bool width_lanes = false;           // per-network lanes that each hold networks of one width
   hipGraphExec_t exec = nullptr;
   std::vector<const void *> key;      // every pointer and size baked into the schedule
   // the schedule
@@ -1897,12 +1898,19 @@ pinn_status batch_build(pinn_batch b, const pinn_net *nets, const pinn_pde *pdes
   if (e) return hip_fail(e, "batch argument table");
   // lanes: one per hidden width (widths in increasing order), folded onto the
   // streams; or, per network, the networks dealt longest first to the lane
-  // with the least estimated work (hidden-layer flops w^2 C H N)
+  // with the least estimated work (hidden-layer flops w^2 C H N); or, per
+  // network by width, the lanes shared out to the widths (one each, the rest
+  // one at a time to the width with the most work per lane) and each width's
+  // networks dealt to its lanes the same way, so that a lane's networks run
+  // the same kernels and group at every phase
   std::vector<std::vector<int>> members;
+  std::vector<int> widths(b->width);
+  std::sort(widths.begin(), widths.end());
+  widths.erase(std::unique(widths.begin(), widths.end()), widths.end());
+  const int n_widths = (int)widths.size();
   if (b->per_network) {
     const int n_lanes = std::min(b->n, b->n_streams);
-    members.assign(n_lanes, {});
-    std::vector<double> cost(b->n), load(n_lanes, 0.0);
+    std::vector<double> cost(b->n);
     std::vector<int> order(b->n);
     for (int i = 0; i < b->n; ++i) {
       const pinn_plan p = b->plans[i];
@@ -1910,17 +1918,42 @@ pinn_status batch_build(pinn_batch b, const pinn_net *nets, const pinn_pde *pdes
       order[i] = i;
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+    // the lanes each width may use: all of them, or its share
+    std::vector<int> lane0(n_widths, 0), nl(n_widths, n_lanes);
+    if (b->width_lanes && n_lanes >= n_widths) {
+      std::vector<double> work(n_widths, 0.0);
+      std::vector<int> count(n_widths, 0);
+      for (int i = 0; i < b->n; ++i) {
+        const int wi = (int)(std::lower_bound(widths.begin(), widths.end(), b->width[i]) - widths.begin());
+        work[wi] += cost[i];
+        ++count[wi];
+      }
+      std::fill(nl.begin(), nl.end(), 1);
+      for (int extra = n_lanes - n_widths; extra > 0; --extra) {
+        int best = -1;
+        for (int k = 0; k < n_widths; ++k)
+          if (nl[k] < count[k] && (best < 0 || work[k] / nl[k] > work[best] / nl[best])) best = k;
+        if (best < 0) break;
+        ++nl[best];
+      }
+      for (int k = 1; k < n_widths; ++k) lane0[k] = lane0[k - 1] + nl[k - 1];
+    }
+    const int total = b->width_lanes && n_lanes >= n_widths ? lane0[n_widths - 1] + nl[n_widths - 1] : n_lanes;
+    members.assign(total, {});
+    std::vector<double> load(total, 0.0);
     for (int i : order) {
-      const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      int k = 0;
+      if (b->width_lanes && n_lanes >= n_widths)
+        k = (int)(std::lower_bound(widths.begin(), widths.end(), b->width[i]) - widths.begin());
+      const int lo = b->width_lanes && n_lanes >= n_widths ? lane0[k] : 0;
+      const int hi = b->width_lanes && n_lanes >= n_widths ? lane0[k] + nl[k] : total;
+      const int l = (int)(std::min_element(load.begin() + lo, load.begin() + hi) - load.begin());
       members[l].push_back(i);
       load[l] += cost[i];
     }
     for (auto &m : members) std::sort(m.begin(), m.end());
   } else {
-    std::vector<int> widths(b->width);
-    std::sort(widths.begin(), widths.end());
-    widths.erase(std::unique(widths.begin(), widths.end()), widths.end());
-    const int n_lanes = std::min<int>((int)widths.size(), b->n_streams);
+    const int n_lanes = std::min<int>(n_widths, b->n_streams);
     members.assign(n_lanes, {});
     for (int i = 0; i < b->n; ++i) {
       const int wi = (int)(std::lower_bound(widths.begin(), widths.end(), b->width[i]) - widths.begin());
@@ -2048,7 +2081,7 @@ pinn_status batch_run(pinn_batch b, const pinn_net *nets, const pinn_pde *pdes, 
     }
   }
   key.push_back(reinterpret_cast<const void *>((intptr_t)b->n_streams));
-  key.push_back(reinterpret_cast<const void *>((intptr_t)b->per_network));
+  key.push_back(reinterpret_cast<const void *>((intptr_t)(b->per_network * 2 + b->width_lanes)));
   hipStream_t caller = (hipStream_t)stream;
   if (b->lanes.empty() || key != b->key) {
     st = batch_build(b, nets, pdes, x, N, loss, dW, db, train);
@@ -2134,12 +2167,15 @@ pinn_status pinn_batch_configure(pinn_batch b, int32_t n_streams, int32_t use_gr
   if (!b) return fail(PINN_ERR_ARG, "batch is NULL");
   if (n_streams < 1 || n_streams > kMaxBatchStreams)
     return fail(PINN_ERR_ARG, "n_streams = %d outside [1, %d]", n_streams, kMaxBatchStreams);
-  if (use_graph & ~(PINN_BATCH_GRAPH | PINN_BATCH_PER_NETWORK))
+  if (use_graph & ~(PINN_BATCH_GRAPH | PINN_BATCH_PER_NETWORK | PINN_BATCH_WIDTH_LANES))
     return fail(PINN_ERR_ARG, "unknown batch flags 0x%x", use_graph);
+  if ((use_graph & PINN_BATCH_WIDTH_LANES) && !(use_graph & PINN_BATCH_PER_NETWORK))
+    return fail(PINN_ERR_ARG, "PINN_BATCH_WIDTH_LANES needs PINN_BATCH_PER_NETWORK");
   hipError_t e = batch_streams(b, n_streams);
   if (e) return hip_fail(e, "batch streams");
   b->use_graph = (use_graph & PINN_BATCH_GRAPH) != 0;
   b->per_network = (use_graph & PINN_BATCH_PER_NETWORK) != 0;
+  b->width_lanes = (use_graph & PINN_BATCH_WIDTH_LANES) != 0;
   invalidate(b);
   return PINN_OK;
 }
@@ -2148,7 +2184,8 @@ pinn_status pinn_batch_get_config(pinn_batch b, int32_t *n_streams, int32_t *fla
   g_err.clear();
   if (!b || !n_streams || !flags) return fail(PINN_ERR_ARG, "a pinn_batch_get_config argument is NULL");
   *n_streams = b->n_streams;
-  *flags = (b->use_graph ? PINN_BATCH_GRAPH : 0) | (b->per_network ? PINN_BATCH_PER_NETWORK : 0);
+  *flags = (b->use_graph ? PINN_BATCH_GRAPH : 0) | (b->per_network ? PINN_BATCH_PER_NETWORK : 0) |
+           (b->width_lanes ? PINN_BATCH_WIDTH_LANES : 0);
   return PINN_OK;
 }
 
@@ -2307,9 +2344,11 @@ pinn_status pinn_batch_autotune(pinn_batch b, const pinn_net *nets, const pinn_p
   }
   // then the number of lanes
   double bms = 1e300;
-  int bs = b->n_streams, bmode = b->per_network ? PINN_BATCH_PER_NETWORK : 0;
+  int bs = b->n_streams,
+      bmode = (b->per_network ? PINN_BATCH_PER_NETWORK : 0) | (b->width_lanes ? PINN_BATCH_WIDTH_LANES : 0);
+  constexpr int PW = PINN_BATCH_PER_NETWORK | PINN_BATCH_WIDTH_LANES;
   const std::pair<int, int> cands[] = {{1, 0}, {2, 0}, {4, 0}, {8, PINN_BATCH_PER_NETWORK},
-                                       {16, PINN_BATCH_PER_NETWORK}};
+                                       {16, PINN_BATCH_PER_NETWORK}, {8, PW}, {12, PW}, {16, PW}};
   for (const auto &cand : cands) {
     const int ns = cand.first, mode = cand.second;
     double ms = 1e300;

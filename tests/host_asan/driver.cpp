@@ -205,13 +205,14 @@ void ensemble(const char *path, int prec, uint64_t seed, int counter_window) {
     OK(pinn_batch_train_step(b, nv.data(), pdes.data(), xs.data(), Ns.data(), loss, dWs.data(), dbs.data(),
                              mWs.data(), vWs.data(), mbs.data(), vbs.data(), &hp, step, nullptr));
   // every lane configuration
-  for (int s : {1, 2, 3, 8, 16})
-    for (int flags : {0, 1, 2, 3}) {
+  for (int s : {1, 2, 3, 4, 5, 8, 12, 16})
+    for (int flags : {0, 1, 2, 3, 6, 7}) {
       OK(pinn_batch_configure(b, s, flags));
       OK(pinn_batch_step(b, nv.data(), pdes.data(), xs.data(), Ns.data(), loss, dWs.data(), dbs.data(), nullptr));
     }
   STATUS(pinn_batch_configure(b, 17, 0), PINN_ERR_ARG);
-  STATUS(pinn_batch_configure(b, 2, 4), PINN_ERR_ARG);
+  STATUS(pinn_batch_configure(b, 2, 4), PINN_ERR_ARG);  // width lanes without per-network lanes
+  STATUS(pinn_batch_configure(b, 2, 8), PINN_ERR_ARG);
   OK(pinn_batch_destroy(b));
   dev_free(step);
   dev_free(loss);

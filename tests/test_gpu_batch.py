@@ -69,15 +69,19 @@ def test_batch_graph_replays_match_eager_and_single_plans(lib, prec):
         assert np.array_equal(loss.cpu().numpy(), eager[0]), rep
         for i in range(len(ens)):
             assert np.array_equal(flat(grads[i]), eager[1][i]), (rep, i)
-    # networks dealt to per-network lanes: the same results
-    batch.configure(3, use_graph=True, per_network=True)
-    assert batch.config() == {"streams": 3, "graph": True, "per_network": True}
-    for rep in range(2):
-        loss, grads = batch.step(params, xs)
-        torch.cuda.synchronize()
-        assert np.array_equal(loss.cpu().numpy(), eager[0]), rep
-        for i in range(len(ens)):
-            assert np.array_equal(flat(grads[i]), eager[1][i]), (rep, i)
+    # networks dealt to per-network lanes, and to lanes kept to one width:
+    # the same results
+    for ns, wl in ((3, False), (5, True), (2, True)):
+        batch.configure(ns, use_graph=True, per_network=True, width_lanes=wl)
+        assert batch.config() == {"streams": ns, "graph": True, "per_network": True, "width_lanes": wl}
+        for rep in range(2):
+            loss, grads = batch.step(params, xs)
+            torch.cuda.synchronize()
+            assert np.array_equal(loss.cpu().numpy(), eager[0]), (ns, wl, rep)
+            for i in range(len(ens)):
+                assert np.array_equal(flat(grads[i]), eager[1][i]), (ns, wl, rep, i)
+    with pytest.raises(lib.PinnError):  # width lanes are per-network lanes
+        batch.configure(4, use_graph=True, per_network=False, width_lanes=True)
     for i in range(len(ens)):
         assert eager[0][i] == np.float32(ref_loss[i])
         assert np.array_equal(eager[1][i], ref_g[i]), i
@@ -107,9 +111,10 @@ def test_batch_recaptures_on_new_inputs_and_autotunes(lib):
     g2 = [flat(g) for g in grads2]
     np.testing.assert_allclose(loss2.cpu().numpy(), l1, rtol=1e-4)
     ns, ms = batch.autotune(params, xs2, reps=2)
-    assert ns in (1, 2, 4, 8, 16) and ms > 0
+    assert ns in (1, 2, 4, 8, 12, 16) and ms > 0
     cfg = batch.config()
     assert cfg["streams"] == ns and cfg["graph"] and (cfg["per_network"] == (ns >= 8))
+    assert not cfg["width_lanes"] or cfg["per_network"]
     # the autotuner may pick other tilings and split counts per member, which
     # reorders sums: close to the earlier step, and steps with the tuned
     # schedule repeat bit for bit
