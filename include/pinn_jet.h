@@ -295,8 +295,8 @@ pinn_status pinn_plan_create_modified(const pinn_modified *arch, const pinn_pde 
  *               operands): 0 = the default; 16 = 16 points per workgroup with
  *               the LDS chunks double-buffered (up to 8 channels); 32 or 64
  *               points per workgroup (up to 6 channels), each weight fragment
- *               then serving two or four 16-point tiles; 128 (width 256, up
- *               to 6 channels) = eight 16-point tiles per workgroup streamed
+ *               then serving two or four 16-point tiles; 256 (width 256, up
+ *               to 6 channels) = sixteen 16-point tiles per workgroup streamed
  *               through LDS with the weights held in registers and the next
  *               tile's loads in flight during the current tile's MFMAs. */
 typedef struct {
@@ -377,7 +377,7 @@ pinn_status pinn_tuning_cache_load(const char *path);
  *                       `reps` grouped steps with those tilings against the
  *                       same steps with every network on the tiling with the
  *                       most points per workgroup its shape allows (forward
- *                       64 points, fused weight gradient, wide backward 128
+ *                       64 points, fused weight gradient, wide backward 256
  *                       points, where supported) and keeps the faster; then
  *                       times width lanes on 1, 2 and 4 streams, per-network
  *                       lanes on 8 and 16, and per-network lanes by width on

@@ -22,7 +22,7 @@ hipError_t launch_layer_fwd(int kind, int prec, const void *A_in, const void *Wo
 bool wide_bwd_points_supported(int points, int C, int w, int prec) {
   if (prec == P_FP32 || w < 256 || w % 128 != 0) return false;
   if (points == 16) return C <= 8;  // the double-buffered 16-point kernel
-  if (points == 128) return w == 256 && C <= 6;  // the streaming kernel with weights in registers
+  if (points == 256) return w == 256 && C <= 6;  // the streaming kernel with weights in registers
   return (points == 32 || points == 64) && C <= 6;
 }
 

@@ -940,11 +940,11 @@ hipError_t launch_bwd_t(const BwdArgs &a, int64_t N_pad, int points, hipStream_t
     // fragment across two or four point tiles (16-bit operands, up to 6
     // channels); chunks of 64 neurons at 64 points keep the LDS in bounds
     if constexpr (sizeof(T) == 2 && CH::C <= 6) {
-      if (points == 128 && w == 256 && N_pad == (a.N + kPointTile - 1) / kPointTile * kPointTile) {
-        // eight 16-point tiles per workgroup, weights in registers, staging pipelined
+      if (points == 256 && w == 256 && N_pad == (a.N + kPointTile - 1) / kPointTile * kPointTile) {
+        // sixteen 16-point tiles per workgroup, weights in registers, staging pipelined
         const size_t lds = (size_t)tiles * 16 * (CH::C * 256 + 8) * sizeof(T);
-        const dim3 grid((unsigned)((N_pad / 16 + 7) / 8 * (256 / 128)));
-        return launch_body<KLayerBwdKs<CH, T, 8, 256, TOP, DOUT, ZSRC, 1, 8>>({a}, grid, lds, st);
+        const dim3 grid((unsigned)((N_pad / 16 + 15) / 16 * (256 / 128)));
+        return launch_body<KLayerBwdKs<CH, T, 8, 256, TOP, DOUT, ZSRC, 1, 16>>({a}, grid, lds, st);
       }
       if (points == 32) {
         const size_t lds = (size_t)tiles * 32 * (CH::C * 128 + 8) * sizeof(T);

@@ -1350,7 +1350,7 @@ pinn_status pinn_plan_autotune(pinn_plan plan, const pinn_net *net, const pinn_p
   for (int sp : {std::max(1, s0 / 2), s0, std::min(p->dw_splits_max, 2 * s0)})
     for (int fp : {0, 16, 32, 64})
     for (int bf : {0, 1})
-    for (int bp : {0, 32, 64, 128}) {  // 16 (double-buffered) measured slower at 4 and 6 channels
+    for (int bp : {0, 32, 64, 256}) {  // 16 (double-buffered) measured slower at 4 and 6 channels
       // 0 (layer-by-layer forward) only when no whole-network tiling exists
       const bool any_fused = pj::fused_fwd_points(p->ki.C, p->w, p->prec) > 0;
       if (fp == 0 ? any_fused : !pj::fused_fwd_fits(fp, p->ki.C, p->w, p->prec)) continue;
@@ -1461,7 +1461,7 @@ pinn_status pinn_tuning_cache_load(const char *path) {
                              &k.nbucket, &v.split_mode, &v.fwd_points, &v.bwd_fused, &v.ms, &v.bwd_points);
     if ((got_n != 10 && got_n != 11) || v.split_mode < 0 || v.split_mode > 2 || (v.bwd_fused != 0 && v.bwd_fused != 1) ||
         (v.bwd_points != 0 && v.bwd_points != 16 && v.bwd_points != 32 && v.bwd_points != 64 &&
-         v.bwd_points != 128)) {
+         v.bwd_points != 256)) {
       fclose(f);
       return fail(PINN_ERR_ARG, "%s:%d: malformed tuning cache entry", path, lineno);
     }
@@ -2327,7 +2327,7 @@ pinn_status pinn_batch_autotune(pinn_batch b, const pinn_net *nets, const pinn_p
       wide[i] = own[i];
       if (pj::fused_fwd_fits(64, p->ki.C, p->w, p->prec)) wide[i].fwd_points = 64;
       if (pj::bwd_dw_fused_supported(p->ki.C, p->w, p->prec)) wide[i].bwd_fused = 1;
-      if (pj::wide_bwd_points_supported(128, p->ki.C, p->w, p->prec)) wide[i].bwd_points = 128;
+      if (pj::wide_bwd_points_supported(256, p->ki.C, p->w, p->prec)) wide[i].bwd_points = 256;
     }
     double ms_own = 1e300, ms_wide = 1e300;
     st = pinn_batch_configure(b, 8, graph | PINN_BATCH_PER_NETWORK);

@@ -558,7 +558,7 @@ def test_forward_tilings_agree_bitwise(lib, pde, dims, prec):
 def test_wide_backward_tilings_agree(lib, pde, dims, prec):
     """The wide-layer backward kernel with 16 points per workgroup (single- or
     double-buffered chunks), 32 and 64 (two or four point tiles sharing every
-    weight fragment), and the streaming form at width 256 (eight 16-point
+    weight fragment), and the streaming form at width 256 (sixteen 16-point
     tiles per workgroup, weights in registers): the same per-element
     arithmetic, so the gradients agree bit for bit with BF16 operands and to
     FP16 rounding with FP16 ones; the 64-point and streaming tilings against
@@ -573,7 +573,7 @@ def test_wide_backward_tilings_agree(lib, pde, dims, prec):
     plan = lib.PinnPlan(dims, pde, N, precision=prec, coef=prob.coef)
     t = plan.tuning()
     grads = {}
-    tilings = (0, 16, 32, 64) + ((128,) if dims[1] == 256 and len(prob.channels) <= 6 else ())
+    tilings = (0, 16, 32, 64) + ((256,) if dims[1] == 256 and len(prob.channels) <= 6 else ())
     for bp in tilings:
         plan.set_tuning(t["dw_splits"], t["fwd_points"], t["bwd_fused"], bp)
         plan.residual(params, x)
