@@ -282,7 +282,10 @@ pinn_status pinn_plan_create_modified(const pinn_modified *arch, const pinn_pde 
  * workgroup shapes, never the arithmetic: every setting is deterministic and
  * agrees with the others to rounding.
  *   dw_splits   number of split-K partials of each hidden-layer weight gradient
- *               (1 .. twice the plan's default)
+ *               (1 .. twice the plan's default); with the fused weight
+ *               gradient, the persistent backward kernels run
+ *               min(2 dw_splits, twice the default, 512, tiles) workgroups,
+ *               one partial each
  *   fwd_points  points per workgroup of the whole-network forward kernel
  *               (0 = the default tiling; else 16, 32, or for 16-bit operands
  *               at widths 64-256 also 64, where each wave works on four
@@ -379,6 +382,9 @@ pinn_status pinn_tuning_cache_load(const char *path);
  *                       most points per workgroup its shape allows (forward
  *                       64 points, fused weight gradient, wide backward 256
  *                       points, where supported) and keeps the faster; then
+ *                       the kept tilings with every network's split count
+ *                       halved, then quartered (fewer, larger weight-gradient
+ *                       partials), while that is faster; then
  *                       times width lanes on 1, 2 and 4 streams, per-network
  *                       lanes on 8 and 16, and per-network lanes by width on
  *                       8, 12 and 16, and keeps the fastest (best_streams

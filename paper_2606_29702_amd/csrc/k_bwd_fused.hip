@@ -274,8 +274,10 @@ struct KBwdDw {
   }
 };
 
-// Double-buffered form of k_bwd_dw for 16-bit operands below the top layer,
-// with z recomputed from A_{m-1}.  The tiles are stored in LDS without row
+// Double-buffered form of k_bwd_dw for 16-bit operands, with z recomputed
+// from A_{m-1}.  At the top layer only A_{H-1} is staged (abar = W_L^T ubar
+// is one FP32 MFMA per neuron tile and channel), and the Zbar half of each
+// buffer pair receives Zbar_H for the gradient.  The tiles are stored in LDS without row
 // padding: 16-byte piece c of row p sits at piece position c ^ p of that row
 // (rows of a multiple of 16 pieces), which keeps the 16 points of an MFMA
 // operand read on different banks.  While a tile's jet adjoint and dW run,
@@ -351,7 +353,7 @@ __device__ __forceinline__ void swz_gemm(f32x4 (&acc)[TPW][C], const T *__restri
   }
 }
 
-template <class CH, class T, int W, int NW, int TPW, int DOUT>
+template <class CH, class T, int W, int NW, int TPW, int DOUT, bool TOP>
 struct KBwdDwDb {
   static constexpr int NT = NW * 64;
   struct Args {
@@ -363,12 +365,11 @@ struct KBwdDwDb {
     const BwdArgs &args = a_.args;
     float *__restrict__ part = a_.part;
     int64_t n_tiles = a_.n_tiles;
-    using M = Mma<T>;
     using M16 = Mma16<T>;
     using L = SwzTile<T, CH::C, W>;
     constexpr int C = CH::C, P = 16;
     constexpr int JW = W / NW;
-    constexpr int JT = JW / 16, KT = W / 16, KS = W / 32;
+    constexpr int JT = JW / 16, KT = W / 16;
     constexpr int ROWS = P * C;
     static_assert(JW % 16 == 0 && ROWS % 16 == 0, "tile shape");
     // two buffer pairs [Zbar][A] as separate objects, so that the compiler can
@@ -392,9 +393,17 @@ struct KBwdDwDb {
       for (int b = 0; b < KT; ++b) dacc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
     float db = 0.f;
 
+    // top layer: this lane's W_L^T operand of each neuron tile, row r, output g
+    [[maybe_unused]] float wl[TOP ? TPW : 1];
+    if constexpr (TOP) {
+      static_assert(DOUT <= 4, "output contraction on one MFMA 16x16x4");
+  #pragma unroll
+      for (int t = 0; t < TPW; ++t) wl[t] = g < DOUT ? args.WL[g * W + (jt0 + t) * 16 + r] : 0.f;
+    }
+
     if (vb.x < n_tiles) {
       const int64_t nb = (int64_t)vb.x * P;
-      prefetch_tile<T, C, W, NW>(pair0, Zb_in + nb * ps, wave, lane);
+      if constexpr (!TOP) prefetch_tile<T, C, W, NW>(pair0, Zb_in + nb * ps, wave, lane);
       prefetch_tile<T, C, W, NW>(pair0 + L::ELEMS, A_prev + nb * ps, wave, lane);
     }
     __builtin_amdgcn_s_waitcnt(0);
@@ -408,8 +417,24 @@ struct KBwdDwDb {
 
       // the GEMMs (their weight fragments stream from L2 ahead of use)
       f32x4 acc_a[TPW][C], acc_z[TPW][C];
-      swz_gemm<T, C, TPW, W>(acc_a, WT, zb_t, jt0, lane);
-      swz_gemm<T, C, TPW, W>(acc_z, Wz, a_t, jt0, lane);
+      if constexpr (TOP) {
+        // abar = W_L^T ubar contracts over the DOUT <= 4 outputs: one FP32
+        // MFMA 16x16x4 per neuron tile and channel, output o = lane group g
+        // (zero beyond DOUT).  The ubar loads are issued before the z GEMM.
+        float ub[C];
+        const int64_t n = nb + r;
+  #pragma unroll
+        for (int c = 0; c < C; ++c) ub[c] = g < DOUT ? args.ubar[(n * DOUT + g) * C + c] : 0.f;
+        swz_gemm<T, C, TPW, W>(acc_z, Wz, a_t, jt0, lane);
+  #pragma unroll
+        for (int t = 0; t < TPW; ++t)
+  #pragma unroll
+          for (int c = 0; c < C; ++c)
+            acc_a[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(wl[t], ub[c], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      } else {
+        swz_gemm<T, C, TPW, W>(acc_a, WT, zb_t, jt0, lane);
+        swz_gemm<T, C, TPW, W>(acc_z, Wz, a_t, jt0, lane);
+      }
       // tanh of the recomputed z_0 (with the bias, a global load) before the
       // prefetch below is issued: the load counter completes in order, so any
       // load waited on after the prefetch would wait for the prefetch too
@@ -430,7 +455,7 @@ struct KBwdDwDb {
       __builtin_amdgcn_s_waitcnt(0);
       const int64_t next = tile + vb.gx;
       if (next < n_tiles) {
-        prefetch_tile<T, C, W, NW>(nxt, Zb_in + next * P * ps, wave, lane);
+        if constexpr (!TOP) prefetch_tile<T, C, W, NW>(nxt, Zb_in + next * P * ps, wave, lane);
         prefetch_tile<T, C, W, NW>(nxt + L::ELEMS, A_prev + next * P * ps, wave, lane);
       }
 
@@ -526,8 +551,8 @@ template <class CH, class T, int W, bool TOP, int DOUT, int ZSRC>
 hipError_t launch_w(const BwdArgs &a, float *part, int64_t n_tiles, int grid, hipStream_t st) {
   constexpr int NW = W == 32 ? 2 : (W == 256 ? 8 : 4);
   constexpr int TPW = (W / 16) / NW;
-  if constexpr (!TOP && ZSRC == Z_FROM_GEMM && bwd_db_ok<T>(CH::C, W))
-    return launch_body<KBwdDwDb<CH, T, W, NW, TPW, DOUT>>({a, part, n_tiles}, dim3((unsigned)grid), 0, st);
+  if constexpr (ZSRC == Z_FROM_GEMM && bwd_db_ok<T>(CH::C, W))
+    return launch_body<KBwdDwDb<CH, T, W, NW, TPW, DOUT, TOP>>({a, part, n_tiles}, dim3((unsigned)grid), 0, st);
   constexpr size_t lds = (size_t)2 * 16 * (CH::C * W + 8) * sizeof(T);
   return launch_body<KBwdDw<CH, T, W, NW, TPW, TOP, DOUT, ZSRC>>({a, part, n_tiles}, dim3((unsigned)grid), lds, st);
 }

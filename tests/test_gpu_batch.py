@@ -129,6 +129,18 @@ def test_batch_recaptures_on_new_inputs_and_autotunes(lib):
     assert np.array_equal(loss4.cpu().numpy(), l3)
     for a, g in zip(g3, grads4):
         assert np.array_equal(a, flat(g))
+    # each member's tuned tiling and split count give the same bits on a plan
+    # of its own
+    for i, m in enumerate(ens):
+        t = batch.tuning(i)
+        plan = lib.PinnPlan(m.dims, "burgers", m.N, precision="bf16", coef=(m.nu,))
+        plan.set_tuning(**t)
+        _, l1, _, _ = plan.residual(params[i], xs2[i])
+        g1 = plan.backward(params[i], xs2[i])
+        torch.cuda.synchronize()
+        assert float(l1) == float(l3[i]), (i, t)
+        assert np.array_equal(flat(g1), g3[i]), (i, t)
+        plan.close()
     batch.close()
 
 

@@ -36,6 +36,9 @@ TILE_BAR = {"fp32": {"r": 1e-5, "jets": 1e-5}, "bf16": {"r": 2.5e-2, "jets": 2.5
 ONE_TILE_BAR = {"fp32": 1e-5, "bf16": 3e-2, "fp16": 5e-3}
 # gradient additivity: FP32 accumulation order only
 ADD_BAR = 1e-5
+# the fused backward at other grid sizes: FP32 order of the partial sums only
+# (measured 5.5e-6 with 2 workgroups, each accumulating 2048 tiles)
+GRID_BAR = 2e-5
 
 
 @pytest.fixture(scope="module")
@@ -137,3 +140,37 @@ def test_gradient_additivity(lib, ns, prec):
     assert share >= 20 * ADD_BAR  # a dropped or doubled tile would show
     plan.close()
     half.close()
+
+
+def test_fused_backward_grid_sizes(lib, ns):
+    """The persistent fused backward runs twice the split count of workgroups
+    (at most 512); each visits tiles blockIdx.x, blockIdx.x + gridDim.x, ...
+    and writes one weight-gradient partial.  Grids of 2, 6 and 80 workgroups
+    (every workgroup wraps many times, and the ragged last tile falls on
+    different workgroups) give the default grid's gradient up to the FP32
+    order of the partial sums, and the same residual."""
+    prob, params, x = ns
+    N = prob.x.shape[0] - 5
+    xs = x[:N].contiguous()
+    plan = lib.PinnPlan(prob.workload.dims, "ns", N, precision="bf16", coef=prob.coef)
+    t0 = plan.tuning()
+    assert t0["bwd_fused"] == 1
+    rb = torch.tensor(np.random.default_rng(83).normal(size=(3, N)).astype(np.float32), device="cuda")
+
+    def run():
+        r, _, _, _ = plan.residual(params, xs)
+        g = flat(plan.backward(params, xs, r_bar=rb))
+        torch.cuda.synchronize()
+        return r.cpu().numpy(), g
+
+    r_ref, g_ref = run()
+    for ds in (1, 3, 40):
+        plan.set_tuning(**{**t0, "dw_splits": ds})
+        r, g = run()
+        e = rel(g, g_ref)
+        print(f"dw_splits {ds} (grid {2 * ds}): gradient vs the default grid {e:.2e}")
+        assert np.array_equal(r, r_ref)
+        assert e <= GRID_BAR, (ds, e)
+        _, g2 = run()
+        assert np.array_equal(g, g2)  # deterministic at every grid
+    plan.close()
