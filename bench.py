@@ -831,12 +831,6 @@ def main():
         log(f"fp32 sequential: {f32_ms:.3f} ms/step (batched {prec} is {f32_ms / ms:.2f}x)")
         out["accuracy_vs_oracle"] = ensemble_accuracy(ens, prec)
         log(f"accuracy: {out['accuracy_vs_oracle']}")
-        if prec != "fp16":  # the other 16-bit operand type, same MFMA peak, no split weights
-            f16 = ensemble_headline(ens, params, xs, "fp16", max(5, args.steps // 2), 2, 1, 20)
-            out["ensemble_fp16"] = {"ms_per_step": round(f16["ms"], 4),
-                                    "value": round(total_N / (f16["ms"] * 1e-3), 1), "unit": "pts/s",
-                                    "accuracy_vs_oracle": ensemble_accuracy(ens, "fp16")}
-            log(f"fp16 grouped ensemble: {out['ensemble_fp16']}")
 
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)

@@ -382,9 +382,6 @@ pinn_status pinn_tuning_cache_load(const char *path);
  *                       most points per workgroup its shape allows (forward
  *                       64 points, fused weight gradient, wide backward 256
  *                       points, where supported) and keeps the faster; then
- *                       the kept tilings with every network's split count
- *                       halved, then quartered (fewer, larger weight-gradient
- *                       partials), while that is faster; then
  *                       times width lanes on 1, 2 and 4 streams, per-network
  *                       lanes on 8 and 16, and per-network lanes by width on
  *                       8, 12 and 16, and keeps the fastest (best_streams

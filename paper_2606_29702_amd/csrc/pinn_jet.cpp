@@ -2336,28 +2336,8 @@ pinn_status pinn_batch_autotune(pinn_batch b, const pinn_net *nets, const pinn_p
     if (st == PINN_OK) st = time_steps(&ms_own);
     for (int i = 0; i < b->n && st == PINN_OK; ++i) st = pinn_plan_set_tuning(b->plans[i], &wide[i]);
     if (st == PINN_OK) st = time_steps(&ms_wide);
-    const std::vector<pinn_tuning> base = ms_own <= ms_wide ? own : wide;
-    std::vector<pinn_tuning> best = base;
-    double ms_best = std::min(ms_own, ms_wide);
-    // then fewer weight-gradient partials (split-K partials, or the fused
-    // backward's persistent workgroups): a grouped launch gathers enough
-    // workgroups from all the networks, so each can take more points and the
-    // partials written and summed per layer shrink
-    for (int div : {2, 4}) {
-      if (st) break;
-      std::vector<pinn_tuning> fewer = base;
-      for (int i = 0; i < b->n; ++i) fewer[i].dw_splits = std::max(1, fewer[i].dw_splits / div);
-      for (int i = 0; i < b->n && st == PINN_OK; ++i) st = pinn_plan_set_tuning(b->plans[i], &fewer[i]);
-      double ms = 1e300;
-      if (st == PINN_OK) st = time_steps(&ms);
-      if (st == PINN_OK && ms < ms_best) {
-        ms_best = ms;
-        best = fewer;
-      } else {
-        break;
-      }
-    }
-    for (int i = 0; i < b->n && st == PINN_OK; ++i) st = pinn_plan_set_tuning(b->plans[i], &best[i]);
+    if (st == PINN_OK && ms_own <= ms_wide)
+      for (int i = 0; i < b->n && st == PINN_OK; ++i) st = pinn_plan_set_tuning(b->plans[i], &own[i]);
     if (st) {
       (void)hipEventDestroy(t0);
       (void)hipEventDestroy(t1);
