@@ -129,12 +129,11 @@ __device__ __forceinline__ TanhDerivs tanh_derivs(float s, float s1) {
   return t;
 }
 
-// Activation jet: z (pre-activation channels, bias already in z[0]) -> a.
-template <class CH, bool FAST = false>
-__device__ __forceinline__ void jet_forward(const float (&z)[CH::C], float (&a)[CH::C], float &s_out) {
-  const TanhS ts = tanh_eval<FAST>(z[0]);
-  const TanhDerivs t = tanh_derivs<CH::MAXK>(ts.s, ts.s1);
-  s_out = t.s;
+// Activation jet from s = tanh(z_0), s1 = 1 - s^2 and the derivative
+// channels z_c (c >= 1; z[0] is not read) -> a.
+template <class CH>
+__device__ __forceinline__ void jet_forward_from(float s, float s1, const float (&z)[CH::C], float (&a)[CH::C]) {
+  const TanhDerivs t = tanh_derivs<CH::MAXK>(s, s1);
   a[0] = t.s;
 #pragma unroll
   for (int d = 0; d < CH::NDIR; ++d) {
@@ -159,6 +158,14 @@ __device__ __forceinline__ void jet_forward(const float (&z)[CH::C], float (&a)[
 #pragma unroll
   for (int m = 0; m < CH::NMIX; ++m)
     a[CH::mix(m, 0)] = t.s2 * z[CH::mix(m, 1)] * z[CH::mix(m, 2)] + t.s1 * z[CH::mix(m, 0)];
+}
+
+// Activation jet: z (pre-activation channels, bias already in z[0]) -> a.
+template <class CH, bool FAST = false>
+__device__ __forceinline__ void jet_forward(const float (&z)[CH::C], float (&a)[CH::C], float &s_out) {
+  const TanhS ts = tanh_eval<FAST>(z[0]);
+  s_out = ts.s;
+  jet_forward_from<CH>(ts.s, ts.s1, z, a);
 }
 
 // Adjoint of jet_forward.  Inputs: the cotangent ab of the activation jet,

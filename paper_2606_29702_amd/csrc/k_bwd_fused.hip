@@ -360,11 +360,13 @@ struct KBwdDwDb {
     BwdArgs args;
     float * part;
     int64_t n_tiles;
+    float * part_out;  // top layer: output-layer gradient partials, or null
   };
   static __device__ __forceinline__ void run(const Args &a_, VBlock vb) {
     const BwdArgs &args = a_.args;
     float *__restrict__ part = a_.part;
     int64_t n_tiles = a_.n_tiles;
+    float *__restrict__ part_out = a_.part_out;
     using M16 = Mma16<T>;
     using L = SwzTile<T, CH::C, W>;
     constexpr int C = CH::C, P = 16;
@@ -395,6 +397,24 @@ struct KBwdDwDb {
 
     // top layer: this lane's W_L^T operand of each neuron tile, row r, output g
     [[maybe_unused]] float wl[TOP ? TPW : 1];
+    // top layer of a one-output network, with part_out: the output layer's
+    // gradient dW_L[j] = sum over points and channels of ubar[n][c] a_H[n][c][j],
+    // with the activation jet a_H recomputed from z_H here (it is not read
+    // back from the stack), for this lane's neurons; db_L in wave 0.  (More
+    // outputs would cost the second wave per SIMD.)
+    constexpr bool OUTG = TOP && DOUT == 1;
+    [[maybe_unused]] float dwl[OUTG ? DOUT : 1][OUTG ? TPW : 1][4];
+    [[maybe_unused]] float dbl[OUTG ? DOUT : 1];
+    if constexpr (OUTG) {
+  #pragma unroll
+      for (int o = 0; o < DOUT; ++o) {
+        dbl[o] = 0.f;
+  #pragma unroll
+        for (int t = 0; t < TPW; ++t)
+  #pragma unroll
+          for (int i = 0; i < 4; ++i) dwl[o][t][i] = 0.f;
+      }
+    }
     if constexpr (TOP) {
       static_assert(DOUT <= 4, "output contraction on one MFMA 16x16x4");
   #pragma unroll
@@ -417,14 +437,23 @@ struct KBwdDwDb {
 
       // the GEMMs (their weight fragments stream from L2 ahead of use)
       f32x4 acc_a[TPW][C], acc_z[TPW][C];
+      [[maybe_unused]] float ubo[OUTG ? DOUT : 1][C];  // ubar of this lane's point (every lane)
       if constexpr (TOP) {
         // abar = W_L^T ubar contracts over the DOUT <= 4 outputs: one FP32
         // MFMA 16x16x4 per neuron tile and channel, output o = lane group g
         // (zero beyond DOUT).  The ubar loads are issued before the z GEMM.
-        float ub[C];
         const int64_t n = nb + r;
+        float ub[C];
+        if constexpr (OUTG) {
   #pragma unroll
-        for (int c = 0; c < C; ++c) ub[c] = g < DOUT ? args.ubar[(n * DOUT + g) * C + c] : 0.f;
+          for (int c = 0; c < C; ++c) {
+            ubo[0][c] = args.ubar[n * C + c];
+            ub[c] = g == 0 ? ubo[0][c] : 0.f;
+          }
+        } else {
+  #pragma unroll
+          for (int c = 0; c < C; ++c) ub[c] = g < DOUT ? args.ubar[(n * DOUT + g) * C + c] : 0.f;
+        }
         swz_gemm<T, C, TPW, W>(acc_z, Wz, a_t, jt0, lane);
   #pragma unroll
         for (int t = 0; t < TPW; ++t)
@@ -480,12 +509,30 @@ struct KBwdDwDb {
           jet_adjoint<CH>(ab, zz[i][0], s1[i], zz[i], zb);
   #pragma unroll
           for (int c = 0; c < C; ++c) out[i][c] = zb[c];
+          if constexpr (OUTG) {
+            if (part_out) {
+              float act[C];
+              jet_forward_from<CH>(zz[i][0], s1[i], zz[i], act);
+  #pragma unroll
+              for (int o = 0; o < DOUT; ++o) {
+                float sacc = 0.f;
+  #pragma unroll
+                for (int c = 0; c < C; ++c) sacc += ubo[o][c] * act[c];
+                dwl[o][t][i] += sacc;
+              }
+            }
+          }
         }
   #pragma unroll
         for (int c = 0; c < C; ++c) {
           store4(Zb_out + n * ps + c * W + mb, out[0][c], out[1][c], out[2][c], out[3][c]);
           store4(zb_t + L::at(r, c * W + mb), out[0][c], out[1][c], out[2][c], out[3][c]);
         }
+      }
+      if constexpr (OUTG) {
+        if (part_out && wave == 0 && g == 0)
+  #pragma unroll
+          for (int o = 0; o < DOUT; ++o) dbl[o] += ubo[o][0];
       }
       // Zbar_m tile complete in LDS.  A plain barrier after the LDS stores have
       // completed: a full __syncthreads() would also wait for the prefetch.
@@ -542,33 +589,57 @@ struct KBwdDwDb {
           pp[(int64_t)j * W + k] = dacc[jt][kt][i];
         }
     if (tid < W) pp[(int64_t)W * W + tid] = db;
+    if constexpr (OUTG) {
+      if (part_out) {  // sums over the 16 points of the lane group, in a fixed order
+        float *po = part_out + (int64_t)vb.x * (DOUT * W + DOUT);
+  #pragma unroll
+        for (int o = 0; o < DOUT; ++o)
+  #pragma unroll
+          for (int t = 0; t < TPW; ++t)
+  #pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const float v = group_sum<16>(dwl[o][t][i]);
+              if (r == 0) po[o * W + (jt0 + t) * 16 + 4 * g + i] = v;
+            }
+        if (wave == 0)
+  #pragma unroll
+          for (int o = 0; o < DOUT; ++o) {
+            const float v = group_sum<16>(dbl[o]);
+            if (lane == 0) po[DOUT * W + o] = v;
+          }
+      }
+    }
   }
 };
 
 namespace {
 
 template <class CH, class T, int W, bool TOP, int DOUT, int ZSRC>
-hipError_t launch_w(const BwdArgs &a, float *part, int64_t n_tiles, int grid, hipStream_t st) {
+hipError_t launch_w(const BwdArgs &a, float *part, int64_t n_tiles, int grid, float *part_out, hipStream_t st) {
   constexpr int NW = W == 32 ? 2 : (W == 256 ? 8 : 4);
   constexpr int TPW = (W / 16) / NW;
   if constexpr (ZSRC == Z_FROM_GEMM && bwd_db_ok<T>(CH::C, W))
-    return launch_body<KBwdDwDb<CH, T, W, NW, TPW, DOUT, TOP>>({a, part, n_tiles}, dim3((unsigned)grid), 0, st);
+    return (part_out && !(TOP && DOUT == 1))
+               ? hipErrorInvalidValue
+               : launch_body<KBwdDwDb<CH, T, W, NW, TPW, DOUT, TOP>>({a, part, n_tiles, part_out},
+                                                                    dim3((unsigned)grid), 0, st);
+  if (part_out) return hipErrorInvalidValue;  // only the double-buffered top layer forms them
   constexpr size_t lds = (size_t)2 * 16 * (CH::C * W + 8) * sizeof(T);
   return launch_body<KBwdDw<CH, T, W, NW, TPW, TOP, DOUT, ZSRC>>({a, part, n_tiles}, dim3((unsigned)grid), lds, st);
 }
 
 template <class PDE, class T>
 hipError_t launch_kind(const BwdArgs &a, bool top, int zsrc, float *part, int64_t n_tiles, int grid,
-                       hipStream_t st) {
+                       float *part_out, hipStream_t st) {
   using CH = typename PDE::CH;
   constexpr int DO = PDE::DOUT;
 #define PJ_W(WV)                                                                                    \
   if (a.w == WV) {                                                                                  \
     if (top)                                                                                        \
-      return zsrc == Z_FROM_S ? launch_w<CH, T, WV, true, DO, Z_FROM_S>(a, part, n_tiles, grid, st)  \
-                              : launch_w<CH, T, WV, true, DO, Z_FROM_GEMM>(a, part, n_tiles, grid, st); \
-    return zsrc == Z_FROM_S ? launch_w<CH, T, WV, false, DO, Z_FROM_S>(a, part, n_tiles, grid, st)   \
-                            : launch_w<CH, T, WV, false, DO, Z_FROM_GEMM>(a, part, n_tiles, grid, st); \
+      return zsrc == Z_FROM_S ? launch_w<CH, T, WV, true, DO, Z_FROM_S>(a, part, n_tiles, grid, part_out, st)  \
+                              : launch_w<CH, T, WV, true, DO, Z_FROM_GEMM>(a, part, n_tiles, grid, part_out, st); \
+    return zsrc == Z_FROM_S ? launch_w<CH, T, WV, false, DO, Z_FROM_S>(a, part, n_tiles, grid, part_out, st)   \
+                            : launch_w<CH, T, WV, false, DO, Z_FROM_GEMM>(a, part, n_tiles, grid, part_out, st); \
   }
   PJ_W(32) PJ_W(64) PJ_W(128)
 #undef PJ_W
@@ -576,6 +647,11 @@ hipError_t launch_kind(const BwdArgs &a, bool top, int zsrc, float *part, int64_
 }
 
 }  // namespace
+
+bool bwd_top_out_grad_supported(int C, int w, int prec, int dout) {
+  return dout == 1 && prec != P_FP32 && (w == 32 || w == 64 || w == 128) && (C * w / 8) % 16 == 0 &&
+         4 * 16 * C * w * 2 <= 80 * 1024;
+}
 
 bool bwd_dw_fused_supported(int C, int w, int prec) {
   if (w != 32 && w != 64 && w != 128) return false;
@@ -591,9 +667,9 @@ hipError_t launch_bwd_dw(int kind, int prec, const LayerBwd &L, float *part, int
   auto by_prec = [&](auto pde) -> hipError_t {
     using PDE = decltype(pde);
     switch (prec) {
-      case P_FP32: return launch_kind<PDE, float>(a, L.top, zsrc, part, n_tiles, grid, st);
-      case P_BF16: return launch_kind<PDE, bf16_t>(a, L.top, zsrc, part, n_tiles, grid, st);
-      case P_FP16: return launch_kind<PDE, f16_t>(a, L.top, zsrc, part, n_tiles, grid, st);
+      case P_FP32: return launch_kind<PDE, float>(a, L.top, zsrc, part, n_tiles, grid, L.out_part, st);
+      case P_BF16: return launch_kind<PDE, bf16_t>(a, L.top, zsrc, part, n_tiles, grid, L.out_part, st);
+      case P_FP16: return launch_kind<PDE, f16_t>(a, L.top, zsrc, part, n_tiles, grid, L.out_part, st);
       default: return hipErrorInvalidValue;
     }
   };

@@ -76,6 +76,11 @@ struct LayerBwd {
   // the wide-layer kernel (w >= 256): 0 the default, 16 the double-buffered
   // 16-point form, 32 / 64 points per workgroup, where wide_bwd_points_supported
   int points = 0;
+  // top layer of the fused backward of a one-output network, where
+  // bwd_top_out_grad_supported: when
+  // non-null, also the output layer's gradient partials
+  // out_part[g][dout*w + dout] (dW_L row-major, then db_L), one per workgroup
+  float *out_part = nullptr;
 };
 bool wide_bwd_points_supported(int points, int C, int w, int prec);
 hipError_t launch_layer_bwd(int kind, int prec, const LayerBwd &L, int64_t N_pad, hipStream_t st);
@@ -108,6 +113,7 @@ struct BwdArgs {
 // even when L.S_in is given.  Writes `grid` partials part[g][w*w + w]
 // (dW row-major, then db), summed by launch_reduce_parts2.
 bool bwd_dw_fused_supported(int C, int w, int prec);
+bool bwd_top_out_grad_supported(int C, int w, int prec, int dout);
 hipError_t launch_bwd_dw(int kind, int prec, const LayerBwd &L, float *part, int64_t N_pad, int grid,
                          hipStream_t st);
 

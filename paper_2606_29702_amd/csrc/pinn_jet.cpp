@@ -390,6 +390,16 @@ pinn_status cast_weights(pinn_plan p, const pinn_net *net, bool transposed, hipS
 pinn_status mod_forward(pinn_plan p, const pinn_net *net, const pinn_pde *pde, const float *x, int64_t N,
                         float *jets, float *r, float *loss, hipStream_t st);
 
+// Whether the backward pass takes the fused weight-gradient path, and whether
+// its top layer kernel also forms the output layer's gradient (then the top
+// stack A_H is never read back, and the forward does not save it).
+bool backward_fused(const pinn_plan p) {
+  return p->bwd_fused && p->H >= 2 && pj::bwd_dw_fused_supported(p->ki.C, p->w, p->prec);
+}
+bool top_forms_out_grad(const pinn_plan p) {
+  return backward_fused(p) && !p->store_S && pj::bwd_top_out_grad_supported(p->ki.C, p->w, p->prec, p->ki.dout);
+}
+
 pinn_status run_forward(pinn_plan p, const pinn_net *net, const pinn_pde *pde, const float *x,
                         int64_t N, float *jets, float *r, float *loss, double *loss_f64,
                         bool save_state, hipStream_t st) {
@@ -410,6 +420,7 @@ pinn_status run_forward(pinn_plan p, const pinn_net *net, const pinn_pde *pde, c
       dest[l] = p->ckpt[l] ? p->ckpt_buf[l] : nullptr;
       Sdest[l] = p->S[l];
     }
+  if (save_state && top_forms_out_grad(p)) dest[H] = nullptr;
   FwdOutputs o;
   o.output = true;
   o.pde = pde;
@@ -587,7 +598,7 @@ static pinn_status plan_build(const pinn_net *net, const pinn_pde *pde, int64_t 
   p->bwd_fused = (prec != PINN_FP32 && pj::bwd_dw_fused_supported(ki.C, w, prec)) ? 1 : 0;
   p->thin_chunks = (int)std::max<int64_t>(1, npad / 64);
   const size_t part_elems = std::max<size_t>(
-      std::max<size_t>((size_t)p->dw_splits_max * ((size_t)w * w + w),
+      std::max<size_t>((size_t)p->dw_splits_max * ((size_t)w * w + w + ki.dout * w + ki.dout),
                        (size_t)p->thin_chunks * std::max(ki.dout * w + ki.dout, w * ki.din + w)),
       (size_t)(npad / 16) * ((size_t)w * ki.din + w));  // first-layer partials, one per 16-point tile
   A(reinterpret_cast<void **>(&p->part), part_elems * sizeof(float));
@@ -948,7 +959,7 @@ static pinn_status backward_impl(pinn_plan plan, const pinn_net *net, const pinn
     }
     return PINN_OK;
   };
-  const bool fused = p->bwd_fused && H >= 2 && pj::bwd_dw_fused_supported(ki.C, w, p->prec);
+  const bool fused = backward_fused(p);
   // layer 1's adjoint kernel also yields the first layer's gradient (H >= 2:
   // layer 1 is then a hidden-layer adjoint from zbar_2, not the top layer)
   const bool seed_fused = H >= 2 && pj::seed_grad_fused_supported(ki.C, w, p->prec);
@@ -979,21 +990,31 @@ static pinn_status backward_impl(pinn_plan plan, const pinn_net *net, const pinn
       e2 = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, grid, (int64_t)w * w + w, (int64_t)w * w, w, dW[m - 1], db[m - 1], f64(dW_f64, m - 1), f64(db_f64, m - 1), s, inv_s); });
       return e2 ? hip_fail(e2, "reduction") : PINN_OK;
     };
+    // the top layer's kernel also forms the output layer's gradient partials
+    // where it is the double-buffered one (after the top layer's own partials)
+    const bool out_fused = top_forms_out_grad(p);
+    float *out_part = out_fused ? p->part + (size_t)grid * ((size_t)w * w + w) : nullptr;
     {
       pj::LayerBwd B{};
       B.top = true;
       B.ubar = p->ubar;
       B.WL = net->W[L - 1];
+      B.out_part = out_part;
       rs = layer(B, H, PINN_K_OUT_BWD);
       if (rs) return rs;
     }
-    const void *AH = nullptr;
-    rs = backward_stack(p, net, x, N, npad, H, &AH, s);
-    if (rs) return rs;
-    e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_dw_out(p->kind, p->prec, p->ubar, AH, npad, w, p->part, p->thin_chunks, s); });
-    if (e) return hip_fail(e, "output-layer gradient");
-    e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, p->thin_chunks, (int64_t)ki.dout * w + ki.dout, (int64_t)ki.dout * w, ki.dout, dW[L - 1], db[L - 1], f64(dW_f64, L - 1), f64(db_f64, L - 1), s, inv_s); });
-    if (e) return hip_fail(e, "reduction");
+    if (out_fused) {
+      e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(out_part, grid, (int64_t)ki.dout * w + ki.dout, (int64_t)ki.dout * w, ki.dout, dW[L - 1], db[L - 1], f64(dW_f64, L - 1), f64(db_f64, L - 1), s, inv_s); });
+      if (e) return hip_fail(e, "reduction");
+    } else {
+      const void *AH = nullptr;
+      rs = backward_stack(p, net, x, N, npad, H, &AH, s);
+      if (rs) return rs;
+      e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_dw_out(p->kind, p->prec, p->ubar, AH, npad, w, p->part, p->thin_chunks, s); });
+      if (e) return hip_fail(e, "output-layer gradient");
+      e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, p->thin_chunks, (int64_t)ki.dout * w + ki.dout, (int64_t)ki.dout * w, ki.dout, dW[L - 1], db[L - 1], f64(dW_f64, L - 1), f64(db_f64, L - 1), s, inv_s); });
+      if (e) return hip_fail(e, "reduction");
+    }
     for (int l = H; l >= 3; --l) {
       pj::LayerBwd B{};
       B.top = false;
