@@ -661,7 +661,7 @@ bool bwd_dw_fused_supported(int C, int w, int prec) {
 
 hipError_t launch_bwd_dw(int kind, int prec, const LayerBwd &L, float *part, int64_t N_pad, int grid,
                          hipStream_t st) {
-  BwdArgs a{L.Zb_in, L.WT, L.ubar, L.WL, L.S_in, L.A_prev, L.Wz, L.bz, L.x, L.W1, L.N, L.Zb_out, L.w, nullptr};
+  BwdArgs a{L.Zb_in, L.WT, L.ubar, L.WL, L.S_in, L.A_prev, L.Wz, L.bz, L.x, L.W1, L.N, L.Zb_out, L.w, nullptr, nullptr};
   const int zsrc = L.S_in ? Z_FROM_S : Z_FROM_GEMM;
   const int64_t n_tiles = N_pad / 16;
   auto by_prec = [&](auto pde) -> hipError_t {

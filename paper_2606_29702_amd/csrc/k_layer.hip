@@ -31,10 +31,14 @@ bool seed_grad_fused_supported(int C, int w, int prec) {
   return (w >= 256 && w % 128 == 0) || (bwd_lds_cfg(C, w, osz, false).P > 0 && C * w * osz % 16 == 0);
 }
 
+bool wide_top_out_grad_supported(int points, int C, int w, int prec, int dout) {
+  return points == 256 && w == 256 && C <= 6 && prec != P_FP32 && dout == 1;
+}
+
 hipError_t launch_layer_bwd(int kind, int prec, const LayerBwd &L, int64_t N_pad, hipStream_t st) {
   if (L.seed_part && (L.top || L.A_prev || !L.x)) return hipErrorInvalidValue;
   BwdArgs a{L.Zb_in, L.WT, L.ubar, L.WL, L.S_in, L.A_prev, L.Wz, L.bz, L.x, L.W1, L.N, L.Zb_out, L.w,
-            L.seed_part};
+            L.seed_part, L.out_part};
   const int zsrc = L.S_in ? Z_FROM_S : (L.A_prev ? Z_FROM_GEMM : Z_FROM_X);
   switch (kind) {
     case K_BURGERS: return layer_bwd_burgers(prec, a, L.top, zsrc, N_pad, L.points, st);

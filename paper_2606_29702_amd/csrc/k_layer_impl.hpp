@@ -399,8 +399,8 @@ __device__ __forceinline__ void bwd_epilogue(const BwdArgs &args, const f32x4 (&
       }
     }
     float ab[4][C];
+    [[maybe_unused]] float ub[TOP ? DOUT : 1][C];
     if constexpr (TOP) {
-      float ub[DOUT][C];
 #pragma unroll
       for (int o = 0; o < DOUT; ++o)
 #pragma unroll
@@ -427,6 +427,27 @@ __device__ __forceinline__ void bwd_epilogue(const BwdArgs &args, const f32x4 (&
       jet_adjoint<CH>(ab[i], zz[i][0], s1[i], zz[i], zb);
 #pragma unroll
       for (int c = 0; c < C; ++c) out[i][c] = zb[c];
+    }
+    if constexpr (TOP && DOUT == 1 && ZSRC == Z_FROM_GEMM) {
+      if (args.out_part) {
+        // the output layer's gradient over this 16-point tile (one output):
+        // dW_L[j] = sum over the tile's points of sum_c ubar[n][c] a_H[n][c][j],
+        // the activation jet recomputed from z_H; the 16 points are the lanes
+        // r of each lane group, summed by a butterfly.  db_L with neuron tile 0.
+        float *op = args.out_part + part_row * ((int64_t)w + 1);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          float act[C];
+          jet_forward_from<CH>(zz[i][0], s1[i], zz[i], act);
+          float v = 0.f;
+#pragma unroll
+          for (int c = 0; c < C; ++c) v += ub[0][c] * act[c];
+          v = group_sum<16>(v);
+          if (r == 0) op[mb + i] = v;
+        }
+        const float v0 = group_sum<16>(ub[0][0]);
+        if (jt0 + t == 0 && lane == 0) op[w] = v0;
+      }
     }
     if constexpr (ZSRC != Z_FROM_GEMM && !TOP) {
       if (args.seed_part) {
@@ -924,6 +945,10 @@ inline BwdLdsCfg bwd_lds_cfg(int C, int w, int osz, bool two_tiles) {
 template <class CH, class T, bool TOP, int DOUT, int ZSRC>
 hipError_t launch_bwd_t(const BwdArgs &a, int64_t N_pad, int points, hipStream_t st) {
   const int w = a.w;
+  // output-layer gradient partials: formed by the streaming 256-wide kernel only
+  if (a.out_part && !(TOP && DOUT == 1 && ZSRC == Z_FROM_GEMM && sizeof(T) == 2 && CH::C <= 6 && points == 256 &&
+                      w == 256 && N_pad == (a.N + kPointTile - 1) / kPointTile * kPointTile))
+    return hipErrorInvalidValue;
   // wide layers: neuron-tiled, contraction staged through LDS in chunks
   // 16-bit operands with 8 channels (one full wave load per point and tile),
   // or up to 8 with points == 16: the double-buffered form (slower than the

@@ -76,13 +76,14 @@ struct LayerBwd {
   // the wide-layer kernel (w >= 256): 0 the default, 16 the double-buffered
   // 16-point form, 32 / 64 points per workgroup, where wide_bwd_points_supported
   int points = 0;
-  // top layer of the fused backward of a one-output network, where
-  // bwd_top_out_grad_supported: when
-  // non-null, also the output layer's gradient partials
-  // out_part[g][dout*w + dout] (dW_L row-major, then db_L), one per workgroup
+  // top layer of a one-output network, where bwd_top_out_grad_supported
+  // (fused backward) or wide_top_out_grad_supported (wide layer kernel): when
+  // non-null, also the output layer's gradient partials out_part[g][w + 1]
+  // (dW_L, then db_L), one per workgroup (fused) or per 16-point tile (wide)
   float *out_part = nullptr;
 };
 bool wide_bwd_points_supported(int points, int C, int w, int prec);
+bool wide_top_out_grad_supported(int points, int C, int w, int prec, int dout);
 hipError_t launch_layer_bwd(int kind, int prec, const LayerBwd &L, int64_t N_pad, hipStream_t st);
 // Whether launch_layer_bwd can produce seed_part for this shape.
 bool seed_grad_fused_supported(int C, int w, int prec);
@@ -105,6 +106,7 @@ struct BwdArgs {
   void *Zb_out;        // [N_pad][C][w] operand type
   int w;
   float *seed_part;    // Z_FROM_X: first-layer gradient partials instead of Zb_out
+  float *out_part;     // TOP, one output: output-layer gradient partials per 16-point tile
 };
 
 

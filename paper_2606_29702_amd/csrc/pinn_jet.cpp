@@ -397,7 +397,9 @@ bool backward_fused(const pinn_plan p) {
   return p->bwd_fused && p->H >= 2 && pj::bwd_dw_fused_supported(p->ki.C, p->w, p->prec);
 }
 bool top_forms_out_grad(const pinn_plan p) {
-  return backward_fused(p) && !p->store_S && pj::bwd_top_out_grad_supported(p->ki.C, p->w, p->prec, p->ki.dout);
+  if (p->store_S || p->H < 2) return false;
+  if (backward_fused(p)) return pj::bwd_top_out_grad_supported(p->ki.C, p->w, p->prec, p->ki.dout);
+  return pj::wide_top_out_grad_supported(p->bwd_points, p->ki.C, p->w, p->prec, p->ki.dout);
 }
 
 pinn_status run_forward(pinn_plan p, const pinn_net *net, const pinn_pde *pde, const float *x,
@@ -1040,6 +1042,9 @@ static pinn_status backward_impl(pinn_plan plan, const pinn_net *net, const pinn
   // Output layer: ubar, then zbar of layer H, then dW_L, db_L.
   e = output_adjoint();
   if (e) return hip_fail(e, "output adjoint");
+  // the wide top layer's kernel also forms the output layer's gradient
+  // partials (one per 16-point tile) where it is the streaming 256-wide one
+  const bool out_wide = top_forms_out_grad(p);
   {
     pj::LayerBwd B{};
     B.top = true;
@@ -1048,20 +1053,26 @@ static pinn_status backward_impl(pinn_plan plan, const pinn_net *net, const pinn
     B.N = N;
     B.w = w;
     B.Zb_out = p->Zb[H % 2];
+    B.out_part = out_wide ? p->part : nullptr;
     rs = zsrc(B, H);
     if (rs) return rs;
     e = timed(p, PINN_K_OUT_BWD, s, [&] { return pj::launch_layer_bwd(p->kind, p->prec, with_points(B, p), npad, s); });
     if (e) return hip_fail(e, "last hidden adjoint");
   }
-  const void *AH = nullptr;
-  rs = backward_stack(p, net, x, N, npad, H, &AH, s);
-  if (rs) return rs;
-  e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_dw_out(p->kind, p->prec, p->ubar, AH, npad, w, p->part, p->thin_chunks, s); });
-  if (e) return hip_fail(e, "output-layer gradient");
-  e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, p->thin_chunks, (int64_t)ki.dout * w + ki.dout,
-                               (int64_t)ki.dout * w, ki.dout, dW[L - 1], db[L - 1], f64(dW_f64, L - 1),
-                               f64(db_f64, L - 1), s, inv_s); });
-  if (e) return hip_fail(e, "reduction");
+  if (out_wide) {
+    e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, (int)(npad / 16), (int64_t)w + 1, w, 1, dW[L - 1], db[L - 1], f64(dW_f64, L - 1), f64(db_f64, L - 1), s, inv_s); });
+    if (e) return hip_fail(e, "reduction");
+  } else {
+    const void *AH = nullptr;
+    rs = backward_stack(p, net, x, N, npad, H, &AH, s);
+    if (rs) return rs;
+    e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_dw_out(p->kind, p->prec, p->ubar, AH, npad, w, p->part, p->thin_chunks, s); });
+    if (e) return hip_fail(e, "output-layer gradient");
+    e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, p->thin_chunks, (int64_t)ki.dout * w + ki.dout,
+                                 (int64_t)ki.dout * w, ki.dout, dW[L - 1], db[L - 1], f64(dW_f64, L - 1),
+                                 f64(db_f64, L - 1), s, inv_s); });
+    if (e) return hip_fail(e, "reduction");
+  }
   // Hidden layers H..2: dW_l, db_l from zbar_l and the stack of layer l - 1,
   // then zbar of layer l - 1.
   for (int l = H; l >= 2; --l) {

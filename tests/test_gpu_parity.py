@@ -561,8 +561,9 @@ def test_wide_backward_tilings_agree(lib, pde, dims, prec):
     weight fragment), and the streaming form at width 256 (sixteen 16-point
     tiles per workgroup, weights in registers): the same per-element
     arithmetic, so the gradients agree bit for bit with BF16 operands and to
-    FP16 rounding with FP16 ones; the 64-point and streaming tilings against
-    the oracle at the 16-bit bars."""
+    FP16 rounding with FP16 ones (the streaming form's output-layer gradient
+    to the stack's rounding); the 64-point and streaming tilings against the
+    oracle at the 16-bit bars."""
     N = 1000
     prob = pi.make_problem(pde, N=N, seed=14, bias_std=0.2, dims=dims)
     if pde == "ks":
@@ -579,11 +580,20 @@ def test_wide_backward_tilings_agree(lib, pde, dims, prec):
         plan.residual(params, x)
         grads[bp] = flat(plan.backward(params, x))
     torch.cuda.synchronize()
+    # the streaming form also forms the output layer's gradient, from the
+    # activation jet recomputed in FP32 instead of the saved 16-bit stack:
+    # those dims[-2] * dims[-1] + dims[-1] entries (last in the flat vector)
+    # agree to the stack's rounding, the rest as for the other tilings
+    n_out = dims[-2] * dims[-1] + dims[-1]
     for bp in tilings[1:]:
+        a, b = grads[bp], grads[0]
+        if bp == 256:
+            assert rel(a[-n_out:], b[-n_out:]) <= 1e-2, bp
+            a, b = a[:-n_out], b[:-n_out]
         if prec == "fp16":
-            assert rel(grads[bp], grads[0]) <= 1e-3, bp
+            assert rel(a, b) <= 1e-3, bp
         else:
-            assert np.array_equal(grads[bp], grads[0]), bp
+            assert np.array_equal(a, b), bp
     orc = oracle.evaluate(prob.params, prob.x, prob.channels, pde, prob.coef)
     assert rel(grads[64], orc.grad) <= LOWP_TOL[prec]["grad"]
     assert rel(grads[tilings[-1]], orc.grad) <= LOWP_TOL[prec]["grad"]
