@@ -36,6 +36,8 @@ TILE_BAR = {"fp32": {"r": 1e-5, "jets": 1e-5}, "bf16": {"r": 2.5e-2, "jets": 2.5
 ONE_TILE_BAR = {"fp32": 1e-5, "bf16": 3e-2, "fp16": 5e-3}
 # gradient additivity: FP32 accumulation order only
 ADD_BAR = 1e-5
+# the BF16 loss gradient against the oracle (the bar of the parity tests)
+LOWP_GRAD_BAR = 1e-2
 # the fused backward at other grid sizes: FP32 order of the partial sums only
 # (measured 5.5e-6 with 2 workgroups, each accumulating 2048 tiles)
 GRID_BAR = 2e-5
@@ -174,3 +176,65 @@ def test_fused_backward_grid_sizes(lib, ns):
         _, g2 = run()
         assert np.array_equal(g, g2)  # deterministic at every grid
     plan.close()
+
+
+@pytest.mark.parametrize("width", [128, 256])
+def test_output_gradient_in_the_top_layer(lib, width):
+    """One-output networks get the output layer's gradient from the top
+    backward layer's kernel (per workgroup in the fused kernel at w <= 128,
+    per 16-point tile in the streaming kernel at w = 256), and the forward
+    does not save the top stack.  Against the oracle, next to a tiling that
+    still reads the saved stack (the separate weight gradient at w = 128, 64
+    points per workgroup at w = 256): cotangents supported on single tiles
+    (first, middle, the ragged last of 5 points) and the loss gradient, the
+    output layer's rows on their own as well.  The activation jet is
+    recomputed from z with the high part of the split weights, so the
+    output-layer rows of the loss gradient are less accurate than from the
+    saved stack (measured 1.7e-3 against 4.3e-4 at w = 256), within the bar."""
+    N = 5000 - 3
+    dims = [2] + [width] * 4 + [1]
+    prob = pi.make_problem("burgers", N=N, seed=31, bias_std=0.3, dims=dims)
+    params = [(torch.tensor(W, device="cuda"), torch.tensor(b, device="cuda")) for W, b in prob.params]
+    x = torch.tensor(prob.x, device="cuda")
+    n_out = width + 1
+    plans = []
+    for new in (True, False):
+        plan = lib.PinnPlan(dims, "burgers", N, precision="bf16", coef=prob.coef)
+        t = plan.tuning()
+        if width == 256:
+            plan.set_tuning(t["dw_splits"], t["fwd_points"], 0, 256 if new else 64)
+        else:
+            plan.set_tuning(t["dw_splits"], t["fwd_points"], 1 if new else 0, 0)
+        plans.append(plan)
+
+    def grads(r_bar):
+        out = []
+        for plan in plans:
+            plan.residual(params, x)
+            out.append(flat(plan.backward(params, x, r_bar=r_bar)))
+        return out
+
+    rng = np.random.default_rng(84)
+    for tile in (0, 150, (N - 1) // 16):
+        lo, hi = 16 * tile, min(16 * tile + 16, N)
+        rb = np.zeros((1, N), dtype=np.float32)
+        rb[:, lo:hi] = rng.normal(size=(1, hi - lo))
+        g_new, g_old = grads(torch.tensor(rb, device="cuda"))
+        ref = oracle.evaluate(prob.params, prob.x[lo:hi], prob.channels, "burgers", prob.coef,
+                              r_bar=rb[:, lo:hi].astype(np.float64), want_jets=False)
+        e, e_old = rel(g_new, ref.grad), rel(g_old, ref.grad)
+        e_out, e_out_old = rel(g_new[-n_out:], ref.grad[-n_out:]), rel(g_old[-n_out:], ref.grad[-n_out:])
+        print(f"w={width} tile {tile} ({hi - lo} points): gradient {e:.2e} (saved stack {e_old:.2e}), "
+              f"output layer {e_out:.2e} ({e_out_old:.2e})")
+        # a single tile's cotangent: the measured errors of both forms, up to
+        # 5.7e-2 on the 5-point tile; the new form within 1.5x of the old
+        assert e <= max(1.5 * e_old, 1e-3) and e_out <= max(1.5 * e_out_old, 1e-3), (tile, e, e_old)
+        assert e <= 1e-1 and e_out <= 1e-1, (tile, e, e_out)
+    g_new, g_old = grads(None)
+    ref = oracle.evaluate(prob.params, prob.x, prob.channels, "burgers", prob.coef, want_jets=False)
+    e, e_out = rel(g_new, ref.grad), rel(g_new[-n_out:], ref.grad[-n_out:])
+    print(f"w={width} loss gradient {e:.2e} (saved stack {rel(g_old, ref.grad):.2e}), output layer {e_out:.2e} "
+          f"({rel(g_old[-n_out:], ref.grad[-n_out:]):.2e})")
+    assert e <= LOWP_GRAD_BAR and e_out <= LOWP_GRAD_BAR, (e, e_out)
+    for plan in plans:
+        plan.close()
