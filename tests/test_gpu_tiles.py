@@ -144,6 +144,36 @@ def test_gradient_additivity(lib, ns, prec):
     half.close()
 
 
+def test_fused_backward_grid_sizes_one_output(lib):
+    """The same at one output, where the top layer's workgroups also
+    accumulate the output layer's gradient over all their tiles: grids of 2,
+    6 and 40 workgroups against the default grid (62 at this size)."""
+    N = 8000 - 5
+    dims = [2, 128, 128, 128, 128, 1]
+    prob = pi.make_problem("burgers", N=N, seed=32, bias_std=0.3, dims=dims)
+    params = [(torch.tensor(W, device="cuda"), torch.tensor(b, device="cuda")) for W, b in prob.params]
+    x = torch.tensor(prob.x, device="cuda")
+    plan = lib.PinnPlan(dims, "burgers", N, precision="bf16", coef=prob.coef)
+    t0 = plan.tuning()
+    assert t0["bwd_fused"] == 1
+
+    def run():
+        plan.residual(params, x)
+        g = flat(plan.backward(params, x))
+        torch.cuda.synchronize()
+        return g
+
+    g_ref = run()
+    for ds in (1, 3, 20):
+        plan.set_tuning(**{**t0, "dw_splits": ds})
+        g = run()
+        e, e_out = rel(g, g_ref), rel(g[-129:], g_ref[-129:])
+        print(f"dw_splits {ds} (grid {2 * ds}): gradient {e:.2e}, output layer {e_out:.2e} vs the default grid")
+        assert e <= GRID_BAR and e_out <= GRID_BAR, (ds, e, e_out)
+        assert np.array_equal(g, run())
+    plan.close()
+
+
 def test_fused_backward_grid_sizes(lib, ns):
     """The persistent fused backward runs twice the split count of workgroups
     (at most 512); each visits tiles blockIdx.x, blockIdx.x + gridDim.x, ...
