@@ -35,6 +35,9 @@ bool wide_top_out_grad_supported(int points, int C, int w, int prec, int dout) {
   return points == 256 && w == 256 && C <= 6 && prec != P_FP32 && dout == 1;
 }
 
+// One partial row per workgroup group of sixteen 16-point tiles.
+int64_t wide_top_out_grad_parts(int64_t N_pad) { return (N_pad / 16 + 15) / 16; }
+
 hipError_t launch_layer_bwd(int kind, int prec, const LayerBwd &L, int64_t N_pad, hipStream_t st) {
   if (L.seed_part && (L.top || L.A_prev || !L.x)) return hipErrorInvalidValue;
   BwdArgs a{L.Zb_in, L.WT, L.ubar, L.WL, L.S_in, L.A_prev, L.Wz, L.bz, L.x, L.W1, L.N, L.Zb_out, L.w,

@@ -347,7 +347,7 @@ __device__ __forceinline__ void lds_gemm(f32x4 (&acc)[TPW][C], const WFrags<T, T
 template <class CH, class T, int TPW, bool TOP, int DOUT, int ZSRC>
 __device__ __forceinline__ void bwd_epilogue(const BwdArgs &args, const f32x4 (&acc_a)[TPW][CH::C],
                                              const f32x4 (&acc_z)[TPW][CH::C], int64_t n, int jt0,
-                                             int64_t part_row, int lane) {
+                                             int64_t part_row, int lane, float *out_acc = nullptr) {
   constexpr int C = CH::C, D = CH::DIN;
   constexpr bool FAST = sizeof(T) == 2;
   const int w = args.w;
@@ -430,10 +430,13 @@ __device__ __forceinline__ void bwd_epilogue(const BwdArgs &args, const f32x4 (&
     }
     if constexpr (TOP && DOUT == 1 && ZSRC == Z_FROM_GEMM) {
       if (args.out_part) {
-        // the output layer's gradient over this 16-point tile (one output):
-        // dW_L[j] = sum over the tile's points of sum_c ubar[n][c] a_H[n][c][j],
-        // the activation jet recomputed from z_H; the 16 points are the lanes
-        // r of each lane group, summed by a butterfly.  db_L with neuron tile 0.
+        // the output layer's gradient (one output): dW_L[j] = sum over the
+        // points of sum_c ubar[n][c] a_H[n][c][j], the activation jet
+        // recomputed from z_H.  With out_acc, this lane's terms are added to
+        // the caller's accumulators (out_acc[t * 4 + i], db_L in
+        // out_acc[TPW * 4]); otherwise the 16 points of the tile (the lanes r
+        // of each lane group) are summed by a butterfly into the partial row
+        // `part_row`, db_L with neuron tile 0.
         float *op = args.out_part + part_row * ((int64_t)w + 1);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -442,11 +445,19 @@ __device__ __forceinline__ void bwd_epilogue(const BwdArgs &args, const f32x4 (&
           float v = 0.f;
 #pragma unroll
           for (int c = 0; c < C; ++c) v += ub[0][c] * act[c];
-          v = group_sum<16>(v);
-          if (r == 0) op[mb + i] = v;
+          if (out_acc) {
+            out_acc[t * 4 + i] += v;
+          } else {
+            v = group_sum<16>(v);
+            if (r == 0) op[mb + i] = v;
+          }
         }
-        const float v0 = group_sum<16>(ub[0][0]);
-        if (jt0 + t == 0 && lane == 0) op[w] = v0;
+        if (out_acc) {
+          if (t == 0) out_acc[TPW * 4] += ub[0][0];
+        } else {
+          const float v0 = group_sum<16>(ub[0][0]);
+          if (jt0 + t == 0 && lane == 0) op[w] = v0;
+        }
       }
     }
     if constexpr (ZSRC != Z_FROM_GEMM && !TOP) {
@@ -743,6 +754,14 @@ struct KLayerBwdKs {
     u32x4 rz[PER_T], ra[PER_T];  // the next tile's pieces (a plain vector type keeps them in registers)
     ks_load_unit<T, C, NT, W, P, PER_T, ZB, AZ>(rz, ra, zb_all, a_all, pt0 * P, ps, tid);
     f32x4 acc_a[PTW][TPW][C], acc_z[PTW][TPW][C];
+    // top layer, one output: the output layer's gradient over the
+    // workgroup's tiles (this lane's neurons and point; db_L last)
+    constexpr bool OUTG = TOP && DOUT == 1 && AZ;
+    [[maybe_unused]] float oacc[OUTG ? TPW * 4 + 1 : 1];
+    if constexpr (OUTG) {
+  #pragma unroll
+      for (int k = 0; k < TPW * 4 + 1; ++k) oacc[k] = 0.f;
+    }
     for (int t = 0; t < n_tiles; ++t) {
       if (t > 0) __syncthreads();  // every wave is done with the previous tile's LDS data
       ks_store_unit<T, C, NT, W, P, PER_T, ZB, AZ>(rz, ra, lds_b, lds_a, tid);
@@ -783,7 +802,22 @@ struct KLayerBwdKs {
   #pragma unroll
       for (int q = 0; q < PTW; ++q)
         bwd_epilogue<CH, T, TPW, TOP, DOUT, ZSRC>(args, acc_a[q], acc_z[q], nb + q * 16 + r, jt0,
-                                                  (pt0 + t) * PTW + q, lane);
+                                                  (pt0 + t) * PTW + q, lane,
+                                                  OUTG ? oacc : nullptr);
+    }
+    if constexpr (OUTG) {
+      if (args.out_part) {  // one partial row per group of tiles, sums in a fixed order
+        float *op = args.out_part + group * ((int64_t)W + 1);
+  #pragma unroll
+        for (int t = 0; t < TPW; ++t)
+  #pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float v = group_sum<16>(oacc[t * 4 + i]);
+            if (r == 0) op[(jt0 + t) * 16 + 4 * g + i] = v;
+          }
+        const float v0 = group_sum<16>(oacc[TPW * 4]);
+        if (jt0 == 0 && lane == 0) op[W] = v0;
+      }
     }
   }
 };

@@ -79,11 +79,14 @@ struct LayerBwd {
   // top layer of a one-output network, where bwd_top_out_grad_supported
   // (fused backward) or wide_top_out_grad_supported (wide layer kernel): when
   // non-null, also the output layer's gradient partials out_part[g][w + 1]
-  // (dW_L, then db_L), one per workgroup (fused) or per 16-point tile (wide)
+  // (dW_L, then db_L), one per workgroup (fused) or per group of sixteen
+  // 16-point tiles (wide, wide_top_out_grad_parts rows)
   float *out_part = nullptr;
 };
 bool wide_bwd_points_supported(int points, int C, int w, int prec);
 bool wide_top_out_grad_supported(int points, int C, int w, int prec, int dout);
+// Number of output-gradient partial rows the wide kernel writes.
+int64_t wide_top_out_grad_parts(int64_t N_pad);
 hipError_t launch_layer_bwd(int kind, int prec, const LayerBwd &L, int64_t N_pad, hipStream_t st);
 // Whether launch_layer_bwd can produce seed_part for this shape.
 bool seed_grad_fused_supported(int C, int w, int prec);

@@ -1043,7 +1043,8 @@ static pinn_status backward_impl(pinn_plan plan, const pinn_net *net, const pinn
   e = output_adjoint();
   if (e) return hip_fail(e, "output adjoint");
   // the wide top layer's kernel also forms the output layer's gradient
-  // partials (one per 16-point tile) where it is the streaming 256-wide one
+  // partials (one per workgroup's sixteen tiles) where it is the streaming
+  // 256-wide one
   const bool out_wide = top_forms_out_grad(p);
   {
     pj::LayerBwd B{};
@@ -1060,7 +1061,7 @@ static pinn_status backward_impl(pinn_plan plan, const pinn_net *net, const pinn
     if (e) return hip_fail(e, "last hidden adjoint");
   }
   if (out_wide) {
-    e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, (int)(npad / 16), (int64_t)w + 1, w, 1, dW[L - 1], db[L - 1], f64(dW_f64, L - 1), f64(db_f64, L - 1), s, inv_s); });
+    e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, (int)pj::wide_top_out_grad_parts(npad), (int64_t)w + 1, w, 1, dW[L - 1], db[L - 1], f64(dW_f64, L - 1), f64(db_f64, L - 1), s, inv_s); });
     if (e) return hip_fail(e, "reduction");
   } else {
     const void *AH = nullptr;
