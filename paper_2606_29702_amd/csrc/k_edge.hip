@@ -775,18 +775,21 @@ hipError_t launch_dw_seed(int kind, int prec, const void *Zb_1, const float *x, 
 
 hipError_t launch_reduce_parts2(const float *part, int splits, int64_t stride, int64_t M1,
                                 int64_t M2, float *a32, float *b32, double *a64, double *b64,
-                                hipStream_t st, float scale) {
+                                hipStream_t st, float scale, int select_splits) {
   const int64_t M = M1 + M2;
   // enough workgroups to keep many loads in flight: more threads per output
-  // when there are few outputs or many splits
-  if (splits >= 64 && M >= 4096 && stride % 4 == 0 && M1 % 4 == 0 && M % 4 == 0 &&
+  // when there are few outputs or many splits.  The variant is chosen by
+  // max(splits, select_splits), so that launches grouped together can use
+  // one variant whatever their split counts.
+  const int sel = splits > select_splits ? splits : select_splits;
+  if (sel >= 64 && M >= 4096 && stride % 4 == 0 && M1 % 4 == 0 && M % 4 == 0 &&
       reinterpret_cast<uintptr_t>(part) % 16 == 0) {
     dim3 grid((unsigned)((M / 4 + 15) / 16));
     return launch_body<KReduceV4<16, 256>>({part, splits, stride, M1, M2, a32, b32, a64, b64, scale}, grid, 0, st);
-  } else if (M * 4 < 256LL * 256 && splits >= 64) {
+  } else if (M * 4 < 256LL * 256 && sel >= 64) {
     dim3 grid((unsigned)((M + 7) / 8));
     return launch_body<KReduceG<32>>({part, splits, stride, M1, M2, a32, b32, a64, b64, scale}, grid, 0, st);
-  } else if (splits >= 64) {
+  } else if (sel >= 64) {
     dim3 grid((unsigned)((M + 15) / 16));
     return launch_body<KReduceG<16>>({part, splits, stride, M1, M2, a32, b32, a64, b64, scale}, grid, 0, st);
   } else {

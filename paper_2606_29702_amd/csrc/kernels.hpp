@@ -190,10 +190,10 @@ hipError_t launch_dw_hidden(int prec, int C, const void *Zb, const void *A_prev,
 // to a[q], q >= M1 to b[q - M1] (packed dW/db partials).  FP32 results into
 // a32/b32, FP64 sums of the same partials into a64/b64; each may be null.
 // scale is a power of two (the inverse of the cotangent scaling), so it
-// adds no rounding.
+// adds no rounding.  The kernel variant follows max(splits, select_splits).
 hipError_t launch_reduce_parts2(const float *part, int splits, int64_t stride, int64_t M1,
                                 int64_t M2, float *a32, float *b32, double *a64, double *b64,
-                                hipStream_t st, float scale = 1.f);
+                                hipStream_t st, float scale = 1.f, int select_splits = 0);
 
 // Modified MLP with a periodic input embedding (k_mod.hip), FP32 operands.
 constexpr int kModMaxHarmonics = 8;

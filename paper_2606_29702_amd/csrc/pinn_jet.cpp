@@ -1061,7 +1061,9 @@ static pinn_status backward_impl(pinn_plan plan, const pinn_net *net, const pinn
     if (e) return hip_fail(e, "last hidden adjoint");
   }
   if (out_wide) {
-    e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, (int)pj::wide_top_out_grad_parts(npad), (int64_t)w + 1, w, 1, dW[L - 1], db[L - 1], f64(dW_f64, L - 1), f64(db_f64, L - 1), s, inv_s); });
+    // one reduction variant for every point count, so that the networks of
+    // an ensemble lane group into one launch here
+    e = timed(p, PINN_K_OTHER, s, [&] { return pj::launch_reduce_parts2(p->part, (int)pj::wide_top_out_grad_parts(npad), (int64_t)w + 1, w, 1, dW[L - 1], db[L - 1], f64(dW_f64, L - 1), f64(db_f64, L - 1), s, inv_s, 64); });
     if (e) return hip_fail(e, "reduction");
   } else {
     const void *AH = nullptr;
