@@ -212,7 +212,7 @@ def test_fused_backward_grid_sizes(lib, ns):
 def test_output_gradient_in_the_top_layer(lib, width):
     """One-output networks get the output layer's gradient from the top
     backward layer's kernel (per workgroup in the fused kernel at w <= 128,
-    per 16-point tile in the streaming kernel at w = 256), and the forward
+    per sixteen 16-point tiles in the streaming kernel at w = 256), and the forward
     does not save the top stack.  Against the oracle, next to a tiling that
     still reads the saved stack (the separate weight gradient at w = 128, 64
     points per workgroup at w = 256): cotangents supported on single tiles
